@@ -1,0 +1,108 @@
+"""The SG linear system K u = F (paper Sec. 2.2).
+
+* Coefficient chaos modes (eq. dataProjection):
+  a_k(x) = E[a_KL(x, y) psi_k(y)] for k in J(q).  With a_KL = a_min +
+  exp(mu + sum_n g_n(x) y_n) and the Hermite generating function
+  exp(g y - g^2/2) = sum_m He_m(y) g^m / m!, this is
+      a_k(x) = a_min [k = 0] + exp(mu + (1/2) sum_n g_n^2) prod_n g_n^{k_n} / sqrt(k_n!).
+  Pinned against direct Gauss-Hermite projection of a_KL.
+* A_k = Q1 stiffness with coefficient a_k at the quadrature points (eq. A_q).
+* K = sum_k G_k (x) A_k (definition after eq. linear_algebraic_2), mode-major
+  rows i*N_h + node.  The paper's eq. linear_algebraic_2 swaps p and p' in
+  the sum; since every G_k is symmetric the reading K u = F with block (i, j)
+  = sum_k [G_k]_{ij} A_k is unambiguous.
+* F = e_0 (x) M_h f_h (the forcing is deterministic, Sec. 2, so only the mean
+  mode is loaded).
+
+apply(U) evaluates K U through the Kronecker identity
+(G (x) A) vec(U) = vec(A U G^T) applied to each term of the definition; it is
+pinned against the explicitly assembled K on small sizes.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import fem, kl, pc
+
+
+def coeff_modes(g: np.ndarray, Jq: np.ndarray, mu: float, a_min: float) -> np.ndarray:
+    """a_k at every quadrature point: array (n_a, N_q)."""
+    E = np.exp(mu + 0.5 * np.sum(g * g, axis=0))
+    out = np.empty((len(Jq), g.shape[1]))
+    for k, kk in enumerate(Jq):
+        v = E.copy()
+        for n, kn in enumerate(kk):
+            v = v * g[n] ** int(kn) / math.sqrt(math.factorial(int(kn)))
+        out[k] = v
+    out[0] += a_min
+    return out
+
+
+class SGSystem:
+    """Everything that defines K and F for one problem instance."""
+
+    def __init__(self, prob, f_nodal=None):
+        self.prob = prob
+        n = prob.n
+        self.n = n
+        self.Nh = (n - 1) * (n - 1)
+        self.Jp = pc.multi_indices(prob.M, prob.p)
+        self.Jq = pc.multi_indices(prob.M, prob.q)
+        self.P = len(self.Jp)
+        self.na = len(self.Jq)
+        self.Gk, self.Gi, self.Gj, self.Gv = pc.triple_products(self.Jp, self.Jq)
+        self.lam, self.B, self.pairs = kl.kl_2d(n, prob.cov, prob.corr_len, prob.sigma, prob.M)
+        self.g = kl.g_at_quad(n, self.lam, self.B)
+        self.a = coeff_modes(self.g, self.Jq, prob.mu, prob.a_min)
+        self.f_nodal = np.ones((n + 1) ** 2) if f_nodal is None else np.asarray(f_nodal, float)
+        self._A = None
+
+    # -- per-mode stiffness matrices (eq. A_q) -------------------------------
+    @property
+    def A(self):
+        if self._A is None:
+            self._A = [fem.stiffness(self.n, self.a[k]) for k in range(self.na)]
+        return self._A
+
+    def G_dense_k(self, k):
+        G = np.zeros((self.P, self.P))
+        m = self.Gk == k
+        G[self.Gi[m], self.Gj[m]] = self.Gv[m]
+        return G
+
+    def rhs(self) -> np.ndarray:
+        F = np.zeros(self.P * self.Nh)
+        F[: self.Nh] = fem.load_vector(self.n, self.f_nodal)
+        return F
+
+    def apply(self, U: np.ndarray) -> np.ndarray:
+        """K U = sum_k vec(A_k U G_k^T), U mode-major (P*N_h,)."""
+        Um = U.reshape(self.P, self.Nh).T            # (N_h, P), column i = mode i
+        W = np.zeros_like(Um)
+        for k in range(self.na):
+            m = self.Gk == k
+            if not np.any(m):
+                continue
+            Gk = np.zeros((self.P, self.P))
+            Gk[self.Gi[m], self.Gj[m]] = self.Gv[m]
+            W += self.A[k] @ (Um @ Gk.T)
+        return W.T.reshape(-1)
+
+    def assemble(self) -> sp.csr_matrix:
+        """Explicit K = sum_k kron(G_k, A_k) (small sizes)."""
+        K = None
+        for k in range(self.na):
+            term = sp.kron(sp.csr_matrix(self.G_dense_k(k)), self.A[k], format="csr")
+            K = term if K is None else K + term
+        return K.tocsr()
+
+    def block(self, i, j) -> sp.csr_matrix:
+        """K_{ij} = sum_k [G_k]_{ij} A_k."""
+        m = (self.Gi == i) & (self.Gj == j)
+        out = sp.csr_matrix((self.Nh, self.Nh))
+        for k, v in zip(self.Gk[m], self.Gv[m]):
+            out = out + v * self.A[k]
+        return out

@@ -1,0 +1,92 @@
+"""Seeded synthetic inputs for the stochastic-Galerkin diffusion solver.
+
+This module is shared by the CPU oracle, the tests and the benchmark.  It holds
+problem parameters and random draws only -- none of the method's arithmetic
+(no index sets, no triple products, no KL, no finite elements).
+
+Problem parameters follow the paper's problem statement: the unit square with
+homogeneous Dirichlet data (Sec. 2, eq. Strong_PS), the shifted lognormal
+coefficient a = a_min + exp(gamma) with a truncated KL expansion of gamma
+(Sec. 2.1, eqs. aKL / KL_gamma), covariance of eq. standard_deviation, the
+total-degree Hermite space of degree p and the coefficient projection of
+degree q (Sec. 2.2, eq. dataProjection).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, replace, asdict
+import numpy as np
+
+BASE_SEED = 11505
+
+COV_EXP_L1 = "exp_l1"   # sigma^2 exp(-sum_i |x_i - y_i| / L_c)  (eq. standard_deviation)
+COV_SQEXP = "sqexp"     # sigma^2 exp(-sum_i (x_i - y_i)^2 / L_c^2)
+
+
+@dataclass(frozen=True)
+class Problem:
+    """One SG instance. n: elements per side (power of two); M: KL terms;
+    p: chaos degree of u; q: chaos degree of the coefficient."""
+    n: int
+    M: int
+    p: int
+    q: int
+    cov: str = COV_EXP_L1
+    mu: float = 0.0
+    sigma: float = 0.5
+    corr_len: float = 0.5
+    a_min: float = 0.01
+
+    def with_(self, **kw) -> "Problem":
+        return replace(self, **kw)
+
+    def as_dict(self) -> dict:
+        return asdict(self)
+
+
+# Workloads (sizes and value distributions of the paper's experiments, Sec. 4,
+# on Q1 elements): c0 small mean-based case, c1 field-split case, c2 sigma sweep,
+# c4 learned-preconditioner case.  The batched set is drawn by batched_instances.
+CONFIGS = {
+    "c0": Problem(n=32, M=2, p=2, q=4, cov=COV_EXP_L1, sigma=0.5, corr_len=0.5),
+    "c1": Problem(n=128, M=4, p=3, q=6, cov=COV_SQEXP, sigma=1.0, corr_len=0.5),
+    "c2": Problem(n=256, M=6, p=3, q=6, cov=COV_EXP_L1, sigma=1.0, corr_len=0.25),
+    "c4": Problem(n=128, M=4, p=3, q=6, cov=COV_SQEXP, sigma=1.0, corr_len=0.5),
+}
+C2_SIGMAS = (0.5, 1.0, 1.5)
+
+
+def config_seed(index: int) -> int:
+    return BASE_SEED + 1000 * index
+
+
+def rhs_ones(n: int) -> np.ndarray:
+    """f = 1 at all (n+1)^2 grid nodes (row-major, x fastest)."""
+    return np.ones((n + 1) * (n + 1), dtype=np.float64)
+
+
+def rhs_noisy(n: int, seed: int, amp: float = 0.1) -> np.ndarray:
+    """f = 1 + amp * N(0,1) at all (n+1)^2 grid nodes, seeded."""
+    rng = np.random.default_rng(seed)
+    return 1.0 + amp * rng.standard_normal((n + 1) * (n + 1))
+
+
+def random_vector(length: int, seed: int) -> np.ndarray:
+    """Seeded standard-normal FP64 vector (test operands for applies)."""
+    return np.random.default_rng(seed).standard_normal(length)
+
+
+def batched_instances(count: int = 64, seed: int = BASE_SEED + 3000,
+                      grids=(64, 128, 256), Ms=(2, 3, 4, 5, 6), ps=(2, 3, 4)):
+    """Draw `count` uneven instances: grid, KL dimension, degree, sigma and
+    correlation length per instance, plus a per-instance RHS seed."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(count):
+        n = int(rng.choice(grids))
+        M = int(rng.choice(Ms))
+        p = int(rng.choice(ps))
+        sigma = float(rng.uniform(0.3, 1.5))
+        lc = float(rng.uniform(0.2, 1.0))
+        prob = Problem(n=n, M=M, p=p, q=2 * p, cov=COV_EXP_L1, sigma=sigma, corr_len=lc)
+        out.append((prob, seed + 1 + b))
+    return out

@@ -1,0 +1,114 @@
+"""Pins for oracle.system: coefficient modes, K and F (paper Sec. 2.2)."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import fem, pc
+from oracle.system import SGSystem, coeff_modes
+from synth import Problem
+
+
+def _psi_multi(J_row, Y):
+    out = np.ones(Y.shape[0])
+    for n, m in enumerate(J_row):
+        c = np.zeros(int(m) + 1)
+        c[int(m)] = 1.0
+        out *= np.polynomial.hermite_e.hermeval(Y[:, n], c) / math.sqrt(math.factorial(int(m)))
+    return out
+
+
+@pytest.mark.parametrize("M,q,nodes", [(1, 8, 60), (2, 6, 40), (3, 4, 24)])
+def test_coeff_modes_match_gauss_hermite_projection(M, q, nodes):
+    # a_k(x) = E[a_KL(x, y) psi_k(y)] (eq. dataProjection) by tensor quadrature
+    rng = np.random.default_rng(1)
+    g = 0.6 * rng.standard_normal((M, 5))
+    mu, a_min = 0.3, 0.01
+    Jq = pc.multi_indices(M, q)
+    a = coeff_modes(g, Jq, mu, a_min)
+    y, w = np.polynomial.hermite_e.hermegauss(nodes)
+    w = w / math.sqrt(2 * math.pi)
+    Y = np.array(list(itertools.product(y, repeat=M)))
+    W = np.prod(np.array(list(itertools.product(w, repeat=M))), axis=1)
+    for x in range(g.shape[1]):
+        aKL = a_min + np.exp(mu + Y @ g[:, x])
+        for k, kk in enumerate(Jq):
+            ref = np.sum(W * aKL * _psi_multi(kk, Y))
+            assert abs(a[k, x] - ref) <= 1e-12 * max(1.0, abs(ref)), (k, a[k, x], ref)
+
+
+def test_mean_mode_is_expectation():
+    rng = np.random.default_rng(2)
+    g = rng.standard_normal((3, 7))
+    a = coeff_modes(g, pc.multi_indices(3, 2), 0.1, 0.01)
+    assert np.allclose(a[0], 0.01 + np.exp(0.1 + 0.5 * np.sum(g * g, axis=0)), rtol=1e-15)
+
+
+TINY = Problem(n=4, M=2, p=2, q=4, cov="exp_l1", sigma=0.8, corr_len=0.5)
+
+
+def test_apply_equals_assembled():
+    S = SGSystem(TINY)
+    K = S.assemble()
+    U = np.random.default_rng(3).standard_normal(S.P * S.Nh)
+    assert np.allclose(S.apply(U), K @ U, rtol=1e-13, atol=1e-13)
+
+
+def test_K_symmetric_positive_definite():
+    S = SGSystem(TINY.with_(sigma=1.5))
+    K = S.assemble().toarray()
+    assert np.allclose(K, K.T, atol=1e-13)
+    np.linalg.cholesky(K)                      # q >= 2p: exact Galerkin matrix, SPD
+    assert np.linalg.eigvalsh(K).min() > 0
+
+
+def test_blocks_by_direct_quadrature():
+    # independent route: block (i, j) = stiffness with coefficient E[a psi_i psi_j]
+    S = SGSystem(TINY)
+    nodes = 30
+    y, w = np.polynomial.hermite_e.hermegauss(nodes)
+    w = w / math.sqrt(2 * math.pi)
+    Y = np.array(list(itertools.product(y, repeat=2)))
+    W = np.prod(np.array(list(itertools.product(w, repeat=2))), axis=1)
+    aKL = S.prob.a_min + np.exp(S.prob.mu + Y @ S.g)        # (nodes^2, N_q)
+    psis = [_psi_multi(r, Y) for r in S.Jp]
+    K = S.assemble().toarray()
+    for i in range(S.P):
+        for j in range(S.P):
+            cij = (W * psis[i] * psis[j]) @ aKL
+            Bij = fem.stiffness(S.n, cij).toarray()
+            blk = K[i * S.Nh:(i + 1) * S.Nh, j * S.Nh:(j + 1) * S.Nh]
+            assert np.allclose(blk, Bij, rtol=1e-11, atol=1e-12)
+
+
+def test_zero_variance_decouples():
+    S = SGSystem(TINY.with_(sigma=0.0))
+    K = S.assemble().toarray()
+    A0 = S.A[0].toarray()
+    assert np.allclose(K, np.kron(np.eye(S.P), A0), atol=1e-15)
+    u = np.linalg.solve(K, S.rhs())
+    assert np.all(u[S.Nh:] == 0)
+
+
+def test_rhs_loads_only_mean_mode():
+    S = SGSystem(TINY)
+    F = S.rhs()
+    assert np.allclose(F[: S.Nh], 1.0 / 16)
+    assert np.all(F[S.Nh:] == 0)
+
+
+def test_coefficient_chaos_converges_in_q():
+    # sum_k a_k^2 increases to E[a^2] as q grows (Parseval, orthonormal chaos)
+    rng = np.random.default_rng(4)
+    g = 0.5 * rng.standard_normal((2, 3))
+    a_min, mu = 0.01, 0.0
+    sig2 = np.sum(g * g, axis=0)
+    Ea2 = a_min ** 2 + 2 * a_min * np.exp(mu + sig2 / 2) + np.exp(2 * mu + 2 * sig2)
+    prev = 0
+    for q in (2, 4, 8, 16):
+        s = np.sum(coeff_modes(g, pc.multi_indices(2, q), mu, a_min) ** 2, axis=0)
+        assert np.all(s >= prev - 1e-15) and np.all(s <= Ea2 * (1 + 1e-14))
+        prev = s
+    assert np.allclose(prev, Ea2, rtol=1e-10)
