@@ -1,0 +1,172 @@
+/*
+ * sg.h -- C ABI of the MI355X stochastic-Galerkin diffusion solver.
+ *
+ * Solves the stochastic Galerkin (SG) system K u = F of
+ *     -div(a(x, y) grad u) = f  on the unit square, u = 0 on the boundary,
+ * with the shifted lognormal coefficient a = a_min + exp(gamma), gamma a
+ * Gaussian field given by a truncated Karhunen-Loeve (KL) expansion
+ * (Aulisa, Capodaglio, Ke: Sec. 2, eqs. Strong_PS, aKL, KL_gamma,
+ * standard_deviation), discretised by Q1 finite elements in space and an
+ * orthonormal Hermite chaos of total degree p in the random variables
+ * (Sec. 2.2), K = sum_k G_k (x) A_k with [G_k]_{ij} = E[psi_k psi_i psi_j].
+ *
+ * Conventions for every entry point:
+ *  - Device pointers are FP64, contiguous, and owned by the caller; the
+ *    library never frees them.  SG vectors are mode-major: entry
+ *    i*N_h + (iy-1)(n-1) + (ix-1) holds mode i at interior grid node
+ *    (ix, iy), 1 <= ix, iy <= n-1 (Dirichlet nodes eliminated), modes in the
+ *    graded, descending-lexicographic order of the index set J(p).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls are asynchronous on that stream unless stated otherwise.
+ *  - Return value: SG_OK (0) or a negative SG_ERR_* code; sg_last_error()
+ *    then gives a message (thread-local, valid until the next call on the
+ *    same thread).  No C++ exception crosses this interface.
+ *  - A handle may be used by one host thread at a time.  Calls on one handle
+ *    share its workspace: calls that overlap in time on different streams race.
+ */
+#ifndef SG_H
+#define SG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SG_OK = 0,
+  SG_ERR_INVALID_ARG = -1,  /* argument outside its documented range        */
+  SG_ERR_UNSUPPORTED = -2,  /* valid, but beyond a compiled limit           */
+  SG_ERR_HIP = -3,          /* a HIP runtime call failed                    */
+  SG_ERR_NOT_BOUND = -4,    /* the handle has no device workspace yet       */
+  SG_ERR_WORKSPACE = -5,    /* workspace too small or misaligned            */
+  SG_ERR_INTERNAL = -6
+};
+
+/* sg_solve_info.status (not errors) */
+enum { SG_CONVERGED = 0, SG_NOT_CONVERGED = 1, SG_BREAKDOWN = 2 };
+
+/* covariance of gamma: eq. standard_deviation (L1 exponential) or the squared
+ * exponential sigma^2 exp(-sum_i (x_i - x'_i)^2 / L_c^2) */
+enum { SG_COV_EXP_L1 = 0, SG_COV_SQEXP = 1 };
+
+/* preconditioners (Sec. 3): none, mean-based (one V(2,2) cycle on the mean
+ * stiffness A_0 per mode), field split (forward block Gauss-Seidel over
+ * ordered splits of the modes, eqs. P_preconditioner / P_group, with the
+ * same V-cycle for every diagonal block) */
+enum { SG_PC_NONE = 0, SG_PC_MEAN = 1, SG_PC_FS = 2 };
+
+/* splits of the modes for SG_PC_FS:
+ *  KLVAR         split n = modes whose first nonzero index is n; mean in split 1
+ *  KLVAR_MEANSEP KLVAR with the mean mode as its own first split
+ *  PERMODE       one split per mode (the paper's G-M-F-I splitting)
+ *  FG            the paper's leading-digit grouping (Sec. 3, worked example
+ *                N=2, p=4 -> splits of 5, 4, 6 modes)                        */
+enum { SG_GROUP_KLVAR = 0, SG_GROUP_KLVAR_MEANSEP = 1, SG_GROUP_PERMODE = 2, SG_GROUP_FG = 3 };
+
+/* Problem statement (Sec. 2, Sec. 2.1, Sec. 2.2):
+ *  n         elements per side, power of two, 4 <= n <= 4096
+ *  M         KL terms (the paper's N), 1 <= M <= 12
+ *  p         chaos degree of u; P = (M+p)!/(M!p!) modes, 1 <= P <= 256
+ *  q         chaos degree of the coefficient projection (eq. dataProjection),
+ *            0 <= q <= 16; q >= 2p makes K the exact Galerkin matrix
+ *  cov       SG_COV_*; mu, sigma >= 0, corr_len > 0, a_min >= 0 as in
+ *            eqs. aKL / KL_gamma / standard_deviation                        */
+typedef struct {
+  int32_t n, M, p, q, cov;
+  double mu, sigma, corr_len, a_min;
+} sg_problem;
+
+/* GMRES(restart) options (Sec. 3): right preconditioning, CGS2 Arnoldi.
+ *  restart 1..200; max_it >= 1 total iterations; pc SG_PC_*; grouping
+ *  SG_GROUP_* (used when pc == SG_PC_FS); use_x0 != 0 starts from the
+ *  content of u; tol > 0 on the true relative residual ||F-Ku||/||F||.      */
+typedef struct {
+  int32_t restart, max_it, pc, grouping, use_x0;
+  double tol;
+} sg_solve_opts;
+
+typedef struct {
+  int32_t status;       /* SG_CONVERGED / SG_NOT_CONVERGED / SG_BREAKDOWN   */
+  int32_t iterations;   /* Arnoldi steps taken                              */
+  int32_t restarts;     /* completed cycles                                 */
+  int32_t reserved;
+  double relres;        /* true ||F - K u|| / ||F|| in FP64 at exit          */
+  double relres_est;    /* last rotated residual estimate / ||F||           */
+} sg_solve_info;
+
+typedef struct sg_handle sg_handle;
+
+/* Host-side set-up of one instance (Sec. 2.1 and 2.2): index sets J(p), J(q),
+ * the triple products G_k, the KL eigenpairs from a 1D Galerkin procedure on
+ * the grid (tensor products on the square), the KL modes at the 2x2 Gauss
+ * points, and the field-split groupings.  f_nodal: host array of (n+1)^2
+ * nodal forcing values (row-major, x fastest), or NULL for f = 1; copied.
+ * *out receives a new handle (free with sg_destroy).  No device work.      */
+int sg_setup(const sg_problem* prob, const double* f_nodal, sg_handle** out);
+
+/* Sizes: P modes, N_h = (n-1)^2 unknowns per mode, n_a coefficient modes,
+ * nnz_G nonzero triple products (any pointer may be NULL).                 */
+int sg_sizes(const sg_handle* h, int64_t* P, int64_t* N_h, int64_t* n_a, int64_t* nnz_G);
+
+/* Device bytes sg_bind needs (coefficient modes a_k at every quadrature
+ * point, stencils of all multigrid levels, triple-product tables, scratch). */
+size_t sg_workspace_bytes(const sg_handle* h);
+
+/* Binds a caller-owned device workspace (>= sg_workspace_bytes, 256-byte
+ * aligned), uploads the set-up tables and computes on the device the
+ * coefficient modes a_k(x_q) (eq. dataProjection in closed form), the mean
+ * stiffness stencil and its Galerkin coarse stencils.  Synchronises
+ * `stream` before returning.  The workspace must outlive the handle's use. */
+int sg_bind(sg_handle* h, void* dev_workspace, size_t bytes, void* stream);
+
+/* F = e_0 (x) M_h f_h (Sec. 2.2, right-hand side of eq. stochastic_matrix):
+ * writes P*N_h values to the device array F.                               */
+int sg_rhs(sg_handle* h, double* F, void* stream);
+
+/* W = K U = sum_k vec(A_k U G_k^T) (Sec. 2.2, definition of K), matrix-free
+ * from a_k at the quadrature points.  U, W: device, P*N_h, must not alias. */
+int sg_apply(sg_handle* h, const double* U, double* W, void* stream);
+
+/* z = P^{-1} r for pc in {SG_PC_NONE, SG_PC_MEAN, SG_PC_FS} and a grouping
+ * (Sec. 3, eqs. P_preconditioner / P_group).  r, z: device, P*N_h, must not
+ * alias.                                                                    */
+int sg_precond_apply(sg_handle* h, int pc, int grouping, const double* r, double* z,
+                     void* stream);
+
+/* Device bytes of the Krylov workspace sg_gmres_solve needs for `opts`.    */
+size_t sg_gmres_workspace_bytes(const sg_handle* h, const sg_solve_opts* opts);
+
+/* Right-preconditioned restarted GMRES for K u = F (Sec. 3).  F: device
+ * right-hand side; u: device solution (initial guess if opts->use_x0);
+ * krylov_ws: caller-owned device buffer of sg_gmres_workspace_bytes bytes;
+ * resid_hist: optional host array receiving the relative residual estimate
+ * after every iteration (entry 0 = initial), at most hist_len entries.
+ * Synchronises `stream`; fills *info.  Non-convergence is reported in
+ * info->status, not as an error.                                          */
+int sg_gmres_solve(sg_handle* h, const sg_solve_opts* opts, const double* F, double* u,
+                   void* krylov_ws, size_t ws_bytes, double* resid_hist, int32_t hist_len,
+                   sg_solve_info* info, void* stream);
+
+/* Copies a set-up table to host memory (for verification):
+ *  SG_EXPORT_COEFF  a_k(x_q), n_a x 4n^2 values, q = 4e + 2qy + qx,
+ *                   e = ey*n + ex (synchronous)
+ *  SG_EXPORT_KL     lambda_1..lambda_M (host table)
+ *  SG_EXPORT_GQ     g_m(x_q) = sqrt(lambda_m) b_m(x_q), M x 4n^2 (host table)
+ *  SG_EXPORT_STENCIL the 9-point mean stiffness of multigrid level `level`
+ *                   (0 = finest), 9 x (n_l - 1)^2 values, entry s*N_l + node,
+ *                   s = 3(dy+1) + (dx+1) (synchronous)
+ *  SG_EXPORT_GROUPS for grouping `level`: the number of splits, then for
+ *                   each split its size followed by its mode indices      */
+enum { SG_EXPORT_COEFF = 0, SG_EXPORT_KL = 1, SG_EXPORT_GQ = 2, SG_EXPORT_STENCIL = 3,
+       SG_EXPORT_GROUPS = 4 };
+int sg_export(sg_handle* h, int what, int level, double* host_out, size_t count);
+
+void sg_destroy(sg_handle* h);
+const char* sg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SG_H */

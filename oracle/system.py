@@ -56,9 +56,16 @@ class SGSystem:
         self.Gk, self.Gi, self.Gj, self.Gv = pc.triple_products(self.Jp, self.Jq)
         self.lam, self.B, self.pairs = kl.kl_2d(n, prob.cov, prob.corr_len, prob.sigma, prob.M)
         self.g = kl.g_at_quad(n, self.lam, self.B)
-        self.a = coeff_modes(self.g, self.Jq, prob.mu, prob.a_min)
+        self._a = None
         self.f_nodal = np.ones((n + 1) ** 2) if f_nodal is None else np.asarray(f_nodal, float)
         self._A = None
+
+    @property
+    def a(self):
+        """Coefficient modes at every quadrature point, (n_a, N_q) (computed on first use)."""
+        if self._a is None:
+            self._a = coeff_modes(self.g, self.Jq, self.prob.mu, self.prob.a_min)
+        return self._a
 
     # -- per-mode stiffness matrices (eq. A_q) -------------------------------
     @property
@@ -105,4 +112,35 @@ class SGSystem:
         out = sp.csr_matrix((self.Nh, self.Nh))
         for k, v in zip(self.Gk[m], self.Gv[m]):
             out = out + v * self.A[k]
+        return out
+
+    def apply_at(self, U: np.ndarray, modes, nodes) -> np.ndarray:
+        """(K U) at selected (mode, interior node) pairs, straight from the
+        definition: sum over the node's elements and their Gauss points of
+        (1/4) grad phi_node . sum_k a_k sum_j [G_k]_{ij} grad U_j.
+        Returns an array (len(modes), len(nodes)); for large grids where
+        assembling every A_k is impractical."""
+        n = self.n
+        Um = U.reshape(self.P, self.Nh)
+        G = fem.ref_grads()                                   # (q, a, 2)
+        out = np.zeros((len(modes), len(nodes)))
+        for t, node in enumerate(nodes):
+            ix, iy = node % (n - 1) + 1, node // (n - 1) + 1
+            for ey in (iy - 1, iy):
+                for ex in (ix - 1, ix):
+                    e = ey * n + ex
+                    la = (ix - ex) + 2 * (iy - ey)
+                    corners = [(ex, ey), (ex + 1, ey), (ex, ey + 1), (ex + 1, ey + 1)]
+                    uc = np.zeros((self.P, 4))
+                    for b, (cx, cy) in enumerate(corners):
+                        if 1 <= cx <= n - 1 and 1 <= cy <= n - 1:
+                            uc[:, b] = Um[:, (cy - 1) * (n - 1) + (cx - 1)]
+                    gq = self.g[:, 4 * e:4 * e + 4]
+                    aq = coeff_modes(gq, self.Jq, self.prob.mu, self.prob.a_min)   # (n_a, 4)
+                    for q in range(4):
+                        gradU = uc @ G[q]                               # (P, 2)
+                        C = np.zeros((self.P, self.P))
+                        np.add.at(C, (self.Gi, self.Gj), aq[self.Gk, q] * self.Gv)
+                        flux = C @ gradU                                # (P, 2)
+                        out[:, t] += 0.25 * flux[list(modes)] @ G[q, la]
         return out

@@ -1,0 +1,15 @@
+"""MI355X stochastic-Galerkin diffusion solver (HIP, gfx950).
+
+Thin Python binding over the C ABI of libsgfs.so (include/sg.h).  Every step
+of the solve runs in the library's HIP kernels; this package only marshals
+arguments and owns device memory through PyTorch tensors.  Importing the
+binding does not load the library; the first call does, and fails loudly when
+the library has not been built.
+"""
+from .binding import (  # noqa: F401
+    SGError, Problem, SolveOpts, SolveInfo, load_library, library_path,
+    sg_setup, sg_sizes, sg_workspace_bytes, sg_bind, sg_rhs, sg_apply,
+    sg_precond_apply, sg_gmres_workspace_bytes, sg_gmres_solve, sg_export,
+    sg_destroy, sg_last_error, SGInstance,
+    COV, PC, GROUPING, EXPORT,
+)

@@ -1,0 +1,258 @@
+"""ctypes binding of include/sg.h (same names, argument marshalling only).
+
+Device arguments are torch CUDA (HIP) tensors of dtype float64 or raw integer
+device addresses; `stream` is a torch.cuda.Stream, a raw hipStream_t integer,
+or None for the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+COV = {"exp_l1": 0, "sqexp": 1}
+PC = {"none": 0, "mean": 1, "fs": 2}
+GROUPING = {"klvar": 0, "klvar_meansep": 1, "permode": 2, "fg": 3}
+EXPORT = {"coeff": 0, "kl": 1, "gq": 2, "stencil": 3, "groups": 4}
+STATUS = {0: "converged", 1: "not_converged", 2: "breakdown"}
+
+
+class SGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sg error {code}: {msg}")
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("M", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("q", ctypes.c_int32), ("cov", ctypes.c_int32), ("mu", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("corr_len", ctypes.c_double),
+                ("a_min", ctypes.c_double)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int32), ("max_it", ctypes.c_int32), ("pc", ctypes.c_int32),
+                ("grouping", ctypes.c_int32), ("use_x0", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("restarts", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("relres", ctypes.c_double), ("relres_est", ctypes.c_double)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return os.environ.get("SG_LIBRARY", os.path.join(HERE, "libsgfs.so"))
+
+
+def load_library():
+    """Loads libsgfs.so; raises if it is missing (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing "
+                           "(run python -m paper_1910_11505_amd.build)")
+    lib = ctypes.CDLL(path)
+    P, VP, SZ, I32, I64P = ctypes.POINTER, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)
+    HP = ctypes.c_void_p
+    sig = {
+        "sg_setup": (I32, [P(Problem), VP, P(HP)]),
+        "sg_sizes": (I32, [HP, I64P, I64P, I64P, I64P]),
+        "sg_workspace_bytes": (SZ, [HP]),
+        "sg_bind": (I32, [HP, VP, SZ, VP]),
+        "sg_rhs": (I32, [HP, VP, VP]),
+        "sg_apply": (I32, [HP, VP, VP, VP]),
+        "sg_precond_apply": (I32, [HP, I32, I32, VP, VP, VP]),
+        "sg_gmres_workspace_bytes": (SZ, [HP, P(SolveOpts)]),
+        "sg_gmres_solve": (I32, [HP, P(SolveOpts), VP, VP, VP, SZ, VP, ctypes.c_int32,
+                                 P(SolveInfo), VP]),
+        "sg_export": (I32, [HP, I32, I32, VP, SZ]),
+        "sg_destroy": (None, [HP]),
+        "sg_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise SGError(rc, load_library().sg_last_error().decode())
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def make_problem(n, M, p, q, cov="exp_l1", mu=0.0, sigma=0.5, corr_len=0.5, a_min=0.01):
+    return Problem(n, M, p, q, COV[cov] if isinstance(cov, str) else int(cov), mu, sigma,
+                   corr_len, a_min)
+
+
+# ---- same names as the C ABI ------------------------------------------------
+def sg_setup(prob: Problem, f_nodal=None):
+    import numpy as np
+    lib = load_library()
+    h = ctypes.c_void_p()
+    fp = None
+    if f_nodal is not None:
+        f_nodal = np.ascontiguousarray(f_nodal, dtype=np.float64)
+        fp = f_nodal.ctypes.data
+    _check(lib.sg_setup(ctypes.byref(prob), fp, ctypes.byref(h)))
+    return h
+
+
+def sg_sizes(h):
+    vals = [ctypes.c_int64() for _ in range(4)]
+    _check(load_library().sg_sizes(h, *[ctypes.byref(v) for v in vals]))
+    return tuple(v.value for v in vals)
+
+
+def sg_workspace_bytes(h) -> int:
+    return int(load_library().sg_workspace_bytes(h))
+
+
+def sg_bind(h, ws, nbytes, stream=None):
+    _check(load_library().sg_bind(h, _ptr(ws), nbytes, _stream(stream)))
+
+
+def sg_rhs(h, F, stream=None):
+    _check(load_library().sg_rhs(h, _ptr(F), _stream(stream)))
+
+
+def sg_apply(h, U, W, stream=None):
+    _check(load_library().sg_apply(h, _ptr(U), _ptr(W), _stream(stream)))
+
+
+def sg_precond_apply(h, pc, grouping, r, z, stream=None):
+    pc = PC[pc] if isinstance(pc, str) else int(pc)
+    grouping = GROUPING[grouping] if isinstance(grouping, str) else int(grouping)
+    _check(load_library().sg_precond_apply(h, pc, grouping, _ptr(r), _ptr(z), _stream(stream)))
+
+
+def sg_gmres_workspace_bytes(h, opts: SolveOpts) -> int:
+    return int(load_library().sg_gmres_workspace_bytes(h, ctypes.byref(opts)))
+
+
+def sg_gmres_solve(h, opts: SolveOpts, F, u, ws, nbytes, hist=None, stream=None):
+    info = SolveInfo()
+    hp, hl = None, 0
+    if hist is not None:
+        hp, hl = hist.ctypes.data, len(hist)
+    _check(load_library().sg_gmres_solve(h, ctypes.byref(opts), _ptr(F), _ptr(u), _ptr(ws), nbytes,
+                                         hp, hl, ctypes.byref(info), _stream(stream)))
+    return info
+
+
+def sg_export(h, what, level, out):
+    what = EXPORT[what] if isinstance(what, str) else int(what)
+    _check(load_library().sg_export(h, what, level, out.ctypes.data, out.size))
+
+
+def sg_destroy(h):
+    load_library().sg_destroy(h)
+
+
+def sg_last_error() -> str:
+    return load_library().sg_last_error().decode()
+
+
+# ---- convenience owner of one bound instance ------------------------------
+class SGInstance:
+    """One problem bound to a device workspace owned by a torch uint8 tensor."""
+
+    def __init__(self, n, M, p, q, cov="exp_l1", mu=0.0, sigma=0.5, corr_len=0.5, a_min=0.01,
+                 f_nodal=None, device="cuda:0", stream=None):
+        import torch
+        self.prob = make_problem(n, M, p, q, cov, mu, sigma, corr_len, a_min)
+        self.h = sg_setup(self.prob, f_nodal)
+        self.P, self.Nh, self.na, self.nnz = sg_sizes(self.h)
+        self.device = torch.device(device)
+        self.stream = stream
+        nb = sg_workspace_bytes(self.h)
+        self.ws = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        sg_bind(self.h, self.ws.data_ptr() + off, nb, stream)
+        self._kws = None
+        self._kws_key = None
+
+    @property
+    def nvec(self):
+        return self.P * self.Nh
+
+    def vec(self):
+        import torch
+        return torch.zeros(self.nvec, dtype=torch.float64, device=self.device)
+
+    def rhs(self):
+        F = self.vec()
+        sg_rhs(self.h, F, self.stream)
+        return F
+
+    def apply(self, U, W=None):
+        W = self.vec() if W is None else W
+        sg_apply(self.h, U, W, self.stream)
+        return W
+
+    def precond(self, r, pc="mean", grouping="klvar", z=None):
+        z = self.vec() if z is None else z
+        sg_precond_apply(self.h, pc, grouping, r, z, self.stream)
+        return z
+
+    def solve(self, F=None, pc="fs", grouping="klvar", restart=50, max_it=5000, tol=1e-8,
+              u=None, use_x0=False, hist_len=0):
+        import numpy as np
+        import torch
+        F = self.rhs() if F is None else F
+        u = self.vec() if u is None else u
+        opts = SolveOpts(restart, max_it, PC[pc], GROUPING[grouping], 1 if use_x0 else 0, tol)
+        nb = sg_gmres_workspace_bytes(self.h, opts)
+        if self._kws is None or self._kws.numel() < nb + 256:
+            self._kws = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._kws.data_ptr()) % 256
+        hist = np.zeros(hist_len) if hist_len else None
+        info = sg_gmres_solve(self.h, opts, F, u, self._kws.data_ptr() + off, nb, hist, self.stream)
+        return u, info, hist
+
+    def export(self, what, level=0, count=None):
+        import numpy as np
+        if count is None:
+            count = {"coeff": self.na * 4 * self.prob.n ** 2, "kl": self.prob.M,
+                     "gq": self.prob.M * 4 * self.prob.n ** 2}.get(what)
+        out = np.zeros(count)
+        sg_export(self.h, what, level, out)
+        return out
+
+    def close(self):
+        if self.h:
+            sg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,733 @@
+// C ABI of the SG solver: handle life cycle, workspace layout, operator and
+// preconditioner applies, and the restarted GMRES driver.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "sg_internal.h"
+
+using namespace sg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define SG_HIP(call)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      throw Error(SG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+constexpr double kOmega = 8.0 / 9.0;
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct FSHost {
+  std::vector<std::vector<int>> splits;
+  std::vector<RowSetHost> partial;  // partial[s] for s >= 1 (index 0 unused)
+  std::vector<int> kc, nchunk;      // chunking of each partial row set
+};
+
+struct FSDev {
+  std::vector<int*> split_idx;
+  std::vector<RowSetDev> partial;
+};
+
+// every device pointer inside the bound workspace
+struct DevPtrs {
+  double *a = nullptr, *g = nullptr, *isf = nullptr, *f = nullptr;
+  int* Jq = nullptr;
+  std::vector<Level> L;
+  RowSetDev full{};
+  FSDev fs[4];
+  double* edge = nullptr;
+  std::vector<double*> mg_b, mg_x, mg_xa, mg_r;
+  double *fsT = nullptr, *fsX = nullptr;
+};
+
+// bump allocator over the caller's workspace (or a dry run to size it)
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += align256(count * sizeof(T));
+    return p;
+  }
+};
+
+}  // namespace
+
+struct sg_handle {
+  sg_problem prob{};
+  int n = 0, M = 0, P = 0, na = 0, nt = 0, ntiles = 0;
+  int64_t Nh = 0, Nq = 0;
+  std::vector<std::vector<int>> Jp, Jq;
+  std::vector<Triple> G;
+  KL kl;
+  std::vector<double> f_nodal, g_tiled, isf;
+  std::vector<int> Jq_flat;
+  RowSetHost full;
+  int full_kc = 0, full_nchunk = 0;
+  FSHost fs[4];
+  std::vector<int> level_n;
+
+  // device state
+  bool bound = false;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  DevPtrs d;
+  double* host_pinned = nullptr;  // small staging for Krylov scalars
+
+  ~sg_handle() {
+    if (host_pinned) (void)hipHostFree(host_pinned);
+  }
+};
+
+namespace {
+
+// kc: modes of a_k staged per chunk; keep LDS <= 80 KB (two workgroups per CU)
+// when the gradients allow, else use the whole 160 KB.
+int choose_kc(int ncols, int na) {
+  auto fit = [&](size_t budget) {
+    long avail = (long)(budget / 8) - 2L * ncols * kTileQ;
+    return (int)(avail / kTileQ);
+  };
+  int kc = fit(80 * 1024);
+  if (kc < 16) kc = fit(160 * 1024);
+  kc = std::min(kc, 128);
+  kc = std::min(kc, na);
+  if (kc < 1 || apply_lds_bytes(ncols, std::max(kc, 1)) > 160 * 1024)
+    throw Error(SG_ERR_UNSUPPORTED, "apply: the gradients of " + std::to_string(ncols) +
+                                        " modes do not fit in LDS");
+  return kc;
+}
+
+RowSetHost build_rowset(const sg_handle& H, const std::vector<int>& rows,
+                        const std::vector<int>& cols, int& kc_out, int& nchunk_out) {
+  RowSetHost rs;
+  rs.rows = rows;
+  rs.cols = cols;
+  rs.nrows = (int)rows.size();
+  rs.ncols = (int)cols.size();
+  const int kc = choose_kc(std::max(rs.ncols, 1), H.na);
+  const int nchunk = (H.na + kc - 1) / kc;
+  std::vector<int> rslot(H.P, -1), cslot(H.P, -1);
+  for (int t = 0; t < rs.nrows; ++t) rslot[rows[t]] = t;
+  for (int t = 0; t < rs.ncols; ++t) cslot[cols[t]] = t;
+  std::vector<std::vector<std::vector<std::pair<int, double>>>> bucket(
+      rs.nrows, std::vector<std::vector<std::pair<int, double>>>(nchunk));
+  for (const Triple& tr : H.G) {
+    int r = rslot[tr.i], c = cslot[tr.j];
+    if (r < 0 || c < 0) continue;
+    int ch = tr.k / kc;
+    bucket[r][ch].push_back({(tr.k - ch * kc) | (c << 16), tr.v});
+  }
+  rs.ptr.assign((size_t)rs.nrows * (nchunk + 1), 0);
+  std::vector<long> load(rs.nrows, 0);
+  for (int r = 0; r < rs.nrows; ++r) {
+    rs.ptr[(size_t)r * (nchunk + 1)] = (int)rs.kj.size();
+    for (int ch = 0; ch < nchunk; ++ch) {
+      for (auto& e : bucket[r][ch]) {
+        rs.kj.push_back(e.first);
+        rs.v.push_back(e.second);
+      }
+      rs.ptr[(size_t)r * (nchunk + 1) + ch + 1] = (int)rs.kj.size();
+    }
+    load[r] = rs.ptr[(size_t)r * (nchunk + 1) + nchunk] - rs.ptr[(size_t)r * (nchunk + 1)];
+  }
+  // rows to wavefronts: longest rows first onto the least loaded wavefront
+  const int need = std::max(1, (rs.nrows + kApplyWaves - 1) / kApplyWaves);
+  int rmax = 1;
+  while (rmax < need) rmax *= 2;
+  if (rmax > 64) throw Error(SG_ERR_UNSUPPORTED, "apply: too many rows per wavefront");
+  rs.rmax = rmax;
+  rs.wrows.assign((size_t)kApplyWaves * rmax, -1);
+  std::vector<int> order(rs.nrows);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return load[a] > load[b]; });
+  std::vector<long> wl(kApplyWaves, 0);
+  std::vector<int> wc(kApplyWaves, 0);
+  for (int r : order) {
+    int best = -1;
+    for (int w = 0; w < kApplyWaves; ++w)
+      if (wc[w] < need && (best < 0 || wl[w] < wl[best])) best = w;
+    rs.wrows[(size_t)best * rmax + wc[best]] = r;
+    wc[best]++;
+    wl[best] += load[r];
+  }
+  kc_out = kc;
+  nchunk_out = nchunk;
+  return rs;
+}
+
+void validate(const sg_problem& p) {
+  auto bad = [](const std::string& m) { throw Error(SG_ERR_INVALID_ARG, m); };
+  if (p.n < 4 || p.n > 4096 || (p.n & (p.n - 1))) bad("n must be a power of two in [4, 4096]");
+  if (p.M < 1 || p.M > 12) bad("M must be in [1, 12]");
+  if (p.p < 0 || p.q < 0 || p.q > 16) bad("p >= 0 and 0 <= q <= 16 required");
+  if (p.cov != SG_COV_EXP_L1 && p.cov != SG_COV_SQEXP) bad("unknown covariance");
+  if (!(p.sigma >= 0.0) || !(p.corr_len > 0.0) || !(p.a_min >= 0.0) || !std::isfinite(p.mu) ||
+      !std::isfinite(p.sigma) || !std::isfinite(p.corr_len) || !std::isfinite(p.a_min))
+    bad("need sigma >= 0, corr_len > 0, a_min >= 0, all finite");
+}
+
+// workspace layout: carved identically for sizing (base = nullptr) and binding
+void carve(const sg_handle& H, DevPtrs& D, Carver& c) {
+  D.a = c.take<double>((size_t)H.na * H.Nq);
+  D.g = c.take<double>((size_t)H.M * H.Nq);
+  D.isf = c.take<double>(H.na);
+  D.Jq = c.take<int>((size_t)H.na * H.M);
+  D.f = c.take<double>((size_t)(H.n + 1) * (H.n + 1));
+  D.L.clear();
+  for (int ln : H.level_n) {
+    Level lv;
+    lv.n = ln;
+    lv.N = (int64_t)(ln - 1) * (ln - 1);
+    lv.S = c.take<double>(9 * (size_t)lv.N);
+    D.L.push_back(lv);
+  }
+  auto put_rowset = [&](const RowSetHost& rs, RowSetDev& d) {
+    d.nrows = rs.nrows;
+    d.ncols = rs.ncols;
+    d.rmax = rs.rmax;
+    d.rows = c.take<int>(rs.rows.size());
+    d.cols = c.take<int>(std::max<size_t>(rs.cols.size(), 1));
+    d.wrows = c.take<int>(rs.wrows.size());
+    d.ptr = c.take<int>(rs.ptr.size());
+    d.kj = c.take<int>(std::max<size_t>(rs.kj.size(), 1));
+    d.v = c.take<double>(std::max<size_t>(rs.v.size(), 1));
+  };
+  put_rowset(H.full, D.full);
+  for (int g = 0; g < 4; ++g) {
+    const FSHost& fh = H.fs[g];
+    FSDev& fd = D.fs[g];
+    fd.split_idx.assign(fh.splits.size(), nullptr);
+    fd.partial.assign(fh.splits.size(), RowSetDev{});
+    for (size_t s = 0; s < fh.splits.size(); ++s) {
+      fd.split_idx[s] = c.take<int>(fh.splits[s].size());
+      if (s >= 1) put_rowset(fh.partial[s], fd.partial[s]);
+    }
+  }
+  D.edge = c.take<double>((size_t)H.P * H.ntiles * kEdgeVals);
+  const size_t nl = D.L.size();
+  D.mg_b.assign(nl, nullptr);
+  D.mg_x.assign(nl, nullptr);
+  D.mg_xa.assign(nl, nullptr);
+  D.mg_r.assign(nl, nullptr);
+  for (size_t l = 0; l < nl; ++l) {
+    const size_t sz = (size_t)H.P * D.L[l].N;
+    if (l > 0) {
+      D.mg_b[l] = c.take<double>(sz);
+      D.mg_x[l] = c.take<double>(sz);
+    }
+    D.mg_xa[l] = c.take<double>(sz);
+    D.mg_r[l] = c.take<double>(sz);
+  }
+  D.fsT = c.take<double>((size_t)H.P * H.Nh);
+  D.fsX = c.take<double>((size_t)H.P * H.Nh);
+}
+
+template <class T>
+void upload(hipStream_t s, const T* dst, const std::vector<T>& src) {
+  if (!src.empty())
+    SG_HIP(hipMemcpyAsync(const_cast<T*>(dst), src.data(), src.size() * sizeof(T),
+                          hipMemcpyHostToDevice, s));
+}
+
+void upload_rowset(hipStream_t s, const RowSetHost& h, const RowSetDev& d) {
+  upload(s, d.rows, h.rows);
+  upload(s, d.cols, h.cols);
+  upload(s, d.wrows, h.wrows);
+  upload(s, d.ptr, h.ptr);
+  upload(s, d.kj, h.kj);
+  upload(s, d.v, h.v);
+}
+
+void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(SG_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+void vcycle(sg_handle& H, hipStream_t s, size_t lvl, int m, const double* b, double* x) {
+  DevPtrs& D = H.d;
+  const Level& Lv = D.L[lvl];
+  if (lvl + 1 == D.L.size()) {
+    launch_coarse(s, Lv, m, b, x);
+    return;
+  }
+  double* xa = D.mg_xa[lvl];
+  double* r = D.mg_r[lvl];
+  launch_jacobi(s, Lv, m, b, nullptr, xa, kOmega, true);
+  launch_jacobi(s, Lv, m, b, xa, x, kOmega, false);
+  launch_residual(s, Lv, m, b, x, r);
+  launch_restrict(s, Lv, D.L[lvl + 1], m, r, D.mg_b[lvl + 1]);
+  vcycle(H, s, lvl + 1, m, D.mg_b[lvl + 1], D.mg_x[lvl + 1]);
+  launch_prolong_add(s, Lv, D.L[lvl + 1], m, D.mg_x[lvl + 1], x);
+  launch_jacobi(s, Lv, m, b, x, xa, kOmega, false);
+  launch_jacobi(s, Lv, m, b, xa, x, kOmega, false);
+}
+
+void do_apply(sg_handle& H, hipStream_t s, const double* U, double* W) {
+  launch_apply(s, H.n, H.full_nchunk, H.full_kc, H.na, H.d.a, H.d.full, U, H.Nh, nullptr, 0.0,
+               1.0, W, H.d.edge);
+}
+
+void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double* r, double* z) {
+  const int64_t Nv = (int64_t)H.P * H.Nh;
+  if (pc == SG_PC_NONE) {
+    SG_HIP(hipMemcpyAsync(z, r, Nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  if (pc == SG_PC_MEAN) {
+    vcycle(H, s, 0, H.P, r, z);
+    return;
+  }
+  if (pc != SG_PC_FS) throw Error(SG_ERR_INVALID_ARG, "unknown preconditioner");
+  if (grouping < 0 || grouping > 3) throw Error(SG_ERR_INVALID_ARG, "unknown grouping");
+  const FSHost& fh = H.fs[grouping];
+  const FSDev& fd = H.d.fs[grouping];
+  for (size_t sp = 0; sp < fh.splits.size(); ++sp) {
+    const int m = (int)fh.splits[sp].size();
+    if (sp == 0) {
+      launch_gather_modes(s, m, fd.split_idx[0], H.Nh, r, H.d.fsT);
+    } else {
+      launch_apply(s, H.n, fh.nchunk[sp], fh.kc[sp], H.na, H.d.a, fd.partial[sp], z, H.Nh, r, 1.0,
+                   -1.0, H.d.fsT, H.d.edge);
+    }
+    vcycle(H, s, 0, m, H.d.fsT, H.d.fsX);
+    launch_scatter_modes(s, m, fd.split_idx[sp], H.Nh, H.d.fsX, z);
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* sg_last_error(void) { return g_last_error.c_str(); }
+
+int sg_setup(const sg_problem* prob, const double* f_nodal, sg_handle** out) {
+  if (!prob || !out) return fail(SG_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  try {
+    validate(*prob);
+    auto H = std::make_unique<sg_handle>();
+    H->prob = *prob;
+    H->n = prob->n;
+    H->M = prob->M;
+    H->Nh = (int64_t)(H->n - 1) * (H->n - 1);
+    H->Nq = (int64_t)4 * H->n * H->n;
+    H->nt = H->n / kTileE;
+    H->ntiles = H->nt * H->nt;
+    H->Jp = total_degree_set(prob->M, prob->p);
+    H->Jq = total_degree_set(prob->M, prob->q);
+    H->P = (int)H->Jp.size();
+    H->na = (int)H->Jq.size();
+    if (H->P > kMaxP) throw Error(SG_ERR_UNSUPPORTED, "P exceeds 256 modes");
+    if (H->na > 65535) throw Error(SG_ERR_UNSUPPORTED, "too many coefficient modes");
+    H->G = triple_list(H->Jp, H->Jq);
+    H->kl = karhunen_loeve(H->n, prob->cov, prob->corr_len, prob->sigma, prob->M);
+    // tile-major copy of g_m(x_q)
+    H->g_tiled.assign((size_t)H->M * H->Nq, 0.0);
+    for (int m = 0; m < H->M; ++m)
+      for (int ey = 0; ey < H->n; ++ey)
+        for (int ex = 0; ex < H->n; ++ex)
+          for (int qy = 0; qy < 2; ++qy)
+            for (int qx = 0; qx < 2; ++qx) {
+              size_t canon = 4 * ((size_t)ey * H->n + ex) + 2 * qy + qx;
+              H->g_tiled[(size_t)m * H->Nq + tiled_q(H->n, ex, ey, qx, qy)] =
+                  H->kl.gq[(size_t)m * H->Nq + canon];
+            }
+    for (auto& k : H->Jq) {
+      double f = 1.0;
+      for (int e : k) {
+        double fac = 1.0;
+        for (int t = 2; t <= e; ++t) fac *= t;
+        f /= std::sqrt(fac);
+      }
+      H->isf.push_back(f);
+      for (int e : k) H->Jq_flat.push_back(e);
+    }
+    const size_t nn = (size_t)(H->n + 1) * (H->n + 1);
+    if (f_nodal) H->f_nodal.assign(f_nodal, f_nodal + nn);
+    else H->f_nodal.assign(nn, 1.0);
+    for (double v : H->f_nodal)
+      if (!std::isfinite(v)) throw Error(SG_ERR_INVALID_ARG, "non-finite forcing");
+    std::vector<int> all(H->P);
+    std::iota(all.begin(), all.end(), 0);
+    H->full = build_rowset(*H, all, all, H->full_kc, H->full_nchunk);
+    for (int g = 0; g < 4; ++g) {
+      FSHost& fh = H->fs[g];
+      fh.splits = make_splits(H->Jp, g);
+      fh.partial.assign(fh.splits.size(), RowSetHost{});
+      fh.kc.assign(fh.splits.size(), 0);
+      fh.nchunk.assign(fh.splits.size(), 0);
+      std::vector<int> prev;
+      for (size_t s = 0; s < fh.splits.size(); ++s) {
+        if (s >= 1)
+          fh.partial[s] = build_rowset(*H, fh.splits[s], prev, fh.kc[s], fh.nchunk[s]);
+        prev.insert(prev.end(), fh.splits[s].begin(), fh.splits[s].end());
+      }
+    }
+    for (int ln = H->n; ln >= 2; ln /= 2) H->level_n.push_back(ln);
+    *out = H.release();
+    return SG_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return fail(SG_ERR_INTERNAL, e.what());
+  }
+}
+
+int sg_sizes(const sg_handle* h, int64_t* P, int64_t* N_h, int64_t* n_a, int64_t* nnz_G) {
+  if (!h) return fail(SG_ERR_INVALID_ARG, "null handle");
+  if (P) *P = h->P;
+  if (N_h) *N_h = h->Nh;
+  if (n_a) *n_a = h->na;
+  if (nnz_G) *nnz_G = (int64_t)h->G.size();
+  return SG_OK;
+}
+
+size_t sg_workspace_bytes(const sg_handle* h) {
+  if (!h) return 0;
+  DevPtrs dry;
+  Carver c{nullptr};
+  carve(*h, dry, c);
+  return c.off;
+}
+
+int sg_bind(sg_handle* h, void* dev_workspace, size_t bytes, void* stream) {
+  if (!h || !dev_workspace) return fail(SG_ERR_INVALID_ARG, "null argument");
+  try {
+    const size_t need = sg_workspace_bytes(h);
+    if (bytes < need)
+      return fail(SG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % 256)
+      return fail(SG_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    sg_handle& H = *h;
+    H.ws = static_cast<char*>(dev_workspace);
+    H.ws_bytes = bytes;
+    Carver c{H.ws};
+    carve(H, H.d, c);
+    DevPtrs& D = H.d;
+    upload(s, D.g, H.g_tiled);
+    upload(s, D.isf, H.isf);
+    upload(s, D.Jq, H.Jq_flat);
+    upload(s, D.f, H.f_nodal);
+    upload_rowset(s, H.full, D.full);
+    for (int g = 0; g < 4; ++g)
+      for (size_t sp = 0; sp < H.fs[g].splits.size(); ++sp) {
+        upload(s, D.fs[g].split_idx[sp], H.fs[g].splits[sp]);
+        if (sp >= 1) upload_rowset(s, H.fs[g].partial[sp], D.fs[g].partial[sp]);
+      }
+    launch_coeff(s, H.n, H.M, H.na, D.g, D.Jq, D.isf, H.prob.mu, H.prob.a_min, D.a);
+    launch_fine_stencil(s, H.n, D.a, D.L[0].S);
+    for (size_t l = 1; l < D.L.size(); ++l) launch_rap(s, D.L[l - 1].n, D.L[l - 1].S, D.L[l].S);
+    check_launch();
+    if (!H.host_pinned)
+      SG_HIP(hipHostMalloc((void**)&H.host_pinned, sizeof(double) * (4 * (kMaxRestart + 2) + 8),
+                           hipHostMallocDefault));
+    SG_HIP(hipStreamSynchronize(s));
+    H.bound = true;
+    return SG_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return fail(SG_ERR_INTERNAL, e.what());
+  }
+}
+
+int sg_rhs(sg_handle* h, double* F, void* stream) {
+  if (!h || !F) return fail(SG_ERR_INVALID_ARG, "null argument");
+  if (!h->bound) return fail(SG_ERR_NOT_BOUND, "handle not bound");
+  try {
+    launch_rhs(reinterpret_cast<hipStream_t>(stream), h->n, h->d.f, F, (int64_t)h->P * h->Nh);
+    check_launch();
+    return SG_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  }
+}
+
+int sg_apply(sg_handle* h, const double* U, double* W, void* stream) {
+  if (!h || !U || !W) return fail(SG_ERR_INVALID_ARG, "null argument");
+  if (U == W) return fail(SG_ERR_INVALID_ARG, "U and W must not alias");
+  if (!h->bound) return fail(SG_ERR_NOT_BOUND, "handle not bound");
+  try {
+    do_apply(*h, reinterpret_cast<hipStream_t>(stream), U, W);
+    check_launch();
+    return SG_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  }
+}
+
+int sg_precond_apply(sg_handle* h, int pc, int grouping, const double* r, double* z,
+                     void* stream) {
+  if (!h || !r || !z) return fail(SG_ERR_INVALID_ARG, "null argument");
+  if (r == z) return fail(SG_ERR_INVALID_ARG, "r and z must not alias");
+  if (!h->bound) return fail(SG_ERR_NOT_BOUND, "handle not bound");
+  if (pc < SG_PC_NONE || pc > SG_PC_FS) return fail(SG_ERR_INVALID_ARG, "unknown preconditioner");
+  if (grouping < 0 || grouping > 3) return fail(SG_ERR_INVALID_ARG, "unknown grouping");
+  try {
+    do_precond(*h, reinterpret_cast<hipStream_t>(stream), pc, grouping, r, z);
+    check_launch();
+    return SG_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  }
+}
+
+namespace {
+struct KrylovWS {
+  double *V, *w, *z, *t, *partial, *hdev, *ydev;
+  int nblk;
+};
+
+size_t krylov_layout(const sg_handle* h, int restart, KrylovWS* k, char* base) {
+  const int64_t Nv = (int64_t)h->P * h->Nh;
+  Carver c{base};
+  KrylovWS tmp;
+  KrylovWS& K = k ? *k : tmp;
+  K.nblk = dot_blocks(Nv);
+  K.V = c.take<double>((size_t)(restart + 1) * Nv);
+  K.w = c.take<double>(Nv);
+  K.z = c.take<double>(Nv);
+  K.t = c.take<double>(Nv);
+  K.partial = c.take<double>((size_t)K.nblk * (restart + 1));
+  K.hdev = c.take<double>(2 * (size_t)(restart + 1) + 2);
+  K.ydev = c.take<double>(restart + 1);
+  return c.off;
+}
+}  // namespace
+
+size_t sg_gmres_workspace_bytes(const sg_handle* h, const sg_solve_opts* o) {
+  if (!h || !o || o->restart < 1 || o->restart > kMaxRestart) return 0;
+  return krylov_layout(h, o->restart, nullptr, nullptr);
+}
+
+int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double* u,
+                   void* krylov_ws, size_t ws_bytes, double* resid_hist, int32_t hist_len,
+                   sg_solve_info* info, void* stream) {
+  if (!h || !o || !F || !u || !krylov_ws || !info) return fail(SG_ERR_INVALID_ARG, "null argument");
+  if (!h->bound) return fail(SG_ERR_NOT_BOUND, "handle not bound");
+  if (o->restart < 1 || o->restart > kMaxRestart) return fail(SG_ERR_INVALID_ARG, "restart out of range");
+  if (o->max_it < 1) return fail(SG_ERR_INVALID_ARG, "max_it must be positive");
+  if (!(o->tol > 0.0)) return fail(SG_ERR_INVALID_ARG, "tol must be positive");
+  if (o->pc < SG_PC_NONE || o->pc > SG_PC_FS) return fail(SG_ERR_INVALID_ARG, "unknown preconditioner");
+  if (o->grouping < 0 || o->grouping > 3) return fail(SG_ERR_INVALID_ARG, "unknown grouping");
+  if (ws_bytes < sg_gmres_workspace_bytes(h, o)) return fail(SG_ERR_WORKSPACE, "Krylov workspace too small");
+  if (reinterpret_cast<uintptr_t>(krylov_ws) % 256) return fail(SG_ERR_WORKSPACE, "Krylov workspace must be 256-byte aligned");
+  try {
+    sg_handle& H = *h;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int m = o->restart;
+    const int64_t Nv = (int64_t)H.P * H.Nh;
+    KrylovWS K;
+    krylov_layout(h, m, &K, static_cast<char*>(krylov_ws));
+    double* hp = H.host_pinned;
+    auto norm2 = [&](const double* x, double* dst) {
+      launch_multidot(s, x, Nv, 1, x, Nv, K.partial, K.nblk);
+      launch_reduce(s, K.partial, K.nblk, 1, dst);
+    };
+    auto fetch = [&](const double* src, int count) {
+      SG_HIP(hipMemcpyAsync(hp, src, count * sizeof(double), hipMemcpyDeviceToHost, s));
+      SG_HIP(hipStreamSynchronize(s));
+    };
+    norm2(F, K.hdev);
+    fetch(K.hdev, 1);
+    const double nF = std::sqrt(hp[0]);
+    std::memset(info, 0, sizeof(*info));
+    int hist_n = 0;
+    auto push_hist = [&](double v) {
+      if (resid_hist && hist_n < hist_len) resid_hist[hist_n] = v;
+      hist_n++;
+    };
+    if (nF == 0.0 || !std::isfinite(nF)) {
+      launch_zero(s, u, Nv);
+      SG_HIP(hipStreamSynchronize(s));
+      info->status = nF == 0.0 ? SG_CONVERGED : SG_BREAKDOWN;
+      push_hist(0.0);
+      return SG_OK;
+    }
+    const double target = o->tol * nF;
+    double beta;
+    if (o->use_x0) {
+      do_apply(H, s, u, K.w);
+      launch_sub(s, F, K.w, K.t, Nv);
+      norm2(K.t, K.hdev);
+      fetch(K.hdev, 1);
+      beta = std::sqrt(hp[0]);
+    } else {
+      launch_zero(s, u, Nv);
+      SG_HIP(hipMemcpyAsync(K.t, F, Nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+      beta = nF;
+    }
+    push_hist(beta / nF);
+    std::vector<double> Hm((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    auto Hat = [&](int i, int j) -> double& { return Hm[(size_t)i * m + j]; };
+    int it = 0, restarts = 0;
+    bool broke = false;
+    double est = beta;
+    while (beta > target && it < o->max_it && !broke) {
+      std::fill(Hm.begin(), Hm.end(), 0.0);
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      launch_axpby(s, 1.0 / beta, K.t, 0.0, K.V, Nv);
+      int kdone = 0;
+      for (int j = 0; j < m; ++j) {
+        double* vj = K.V + (int64_t)j * Nv;
+        do_precond(H, s, o->pc, o->grouping, vj, K.z);
+        do_apply(H, s, K.z, K.w);
+        double* h1 = K.hdev;
+        double* h2 = K.hdev + (m + 1);
+        double* nrm = K.hdev + 2 * (m + 1);
+        launch_multidot(s, K.V, Nv, j + 1, K.w, Nv, K.partial, K.nblk);
+        launch_reduce(s, K.partial, K.nblk, j + 1, h1);
+        launch_update(s, K.V, Nv, j + 1, h1, K.w, Nv, -1.0);
+        launch_multidot(s, K.V, Nv, j + 1, K.w, Nv, K.partial, K.nblk);
+        launch_reduce(s, K.partial, K.nblk, j + 1, h2);
+        launch_update(s, K.V, Nv, j + 1, h2, K.w, Nv, -1.0);
+        norm2(K.w, nrm);
+        launch_scale_by_inv_norm(s, K.w, nrm, K.V + (int64_t)(j + 1) * Nv, Nv);
+        check_launch();
+        fetch(K.hdev, 2 * (m + 1) + 1);
+        for (int i = 0; i <= j; ++i) Hat(i, j) = hp[i] + hp[m + 1 + i];
+        Hat(j + 1, j) = std::sqrt(hp[2 * (m + 1)]);
+        if (!std::isfinite(Hat(j + 1, j))) {
+          broke = true;
+          break;
+        }
+        for (int i = 0; i < j; ++i) {
+          double tmp = cs[i] * Hat(i, j) + sn[i] * Hat(i + 1, j);
+          Hat(i + 1, j) = -sn[i] * Hat(i, j) + cs[i] * Hat(i + 1, j);
+          Hat(i, j) = tmp;
+        }
+        double a = Hat(j, j), b = Hat(j + 1, j);
+        if (b == 0.0) {
+          cs[j] = 1.0;
+          sn[j] = 0.0;
+        } else {
+          double r = std::hypot(a, b);
+          cs[j] = a / r;
+          sn[j] = b / r;
+        }
+        Hat(j, j) = cs[j] * a + sn[j] * b;
+        Hat(j + 1, j) = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        ++it;
+        kdone = j + 1;
+        est = std::fabs(g[j + 1]);
+        push_hist(est / nF);
+        if (est <= target || it >= o->max_it) break;
+        if (Hat(j, j) == 0.0) {
+          broke = true;
+          break;
+        }
+      }
+      if (kdone == 0) break;
+      for (int i = kdone - 1; i >= 0; --i) {
+        double acc = g[i];
+        for (int l = i + 1; l < kdone; ++l) acc -= Hat(i, l) * y[l];
+        y[i] = acc / Hat(i, i);
+      }
+      for (int i = 0; i < kdone; ++i) hp[i] = y[i];
+      SG_HIP(hipMemcpyAsync(K.ydev, hp, kdone * sizeof(double), hipMemcpyHostToDevice, s));
+      launch_combine(s, K.V, Nv, kdone, K.ydev, K.t, Nv);
+      do_precond(H, s, o->pc, o->grouping, K.t, K.z);
+      launch_axpby(s, 1.0, K.z, 1.0, u, Nv);
+      do_apply(H, s, u, K.w);
+      launch_sub(s, F, K.w, K.t, Nv);
+      norm2(K.t, K.hdev);
+      fetch(K.hdev, 1);
+      beta = std::sqrt(hp[0]);
+      ++restarts;
+      if (!std::isfinite(beta)) broke = true;
+    }
+    info->iterations = it;
+    info->restarts = restarts;
+    info->relres = beta / nF;
+    info->relres_est = est / nF;
+    info->status = (beta <= target) ? SG_CONVERGED : (broke ? SG_BREAKDOWN : SG_NOT_CONVERGED);
+    return SG_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return fail(SG_ERR_INTERNAL, e.what());
+  }
+}
+
+int sg_export(sg_handle* h, int what, int level, double* out, size_t count) {
+  if (!h || !out) return fail(SG_ERR_INVALID_ARG, "null argument");
+  try {
+    sg_handle& H = *h;
+    auto need = [&](size_t c) {
+      if (count < c) throw Error(SG_ERR_INVALID_ARG, "output buffer too small: need " + std::to_string(c));
+    };
+    switch (what) {
+      case SG_EXPORT_KL:
+        need(H.kl.lam.size());
+        std::copy(H.kl.lam.begin(), H.kl.lam.end(), out);
+        return SG_OK;
+      case SG_EXPORT_GQ:
+        need(H.kl.gq.size());
+        std::copy(H.kl.gq.begin(), H.kl.gq.end(), out);
+        return SG_OK;
+      case SG_EXPORT_GROUPS: {
+        if (level < 0 || level > 3) throw Error(SG_ERR_INVALID_ARG, "grouping out of range");
+        std::vector<double> v;
+        v.push_back((double)H.fs[level].splits.size());
+        for (auto& sp : H.fs[level].splits) {
+          v.push_back((double)sp.size());
+          for (int i : sp) v.push_back(i);
+        }
+        need(v.size());
+        std::copy(v.begin(), v.end(), out);
+        return SG_OK;
+      }
+      case SG_EXPORT_COEFF: {
+        if (!H.bound) return fail(SG_ERR_NOT_BOUND, "handle not bound");
+        need((size_t)H.na * H.Nq);
+        std::vector<double> tiled((size_t)H.na * H.Nq);
+        SG_HIP(hipMemcpy(tiled.data(), H.d.a, tiled.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (int k = 0; k < H.na; ++k)
+          for (int ey = 0; ey < H.n; ++ey)
+            for (int ex = 0; ex < H.n; ++ex)
+              for (int qy = 0; qy < 2; ++qy)
+                for (int qx = 0; qx < 2; ++qx)
+                  out[(size_t)k * H.Nq + 4 * ((size_t)ey * H.n + ex) + 2 * qy + qx] =
+                      tiled[(size_t)k * H.Nq + tiled_q(H.n, ex, ey, qx, qy)];
+        return SG_OK;
+      }
+      case SG_EXPORT_STENCIL: {
+        if (!H.bound) return fail(SG_ERR_NOT_BOUND, "handle not bound");
+        if (level < 0 || level >= (int)H.d.L.size()) throw Error(SG_ERR_INVALID_ARG, "level out of range");
+        need(9 * (size_t)H.d.L[level].N);
+        SG_HIP(hipMemcpy(out, H.d.L[level].S, 9 * H.d.L[level].N * sizeof(double), hipMemcpyDeviceToHost));
+        return SG_OK;
+      }
+      default:
+        return fail(SG_ERR_INVALID_ARG, "unknown export");
+    }
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  }
+}
+
+void sg_destroy(sg_handle* h) { delete h; }
+
+}  // extern "C"

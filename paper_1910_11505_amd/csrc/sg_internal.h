@@ -1,0 +1,125 @@
+// Internal declarations shared by the host set-up, the ABI layer and the HIP
+// kernels of the stochastic-Galerkin solver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/sg.h"
+
+namespace sg {
+
+// ---- fixed geometry of the apply kernel -----------------------------------
+// Elements are processed in 4x4 tiles: 16 elements, 64 Gauss points, one
+// point per lane of a 64-wide wavefront.  Coefficient modes are stored
+// tile-major so that a tile's 64 values of one mode are 512 contiguous bytes.
+constexpr int kTileE = 4;            // elements per tile side
+constexpr int kTileQ = 64;           // Gauss points per tile
+constexpr int kApplyWaves = 4;       // wavefronts per apply workgroup
+constexpr int kEdgeVals = 9;         // right edge 4, top edge 4, corner 1
+constexpr int kMaxP = 256;
+constexpr int kMaxRestart = 200;
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+// ---- host set-up (sg_host.cpp) ---------------------------------------------
+std::vector<std::vector<int>> total_degree_set(int M, int p);
+double hermite_triple(int a, int b, int c);
+
+struct Triple { int k, i, j; double v; };
+std::vector<Triple> triple_list(const std::vector<std::vector<int>>& Jp,
+                                const std::vector<std::vector<int>>& Jq);
+
+struct KL {
+  std::vector<double> lam;               // M eigenvalues (with sigma^2)
+  std::vector<std::pair<int, int>> pairs;
+  std::vector<double> gq;                // M x Nq, canonical q order
+};
+KL karhunen_loeve(int n, int cov, double corr_len, double sigma, int M);
+
+std::vector<std::vector<int>> make_splits(const std::vector<std::vector<int>>& J, int grouping);
+
+// canonical Gauss point index q = 4e + 2qy + qx  ->  tile-major index
+__host__ __device__ inline int64_t tiled_q(int n, int ex, int ey, int qx, int qy) {
+  int nt = n / kTileE;
+  int64_t t = (int64_t)(ey / kTileE) * nt + (ex / kTileE);
+  int el = (ey % kTileE) * kTileE + (ex % kTileE);
+  return t * kTileQ + el * 4 + qy * 2 + qx;
+}
+
+// ---- device-side descriptors -----------------------------------------------
+// A row set of the operator: output modes `rows`, their nonzero triple
+// products bucketed by coefficient-mode chunk, and the input columns whose
+// gradients are needed.
+struct RowSetHost {
+  int nrows = 0, ncols = 0, rmax = 0;
+  std::vector<int> rows;        // mode index of each output row
+  std::vector<int> cols;        // mode index of each gradient column
+  std::vector<int> wrows;       // kApplyWaves x rmax, row slot per wave (-1 pad)
+  std::vector<int> ptr;         // nrows x (nchunk+1)
+  std::vector<int> kj;          // (k - chunk base) | (col slot << 16)
+  std::vector<double> v;
+};
+
+struct RowSetDev {
+  int nrows, ncols, rmax;
+  const int* rows;
+  const int* cols;
+  const int* wrows;
+  const int* ptr;
+  const int* kj;
+  const double* v;
+};
+
+struct Level {
+  int n;          // elements per side on this level
+  int64_t N;      // (n-1)^2
+  double* S;      // 9 x N stencil
+};
+
+// launch wrappers (sg_kernels.hip)
+void launch_coeff(hipStream_t s, int n, int M, int na, const double* g, const int* Jq,
+                  const double* inv_sqrt_fact, double mu, double a_min, double* a);
+void launch_fine_stencil(hipStream_t s, int n, const double* a0, double* S);
+void launch_rap(hipStream_t s, int nf, const double* Sf, double* Sc);
+void launch_rhs(hipStream_t s, int n, const double* f_nodal, double* F, int64_t total);
+void launch_apply(hipStream_t s, int n, int nchunk, int kc, int na, const double* a,
+                  const RowSetDev& rs, const double* U, int64_t Nh, const double* rin,
+                  double beta, double sgn, double* out, double* edge);
+size_t apply_lds_bytes(int ncols, int kc);
+void launch_zero(hipStream_t s, double* x, int64_t n);
+void launch_jacobi(hipStream_t s, const Level& L, int m, const double* b, const double* xin,
+                   double* xout, double omega, bool first);
+void launch_residual(hipStream_t s, const Level& L, int m, const double* b, const double* x,
+                     double* r);
+void launch_restrict(hipStream_t s, const Level& Lf, const Level& Lc, int m, const double* rf,
+                     double* bc);
+void launch_prolong_add(hipStream_t s, const Level& Lf, const Level& Lc, int m,
+                        const double* xc, double* xf);
+void launch_coarse(hipStream_t s, const Level& L, int m, const double* b, double* x);
+void launch_gather_modes(hipStream_t s, int m, const int* modes, int64_t Nh, const double* src,
+                         double* dst);
+void launch_scatter_modes(hipStream_t s, int m, const int* modes, int64_t Nh, const double* src,
+                          double* dst);
+// Krylov helpers
+int dot_blocks(int64_t N);
+void launch_multidot(hipStream_t s, const double* V, int64_t ldv, int nv, const double* w,
+                     int64_t N, double* partial, int nblk);
+void launch_reduce(hipStream_t s, const double* partial, int nblk, int nv, double* out);
+void launch_update(hipStream_t s, const double* V, int64_t ldv, int nv, const double* h,
+                   double* w, int64_t N, double sign);
+void launch_combine(hipStream_t s, const double* V, int64_t ldv, int nv, const double* y,
+                    double* out, int64_t N);
+void launch_scale_by_inv_norm(hipStream_t s, const double* w, const double* nrm2, double* v,
+                              int64_t N);
+void launch_axpby(hipStream_t s, double a, const double* x, double b, double* y, int64_t N);
+void launch_sub(hipStream_t s, const double* a, const double* b, double* out, int64_t N);
+
+}  // namespace sg

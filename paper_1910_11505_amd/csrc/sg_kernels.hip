@@ -1,0 +1,712 @@
+// HIP kernels (gfx950) of the stochastic-Galerkin solver.
+//
+//  * set-up: coefficient chaos modes a_k at the Gauss points, the mean
+//    stiffness stencil and its Galerkin coarse stencils, the load vector;
+//  * the matrix-free SG operator W = sum_k vec(A_k U G_k^T) (Sec. 2.2);
+//  * geometric-multigrid pieces on the 9-point mean stiffness, batched over
+//    stochastic modes (inner solver of the preconditioners of Sec. 3);
+//  * FP64 Krylov helpers with fixed-order (deterministic) reductions.
+//
+// No floating-point atomics are used: every output element is written by one
+// thread and every sum is taken in a fixed order, so results are bitwise
+// reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "sg_internal.h"
+
+namespace sg {
+
+namespace {
+
+// 2-point Gauss-Legendre abscissae on [0, 1]
+__device__ __forceinline__ double gauss_pt(int i) {
+  return i ? 0.78867513459481288225 : 0.21132486540518711775;
+}
+
+// reference gradient of the bilinear hat of local node a = (ax, ay) at (xi, eta)
+__device__ __forceinline__ void ref_grad(int a, double xi, double eta, double& gx, double& gy) {
+  const int ax = a & 1, ay = a >> 1;
+  const double fy = ay ? eta : 1.0 - eta;
+  const double fx = ax ? xi : 1.0 - xi;
+  gx = (ax ? 1.0 : -1.0) * fy;
+  gy = (ay ? 1.0 : -1.0) * fx;
+}
+
+inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// a_k(x_q) = a_min [k=0] + exp(mu + sum_m g_m^2 / 2) prod_m g_m^{k_m} / sqrt(k_m!)
+// (eq. dataProjection evaluated in closed form through the Hermite generating
+// function).  One thread per Gauss point, a slice of modes per block row.
+// ---------------------------------------------------------------------------
+__global__ void coeff_kernel(int64_t Nq, int M, int na, int kper, const double* __restrict__ g,
+                             const int* __restrict__ Jq, const double* __restrict__ isf,
+                             double mu, double a_min, double* __restrict__ a) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Nq) return;
+  double gv[16];
+  double s = 0.0;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    gv[m] = (m < M) ? g[(int64_t)m * Nq + q] : 0.0;
+    s += gv[m] * gv[m];
+  }
+  const double E = exp(mu + 0.5 * s);
+  const int k0 = blockIdx.y * kper;
+  const int k1 = min(na, k0 + kper);
+  for (int k = k0; k < k1; ++k) {
+    double prod = 1.0;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      if (m < M) {
+        const int e = Jq[k * M + m];
+        for (int t = 0; t < e; ++t) prod *= gv[m];
+      }
+    }
+    double v = E * isf[k] * prod;
+    if (k == 0) v += a_min;
+    a[(int64_t)k * Nq + q] = v;
+  }
+}
+
+void launch_coeff(hipStream_t s, int n, int M, int na, const double* g, const int* Jq,
+                  const double* isf, double mu, double a_min, double* a) {
+  const int64_t Nq = (int64_t)4 * n * n;
+  const int kper = 32;
+  dim3 grid(cdiv(Nq, 256), cdiv(na, kper));
+  hipLaunchKernelGGL(coeff_kernel, grid, dim3(256), 0, s, Nq, M, na, kper, g, Jq, isf, mu,
+                     a_min, a);
+}
+
+// ---------------------------------------------------------------------------
+// Mean stiffness stencil (eq. A_q with coefficient a_0): for every interior
+// node, the 9 couplings summed over its 4 elements; couplings to Dirichlet
+// nodes are dropped.  Stencil entry s = 3(dy+1) + (dx+1), SoA layout.
+// ---------------------------------------------------------------------------
+__global__ void fine_stencil_kernel(int n, const double* __restrict__ a0, double* __restrict__ S) {
+  const int m = n - 1;
+  const int64_t N = (int64_t)m * m;
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= N) return;
+  const int ix = (int)(node % m) + 1, iy = (int)(node / m) + 1;
+  double st[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) st[t] = 0.0;
+  for (int de = 0; de < 4; ++de) {
+    const int ex = ix - 1 + (de & 1), ey = iy - 1 + (de >> 1);
+    // local index of this node inside element (ex, ey)
+    const int la = (ix - ex) + 2 * (iy - ey);
+    double ke[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int qy = 0; qy < 2; ++qy)
+      for (int qx = 0; qx < 2; ++qx) {
+        const double xi = gauss_pt(qx), eta = gauss_pt(qy);
+        const double c = 0.25 * a0[tiled_q(n, ex, ey, qx, qy)];
+        double gax, gay;
+        ref_grad(la, xi, eta, gax, gay);
+        for (int b = 0; b < 4; ++b) {
+          double gbx, gby;
+          ref_grad(b, xi, eta, gbx, gby);
+          ke[b] += c * (gax * gbx + gay * gby);
+        }
+      }
+    for (int b = 0; b < 4; ++b) {
+      const int jx = ex + (b & 1), jy = ey + (b >> 1);
+      st[3 * (jy - iy + 1) + (jx - ix + 1)] += ke[b];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int jx = ix + (t % 3) - 1, jy = iy + (t / 3) - 1;
+    const bool inside = jx >= 1 && jx <= m && jy >= 1 && jy <= m;
+    S[(int64_t)t * N + node] = inside ? st[t] : 0.0;
+  }
+}
+
+void launch_fine_stencil(hipStream_t s, int n, const double* a0, double* S) {
+  const int64_t N = (int64_t)(n - 1) * (n - 1);
+  hipLaunchKernelGGL(fine_stencil_kernel, dim3(cdiv(N, 256)), dim3(256), 0, s, n, a0, S);
+}
+
+// 1D interpolation weight of coarse node I at fine node i (fine interior
+// numbering 1..nf-1, coarse 1..nc-1): 1 at i = 2I, 1/2 at i = 2I +- 1
+__device__ __forceinline__ double pw(int i, int I) {
+  const int d = i - 2 * I;
+  return d == 0 ? 1.0 : ((d == 1 || d == -1) ? 0.5 : 0.0);
+}
+
+// Galerkin coarse stencil A_c = P^T A_f P for bilinear interpolation P.
+__global__ void rap_kernel(int nf, const double* __restrict__ Sf, double* __restrict__ Sc) {
+  const int mf = nf - 1, nc = nf / 2, mc = nc - 1;
+  const int64_t Nf = (int64_t)mf * mf, Nc = (int64_t)mc * mc;
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= Nc) return;
+  const int I = (int)(node % mc) + 1, J = (int)(node / mc) + 1;
+  double st[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) st[t] = 0.0;
+  for (int fy = 2 * J - 1; fy <= 2 * J + 1; ++fy)
+    for (int fx = 2 * I - 1; fx <= 2 * I + 1; ++fx) {
+      const double wf = pw(fx, I) * pw(fy, J);
+      const int64_t f = (int64_t)(fy - 1) * mf + (fx - 1);
+      for (int t = 0; t < 9; ++t) {
+        const int gx = fx + (t % 3) - 1, gy = fy + (t / 3) - 1;
+        if (gx < 1 || gx > mf || gy < 1 || gy > mf) continue;
+        const double afg = Sf[(int64_t)t * Nf + f];
+        if (afg == 0.0) continue;
+        // coarse nodes that interpolate to fine node g
+        for (int cy = J - 1; cy <= J + 1; ++cy)
+          for (int cx = I - 1; cx <= I + 1; ++cx) {
+            if (cx < 1 || cx > mc || cy < 1 || cy > mc) continue;
+            const double w = pw(gx, cx) * pw(gy, cy);
+            if (w != 0.0) st[3 * (cy - J + 1) + (cx - I + 1)] += wf * afg * w;
+          }
+      }
+    }
+#pragma unroll
+  for (int t = 0; t < 9; ++t) Sc[(int64_t)t * Nc + node] = st[t];
+}
+
+void launch_rap(hipStream_t s, int nf, const double* Sf, double* Sc) {
+  const int64_t Nc = (int64_t)(nf / 2 - 1) * (nf / 2 - 1);
+  hipLaunchKernelGGL(rap_kernel, dim3(cdiv(Nc, 128)), dim3(128), 0, s, nf, Sf, Sc);
+}
+
+// F = e_0 (x) M_h f_h: consistent Q1 mass on the nodal forcing, mode 0 only.
+__global__ void rhs_kernel(int n, const double* __restrict__ f, double* __restrict__ F,
+                           int64_t total) {
+  const int m = n - 1;
+  const int64_t N = (int64_t)m * m;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  if (idx >= N) {
+    F[idx] = 0.0;
+    return;
+  }
+  const int ix = (int)(idx % m) + 1, iy = (int)(idx / m) + 1;
+  const double h = 1.0 / n;
+  double acc = 0.0;
+  for (int de = 0; de < 4; ++de) {
+    const int ex = ix - 1 + (de & 1), ey = iy - 1 + (de >> 1);
+    const int la = (ix - ex) + 2 * (iy - ey);
+    for (int b = 0; b < 4; ++b) {
+      const int jx = ex + (b & 1), jy = ey + (b >> 1);
+      const int same = (la == b), opposite = ((la ^ b) == 3);
+      const double w = same ? 4.0 : (opposite ? 1.0 : 2.0);
+      acc += w * f[(int64_t)jy * (n + 1) + jx];
+    }
+  }
+  F[idx] = acc * (h * h / 36.0);
+}
+
+void launch_rhs(hipStream_t s, int n, const double* f, double* F, int64_t total) {
+  hipLaunchKernelGGL(rhs_kernel, dim3(cdiv(total, 256)), dim3(256), 0, s, n, f, F, total);
+}
+
+// ---------------------------------------------------------------------------
+// SG operator apply.  One workgroup = one 4x4 element tile (64 Gauss points,
+// one per lane), four wavefronts splitting the output rows.
+//   1. stage the tile's 5x5 nodal values of every needed input mode in LDS;
+//   2. reference gradients of those modes at the 64 points -> LDS;
+//   3. stream the coefficient modes a_k in chunks of kc modes through LDS
+//      (each value read from HBM once, coalesced 512-byte rows) and, per
+//      output row, accumulate flux_i(q) += a_k(q) [G_k]_{ij} grad U_j(q) over
+//      the row's nonzero triple products of that chunk (wave-uniform, so the
+//      (k, j, value) stream is read through the scalar cache);
+//   4. per row: element-node contributions (1/4) grad phi_a . flux, summed over
+//      the element's four lanes, then node sums in fixed order; nodes owned
+//      by the tile are written, the right/top edge and corner go to a small
+//      edge buffer folded in by apply_fixup_kernel.
+// out[slot] = beta * rin[row] + sgn * (K_sub U)[row].
+// ---------------------------------------------------------------------------
+template <int RMAX>
+__global__ __launch_bounds__(256) void apply_kernel(
+    int n, int nchunk, int kc, int na, const double* __restrict__ a, RowSetDev rs,
+    const double* __restrict__ U, int64_t Nh, const double* __restrict__ rin, double beta,
+    double sgn, double* __restrict__ out, double* __restrict__ edge) {
+  extern __shared__ double smem[];
+  const int nt = n / kTileE;
+  const int ntiles = nt * nt;
+  const int tile = blockIdx.x;
+  const int tx = tile % nt, ty = tile / nt;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ncols = rs.ncols;
+  const int64_t Nq = (int64_t)4 * n * n;
+  const int m = n - 1;
+  double2* sG = reinterpret_cast<double2*>(smem);
+  double* sA = smem + 2 * ncols * kTileQ;
+  const int x0 = tx * kTileE, y0 = ty * kTileE;
+
+  // 1. nodal values of the needed modes on the tile's 5x5 nodes
+  for (int idx = tid; idx < ncols * 25; idx += 256) {
+    const int c = idx / 25, nd = idx - c * 25;
+    const int gx = x0 + nd % 5, gy = y0 + nd / 5;
+    double v = 0.0;
+    if (gx >= 1 && gx <= m && gy >= 1 && gy <= m)
+      v = U[(int64_t)rs.cols[c] * Nh + (int64_t)(gy - 1) * m + (gx - 1)];
+    sA[idx] = v;
+  }
+  __syncthreads();
+  // 2. reference gradients at the Gauss points
+  for (int idx = tid; idx < ncols * kTileQ; idx += 256) {
+    const int c = idx >> 6, lq = idx & 63;
+    const int el = lq >> 2, ql = lq & 3;
+    const int elx = el & 3, ely = el >> 2;
+    const double xi = gauss_pt(ql & 1), eta = gauss_pt(ql >> 1);
+    const double* u = sA + c * 25;
+    const double u00 = u[ely * 5 + elx], u10 = u[ely * 5 + elx + 1];
+    const double u01 = u[(ely + 1) * 5 + elx], u11 = u[(ely + 1) * 5 + elx + 1];
+    sG[idx] = make_double2((1.0 - eta) * (u10 - u00) + eta * (u11 - u01),
+                           (1.0 - xi) * (u01 - u00) + xi * (u11 - u10));
+  }
+  __syncthreads();
+
+  // 3. flux accumulation
+  double ax[RMAX], ay[RMAX];
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) ax[r] = ay[r] = 0.0;
+  const int* wrows = rs.wrows + wave * RMAX;
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int k0 = ch * kc;
+    const int kn = min(kc, na - k0);
+    const double* src = a + (int64_t)k0 * Nq + (int64_t)tile * kTileQ;
+    for (int idx = tid; idx < kn * kTileQ; idx += 256)
+      sA[idx] = src[(int64_t)(idx >> 6) * Nq + (idx & 63)];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      const int slot = wrows[r];
+      if (slot >= 0) {
+        const int b = rs.ptr[slot * (nchunk + 1) + ch];
+        const int e = rs.ptr[slot * (nchunk + 1) + ch + 1];
+        double sx = ax[r], sy = ay[r];
+        for (int t = b; t < e; ++t) {
+          const int kj = rs.kj[t];
+          const double v = rs.v[t];
+          const double av = sA[(kj & 0xffff) * kTileQ + lane] * v;
+          const double2 gg = sG[(kj >> 16) * kTileQ + lane];
+          sx = fma(av, gg.x, sx);
+          sy = fma(av, gg.y, sy);
+        }
+        ax[r] = sx;
+        ay[r] = sy;
+      }
+    }
+    __syncthreads();
+  }
+
+  // 4. node contributions, row by row
+  const int ql = lane & 3;
+  const double xi = gauss_pt(ql & 1), eta = gauss_pt(ql >> 1);
+  double gpx[4], gpy[4];
+#pragma unroll
+  for (int a4 = 0; a4 < 4; ++a4) ref_grad(a4, xi, eta, gpx[a4], gpy[a4]);
+  double* sE = sA + wave * kTileQ;
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) {
+    const int slot = wrows[r];
+    if (slot >= 0) {
+      double c[4];
+#pragma unroll
+      for (int a4 = 0; a4 < 4; ++a4) c[a4] = 0.25 * (gpx[a4] * ax[r] + gpy[a4] * ay[r]);
+#pragma unroll
+      for (int a4 = 0; a4 < 4; ++a4) {
+        c[a4] += __shfl_xor(c[a4], 1);
+        c[a4] += __shfl_xor(c[a4], 2);
+      }
+      const double mine = (ql == 0) ? c[0] : (ql == 1) ? c[1] : (ql == 2) ? c[2] : c[3];
+      sE[lane] = mine;
+    }
+    __syncthreads();
+    if (slot >= 0 && lane < 25) {
+      const int nx = lane % 5, ny = lane / 5;
+      double sum = 0.0;
+      // fixed order: NE of (nx-1,ny-1), NW of (nx,ny-1), SE of (nx-1,ny), SW of (nx,ny)
+      if (nx >= 1 && ny >= 1) sum += sE[((ny - 1) * 4 + (nx - 1)) * 4 + 3];
+      if (nx <= 3 && ny >= 1) sum += sE[((ny - 1) * 4 + nx) * 4 + 2];
+      if (nx >= 1 && ny <= 3) sum += sE[(ny * 4 + (nx - 1)) * 4 + 1];
+      if (nx <= 3 && ny <= 3) sum += sE[(ny * 4 + nx) * 4 + 0];
+      if (nx <= 3 && ny <= 3) {
+        const int gx = x0 + nx, gy = y0 + ny;
+        if (gx >= 1 && gy >= 1) {
+          const int64_t node = (int64_t)(gy - 1) * m + (gx - 1);
+          double base = 0.0;
+          if (beta != 0.0) base = beta * rin[(int64_t)rs.rows[slot] * Nh + node];
+          out[(int64_t)slot * Nh + node] = base + sgn * sum;
+        }
+      } else {
+        const int idx = (nx == 4 && ny == 4) ? 8 : (nx == 4 ? ny : 4 + nx);
+        edge[((int64_t)slot * ntiles + tile) * kEdgeVals + idx] = sum;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Folds the edge contributions of the left, bottom and diagonal neighbour
+// tiles into the nodes on a tile's left column and bottom row.
+__global__ void apply_fixup_kernel(int n, int nrows, double sgn, const double* __restrict__ edge,
+                                   double* __restrict__ out, int64_t Nh) {
+  const int nt = n / kTileE, ntiles = nt * nt, m = n - 1;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)nrows * ntiles * 7;
+  if (gid >= total) return;
+  const int j = (int)(gid % 7);
+  const int64_t rt = gid / 7;
+  const int tile = (int)(rt % ntiles);
+  const int slot = (int)(rt / ntiles);
+  const int tx = tile % nt, ty = tile / nt;
+  const int nx = j < 4 ? 0 : j - 3;  // (0,0..3) then (1..3,0)
+  const int ny = j < 4 ? j : 0;
+  const int gx = tx * kTileE + nx, gy = ty * kTileE + ny;
+  if (gx < 1 || gy < 1) return;
+  const int64_t node = (int64_t)(gy - 1) * m + (gx - 1);
+  const double* eb = edge + (int64_t)slot * ntiles * kEdgeVals;
+  double v = out[(int64_t)slot * Nh + node];
+  if (nx == 0) v += sgn * eb[(int64_t)(tile - 1) * kEdgeVals + ny];
+  if (ny == 0) v += sgn * eb[(int64_t)(tile - nt) * kEdgeVals + 4 + nx];
+  if (nx == 0 && ny == 0) v += sgn * eb[(int64_t)(tile - nt - 1) * kEdgeVals + 8];
+  out[(int64_t)slot * Nh + node] = v;
+}
+
+size_t apply_lds_bytes(int ncols, int kc) {
+  size_t sa = std::max<size_t>({(size_t)kc * kTileQ, (size_t)ncols * 25, (size_t)kApplyWaves * kTileQ});
+  return 8 * (2 * (size_t)ncols * kTileQ + sa);
+}
+
+void launch_apply(hipStream_t s, int n, int nchunk, int kc, int na, const double* a,
+                  const RowSetDev& rs, const double* U, int64_t Nh, const double* rin,
+                  double beta, double sgn, double* out, double* edge) {
+  const int nt = n / kTileE;
+  const int ntiles = nt * nt;
+  const size_t lds = apply_lds_bytes(rs.ncols, kc);
+  dim3 grid(ntiles), block(256);
+#define SG_APPLY_CASE(R)                                                                     \
+  case R:                                                                                    \
+    hipLaunchKernelGGL(apply_kernel<R>, grid, block, lds, s, n, nchunk, kc, na, a, rs, U,    \
+                       Nh, rin, beta, sgn, out, edge);                                       \
+    break;
+  switch (rs.rmax) {
+    SG_APPLY_CASE(1)
+    SG_APPLY_CASE(2)
+    SG_APPLY_CASE(4)
+    SG_APPLY_CASE(8)
+    SG_APPLY_CASE(16)
+    SG_APPLY_CASE(32)
+    SG_APPLY_CASE(64)
+    default:
+      throw Error(SG_ERR_INTERNAL, "apply: unsupported rows per wavefront");
+  }
+#undef SG_APPLY_CASE
+  const int64_t total = (int64_t)rs.nrows * ntiles * 7;
+  hipLaunchKernelGGL(apply_fixup_kernel, dim3(cdiv(total, 256)), dim3(256), 0, s, n, rs.nrows,
+                     sgn, edge, out, Nh);
+}
+
+// ---------------------------------------------------------------------------
+// Multigrid pieces on a level with a 9-point stencil, batched over m modes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double stencil_apply(const double* __restrict__ S, int64_t N, int m,
+                                                int64_t node, int ix, int iy,
+                                                const double* __restrict__ x) {
+  double acc = 0.0;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int jx = ix + (t % 3) - 1, jy = iy + (t / 3) - 1;
+    if (jx >= 0 && jx < m && jy >= 0 && jy < m)
+      acc += S[(int64_t)t * N + node] * x[(int64_t)jy * m + jx];
+  }
+  return acc;
+}
+
+__global__ void jacobi_kernel(const double* __restrict__ S, int n, int64_t N, int modes,
+                              const double* __restrict__ b, const double* __restrict__ xin,
+                              double* __restrict__ xout, double omega, int first) {
+  const int m = n - 1;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= N * modes) return;
+  const int64_t node = gid % N;
+  const int64_t off = gid - node;
+  const double d = S[4 * N + node];
+  if (first) {
+    xout[gid] = omega * b[gid] / d;
+    return;
+  }
+  const int ix = (int)(node % m), iy = (int)(node / m);
+  const double ax = stencil_apply(S, N, m, node, ix, iy, xin + off);
+  xout[gid] = xin[gid] + omega * (b[gid] - ax) / d;
+}
+
+void launch_jacobi(hipStream_t s, const Level& L, int modes, const double* b, const double* xin,
+                   double* xout, double omega, bool first) {
+  const int64_t tot = L.N * modes;
+  hipLaunchKernelGGL(jacobi_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, s, L.S, L.n, L.N, modes,
+                     b, xin, xout, omega, first ? 1 : 0);
+}
+
+__global__ void residual_kernel(const double* __restrict__ S, int n, int64_t N, int modes,
+                                const double* __restrict__ b, const double* __restrict__ x,
+                                double* __restrict__ r) {
+  const int m = n - 1;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= N * modes) return;
+  const int64_t node = gid % N;
+  const int64_t off = gid - node;
+  const int ix = (int)(node % m), iy = (int)(node / m);
+  r[gid] = b[gid] - stencil_apply(S, N, m, node, ix, iy, x + off);
+}
+
+void launch_residual(hipStream_t s, const Level& L, int modes, const double* b, const double* x,
+                     double* r) {
+  const int64_t tot = L.N * modes;
+  hipLaunchKernelGGL(residual_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, s, L.S, L.n, L.N, modes,
+                     b, x, r);
+}
+
+// b_c = P^T r_f (full weighting with weights 1, 1/2, 1/4)
+__global__ void restrict_kernel(int nf, int64_t Nf, int64_t Nc, int modes,
+                                const double* __restrict__ rf, double* __restrict__ bc) {
+  const int mf = nf - 1, mc = nf / 2 - 1;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= Nc * modes) return;
+  const int64_t node = gid % Nc;
+  const int64_t mode = gid / Nc;
+  const int I = (int)(node % mc) + 1, J = (int)(node / mc) + 1;
+  const double* r = rf + mode * Nf;
+  double acc = 0.0;
+  for (int dy = -1; dy <= 1; ++dy)
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int fx = 2 * I + dx, fy = 2 * J + dy;   // always interior
+      const double w = (dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0);
+      acc += w * r[(int64_t)(fy - 1) * mf + (fx - 1)];
+    }
+  bc[gid] = acc;
+}
+
+void launch_restrict(hipStream_t s, const Level& Lf, const Level& Lc, int modes, const double* rf,
+                     double* bc) {
+  const int64_t tot = Lc.N * modes;
+  hipLaunchKernelGGL(restrict_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, s, Lf.n, Lf.N, Lc.N,
+                     modes, rf, bc);
+}
+
+// x_f += P x_c (bilinear interpolation, zero coarse boundary)
+__global__ void prolong_add_kernel(int nf, int64_t Nf, int64_t Nc, int modes,
+                                   const double* __restrict__ xc, double* __restrict__ xf) {
+  const int mf = nf - 1, mc = nf / 2 - 1;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= Nf * modes) return;
+  const int64_t node = gid % Nf;
+  const int64_t mode = gid / Nf;
+  const int i = (int)(node % mf) + 1, j = (int)(node / mf) + 1;
+  const double* c = xc + mode * Nc;
+  const int Ia = i >> 1, Ib = (i + 1) >> 1, Ja = j >> 1, Jb = (j + 1) >> 1;
+  double acc = 0.0;
+  if (i & 1) {
+    if (j & 1) {
+      // four coarse neighbours, 1/4 each
+      if (Ia >= 1 && Ja >= 1) acc += 0.25 * c[(int64_t)(Ja - 1) * mc + (Ia - 1)];
+      if (Ib <= mc && Ja >= 1) acc += 0.25 * c[(int64_t)(Ja - 1) * mc + (Ib - 1)];
+      if (Ia >= 1 && Jb <= mc) acc += 0.25 * c[(int64_t)(Jb - 1) * mc + (Ia - 1)];
+      if (Ib <= mc && Jb <= mc) acc += 0.25 * c[(int64_t)(Jb - 1) * mc + (Ib - 1)];
+    } else {
+      if (Ia >= 1) acc += 0.5 * c[(int64_t)(Ja - 1) * mc + (Ia - 1)];
+      if (Ib <= mc) acc += 0.5 * c[(int64_t)(Ja - 1) * mc + (Ib - 1)];
+    }
+  } else {
+    if (j & 1) {
+      if (Ja >= 1) acc += 0.5 * c[(int64_t)(Ja - 1) * mc + (Ia - 1)];
+      if (Jb <= mc) acc += 0.5 * c[(int64_t)(Jb - 1) * mc + (Ia - 1)];
+    } else {
+      acc = c[(int64_t)(Ja - 1) * mc + (Ia - 1)];
+    }
+  }
+  xf[gid] += acc;
+}
+
+void launch_prolong_add(hipStream_t s, const Level& Lf, const Level& Lc, int modes,
+                        const double* xc, double* xf) {
+  const int64_t tot = Lf.N * modes;
+  hipLaunchKernelGGL(prolong_add_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, s, Lf.n, Lf.N, Lc.N,
+                     modes, xc, xf);
+}
+
+// coarsest grid (n = 2): one unknown per mode, solved exactly
+__global__ void coarse_kernel(const double* __restrict__ S, int64_t N, int modes,
+                              const double* __restrict__ b, double* __restrict__ x) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= N * modes) return;
+  x[gid] = b[gid] / S[4 * N + gid % N];
+}
+
+void launch_coarse(hipStream_t s, const Level& L, int modes, const double* b, double* x) {
+  if (L.N != 1) throw Error(SG_ERR_INTERNAL, "coarsest level must have one unknown");
+  hipLaunchKernelGGL(coarse_kernel, dim3(cdiv(L.N * modes, 256)), dim3(256), 0, s, L.S, L.N,
+                     modes, b, x);
+}
+
+__global__ void gather_modes_kernel(int modes, const int* __restrict__ idx, int64_t Nh,
+                                    const double* __restrict__ src, double* __restrict__ dst,
+                                    int scatter) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= Nh * modes) return;
+  const int64_t node = gid % Nh;
+  const int t = (int)(gid / Nh);
+  const int64_t full = (int64_t)idx[t] * Nh + node;
+  if (scatter) dst[full] = src[gid];
+  else dst[gid] = src[full];
+}
+
+void launch_gather_modes(hipStream_t s, int modes, const int* idx, int64_t Nh, const double* src,
+                         double* dst) {
+  hipLaunchKernelGGL(gather_modes_kernel, dim3(cdiv(Nh * modes, 256)), dim3(256), 0, s, modes, idx,
+                     Nh, src, dst, 0);
+}
+
+void launch_scatter_modes(hipStream_t s, int modes, const int* idx, int64_t Nh, const double* src,
+                          double* dst) {
+  hipLaunchKernelGGL(gather_modes_kernel, dim3(cdiv(Nh * modes, 256)), dim3(256), 0, s, modes, idx,
+                     Nh, src, dst, 1);
+}
+
+__global__ void zero_kernel(double* x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.0;
+}
+
+void launch_zero(hipStream_t s, double* x, int64_t n) {
+  if (n > 0) hipLaunchKernelGGL(zero_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, x, n);
+}
+
+// ---------------------------------------------------------------------------
+// Krylov helpers.  Dots: every block reduces a fixed contiguous slice in a
+// fixed tree, partials are summed by one wavefront in block order.
+// ---------------------------------------------------------------------------
+constexpr int kDotThreads = 256;
+
+int dot_blocks(int64_t N) {
+  int64_t b = (N + 4 * kDotThreads - 1) / (4 * kDotThreads);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 1024));
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  // wavefront tree then across the block's four wavefronts
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// partial[l * nblk + block] = sum over the block's slice of V_l . w
+__global__ __launch_bounds__(kDotThreads) void multidot_kernel(
+    const double* __restrict__ V, int64_t ldv, int nv, const double* __restrict__ w, int64_t N,
+    double* __restrict__ partial, int nblk) {
+  __shared__ double red[4];
+  const int64_t per = (N + nblk - 1) / nblk;
+  const int64_t lo = (int64_t)blockIdx.x * per;
+  const int64_t hi = std::min<int64_t>(N, lo + per);
+  for (int l = 0; l < nv; ++l) {
+    const double* v = V + (int64_t)l * ldv;
+    double acc = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kDotThreads) acc = fma(v[i], w[i], acc);
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[(int64_t)l * nblk + blockIdx.x] = s;
+  }
+}
+
+void launch_multidot(hipStream_t s, const double* V, int64_t ldv, int nv, const double* w,
+                     int64_t N, double* partial, int nblk) {
+  hipLaunchKernelGGL(multidot_kernel, dim3(nblk), dim3(kDotThreads), 0, s, V, ldv, nv, w, N,
+                     partial, nblk);
+}
+
+// out[l] = sum_b partial[l * nblk + b], one wavefront per l
+__global__ void reduce_kernel(const double* __restrict__ partial, int nblk, int nv,
+                              double* __restrict__ out) {
+  const int l = blockIdx.x;
+  if (l >= nv) return;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 64) acc += partial[(int64_t)l * nblk + b];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+  if (threadIdx.x == 0) out[l] = acc;
+}
+
+void launch_reduce(hipStream_t s, const double* partial, int nblk, int nv, double* out) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(nv), dim3(64), 0, s, partial, nblk, nv, out);
+}
+
+// w += sign * sum_l h[l] V_l
+__global__ void update_kernel(const double* __restrict__ V, int64_t ldv, int nv,
+                              const double* __restrict__ h, double* __restrict__ w, int64_t N,
+                              double sign) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double acc = 0.0;
+  for (int l = 0; l < nv; ++l) acc = fma(h[l], V[(int64_t)l * ldv + i], acc);
+  w[i] += sign * acc;
+}
+
+void launch_update(hipStream_t s, const double* V, int64_t ldv, int nv, const double* h, double* w,
+                   int64_t N, double sign) {
+  hipLaunchKernelGGL(update_kernel, dim3(cdiv(N, 256)), dim3(256), 0, s, V, ldv, nv, h, w, N, sign);
+}
+
+// out = sum_l y[l] V_l
+__global__ void combine_kernel(const double* __restrict__ V, int64_t ldv, int nv,
+                               const double* __restrict__ y, double* __restrict__ out, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double acc = 0.0;
+  for (int l = 0; l < nv; ++l) acc = fma(y[l], V[(int64_t)l * ldv + i], acc);
+  out[i] = acc;
+}
+
+void launch_combine(hipStream_t s, const double* V, int64_t ldv, int nv, const double* y,
+                    double* out, int64_t N) {
+  hipLaunchKernelGGL(combine_kernel, dim3(cdiv(N, 256)), dim3(256), 0, s, V, ldv, nv, y, out, N);
+}
+
+// v = w / sqrt(nrm2[0]) (v = 0 when the norm vanishes: breakdown)
+__global__ void scale_kernel(const double* __restrict__ w, const double* __restrict__ nrm2,
+                             double* __restrict__ v, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double nn = sqrt(nrm2[0]);
+  v[i] = nn > 0.0 ? w[i] / nn : 0.0;
+}
+
+void launch_scale_by_inv_norm(hipStream_t s, const double* w, const double* nrm2, double* v,
+                              int64_t N) {
+  hipLaunchKernelGGL(scale_kernel, dim3(cdiv(N, 256)), dim3(256), 0, s, w, nrm2, v, N);
+}
+
+__global__ void axpby_kernel(double a, const double* __restrict__ x, double b,
+                             double* __restrict__ y, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];
+}
+
+void launch_axpby(hipStream_t s, double a, const double* x, double b, double* y, int64_t N) {
+  hipLaunchKernelGGL(axpby_kernel, dim3(cdiv(N, 256)), dim3(256), 0, s, a, x, b, y, N);
+}
+
+__global__ void sub_kernel(const double* __restrict__ a, const double* __restrict__ b,
+                           double* __restrict__ out, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) out[i] = a[i] - b[i];
+}
+
+void launch_sub(hipStream_t s, const double* a, const double* b, double* out, int64_t N) {
+  hipLaunchKernelGGL(sub_kernel, dim3(cdiv(N, 256)), dim3(256), 0, s, a, b, out, N);
+}
+
+}  // namespace sg

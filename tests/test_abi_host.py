@@ -1,0 +1,112 @@
+"""CPU-side checks of the C ABI library: it loads, exports every declared entry
+point, validates arguments, and its host set-up tables (written independently
+in C++) agree with the oracle.  No device call is made here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1910_11505_amd as sg
+from paper_1910_11505_amd.binding import make_problem
+from oracle import kl as okl
+from oracle import pc as opc
+from oracle.precond import make_groups
+from oracle.system import SGSystem
+from synth import CONFIGS, Problem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "sg.h")).read()
+    return sorted(set(re.findall(r"\b(sg_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = sg.load_library()
+    names = _declared()
+    assert "sg_apply" in names and "sg_gmres_solve" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def _setup(**kw):
+    base = dict(n=16, M=2, p=2, q=4, cov="exp_l1", mu=0.0, sigma=0.5, corr_len=0.5, a_min=0.01)
+    base.update(kw)
+    return sg.sg_setup(make_problem(**base))
+
+
+@pytest.mark.parametrize("kw", [dict(n=12), dict(n=2), dict(M=0), dict(p=-1), dict(q=17),
+                                dict(sigma=-1.0), dict(corr_len=0.0), dict(a_min=-0.1),
+                                dict(cov=7), dict(sigma=float("nan"))])
+def test_invalid_problem_rejected(kw):
+    with pytest.raises(sg.SGError) as e:
+        _setup(**kw)
+    assert e.value.code == -1
+
+
+def test_unsupported_size_rejected():
+    with pytest.raises(sg.SGError) as e:
+        _setup(M=6, p=6, q=6)          # P = 924 modes
+    assert e.value.code == -2
+
+
+def test_device_calls_need_binding():
+    h = _setup()
+    with pytest.raises(sg.SGError) as e:
+        sg.sg_apply(h, 256, 512, 0)
+    assert e.value.code == -4
+    with pytest.raises(sg.SGError):
+        sg.sg_precond_apply(h, "mean", "klvar", 256, 256, 0)   # aliasing / not bound
+    sg.sg_destroy(h)
+
+
+def test_nonfinite_forcing_rejected():
+    f = np.ones(17 * 17)
+    f[5] = np.inf
+    with pytest.raises(sg.SGError) as e:
+        sg.sg_setup(make_problem(16, 2, 2, 4), f)
+    assert e.value.code == -1
+
+
+@pytest.mark.parametrize("M,p,q", [(2, 2, 4), (4, 3, 6), (6, 3, 6), (3, 2, 3)])
+def test_sizes_match_oracle(M, p, q):
+    h = _setup(M=M, p=p, q=q)
+    P, Nh, na, nnz = sg.sg_sizes(h)
+    Jp, Jq = opc.multi_indices(M, p), opc.multi_indices(M, q)
+    assert (P, Nh, na, nnz) == (len(Jp), 15 * 15, len(Jq), len(opc.triple_products(Jp, Jq)[3]))
+    assert sg.sg_workspace_bytes(h) > 8 * na * 4 * 16 * 16
+    sg.sg_destroy(h)
+
+
+@pytest.mark.parametrize("name", ["c0", "c1"])
+def test_kl_tables_match_oracle(name):
+    pr = CONFIGS[name]
+    h = _setup(n=pr.n, M=pr.M, p=pr.p, q=pr.q, cov=pr.cov, sigma=pr.sigma, corr_len=pr.corr_len)
+    lam = np.zeros(pr.M)
+    sg.sg_export(h, "kl", 0, lam)
+    gq = np.zeros(pr.M * 4 * pr.n * pr.n)
+    sg.sg_export(h, "gq", 0, gq)
+    olam, B, _ = okl.kl_2d(pr.n, pr.cov, pr.corr_len, pr.sigma, pr.M)
+    og = okl.g_at_quad(pr.n, olam, B).reshape(-1)
+    assert np.allclose(lam, olam, rtol=1e-12, atol=0)
+    assert np.abs(gq - og).max() <= 1e-12 * np.abs(og).max()
+    sg.sg_destroy(h)
+
+
+@pytest.mark.parametrize("M,p", [(2, 4), (4, 3), (6, 3), (3, 3)])
+@pytest.mark.parametrize("gname,gid", [("klvar", 0), ("klvar_meansep", 1), ("permode", 2), ("fg", 3)])
+def test_groupings_match_oracle(M, p, gname, gid):
+    h = _setup(M=M, p=p, q=2 * p)
+    out = np.zeros(2000)
+    sg.sg_export(h, "groups", gid, out)
+    S = int(out[0])
+    pos, got = 1, []
+    for _ in range(S):
+        sz = int(out[pos])
+        got.append([int(v) for v in out[pos + 1:pos + 1 + sz]])
+        pos += 1 + sz
+    assert got == make_groups(opc.multi_indices(M, p), gname)
+    sg.sg_destroy(h)

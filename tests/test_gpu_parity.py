@@ -1,0 +1,131 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: set-up tables 1e-13 relative; operator and preconditioner applies 1e-12
+relative (max-norm, relative to the oracle's max); solves 1e-10 on the
+solution where both sides run the same algorithm to a tight tolerance."""
+import numpy as np
+import pytest
+
+import paper_1910_11505_amd as sg
+from synth import Problem, random_vector, rhs_noisy
+
+from gpu_common import instance, need_gpu, relmax, stencil_of, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # several 4x4 tiles, L1-exponential field, f = 1
+    "n16_m2p2": Problem(n=16, M=2, p=2, q=4, cov="exp_l1", sigma=0.8, corr_len=0.5),
+    # squared-exponential field, chunked coefficient stream (n_a = 210)
+    "n16_m4p3": Problem(n=16, M=4, p=3, q=6, cov="sqexp", sigma=1.0, corr_len=0.5),
+    # the largest mode count of the workloads (P = 84, n_a = 924)
+    "n8_m6p3": Problem(n=8, M=6, p=3, q=6, cov="exp_l1", sigma=1.0, corr_len=0.25),
+    # one tile only, q < 2p (truncated coefficient), odd splits
+    "n4_m3p2q3": Problem(n=4, M=3, p=2, q=3, cov="exp_l1", sigma=0.6, corr_len=0.7),
+    # wider grid, nodal-noise forcing
+    "n32_m3p2": Problem(n=32, M=3, p=2, q=4, cov="sqexp", sigma=1.2, corr_len=0.4),
+}
+
+_cache = {}
+
+
+def pair(name):
+    need_gpu()
+    if name not in _cache:
+        from oracle.system import SGSystem
+        from oracle.gmg import GMGHierarchy
+        prob = CASES[name]
+        f = rhs_noisy(prob.n, 7) if name == "n32_m3p2" else None
+        S = SGSystem(prob, f)
+        H = GMGHierarchy(S.A[0], prob.n)
+        print(f"[parity case {name}] P={S.P} n_a={S.na} N_h={S.Nh}", flush=True)
+        _cache[name] = (S, H, instance(prob, f))
+    return _cache[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_setup_tables(name):
+    S, H, G = pair(name)
+    a = G.export("coeff")
+    assert relmax(a, S.a.reshape(-1)) < 1e-13
+    for lvl, A in enumerate(H.A):
+        st = np.zeros(9 * A.shape[0])
+        sg.sg_export(G.h, "stencil", lvl, st)
+        ref = stencil_of(A, H.ns[lvl]).reshape(-1)
+        assert relmax(st, ref) < 1e-13, lvl
+    F = to_host(G.rhs())
+    assert relmax(F, S.rhs()) < 1e-14
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply(name):
+    S, H, G = pair(name)
+    U = random_vector(S.P * S.Nh, 101)
+    W = to_host(G.apply(to_dev(U)))
+    assert relmax(W, S.apply(U)) < 1e-12
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply_is_deterministic(name):
+    S, H, G = pair(name)
+    U = to_dev(random_vector(S.P * S.Nh, 102))
+    W1 = to_host(G.apply(U))
+    W2 = to_host(G.apply(U))
+    assert np.array_equal(W1, W2)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("pc,grouping", [("mean", "klvar"), ("fs", "klvar"), ("fs", "klvar_meansep"),
+                                         ("fs", "permode"), ("fs", "fg")])
+def test_precond(name, pc, grouping):
+    from oracle.precond import FieldSplit, make_groups
+    S, H, G = pair(name)
+    r = random_vector(S.P * S.Nh, 103)
+    z = to_host(G.precond(to_dev(r), pc, grouping))
+    groups = make_groups(S.Jp, "mean" if pc == "mean" else grouping)
+    ref = FieldSplit(S, H, groups).apply(r)
+    assert relmax(z, ref) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["n16_m2p2", "n16_m4p3", "n32_m3p2"])
+@pytest.mark.parametrize("pc", ["mean", "fs"])
+def test_gmres_same_algorithm(name, pc):
+    from oracle.gmres import gmres
+    from oracle.precond import FieldSplit, make_groups
+    S, H, G = pair(name)
+    K = S.assemble()
+    fs = FieldSplit(S, H, make_groups(S.Jp, "mean" if pc == "mean" else "klvar"))
+    F = S.rhs()
+    xo, io = gmres(lambda v: K @ v, fs.apply, F, tol=1e-8, restart=50)
+    u, info, hist = G.solve(pc=pc, grouping="klvar", tol=1e-8, restart=50, hist_len=200)
+    ug = to_host(u)
+    assert info.status == 0
+    assert abs(info.iterations - io["iterations"]) <= 1
+    relres = np.linalg.norm(F - K @ ug) / np.linalg.norm(F)
+    assert relres <= 1e-8 * (1 + 1e-6)
+    assert abs(relres - info.relres) <= 1e-12
+    # same Krylov method, same iterates: solutions agree far below the stop
+    assert np.linalg.norm(ug - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("name", ["n16_m2p2", "n8_m6p3"])
+def test_gmres_tight_matches_direct(name):
+    import scipy.sparse.linalg as spla
+    S, H, G = pair(name)
+    K = S.assemble()
+    F = S.rhs()
+    xs = spla.spsolve(K.tocsc(), F)
+    u, info, _ = G.solve(pc="fs", grouping="klvar", tol=1e-13, restart=50)
+    assert info.status == 0
+    assert np.linalg.norm(to_host(u) - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_gmres_restart_and_max_it():
+    S, H, G = pair("n16_m2p2")
+    u, info, hist = G.solve(pc="none", grouping="klvar", tol=1e-10, restart=5, max_it=7, hist_len=10)
+    assert info.status == 1 and info.iterations == 7 and info.restarts == 2
+    u, info, hist = G.solve(pc="mean", tol=1e-9, restart=3, hist_len=100)
+    assert info.status == 0 and info.restarts >= 2 and info.relres <= 1e-9
+    u0 = u.clone()
+    u, info, _ = G.solve(pc="mean", tol=1e-9, restart=3, u=u0, use_x0=True)
+    assert info.iterations == 0 and info.status == 0

@@ -112,3 +112,13 @@ def test_coefficient_chaos_converges_in_q():
         assert np.all(s >= prev - 1e-15) and np.all(s <= Ea2 * (1 + 1e-14))
         prev = s
     assert np.allclose(prev, Ea2, rtol=1e-10)
+
+
+def test_sampled_apply_matches_full_apply():
+    S = SGSystem(TINY.with_(n=8))
+    U = np.random.default_rng(10).standard_normal(S.P * S.Nh)
+    W = S.apply(U).reshape(S.P, S.Nh)
+    nodes = [0, 5, 17, 48]
+    modes = [0, 2, 5]
+    Ws = S.apply_at(U, modes, nodes)
+    assert np.allclose(Ws, W[np.ix_(modes, nodes)], rtol=1e-13, atol=1e-13)
