@@ -56,6 +56,10 @@ enum { SG_COV_EXP_L1 = 0, SG_COV_SQEXP = 1 };
  * ordered splits of the modes, eqs. P_preconditioner / P_group, with the
  * same V-cycle for every diagonal block) */
 enum { SG_PC_NONE = 0, SG_PC_MEAN = 1, SG_PC_FS = 2 };
+/* flag OR-ed into SG_PC_MEAN or SG_PC_FS: the V(2,2) cycle of mode i runs on
+ * that mode's own diagonal block K_ii = sum_k [G_k]_{ii} A_k (the paper's
+ * diagonal blocks of eq. P_preconditioner) instead of the mean stiffness A_0 */
+enum { SG_PC_DIAG_KII = 0x100 };
 
 /* splits of the modes for SG_PC_FS:
  *  KLVAR         split n = modes whose first nonzero index is n; mean in split 1

@@ -36,10 +36,12 @@ struct FSHost {
   std::vector<std::vector<int>> splits;
   std::vector<RowSetHost> partial;  // partial[s] for s >= 1 (index 0 unused)
   std::vector<int> kc, nchunk;      // chunking of each partial row set
+  std::vector<std::vector<int>> sid;  // stencil ids (mode + 1) of each split
 };
 
 struct FSDev {
   std::vector<int*> split_idx;
+  std::vector<int*> split_sid;   // stencil id (mode + 1) of every mode of a split
   std::vector<RowSetDev> partial;
 };
 
@@ -53,6 +55,10 @@ struct DevPtrs {
   double* edge = nullptr;
   std::vector<double*> mg_b, mg_x, mg_xa, mg_r;
   double *fsT = nullptr, *fsX = nullptr;
+  int* all_sid = nullptr;        // mode + 1 for every mode
+  int* diag_k = nullptr;         // (k, v) lists of the diagonal blocks
+  double* diag_v = nullptr;
+  double* cdiag = nullptr;       // one coefficient field (set-up scratch)
 };
 
 // bump allocator over the caller's workspace (or a dry run to size it)
@@ -82,6 +88,9 @@ struct sg_handle {
   int full_kc = 0, full_nchunk = 0;
   FSHost fs[4];
   std::vector<int> level_n;
+  std::vector<int> diag_ptr, diag_k, diag_sid;  // per mode i: [G_k]_{ii} != 0 entries
+  std::vector<double> diag_v;
+  int nfine = 0;                                // levels with n > kCoarseN
 
   // device state
   bool bound = false;
@@ -97,21 +106,36 @@ struct sg_handle {
 
 namespace {
 
-// kc: modes of a_k staged per chunk; keep LDS <= 80 KB (two workgroups per CU)
-// when the gradients allow, else use the whole 160 KB.
-int choose_kc(int ncols, int na) {
-  auto fit = [&](size_t budget) {
-    long avail = (long)(budget / 8) - 2L * ncols * kTileQ;
-    return (int)(avail / kTileQ);
-  };
-  int kc = fit(80 * 1024);
-  if (kc < 16) kc = fit(160 * 1024);
-  kc = std::min(kc, 128);
-  kc = std::min(kc, na);
-  if (kc < 1 || apply_lds_bytes(ncols, std::max(kc, 1)) > 160 * 1024)
-    throw Error(SG_ERR_UNSUPPORTED, "apply: the gradients of " + std::to_string(ncols) +
-                                        " modes do not fit in LDS");
-  return kc;
+// Groups a row set's nonzero triple products by coefficient chunk of kc modes:
+// chunk-major, and inside a chunk row by row, every row segment padded to
+// kEntryUnroll entries.  Returns the largest entry count of one chunk.
+int layout_entries(const sg_handle& H, RowSetHost& rs, int kc, const std::vector<int>& rslot,
+                   const std::vector<int>& cslot) {
+  const int nchunk = (H.na + kc - 1) / kc;
+  std::vector<std::vector<std::vector<std::pair<int, double>>>> bucket(
+      nchunk, std::vector<std::vector<std::pair<int, double>>>(rs.nrows));
+  for (const Triple& tr : H.G) {
+    int r = rslot[tr.i], c = cslot[tr.j];
+    if (r < 0 || c < 0) continue;
+    int ch = tr.k / kc;
+    bucket[ch][r].push_back({(tr.k - ch * kc) | (c << 16), tr.v});
+  }
+  rs.ent.clear();
+  rs.ptr.assign((size_t)nchunk * (rs.nrows + 1), 0);
+  int maxent = 0;
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int base = (int)rs.ent.size();
+    for (int r = 0; r < rs.nrows; ++r) {
+      rs.ptr[(size_t)ch * (rs.nrows + 1) + r] = (int)rs.ent.size();
+      for (auto& e : bucket[ch][r]) rs.ent.push_back(Entry{e.first, 0, e.second});
+      while (rs.ent.size() % kEntryUnroll) rs.ent.push_back(Entry{0, 0, 0.0});
+    }
+    rs.ptr[(size_t)ch * (rs.nrows + 1) + rs.nrows] = (int)rs.ent.size();
+    maxent = std::max(maxent, (int)rs.ent.size() - base);
+  }
+  // one zero group past the end: the apply kernel loads a group ahead
+  for (int u = 0; u < kEntryUnroll; ++u) rs.ent.push_back(Entry{0, 0, 0.0});
+  return maxent;
 }
 
 RowSetHost build_rowset(const sg_handle& H, const std::vector<int>& rows,
@@ -121,32 +145,38 @@ RowSetHost build_rowset(const sg_handle& H, const std::vector<int>& rows,
   rs.cols = cols;
   rs.nrows = (int)rows.size();
   rs.ncols = (int)cols.size();
-  const int kc = choose_kc(std::max(rs.ncols, 1), H.na);
-  const int nchunk = (H.na + kc - 1) / kc;
   std::vector<int> rslot(H.P, -1), cslot(H.P, -1);
   for (int t = 0; t < rs.nrows; ++t) rslot[rows[t]] = t;
   for (int t = 0; t < rs.ncols; ++t) cslot[cols[t]] = t;
-  std::vector<std::vector<std::vector<std::pair<int, double>>>> bucket(
-      rs.nrows, std::vector<std::vector<std::pair<int, double>>>(nchunk));
-  for (const Triple& tr : H.G) {
-    int r = rslot[tr.i], c = cslot[tr.j];
-    if (r < 0 || c < 0) continue;
-    int ch = tr.k / kc;
-    bucket[r][ch].push_back({(tr.k - ch * kc) | (c << 16), tr.v});
-  }
-  rs.ptr.assign((size_t)rs.nrows * (nchunk + 1), 0);
-  std::vector<long> load(rs.nrows, 0);
-  for (int r = 0; r < rs.nrows; ++r) {
-    rs.ptr[(size_t)r * (nchunk + 1)] = (int)rs.kj.size();
-    for (int ch = 0; ch < nchunk; ++ch) {
-      for (auto& e : bucket[r][ch]) {
-        rs.kj.push_back(e.first);
-        rs.v.push_back(e.second);
+  // kc: coefficient modes staged per chunk.  Prefer three workgroups per CU
+  // (<= 53 KB of LDS) with chunks of >= 32 modes, then two, then one.
+  const int ncl = std::max(rs.ncols, 1);
+  const int cands[] = {64, 48, 32, 24, 16, 12, 8, 6, 4, 3, 2, 1};
+  static_assert(kMaxChunk == 64, "candidate list starts at kMaxChunk");
+  const struct { size_t budget; int minkc; } tiers[] = {{53 * 1024, 32}, {80 * 1024, 16},
+                                                         {160 * 1024, 1}};
+  int kc = 0;
+  for (auto& tier : tiers) {
+    for (int c : cands) {
+      const int kcc = std::min(c, H.na);
+      if (kcc < std::min(tier.minkc, H.na)) break;
+      const int maxent = layout_entries(H, rs, kcc, rslot, cslot);
+      if (apply_lds_bytes(ncl, kcc, maxent) <= tier.budget) {
+        kc = kcc;
+        rs.maxent = maxent;
+        break;
       }
-      rs.ptr[(size_t)r * (nchunk + 1) + ch + 1] = (int)rs.kj.size();
     }
-    load[r] = rs.ptr[(size_t)r * (nchunk + 1) + nchunk] - rs.ptr[(size_t)r * (nchunk + 1)];
+    if (kc) break;
   }
+  if (!kc)
+    throw Error(SG_ERR_UNSUPPORTED, "apply: the gradients of " + std::to_string(rs.ncols) +
+                                        " modes do not fit in LDS");
+  const int nchunk = (H.na + kc - 1) / kc;
+  std::vector<long> load(rs.nrows, 0);
+  for (int ch = 0; ch < nchunk; ++ch)
+    for (int r = 0; r < rs.nrows; ++r)
+      load[r] += rs.ptr[(size_t)ch * (rs.nrows + 1) + r + 1] - rs.ptr[(size_t)ch * (rs.nrows + 1) + r];
   // rows to wavefronts: longest rows first onto the least loaded wavefront
   const int need = std::max(1, (rs.nrows + kApplyWaves - 1) / kApplyWaves);
   int rmax = 1;
@@ -195,28 +225,30 @@ void carve(const sg_handle& H, DevPtrs& D, Carver& c) {
     Level lv;
     lv.n = ln;
     lv.N = (int64_t)(ln - 1) * (ln - 1);
-    lv.S = c.take<double>(9 * (size_t)lv.N);
+    lv.S = c.take<double>(9 * (size_t)lv.N * (1 + H.P));  // A_0, then K_ii per mode
     D.L.push_back(lv);
   }
   auto put_rowset = [&](const RowSetHost& rs, RowSetDev& d) {
     d.nrows = rs.nrows;
     d.ncols = rs.ncols;
     d.rmax = rs.rmax;
+    d.maxent = rs.maxent;
     d.rows = c.take<int>(rs.rows.size());
     d.cols = c.take<int>(std::max<size_t>(rs.cols.size(), 1));
     d.wrows = c.take<int>(rs.wrows.size());
     d.ptr = c.take<int>(rs.ptr.size());
-    d.kj = c.take<int>(std::max<size_t>(rs.kj.size(), 1));
-    d.v = c.take<double>(std::max<size_t>(rs.v.size(), 1));
+    d.ent = c.take<Entry>(std::max<size_t>(rs.ent.size(), 1));
   };
   put_rowset(H.full, D.full);
   for (int g = 0; g < 4; ++g) {
     const FSHost& fh = H.fs[g];
     FSDev& fd = D.fs[g];
     fd.split_idx.assign(fh.splits.size(), nullptr);
+    fd.split_sid.assign(fh.splits.size(), nullptr);
     fd.partial.assign(fh.splits.size(), RowSetDev{});
     for (size_t s = 0; s < fh.splits.size(); ++s) {
       fd.split_idx[s] = c.take<int>(fh.splits[s].size());
+      fd.split_sid[s] = c.take<int>(fh.splits[s].size());
       if (s >= 1) put_rowset(fh.partial[s], fd.partial[s]);
     }
   }
@@ -237,6 +269,10 @@ void carve(const sg_handle& H, DevPtrs& D, Carver& c) {
   }
   D.fsT = c.take<double>((size_t)H.P * H.Nh);
   D.fsX = c.take<double>((size_t)H.P * H.Nh);
+  D.all_sid = c.take<int>(H.P);
+  D.diag_k = c.take<int>(std::max<size_t>(H.diag_k.size(), 1));
+  D.diag_v = c.take<double>(std::max<size_t>(H.diag_v.size(), 1));
+  D.cdiag = c.take<double>(H.Nq);
 }
 
 template <class T>
@@ -251,8 +287,7 @@ void upload_rowset(hipStream_t s, const RowSetHost& h, const RowSetDev& d) {
   upload(s, d.cols, h.cols);
   upload(s, d.wrows, h.wrows);
   upload(s, d.ptr, h.ptr);
-  upload(s, d.kj, h.kj);
-  upload(s, d.v, h.v);
+  upload(s, d.ent, h.ent);
 }
 
 void check_launch() {
@@ -260,23 +295,31 @@ void check_launch() {
   if (e != hipSuccess) throw Error(SG_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
 }
 
-void vcycle(sg_handle& H, hipStream_t s, size_t lvl, int m, const double* b, double* x) {
+// One V(2,2) cycle for m modes: b and x hold m compact vectors of the finest
+// level; smode (device, may be null) gives each mode's stencil id.
+void vcycle(sg_handle& H, hipStream_t s, int m, const int* smode, const double* b, double* x) {
   DevPtrs& D = H.d;
-  const Level& Lv = D.L[lvl];
-  if (lvl + 1 == D.L.size()) {
-    launch_coarse(s, Lv, m, b, x);
-    return;
+  const int nf = H.nfine;
+  std::vector<const double*> bl(D.L.size());
+  std::vector<double*> xl(D.L.size());
+  bl[0] = b;
+  xl[0] = x;
+  for (size_t l = 1; l < D.L.size(); ++l) {
+    bl[l] = D.mg_b[l];
+    xl[l] = D.mg_x[l];
   }
-  double* xa = D.mg_xa[lvl];
-  double* r = D.mg_r[lvl];
-  launch_jacobi(s, Lv, m, b, nullptr, xa, kOmega, true);
-  launch_jacobi(s, Lv, m, b, xa, x, kOmega, false);
-  launch_residual(s, Lv, m, b, x, r);
-  launch_restrict(s, Lv, D.L[lvl + 1], m, r, D.mg_b[lvl + 1]);
-  vcycle(H, s, lvl + 1, m, D.mg_b[lvl + 1], D.mg_x[lvl + 1]);
-  launch_prolong_add(s, Lv, D.L[lvl + 1], m, D.mg_x[lvl + 1], x);
-  launch_jacobi(s, Lv, m, b, x, xa, kOmega, false);
-  launch_jacobi(s, Lv, m, b, xa, x, kOmega, false);
+  for (int l = 0; l < nf; ++l)
+    launch_vdown(s, D.L[l], D.L[l + 1], m, smode, bl[l], D.mg_xa[l], D.mg_b[l + 1], kOmega);
+  CoarseLevels cl{};
+  cl.nl = (int)D.L.size() - nf;
+  for (int l = 0; l < cl.nl; ++l) {
+    cl.n[l] = D.L[nf + l].n;
+    cl.N[l] = D.L[nf + l].N;
+    cl.S[l] = D.L[nf + l].S;
+  }
+  launch_vcoarse(s, cl, m, smode, bl[nf], xl[nf], kOmega);
+  for (int l = nf - 1; l >= 0; --l)
+    launch_vup(s, D.L[l], D.L[l + 1], m, smode, bl[l], D.mg_xa[l], xl[l + 1], xl[l], kOmega);
 }
 
 void do_apply(sg_handle& H, hipStream_t s, const double* U, double* W) {
@@ -286,15 +329,17 @@ void do_apply(sg_handle& H, hipStream_t s, const double* U, double* W) {
 
 void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double* r, double* z) {
   const int64_t Nv = (int64_t)H.P * H.Nh;
-  if (pc == SG_PC_NONE) {
+  const bool kii = (pc & SG_PC_DIAG_KII) != 0;
+  const int kind = pc & 0xff;
+  if (kind == SG_PC_NONE) {
     SG_HIP(hipMemcpyAsync(z, r, Nv * sizeof(double), hipMemcpyDeviceToDevice, s));
     return;
   }
-  if (pc == SG_PC_MEAN) {
-    vcycle(H, s, 0, H.P, r, z);
+  if (kind == SG_PC_MEAN) {
+    vcycle(H, s, H.P, kii ? H.d.all_sid : nullptr, r, z);
     return;
   }
-  if (pc != SG_PC_FS) throw Error(SG_ERR_INVALID_ARG, "unknown preconditioner");
+  if (kind != SG_PC_FS) throw Error(SG_ERR_INVALID_ARG, "unknown preconditioner");
   if (grouping < 0 || grouping > 3) throw Error(SG_ERR_INVALID_ARG, "unknown grouping");
   const FSHost& fh = H.fs[grouping];
   const FSDev& fd = H.d.fs[grouping];
@@ -306,9 +351,16 @@ void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double*
       launch_apply(s, H.n, fh.nchunk[sp], fh.kc[sp], H.na, H.d.a, fd.partial[sp], z, H.Nh, r, 1.0,
                    -1.0, H.d.fsT, H.d.edge);
     }
-    vcycle(H, s, 0, m, H.d.fsT, H.d.fsX);
+    vcycle(H, s, m, kii ? fd.split_sid[sp] : nullptr, H.d.fsT, H.d.fsX);
     launch_scatter_modes(s, m, fd.split_idx[sp], H.Nh, H.d.fsX, z);
   }
+}
+
+bool valid_pc(int pc) {
+  const int kind = pc & 0xff, flags = pc & ~0xff;
+  if (kind < SG_PC_NONE || kind > SG_PC_FS) return false;
+  if (flags & ~SG_PC_DIAG_KII) return false;
+  return true;
 }
 
 }  // namespace
@@ -373,6 +425,9 @@ int sg_setup(const sg_problem* prob, const double* f_nodal, sg_handle** out) {
       fh.splits = make_splits(H->Jp, g);
       fh.partial.assign(fh.splits.size(), RowSetHost{});
       fh.kc.assign(fh.splits.size(), 0);
+      fh.sid.assign(fh.splits.size(), {});
+      for (size_t sp = 0; sp < fh.splits.size(); ++sp)
+        for (int i : fh.splits[sp]) fh.sid[sp].push_back(i + 1);
       fh.nchunk.assign(fh.splits.size(), 0);
       std::vector<int> prev;
       for (size_t s = 0; s < fh.splits.size(); ++s) {
@@ -381,7 +436,22 @@ int sg_setup(const sg_problem* prob, const double* f_nodal, sg_handle** out) {
         prev.insert(prev.end(), fh.splits[s].begin(), fh.splits[s].end());
       }
     }
-    for (int ln = H->n; ln >= 2; ln /= 2) H->level_n.push_back(ln);
+    for (int ln = H->n; ln >= 2; ln /= 2) {
+      H->level_n.push_back(ln);
+      if (ln > kCoarseN) H->nfine++;
+    }
+    if ((int)H->level_n.size() - H->nfine > kMaxCoarseLevels)
+      throw Error(SG_ERR_INTERNAL, "too many coarse levels");
+    H->diag_ptr.assign(1, 0);
+    for (int i = 0; i < H->P; ++i) {
+      for (const Triple& t : H->G)
+        if (t.i == i && t.j == i) {
+          H->diag_k.push_back(t.k);
+          H->diag_v.push_back(t.v);
+        }
+      H->diag_ptr.push_back((int)H->diag_k.size());
+      H->diag_sid.push_back(i + 1);
+    }
     *out = H.release();
     return SG_OK;
   } catch (const Error& e) {
@@ -431,11 +501,26 @@ int sg_bind(sg_handle* h, void* dev_workspace, size_t bytes, void* stream) {
     for (int g = 0; g < 4; ++g)
       for (size_t sp = 0; sp < H.fs[g].splits.size(); ++sp) {
         upload(s, D.fs[g].split_idx[sp], H.fs[g].splits[sp]);
+        upload(s, D.fs[g].split_sid[sp], H.fs[g].sid[sp]);
         if (sp >= 1) upload_rowset(s, H.fs[g].partial[sp], D.fs[g].partial[sp]);
       }
+    upload(s, D.all_sid, H.diag_sid);
+    upload(s, D.diag_k, H.diag_k);
+    upload(s, D.diag_v, H.diag_v);
     launch_coeff(s, H.n, H.M, H.na, D.g, D.Jq, D.isf, H.prob.mu, H.prob.a_min, D.a);
-    launch_fine_stencil(s, H.n, D.a, D.L[0].S);
-    for (size_t l = 1; l < D.L.size(); ++l) launch_rap(s, D.L[l - 1].n, D.L[l - 1].S, D.L[l].S);
+    // stencil 0: mean stiffness A_0; stencil i+1: diagonal block K_ii
+    for (int id = 0; id <= H.P; ++id) {
+      const double* coef = D.a;
+      if (id > 0) {
+        const int b0 = H.diag_ptr[id - 1], b1 = H.diag_ptr[id];
+        launch_diag_coeff(s, H.n, b1 - b0, D.diag_k + b0, D.diag_v + b0, D.a, D.cdiag);
+        coef = D.cdiag;
+      }
+      launch_fine_stencil(s, H.n, coef, D.L[0].S + (int64_t)id * 9 * D.L[0].N);
+      for (size_t l = 1; l < D.L.size(); ++l)
+        launch_rap(s, D.L[l - 1].n, D.L[l - 1].S + (int64_t)id * 9 * D.L[l - 1].N,
+                   D.L[l].S + (int64_t)id * 9 * D.L[l].N);
+    }
     check_launch();
     if (!H.host_pinned)
       SG_HIP(hipHostMalloc((void**)&H.host_pinned, sizeof(double) * (4 * (kMaxRestart + 2) + 8),
@@ -480,7 +565,7 @@ int sg_precond_apply(sg_handle* h, int pc, int grouping, const double* r, double
   if (!h || !r || !z) return fail(SG_ERR_INVALID_ARG, "null argument");
   if (r == z) return fail(SG_ERR_INVALID_ARG, "r and z must not alias");
   if (!h->bound) return fail(SG_ERR_NOT_BOUND, "handle not bound");
-  if (pc < SG_PC_NONE || pc > SG_PC_FS) return fail(SG_ERR_INVALID_ARG, "unknown preconditioner");
+  if (!valid_pc(pc)) return fail(SG_ERR_INVALID_ARG, "unknown preconditioner");
   if (grouping < 0 || grouping > 3) return fail(SG_ERR_INVALID_ARG, "unknown grouping");
   try {
     do_precond(*h, reinterpret_cast<hipStream_t>(stream), pc, grouping, r, z);
@@ -527,7 +612,7 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
   if (o->restart < 1 || o->restart > kMaxRestart) return fail(SG_ERR_INVALID_ARG, "restart out of range");
   if (o->max_it < 1) return fail(SG_ERR_INVALID_ARG, "max_it must be positive");
   if (!(o->tol > 0.0)) return fail(SG_ERR_INVALID_ARG, "tol must be positive");
-  if (o->pc < SG_PC_NONE || o->pc > SG_PC_FS) return fail(SG_ERR_INVALID_ARG, "unknown preconditioner");
+  if (!valid_pc(o->pc)) return fail(SG_ERR_INVALID_ARG, "unknown preconditioner");
   if (o->grouping < 0 || o->grouping > 3) return fail(SG_ERR_INVALID_ARG, "unknown grouping");
   if (ws_bytes < sg_gmres_workspace_bytes(h, o)) return fail(SG_ERR_WORKSPACE, "Krylov workspace too small");
   if (reinterpret_cast<uintptr_t>(krylov_ws) % 256) return fail(SG_ERR_WORKSPACE, "Krylov workspace must be 256-byte aligned");

@@ -23,6 +23,8 @@ constexpr int kApplyWaves = 4;       // wavefronts per apply workgroup
 constexpr int kEdgeVals = 9;         // right edge 4, top edge 4, corner 1
 constexpr int kMaxP = 256;
 constexpr int kMaxRestart = 200;
+constexpr int kCoarseN = 16;          // levels with n <= kCoarseN run in one LDS kernel
+constexpr int kMaxCoarseLevels = 8;
 
 struct Error : std::runtime_error {
   int code;
@@ -58,24 +60,31 @@ __host__ __device__ inline int64_t tiled_q(int n, int ex, int ey, int qx, int qy
 // A row set of the operator: output modes `rows`, their nonzero triple
 // products bucketed by coefficient-mode chunk, and the input columns whose
 // gradients are needed.
+// one nonzero triple product of a row: (k - chunk base) | (column slot << 16), value
+struct alignas(16) Entry {
+  int kj;
+  int pad;
+  double v;
+};
+constexpr int kEntryUnroll = 4;  // row segments are padded to this many entries
+constexpr int kMaxChunk = 64;    // coefficient modes staged per chunk at most
+
 struct RowSetHost {
-  int nrows = 0, ncols = 0, rmax = 0;
+  int nrows = 0, ncols = 0, rmax = 0, maxent = 0;
   std::vector<int> rows;        // mode index of each output row
   std::vector<int> cols;        // mode index of each gradient column
   std::vector<int> wrows;       // kApplyWaves x rmax, row slot per wave (-1 pad)
-  std::vector<int> ptr;         // nrows x (nchunk+1)
-  std::vector<int> kj;          // (k - chunk base) | (col slot << 16)
-  std::vector<double> v;
+  std::vector<int> ptr;         // nchunk x (nrows+1): chunk-major row segments
+  std::vector<Entry> ent;       // zero-valued padding entries point at (0, 0)
 };
 
 struct RowSetDev {
-  int nrows, ncols, rmax;
+  int nrows, ncols, rmax, maxent;
   const int* rows;
   const int* cols;
   const int* wrows;
   const int* ptr;
-  const int* kj;
-  const double* v;
+  const Entry* ent;
 };
 
 struct Level {
@@ -93,7 +102,7 @@ void launch_rhs(hipStream_t s, int n, const double* f_nodal, double* F, int64_t 
 void launch_apply(hipStream_t s, int n, int nchunk, int kc, int na, const double* a,
                   const RowSetDev& rs, const double* U, int64_t Nh, const double* rin,
                   double beta, double sgn, double* out, double* edge);
-size_t apply_lds_bytes(int ncols, int kc);
+size_t apply_lds_bytes(int ncols, int kc, int maxent);
 void launch_zero(hipStream_t s, double* x, int64_t n);
 void launch_jacobi(hipStream_t s, const Level& L, int m, const double* b, const double* xin,
                    double* xout, double omega, bool first);
@@ -108,6 +117,22 @@ void launch_gather_modes(hipStream_t s, int m, const int* modes, int64_t Nh, con
                          double* dst);
 void launch_scatter_modes(hipStream_t s, int m, const int* modes, int64_t Nh, const double* src,
                           double* dst);
+// fused multigrid
+struct CoarseLevels {
+  int nl;
+  int n[kMaxCoarseLevels];
+  int64_t N[kMaxCoarseLevels];
+  const double* S[kMaxCoarseLevels];
+};
+void launch_vdown(hipStream_t s, const Level& Lf, const Level& Lc, int modes, const int* smode,
+                  const double* b, double* x2, double* bc, double omega);
+void launch_vup(hipStream_t s, const Level& Lf, const Level& Lc, int modes, const int* smode,
+                const double* b, const double* x2, const double* xc, double* x, double omega);
+void launch_vcoarse(hipStream_t s, const CoarseLevels& cl, int modes, const int* smode,
+                    const double* b, double* x, double omega);
+size_t vcoarse_lds_bytes(const CoarseLevels& cl);
+void launch_diag_coeff(hipStream_t s, int n, int cnt, const int* ks, const double* vs,
+                       const double* a, double* c);
 // Krylov helpers
 int dot_blocks(int64_t N);
 void launch_multidot(hipStream_t s, const double* V, int64_t ldv, int nv, const double* w,

@@ -240,16 +240,27 @@ __global__ __launch_bounds__(256) void apply_kernel(
   const int m = n - 1;
   double2* sG = reinterpret_cast<double2*>(smem);
   double* sA = smem + 2 * ncols * kTileQ;
+  const int sa_len = (max(max(kc * kTileQ, ncols * 25), kApplyWaves * kTileQ) + 1) & ~1;
+  Entry* sEnt = reinterpret_cast<Entry*>(sA + sa_len);
   const int x0 = tx * kTileE, y0 = ty * kTileE;
 
-  // 1. nodal values of the needed modes on the tile's 5x5 nodes
-  for (int idx = tid; idx < ncols * 25; idx += 256) {
-    const int c = idx / 25, nd = idx - c * 25;
-    const int gx = x0 + nd % 5, gy = y0 + nd / 5;
-    double v = 0.0;
-    if (gx >= 1 && gx <= m && gy >= 1 && gy <= m)
-      v = U[(int64_t)rs.cols[c] * Nh + (int64_t)(gy - 1) * m + (gx - 1)];
-    sA[idx] = v;
+  // 1. nodal values of the needed modes on the tile's 5x5 nodes (batched loads)
+  for (int base = tid; base < ncols * 25; base += 256 * 4) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = base + u * 256;
+      v[u] = 0.0;
+      if (idx < ncols * 25) {
+        const int c = idx / 25, nd = idx - c * 25;
+        const int gx = x0 + nd % 5, gy = y0 + nd / 5;
+        if (gx >= 1 && gx <= m && gy >= 1 && gy <= m)
+          v[u] = U[(int64_t)rs.cols[c] * Nh + (int64_t)(gy - 1) * m + (gx - 1)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (base + u * 256 < ncols * 25) sA[base + u * 256] = v[u];
   }
   __syncthreads();
   // 2. reference gradients at the Gauss points
@@ -271,27 +282,67 @@ __global__ __launch_bounds__(256) void apply_kernel(
 #pragma unroll
   for (int r = 0; r < RMAX; ++r) ax[r] = ay[r] = 0.0;
   const int* wrows = rs.wrows + wave * RMAX;
-  for (int ch = 0; ch < nchunk; ++ch) {
+  const int nrows = rs.nrows;
+  // coefficient chunks are prefetched into registers one chunk ahead, so the
+  // HBM latency of chunk ch+1 overlaps the flux work on chunk ch
+  constexpr int kPre = kMaxChunk * kTileQ / 256;
+  double pre[kPre];
+  auto prefetch = [&](int ch) {
     const int k0 = ch * kc;
-    const int kn = min(kc, na - k0);
+    const int cnt = min(kc, na - k0) * kTileQ;
     const double* src = a + (int64_t)k0 * Nq + (int64_t)tile * kTileQ;
-    for (int idx = tid; idx < kn * kTileQ; idx += 256)
-      sA[idx] = src[(int64_t)(idx >> 6) * Nq + (idx & 63)];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int idx = tid + u * 256;
+      pre[u] = (idx < cnt) ? src[(int64_t)(idx >> 6) * Nq + (idx & 63)] : 0.0;
+    }
+  };
+  prefetch(0);
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int cnt = min(kc, na - ch * kc) * kTileQ;
+#pragma unroll
+    for (int u = 0; u < kPre; ++u)
+      if (tid + u * 256 < cnt) sA[tid + u * 256] = pre[u];
+    // this chunk's triple products, all rows, as 16-byte records
+    const int cb = rs.ptr[ch * (nrows + 1)];
+    const int ce = rs.ptr[ch * (nrows + 1) + nrows];
+    const int4* esrc = reinterpret_cast<const int4*>(rs.ent + cb);
+    int4* edst = reinterpret_cast<int4*>(sEnt);
+    for (int base = tid; base < ce - cb; base += 256 * 4) {
+      int4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (base + u * 256 < ce - cb) v[u] = esrc[base + u * 256];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (base + u * 256 < ce - cb) edst[base + u * 256] = v[u];
+    }
     __syncthreads();
+    if (ch + 1 < nchunk) prefetch(ch + 1);
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) {
       const int slot = wrows[r];
       if (slot >= 0) {
-        const int b = rs.ptr[slot * (nchunk + 1) + ch];
-        const int e = rs.ptr[slot * (nchunk + 1) + ch + 1];
+        const int b = rs.ptr[ch * (nrows + 1) + slot] - cb;
+        const int e = rs.ptr[ch * (nrows + 1) + slot + 1] - cb;
         double sx = ax[r], sy = ay[r];
-        for (int t = b; t < e; ++t) {
-          const int kj = rs.kj[t];
-          const double v = rs.v[t];
-          const double av = sA[(kj & 0xffff) * kTileQ + lane] * v;
-          const double2 gg = sG[(kj >> 16) * kTileQ + lane];
-          sx = fma(av, gg.x, sx);
-          sy = fma(av, gg.y, sy);
+        for (int t = b; t < e; t += kEntryUnroll) {
+          Entry en[kEntryUnroll];
+#pragma unroll
+          for (int u = 0; u < kEntryUnroll; ++u) en[u] = sEnt[t + u];
+          double av[kEntryUnroll];
+          double2 gg[kEntryUnroll];
+#pragma unroll
+          for (int u = 0; u < kEntryUnroll; ++u) {
+            av[u] = sA[(en[u].kj & 0xffff) * kTileQ + lane];
+            gg[u] = sG[(en[u].kj >> 16) * kTileQ + lane];
+          }
+#pragma unroll
+          for (int u = 0; u < kEntryUnroll; ++u) {
+            const double c = av[u] * en[u].v;
+            sx = fma(c, gg[u].x, sx);
+            sy = fma(c, gg[u].y, sy);
+          }
         }
         ax[r] = sx;
         ay[r] = sy;
@@ -374,9 +425,10 @@ __global__ void apply_fixup_kernel(int n, int nrows, double sgn, const double* _
   out[(int64_t)slot * Nh + node] = v;
 }
 
-size_t apply_lds_bytes(int ncols, int kc) {
+size_t apply_lds_bytes(int ncols, int kc, int maxent) {
   size_t sa = std::max<size_t>({(size_t)kc * kTileQ, (size_t)ncols * 25, (size_t)kApplyWaves * kTileQ});
-  return 8 * (2 * (size_t)ncols * kTileQ + sa);
+  sa = (sa + 1) & ~size_t(1);  // keeps the entry records 16-byte aligned
+  return 8 * (2 * (size_t)ncols * kTileQ + sa) + sizeof(Entry) * (size_t)maxent;
 }
 
 void launch_apply(hipStream_t s, int n, int nchunk, int kc, int na, const double* a,
@@ -384,7 +436,7 @@ void launch_apply(hipStream_t s, int n, int nchunk, int kc, int na, const double
                   double beta, double sgn, double* out, double* edge) {
   const int nt = n / kTileE;
   const int ntiles = nt * nt;
-  const size_t lds = apply_lds_bytes(rs.ncols, kc);
+  const size_t lds = apply_lds_bytes(rs.ncols, kc, rs.maxent);
   dim3 grid(ntiles), block(256);
 #define SG_APPLY_CASE(R)                                                                     \
   case R:                                                                                    \
@@ -707,6 +759,343 @@ __global__ void sub_kernel(const double* __restrict__ a, const double* __restric
 
 void launch_sub(hipStream_t s, const double* a, const double* b, double* out, int64_t N) {
   hipLaunchKernelGGL(sub_kernel, dim3(cdiv(N, 256)), dim3(256), 0, s, a, b, out, N);
+}
+
+
+// ===========================================================================
+// Fused multigrid V-cycle kernels.
+//
+// Fine levels run as two kernels each, on tiles of TC x TC coarse nodes (the
+// fine nodes 2I-1 and 2I of coarse slot I are owned by that slot's tile; slot
+// nc owns the last fine node):
+//   vdown: x1 = w D^-1 b, x2 = x1 + w D^-1 (b - A x1), r = b - A x2, b_c = P^T r
+//          (halo 2 recomputed per tile), writes x2 and b_c;
+//   vup:   x3 = x2 + P x_c, x4, x5 = two more damped Jacobi sweeps, writes x5.
+// Levels with n <= kCoarseN run inside one workgroup per mode (vcoarse), with
+// every vector and stencil of those levels resident in LDS.
+// Each mode may use its own stencil: stencil id smode[t] (0 if smode is null),
+// at S + id * 9 * N on every level.
+// ===========================================================================
+namespace {
+
+constexpr int kTC = 8;                     // coarse nodes per tile side
+constexpr int kDE = 2 * kTC + 5;           // fine extent incl. halo 2 (down)
+constexpr int kUE = 2 * kTC + 4;           // fine extent incl. halo 2 (up)
+constexpr int kCE = kTC + 4;               // coarse extent (up)
+
+__device__ __forceinline__ const double* sel_stencil(const double* S, int64_t N,
+                                                     const int* smode, int t) {
+  return S + (smode ? (int64_t)smode[t] * 9 * N : 0);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void vdown_kernel(const double* __restrict__ Sbase, int nf,
+                                                    int64_t Nf, int64_t Nc, const int* smode,
+                                                    const double* __restrict__ bglob,
+                                                    double* __restrict__ x2out,
+                                                    double* __restrict__ bcout, double omega) {
+  __shared__ double sb[kDE * kDE], sd[kDE * kDE], sx1[kDE * kDE], sx2[kDE * kDE], sr[kDE * kDE];
+  const int mf = nf - 1, nc = nf / 2, mc = nc - 1;
+  const int tpr = (nc + kTC - 1) / kTC;
+  const int tx = blockIdx.x % tpr, ty = blockIdx.x / tpr;
+  const int mode = blockIdx.y;
+  const double* S = sel_stencil(Sbase, Nf, smode, mode);
+  const double* b = bglob + (int64_t)mode * Nf;
+  const int I0 = 1 + tx * kTC, J0 = 1 + ty * kTC;
+  const int ox = 2 * I0 - 3, oy = 2 * J0 - 3;  // fine index of LDS (0,0)
+  const int tid = threadIdx.x;
+  auto inside = [&](int fx, int fy) { return fx >= 1 && fx <= mf && fy >= 1 && fy <= mf; };
+  auto gidx = [&](int fx, int fy) { return (int64_t)(fy - 1) * mf + (fx - 1); };
+  for (int e = tid; e < kDE * kDE; e += 256) {
+    const int lx = e % kDE, ly = e / kDE, fx = ox + lx, fy = oy + ly;
+    double bv = 0.0, dv = 1.0;
+    if (inside(fx, fy)) {
+      const int64_t g = gidx(fx, fy);
+      bv = b[g];
+      dv = S[4 * Nf + g];
+    }
+    sb[e] = bv;
+    sd[e] = dv;
+    sx1[e] = inside(fx, fy) ? omega * bv / dv : 0.0;
+  }
+  __syncthreads();
+  // x2 on [1, kDE-2)^2 local
+  for (int e = tid; e < kDE * kDE; e += 256) {
+    const int lx = e % kDE, ly = e / kDE, fx = ox + lx, fy = oy + ly;
+    double v = 0.0;
+    if (lx >= 1 && lx < kDE - 1 && ly >= 1 && ly < kDE - 1 && inside(fx, fy)) {
+      const int64_t g = gidx(fx, fy);
+      double ax = 0.0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t)
+        ax += S[t * Nf + g] * sx1[(ly + t / 3 - 1) * kDE + (lx + t % 3 - 1)];
+      v = sx1[e] + omega * (sb[e] - ax) / sd[e];
+    }
+    sx2[e] = v;
+  }
+  __syncthreads();
+  // r on [2, kDE-2)^2 local; owned x2 written out
+  for (int e = tid; e < kDE * kDE; e += 256) {
+    const int lx = e % kDE, ly = e / kDE, fx = ox + lx, fy = oy + ly;
+    double v = 0.0;
+    if (lx >= 2 && lx < kDE - 2 && ly >= 2 && ly < kDE - 2 && inside(fx, fy)) {
+      const int64_t g = gidx(fx, fy);
+      double ax = 0.0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t)
+        ax += S[t * Nf + g] * sx2[(ly + t / 3 - 1) * kDE + (lx + t % 3 - 1)];
+      v = sb[e] - ax;
+      if (lx < kDE - 3 && ly < kDE - 3) x2out[(int64_t)mode * Nf + g] = sx2[e];
+    }
+    sr[e] = v;
+  }
+  __syncthreads();
+  // restriction to the tile's coarse nodes
+  if (tid < kTC * kTC) {
+    const int I = I0 + tid % kTC, J = J0 + tid / kTC;
+    if (I <= mc && J <= mc) {
+      double acc = 0.0;
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const double w = (dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0);
+          acc += w * sr[(2 * J + dy - oy) * kDE + (2 * I + dx - ox)];
+        }
+      bcout[(int64_t)mode * Nc + (int64_t)(J - 1) * mc + (I - 1)] = acc;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void vup_kernel(const double* __restrict__ Sbase, int nf,
+                                                  int64_t Nf, int64_t Nc, const int* smode,
+                                                  const double* __restrict__ bglob,
+                                                  const double* __restrict__ x2glob,
+                                                  const double* __restrict__ xcglob,
+                                                  double* __restrict__ xout, double omega) {
+  __shared__ double sb[kUE * kUE], sd[kUE * kUE], sx3[kUE * kUE], sx4[kUE * kUE], sc[kCE * kCE];
+  const int mf = nf - 1, nc = nf / 2, mc = nc - 1;
+  const int tpr = (nc + kTC - 1) / kTC;
+  const int tx = blockIdx.x % tpr, ty = blockIdx.x / tpr;
+  const int mode = blockIdx.y;
+  const double* S = sel_stencil(Sbase, Nf, smode, mode);
+  const double* b = bglob + (int64_t)mode * Nf;
+  const double* x2 = x2glob + (int64_t)mode * Nf;
+  const double* xc = xcglob + (int64_t)mode * Nc;
+  const int I0 = 1 + tx * kTC, J0 = 1 + ty * kTC;
+  const int ox = 2 * I0 - 3, oy = 2 * J0 - 3;  // fine index of LDS (0,0)
+  const int cx0 = I0 - 2, cy0 = J0 - 2;        // coarse index of sc(0,0)
+  const int tid = threadIdx.x;
+  auto inside = [&](int fx, int fy) { return fx >= 1 && fx <= mf && fy >= 1 && fy <= mf; };
+  auto gidx = [&](int fx, int fy) { return (int64_t)(fy - 1) * mf + (fx - 1); };
+  for (int e = tid; e < kCE * kCE; e += 256) {
+    const int cx = cx0 + e % kCE, cy = cy0 + e / kCE;
+    sc[e] = (cx >= 1 && cx <= mc && cy >= 1 && cy <= mc) ? xc[(int64_t)(cy - 1) * mc + (cx - 1)] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < kUE * kUE; e += 256) {
+    const int lx = e % kUE, ly = e / kUE, fx = ox + lx, fy = oy + ly;
+    double bv = 0.0, dv = 1.0, x3 = 0.0;
+    if (inside(fx, fy)) {
+      const int64_t g = gidx(fx, fy);
+      bv = b[g];
+      dv = S[4 * Nf + g];
+      // bilinear interpolation from the coarse neighbours
+      const int Ia = fx >> 1, Ib = (fx + 1) >> 1, Ja = fy >> 1, Jb = (fy + 1) >> 1;
+      auto C = [&](int I, int J) { return sc[(J - cy0) * kCE + (I - cx0)]; };
+      double p;
+      if (fx & 1) {
+        if (fy & 1) p = 0.25 * C(Ia, Ja) + 0.25 * C(Ib, Ja) + 0.25 * C(Ia, Jb) + 0.25 * C(Ib, Jb);
+        else p = 0.5 * C(Ia, Ja) + 0.5 * C(Ib, Ja);
+      } else {
+        if (fy & 1) p = 0.5 * C(Ia, Ja) + 0.5 * C(Ia, Jb);
+        else p = C(Ia, Ja);
+      }
+      x3 = x2[g] + p;
+    }
+    sb[e] = bv;
+    sd[e] = dv;
+    sx3[e] = x3;
+  }
+  __syncthreads();
+  for (int e = tid; e < kUE * kUE; e += 256) {
+    const int lx = e % kUE, ly = e / kUE, fx = ox + lx, fy = oy + ly;
+    double v = 0.0;
+    if (lx >= 1 && lx < kUE - 1 && ly >= 1 && ly < kUE - 1 && inside(fx, fy)) {
+      const int64_t g = gidx(fx, fy);
+      double ax = 0.0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t)
+        ax += S[t * Nf + g] * sx3[(ly + t / 3 - 1) * kUE + (lx + t % 3 - 1)];
+      v = sx3[e] + omega * (sb[e] - ax) / sd[e];
+    }
+    sx4[e] = v;
+  }
+  __syncthreads();
+  for (int e = tid; e < kUE * kUE; e += 256) {
+    const int lx = e % kUE, ly = e / kUE, fx = ox + lx, fy = oy + ly;
+    if (lx >= 2 && lx < kUE - 2 && ly >= 2 && ly < kUE - 2 && inside(fx, fy)) {
+      const int64_t g = gidx(fx, fy);
+      double ax = 0.0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t)
+        ax += S[t * Nf + g] * sx4[(ly + t / 3 - 1) * kUE + (lx + t % 3 - 1)];
+      xout[(int64_t)mode * Nf + g] = sx4[e] + omega * (sb[e] - ax) / sd[e];
+    }
+  }
+}
+
+void launch_vdown(hipStream_t s, const Level& Lf, const Level& Lc, int modes, const int* smode,
+                  const double* b, double* x2, double* bc, double omega) {
+  const int tpr = (Lf.n / 2 + kTC - 1) / kTC;
+  hipLaunchKernelGGL(vdown_kernel, dim3(tpr * tpr, modes), dim3(256), 0, s, Lf.S, Lf.n, Lf.N, Lc.N,
+                     smode, b, x2, bc, omega);
+}
+
+void launch_vup(hipStream_t s, const Level& Lf, const Level& Lc, int modes, const int* smode,
+                const double* b, const double* x2, const double* xc, double* x, double omega) {
+  const int tpr = (Lf.n / 2 + kTC - 1) / kTC;
+  hipLaunchKernelGGL(vup_kernel, dim3(tpr * tpr, modes), dim3(256), 0, s, Lf.S, Lf.n, Lf.N, Lc.N,
+                     smode, b, x2, xc, x, omega);
+}
+
+// ---- coarse levels in LDS, one workgroup per mode --------------------------
+namespace {
+
+__device__ __forceinline__ double lds_stencil(const double* S, int N, int m, int node,
+                                              const double* x) {
+  const int ix = node % m, iy = node / m;
+  double acc = 0.0;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int jx = ix + (t % 3) - 1, jy = iy + (t / 3) - 1;
+    if (jx >= 0 && jx < m && jy >= 0 && jy < m) acc += S[t * N + node] * x[jy * m + jx];
+  }
+  return acc;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void vcoarse_kernel(CoarseLevels cl, const int* smode,
+                                                      const double* __restrict__ bglob,
+                                                      double* __restrict__ xglob, double omega) {
+  extern __shared__ double lds[];
+  const int mode = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int nth = blockDim.x;
+  int off[kMaxCoarseLevels];
+  int tot = 0;
+  for (int l = 0; l < cl.nl; ++l) {
+    off[l] = tot;
+    tot += (int)cl.N[l];
+  }
+  double* S = lds;                 // 9 x tot
+  double* B = S + 9 * tot;
+  double* X = B + tot;
+  double* T = X + tot;
+  double* R = T + tot;
+  for (int l = 0; l < cl.nl; ++l) {
+    const int N = (int)cl.N[l];
+    const double* src = sel_stencil(cl.S[l], N, smode, mode);
+    for (int e = tid; e < 9 * N; e += nth) S[9 * off[l] + e] = src[e];
+  }
+  {
+    const int N = (int)cl.N[0];
+    for (int e = tid; e < N; e += nth) B[e] = bglob[(int64_t)mode * N + e];
+  }
+  __syncthreads();
+  // descend
+  for (int l = 0; l < cl.nl; ++l) {
+    const int N = (int)cl.N[l], m = cl.n[l] - 1;
+    const double* Sl = S + 9 * off[l];
+    double *b = B + off[l], *x = X + off[l], *t = T + off[l], *r = R + off[l];
+    if (l == cl.nl - 1) {
+      for (int e = tid; e < N; e += nth) x[e] = b[e] / Sl[4 * N + e];
+      __syncthreads();
+      break;
+    }
+    for (int e = tid; e < N; e += nth) t[e] = omega * b[e] / Sl[4 * N + e];
+    __syncthreads();
+    for (int e = tid; e < N; e += nth)
+      x[e] = t[e] + omega * (b[e] - lds_stencil(Sl, N, m, e, t)) / Sl[4 * N + e];
+    __syncthreads();
+    for (int e = tid; e < N; e += nth) r[e] = b[e] - lds_stencil(Sl, N, m, e, x);
+    __syncthreads();
+    const int mc = cl.n[l + 1] - 1;
+    double* bc = B + off[l + 1];
+    for (int e = tid; e < mc * mc; e += nth) {
+      const int I = e % mc + 1, J = e / mc + 1;
+      double acc = 0.0;
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx)
+          acc += (dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * r[(2 * J + dy - 1) * m + (2 * I + dx - 1)];
+      bc[e] = acc;
+    }
+    __syncthreads();
+  }
+  // ascend
+  for (int l = cl.nl - 2; l >= 0; --l) {
+    const int N = (int)cl.N[l], m = cl.n[l] - 1, mc = cl.n[l + 1] - 1;
+    const double* Sl = S + 9 * off[l];
+    double *b = B + off[l], *x = X + off[l], *t = T + off[l];
+    const double* xc = X + off[l + 1];
+    for (int e = tid; e < N; e += nth) {
+      const int i = e % m + 1, j = e / m + 1;
+      const int Ia = i >> 1, Ib = (i + 1) >> 1, Ja = j >> 1, Jb = (j + 1) >> 1;
+      auto C = [&](int I, int J) {
+        return (I >= 1 && I <= mc && J >= 1 && J <= mc) ? xc[(J - 1) * mc + (I - 1)] : 0.0;
+      };
+      double p;
+      if (i & 1) {
+        if (j & 1) p = 0.25 * C(Ia, Ja) + 0.25 * C(Ib, Ja) + 0.25 * C(Ia, Jb) + 0.25 * C(Ib, Jb);
+        else p = 0.5 * C(Ia, Ja) + 0.5 * C(Ib, Ja);
+      } else {
+        if (j & 1) p = 0.5 * C(Ia, Ja) + 0.5 * C(Ia, Jb);
+        else p = C(Ia, Ja);
+      }
+      x[e] += p;
+    }
+    __syncthreads();
+    for (int e = tid; e < N; e += nth)
+      t[e] = x[e] + omega * (b[e] - lds_stencil(Sl, N, m, e, x)) / Sl[4 * N + e];
+    __syncthreads();
+    for (int e = tid; e < N; e += nth)
+      x[e] = t[e] + omega * (b[e] - lds_stencil(Sl, N, m, e, t)) / Sl[4 * N + e];
+    __syncthreads();
+  }
+  {
+    const int N = (int)cl.N[0];
+    for (int e = tid; e < N; e += nth) xglob[(int64_t)mode * N + e] = X[e];
+  }
+}
+
+size_t vcoarse_lds_bytes(const CoarseLevels& cl) {
+  size_t tot = 0;
+  for (int l = 0; l < cl.nl; ++l) tot += cl.N[l];
+  return 8 * 13 * tot;
+}
+
+void launch_vcoarse(hipStream_t s, const CoarseLevels& cl, int modes, const int* smode,
+                    const double* b, double* x, double omega) {
+  hipLaunchKernelGGL(vcoarse_kernel, dim3(modes), dim3(256), vcoarse_lds_bytes(cl), s, cl, smode,
+                     b, x, omega);
+}
+
+// c[q] = sum over the (k, v) list of v * a_k(q): the coefficient of a diagonal
+// block K_ii = sum_k [G_k]_{ii} A_k
+__global__ void diag_coeff_kernel(int64_t Nq, int cnt, const int* __restrict__ ks,
+                                  const double* __restrict__ vs, const double* __restrict__ a,
+                                  double* __restrict__ c) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Nq) return;
+  double acc = 0.0;
+  for (int t = 0; t < cnt; ++t) acc += vs[t] * a[(int64_t)ks[t] * Nq + q];
+  c[q] = acc;
+}
+
+void launch_diag_coeff(hipStream_t s, int n, int cnt, const int* ks, const double* vs,
+                       const double* a, double* c) {
+  const int64_t Nq = (int64_t)4 * n * n;
+  hipLaunchKernelGGL(diag_coeff_kernel, dim3(cdiv(Nq, 256)), dim3(256), 0, s, Nq, cnt, ks, vs, a, c);
 }
 
 }  // namespace sg

@@ -24,6 +24,8 @@ CASES = {
     "n4_m3p2q3": Problem(n=4, M=3, p=2, q=3, cov="exp_l1", sigma=0.6, corr_len=0.7),
     # wider grid, nodal-noise forcing
     "n32_m3p2": Problem(n=32, M=3, p=2, q=4, cov="sqexp", sigma=1.2, corr_len=0.4),
+    # three fused fine multigrid levels above the LDS-resident coarse levels
+    "n128_m1p2": Problem(n=128, M=1, p=2, q=4, cov="exp_l1", sigma=0.9, corr_len=0.3),
 }
 
 _cache = {}
@@ -74,16 +76,38 @@ def test_apply_is_deterministic(name):
     assert np.array_equal(W1, W2)
 
 
+_kii_cache = {}
+
+
+def kii_solver(name):
+    """V(2,2) on each mode's own diagonal block K_ii = sum_k [G_k]_ii A_k (oracle)."""
+    if name not in _kii_cache:
+        from oracle import fem
+        from oracle.gmg import GMGHierarchy
+        S, H, G = pair(name)
+        hs = []
+        for i in range(S.P):
+            m = (S.Gi == i) & (S.Gj == i)
+            c = np.zeros(S.a.shape[1])
+            for k, v in zip(S.Gk[m], S.Gv[m]):
+                c += v * S.a[k]
+            hs.append(GMGHierarchy(fem.stiffness(S.n, c), S.n))
+        _kii_cache[name] = lambda t, i: hs[i].vcycle(t)
+    return _kii_cache[name]
+
+
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("pc,grouping", [("mean", "klvar"), ("fs", "klvar"), ("fs", "klvar_meansep"),
-                                         ("fs", "permode"), ("fs", "fg")])
+                                         ("fs", "permode"), ("fs", "fg"), ("mean_kii", "klvar"),
+                                         ("fs_kii", "klvar"), ("fs_kii", "permode")])
 def test_precond(name, pc, grouping):
     from oracle.precond import FieldSplit, make_groups
     S, H, G = pair(name)
     r = random_vector(S.P * S.Nh, 103)
     z = to_host(G.precond(to_dev(r), pc, grouping))
-    groups = make_groups(S.Jp, "mean" if pc == "mean" else grouping)
-    ref = FieldSplit(S, H, groups).apply(r)
+    groups = make_groups(S.Jp, "mean" if pc.startswith("mean") else grouping)
+    bs = kii_solver(name) if pc.endswith("kii") else None
+    ref = FieldSplit(S, H, groups, block_solve=bs).apply(r)
     assert relmax(z, ref) < 1e-12
 
 
