@@ -55,7 +55,7 @@ enum { SG_COV_EXP_L1 = 0, SG_COV_SQEXP = 1 };
  * stiffness A_0 per mode), field split (forward block Gauss-Seidel over
  * ordered splits of the modes, eqs. P_preconditioner / P_group, with the
  * same V-cycle for every diagonal block) */
-enum { SG_PC_NONE = 0, SG_PC_MEAN = 1, SG_PC_FS = 2 };
+enum { SG_PC_NONE = 0, SG_PC_MEAN = 1, SG_PC_FS = 2, SG_PC_LEARNED = 3 };
 /* flag OR-ed into SG_PC_MEAN or SG_PC_FS: the V(2,2) cycle of mode i runs on
  * that mode's own diagonal block K_ii = sum_k [G_k]_{ii} A_k (the paper's
  * diagonal blocks of eq. P_preconditioner) instead of the mean stiffness A_0 */
@@ -84,8 +84,12 @@ typedef struct {
 
 /* GMRES(restart) options (Sec. 3): right preconditioning, CGS2 Arnoldi.
  *  restart 1..200; max_it >= 1 total iterations; pc SG_PC_*; grouping
- *  SG_GROUP_* (used when pc == SG_PC_FS); use_x0 != 0 starts from the
- *  content of u; tol > 0 on the true relative residual ||F-Ku||/||F||.      */
+ *  SG_GROUP_* (used when pc is SG_PC_FS or SG_PC_LEARNED); use_x0 != 0
+ *  starts from the content of u; tol > 0 on the true relative residual
+ *  ||F-Ku||/||F||.  SG_PC_LEARNED runs flexible GMRES whose preconditioner
+ *  stage is z = c + P_FS^{-1}(v - K c) with c the attached network's
+ *  prediction for v, falling back to z = P_FS^{-1} v when c is not finite or
+ *  ||v - K c|| >= ||v|| (the field split is the judge of the prediction).   */
 typedef struct {
   int32_t restart, max_it, pc, grouping, use_x0;
   double tol;
@@ -95,7 +99,7 @@ typedef struct {
   int32_t status;       /* SG_CONVERGED / SG_NOT_CONVERGED / SG_BREAKDOWN   */
   int32_t iterations;   /* Arnoldi steps taken                              */
   int32_t restarts;     /* completed cycles                                 */
-  int32_t reserved;
+  int32_t fallbacks;    /* learned stage: steps that fell back to plain FS  */
   double relres;        /* true ||F - K u|| / ||F|| in FP64 at exit          */
   double relres_est;    /* last rotated residual estimate / ||F||           */
 } sg_solve_info;
@@ -169,6 +173,51 @@ int sg_export(sg_handle* h, int what, int level, double* host_out, size_t count)
 
 void sg_destroy(sg_handle* h);
 const char* sg_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Learned preconditioner stage: a mode-channel CNN (3x3 convolutions over four
+ * grid levels, widths 32 and 64, BF16 weights and activations with FP32
+ * accumulation on the matrix cores, FP32 master weights trained with Adam).
+ * Input: a residual field of P modes on the n x n pixel grid of interior
+ * nodes plus a constant sigma channel, scaled by sqrt(P N_h)/||r||; output:
+ * the error field scaled by sqrt(P N_h)/(||r|| n^2).  Not part of the paper.
+ * Errors are reported through sg_cnn_last_error().
+ * ------------------------------------------------------------------------- */
+typedef struct sg_cnn sg_cnn;
+/* P in [1, 63] modes, n grid (power of two in [16, 1024]), widths c0 = 32,
+ * c1 = 64, max_batch in [1, 256] samples per training step.                */
+int    sg_cnn_create(int32_t P, int32_t n, int32_t c0, int32_t c1, int32_t max_batch, sg_cnn** out);
+/* number of weights (layers concatenated, each (9, c_out, c_in), tap =
+ * 3(dy+1)+(dx+1)) and of biases                                              */
+int    sg_cnn_param_counts(const sg_cnn* c, int64_t* n_weights, int64_t* n_bias);
+size_t sg_cnn_workspace_bytes(const sg_cnn* c);
+/* binds a caller-owned, 256-byte aligned device workspace (zeroed here)      */
+int    sg_cnn_bind(sg_cnn* c, void* dev_workspace, size_t bytes, void* stream);
+/* host FP32 weights/biases in, Adam moments reset (synchronous)               */
+int    sg_cnn_set_params(sg_cnn* c, const float* w_host, const float* b_host, void* stream);
+int    sg_cnn_get_params(sg_cnn* c, float* w_host, float* b_host);
+/* one training pair from device FP64 SG vectors r (residual) and e (error):
+ * R_out = bf16(r s), T_out = bf16(e s / n^2), s = sqrt(P N_h)/||r||, both
+ * P*N_h device arrays                                                        */
+int    sg_cnn_make_pair(sg_cnn* c, const double* r, const double* e, uint16_t* R_out,
+                        uint16_t* T_out, void* stream);
+/* forward (mode 0), + gradients (1), + one Adam step with learning rate lr at
+ * step number `step` >= 1 (2) on the stored pairs idx[0..batch) (host array);
+ * R, T: npairs x P x N_h bf16 device arrays, sigma: npairs device floats;
+ * Y_out (device, nullable): batch x n x n x c_out FP32 outputs; loss (host,
+ * nullable): mean relative squared error.  Synchronous when loss != NULL.  */
+int    sg_cnn_run(sg_cnn* c, const uint16_t* R, const uint16_t* T, const float* sigma,
+                  const int32_t* idx, int32_t batch, int32_t mode, float lr, int32_t step,
+                  float* Y_out, double* loss, void* stream);
+/* weight and bias gradients of the last sg_cnn_run with mode >= 1 (host)    */
+int    sg_cnn_get_grads(sg_cnn* c, float* dw_host, float* db_host);
+/* c = prediction for the FP64 SG vector v (device, P*N_h), SG units          */
+int    sg_cnn_apply(sg_cnn* c, const double* v, double sigma, double* out, void* stream);
+void   sg_cnn_destroy(sg_cnn* c);
+const char* sg_cnn_last_error(void);
+/* attaches a bound network (P and n must match) and the sigma fed to it for
+ * SG_PC_LEARNED solves of this handle; NULL detaches                        */
+int    sg_attach_cnn(sg_handle* h, sg_cnn* c, double sigma);
 
 #ifdef __cplusplus
 }

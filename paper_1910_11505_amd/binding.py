@@ -13,7 +13,8 @@ from dataclasses import dataclass
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 COV = {"exp_l1": 0, "sqexp": 1}
-PC = {"none": 0, "mean": 1, "fs": 2, "mean_kii": 0x101, "fs_kii": 0x102}
+PC = {"none": 0, "mean": 1, "fs": 2, "learned": 3, "mean_kii": 0x101, "fs_kii": 0x102,
+      "learned_kii": 0x103}
 GROUPING = {"klvar": 0, "klvar_meansep": 1, "permode": 2, "fg": 3}
 EXPORT = {"coeff": 0, "kl": 1, "gq": 2, "stencil": 3, "groups": 4}
 STATUS = {0: "converged", 1: "not_converged", 2: "breakdown"}
@@ -39,7 +40,7 @@ class SolveOpts(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
-                ("restarts", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("restarts", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
                 ("relres", ctypes.c_double), ("relres_est", ctypes.c_double)]
 
 
@@ -76,6 +77,21 @@ def load_library():
         "sg_export": (I32, [HP, I32, I32, VP, SZ]),
         "sg_destroy": (None, [HP]),
         "sg_last_error": (ctypes.c_char_p, []),
+        "sg_cnn_create": (I32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.c_int32, P(HP)]),
+        "sg_cnn_param_counts": (I32, [HP, I64P, I64P]),
+        "sg_cnn_workspace_bytes": (SZ, [HP]),
+        "sg_cnn_bind": (I32, [HP, VP, SZ, VP]),
+        "sg_cnn_set_params": (I32, [HP, VP, VP, VP]),
+        "sg_cnn_get_params": (I32, [HP, VP, VP]),
+        "sg_cnn_make_pair": (I32, [HP, VP, VP, VP, VP, VP]),
+        "sg_cnn_run": (I32, [HP, VP, VP, VP, VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                             ctypes.c_int32, VP, ctypes.POINTER(ctypes.c_double), VP]),
+        "sg_cnn_get_grads": (I32, [HP, VP, VP]),
+        "sg_cnn_apply": (I32, [HP, VP, ctypes.c_double, VP, VP]),
+        "sg_cnn_destroy": (None, [HP]),
+        "sg_cnn_last_error": (ctypes.c_char_p, []),
+        "sg_attach_cnn": (I32, [HP, HP, ctypes.c_double]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -180,6 +196,78 @@ def sg_last_error() -> str:
     return load_library().sg_last_error().decode()
 
 
+def _ccheck(rc):
+    if rc != 0:
+        raise SGError(rc, load_library().sg_cnn_last_error().decode())
+
+
+def sg_cnn_create(P, n, c0=32, c1=64, max_batch=16):
+    h = ctypes.c_void_p()
+    _ccheck(load_library().sg_cnn_create(P, n, c0, c1, max_batch, ctypes.byref(h)))
+    return h
+
+
+def sg_cnn_param_counts(c):
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _ccheck(load_library().sg_cnn_param_counts(c, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def sg_cnn_workspace_bytes(c) -> int:
+    return int(load_library().sg_cnn_workspace_bytes(c))
+
+
+def sg_cnn_bind(c, ws, nbytes, stream=None):
+    _ccheck(load_library().sg_cnn_bind(c, _ptr(ws), nbytes, _stream(stream)))
+
+
+def sg_cnn_set_params(c, w, b, stream=None):
+    import numpy as np
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    b = np.ascontiguousarray(b, dtype=np.float32)
+    _ccheck(load_library().sg_cnn_set_params(c, w.ctypes.data, b.ctypes.data, _stream(stream)))
+
+
+def sg_cnn_get_params(c, w, b):
+    _ccheck(load_library().sg_cnn_get_params(c, w.ctypes.data, b.ctypes.data))
+
+
+def sg_cnn_make_pair(c, r, e, R_out, T_out, stream=None):
+    _ccheck(load_library().sg_cnn_make_pair(c, _ptr(r), _ptr(e), _ptr(R_out), _ptr(T_out),
+                                            _stream(stream)))
+
+
+def sg_cnn_run(c, R, T, sigma, idx, mode, lr=0.0, step=1, Y_out=None, want_loss=True, stream=None):
+    import numpy as np
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    loss = ctypes.c_double(0.0)
+    _ccheck(load_library().sg_cnn_run(c, _ptr(R), _ptr(T), _ptr(sigma), idx.ctypes.data, len(idx),
+                                      mode, lr, step, _ptr(Y_out),
+                                      ctypes.byref(loss) if (want_loss and T is not None) else None,
+                                      _stream(stream)))
+    return loss.value
+
+
+def sg_cnn_get_grads(c, dw, db):
+    _ccheck(load_library().sg_cnn_get_grads(c, dw.ctypes.data, db.ctypes.data))
+
+
+def sg_cnn_apply(c, v, sigma, out, stream=None):
+    _ccheck(load_library().sg_cnn_apply(c, _ptr(v), sigma, _ptr(out), _stream(stream)))
+
+
+def sg_cnn_destroy(c):
+    load_library().sg_cnn_destroy(c)
+
+
+def sg_cnn_last_error() -> str:
+    return load_library().sg_cnn_last_error().decode()
+
+
+def sg_attach_cnn(h, c, sigma):
+    _check(load_library().sg_attach_cnn(h, c, sigma))
+
+
 # ---- convenience owner of one bound instance ------------------------------
 class SGInstance:
     """One problem bound to a device workspace owned by a torch uint8 tensor."""
@@ -246,10 +334,60 @@ class SGInstance:
         sg_export(self.h, what, level, out)
         return out
 
+    def attach(self, net, sigma):
+        """Attaches a bound CNN (see CNN) for pc="learned" solves."""
+        sg_attach_cnn(self.h, net.c if net is not None else None, sigma)
+
     def close(self):
         if self.h:
             sg_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class CNN:
+    """Owner of one bound mode-channel network (device workspace in torch)."""
+
+    def __init__(self, P, n, max_batch=16, device="cuda:0", stream=None, c0=32, c1=64):
+        import torch
+        self.P, self.n = P, n
+        self.c = sg_cnn_create(P, n, c0, c1, max_batch)
+        self.nw, self.nb = sg_cnn_param_counts(self.c)
+        self.device = torch.device(device)
+        self.stream = stream
+        nbytes = sg_cnn_workspace_bytes(self.c)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        sg_cnn_bind(self.c, self.ws.data_ptr() + off, nbytes, stream)
+
+    def set_params(self, Ws, bs):
+        import numpy as np
+        sg_cnn_set_params(self.c, np.concatenate([w.reshape(-1) for w in Ws]),
+                          np.concatenate([b.reshape(-1) for b in bs]), self.stream)
+
+    def get_params(self):
+        import numpy as np
+        w = np.zeros(self.nw, dtype=np.float32)
+        b = np.zeros(self.nb, dtype=np.float32)
+        sg_cnn_get_params(self.c, w, b)
+        return w, b
+
+    def get_grads(self):
+        import numpy as np
+        w = np.zeros(self.nw, dtype=np.float32)
+        b = np.zeros(self.nb, dtype=np.float32)
+        sg_cnn_get_grads(self.c, w, b)
+        return w, b
+
+    def close(self):
+        if self.c:
+            sg_cnn_destroy(self.c)
+            self.c = None
 
     def __del__(self):
         try:

@@ -98,6 +98,8 @@ struct sg_handle {
   size_t ws_bytes = 0;
   DevPtrs d;
   double* host_pinned = nullptr;  // small staging for Krylov scalars
+  sg_cnn* cnn = nullptr;          // attached learned stage (not owned)
+  double cnn_sigma = 0.0;
 
   ~sg_handle() {
     if (host_pinned) (void)hipHostFree(host_pinned);
@@ -356,9 +358,9 @@ void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double*
   }
 }
 
-bool valid_pc(int pc) {
+bool valid_pc(int pc, bool allow_learned = false) {
   const int kind = pc & 0xff, flags = pc & ~0xff;
-  if (kind < SG_PC_NONE || kind > SG_PC_FS) return false;
+  if (kind < SG_PC_NONE || kind > (allow_learned ? SG_PC_LEARNED : SG_PC_FS)) return false;
   if (flags & ~SG_PC_DIAG_KII) return false;
   return true;
 }
@@ -578,30 +580,47 @@ int sg_precond_apply(sg_handle* h, int pc, int grouping, const double* r, double
 
 namespace {
 struct KrylovWS {
-  double *V, *w, *z, *t, *partial, *hdev, *ydev;
+  double *V, *Z, *w, *z, *t, *x2, *partial, *hdev, *ydev;
   int nblk;
 };
 
-size_t krylov_layout(const sg_handle* h, int restart, KrylovWS* k, char* base) {
+size_t krylov_layout(const sg_handle* h, int restart, bool flexible, KrylovWS* k, char* base) {
   const int64_t Nv = (int64_t)h->P * h->Nh;
   Carver c{base};
   KrylovWS tmp;
   KrylovWS& K = k ? *k : tmp;
   K.nblk = dot_blocks(Nv);
   K.V = c.take<double>((size_t)(restart + 1) * Nv);
+  K.Z = flexible ? c.take<double>((size_t)restart * Nv) : nullptr;
   K.w = c.take<double>(Nv);
   K.z = c.take<double>(Nv);
   K.t = c.take<double>(Nv);
+  K.x2 = c.take<double>(Nv);
   K.partial = c.take<double>((size_t)K.nblk * (restart + 1));
-  K.hdev = c.take<double>(2 * (size_t)(restart + 1) + 2);
+  K.hdev = c.take<double>(2 * (size_t)(restart + 1) + 4);
   K.ydev = c.take<double>(restart + 1);
   return c.off;
 }
+
+bool is_learned(const sg_solve_opts* o) { return (o->pc & 0xff) == SG_PC_LEARNED; }
 }  // namespace
 
 size_t sg_gmres_workspace_bytes(const sg_handle* h, const sg_solve_opts* o) {
   if (!h || !o || o->restart < 1 || o->restart > kMaxRestart) return 0;
-  return krylov_layout(h, o->restart, nullptr, nullptr);
+  return krylov_layout(h, o->restart, is_learned(o), nullptr, nullptr);
+}
+
+int sg_attach_cnn(sg_handle* h, sg_cnn* c, double sigma) {
+  if (!h) return fail(SG_ERR_INVALID_ARG, "null handle");
+  if (c) {
+    if (!cnn_bound(c)) return fail(SG_ERR_NOT_BOUND, "network not bound");
+    if (cnn_modes(c) != h->P || cnn_grid(c) != h->n)
+      return fail(SG_ERR_INVALID_ARG, "network P / n do not match the problem");
+    if (!std::isfinite(sigma)) return fail(SG_ERR_INVALID_ARG, "sigma must be finite");
+  }
+  h->cnn = c;
+  h->cnn_sigma = sigma;
+  return SG_OK;
 }
 
 int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double* u,
@@ -612,7 +631,8 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
   if (o->restart < 1 || o->restart > kMaxRestart) return fail(SG_ERR_INVALID_ARG, "restart out of range");
   if (o->max_it < 1) return fail(SG_ERR_INVALID_ARG, "max_it must be positive");
   if (!(o->tol > 0.0)) return fail(SG_ERR_INVALID_ARG, "tol must be positive");
-  if (!valid_pc(o->pc)) return fail(SG_ERR_INVALID_ARG, "unknown preconditioner");
+  if (!valid_pc(o->pc, true)) return fail(SG_ERR_INVALID_ARG, "unknown preconditioner");
+  if (is_learned(o) && !h->cnn) return fail(SG_ERR_INVALID_ARG, "learned stage needs an attached network");
   if (o->grouping < 0 || o->grouping > 3) return fail(SG_ERR_INVALID_ARG, "unknown grouping");
   if (ws_bytes < sg_gmres_workspace_bytes(h, o)) return fail(SG_ERR_WORKSPACE, "Krylov workspace too small");
   if (reinterpret_cast<uintptr_t>(krylov_ws) % 256) return fail(SG_ERR_WORKSPACE, "Krylov workspace must be 256-byte aligned");
@@ -622,7 +642,10 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
     const int m = o->restart;
     const int64_t Nv = (int64_t)H.P * H.Nh;
     KrylovWS K;
-    krylov_layout(h, m, &K, static_cast<char*>(krylov_ws));
+    const bool learned = is_learned(o);
+    krylov_layout(h, m, learned, &K, static_cast<char*>(krylov_ws));
+    const int fs_pc = (o->pc & ~0xff) | SG_PC_FS;
+    int fallbacks = 0;
     double* hp = H.host_pinned;
     auto norm2 = [&](const double* x, double* dst) {
       launch_multidot(s, x, Nv, 1, x, Nv, K.partial, K.nblk);
@@ -675,8 +698,31 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
       int kdone = 0;
       for (int j = 0; j < m; ++j) {
         double* vj = K.V + (int64_t)j * Nv;
-        do_precond(H, s, o->pc, o->grouping, vj, K.z);
-        do_apply(H, s, K.z, K.w);
+        double* zj = K.z;
+        if (learned) {
+          // z = c + P_FS^{-1}(v - K c), c the network's prediction; the field
+          // split judges it and is the fallback
+          zj = K.Z + (int64_t)j * Nv;
+          double* c = K.z;
+          cnn_apply_sg(H.cnn, s, vj, H.cnn_sigma, c, K.partial, K.nblk);
+          do_apply(H, s, c, K.t);
+          launch_sub(s, vj, K.t, K.x2, Nv);
+          double* nn = K.hdev + 2 * (m + 1) + 1;
+          norm2(K.x2, nn);
+          norm2(vj, nn + 1);
+          fetch(nn, 2);
+          const double rn = std::sqrt(hp[0]), vn = std::sqrt(hp[1]);
+          if (std::isfinite(rn) && rn < vn) {
+            do_precond(H, s, fs_pc, o->grouping, K.x2, zj);
+            launch_axpby(s, 1.0, c, 1.0, zj, Nv);
+          } else {
+            do_precond(H, s, fs_pc, o->grouping, vj, zj);
+            ++fallbacks;
+          }
+        } else {
+          do_precond(H, s, o->pc, o->grouping, vj, K.z);
+        }
+        do_apply(H, s, zj, K.w);
         double* h1 = K.hdev;
         double* h2 = K.hdev + (m + 1);
         double* nrm = K.hdev + 2 * (m + 1);
@@ -732,9 +778,14 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
       }
       for (int i = 0; i < kdone; ++i) hp[i] = y[i];
       SG_HIP(hipMemcpyAsync(K.ydev, hp, kdone * sizeof(double), hipMemcpyHostToDevice, s));
-      launch_combine(s, K.V, Nv, kdone, K.ydev, K.t, Nv);
-      do_precond(H, s, o->pc, o->grouping, K.t, K.z);
-      launch_axpby(s, 1.0, K.z, 1.0, u, Nv);
+      if (learned) {
+        launch_combine(s, K.Z, Nv, kdone, K.ydev, K.t, Nv);
+        launch_axpby(s, 1.0, K.t, 1.0, u, Nv);
+      } else {
+        launch_combine(s, K.V, Nv, kdone, K.ydev, K.t, Nv);
+        do_precond(H, s, o->pc, o->grouping, K.t, K.z);
+        launch_axpby(s, 1.0, K.z, 1.0, u, Nv);
+      }
       do_apply(H, s, u, K.w);
       launch_sub(s, F, K.w, K.t, Nv);
       norm2(K.t, K.hdev);
@@ -745,6 +796,7 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
     }
     info->iterations = it;
     info->restarts = restarts;
+    info->fallbacks = fallbacks;
     info->relres = beta / nF;
     info->relres_est = est / nF;
     info->status = (beta <= target) ? SG_CONVERGED : (broke ? SG_BREAKDOWN : SG_NOT_CONVERGED);

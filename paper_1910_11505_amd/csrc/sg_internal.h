@@ -147,4 +147,11 @@ void launch_scale_by_inv_norm(hipStream_t s, const double* w, const double* nrm2
 void launch_axpby(hipStream_t s, double a, const double* x, double b, double* y, int64_t N);
 void launch_sub(hipStream_t s, const double* a, const double* b, double* out, int64_t N);
 
+// learned stage (sg_cnn.hip)
+void cnn_apply_sg(sg_cnn* C, hipStream_t s, const double* v, double sigma, double* c,
+                  double* scratch_partial, int nblk);
+int cnn_modes(const sg_cnn* C);
+int cnn_grid(const sg_cnn* C);
+bool cnn_bound(const sg_cnn* C);
+
 }  // namespace sg

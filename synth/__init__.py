@@ -90,3 +90,41 @@ def batched_instances(count: int = 64, seed: int = BASE_SEED + 3000,
         prob = Problem(n=n, M=M, p=p, q=2 * p, cov=COV_EXP_L1, sigma=sigma, corr_len=lc)
         out.append((prob, seed + 1 + b))
     return out
+
+
+# ---- learned-preconditioner network: architecture table and initial weights --
+# Mode-channel CNN on the (n x n) pixel grid of interior nodes (the last row and
+# column are zero padding): 4 resolution levels, 3x3 convolutions, channel
+# counts padded to MFMA-friendly multiples (padding channels carry zero weights).
+def cnn_layers(P: int, c0: int = 32, c1: int = 64):
+    """List of (c_in, c_out, relu, level) per 3x3 convolution; the input (P modes
+    + sigma) and the output (P modes) are padded to multiples of 32 channels."""
+    cin0 = ((P + 1 + 31) // 32) * 32
+    cout_last = ((P + 31) // 32) * 32
+    return [
+        (cin0, c0, True, 0), (c0, c0, True, 0),        # level 0 -> skip 0
+        (c0, c1, True, 1),                             # level 1 -> skip 1
+        (c1, c1, True, 2),                             # level 2 -> skip 2
+        (c1, c1, True, 3),                             # level 3 (coarsest)
+        (c1, c1, True, 2),                             # up + skip 2
+        (c1, c0, True, 1),                             # up + skip 1
+        (c0, c0, True, 0),                             # up + skip 0
+        (c0, cout_last, False, 0),                     # linear output
+    ]
+
+
+def cnn_init(P: int, seed: int, c0: int = 32, c1: int = 64):
+    """He-normal FP32 weights W[l] of shape (9, c_out, c_in) (tap = 3*(dy+1) + (dx+1))
+    and zero biases; weights touching padding channels are zero."""
+    rng = np.random.default_rng(seed)
+    layers = cnn_layers(P, c0, c1)
+    Ws, bs = [], []
+    for li, (ci, co, relu, lvl) in enumerate(layers):
+        real_ci = P + 1 if li == 0 else ci
+        real_co = P if li == len(layers) - 1 else co
+        std = np.sqrt(2.0 / (9 * real_ci)) if relu else np.sqrt(1.0 / (9 * real_ci))
+        W = np.zeros((9, co, ci), dtype=np.float32)
+        W[:, :real_co, :real_ci] = (std * rng.standard_normal((9, real_co, real_ci))).astype(np.float32)
+        Ws.append(W)
+        bs.append(np.zeros(co, dtype=np.float32))
+    return Ws, bs

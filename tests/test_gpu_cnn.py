@@ -1,0 +1,134 @@
+"""GPU parity of the learned stage's network: forward, loss, gradients and the
+Adam step of the HIP kernels (through the C ABI) against the CNN oracle in
+device numerics (bf16 weights/activations, FP32 accumulation).  Bars: outputs
+and loss 1e-2 relative (norm), gradients 3e-2 relative per layer (norm)."""
+import numpy as np
+import pytest
+
+import paper_1910_11505_amd as sg
+from oracle import cnn as ocnn
+from synth import cnn_init, cnn_layers
+
+from gpu_common import need_gpu, torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16_bits(x):
+    return (ocnn.bf16(x).view(np.uint32) >> 16).astype(np.uint16)
+
+
+def _case(P, n, B, seed):
+    rng = np.random.default_rng(seed)
+    Nh = (n - 1) ** 2
+    R = ocnn.bf16(rng.standard_normal((B, P, Nh)))
+    T = ocnn.bf16(0.1 * rng.standard_normal((B, P, Nh)))
+    sig = rng.uniform(0.3, 1.5, B).astype(np.float32)
+    Ws, bs = cnn_init(P, seed + 1)
+    bs = [(0.05 * rng.standard_normal(b.shape)).astype(np.float32) for b in bs]
+    layers = cnn_layers(P)
+    CI0, CO = layers[0][0], layers[-1][1]
+    X0 = np.zeros((B, n, n, CI0))
+    Tt = np.zeros((B, n, n, CO))
+    for b in range(B):
+        X0[b, : n - 1, : n - 1, :P] = R[b].reshape(P, n - 1, n - 1).transpose(1, 2, 0)
+        X0[b, :, :, P] = ocnn.bf16(np.float32(sig[b]))
+        Tt[b, : n - 1, : n - 1, :P] = T[b].reshape(P, n - 1, n - 1).transpose(1, 2, 0)
+    return R, T, sig, Ws, bs, X0, Tt
+
+
+def _net(P, n, B, Ws, bs):
+    net = sg.CNN(P, n, max_batch=B)
+    net.set_params(Ws, bs)
+    return net
+
+
+def _dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dtype).cuda()
+
+
+@pytest.mark.parametrize("P,n,B", [(3, 16, 2), (35, 32, 2)])
+def test_forward_loss_and_gradients(P, n, B):
+    need_gpu()
+    R, T, sig, Ws, bs, X0, Tt = _case(P, n, B, 7)
+    net = _net(P, n, B, Ws, bs)
+    Rd = torch.from_numpy(_bf16_bits(R).view(np.int16)).cuda()
+    Td = torch.from_numpy(_bf16_bits(T).view(np.int16)).cuda()
+    sd = _dev(sig, torch.float32)
+    CO = cnn_layers(P)[-1][1]
+    Y = torch.zeros(B * n * n * CO, dtype=torch.float32, device="cuda")
+    loss = sg.sg_cnn_run(net.c, Rd, Td, sd, np.arange(B), 1, Y_out=Y)
+    Yg = Y.cpu().numpy().reshape(B, n, n, CO)
+    Yo, cache = ocnn.forward(Ws, bs, X0, exact=False)
+    Lo, dY = ocnn.loss_and_grad(Yo, Tt, P, n)
+    assert np.linalg.norm(Yg - Yo) <= 1e-2 * np.linalg.norm(Yo)
+    assert abs(loss - Lo) <= 1e-2 * abs(Lo)
+    dWo, dbo = ocnn.backward(Ws, cache, dY, exact=False)
+    dw, db = net.get_grads()
+    ow = ob = 0
+    for l, (W, b) in enumerate(zip(dWo, dbo)):
+        gw = dw[ow: ow + W.size].reshape(W.shape)
+        gb = db[ob: ob + b.size]
+        ow += W.size
+        ob += b.size
+        assert np.linalg.norm(gw - W) <= 3e-2 * np.linalg.norm(W), l
+        assert np.linalg.norm(gb - b) <= 3e-2 * np.linalg.norm(b) + 1e-12, l
+    net.close()
+
+
+def test_adam_step_matches_oracle():
+    need_gpu()
+    P, n, B = 3, 16, 2
+    R, T, sig, Ws, bs, X0, Tt = _case(P, n, B, 11)
+    net = _net(P, n, B, Ws, bs)
+    Rd = torch.from_numpy(_bf16_bits(R).view(np.int16)).cuda()
+    Td = torch.from_numpy(_bf16_bits(T).view(np.int16)).cuda()
+    sd = _dev(sig, torch.float32)
+    sg.sg_cnn_run(net.c, Rd, Td, sd, np.arange(B), 1)
+    gw, gb = net.get_grads()
+    lr = 1e-3
+    sg.sg_cnn_run(net.c, Rd, Td, sd, np.arange(B), 2, lr=lr, step=1)
+    w1, b1 = net.get_params()
+    w0 = np.concatenate([w.reshape(-1) for w in Ws])
+    b0 = np.concatenate([b.reshape(-1) for b in bs])
+    ew, _, _ = ocnn.adam_step(w0.astype(np.float64), 0.0, 0.0, gw.astype(np.float64), 1, lr)
+    eb, _, _ = ocnn.adam_step(b0.astype(np.float64), 0.0, 0.0, gb.astype(np.float64), 1, lr)
+    assert np.abs(w1 - ew).max() <= 1e-6 and np.abs(b1 - eb).max() <= 1e-6
+    net.close()
+
+
+def test_training_lowers_the_loss():
+    need_gpu()
+    P, n, B = 3, 16, 4
+    R, T, sig, Ws, bs, X0, Tt = _case(P, n, B, 13)
+    net = _net(P, n, B, Ws, bs)
+    Rd = torch.from_numpy(_bf16_bits(R).view(np.int16)).cuda()
+    Td = torch.from_numpy(_bf16_bits(T).view(np.int16)).cuda()
+    sd = _dev(sig, torch.float32)
+    l0 = sg.sg_cnn_run(net.c, Rd, Td, sd, np.arange(B), 0)
+    for step in range(1, 61):
+        sg.sg_cnn_run(net.c, Rd, Td, sd, np.arange(B), 2, lr=3e-3, step=step, want_loss=False)
+    l1 = sg.sg_cnn_run(net.c, Rd, Td, sd, np.arange(B), 0)
+    assert l1 < 0.5 * l0, (l0, l1)
+    net.close()
+
+
+def test_apply_in_sg_units_matches_oracle():
+    need_gpu()
+    P, n = 35, 32
+    rng = np.random.default_rng(17)
+    Ws, bs = cnn_init(P, 19)
+    net = _net(P, n, 1, Ws, bs)
+    Nh = (n - 1) ** 2
+    v = rng.standard_normal(P * Nh)
+    c = torch.zeros(P * Nh, dtype=torch.float64, device="cuda")
+    sg.sg_cnn_apply(net.c, torch.from_numpy(v).cuda(), 0.8, c)
+    s = np.sqrt(P * Nh) / np.linalg.norm(v)
+    X0 = np.zeros((1, n, n, cnn_layers(P)[0][0]))
+    X0[0, : n - 1, : n - 1, :P] = (v * s).reshape(P, n - 1, n - 1).transpose(1, 2, 0)
+    X0[0, :, :, P] = 0.8
+    Yo, _ = ocnn.forward(Ws, bs, X0, exact=False)
+    ref = (Yo[0, : n - 1, : n - 1, :P].transpose(2, 0, 1).reshape(-1) / s * n * n)
+    cg = c.cpu().numpy()
+    assert np.linalg.norm(cg - ref) <= 1e-2 * np.linalg.norm(ref)
+    net.close()
