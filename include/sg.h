@@ -87,9 +87,11 @@ typedef struct {
  *  SG_GROUP_* (used when pc is SG_PC_FS or SG_PC_LEARNED); use_x0 != 0
  *  starts from the content of u; tol > 0 on the true relative residual
  *  ||F-Ku||/||F||.  SG_PC_LEARNED runs flexible GMRES whose preconditioner
- *  stage is z = c + P_FS^{-1}(v - K c) with c the attached network's
- *  prediction for v, falling back to z = P_FS^{-1} v when c is not finite or
- *  ||v - K c|| >= ||v|| (the field split is the judge of the prediction).   */
+ *  stage is z = P_FS^{-1} v + alpha c: c is the attached network's prediction
+ *  of the error left in the field-split residual r = v - K P_FS^{-1} v, and
+ *  alpha = <r, K c>/||K c||^2 minimises ||v - K z||, so the field split is
+ *  both the judge (the stage never has a larger residual) and the fallback
+ *  (alpha = 0 when the prediction is not finite; counted in fallbacks).     */
 typedef struct {
   int32_t restart, max_it, pc, grouping, use_x0;
   double tol;
@@ -143,6 +145,9 @@ int sg_apply(sg_handle* h, const double* U, double* W, void* stream);
 int sg_precond_apply(sg_handle* h, int pc, int grouping, const double* r, double* z,
                      void* stream);
 
+/* r = F - K u (device, P*N_h each; r must not alias F or u)                */
+int sg_residual(sg_handle* h, const double* F, const double* u, double* r, void* stream);
+
 /* Device bytes of the Krylov workspace sg_gmres_solve needs for `opts`.    */
 size_t sg_gmres_workspace_bytes(const sg_handle* h, const sg_solve_opts* opts);
 
@@ -180,7 +185,8 @@ const char* sg_last_error(void);
  * accumulation on the matrix cores, FP32 master weights trained with Adam).
  * Input: a residual field of P modes on the n x n pixel grid of interior
  * nodes plus a constant sigma channel, scaled by sqrt(P N_h)/||r||; output:
- * the error field scaled by sqrt(P N_h)/(||r|| n^2).  Not part of the paper.
+ * the error field scaled by kappa sqrt(P N_h)/(||r|| n^2), kappa = 2 pi^2.
+ * Not part of the paper.
  * Errors are reported through sg_cnn_last_error().
  * ------------------------------------------------------------------------- */
 typedef struct sg_cnn sg_cnn;
@@ -196,11 +202,12 @@ int    sg_cnn_bind(sg_cnn* c, void* dev_workspace, size_t bytes, void* stream);
 /* host FP32 weights/biases in, Adam moments reset (synchronous)               */
 int    sg_cnn_set_params(sg_cnn* c, const float* w_host, const float* b_host, void* stream);
 int    sg_cnn_get_params(sg_cnn* c, float* w_host, float* b_host);
-/* one training pair from device FP64 SG vectors r (residual) and e (error):
- * R_out = bf16(r s), T_out = bf16(e s / n^2), s = sqrt(P N_h)/||r||, both
+/* one training pair from device FP64 SG vectors: residual r = F - K u of an
+ * iterate u and the reference solution ustar (error e = ustar - u):
+ * R_out = bf16(r s), T_out = bf16(e s kappa / n^2), s = sqrt(P N_h)/||r||, both
  * P*N_h device arrays                                                        */
-int    sg_cnn_make_pair(sg_cnn* c, const double* r, const double* e, uint16_t* R_out,
-                        uint16_t* T_out, void* stream);
+int    sg_cnn_make_pair(sg_cnn* c, const double* r, const double* ustar, const double* u,
+                        uint16_t* R_out, uint16_t* T_out, void* stream);
 /* forward (mode 0), + gradients (1), + one Adam step with learning rate lr at
  * step number `step` >= 1 (2) on the stored pairs idx[0..batch) (host array);
  * R, T: npairs x P x N_h bf16 device arrays, sigma: npairs device floats;

@@ -84,7 +84,8 @@ def load_library():
         "sg_cnn_bind": (I32, [HP, VP, SZ, VP]),
         "sg_cnn_set_params": (I32, [HP, VP, VP, VP]),
         "sg_cnn_get_params": (I32, [HP, VP, VP]),
-        "sg_cnn_make_pair": (I32, [HP, VP, VP, VP, VP, VP]),
+        "sg_cnn_make_pair": (I32, [HP, VP, VP, VP, VP, VP, VP]),
+        "sg_residual": (I32, [HP, VP, VP, VP, VP]),
         "sg_cnn_run": (I32, [HP, VP, VP, VP, VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
                              ctypes.c_int32, VP, ctypes.POINTER(ctypes.c_double), VP]),
         "sg_cnn_get_grads": (I32, [HP, VP, VP]),
@@ -232,9 +233,13 @@ def sg_cnn_get_params(c, w, b):
     _ccheck(load_library().sg_cnn_get_params(c, w.ctypes.data, b.ctypes.data))
 
 
-def sg_cnn_make_pair(c, r, e, R_out, T_out, stream=None):
-    _ccheck(load_library().sg_cnn_make_pair(c, _ptr(r), _ptr(e), _ptr(R_out), _ptr(T_out),
-                                            _stream(stream)))
+def sg_cnn_make_pair(c, r, ustar, u, R_out, T_out, stream=None):
+    _ccheck(load_library().sg_cnn_make_pair(c, _ptr(r), _ptr(ustar), _ptr(u), _ptr(R_out),
+                                            _ptr(T_out), _stream(stream)))
+
+
+def sg_residual(h, F, u, r, stream=None):
+    _check(load_library().sg_residual(h, _ptr(F), _ptr(u), _ptr(r), _stream(stream)))
 
 
 def sg_cnn_run(c, R, T, sigma, idx, mode, lr=0.0, step=1, Y_out=None, want_loss=True, stream=None):
@@ -333,6 +338,11 @@ class SGInstance:
         out = np.zeros(count)
         sg_export(self.h, what, level, out)
         return out
+
+    def residual(self, F, u, r=None):
+        r = self.vec() if r is None else r
+        sg_residual(self.h, F, u, r, self.stream)
+        return r
 
     def attach(self, net, sigma):
         """Attaches a bound CNN (see CNN) for pc="learned" solves."""

@@ -562,6 +562,21 @@ int sg_apply(sg_handle* h, const double* U, double* W, void* stream) {
   }
 }
 
+int sg_residual(sg_handle* h, const double* F, const double* u, double* r, void* stream) {
+  if (!h || !F || !u || !r) return fail(SG_ERR_INVALID_ARG, "null argument");
+  if (r == F || r == u) return fail(SG_ERR_INVALID_ARG, "r must not alias F or u");
+  if (!h->bound) return fail(SG_ERR_NOT_BOUND, "handle not bound");
+  try {
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    do_apply(*h, s, u, r);
+    launch_axpby(s, 1.0, F, -1.0, r, (int64_t)h->P * h->Nh);
+    check_launch();
+    return SG_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  }
+}
+
 int sg_precond_apply(sg_handle* h, int pc, int grouping, const double* r, double* z,
                      void* stream) {
   if (!h || !r || !z) return fail(SG_ERR_INVALID_ARG, "null argument");
@@ -700,29 +715,35 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
         double* vj = K.V + (int64_t)j * Nv;
         double* zj = K.z;
         if (learned) {
-          // z = c + P_FS^{-1}(v - K c), c the network's prediction; the field
-          // split judges it and is the fallback
+          // field split first, then the network's prediction c of the error
+          // left in the field-split residual r = v - K P_FS^{-1} v, weighted by
+          // alpha = <r, K c> / ||K c||^2 (the residual-minimising step), so the
+          // stage's residual never exceeds the field split's; alpha = 0 (plain
+          // field split) when the prediction is not finite
           zj = K.Z + (int64_t)j * Nv;
           double* c = K.z;
-          cnn_apply_sg(H.cnn, s, vj, H.cnn_sigma, c, K.partial, K.nblk);
+          do_precond(H, s, fs_pc, o->grouping, vj, zj);
+          do_apply(H, s, zj, K.w);
+          launch_sub(s, vj, K.w, K.x2, Nv);
+          cnn_apply_sg(H.cnn, s, K.x2, H.cnn_sigma, c, K.partial, K.nblk);
           do_apply(H, s, c, K.t);
-          launch_sub(s, vj, K.t, K.x2, Nv);
           double* nn = K.hdev + 2 * (m + 1) + 1;
-          norm2(K.x2, nn);
-          norm2(vj, nn + 1);
+          launch_multidot(s, K.x2, Nv, 1, K.t, Nv, K.partial, K.nblk);
+          launch_reduce(s, K.partial, K.nblk, 1, nn);
+          norm2(K.t, nn + 1);
           fetch(nn, 2);
-          const double rn = std::sqrt(hp[0]), vn = std::sqrt(hp[1]);
-          if (std::isfinite(rn) && rn < vn) {
-            do_precond(H, s, fs_pc, o->grouping, K.x2, zj);
-            launch_axpby(s, 1.0, c, 1.0, zj, Nv);
+          const double rkc = hp[0], kc2 = hp[1];
+          const double alpha = (std::isfinite(rkc) && std::isfinite(kc2) && kc2 > 0.0) ? rkc / kc2 : 0.0;
+          if (alpha != 0.0) {
+            launch_axpby(s, alpha, c, 1.0, zj, Nv);
+            launch_axpby(s, alpha, K.t, 1.0, K.w, Nv);
           } else {
-            do_precond(H, s, fs_pc, o->grouping, vj, zj);
             ++fallbacks;
           }
         } else {
           do_precond(H, s, o->pc, o->grouping, vj, K.z);
+          do_apply(H, s, zj, K.w);
         }
-        do_apply(H, s, zj, K.w);
         double* h1 = K.hdev;
         double* h2 = K.hdev + (m + 1);
         double* nrm = K.hdev + 2 * (m + 1);

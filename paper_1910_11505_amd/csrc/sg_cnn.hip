@@ -40,6 +40,10 @@ __host__ __device__ inline float bf2f(bf16_t b) {
 
 inline int cdivl(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// Target scale kappa = 2 pi^2: the smallest eigenvalue of the unit-square
+// Laplacian, so that the smoothest error of a unit residual maps to O(1).
+constexpr double kTargetScale = 19.739208802178716;
+
 __device__ __forceinline__ f32x4 mfma32(short8 a, short8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
@@ -418,7 +422,7 @@ __global__ void sg_to_image_kernel(const double* __restrict__ v, const double* _
   }
 }
 
-// network output image -> SG vector c = Y * ||v|| n^2 / sqrt(P N_h)
+// network output image -> SG vector c = Y ||v|| n^2 / (sqrt(P N_h) kappa)
 __global__ void image_to_sg_kernel(const float* __restrict__ Y, const double* __restrict__ nrm2,
                                    int P, int n, int CO, double* __restrict__ c) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -428,20 +432,21 @@ __global__ void image_to_sg_kernel(const float* __restrict__ Y, const double* __
   const int mode = (int)(i / Nh);
   const int64_t node = i - (int64_t)mode * Nh;
   const int x = (int)(node % m), y = (int)(node / m);
-  const double s = sqrt(nrm2[0]) * (double)n * n / sqrt((double)P * Nh);
+  const double s = sqrt(nrm2[0]) * (double)n * n / (sqrt((double)P * Nh) * kTargetScale);
   c[i] = (double)Y[((int64_t)y * n + x) * CO + mode] * s;
 }
 
-// one training pair from FP64 SG vectors r, e: R = bf16(r s), T = bf16(e s / n^2),
-// s = sqrt(P N_h) / ||r||
-__global__ void make_pair_kernel(const double* __restrict__ r, const double* __restrict__ e,
-                                 const double* __restrict__ nrm2, int n, int64_t len,
-                                 bf16_t* __restrict__ R, bf16_t* __restrict__ T) {
+// one training pair from FP64 SG vectors: residual r and error e = ustar - u;
+// R = bf16(r s), T = bf16(e s kappa / n^2), s = sqrt(P N_h) / ||r||
+__global__ void make_pair_kernel(const double* __restrict__ r, const double* __restrict__ ustar,
+                                 const double* __restrict__ u, const double* __restrict__ nrm2,
+                                 int n, int64_t len, bf16_t* __restrict__ R,
+                                 bf16_t* __restrict__ T) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= len) return;
   const double s = sqrt((double)len) / sqrt(nrm2[0]);
   R[i] = f2bf((float)(r[i] * s));
-  T[i] = f2bf((float)(e[i] * s / ((double)n * n)));
+  T[i] = f2bf((float)((ustar[i] - u[i]) * s * kTargetScale / ((double)n * n)));
 }
 
 // ===========================================================================
@@ -808,18 +813,19 @@ int sg_cnn_get_params(sg_cnn* C, float* W, float* b) {
   return SG_OK;
 }
 
-// One training pair from FP64 SG vectors (device): R_out, T_out are P*N_h bf16
-int sg_cnn_make_pair(sg_cnn* C, const double* r, const double* e, uint16_t* R_out, uint16_t* T_out,
-                     void* stream) {
-  if (!C || !r || !e || !R_out || !T_out) return cfail(SG_ERR_INVALID_ARG, "null argument");
+// One training pair from device FP64 SG vectors: residual r, reference solution
+// ustar and iterate u (error ustar - u); R_out, T_out are P*N_h bf16
+int sg_cnn_make_pair(sg_cnn* C, const double* r, const double* ustar, const double* u,
+                     uint16_t* R_out, uint16_t* T_out, void* stream) {
+  if (!C || !r || !ustar || !u || !R_out || !T_out) return cfail(SG_ERR_INVALID_ARG, "null argument");
   if (!C->bound) return cfail(SG_ERR_NOT_BOUND, "CNN not bound");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int64_t len = (int64_t)C->P * (C->n - 1) * (C->n - 1);
   const int nblk = dot_blocks(len);
   launch_multidot(s, r, len, 1, r, len, C->dscr, nblk);
   launch_reduce(s, C->dscr, nblk, 1, C->nrm);
-  hipLaunchKernelGGL(make_pair_kernel, dim3(cdivl(len, 256)), dim3(256), 0, s, r, e, C->nrm, C->n,
-                     len, R_out, T_out);
+  hipLaunchKernelGGL(make_pair_kernel, dim3(cdivl(len, 256)), dim3(256), 0, s, r, ustar, u, C->nrm,
+                     C->n, len, reinterpret_cast<bf16_t*>(R_out), reinterpret_cast<bf16_t*>(T_out));
   return hipGetLastError() == hipSuccess ? SG_OK : cfail(SG_ERR_HIP, "launch failed");
 }
 

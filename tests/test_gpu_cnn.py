@@ -128,7 +128,8 @@ def test_apply_in_sg_units_matches_oracle():
     X0[0, : n - 1, : n - 1, :P] = (v * s).reshape(P, n - 1, n - 1).transpose(1, 2, 0)
     X0[0, :, :, P] = 0.8
     Yo, _ = ocnn.forward(Ws, bs, X0, exact=False)
-    ref = (Yo[0, : n - 1, : n - 1, :P].transpose(2, 0, 1).reshape(-1) / s * n * n)
+    kappa = 2 * np.pi ** 2
+    ref = (Yo[0, : n - 1, : n - 1, :P].transpose(2, 0, 1).reshape(-1) / s * n * n / kappa)
     cg = c.cpu().numpy()
     assert np.linalg.norm(cg - ref) <= 1e-2 * np.linalg.norm(ref)
     net.close()
