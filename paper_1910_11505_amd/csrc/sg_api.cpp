@@ -35,7 +35,6 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 struct FSHost {
   std::vector<std::vector<int>> splits;
   std::vector<RowSetHost> partial;  // partial[s] for s >= 1 (index 0 unused)
-  std::vector<int> kc, nchunk;      // chunking of each partial row set
   std::vector<std::vector<int>> sid;  // stencil ids (mode + 1) of each split
 };
 
@@ -85,7 +84,6 @@ struct sg_handle {
   std::vector<double> f_nodal, g_tiled, isf;
   std::vector<int> Jq_flat;
   RowSetHost full;
-  int full_kc = 0, full_nchunk = 0;
   FSHost fs[4];
   std::vector<int> level_n;
   std::vector<int> diag_ptr, diag_k, diag_sid;  // per mode i: [G_k]_{ii} != 0 entries
@@ -108,40 +106,44 @@ struct sg_handle {
 
 namespace {
 
-// Groups a row set's nonzero triple products by coefficient chunk of kc modes:
-// chunk-major, and inside a chunk row by row, every row segment padded to
-// kEntryUnroll entries.  Returns the largest entry count of one chunk.
+// Groups a row set's nonzero triple products by column pass and coefficient
+// chunk of kc modes: pass-major, then chunk-major, and inside a chunk row by
+// row, every row segment padded to kEntryUnroll entries.  Column slots are
+// relative to the pass.  Returns the largest entry count of one (pass, chunk).
 int layout_entries(const sg_handle& H, RowSetHost& rs, int kc, const std::vector<int>& rslot,
                    const std::vector<int>& cslot) {
   const int nchunk = (H.na + kc - 1) / kc;
+  const int np = rs.npass;
+  std::vector<int> cpass_of(rs.ncols);
+  for (int p = 0; p < np; ++p)
+    for (int c = rs.cpass[p]; c < rs.cpass[p + 1]; ++c) cpass_of[c] = p;
   std::vector<std::vector<std::vector<std::pair<int, double>>>> bucket(
-      nchunk, std::vector<std::vector<std::pair<int, double>>>(rs.nrows));
+      (size_t)np * nchunk, std::vector<std::vector<std::pair<int, double>>>(rs.nrows));
   for (const Triple& tr : H.G) {
     int r = rslot[tr.i], c = cslot[tr.j];
     if (r < 0 || c < 0) continue;
-    int ch = tr.k / kc;
-    bucket[ch][r].push_back({(tr.k - ch * kc) | (c << 16), tr.v});
+    const int p = cpass_of[c];
+    const int ch = tr.k / kc;
+    bucket[(size_t)p * nchunk + ch][r].push_back({(tr.k - ch * kc) | ((c - rs.cpass[p]) << 16), tr.v});
   }
   rs.ent.clear();
-  rs.ptr.assign((size_t)nchunk * (rs.nrows + 1), 0);
+  rs.ptr.assign((size_t)np * nchunk * (rs.nrows + 1), 0);
   int maxent = 0;
-  for (int ch = 0; ch < nchunk; ++ch) {
+  for (int pc = 0; pc < np * nchunk; ++pc) {
     const int base = (int)rs.ent.size();
     for (int r = 0; r < rs.nrows; ++r) {
-      rs.ptr[(size_t)ch * (rs.nrows + 1) + r] = (int)rs.ent.size();
-      for (auto& e : bucket[ch][r]) rs.ent.push_back(Entry{e.first, 0, e.second});
+      rs.ptr[(size_t)pc * (rs.nrows + 1) + r] = (int)rs.ent.size();
+      for (auto& e : bucket[pc][r]) rs.ent.push_back(Entry{e.first, 0, e.second});
       while (rs.ent.size() % kEntryUnroll) rs.ent.push_back(Entry{0, 0, 0.0});
     }
-    rs.ptr[(size_t)ch * (rs.nrows + 1) + rs.nrows] = (int)rs.ent.size();
+    rs.ptr[(size_t)pc * (rs.nrows + 1) + rs.nrows] = (int)rs.ent.size();
     maxent = std::max(maxent, (int)rs.ent.size() - base);
   }
-  // one zero group past the end: the apply kernel loads a group ahead
-  for (int u = 0; u < kEntryUnroll; ++u) rs.ent.push_back(Entry{0, 0, 0.0});
   return maxent;
 }
 
 RowSetHost build_rowset(const sg_handle& H, const std::vector<int>& rows,
-                        const std::vector<int>& cols, int& kc_out, int& nchunk_out) {
+                        const std::vector<int>& cols) {
   RowSetHost rs;
   rs.rows = rows;
   rs.cols = cols;
@@ -151,34 +153,44 @@ RowSetHost build_rowset(const sg_handle& H, const std::vector<int>& rows,
   for (int t = 0; t < rs.nrows; ++t) rslot[rows[t]] = t;
   for (int t = 0; t < rs.ncols; ++t) cslot[cols[t]] = t;
   // kc: coefficient modes staged per chunk.  Prefer three workgroups per CU
-  // (<= 53 KB of LDS) with chunks of >= 32 modes, then two, then one.
-  const int ncl = std::max(rs.ncols, 1);
+  // (<= 53 KB of LDS) with chunks of >= 32 modes, then two, then one; when the
+  // gradients of all columns do not fit, split the columns into passes.
   const int cands[] = {64, 48, 32, 24, 16, 12, 8, 6, 4, 3, 2, 1};
   static_assert(kMaxChunk == 64, "candidate list starts at kMaxChunk");
   const struct { size_t budget; int minkc; } tiers[] = {{53 * 1024, 32}, {80 * 1024, 16},
                                                          {160 * 1024, 1}};
   int kc = 0;
-  for (auto& tier : tiers) {
-    for (int c : cands) {
-      const int kcc = std::min(c, H.na);
-      if (kcc < std::min(tier.minkc, H.na)) break;
-      const int maxent = layout_entries(H, rs, kcc, rslot, cslot);
-      if (apply_lds_bytes(ncl, kcc, maxent) <= tier.budget) {
-        kc = kcc;
-        rs.maxent = maxent;
-        break;
+  for (int np = 1; np <= 8 && !kc; ++np) {
+    rs.npass = np;
+    rs.cpass.assign(np + 1, 0);
+    for (int p = 0; p <= np; ++p) rs.cpass[p] = (int)((int64_t)rs.ncols * p / np);
+    rs.maxcols = 1;
+    for (int p = 0; p < np; ++p) rs.maxcols = std::max(rs.maxcols, rs.cpass[p + 1] - rs.cpass[p]);
+    for (auto& tier : tiers) {
+      if (np > 1 && tier.budget < 160 * 1024) continue;
+      for (int c : cands) {
+        const int kcc = std::min(c, H.na);
+        if (kcc < std::min(np > 1 ? 16 : tier.minkc, H.na)) break;
+        const int maxent = layout_entries(H, rs, kcc, rslot, cslot);
+        if (apply_lds_bytes(rs.maxcols, kcc, maxent) <= tier.budget) {
+          kc = kcc;
+          rs.maxent = maxent;
+          break;
+        }
       }
+      if (kc) break;
     }
-    if (kc) break;
   }
   if (!kc)
     throw Error(SG_ERR_UNSUPPORTED, "apply: the gradients of " + std::to_string(rs.ncols) +
                                         " modes do not fit in LDS");
   const int nchunk = (H.na + kc - 1) / kc;
+  rs.kc = kc;
+  rs.nchunk = nchunk;
   std::vector<long> load(rs.nrows, 0);
-  for (int ch = 0; ch < nchunk; ++ch)
+  for (int pc = 0; pc < rs.npass * nchunk; ++pc)
     for (int r = 0; r < rs.nrows; ++r)
-      load[r] += rs.ptr[(size_t)ch * (rs.nrows + 1) + r + 1] - rs.ptr[(size_t)ch * (rs.nrows + 1) + r];
+      load[r] += rs.ptr[(size_t)pc * (rs.nrows + 1) + r + 1] - rs.ptr[(size_t)pc * (rs.nrows + 1) + r];
   // rows to wavefronts: longest rows first onto the least loaded wavefront
   const int need = std::max(1, (rs.nrows + kApplyWaves - 1) / kApplyWaves);
   int rmax = 1;
@@ -199,8 +211,8 @@ RowSetHost build_rowset(const sg_handle& H, const std::vector<int>& rows,
     wc[best]++;
     wl[best] += load[r];
   }
-  kc_out = kc;
-  nchunk_out = nchunk;
+  // one zero group past the end (reads of a padded group never leave the array)
+  for (int u = 0; u < kEntryUnroll; ++u) rs.ent.push_back(Entry{0, 0, 0.0});
   return rs;
 }
 
@@ -235,8 +247,13 @@ void carve(const sg_handle& H, DevPtrs& D, Carver& c) {
     d.ncols = rs.ncols;
     d.rmax = rs.rmax;
     d.maxent = rs.maxent;
+    d.kc = rs.kc;
+    d.nchunk = rs.nchunk;
+    d.npass = rs.npass;
+    d.maxcols = rs.maxcols;
     d.rows = c.take<int>(rs.rows.size());
     d.cols = c.take<int>(std::max<size_t>(rs.cols.size(), 1));
+    d.cpass = c.take<int>(rs.cpass.size());
     d.wrows = c.take<int>(rs.wrows.size());
     d.ptr = c.take<int>(rs.ptr.size());
     d.ent = c.take<Entry>(std::max<size_t>(rs.ent.size(), 1));
@@ -287,6 +304,7 @@ void upload(hipStream_t s, const T* dst, const std::vector<T>& src) {
 void upload_rowset(hipStream_t s, const RowSetHost& h, const RowSetDev& d) {
   upload(s, d.rows, h.rows);
   upload(s, d.cols, h.cols);
+  upload(s, d.cpass, h.cpass);
   upload(s, d.wrows, h.wrows);
   upload(s, d.ptr, h.ptr);
   upload(s, d.ent, h.ent);
@@ -325,8 +343,7 @@ void vcycle(sg_handle& H, hipStream_t s, int m, const int* smode, const double* 
 }
 
 void do_apply(sg_handle& H, hipStream_t s, const double* U, double* W) {
-  launch_apply(s, H.n, H.full_nchunk, H.full_kc, H.na, H.d.a, H.d.full, U, H.Nh, nullptr, 0.0,
-               1.0, W, H.d.edge);
+  launch_apply(s, H.n, H.na, H.d.a, H.d.full, U, H.Nh, nullptr, 0.0, 1.0, W, H.d.edge);
 }
 
 void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double* r, double* z) {
@@ -350,8 +367,8 @@ void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double*
     if (sp == 0) {
       launch_gather_modes(s, m, fd.split_idx[0], H.Nh, r, H.d.fsT);
     } else {
-      launch_apply(s, H.n, fh.nchunk[sp], fh.kc[sp], H.na, H.d.a, fd.partial[sp], z, H.Nh, r, 1.0,
-                   -1.0, H.d.fsT, H.d.edge);
+      launch_apply(s, H.n, H.na, H.d.a, fd.partial[sp], z, H.Nh, r, 1.0, -1.0, H.d.fsT,
+                   H.d.edge);
     }
     vcycle(H, s, m, kii ? fd.split_sid[sp] : nullptr, H.d.fsT, H.d.fsX);
     launch_scatter_modes(s, m, fd.split_idx[sp], H.Nh, H.d.fsX, z);
@@ -421,20 +438,18 @@ int sg_setup(const sg_problem* prob, const double* f_nodal, sg_handle** out) {
       if (!std::isfinite(v)) throw Error(SG_ERR_INVALID_ARG, "non-finite forcing");
     std::vector<int> all(H->P);
     std::iota(all.begin(), all.end(), 0);
-    H->full = build_rowset(*H, all, all, H->full_kc, H->full_nchunk);
+    H->full = build_rowset(*H, all, all);
     for (int g = 0; g < 4; ++g) {
       FSHost& fh = H->fs[g];
       fh.splits = make_splits(H->Jp, g);
       fh.partial.assign(fh.splits.size(), RowSetHost{});
-      fh.kc.assign(fh.splits.size(), 0);
       fh.sid.assign(fh.splits.size(), {});
       for (size_t sp = 0; sp < fh.splits.size(); ++sp)
         for (int i : fh.splits[sp]) fh.sid[sp].push_back(i + 1);
-      fh.nchunk.assign(fh.splits.size(), 0);
       std::vector<int> prev;
       for (size_t s = 0; s < fh.splits.size(); ++s) {
         if (s >= 1)
-          fh.partial[s] = build_rowset(*H, fh.splits[s], prev, fh.kc[s], fh.nchunk[s]);
+          fh.partial[s] = build_rowset(*H, fh.splits[s], prev);
         prev.insert(prev.end(), fh.splits[s].begin(), fh.splits[s].end());
       }
     }

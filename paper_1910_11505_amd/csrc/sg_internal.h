@@ -71,17 +71,21 @@ constexpr int kMaxChunk = 64;    // coefficient modes staged per chunk at most
 
 struct RowSetHost {
   int nrows = 0, ncols = 0, rmax = 0, maxent = 0;
+  int kc = 0, nchunk = 0, npass = 1, maxcols = 0;
   std::vector<int> rows;        // mode index of each output row
-  std::vector<int> cols;        // mode index of each gradient column
+  std::vector<int> cols;        // mode index of each gradient column, pass by pass
+  std::vector<int> cpass;       // npass + 1 column offsets of the passes
   std::vector<int> wrows;       // kApplyWaves x rmax, row slot per wave (-1 pad)
-  std::vector<int> ptr;         // nchunk x (nrows+1): chunk-major row segments
+  std::vector<int> ptr;         // npass x nchunk x (nrows+1): row segments
   std::vector<Entry> ent;       // zero-valued padding entries point at (0, 0)
 };
 
 struct RowSetDev {
   int nrows, ncols, rmax, maxent;
+  int kc, nchunk, npass, maxcols;
   const int* rows;
   const int* cols;
+  const int* cpass;
   const int* wrows;
   const int* ptr;
   const Entry* ent;
@@ -99,10 +103,10 @@ void launch_coeff(hipStream_t s, int n, int M, int na, const double* g, const in
 void launch_fine_stencil(hipStream_t s, int n, const double* a0, double* S);
 void launch_rap(hipStream_t s, int nf, const double* Sf, double* Sc);
 void launch_rhs(hipStream_t s, int n, const double* f_nodal, double* F, int64_t total);
-void launch_apply(hipStream_t s, int n, int nchunk, int kc, int na, const double* a,
-                  const RowSetDev& rs, const double* U, int64_t Nh, const double* rin,
-                  double beta, double sgn, double* out, double* edge);
-size_t apply_lds_bytes(int ncols, int kc, int maxent);
+void launch_apply(hipStream_t s, int n, int na, const double* a, const RowSetDev& rs,
+                  const double* U, int64_t Nh, const double* rin, double beta, double sgn,
+                  double* out, double* edge);
+size_t apply_lds_bytes(int maxcols, int kc, int maxent);
 void launch_zero(hipStream_t s, double* x, int64_t n);
 void launch_jacobi(hipStream_t s, const Level& L, int m, const double* b, const double* xin,
                    double* xout, double omega, bool first);

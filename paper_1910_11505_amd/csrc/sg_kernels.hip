@@ -208,83 +208,48 @@ void launch_rhs(hipStream_t s, int n, const double* f, double* F, int64_t total)
 }
 
 // ---------------------------------------------------------------------------
-// SG operator apply.  One workgroup = one 4x4 element tile (64 Gauss points,
-// one per lane), four wavefronts splitting the output rows.
-//   1. stage the tile's 5x5 nodal values of every needed input mode in LDS;
+// SG operator apply.  One tile = 4x4 elements (64 Gauss points, one per lane),
+// four wavefronts splitting the output rows.  For each pass over a slice of
+// the input columns (all columns in one pass unless their gradients exceed
+// LDS):
+//   1. stage the tile's 5x5 nodal values of the pass's input modes in LDS;
 //   2. reference gradients of those modes at the 64 points -> LDS;
 //   3. stream the coefficient modes a_k in chunks of kc modes through LDS
-//      (each value read from HBM once, coalesced 512-byte rows) and, per
-//      output row, accumulate flux_i(q) += a_k(q) [G_k]_{ij} grad U_j(q) over
-//      the row's nonzero triple products of that chunk (wave-uniform, so the
-//      (k, j, value) stream is read through the scalar cache);
-//   4. per row: element-node contributions (1/4) grad phi_a . flux, summed over
-//      the element's four lanes, then node sums in fixed order; nodes owned
-//      by the tile are written, the right/top edge and corner go to a small
-//      edge buffer folded in by apply_fixup_kernel.
+//      (each value read from HBM once per pass, coalesced 512-byte rows,
+//      prefetched into registers one chunk ahead) together with the chunk's
+//      (k, j, value) records, and per output row accumulate
+//      flux_i(q) += a_k(q) [G_k]_{ij} grad U_j(q);
+// then per row: element-node contributions (1/4) grad phi_a . flux, summed over
+// the element's four lanes, then node sums in fixed order; nodes owned by the
+// tile are written, the right/top edge and corner go to a small edge buffer
+// folded in by the fixup step.
 // out[slot] = beta * rin[row] + sgn * (K_sub U)[row].
 // ---------------------------------------------------------------------------
 template <int RMAX>
-__global__ __launch_bounds__(256) void apply_kernel(
-    int n, int nchunk, int kc, int na, const double* __restrict__ a, RowSetDev rs,
-    const double* __restrict__ U, int64_t Nh, const double* __restrict__ rin, double beta,
-    double sgn, double* __restrict__ out, double* __restrict__ edge) {
-  extern __shared__ double smem[];
+__device__ __forceinline__ void apply_tile(double* smem, int tile, int n, int na,
+                                           const double* __restrict__ a, const RowSetDev& rs,
+                                           const double* __restrict__ U, int64_t Nh,
+                                           const double* __restrict__ rin, double beta,
+                                           double sgn, double* __restrict__ out,
+                                           double* __restrict__ edge) {
   const int nt = n / kTileE;
   const int ntiles = nt * nt;
-  const int tile = blockIdx.x;
   const int tx = tile % nt, ty = tile / nt;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int ncols = rs.ncols;
   const int64_t Nq = (int64_t)4 * n * n;
   const int m = n - 1;
+  const int kc = rs.kc, nchunk = rs.nchunk, nrows = rs.nrows;
   double2* sG = reinterpret_cast<double2*>(smem);
-  double* sA = smem + 2 * ncols * kTileQ;
-  const int sa_len = (max(max(kc * kTileQ, ncols * 25), kApplyWaves * kTileQ) + 1) & ~1;
+  double* sA = smem + 2 * rs.maxcols * kTileQ;
+  const int sa_len = (max(max(kc * kTileQ, rs.maxcols * 25), kApplyWaves * kTileQ) + 1) & ~1;
   Entry* sEnt = reinterpret_cast<Entry*>(sA + sa_len);
   const int x0 = tx * kTileE, y0 = ty * kTileE;
 
-  // 1. nodal values of the needed modes on the tile's 5x5 nodes (batched loads)
-  for (int base = tid; base < ncols * 25; base += 256 * 4) {
-    double v[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int idx = base + u * 256;
-      v[u] = 0.0;
-      if (idx < ncols * 25) {
-        const int c = idx / 25, nd = idx - c * 25;
-        const int gx = x0 + nd % 5, gy = y0 + nd / 5;
-        if (gx >= 1 && gx <= m && gy >= 1 && gy <= m)
-          v[u] = U[(int64_t)rs.cols[c] * Nh + (int64_t)(gy - 1) * m + (gx - 1)];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (base + u * 256 < ncols * 25) sA[base + u * 256] = v[u];
-  }
-  __syncthreads();
-  // 2. reference gradients at the Gauss points
-  for (int idx = tid; idx < ncols * kTileQ; idx += 256) {
-    const int c = idx >> 6, lq = idx & 63;
-    const int el = lq >> 2, ql = lq & 3;
-    const int elx = el & 3, ely = el >> 2;
-    const double xi = gauss_pt(ql & 1), eta = gauss_pt(ql >> 1);
-    const double* u = sA + c * 25;
-    const double u00 = u[ely * 5 + elx], u10 = u[ely * 5 + elx + 1];
-    const double u01 = u[(ely + 1) * 5 + elx], u11 = u[(ely + 1) * 5 + elx + 1];
-    sG[idx] = make_double2((1.0 - eta) * (u10 - u00) + eta * (u11 - u01),
-                           (1.0 - xi) * (u01 - u00) + xi * (u11 - u10));
-  }
-  __syncthreads();
-
-  // 3. flux accumulation
   double ax[RMAX], ay[RMAX];
 #pragma unroll
   for (int r = 0; r < RMAX; ++r) ax[r] = ay[r] = 0.0;
   const int* wrows = rs.wrows + wave * RMAX;
-  const int nrows = rs.nrows;
-  // coefficient chunks are prefetched into registers one chunk ahead, so the
-  // HBM latency of chunk ch+1 overlaps the flux work on chunk ch
   constexpr int kPre = kMaxChunk * kTileQ / 256;
   double pre[kPre];
   auto prefetch = [&](int ch) {
@@ -297,58 +262,96 @@ __global__ __launch_bounds__(256) void apply_kernel(
       pre[u] = (idx < cnt) ? src[(int64_t)(idx >> 6) * Nq + (idx & 63)] : 0.0;
     }
   };
-  prefetch(0);
-  for (int ch = 0; ch < nchunk; ++ch) {
-    const int cnt = min(kc, na - ch * kc) * kTileQ;
+
+  for (int pass = 0; pass < rs.npass; ++pass) {
+    const int c0 = rs.cpass[pass];
+    const int ncols = rs.cpass[pass + 1] - c0;
+    prefetch(0);
+    // 1. nodal values of the pass's modes on the tile's 5x5 nodes (batched loads)
+    for (int base = tid; base < ncols * 25; base += 256 * 4) {
+      double v[4];
 #pragma unroll
-    for (int u = 0; u < kPre; ++u)
-      if (tid + u * 256 < cnt) sA[tid + u * 256] = pre[u];
-    // this chunk's triple products, all rows, as 16-byte records
-    const int cb = rs.ptr[ch * (nrows + 1)];
-    const int ce = rs.ptr[ch * (nrows + 1) + nrows];
-    const int4* esrc = reinterpret_cast<const int4*>(rs.ent + cb);
-    int4* edst = reinterpret_cast<int4*>(sEnt);
-    for (int base = tid; base < ce - cb; base += 256 * 4) {
-      int4 v[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (base + u * 256 < ce - cb) v[u] = esrc[base + u * 256];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (base + u * 256 < ce - cb) edst[base + u * 256] = v[u];
-    }
-    __syncthreads();
-    if (ch + 1 < nchunk) prefetch(ch + 1);
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-      const int slot = wrows[r];
-      if (slot >= 0) {
-        const int b = rs.ptr[ch * (nrows + 1) + slot] - cb;
-        const int e = rs.ptr[ch * (nrows + 1) + slot + 1] - cb;
-        double sx = ax[r], sy = ay[r];
-        for (int t = b; t < e; t += kEntryUnroll) {
-          Entry en[kEntryUnroll];
-#pragma unroll
-          for (int u = 0; u < kEntryUnroll; ++u) en[u] = sEnt[t + u];
-          double av[kEntryUnroll];
-          double2 gg[kEntryUnroll];
-#pragma unroll
-          for (int u = 0; u < kEntryUnroll; ++u) {
-            av[u] = sA[(en[u].kj & 0xffff) * kTileQ + lane];
-            gg[u] = sG[(en[u].kj >> 16) * kTileQ + lane];
-          }
-#pragma unroll
-          for (int u = 0; u < kEntryUnroll; ++u) {
-            const double c = av[u] * en[u].v;
-            sx = fma(c, gg[u].x, sx);
-            sy = fma(c, gg[u].y, sy);
-          }
+      for (int u = 0; u < 4; ++u) {
+        const int idx = base + u * 256;
+        v[u] = 0.0;
+        if (idx < ncols * 25) {
+          const int c = idx / 25, nd = idx - c * 25;
+          const int gx = x0 + nd % 5, gy = y0 + nd / 5;
+          if (gx >= 1 && gx <= m && gy >= 1 && gy <= m)
+            v[u] = U[(int64_t)rs.cols[c0 + c] * Nh + (int64_t)(gy - 1) * m + (gx - 1)];
         }
-        ax[r] = sx;
-        ay[r] = sy;
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (base + u * 256 < ncols * 25) sA[base + u * 256] = v[u];
     }
     __syncthreads();
+    // 2. reference gradients at the Gauss points
+    for (int idx = tid; idx < ncols * kTileQ; idx += 256) {
+      const int c = idx >> 6, lq = idx & 63;
+      const int el = lq >> 2, ql = lq & 3;
+      const int elx = el & 3, ely = el >> 2;
+      const double xi = gauss_pt(ql & 1), eta = gauss_pt(ql >> 1);
+      const double* u = sA + c * 25;
+      const double u00 = u[ely * 5 + elx], u10 = u[ely * 5 + elx + 1];
+      const double u01 = u[(ely + 1) * 5 + elx], u11 = u[(ely + 1) * 5 + elx + 1];
+      sG[idx] = make_double2((1.0 - eta) * (u10 - u00) + eta * (u11 - u01),
+                             (1.0 - xi) * (u01 - u00) + xi * (u11 - u10));
+    }
+    __syncthreads();
+    // 3. flux accumulation over the coefficient chunks
+    const int* pptr = rs.ptr + (int64_t)pass * nchunk * (nrows + 1);
+    for (int ch = 0; ch < nchunk; ++ch) {
+      const int cnt = min(kc, na - ch * kc) * kTileQ;
+#pragma unroll
+      for (int u = 0; u < kPre; ++u)
+        if (tid + u * 256 < cnt) sA[tid + u * 256] = pre[u];
+      const int cb = pptr[ch * (nrows + 1)];
+      const int ce = pptr[ch * (nrows + 1) + nrows];
+      const int4* esrc = reinterpret_cast<const int4*>(rs.ent + cb);
+      int4* edst = reinterpret_cast<int4*>(sEnt);
+      for (int base = tid; base < ce - cb; base += 256 * 4) {
+        int4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (base + u * 256 < ce - cb) v[u] = esrc[base + u * 256];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (base + u * 256 < ce - cb) edst[base + u * 256] = v[u];
+      }
+      __syncthreads();
+      if (ch + 1 < nchunk) prefetch(ch + 1);
+#pragma unroll
+      for (int r = 0; r < RMAX; ++r) {
+        const int slot = wrows[r];
+        if (slot >= 0) {
+          const int b = pptr[ch * (nrows + 1) + slot] - cb;
+          const int e = pptr[ch * (nrows + 1) + slot + 1] - cb;
+          double sx = ax[r], sy = ay[r];
+          for (int t = b; t < e; t += kEntryUnroll) {
+            Entry en[kEntryUnroll];
+#pragma unroll
+            for (int u = 0; u < kEntryUnroll; ++u) en[u] = sEnt[t + u];
+            double av[kEntryUnroll];
+            double2 gg[kEntryUnroll];
+#pragma unroll
+            for (int u = 0; u < kEntryUnroll; ++u) {
+              av[u] = sA[(en[u].kj & 0xffff) * kTileQ + lane];
+              gg[u] = sG[(en[u].kj >> 16) * kTileQ + lane];
+            }
+#pragma unroll
+            for (int u = 0; u < kEntryUnroll; ++u) {
+              const double c = av[u] * en[u].v;
+              sx = fma(c, gg[u].x, sx);
+              sy = fma(c, gg[u].y, sy);
+            }
+          }
+          ax[r] = sx;
+          ay[r] = sy;
+        }
+      }
+      __syncthreads();
+    }
   }
 
   // 4. node contributions, row by row
@@ -399,14 +402,24 @@ __global__ __launch_bounds__(256) void apply_kernel(
   }
 }
 
+template <int RMAX>
+__global__ __launch_bounds__(256) void apply_kernel(int n, int na, const double* __restrict__ a,
+                                                    RowSetDev rs, const double* __restrict__ U,
+                                                    int64_t Nh, const double* __restrict__ rin,
+                                                    double beta, double sgn,
+                                                    double* __restrict__ out,
+                                                    double* __restrict__ edge) {
+  extern __shared__ double smem[];
+  apply_tile<RMAX>(smem, blockIdx.x, n, na, a, rs, U, Nh, rin, beta, sgn, out, edge);
+}
+
 // Folds the edge contributions of the left, bottom and diagonal neighbour
-// tiles into the nodes on a tile's left column and bottom row.
-__global__ void apply_fixup_kernel(int n, int nrows, double sgn, const double* __restrict__ edge,
-                                   double* __restrict__ out, int64_t Nh) {
+// tiles into the nodes on a tile's left column and bottom row (item gid of
+// nrows * ntiles * 7).
+__device__ __forceinline__ void apply_fixup_item(int64_t gid, int n, double sgn,
+                                                 const double* __restrict__ edge,
+                                                 double* __restrict__ out, int64_t Nh) {
   const int nt = n / kTileE, ntiles = nt * nt, m = n - 1;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)nrows * ntiles * 7;
-  if (gid >= total) return;
   const int j = (int)(gid % 7);
   const int64_t rt = gid / 7;
   const int tile = (int)(rt % ntiles);
@@ -425,23 +438,31 @@ __global__ void apply_fixup_kernel(int n, int nrows, double sgn, const double* _
   out[(int64_t)slot * Nh + node] = v;
 }
 
-size_t apply_lds_bytes(int ncols, int kc, int maxent) {
-  size_t sa = std::max<size_t>({(size_t)kc * kTileQ, (size_t)ncols * 25, (size_t)kApplyWaves * kTileQ});
-  sa = (sa + 1) & ~size_t(1);  // keeps the entry records 16-byte aligned
-  return 8 * (2 * (size_t)ncols * kTileQ + sa) + sizeof(Entry) * (size_t)maxent;
+__global__ void apply_fixup_kernel(int n, int nrows, double sgn, const double* __restrict__ edge,
+                                   double* __restrict__ out, int64_t Nh) {
+  const int nt = n / kTileE;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)nrows * nt * nt * 7) return;
+  apply_fixup_item(gid, n, sgn, edge, out, Nh);
 }
 
-void launch_apply(hipStream_t s, int n, int nchunk, int kc, int na, const double* a,
-                  const RowSetDev& rs, const double* U, int64_t Nh, const double* rin,
-                  double beta, double sgn, double* out, double* edge) {
+size_t apply_lds_bytes(int maxcols, int kc, int maxent) {
+  size_t sa = std::max<size_t>({(size_t)kc * kTileQ, (size_t)maxcols * 25, (size_t)kApplyWaves * kTileQ});
+  sa = (sa + 1) & ~size_t(1);  // keeps the entry records 16-byte aligned
+  return 8 * (2 * (size_t)maxcols * kTileQ + sa) + sizeof(Entry) * (size_t)maxent;
+}
+
+void launch_apply(hipStream_t s, int n, int na, const double* a, const RowSetDev& rs,
+                  const double* U, int64_t Nh, const double* rin, double beta, double sgn,
+                  double* out, double* edge) {
   const int nt = n / kTileE;
   const int ntiles = nt * nt;
-  const size_t lds = apply_lds_bytes(rs.ncols, kc, rs.maxent);
+  const size_t lds = apply_lds_bytes(rs.maxcols, rs.kc, rs.maxent);
   dim3 grid(ntiles), block(256);
 #define SG_APPLY_CASE(R)                                                                     \
   case R:                                                                                    \
-    hipLaunchKernelGGL(apply_kernel<R>, grid, block, lds, s, n, nchunk, kc, na, a, rs, U,    \
-                       Nh, rin, beta, sgn, out, edge);                                       \
+    hipLaunchKernelGGL(apply_kernel<R>, grid, block, lds, s, n, na, a, rs, U, Nh, rin, beta, \
+                       sgn, out, edge);                                                      \
     break;
   switch (rs.rmax) {
     SG_APPLY_CASE(1)
