@@ -226,6 +226,43 @@ const char* sg_cnn_last_error(void);
  * SG_PC_LEARNED solves of this handle; NULL detaches                        */
 int    sg_attach_cnn(sg_handle* h, sg_cnn* c, double sigma);
 
+/* ---------------------------------------------------------------------------
+ * Batched solves: many instances of uneven grid size, KL dimension, degree
+ * and sigma solved together.  Persistent kernels walk device work-item tables
+ * that cover every instance; per-instance Krylov state stays on the device,
+ * so one Arnoldi step of all instances (and the restart step) is captured
+ * once in a HIP graph and replayed.  Instances advance in lockstep; converged
+ * instances are masked.  Not part of the paper.
+ * ------------------------------------------------------------------------- */
+typedef struct sg_batch sg_batch;
+/* count instances; f_nodal: NULL or an array of count host pointers (each
+ * NULL or (n_i+1)^2 values).  autotune != 0 picks each problem class's
+ * coefficient chunk of the operator apply by timing candidates on the
+ * current device (cached on disk, keyed by device, n, M, p, q; the cache
+ * file is $SG_AUTOTUNE_CACHE or ~/.sgfs_autotune.txt).                      */
+int    sg_batch_create(int32_t count, const sg_problem* probs, const double* const* f_nodal,
+                       int32_t autotune, sg_batch** out);
+/* packed vector layout: offsets[0..count] (instance i occupies
+ * [offsets[i], offsets[i+1]) of every packed SG vector); chunk (nullable):
+ * the chosen coefficient chunk of each instance's apply                     */
+int    sg_batch_layout(const sg_batch* b, int64_t* offsets, int32_t* chunk);
+size_t sg_batch_workspace_bytes(const sg_batch* b, int32_t restart);
+/* binds a caller-owned 256-byte aligned workspace for GMRES(restart)      */
+int    sg_batch_bind(sg_batch* b, int32_t restart, void* ws, size_t bytes, void* stream);
+/* packed right-hand sides                                                  */
+int    sg_batch_rhs(sg_batch* b, double* F, void* stream);
+/* the bound handle of instance i (for single-instance calls; owned by b)   */
+int    sg_batch_handle(sg_batch* b, int32_t i, sg_handle** h);
+/* solves every instance from zero with opts (pc SG_PC_MEAN or SG_PC_FS, any
+ * grouping, restart equal to the bound value); F, u packed device vectors;
+ * infos: count entries.  Graph capture needs a non-null stream (the null
+ * stream runs the same launch sequences eagerly).  Synchronous.            */
+int    sg_batch_solve(sg_batch* b, const sg_solve_opts* opts, const double* F, double* u,
+                      sg_solve_info* infos, void* stream);
+void   sg_batch_destroy(sg_batch* b);
+/* the autotuner on its own: fastest coefficient chunk for one problem      */
+int    sg_autotune_apply(const sg_problem* prob, int32_t* best_chunk, float* best_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -93,6 +93,16 @@ def load_library():
         "sg_cnn_destroy": (None, [HP]),
         "sg_cnn_last_error": (ctypes.c_char_p, []),
         "sg_attach_cnn": (I32, [HP, HP, ctypes.c_double]),
+        "sg_batch_create": (I32, [ctypes.c_int32, P(Problem), VP, ctypes.c_int32, P(HP)]),
+        "sg_batch_layout": (I32, [HP, I64P, VP]),
+        "sg_batch_workspace_bytes": (SZ, [HP, ctypes.c_int32]),
+        "sg_batch_bind": (I32, [HP, ctypes.c_int32, VP, SZ, VP]),
+        "sg_batch_rhs": (I32, [HP, VP, VP]),
+        "sg_batch_handle": (I32, [HP, ctypes.c_int32, P(HP)]),
+        "sg_batch_solve": (I32, [HP, P(SolveOpts), VP, VP, P(SolveInfo), VP]),
+        "sg_batch_destroy": (None, [HP]),
+        "sg_autotune_apply": (I32, [P(Problem), ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_float)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -398,6 +408,83 @@ class CNN:
         if self.c:
             sg_cnn_destroy(self.c)
             self.c = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sg_autotune_apply(prob: Problem):
+    kc = ctypes.c_int32(0)
+    ms = ctypes.c_float(0.0)
+    _check(load_library().sg_autotune_apply(ctypes.byref(prob), ctypes.byref(kc), ctypes.byref(ms)))
+    return kc.value, ms.value
+
+
+class Batch:
+    """Many instances solved together by the batched persistent kernels."""
+
+    def __init__(self, problems, f_nodal=None, restart=50, autotune=False, device="cuda:0",
+                 stream=None):
+        import numpy as np
+        import torch
+        self.count = len(problems)
+        arr = (Problem * self.count)(*problems)
+        self._f = None
+        fp = None
+        if f_nodal is not None:
+            self._f = [None if f is None else np.ascontiguousarray(f, dtype=np.float64) for f in f_nodal]
+            ptrs = (ctypes.c_void_p * self.count)(*[None if f is None else f.ctypes.data for f in self._f])
+            fp = ctypes.cast(ptrs, ctypes.c_void_p)
+            self._ptrs = ptrs
+        self.b = ctypes.c_void_p()
+        _check(load_library().sg_batch_create(self.count, arr, fp, 1 if autotune else 0,
+                                              ctypes.byref(self.b)))
+        self.offsets = np.zeros(self.count + 1, dtype=np.int64)
+        self.chunk = np.zeros(self.count, dtype=np.int32)
+        _check(load_library().sg_batch_layout(self.b, self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                              self.chunk.ctypes.data))
+        self.restart = restart
+        self.device = torch.device(device)
+        self.stream = stream
+        nb = int(load_library().sg_batch_workspace_bytes(self.b, restart))
+        self.ws = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        _check(load_library().sg_batch_bind(self.b, restart, self.ws.data_ptr() + off, nb,
+                                            _stream(stream)))
+
+    @property
+    def total(self):
+        return int(self.offsets[-1])
+
+    def vec(self):
+        import torch
+        return torch.zeros(self.total, dtype=torch.float64, device=self.device)
+
+    def rhs(self):
+        F = self.vec()
+        _check(load_library().sg_batch_rhs(self.b, F.data_ptr(), _stream(self.stream)))
+        return F
+
+    def handle(self, i):
+        h = ctypes.c_void_p()
+        _check(load_library().sg_batch_handle(self.b, i, ctypes.byref(h)))
+        return h
+
+    def solve(self, F, u=None, pc="fs", grouping="klvar", tol=1e-8, max_it=5000):
+        u = self.vec() if u is None else u
+        opts = SolveOpts(self.restart, max_it, PC[pc], GROUPING[grouping], 0, tol)
+        infos = (SolveInfo * self.count)()
+        _check(load_library().sg_batch_solve(self.b, ctypes.byref(opts), F.data_ptr(), u.data_ptr(),
+                                             infos, _stream(self.stream)))
+        return u, list(infos)
+
+    def close(self):
+        if self.b:
+            load_library().sg_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

@@ -143,7 +143,7 @@ int layout_entries(const sg_handle& H, RowSetHost& rs, int kc, const std::vector
 }
 
 RowSetHost build_rowset(const sg_handle& H, const std::vector<int>& rows,
-                        const std::vector<int>& cols) {
+                        const std::vector<int>& cols, int force_kc = 0) {
   RowSetHost rs;
   rs.rows = rows;
   rs.cols = cols;
@@ -169,6 +169,7 @@ RowSetHost build_rowset(const sg_handle& H, const std::vector<int>& rows,
     for (auto& tier : tiers) {
       if (np > 1 && tier.budget < 160 * 1024) continue;
       for (int c : cands) {
+        if (force_kc > 0 && c != force_kc) continue;
         const int kcc = std::min(c, H.na);
         if (kcc < std::min(np > 1 ? 16 : tier.minkc, H.na)) break;
         const int maxent = layout_entries(H, rs, kcc, rslot, cslot);
@@ -389,7 +390,16 @@ extern "C" {
 
 const char* sg_last_error(void) { return g_last_error.c_str(); }
 
+namespace {
+int setup_impl(const sg_problem* prob, const double* f_nodal, int force_kc, sg_handle** out);
+}
+
 int sg_setup(const sg_problem* prob, const double* f_nodal, sg_handle** out) {
+  return setup_impl(prob, f_nodal, 0, out);
+}
+
+namespace {
+int setup_impl(const sg_problem* prob, const double* f_nodal, int force_kc, sg_handle** out) {
   if (!prob || !out) return fail(SG_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
   try {
@@ -438,7 +448,7 @@ int sg_setup(const sg_problem* prob, const double* f_nodal, sg_handle** out) {
       if (!std::isfinite(v)) throw Error(SG_ERR_INVALID_ARG, "non-finite forcing");
     std::vector<int> all(H->P);
     std::iota(all.begin(), all.end(), 0);
-    H->full = build_rowset(*H, all, all);
+    H->full = build_rowset(*H, all, all, force_kc);
     for (int g = 0; g < 4; ++g) {
       FSHost& fh = H->fs[g];
       fh.splits = make_splits(H->Jp, g);
@@ -477,6 +487,8 @@ int sg_setup(const sg_problem* prob, const double* f_nodal, sg_handle** out) {
     return fail(SG_ERR_INTERNAL, e.what());
   }
 }
+
+}  // namespace
 
 int sg_sizes(const sg_handle* h, int64_t* P, int64_t* N_h, int64_t* n_a, int64_t* nnz_G) {
   if (!h) return fail(SG_ERR_INVALID_ARG, "null handle");
@@ -902,5 +914,690 @@ int sg_export(sg_handle* h, int what, int level, double* out, size_t count) {
 }
 
 void sg_destroy(sg_handle* h) { delete h; }
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched solves: many instances of uneven size advanced in lockstep by
+// persistent kernels over device work-item tables; one Arnoldi step of every
+// instance and the restart step are each captured once in a HIP graph.
+// ===========================================================================
+#include <fstream>
+#include <map>
+#include <sstream>
+
+namespace {
+
+struct KPtr {
+  double *V, *w, *z, *t, *partial, *H, *cs, *sn, *g, *y, *hv;
+  int* ident;
+  int nblk;
+};
+
+struct LaunchRec {
+  int kind;       // BK_*
+  int64_t off;    // offset of the work items in the item array
+  int count;      // work items
+  int gate;       // 0: instances in the current cycle, 1: instances not done
+  int a0, a1, a2, a3, a4;
+  double d0, d1;
+  size_t lds;
+};
+
+enum {
+  BK_APPLY = 0, BK_FIXUP, BK_VDOWN, BK_VUP, BK_VCOARSE, BK_GATHER, BK_VEC, BK_DOT, BK_REDUCE,
+  BK_GIVENS, BK_SOLVE, BK_INIT
+};
+
+struct Plan {
+  std::vector<BItem> items;
+  std::vector<LaunchRec> step, restart, start;
+  std::vector<BInst> inst;
+  hipGraphExec_t gstep = nullptr, grestart = nullptr;
+};
+
+}  // namespace
+
+struct sg_batch {
+  std::vector<sg_handle*> h;
+  int count = 0, restart = 0;
+  bool bound = false;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::vector<int64_t> voff;
+  std::vector<KPtr> kp;
+  BInst* dI = nullptr;
+  BState* dS = nullptr;
+  BItem* dItems = nullptr;
+  size_t item_cap = 0;
+  BState* hS = nullptr;  // pinned
+  std::map<int, Plan> plans;
+  ~sg_batch() {
+    for (auto& kv : plans) {
+      if (kv.second.gstep) (void)hipGraphExecDestroy(kv.second.gstep);
+      if (kv.second.grestart) (void)hipGraphExecDestroy(kv.second.grestart);
+    }
+    for (auto* x : h) sg_destroy(x);
+    if (hS) (void)hipHostFree(hS);
+  }
+};
+
+namespace {
+
+constexpr size_t kBatchItemCap = 1 << 24;  // work items of all tables of one plan
+
+int cdivi(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+size_t batch_layout(sg_batch& B, char* base) {
+  Carver c{base};
+  B.kp.assign(B.count, KPtr{});
+  for (int i = 0; i < B.count; ++i) {
+    sg_handle& H = *B.h[i];
+    const size_t hb = sg_workspace_bytes(&H);
+    char* hbase = c.take<char>(hb);
+    if (base) {
+      H.ws = hbase;
+      H.ws_bytes = hb;
+    }
+  }
+  for (int i = 0; i < B.count; ++i) {
+    const sg_handle& H = *B.h[i];
+    const int64_t Nv = (int64_t)H.P * H.Nh;
+    const int m = B.restart;
+    KPtr& k = B.kp[i];
+    k.nblk = dot_blocks(Nv);
+    k.V = c.take<double>((size_t)(m + 1) * Nv);
+    k.w = c.take<double>(Nv);
+    k.z = c.take<double>(Nv);
+    k.t = c.take<double>(Nv);
+    k.partial = c.take<double>((size_t)k.nblk * (m + 1));
+    k.H = c.take<double>((size_t)(m + 1) * m);
+    k.cs = c.take<double>(m);
+    k.sn = c.take<double>(m);
+    k.g = c.take<double>(m + 1);
+    k.y = c.take<double>(m + 1);
+    k.hv = c.take<double>(2 * (size_t)(m + 1) + 2);
+    k.ident = c.take<int>(H.P);
+  }
+  B.dI = c.take<BInst>(B.count);
+  B.dS = c.take<BState>(B.count);
+  B.dItems = c.take<BItem>(kBatchItemCap);
+  B.item_cap = kBatchItemCap;
+  return c.off;
+}
+
+// Builds the descriptors, work-item tables and launch sequences for one
+// preconditioner (mean-based, or field split with a grouping).
+Plan build_plan(sg_batch& B, int pc_kind, int grouping, const double* F, double* u) {
+  Plan pl;
+  const int m = B.restart;
+  int maxS = 0, maxfine = 0;
+  pl.inst.resize(B.count);
+  for (int i = 0; i < B.count; ++i) {
+    sg_handle& H = *B.h[i];
+    const DevPtrs& D = H.d;
+    const KPtr& k = B.kp[i];
+    BInst& I = pl.inst[i];
+    std::memset(&I, 0, sizeof(I));
+    I.n = H.n;
+    I.P = H.P;
+    I.na = H.na;
+    I.nlev = (int)D.L.size();
+    I.nfine = H.nfine;
+    I.m = m;
+    I.nblk = k.nblk;
+    I.Nh = H.Nh;
+    I.Nv = (int64_t)H.P * H.Nh;
+    I.a = D.a;
+    I.full = D.full;
+    if (I.nlev > kMaxLevelsB) throw Error(SG_ERR_UNSUPPORTED, "batch: too many grid levels");
+    for (int l = 0; l < I.nlev; ++l) {
+      I.L[l] = D.L[l];
+      I.mg_b[l] = D.mg_b[l];
+      I.mg_x[l] = D.mg_x[l];
+      I.mg_xa[l] = D.mg_xa[l];
+    }
+    if (pc_kind == SG_PC_MEAN) {
+      I.nsplit = 1;
+      I.split_idx[0] = k.ident;
+      I.split_m[0] = H.P;
+    } else {
+      const FSHost& fh = H.fs[grouping];
+      I.nsplit = (int)fh.splits.size();
+      if (I.nsplit > kMaxSplitsB) throw Error(SG_ERR_UNSUPPORTED, "batch: too many splits");
+      for (int s = 0; s < I.nsplit; ++s) {
+        I.split_idx[s] = D.fs[grouping].split_idx[s];
+        I.split_m[s] = (int)fh.splits[s].size();
+        if (s >= 1) I.part[s] = D.fs[grouping].partial[s];
+      }
+    }
+    I.edge = D.edge;
+    I.fsT = D.fsT;
+    I.fsX = D.fsX;
+    I.F = F + B.voff[i];
+    I.u = u + B.voff[i];
+    I.V = k.V;
+    I.w = k.w;
+    I.z = k.z;
+    I.t = k.t;
+    I.partial = k.partial;
+    I.H = k.H;
+    I.cs = k.cs;
+    I.sn = k.sn;
+    I.g = k.g;
+    I.y = k.y;
+    I.hv = k.hv;
+    maxS = std::max(maxS, I.nsplit);
+    maxfine = std::max(maxfine, I.nfine);
+  }
+  auto rec = [&](int kind, const std::vector<BItem>& t, int gate) {
+    LaunchRec r{};
+    r.kind = kind;
+    r.off = (int64_t)pl.items.size();
+    r.count = (int)t.size();
+    r.gate = gate;
+    pl.items.insert(pl.items.end(), t.begin(), t.end());
+    return r;
+  };
+  std::vector<BItem> tvec, tdot;
+  for (int i = 0; i < B.count; ++i) {
+    const BInst& I = pl.inst[i];
+    for (int c = 0; c < cdivi(I.Nv, kVecChunk); ++c) tvec.push_back({i, c});
+    for (int b = 0; b < I.nblk; ++b) tdot.push_back({i, b});
+  }
+  // operator launches for a row set (0 = full, s = partial of split s): one
+  // persistent launch per rows-per-wavefront class, then the edge fixup
+  auto apply_recs = [&](int rowset, int src, int rin, int dst, double beta, double sgn, int gate,
+                        std::vector<LaunchRec>& out) {
+    std::map<int, std::pair<std::vector<BItem>, size_t>> classes;
+    std::vector<BItem> tfix;
+    for (int i = 0; i < B.count; ++i) {
+      const BInst& I = pl.inst[i];
+      if (rowset > 0 && rowset >= I.nsplit) continue;
+      const RowSetDev& rs = rowset == 0 ? I.full : I.part[rowset];
+      auto& cl = classes[rs.rmax];
+      const int nt = I.n / kTileE;
+      for (int t = 0; t < nt * nt; ++t) cl.first.push_back({i, t});
+      cl.second = std::max(cl.second, apply_lds_bytes(rs.maxcols, rs.kc, rs.maxent));
+      const int64_t fixn = (int64_t)rs.nrows * nt * nt * 7;
+      for (int c = 0; c < cdivi(fixn, kVecChunk); ++c) tfix.push_back({i, c});
+    }
+    for (auto& kv : classes) {
+      LaunchRec r = rec(BK_APPLY, kv.second.first, gate);
+      r.a0 = kv.first;
+      r.a1 = rowset;
+      r.a2 = src;
+      r.a3 = rin;
+      r.a4 = dst;
+      r.d0 = beta;
+      r.d1 = sgn;
+      r.lds = kv.second.second;
+      out.push_back(r);
+    }
+    LaunchRec fx = rec(BK_FIXUP, tfix, gate);
+    fx.a0 = rowset;
+    fx.a1 = dst;
+    fx.d0 = sgn;
+    out.push_back(fx);
+  };
+  size_t coarse_lds = 0;
+  for (int i = 0; i < B.count; ++i) {
+    const BInst& I = pl.inst[i];
+    CoarseLevels cl{};
+    cl.nl = I.nlev - I.nfine;
+    for (int l = 0; l < cl.nl; ++l) cl.N[l] = I.L[I.nfine + l].N;
+    coarse_lds = std::max(coarse_lds, vcoarse_lds_bytes(cl));
+  }
+  // preconditioner src -> dst: forward block Gauss-Seidel over the splits
+  auto fs_recs = [&](int src, int dst, int gate, std::vector<LaunchRec>& out) {
+    for (int s = 0; s < maxS; ++s) {
+      std::vector<BItem> tsplit, tcoarse;
+      std::vector<std::vector<BItem>> tdepth(maxfine);
+      for (int i = 0; i < B.count; ++i) {
+        const BInst& I = pl.inst[i];
+        if (s >= I.nsplit) continue;
+        const int ms = I.split_m[s];
+        for (int c = 0; c < cdivi((int64_t)ms * I.Nh, kVecChunk); ++c) tsplit.push_back({i, c});
+        for (int md = 0; md < ms; ++md) tcoarse.push_back({i, md});
+        for (int d = 0; d < I.nfine; ++d) {
+          const int tpr = (I.L[d].n / 2 + 7) / 8;
+          for (int t = 0; t < tpr * tpr * ms; ++t) tdepth[d].push_back({i, t});
+        }
+      }
+      if (s == 0) {
+        LaunchRec g = rec(BK_GATHER, tsplit, gate);
+        g.a0 = s;
+        g.a1 = src;
+        g.a2 = 0;
+        out.push_back(g);
+      } else {
+        apply_recs(s, dst, src, BUF_FST, 1.0, -1.0, gate, out);
+      }
+      for (int d = 0; d < maxfine; ++d) {
+        LaunchRec r = rec(BK_VDOWN, tdepth[d], gate);
+        r.a0 = d;
+        r.a1 = s;
+        out.push_back(r);
+      }
+      LaunchRec c = rec(BK_VCOARSE, tcoarse, gate);
+      c.a0 = s;
+      c.lds = coarse_lds;
+      out.push_back(c);
+      for (int d = maxfine - 1; d >= 0; --d) {
+        LaunchRec r = rec(BK_VUP, tdepth[d], gate);
+        r.a0 = d;
+        r.a1 = s;
+        out.push_back(r);
+      }
+      LaunchRec g = rec(BK_GATHER, tsplit, gate);
+      g.a0 = s;
+      g.a1 = dst;
+      g.a2 = 1;
+      out.push_back(g);
+    }
+  };
+  auto vec = [&](int op, int x, int y, int o, double a, double b, int gate) {
+    LaunchRec r = rec(BK_VEC, tvec, gate);
+    r.a0 = op;
+    r.a1 = x;
+    r.a2 = y;
+    r.a3 = o;
+    r.d0 = a;
+    r.d1 = b;
+    return r;
+  };
+  auto dot = [&](int self_buf, int gate) {
+    LaunchRec r = rec(BK_DOT, tdot, gate);
+    r.a0 = self_buf;
+    return r;
+  };
+  auto reduce = [&](int which, int gate) {
+    LaunchRec r = rec(BK_REDUCE, {}, gate);
+    r.a0 = which;
+    return r;
+  };
+  auto simple = [&](int kind, int a0) {
+    LaunchRec r = rec(kind, {}, 0);
+    r.a0 = a0;
+    return r;
+  };
+  // first start: u = 0, t = F, beta = ||F||, V_0 = t / beta
+  pl.start.push_back(vec(BV_AXPBY, BUF_U, BUF_U, BUF_U, 0.0, 0.0, 1));
+  pl.start.push_back(vec(BV_AXPBY, BUF_F, BUF_F, BUF_T, 1.0, 0.0, 1));
+  pl.start.push_back(dot(BUF_T, 1));
+  pl.start.push_back(reduce(2, 1));
+  pl.start.push_back(simple(BK_INIT, 1));
+  pl.start.push_back(vec(BV_START, 0, 0, 0, 0, 0, 0));
+  // one Arnoldi step: z = P^{-1} v_j, w = K z, CGS2, Givens
+  fs_recs(BUF_VJ, BUF_Z, 0, pl.step);
+  apply_recs(0, BUF_Z, -1, BUF_W, 0.0, 1.0, 0, pl.step);
+  pl.step.push_back(dot(-1, 0));
+  pl.step.push_back(reduce(0, 0));
+  pl.step.push_back(vec(BV_UPDATE1, 0, 0, 0, 0, 0, 0));
+  pl.step.push_back(dot(-1, 0));
+  pl.step.push_back(reduce(1, 0));
+  pl.step.push_back(vec(BV_UPDATE2, 0, 0, 0, 0, 0, 0));
+  pl.step.push_back(dot(BUF_W, 0));
+  pl.step.push_back(reduce(2, 0));
+  pl.step.push_back(vec(BV_SCALE_NEXT, 0, 0, 0, 0, 0, 0));
+  pl.step.push_back(simple(BK_GIVENS, 0));
+  // restart: y, u += P^{-1}(V y), t = F - K u, beta, next cycle
+  pl.restart.push_back(simple(BK_SOLVE, 0));
+  pl.restart.push_back(vec(BV_COMBINE, 0, 0, 0, 0, 0, 1));
+  fs_recs(BUF_T, BUF_Z, 1, pl.restart);
+  pl.restart.push_back(vec(BV_AXPBY, BUF_Z, BUF_U, BUF_U, 1.0, 1.0, 1));
+  apply_recs(0, BUF_U, -1, BUF_W, 0.0, 1.0, 1, pl.restart);
+  pl.restart.push_back(vec(BV_AXPBY, BUF_F, BUF_W, BUF_T, 1.0, -1.0, 1));
+  pl.restart.push_back(dot(BUF_T, 1));
+  pl.restart.push_back(reduce(2, 1));
+  pl.restart.push_back(simple(BK_INIT, 0));
+  pl.restart.push_back(vec(BV_START, 0, 0, 0, 0, 0, 0));
+  if (pl.items.size() > B.item_cap) throw Error(SG_ERR_UNSUPPORTED, "batch: too many work items");
+  return pl;
+}
+
+void run_recs(sg_batch& B, hipStream_t s, const std::vector<LaunchRec>& recs, double tol) {
+  for (const LaunchRec& r : recs) {
+    const BItem* it = B.dItems + r.off;
+    switch (r.kind) {
+      case BK_APPLY:
+        launch_bapply(s, r.a0, r.lds, B.dI, B.dS, it, r.count, r.a1, r.a2, r.a3, r.a4, r.d0, r.d1,
+                      r.gate);
+        break;
+      case BK_FIXUP: launch_bfixup(s, B.dI, B.dS, it, r.count, r.a0, r.a1, r.d0, r.gate); break;
+      case BK_VDOWN: launch_bvdown(s, B.dI, B.dS, it, r.count, r.a0, r.a1, r.gate); break;
+      case BK_VUP: launch_bvup(s, B.dI, B.dS, it, r.count, r.a0, r.a1, r.gate); break;
+      case BK_VCOARSE: launch_bvcoarse(s, r.lds, B.dI, B.dS, it, r.count, r.a0, r.gate); break;
+      case BK_GATHER: launch_bgather(s, B.dI, B.dS, it, r.count, r.a0, r.a1, r.a2, r.gate); break;
+      case BK_VEC:
+        launch_bvec(s, B.dI, B.dS, it, r.count, r.a0, r.a1, r.a2, r.a3, r.d0, r.d1, r.gate);
+        break;
+      case BK_DOT: launch_bmultidot(s, B.dI, B.dS, it, r.count, r.a0, r.gate); break;
+      case BK_REDUCE: launch_breduce(s, B.dI, B.dS, B.count, r.a0, r.gate); break;
+      case BK_GIVENS: launch_bgivens(s, B.dI, B.dS, B.count); break;
+      case BK_SOLVE: launch_bsolve(s, B.dI, B.dS, B.count); break;
+      case BK_INIT: launch_binit(s, B.dI, B.dS, B.count, r.a0, tol); break;
+      default: throw Error(SG_ERR_INTERNAL, "batch: unknown launch");
+    }
+  }
+}
+
+hipGraphExec_t capture(sg_batch& B, hipStream_t s, const std::vector<LaunchRec>& recs,
+                       double tol) {
+  hipGraph_t g = nullptr;
+  SG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  try {
+    run_recs(B, s, recs, tol);
+  } catch (...) {
+    (void)hipStreamEndCapture(s, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  SG_HIP(hipStreamEndCapture(s, &g));
+  hipGraphExec_t ex = nullptr;
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess)
+    throw Error(SG_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+  return ex;
+}
+
+// ---- autotuner: coefficient chunk size (the staging tile depth) of the apply --
+std::string tune_cache_path() {
+  const char* p = getenv("SG_AUTOTUNE_CACHE");
+  if (p && *p) return p;
+  const char* home = getenv("HOME");
+  return std::string(home ? home : "/tmp") + "/.sgfs_autotune.txt";
+}
+
+std::map<std::string, int> tune_load() {
+  std::map<std::string, int> m;
+  std::ifstream f(tune_cache_path());
+  std::string key;
+  int kc;
+  while (f >> key >> kc) m[key] = kc;
+  return m;
+}
+
+void tune_store(const std::map<std::string, int>& m) {
+  std::ofstream f(tune_cache_path());
+  for (auto& kv : m) f << kv.first << ' ' << kv.second << '\n';
+}
+
+std::string tune_key(const sg_problem& p) {
+  hipDeviceProp_t prop;
+  std::string arch = "gfx";
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    arch = prop.gcnArchName;
+  for (char& c : arch)
+    if (c == ':' || c == ' ') c = '_';
+  std::ostringstream o;
+  o << arch << "_n" << p.n << "_M" << p.M << "_p" << p.p << "_q" << p.q;
+  return o.str();
+}
+
+// Times the operator apply of one problem class for each candidate chunk size
+// on scratch device memory; returns the fastest (0 if none could be timed).
+int tune_apply(const sg_problem& prob, float* best_ms_out) {
+  const int cands[] = {16, 32, 48, 64};
+  int best = 0;
+  float best_ms = 1e30f;
+  for (int kc : cands) {
+    sg_handle* h = nullptr;
+    if (setup_impl(&prob, nullptr, kc, &h) != SG_OK) continue;
+    std::unique_ptr<sg_handle> hold(h);
+    if (h->full.kc != kc) continue;
+    const size_t wb = sg_workspace_bytes(h);
+    const int64_t Nv = (int64_t)h->P * h->Nh;
+    void* ws = nullptr;
+    double* v = nullptr;
+    if (hipMalloc(&ws, wb + 256) != hipSuccess) continue;
+    if (hipMalloc((void**)&v, 2 * Nv * sizeof(double)) != hipSuccess) {
+      (void)hipFree(ws);
+      continue;
+    }
+    char* aligned =
+        reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+    float ms = 1e30f;
+    if (sg_bind(h, aligned, wb, nullptr) == SG_OK &&
+        hipMemset(v, 0, 2 * Nv * sizeof(double)) == hipSuccess) {
+      hipEvent_t e0, e1;
+      if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+        (void)sg_apply(h, v, v + Nv, nullptr);
+        (void)hipEventRecord(e0, nullptr);
+        for (int r = 0; r < 5; ++r) (void)sg_apply(h, v, v + Nv, nullptr);
+        (void)hipEventRecord(e1, nullptr);
+        if (hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+      }
+    }
+    (void)hipDeviceSynchronize();
+    (void)hipFree(v);
+    (void)hipFree(ws);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = kc;
+    }
+  }
+  if (best_ms_out) *best_ms_out = best_ms / 5;
+  return best;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sg_autotune_apply(const sg_problem* prob, int32_t* best_kc, float* best_ms) {
+  if (!prob || !best_kc) return fail(SG_ERR_INVALID_ARG, "null argument");
+  try {
+    validate(*prob);
+    *best_kc = tune_apply(*prob, best_ms);
+    return *best_kc > 0 ? SG_OK : fail(SG_ERR_HIP, "no candidate could be timed");
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  }
+}
+
+int sg_batch_create(int32_t count, const sg_problem* probs, const double* const* f_nodal,
+                    int32_t autotune, sg_batch** out) {
+  if (!probs || !out || count < 1) return fail(SG_ERR_INVALID_ARG, "need count >= 1 and problems");
+  *out = nullptr;
+  try {
+    auto B = std::make_unique<sg_batch>();
+    B->count = count;
+    std::map<std::string, int> cache;
+    bool dirty = false;
+    if (autotune) cache = tune_load();
+    for (int i = 0; i < count; ++i) {
+      validate(probs[i]);
+      int kc = 0;
+      if (autotune) {
+        const std::string key = tune_key(probs[i]);
+        auto itc = cache.find(key);
+        if (itc != cache.end()) {
+          kc = itc->second;
+        } else {
+          kc = tune_apply(probs[i], nullptr);
+          cache[key] = kc;
+          dirty = true;
+        }
+      }
+      sg_handle* h = nullptr;
+      const double* f = f_nodal ? f_nodal[i] : nullptr;
+      int rc = setup_impl(&probs[i], f, kc, &h);
+      if (rc != SG_OK && kc != 0) rc = setup_impl(&probs[i], f, 0, &h);
+      if (rc != SG_OK) return rc;
+      B->h.push_back(h);
+    }
+    if (dirty) tune_store(cache);
+    B->voff.assign(count + 1, 0);
+    for (int i = 0; i < count; ++i) B->voff[i + 1] = B->voff[i] + (int64_t)B->h[i]->P * B->h[i]->Nh;
+    *out = B.release();
+    return SG_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  }
+}
+
+int sg_batch_layout(const sg_batch* b, int64_t* offsets, int32_t* chunk) {
+  if (!b || !offsets) return fail(SG_ERR_INVALID_ARG, "null argument");
+  for (int i = 0; i <= b->count; ++i) offsets[i] = b->voff[i];
+  if (chunk)
+    for (int i = 0; i < b->count; ++i) chunk[i] = b->h[i]->full.kc;
+  return SG_OK;
+}
+
+size_t sg_batch_workspace_bytes(const sg_batch* b, int32_t restart) {
+  if (!b || restart < 1 || restart > kMaxRestart) return 0;
+  sg_batch& B = const_cast<sg_batch&>(*b);
+  const int keep = B.restart;
+  std::vector<KPtr> kp = B.kp;
+  B.restart = restart;
+  const size_t n = batch_layout(B, nullptr);
+  B.restart = keep;
+  B.kp = kp;
+  return n;
+}
+
+int sg_batch_bind(sg_batch* b, int32_t restart, void* ws, size_t bytes, void* stream) {
+  if (!b || !ws) return fail(SG_ERR_INVALID_ARG, "null argument");
+  if (restart < 1 || restart > kMaxRestart) return fail(SG_ERR_INVALID_ARG, "restart out of range");
+  if (bytes < sg_batch_workspace_bytes(b, restart))
+    return fail(SG_ERR_WORKSPACE, "batch workspace too small");
+  if (reinterpret_cast<uintptr_t>(ws) % 256)
+    return fail(SG_ERR_WORKSPACE, "batch workspace must be 256-byte aligned");
+  try {
+    sg_batch& B = *b;
+    for (auto& kv : B.plans) {
+      if (kv.second.gstep) (void)hipGraphExecDestroy(kv.second.gstep);
+      if (kv.second.grestart) (void)hipGraphExecDestroy(kv.second.grestart);
+    }
+    B.plans.clear();
+    B.restart = restart;
+    B.ws = static_cast<char*>(ws);
+    B.ws_bytes = bytes;
+    batch_layout(B, B.ws);
+    for (int i = 0; i < B.count; ++i) {
+      int rc = sg_bind(B.h[i], B.h[i]->ws, B.h[i]->ws_bytes, stream);
+      if (rc != SG_OK) return rc;
+      std::vector<int> ident(B.h[i]->P);
+      std::iota(ident.begin(), ident.end(), 0);
+      SG_HIP(hipMemcpy(B.kp[i].ident, ident.data(), ident.size() * sizeof(int),
+                       hipMemcpyHostToDevice));
+    }
+    if (!B.hS) SG_HIP(hipHostMalloc((void**)&B.hS, sizeof(BState) * B.count, hipHostMallocDefault));
+    B.bound = true;
+    return SG_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  }
+}
+
+int sg_batch_rhs(sg_batch* b, double* F, void* stream) {
+  if (!b || !F) return fail(SG_ERR_INVALID_ARG, "null argument");
+  if (!b->bound) return fail(SG_ERR_NOT_BOUND, "batch not bound");
+  for (int i = 0; i < b->count; ++i) {
+    int rc = sg_rhs(b->h[i], F + b->voff[i], stream);
+    if (rc != SG_OK) return rc;
+  }
+  return SG_OK;
+}
+
+int sg_batch_handle(sg_batch* b, int32_t i, sg_handle** h) {
+  if (!b || !h || i < 0 || i >= b->count) return fail(SG_ERR_INVALID_ARG, "index out of range");
+  *h = b->h[i];
+  return SG_OK;
+}
+
+int sg_batch_solve(sg_batch* b, const sg_solve_opts* o, const double* F, double* u,
+                   sg_solve_info* infos, void* stream) {
+  if (!b || !o || !F || !u || !infos) return fail(SG_ERR_INVALID_ARG, "null argument");
+  if (!b->bound) return fail(SG_ERR_NOT_BOUND, "batch not bound");
+  if (o->restart != b->restart) return fail(SG_ERR_INVALID_ARG, "restart must match the bound value");
+  const int kind = o->pc & 0xff;
+  if ((kind != SG_PC_MEAN && kind != SG_PC_FS) || (o->pc & ~0xff))
+    return fail(SG_ERR_UNSUPPORTED, "batched solves take the mean-based or field-split preconditioner");
+  if (o->grouping < 0 || o->grouping > 3) return fail(SG_ERR_INVALID_ARG, "unknown grouping");
+  if (o->use_x0) return fail(SG_ERR_UNSUPPORTED, "batched solves start from zero");
+  if (!(o->tol > 0.0) || o->max_it < 1) return fail(SG_ERR_INVALID_ARG, "need tol > 0 and max_it >= 1");
+  try {
+    sg_batch& B = *b;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int key = kind * 16 + (kind == SG_PC_FS ? o->grouping : 0);
+    auto itp = B.plans.find(key);
+    if (itp != B.plans.end() && (itp->second.inst[0].F != F || itp->second.inst[0].u != u)) {
+      if (itp->second.gstep) (void)hipGraphExecDestroy(itp->second.gstep);
+      if (itp->second.grestart) (void)hipGraphExecDestroy(itp->second.grestart);
+      B.plans.erase(itp);
+      itp = B.plans.end();
+    }
+    if (itp == B.plans.end())
+      itp = B.plans.emplace(key, build_plan(B, kind, o->grouping, F, u)).first;
+    Plan& pl = itp->second;
+    // descriptors and work items, stream-ordered before any use
+    SG_HIP(hipMemcpyAsync(B.dI, pl.inst.data(), pl.inst.size() * sizeof(BInst),
+                          hipMemcpyHostToDevice, s));
+    SG_HIP(hipMemcpyAsync(B.dItems, pl.items.data(), pl.items.size() * sizeof(BItem),
+                          hipMemcpyHostToDevice, s));
+    for (int i = 0; i < B.count; ++i) {
+      BState st{};
+      st.max_it = o->max_it;
+      B.hS[i] = st;
+    }
+    SG_HIP(hipMemcpyAsync(B.dS, B.hS, sizeof(BState) * B.count, hipMemcpyHostToDevice, s));
+    SG_HIP(hipStreamSynchronize(s));
+    // one Arnoldi step and the restart are captured once per plan (needs a
+    // non-null stream; on the null stream the same sequences run eagerly)
+    const bool graphs = (s != nullptr);
+    if (graphs && !pl.gstep) {
+      pl.gstep = capture(B, s, pl.step, o->tol);
+      pl.grestart = capture(B, s, pl.restart, o->tol);
+    }
+    run_recs(B, s, pl.start, o->tol);
+    check_launch();
+    const int m = B.restart;
+    const int max_cycles = o->max_it + 1;
+    for (int cycle = 0; cycle < max_cycles; ++cycle) {
+      for (int j = 0; j < m; ++j) {
+        if (graphs) SG_HIP(hipGraphLaunch(pl.gstep, s));
+        else run_recs(B, s, pl.step, o->tol);
+        if ((j + 1) % 10 == 0 && j + 1 < m) {
+          SG_HIP(hipMemcpyAsync(B.hS, B.dS, sizeof(BState) * B.count, hipMemcpyDeviceToHost, s));
+          SG_HIP(hipStreamSynchronize(s));
+          bool any = false;
+          for (int i = 0; i < B.count; ++i) any = any || B.hS[i].active;
+          if (!any) break;
+        }
+      }
+      if (graphs) SG_HIP(hipGraphLaunch(pl.grestart, s));
+      else run_recs(B, s, pl.restart, o->tol);
+      SG_HIP(hipMemcpyAsync(B.hS, B.dS, sizeof(BState) * B.count, hipMemcpyDeviceToHost, s));
+      SG_HIP(hipStreamSynchronize(s));
+      check_launch();
+      bool all = true;
+      for (int i = 0; i < B.count; ++i) all = all && B.hS[i].done;
+      if (all) break;
+    }
+    for (int i = 0; i < B.count; ++i) {
+      const BState& st = B.hS[i];
+      sg_solve_info& inf = infos[i];
+      std::memset(&inf, 0, sizeof(inf));
+      inf.status = st.done ? st.status : SG_NOT_CONVERGED;
+      inf.iterations = st.it;
+      inf.restarts = st.restarts;
+      inf.relres = st.nF > 0 ? st.beta / st.nF : 0.0;
+      inf.relres_est = st.nF > 0 ? st.est / st.nF : 0.0;
+    }
+    return SG_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return fail(SG_ERR_INTERNAL, e.what());
+  }
+}
+
+void sg_batch_destroy(sg_batch* b) { delete b; }
 
 }  // extern "C"

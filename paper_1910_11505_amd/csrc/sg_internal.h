@@ -151,6 +151,66 @@ void launch_scale_by_inv_norm(hipStream_t s, const double* w, const double* nrm2
 void launch_axpby(hipStream_t s, double a, const double* x, double b, double* y, int64_t N);
 void launch_sub(hipStream_t s, const double* a, const double* b, double* out, int64_t N);
 
+// ---- batched solves (sg_batch.cpp, batched kernels in sg_kernels.hip) ------
+constexpr int kMaxSplitsB = 12;
+constexpr int kMaxLevelsB = 12;
+
+// buffers a batched kernel can address by id (resolved per instance on device)
+enum BufId { BUF_F = 0, BUF_U, BUF_VJ, BUF_VJ1, BUF_V0, BUF_W, BUF_Z, BUF_T, BUF_FST, BUF_FSX };
+
+struct BInst {  // one instance of a batch, device-resident
+  int n, P, na, nlev, nfine, nsplit, m, nblk;
+  int64_t Nh, Nv;
+  const double* a;
+  RowSetDev full;
+  RowSetDev part[kMaxSplitsB];
+  const int* split_idx[kMaxSplitsB];
+  int split_m[kMaxSplitsB];
+  Level L[kMaxLevelsB];
+  double* mg_b[kMaxLevelsB];
+  double* mg_x[kMaxLevelsB];
+  double* mg_xa[kMaxLevelsB];
+  double *edge, *fsT, *fsX;
+  const double* F;
+  double *u, *V, *w, *z, *t;
+  double *partial, *H, *cs, *sn, *g, *y, *hv;  // hv: h1 (m+1), h2 (m+1), nrm
+};
+
+struct BState {  // per-instance solver state, device-resident
+  int j, active, done, kdone, it, restarts, status, max_it;
+  double beta, nF, est, target;
+};
+
+struct BItem {  // one work item of a persistent batched kernel
+  int inst, local;
+};
+
+// gate: 0 = instances still in the current Arnoldi cycle, 1 = instances not done
+constexpr int kVecChunk = 4096;     // elements per item of the batched vector kernels
+void launch_bapply(hipStream_t s, int rmax, size_t lds, const BInst* I, const BState* st,
+                   const BItem* items, int nitems, int rowset, int src, int rin, int dst,
+                   double beta, double sgn, int gate);
+void launch_bfixup(hipStream_t s, const BInst* I, const BState* st, const BItem* items, int nitems,
+                   int rowset, int dst, double sgn, int gate);
+void launch_bvdown(hipStream_t s, const BInst* I, const BState* st, const BItem* items, int nitems,
+                   int depth, int split, int gate);
+void launch_bvup(hipStream_t s, const BInst* I, const BState* st, const BItem* items, int nitems,
+                 int depth, int split, int gate);
+void launch_bvcoarse(hipStream_t s, size_t lds, const BInst* I, const BState* st,
+                     const BItem* items, int nitems, int split, int gate);
+void launch_bgather(hipStream_t s, const BInst* I, const BState* st, const BItem* items,
+                    int nitems, int split, int buf, int scatter, int gate);
+void launch_bvec(hipStream_t s, const BInst* I, const BState* st, const BItem* items, int nitems,
+                 int op, int x, int y, int out, double a, double b, int gate);
+void launch_bmultidot(hipStream_t s, const BInst* I, const BState* st, const BItem* items,
+                      int nitems, int self_buf, int gate);
+void launch_breduce(hipStream_t s, const BInst* I, const BState* st, int count, int which,
+                    int gate);
+void launch_bgivens(hipStream_t s, const BInst* I, BState* st, int count);
+void launch_bsolve(hipStream_t s, const BInst* I, const BState* st, int count);
+void launch_binit(hipStream_t s, const BInst* I, BState* st, int count, int first, double tol);
+enum BVecOp { BV_AXPBY = 0, BV_UPDATE1, BV_UPDATE2, BV_SCALE_NEXT, BV_COMBINE, BV_START };
+
 // learned stage (sg_cnn.hip)
 void cnn_apply_sg(sg_cnn* C, hipStream_t s, const double* v, double sigma, double* c,
                   double* scratch_partial, int nblk);

@@ -249,7 +249,8 @@ __device__ __forceinline__ void apply_tile(double* smem, int tile, int n, int na
   double ax[RMAX], ay[RMAX];
 #pragma unroll
   for (int r = 0; r < RMAX; ++r) ax[r] = ay[r] = 0.0;
-  const int* wrows = rs.wrows + wave * RMAX;
+  // RMAX is the compiled bound; the row set's own per-wave stride is rs.rmax <= RMAX
+  const int* wrows = rs.wrows + wave * rs.rmax;
   constexpr int kPre = kMaxChunk * kTileQ / 256;
   double pre[kPre];
   auto prefetch = [&](int ch) {
@@ -323,7 +324,7 @@ __device__ __forceinline__ void apply_tile(double* smem, int tile, int n, int na
       if (ch + 1 < nchunk) prefetch(ch + 1);
 #pragma unroll
       for (int r = 0; r < RMAX; ++r) {
-        const int slot = wrows[r];
+        const int slot = (r < rs.rmax) ? wrows[r] : -1;
         if (slot >= 0) {
           const int b = pptr[ch * (nrows + 1) + slot] - cb;
           const int e = pptr[ch * (nrows + 1) + slot + 1] - cb;
@@ -363,7 +364,7 @@ __device__ __forceinline__ void apply_tile(double* smem, int tile, int n, int na
   double* sE = sA + wave * kTileQ;
 #pragma unroll
   for (int r = 0; r < RMAX; ++r) {
-    const int slot = wrows[r];
+    const int slot = (r < rs.rmax) ? wrows[r] : -1;
     if (slot >= 0) {
       double c[4];
 #pragma unroll
@@ -811,16 +812,26 @@ __device__ __forceinline__ const double* sel_stencil(const double* S, int64_t N,
 
 }  // namespace
 
-__global__ __launch_bounds__(256) void vdown_kernel(const double* __restrict__ Sbase, int nf,
-                                                    int64_t Nf, int64_t Nc, const int* smode,
-                                                    const double* __restrict__ bglob,
-                                                    double* __restrict__ x2out,
-                                                    double* __restrict__ bcout, double omega) {
-  __shared__ double sb[kDE * kDE], sd[kDE * kDE], sx1[kDE * kDE], sx2[kDE * kDE], sr[kDE * kDE];
+struct VDownLds {
+  double sb[kDE * kDE], sd[kDE * kDE], sx1[kDE * kDE], sx2[kDE * kDE], sr[kDE * kDE];
+};
+
+// One (tile, mode) item of the down sweep; ends with a barrier so the LDS can
+// be reused by the next item of a persistent workgroup.
+__device__ __forceinline__ void vdown_tile(VDownLds& L, int tile, int mode,
+                                           const double* __restrict__ Sbase, int nf, int64_t Nf,
+                                           int64_t Nc, const int* smode,
+                                           const double* __restrict__ bglob,
+                                           double* __restrict__ x2out,
+                                           double* __restrict__ bcout, double omega) {
+  double* sb = L.sb;
+  double* sd = L.sd;
+  double* sx1 = L.sx1;
+  double* sx2 = L.sx2;
+  double* sr = L.sr;
   const int mf = nf - 1, nc = nf / 2, mc = nc - 1;
   const int tpr = (nc + kTC - 1) / kTC;
-  const int tx = blockIdx.x % tpr, ty = blockIdx.x / tpr;
-  const int mode = blockIdx.y;
+  const int tx = tile % tpr, ty = tile / tpr;
   const double* S = sel_stencil(Sbase, Nf, smode, mode);
   const double* b = bglob + (int64_t)mode * Nf;
   const int I0 = 1 + tx * kTC, J0 = 1 + ty * kTC;
@@ -885,19 +896,38 @@ __global__ __launch_bounds__(256) void vdown_kernel(const double* __restrict__ S
       bcout[(int64_t)mode * Nc + (int64_t)(J - 1) * mc + (I - 1)] = acc;
     }
   }
+  __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void vup_kernel(const double* __restrict__ Sbase, int nf,
-                                                  int64_t Nf, int64_t Nc, const int* smode,
-                                                  const double* __restrict__ bglob,
-                                                  const double* __restrict__ x2glob,
-                                                  const double* __restrict__ xcglob,
-                                                  double* __restrict__ xout, double omega) {
-  __shared__ double sb[kUE * kUE], sd[kUE * kUE], sx3[kUE * kUE], sx4[kUE * kUE], sc[kCE * kCE];
+__global__ __launch_bounds__(256) void vdown_kernel(const double* __restrict__ Sbase, int nf,
+                                                    int64_t Nf, int64_t Nc, const int* smode,
+                                                    const double* __restrict__ bglob,
+                                                    double* __restrict__ x2out,
+                                                    double* __restrict__ bcout, double omega) {
+  __shared__ VDownLds L;
+  vdown_tile(L, blockIdx.x, blockIdx.y, Sbase, nf, Nf, Nc, smode, bglob, x2out, bcout, omega);
+}
+
+struct VUpLds {
+  double sb[kUE * kUE], sd[kUE * kUE], sx3[kUE * kUE], sx4[kUE * kUE], sc[kCE * kCE];
+};
+
+// One (tile, mode) item of the up sweep; ends with a barrier.
+__device__ __forceinline__ void vup_tile(VUpLds& L, int tile, int mode,
+                                         const double* __restrict__ Sbase, int nf, int64_t Nf,
+                                         int64_t Nc, const int* smode,
+                                         const double* __restrict__ bglob,
+                                         const double* __restrict__ x2glob,
+                                         const double* __restrict__ xcglob,
+                                         double* __restrict__ xout, double omega) {
+  double* sb = L.sb;
+  double* sd = L.sd;
+  double* sx3 = L.sx3;
+  double* sx4 = L.sx4;
+  double* sc = L.sc;
   const int mf = nf - 1, nc = nf / 2, mc = nc - 1;
   const int tpr = (nc + kTC - 1) / kTC;
-  const int tx = blockIdx.x % tpr, ty = blockIdx.x / tpr;
-  const int mode = blockIdx.y;
+  const int tx = tile % tpr, ty = tile / tpr;
   const double* S = sel_stencil(Sbase, Nf, smode, mode);
   const double* b = bglob + (int64_t)mode * Nf;
   const double* x2 = x2glob + (int64_t)mode * Nf;
@@ -963,6 +993,17 @@ __global__ __launch_bounds__(256) void vup_kernel(const double* __restrict__ Sba
       xout[(int64_t)mode * Nf + g] = sx4[e] + omega * (sb[e] - ax) / sd[e];
     }
   }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void vup_kernel(const double* __restrict__ Sbase, int nf,
+                                                  int64_t Nf, int64_t Nc, const int* smode,
+                                                  const double* __restrict__ bglob,
+                                                  const double* __restrict__ x2glob,
+                                                  const double* __restrict__ xcglob,
+                                                  double* __restrict__ xout, double omega) {
+  __shared__ VUpLds L;
+  vup_tile(L, blockIdx.x, blockIdx.y, Sbase, nf, Nf, Nc, smode, bglob, x2glob, xcglob, xout, omega);
 }
 
 void launch_vdown(hipStream_t s, const Level& Lf, const Level& Lc, int modes, const int* smode,
@@ -996,11 +1037,10 @@ __device__ __forceinline__ double lds_stencil(const double* S, int N, int m, int
 
 }  // namespace
 
-__global__ __launch_bounds__(256) void vcoarse_kernel(CoarseLevels cl, const int* smode,
-                                                      const double* __restrict__ bglob,
-                                                      double* __restrict__ xglob, double omega) {
-  extern __shared__ double lds[];
-  const int mode = blockIdx.x;
+// One mode of the LDS-resident coarse V-cycle; ends with a barrier.
+__device__ __forceinline__ void vcoarse_mode(double* lds, int mode, const CoarseLevels& cl,
+                                             const int* smode, const double* __restrict__ bglob,
+                                             double* __restrict__ xglob, double omega) {
   const int tid = threadIdx.x;
   const int nth = blockDim.x;
   int off[kMaxCoarseLevels];
@@ -1087,6 +1127,14 @@ __global__ __launch_bounds__(256) void vcoarse_kernel(CoarseLevels cl, const int
     const int N = (int)cl.N[0];
     for (int e = tid; e < N; e += nth) xglob[(int64_t)mode * N + e] = X[e];
   }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void vcoarse_kernel(CoarseLevels cl, const int* smode,
+                                                      const double* __restrict__ bglob,
+                                                      double* __restrict__ xglob, double omega) {
+  extern __shared__ double lds[];
+  vcoarse_mode(lds, blockIdx.x, cl, smode, bglob, xglob, omega);
 }
 
 size_t vcoarse_lds_bytes(const CoarseLevels& cl) {
@@ -1117,6 +1165,437 @@ void launch_diag_coeff(hipStream_t s, int n, int cnt, const int* ks, const doubl
                        const double* a, double* c) {
   const int64_t Nq = (int64_t)4 * n * n;
   hipLaunchKernelGGL(diag_coeff_kernel, dim3(cdiv(Nq, 256)), dim3(256), 0, s, Nq, cnt, ks, vs, a, c);
+}
+
+}  // namespace sg
+
+// ===========================================================================
+// Batched, persistent versions for many instances in one launch.  Every
+// kernel walks a table of (instance, local item) work items with a grid-stride
+// loop (items are assigned to workgroups round-robin, so results do not depend
+// on scheduling), reads the instance's descriptor, and skips instances that
+// are gated off (finished, or out of the current Arnoldi cycle).  Per-instance
+// solver state (the Arnoldi index j, the Givens rotations, the convergence
+// flags) lives on the device, so one Arnoldi step of every instance is a fixed
+// launch sequence that can be captured once in a HIP graph and replayed.
+// ===========================================================================
+namespace sg {
+
+namespace {
+
+__device__ __forceinline__ bool gated(const BState& S, int gate) {
+  return gate == 0 ? (S.active == 0) : (S.done != 0);
+}
+
+__device__ __forceinline__ double* bbuf(const BInst& I, const BState& S, int id) {
+  switch (id) {
+    case BUF_F: return const_cast<double*>(I.F);
+    case BUF_U: return I.u;
+    case BUF_VJ: return I.V + (int64_t)S.j * I.Nv;
+    case BUF_VJ1: return I.V + (int64_t)(S.j + 1) * I.Nv;
+    case BUF_V0: return I.V;
+    case BUF_W: return I.w;
+    case BUF_Z: return I.z;
+    case BUF_T: return I.t;
+    case BUF_FST: return I.fsT;
+    default: return I.fsX;
+  }
+}
+
+}  // namespace
+
+template <int RMAX>
+__global__ __launch_bounds__(256) void bapply_kernel(const BInst* __restrict__ Is,
+                                                     const BState* __restrict__ Ss,
+                                                     const BItem* __restrict__ items, int nitems,
+                                                     int rowset, int src, int rin, int dst,
+                                                     double beta, double sgn, int gate) {
+  extern __shared__ double smem[];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BItem w = items[it];
+    const BInst& I = Is[w.inst];
+    const BState& S = Ss[w.inst];
+    if (gated(S, gate)) continue;
+    const RowSetDev& rs = rowset == 0 ? I.full : I.part[rowset];
+    apply_tile<RMAX>(smem, w.local, I.n, I.na, I.a, rs, bbuf(I, S, src), I.Nh,
+                     rin >= 0 ? bbuf(I, S, rin) : nullptr, beta, sgn, bbuf(I, S, dst), I.edge);
+  }
+}
+
+void launch_bapply(hipStream_t s, int rmax, size_t lds, const BInst* I, const BState* st,
+                   const BItem* items, int nitems, int rowset, int src, int rin, int dst,
+                   double beta, double sgn, int gate) {
+  if (nitems <= 0) return;
+  const int per_cu = std::max(1, (int)((160 * 1024) / std::max<size_t>(lds, 1)));
+  const int grid = std::min(nitems, 256 * std::min(per_cu, 4));
+#define SG_BAPPLY(R)                                                                       \
+  case R:                                                                                  \
+    hipLaunchKernelGGL(bapply_kernel<R>, dim3(grid), dim3(256), lds, s, I, st, items, nitems, \
+                       rowset, src, rin, dst, beta, sgn, gate);                            \
+    break;
+  switch (rmax) {
+    SG_BAPPLY(1) SG_BAPPLY(2) SG_BAPPLY(4) SG_BAPPLY(8) SG_BAPPLY(16) SG_BAPPLY(32) SG_BAPPLY(64)
+    default: throw Error(SG_ERR_INTERNAL, "batched apply: unsupported rows per wavefront");
+  }
+#undef SG_BAPPLY
+}
+
+// fixup items: local = chunk of kVecChunk fixup points of the row set
+__global__ void bfixup_kernel(const BInst* __restrict__ Is, const BState* __restrict__ Ss,
+                              const BItem* __restrict__ items, int nitems, int rowset, int dst,
+                              double sgn, int gate) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BItem w = items[it];
+    const BInst& I = Is[w.inst];
+    const BState& S = Ss[w.inst];
+    if (gated(S, gate)) continue;
+    const RowSetDev& rs = rowset == 0 ? I.full : I.part[rowset];
+    const int nt = I.n / kTileE;
+    const int64_t total = (int64_t)rs.nrows * nt * nt * 7;
+    const int64_t g0 = (int64_t)w.local * kVecChunk;
+    for (int64_t g = g0 + threadIdx.x; g < std::min<int64_t>(total, g0 + kVecChunk); g += blockDim.x)
+      apply_fixup_item(g, I.n, sgn, I.edge, bbuf(I, S, dst), I.Nh);
+  }
+}
+
+void launch_bfixup(hipStream_t s, const BInst* I, const BState* st, const BItem* items, int nitems,
+                   int rowset, int dst, double sgn, int gate) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(bfixup_kernel, dim3(std::min(nitems, 2048)), dim3(256), 0, s, I, st, items,
+                     nitems, rowset, dst, sgn, gate);
+}
+
+// V-cycle items: local = tile * m + mode on the instance's level `depth`
+__global__ __launch_bounds__(256) void bvdown_kernel(const BInst* __restrict__ Is,
+                                                     const BState* __restrict__ Ss,
+                                                     const BItem* __restrict__ items, int nitems,
+                                                     int depth, int split, int gate) {
+  __shared__ VDownLds L;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BItem w = items[it];
+    const BInst& I = Is[w.inst];
+    if (gated(Ss[w.inst], gate)) continue;
+    const int m = I.split_m[split];
+    const Level& Lf = I.L[depth];
+    const Level& Lc = I.L[depth + 1];
+    const double* b = depth == 0 ? I.fsT : I.mg_b[depth];
+    vdown_tile(L, w.local / m, w.local % m, Lf.S, Lf.n, Lf.N, Lc.N, nullptr, b, I.mg_xa[depth],
+               I.mg_b[depth + 1], 8.0 / 9.0);
+  }
+}
+
+__global__ __launch_bounds__(256) void bvup_kernel(const BInst* __restrict__ Is,
+                                                   const BState* __restrict__ Ss,
+                                                   const BItem* __restrict__ items, int nitems,
+                                                   int depth, int split, int gate) {
+  __shared__ VUpLds L;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BItem w = items[it];
+    const BInst& I = Is[w.inst];
+    if (gated(Ss[w.inst], gate)) continue;
+    const int m = I.split_m[split];
+    const Level& Lf = I.L[depth];
+    const Level& Lc = I.L[depth + 1];
+    const double* b = depth == 0 ? I.fsT : I.mg_b[depth];
+    double* x = depth == 0 ? I.fsX : I.mg_x[depth];
+    vup_tile(L, w.local / m, w.local % m, Lf.S, Lf.n, Lf.N, Lc.N, nullptr, b, I.mg_xa[depth],
+             I.mg_x[depth + 1], x, 8.0 / 9.0);
+  }
+}
+
+void launch_bvdown(hipStream_t s, const BInst* I, const BState* st, const BItem* items, int nitems,
+                   int depth, int split, int gate) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(bvdown_kernel, dim3(std::min(nitems, 2048)), dim3(256), 0, s, I, st, items,
+                     nitems, depth, split, gate);
+}
+
+void launch_bvup(hipStream_t s, const BInst* I, const BState* st, const BItem* items, int nitems,
+                 int depth, int split, int gate) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(bvup_kernel, dim3(std::min(nitems, 2048)), dim3(256), 0, s, I, st, items,
+                     nitems, depth, split, gate);
+}
+
+// coarse items: local = mode
+__global__ __launch_bounds__(256) void bvcoarse_kernel(const BInst* __restrict__ Is,
+                                                       const BState* __restrict__ Ss,
+                                                       const BItem* __restrict__ items,
+                                                       int nitems, int split, int gate) {
+  extern __shared__ double lds[];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BItem w = items[it];
+    const BInst& I = Is[w.inst];
+    if (gated(Ss[w.inst], gate)) continue;
+    CoarseLevels cl{};
+    cl.nl = I.nlev - I.nfine;
+    for (int l = 0; l < cl.nl; ++l) {
+      cl.n[l] = I.L[I.nfine + l].n;
+      cl.N[l] = I.L[I.nfine + l].N;
+      cl.S[l] = I.L[I.nfine + l].S;
+    }
+    const double* b = I.nfine == 0 ? I.fsT : I.mg_b[I.nfine];
+    double* x = I.nfine == 0 ? I.fsX : I.mg_x[I.nfine];
+    vcoarse_mode(lds, w.local, cl, nullptr, b, x, 8.0 / 9.0);
+  }
+}
+
+void launch_bvcoarse(hipStream_t s, size_t lds, const BInst* I, const BState* st,
+                     const BItem* items, int nitems, int split, int gate) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(bvcoarse_kernel, dim3(std::min(nitems, 2048)), dim3(256), lds, s, I, st,
+                     items, nitems, split, gate);
+}
+
+// gather (scatter = 0): fsT[t][node] = buf[idx[t]][node]; scatter: buf[idx[t]] = fsX[t]
+// items: local = chunk of kVecChunk elements of m * N_h
+__global__ void bgather_kernel(const BInst* __restrict__ Is, const BState* __restrict__ Ss,
+                               const BItem* __restrict__ items, int nitems, int split, int buf,
+                               int scatter, int gate) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BItem w = items[it];
+    const BInst& I = Is[w.inst];
+    const BState& S = Ss[w.inst];
+    if (gated(S, gate)) continue;
+    const int64_t total = (int64_t)I.split_m[split] * I.Nh;
+    const int* idx = I.split_idx[split];
+    double* full = bbuf(I, S, buf);
+    const int64_t g0 = (int64_t)w.local * kVecChunk;
+    for (int64_t g = g0 + threadIdx.x; g < std::min<int64_t>(total, g0 + kVecChunk); g += blockDim.x) {
+      const int t = (int)(g / I.Nh);
+      const int64_t f = (int64_t)idx[t] * I.Nh + (g - (int64_t)t * I.Nh);
+      if (scatter) full[f] = I.fsX[g];
+      else I.fsT[g] = full[f];
+    }
+  }
+}
+
+void launch_bgather(hipStream_t s, const BInst* I, const BState* st, const BItem* items,
+                    int nitems, int split, int buf, int scatter, int gate) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(bgather_kernel, dim3(std::min(nitems, 2048)), dim3(256), 0, s, I, st, items,
+                     nitems, split, buf, scatter, gate);
+}
+
+// vector operations on N_v-long vectors, items: local = chunk of kVecChunk
+__global__ void bvec_kernel(const BInst* __restrict__ Is, const BState* __restrict__ Ss,
+                            const BItem* __restrict__ items, int nitems, int op, int xb, int yb,
+                            int ob, double a, double b, int gate) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BItem w = items[it];
+    const BInst& I = Is[w.inst];
+    const BState& S = Ss[w.inst];
+    if (gated(S, gate)) continue;
+    const int64_t g0 = (int64_t)w.local * kVecChunk;
+    const int64_t g1 = std::min<int64_t>(I.Nv, g0 + kVecChunk);
+    const int m = I.m;
+    if (op == BV_AXPBY) {
+      const double* x = bbuf(I, S, xb);
+      const double* y = bbuf(I, S, yb);
+      double* o = bbuf(I, S, ob);
+      for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x)
+        o[g] = (b == 0.0) ? (a == 0.0 ? 0.0 : a * x[g]) : a * x[g] + b * y[g];
+    } else if (op == BV_UPDATE1 || op == BV_UPDATE2) {
+      const double* h = I.hv + (op == BV_UPDATE1 ? 0 : m + 1);
+      for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
+        double acc = 0.0;
+        for (int l = 0; l <= S.j; ++l) acc = fma(h[l], I.V[(int64_t)l * I.Nv + g], acc);
+        I.w[g] -= acc;
+      }
+    } else if (op == BV_SCALE_NEXT) {
+      const double nn = sqrt(I.hv[2 * m + 2]);
+      double* v = I.V + (int64_t)(S.j + 1) * I.Nv;
+      for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) v[g] = nn > 0.0 ? I.w[g] / nn : 0.0;
+    } else if (op == BV_COMBINE) {
+      for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
+        double acc = 0.0;
+        for (int l = 0; l < S.kdone; ++l) acc = fma(I.y[l], I.V[(int64_t)l * I.Nv + g], acc);
+        I.t[g] = acc;
+      }
+    } else {  // BV_START: V_0 = t / beta
+      for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) I.V[g] = I.t[g] / S.beta;
+    }
+  }
+}
+
+void launch_bvec(hipStream_t s, const BInst* I, const BState* st, const BItem* items, int nitems,
+                 int op, int x, int y, int out, double a, double b, int gate) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(bvec_kernel, dim3(std::min(nitems, 2048)), dim3(256), 0, s, I, st, items,
+                     nitems, op, x, y, out, a, b, gate);
+}
+
+// dots: items (inst, block b < nblk); self_buf < 0: V_l . w for l <= j, else buf . buf
+__global__ __launch_bounds__(256) void bmultidot_kernel(const BInst* __restrict__ Is,
+                                                        const BState* __restrict__ Ss,
+                                                        const BItem* __restrict__ items,
+                                                        int nitems, int self_buf, int gate) {
+  __shared__ double red[4];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BItem w = items[it];
+    const BInst& I = Is[w.inst];
+    const BState& S = Ss[w.inst];
+    if (gated(S, gate)) continue;
+    const int nblk = I.nblk;
+    const int64_t per = (I.Nv + nblk - 1) / nblk;
+    const int64_t lo = (int64_t)w.local * per;
+    const int64_t hi = std::min<int64_t>(I.Nv, lo + per);
+    const double* x = self_buf >= 0 ? bbuf(I, S, self_buf) : I.w;
+    const int nv = self_buf >= 0 ? 1 : S.j + 1;
+    for (int l = 0; l < nv; ++l) {
+      const double* v = self_buf >= 0 ? x : I.V + (int64_t)l * I.Nv;
+      double acc = 0.0;
+      for (int64_t i = lo + threadIdx.x; i < hi; i += 256) acc = fma(v[i], x[i], acc);
+      const double sm = block_sum(acc, red);
+      if (threadIdx.x == 0) I.partial[(int64_t)l * nblk + w.local] = sm;
+      __syncthreads();
+    }
+  }
+}
+
+void launch_bmultidot(hipStream_t s, const BInst* I, const BState* st, const BItem* items,
+                      int nitems, int self_buf, int gate) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(bmultidot_kernel, dim3(std::min(nitems, 2048)), dim3(256), 0, s, I, st, items,
+                     nitems, self_buf, gate);
+}
+
+// which: 0 -> h1[0..j], 1 -> h2[0..j], 2 -> nrm (one value); one workgroup per instance
+__global__ void breduce_kernel(const BInst* __restrict__ Is, const BState* __restrict__ Ss,
+                               int which, int gate) {
+  const BInst& I = Is[blockIdx.x];
+  const BState& S = Ss[blockIdx.x];
+  if (gated(S, gate)) return;
+  const int m = I.m;
+  const int nv = which == 2 ? 1 : S.j + 1;
+  double* out = I.hv + (which == 0 ? 0 : which == 1 ? m + 1 : 2 * m + 2);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int l = wave; l < nv; l += blockDim.x / 64) {
+    double acc = 0.0;
+    for (int b = lane; b < I.nblk; b += 64) acc += I.partial[(int64_t)l * I.nblk + b];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) out[l] = acc;
+  }
+}
+
+void launch_breduce(hipStream_t s, const BInst* I, const BState* st, int count, int which,
+                    int gate) {
+  hipLaunchKernelGGL(breduce_kernel, dim3(count), dim3(256), 0, s, I, st, which, gate);
+}
+
+// Hessenberg column, Givens rotations and the residual estimate of step j
+__global__ void bgivens_kernel(const BInst* __restrict__ Is, BState* __restrict__ Ss, int count) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const BInst& I = Is[k];
+  BState& S = Ss[k];
+  if (!S.active) return;
+  const int m = I.m, j = S.j;
+  double* H = I.H;  // (m + 1) x m, row-major
+  for (int i = 0; i <= j; ++i) H[i * m + j] = I.hv[i] + I.hv[m + 1 + i];
+  H[(j + 1) * m + j] = sqrt(I.hv[2 * m + 2]);
+  if (!isfinite(H[(j + 1) * m + j])) {
+    S.status = SG_BREAKDOWN;
+    S.kdone = j;
+    S.active = 0;
+    return;
+  }
+  for (int i = 0; i < j; ++i) {
+    const double t = I.cs[i] * H[i * m + j] + I.sn[i] * H[(i + 1) * m + j];
+    H[(i + 1) * m + j] = -I.sn[i] * H[i * m + j] + I.cs[i] * H[(i + 1) * m + j];
+    H[i * m + j] = t;
+  }
+  const double a = H[j * m + j], b = H[(j + 1) * m + j];
+  double c = 1.0, sn = 0.0;
+  if (b != 0.0) {
+    const double r = hypot(a, b);
+    c = a / r;
+    sn = b / r;
+  }
+  I.cs[j] = c;
+  I.sn[j] = sn;
+  H[j * m + j] = c * a + sn * b;
+  H[(j + 1) * m + j] = 0.0;
+  I.g[j + 1] = -sn * I.g[j];
+  I.g[j] = c * I.g[j];
+  S.it += 1;
+  S.est = fabs(I.g[j + 1]);
+  S.kdone = j + 1;
+  S.j = j + 1;
+  if (H[j * m + j] == 0.0) {
+    S.status = SG_BREAKDOWN;
+    S.kdone = j;
+    S.active = 0;
+  } else if (S.est <= S.target || S.it >= S.max_it || j + 1 == m) {
+    S.active = 0;
+  }
+}
+
+void launch_bgivens(hipStream_t s, const BInst* I, BState* st, int count) {
+  hipLaunchKernelGGL(bgivens_kernel, dim3((count + 63) / 64), dim3(64), 0, s, I, st, count);
+}
+
+// back substitution H y = g over the cycle's kdone columns
+__global__ void bsolve_kernel(const BInst* __restrict__ Is, const BState* __restrict__ Ss,
+                              int count) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const BInst& I = Is[k];
+  const BState& S = Ss[k];
+  if (S.done) return;
+  const int m = I.m;
+  for (int i = S.kdone - 1; i >= 0; --i) {
+    double acc = I.g[i];
+    for (int l = i + 1; l < S.kdone; ++l) acc -= I.H[i * m + l] * I.y[l];
+    I.y[i] = acc / I.H[i * m + i];
+  }
+}
+
+void launch_bsolve(hipStream_t s, const BInst* I, const BState* st, int count) {
+  hipLaunchKernelGGL(bsolve_kernel, dim3((count + 63) / 64), dim3(64), 0, s, I, st, count);
+}
+
+// cycle start: beta = ||t|| (norm squared in hv[2m+2]); finish or reset the cycle
+__global__ void binit_kernel(const BInst* __restrict__ Is, BState* __restrict__ Ss, int count,
+                             int first, double tol) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const BInst& I = Is[k];
+  BState& S = Ss[k];
+  if (S.done) return;
+  const int m = I.m;
+  const double beta = sqrt(I.hv[2 * m + 2]);
+  if (first) {
+    S.nF = beta;
+    S.target = tol * beta;
+    S.it = 0;
+    S.restarts = 0;
+    S.status = SG_NOT_CONVERGED;
+  } else {
+    S.restarts += 1;
+  }
+  S.beta = beta;
+  S.kdone = 0;
+  S.j = 0;
+  const bool broke = S.status == SG_BREAKDOWN;
+  if (S.nF == 0.0 || beta <= S.target) {
+    S.status = SG_CONVERGED;
+    S.done = 1;
+    S.active = 0;
+  } else if (!isfinite(beta) || broke || S.it >= S.max_it) {
+    S.status = (!isfinite(beta) || broke) ? SG_BREAKDOWN : SG_NOT_CONVERGED;
+    S.done = 1;
+    S.active = 0;
+  } else {
+    for (int i = 0; i <= m; ++i) I.g[i] = 0.0;
+    I.g[0] = beta;
+    S.active = 1;
+  }
+}
+
+void launch_binit(hipStream_t s, const BInst* I, BState* st, int count, int first, double tol) {
+  hipLaunchKernelGGL(binit_kernel, dim3((count + 63) / 64), dim3(64), 0, s, I, st, count, first, tol);
 }
 
 }  // namespace sg

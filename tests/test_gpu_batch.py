@@ -1,0 +1,95 @@
+"""Batched solves: many uneven instances advanced together by the persistent
+kernels under HIP-graph capture must reproduce the single-instance solver
+(same algorithm, same reduction trees: iteration counts equal, solutions to
+1e-12) and meet the FP64 true relative residual 1e-8 checked by the oracle."""
+import numpy as np
+import pytest
+
+import paper_1910_11505_amd as sg
+from paper_1910_11505_amd.binding import make_problem
+from synth import Problem, rhs_noisy
+
+from gpu_common import need_gpu, torch
+
+pytestmark = pytest.mark.gpu
+
+PROBS = [
+    Problem(n=16, M=2, p=2, q=4, cov="exp_l1", sigma=0.9, corr_len=0.5),
+    Problem(n=32, M=3, p=2, q=4, cov="exp_l1", sigma=0.4, corr_len=0.3),
+    Problem(n=16, M=1, p=3, q=6, cov="exp_l1", sigma=1.3, corr_len=0.8),
+    Problem(n=64, M=2, p=1, q=2, cov="exp_l1", sigma=0.6, corr_len=0.25),
+    Problem(n=32, M=4, p=2, q=4, cov="exp_l1", sigma=1.1, corr_len=0.6),
+    Problem(n=8, M=2, p=2, q=4, cov="exp_l1", sigma=0.7, corr_len=0.9),
+]
+
+
+def _make(stream_obj, autotune=False):
+    probs = [make_problem(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma, p.corr_len, p.a_min) for p in PROBS]
+    fs = [rhs_noisy(p.n, 100 + i) for i, p in enumerate(PROBS)]
+    return sg.Batch(probs, f_nodal=fs, restart=20, autotune=autotune, stream=stream_obj), fs
+
+
+@pytest.mark.parametrize("pc", ["fs", "mean"])
+def test_batch_matches_single_instance_solves(pc):
+    need_gpu()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        B, fs = _make(stream)
+        F = B.rhs()
+        u, infos = B.solve(F, pc=pc, grouping="klvar", tol=1e-8)
+        torch.cuda.synchronize()
+        ub = u.cpu().numpy()
+        for i, p in enumerate(PROBS):
+            inst = sg.SGInstance(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma, p.corr_len, p.a_min,
+                                 f_nodal=fs[i], stream=stream)
+            Fi = inst.rhs()
+            ui, info, _ = inst.solve(Fi, pc=pc, grouping="klvar", restart=20, tol=1e-8)
+            torch.cuda.synchronize()
+            o0, o1 = B.offsets[i], B.offsets[i + 1]
+            assert infos[i].status == 0, (i, infos[i].status)
+            assert infos[i].iterations == info.iterations, (i, infos[i].iterations, info.iterations)
+            uref = ui.cpu().numpy()
+            assert np.linalg.norm(ub[o0:o1] - uref) <= 1e-12 * np.linalg.norm(uref)
+            inst.close()
+        B.close()
+
+
+def test_batch_true_residual_by_oracle():
+    need_gpu()
+    from oracle.system import SGSystem
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        B, fs = _make(stream)
+        F = B.rhs()
+        u, infos = B.solve(F, pc="fs", grouping="klvar", tol=1e-8)
+        torch.cuda.synchronize()
+        ub = u.cpu().numpy()
+        for i, p in enumerate(PROBS):
+            S = SGSystem(p, fs[i])
+            Fo = S.rhs()
+            ui = ub[B.offsets[i]:B.offsets[i + 1]]
+            rr = np.linalg.norm(Fo - S.apply(ui)) / np.linalg.norm(Fo)
+            assert rr <= 1e-8 * (1 + 1e-6), (i, rr)
+            assert abs(rr - infos[i].relres) <= 1e-12
+        # a second solve replays the captured graphs and reproduces the result
+        u2, infos2 = B.solve(F, pc="fs", grouping="klvar", tol=1e-8)
+        torch.cuda.synchronize()
+        assert np.array_equal(u2.cpu().numpy(), ub)
+        B.close()
+
+
+def test_autotuner_picks_a_candidate_and_batch_uses_it(tmp_path, monkeypatch):
+    need_gpu()
+    monkeypatch.setenv("SG_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    p = PROBS[4]
+    kc, ms = sg.sg_autotune_apply(make_problem(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma,
+                                               p.corr_len, p.a_min))
+    assert kc in (16, 32, 48, 64) and ms > 0
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        B, fs = _make(stream, autotune=True)
+        assert (tmp_path / "tune.txt").exists()
+        F = B.rhs()
+        u, infos = B.solve(F, pc="fs", grouping="klvar", tol=1e-8)
+        assert all(i.status == 0 for i in infos)
+        B.close()
