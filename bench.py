@@ -29,6 +29,27 @@ sys.path.insert(0, ROOT)
 METRIC = "GMRES time-to-relres-1e-8 (s) + SG apply HBM GB/s; learned-FGMRES vs field-split"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per apply dispatch on the 128x128 workload from two rocprofv3 --pmc passes
+# (FETCH_SIZE, WRITE_SIZE), scaled by the same counters read on a plain 256 MiB copy
+# (factors 2.0 and 1.0).  Valid only for the apply source they were taken on: the
+# sha256 of the apply section of sg_kernels.hip is compared at run time.
+APPLY_TRAFFIC = {"src_sha256": "356e1f17047c438b59cd7d9250825722eed14474acf6d55cf211a16ab4711af8",
+                 "fetch_bytes": 67722.0 * 1024 * 2.0, "write_bytes": 28185.0 * 1024 * 1.0}
+
+
+def apply_traffic():
+    """Measured HBM bytes per apply, or None once the apply source has changed."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_1910_11505_amd", "csrc", "sg_kernels.hip")
+    try:
+        src = open(path).read()
+        sec = src[src.index("// SG operator apply."):src.index("// Folds the edge contributions")]
+    except (OSError, ValueError):
+        return None
+    if hashlib.sha256(sec.encode()).hexdigest() != APPLY_TRAFFIC["src_sha256"]:
+        return None
+    return APPLY_TRAFFIC["fetch_bytes"] + APPLY_TRAFFIC["write_bytes"]
+
 
 def _args():
     ap = argparse.ArgumentParser()
@@ -37,8 +58,43 @@ def _args():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--cpu-iters", type=int, default=24)
+    ap.add_argument("--no-c2-apply", action="store_true",
+                    help="skip the HBM-bound apply measurement on the 256x256, 924-mode shape")
+    ap.add_argument("--profile-apply", action="store_true",
+                    help="counter-collection mode: only the 128x128 apply loop and a plain "
+                         "256 MiB device copy (the scale reference for FETCH_SIZE/WRITE_SIZE)")
     return ap.parse_args()
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_applies(inst, reps, stream, seed=11505):
+    """Average SG-apply launch time (ms) over `reps` back-to-back applies on the
+    stream the kernels run on, plus the algorithmic bytes of one apply:
+    every coefficient mode at every quadrature point once, U read once, W
+    written once (FP64)."""
+    import torch
+    from synth import random_vector
+    dev = torch.device("cuda:0")
+    U = torch.from_numpy(random_vector(inst.nvec, seed)).to(dev)
+    W = inst.vec()
+    for _ in range(3):
+        inst.apply(U, W)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        inst.apply(U, W)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    Nq = 4 * inst.prob.n * inst.prob.n
+    nbytes = 8.0 * (inst.na * Nq + 2 * inst.P * inst.Nh)
+    return ms, nbytes
 
 
 def cpu_baseline(prob, gpu_iters, gpu_restarts, n_iters):
@@ -85,7 +141,7 @@ def main():
     import torch
 
     import paper_1910_11505_amd as sg
-    from synth import CONFIGS, random_vector
+    from synth import CONFIGS
 
     prob = CONFIGS["c1"]
     dev = torch.device("cuda:0")
@@ -97,8 +153,20 @@ def main():
                          prob.corr_len, prob.a_min)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    _log(f"set-up {setup_s:.2f} s (P={inst.P}, n_a={inst.na})")
     F = inst.rhs()
     u = inst.vec()
+
+    if args.profile_apply:
+        ms, nb = time_applies(inst, args.apply_reps, stream)
+        src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": "apply", "apply_ms": ms, "apply_algorithmic_bytes": nb,
+                          "copy_bytes_each_way": src.numel() * 8, "copies": 5}), flush=True)
+        return
 
     def solve(pc):
         return inst.solve(F, pc=pc, grouping="klvar", restart=50, tol=1e-8, u=u)
@@ -117,6 +185,7 @@ def main():
     torch.cuda.synchronize()
     ms_fs = e0.elapsed_time(e1) / args.steps
     it_fs, rs_fs, relres_fs, st_fs = infos[-1]
+    _log(f"field-split solve {ms_fs:.2f} ms, {it_fs} iterations, relres {relres_fs:.3e}")
 
     # mean-based preconditioner on the same system (context)
     solve("mean")
@@ -128,20 +197,29 @@ def main():
     ms_mean = e0.elapsed_time(e1)
 
     # SG apply: average launch time over a loop of applies on this stream
-    U = torch.from_numpy(random_vector(inst.nvec, 11505)).to(dev)
-    W = inst.vec()
-    for _ in range(5):
-        inst.apply(U, W)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.apply_reps):
-        inst.apply(U, W)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    apply_ms = e0.elapsed_time(e1) / args.apply_reps
-    Nq = 4 * prob.n * prob.n
-    apply_bytes = 8.0 * (inst.na * Nq + 2 * inst.P * inst.Nh)
+    apply_ms, apply_bytes = time_applies(inst, args.apply_reps, stream)
     apply_gbs = apply_bytes / (apply_ms * 1e-3) / 1e9
+    _log(f"apply {apply_ms * 1e3:.1f} us, {apply_gbs:.0f} GB/s")
+
+    c2_apply = None
+    if not args.no_c2_apply:
+        # the 256x256 shape: 924 coefficient modes (1.94 GB) cannot stay in the
+        # 256 MB last-level cache, so this rate is HBM-bound
+        inst.close()
+        torch.cuda.empty_cache()
+        p2 = CONFIGS["c2"]
+        t0 = time.perf_counter()
+        inst2 = sg.SGInstance(p2.n, p2.M, p2.p, p2.q, p2.cov, p2.mu, p2.sigma, p2.corr_len,
+                              p2.a_min)
+        torch.cuda.synchronize()
+        setup2 = time.perf_counter() - t0
+        ms2, b2 = time_applies(inst2, 10, stream)
+        g2 = b2 / (ms2 * 1e-3) / 1e9
+        c2_apply = {"shape": "Q1 256x256, M=6, p=3 (P=84), q=6 (924 modes)", "ms": ms2,
+                    "algorithmic_bytes": b2, "gbs": g2, "frac_hbm_peak": g2 / HBM_PEAK_GBS,
+                    "setup_s": setup2}
+        inst2.close()
+        _log(f"256x256 apply {ms2:.3f} ms, {g2:.0f} GB/s")
 
     line = {
         "metric": METRIC,
@@ -174,6 +252,7 @@ def main():
         "apply": {"ms": apply_ms, "algorithmic_bytes": apply_bytes, "gbs": apply_gbs,
                   "note": "coefficient modes (110 MB) fit the 256 MB Infinity Cache: "
                           "cache-resident effective rate"},
+        "apply_c2_hbm": c2_apply,
         "roofline": {
             "kernel": "apply_kernel (SG operator apply) + fixup",
             "bound": "hbm",
@@ -181,10 +260,11 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": apply_gbs / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": apply_traffic(),
         },
     }
     if not args.no_cpu_baseline:
+        _log("timing the oracle sample")
         line["cpu_baseline"] = cpu_baseline(prob, it_fs, rs_fs, args.cpu_iters)
     print(json.dumps(line), flush=True)
 

@@ -108,15 +108,6 @@ void launch_apply(hipStream_t s, int n, int na, const double* a, const RowSetDev
                   double* out, double* edge);
 size_t apply_lds_bytes(int maxcols, int kc, int maxent);
 void launch_zero(hipStream_t s, double* x, int64_t n);
-void launch_jacobi(hipStream_t s, const Level& L, int m, const double* b, const double* xin,
-                   double* xout, double omega, bool first);
-void launch_residual(hipStream_t s, const Level& L, int m, const double* b, const double* x,
-                     double* r);
-void launch_restrict(hipStream_t s, const Level& Lf, const Level& Lc, int m, const double* rf,
-                     double* bc);
-void launch_prolong_add(hipStream_t s, const Level& Lf, const Level& Lc, int m,
-                        const double* xc, double* xf);
-void launch_coarse(hipStream_t s, const Level& L, int m, const double* b, double* x);
 void launch_gather_modes(hipStream_t s, int m, const int* modes, int64_t Nh, const double* src,
                          double* dst);
 void launch_scatter_modes(hipStream_t s, int m, const int* modes, int64_t Nh, const double* src,

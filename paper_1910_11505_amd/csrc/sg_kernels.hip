@@ -483,147 +483,8 @@ void launch_apply(hipStream_t s, int n, int na, const double* a, const RowSetDev
 }
 
 // ---------------------------------------------------------------------------
-// Multigrid pieces on a level with a 9-point stencil, batched over m modes.
+// Mode gather/scatter for the field-split groups.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double stencil_apply(const double* __restrict__ S, int64_t N, int m,
-                                                int64_t node, int ix, int iy,
-                                                const double* __restrict__ x) {
-  double acc = 0.0;
-#pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const int jx = ix + (t % 3) - 1, jy = iy + (t / 3) - 1;
-    if (jx >= 0 && jx < m && jy >= 0 && jy < m)
-      acc += S[(int64_t)t * N + node] * x[(int64_t)jy * m + jx];
-  }
-  return acc;
-}
-
-__global__ void jacobi_kernel(const double* __restrict__ S, int n, int64_t N, int modes,
-                              const double* __restrict__ b, const double* __restrict__ xin,
-                              double* __restrict__ xout, double omega, int first) {
-  const int m = n - 1;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= N * modes) return;
-  const int64_t node = gid % N;
-  const int64_t off = gid - node;
-  const double d = S[4 * N + node];
-  if (first) {
-    xout[gid] = omega * b[gid] / d;
-    return;
-  }
-  const int ix = (int)(node % m), iy = (int)(node / m);
-  const double ax = stencil_apply(S, N, m, node, ix, iy, xin + off);
-  xout[gid] = xin[gid] + omega * (b[gid] - ax) / d;
-}
-
-void launch_jacobi(hipStream_t s, const Level& L, int modes, const double* b, const double* xin,
-                   double* xout, double omega, bool first) {
-  const int64_t tot = L.N * modes;
-  hipLaunchKernelGGL(jacobi_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, s, L.S, L.n, L.N, modes,
-                     b, xin, xout, omega, first ? 1 : 0);
-}
-
-__global__ void residual_kernel(const double* __restrict__ S, int n, int64_t N, int modes,
-                                const double* __restrict__ b, const double* __restrict__ x,
-                                double* __restrict__ r) {
-  const int m = n - 1;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= N * modes) return;
-  const int64_t node = gid % N;
-  const int64_t off = gid - node;
-  const int ix = (int)(node % m), iy = (int)(node / m);
-  r[gid] = b[gid] - stencil_apply(S, N, m, node, ix, iy, x + off);
-}
-
-void launch_residual(hipStream_t s, const Level& L, int modes, const double* b, const double* x,
-                     double* r) {
-  const int64_t tot = L.N * modes;
-  hipLaunchKernelGGL(residual_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, s, L.S, L.n, L.N, modes,
-                     b, x, r);
-}
-
-// b_c = P^T r_f (full weighting with weights 1, 1/2, 1/4)
-__global__ void restrict_kernel(int nf, int64_t Nf, int64_t Nc, int modes,
-                                const double* __restrict__ rf, double* __restrict__ bc) {
-  const int mf = nf - 1, mc = nf / 2 - 1;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= Nc * modes) return;
-  const int64_t node = gid % Nc;
-  const int64_t mode = gid / Nc;
-  const int I = (int)(node % mc) + 1, J = (int)(node / mc) + 1;
-  const double* r = rf + mode * Nf;
-  double acc = 0.0;
-  for (int dy = -1; dy <= 1; ++dy)
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int fx = 2 * I + dx, fy = 2 * J + dy;   // always interior
-      const double w = (dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0);
-      acc += w * r[(int64_t)(fy - 1) * mf + (fx - 1)];
-    }
-  bc[gid] = acc;
-}
-
-void launch_restrict(hipStream_t s, const Level& Lf, const Level& Lc, int modes, const double* rf,
-                     double* bc) {
-  const int64_t tot = Lc.N * modes;
-  hipLaunchKernelGGL(restrict_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, s, Lf.n, Lf.N, Lc.N,
-                     modes, rf, bc);
-}
-
-// x_f += P x_c (bilinear interpolation, zero coarse boundary)
-__global__ void prolong_add_kernel(int nf, int64_t Nf, int64_t Nc, int modes,
-                                   const double* __restrict__ xc, double* __restrict__ xf) {
-  const int mf = nf - 1, mc = nf / 2 - 1;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= Nf * modes) return;
-  const int64_t node = gid % Nf;
-  const int64_t mode = gid / Nf;
-  const int i = (int)(node % mf) + 1, j = (int)(node / mf) + 1;
-  const double* c = xc + mode * Nc;
-  const int Ia = i >> 1, Ib = (i + 1) >> 1, Ja = j >> 1, Jb = (j + 1) >> 1;
-  double acc = 0.0;
-  if (i & 1) {
-    if (j & 1) {
-      // four coarse neighbours, 1/4 each
-      if (Ia >= 1 && Ja >= 1) acc += 0.25 * c[(int64_t)(Ja - 1) * mc + (Ia - 1)];
-      if (Ib <= mc && Ja >= 1) acc += 0.25 * c[(int64_t)(Ja - 1) * mc + (Ib - 1)];
-      if (Ia >= 1 && Jb <= mc) acc += 0.25 * c[(int64_t)(Jb - 1) * mc + (Ia - 1)];
-      if (Ib <= mc && Jb <= mc) acc += 0.25 * c[(int64_t)(Jb - 1) * mc + (Ib - 1)];
-    } else {
-      if (Ia >= 1) acc += 0.5 * c[(int64_t)(Ja - 1) * mc + (Ia - 1)];
-      if (Ib <= mc) acc += 0.5 * c[(int64_t)(Ja - 1) * mc + (Ib - 1)];
-    }
-  } else {
-    if (j & 1) {
-      if (Ja >= 1) acc += 0.5 * c[(int64_t)(Ja - 1) * mc + (Ia - 1)];
-      if (Jb <= mc) acc += 0.5 * c[(int64_t)(Jb - 1) * mc + (Ia - 1)];
-    } else {
-      acc = c[(int64_t)(Ja - 1) * mc + (Ia - 1)];
-    }
-  }
-  xf[gid] += acc;
-}
-
-void launch_prolong_add(hipStream_t s, const Level& Lf, const Level& Lc, int modes,
-                        const double* xc, double* xf) {
-  const int64_t tot = Lf.N * modes;
-  hipLaunchKernelGGL(prolong_add_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, s, Lf.n, Lf.N, Lc.N,
-                     modes, xc, xf);
-}
-
-// coarsest grid (n = 2): one unknown per mode, solved exactly
-__global__ void coarse_kernel(const double* __restrict__ S, int64_t N, int modes,
-                              const double* __restrict__ b, double* __restrict__ x) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= N * modes) return;
-  x[gid] = b[gid] / S[4 * N + gid % N];
-}
-
-void launch_coarse(hipStream_t s, const Level& L, int modes, const double* b, double* x) {
-  if (L.N != 1) throw Error(SG_ERR_INTERNAL, "coarsest level must have one unknown");
-  hipLaunchKernelGGL(coarse_kernel, dim3(cdiv(L.N * modes, 256)), dim3(256), 0, s, L.S, L.N,
-                     modes, b, x);
-}
-
 __global__ void gather_modes_kernel(int modes, const int* __restrict__ idx, int64_t Nh,
                                     const double* __restrict__ src, double* __restrict__ dst,
                                     int scatter) {
