@@ -69,6 +69,18 @@ enum { SG_PC_DIAG_KII = 0x100 };
  *                N=2, p=4 -> splits of 5, 4, 6 modes)                        */
 enum { SG_GROUP_KLVAR = 0, SG_GROUP_KLVAR_MEANSEP = 1, SG_GROUP_PERMODE = 2, SG_GROUP_FG = 3 };
 
+/* form of the operator apply (sg_set_apply):
+ *  TRIPLE    sum over the n_a coefficient modes a_k(x_q) with the triple
+ *            products [G_k]_{ij} (Sec. 2.2, eqs. dataProjection, K_matrix);
+ *            valid for every q
+ *  FACTORED  the same matrix through E[a psi_i psi_j] = a_min delta_ij +
+ *            exp(mu + |g|^2/2) (T T^T)_ij, T the Hermite translation matrix
+ *            of the KL values g_n(x_q); equal to TRIPLE when q >= 2p (the
+ *            projection of eq. dataProjection is then exact on every block),
+ *            rejected otherwise
+ *  AUTO      FACTORED when q >= 2p, else TRIPLE (the default)              */
+enum { SG_APPLY_AUTO = 0, SG_APPLY_TRIPLE = 1, SG_APPLY_FACTORED = 2 };
+
 /* Problem statement (Sec. 2, Sec. 2.1, Sec. 2.2):
  *  n         elements per side, power of two, 4 <= n <= 4096
  *  M         KL terms (the paper's N), 1 <= M <= 12
@@ -136,8 +148,17 @@ int sg_bind(sg_handle* h, void* dev_workspace, size_t bytes, void* stream);
 int sg_rhs(sg_handle* h, double* F, void* stream);
 
 /* W = K U = sum_k vec(A_k U G_k^T) (Sec. 2.2, definition of K), matrix-free
- * from a_k at the quadrature points.  U, W: device, P*N_h, must not alias. */
+ * in the form chosen by sg_set_apply.  U, W: device, P*N_h, must not alias. */
 int sg_apply(sg_handle* h, const double* U, double* W, void* stream);
+
+/* Chooses the apply form used by sg_apply, sg_residual, the field-split
+ * preconditioner and sg_gmres_solve.  points_per_batch (FACTORED only): Gauss
+ * points per sub-batch of a 4x4-element tile, 8, 16, 32 or 64, or 0 for the
+ * planner's choice.  Re-uploads the plan on `stream` when the handle is bound
+ * and synchronises it.  Errors: INVALID_ARG (unknown kind or size),
+ * UNSUPPORTED (FACTORED with q < 2p, or a size whose LDS exceeds 160 KB; the
+ * previous plan stays in place).                                            */
+int sg_set_apply(sg_handle* h, int kind, int points_per_batch, void* stream);
 
 /* z = P^{-1} r for pc in {SG_PC_NONE, SG_PC_MEAN, SG_PC_FS} and a grouping
  * (Sec. 3, eqs. P_preconditioner / P_group).  r, z: device, P*N_h, must not

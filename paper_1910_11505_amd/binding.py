@@ -70,6 +70,7 @@ def load_library():
         "sg_bind": (I32, [HP, VP, SZ, VP]),
         "sg_rhs": (I32, [HP, VP, VP]),
         "sg_apply": (I32, [HP, VP, VP, VP]),
+        "sg_set_apply": (I32, [HP, I32, I32, VP]),
         "sg_precond_apply": (I32, [HP, I32, I32, VP, VP, VP]),
         "sg_gmres_workspace_bytes": (SZ, [HP, P(SolveOpts)]),
         "sg_gmres_solve": (I32, [HP, P(SolveOpts), VP, VP, VP, SZ, VP, ctypes.c_int32,
@@ -172,6 +173,14 @@ def sg_rhs(h, F, stream=None):
 
 def sg_apply(h, U, W, stream=None):
     _check(load_library().sg_apply(h, _ptr(U), _ptr(W), _stream(stream)))
+
+
+APPLY = {"auto": 0, "triple": 1, "factored": 2}
+
+
+def sg_set_apply(h, kind="auto", points_per_batch=0, stream=None):
+    kind = APPLY[kind] if isinstance(kind, str) else int(kind)
+    _check(load_library().sg_set_apply(h, kind, int(points_per_batch), _stream(stream)))
 
 
 def sg_precond_apply(h, pc, grouping, r, z, stream=None):
@@ -319,6 +328,10 @@ class SGInstance:
         W = self.vec() if W is None else W
         sg_apply(self.h, U, W, self.stream)
         return W
+
+    def set_apply(self, kind="auto", points_per_batch=0):
+        """Apply form: "auto" (factored when q >= 2p), "triple" or "factored"."""
+        sg_set_apply(self.h, kind, points_per_batch, self.stream)
 
     def precond(self, r, pc="mean", grouping="klvar", z=None):
         z = self.vec() if z is None else z

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <numeric>
 #include <string>
@@ -32,9 +33,21 @@ constexpr double kOmega = 8.0 / 9.0;
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// Host plan of a factored row set (see FRowSetDev): gamma slots, the two
+// entry lists, and the rows of every row group.
+struct FRowSetHost {
+  int nrows = 0, ncols = 0, ngam = 0, qb = 0, rmax = 0;
+  std::vector<int> rows, cols, gam, l1, l2, dcol, p1, p2;
+  std::vector<Entry> e1, e2;
+};
+
+// capacity of the per-group row tables (groups * rmax <= kMaxP + 32 for every plan)
+constexpr int kFGroupCap = kMaxP + 32;
+
 struct FSHost {
   std::vector<std::vector<int>> splits;
-  std::vector<RowSetHost> partial;  // partial[s] for s >= 1 (index 0 unused)
+  std::vector<RowSetHost> partial;    // partial[s] for s >= 1 (index 0 unused)
+  std::vector<FRowSetHost> fpartial;  // the same blocks in factored form
   std::vector<std::vector<int>> sid;  // stencil ids (mode + 1) of each split
 };
 
@@ -42,6 +55,7 @@ struct FSDev {
   std::vector<int*> split_idx;
   std::vector<int*> split_sid;   // stencil id (mode + 1) of every mode of a split
   std::vector<RowSetDev> partial;
+  std::vector<FRowSetDev> fpartial;
 };
 
 // every device pointer inside the bound workspace
@@ -50,6 +64,8 @@ struct DevPtrs {
   int* Jq = nullptr;
   std::vector<Level> L;
   RowSetDev full{};
+  FRowSetDev ffull{};
+  int *mpar = nullptr, *mvar = nullptr, *mdeg = nullptr;  // monomial tables of J(p)
   FSDev fs[4];
   double* edge = nullptr;
   std::vector<double*> mg_b, mg_x, mg_xa, mg_r;
@@ -84,6 +100,11 @@ struct sg_handle {
   std::vector<double> f_nodal, g_tiled, isf;
   std::vector<int> Jq_flat;
   RowSetHost full;
+  FRowSetHost ffull;
+  std::vector<int> mpar, mvar, mdeg;  // monomial recursion over J(p)
+  bool factored_ok = false;           // q >= 2p: the factored apply is exact
+  bool use_factored = false;          // apply form in use
+  int fqb = 0;                        // forced sub-batch size (0: planner's choice)
   FSHost fs[4];
   std::vector<int> level_n;
   std::vector<int> diag_ptr, diag_k, diag_sid;  // per mode i: [G_k]_{ii} != 0 entries
@@ -217,6 +238,165 @@ RowSetHost build_rowset(const sg_handle& H, const std::vector<int>& rows,
   return rs;
 }
 
+// Pairs gamma <= alpha (componentwise) of J(p) with the coefficient
+// c_{alpha,gamma} = prod_n sqrt(alpha_n!/gamma_n!) / (alpha_n - gamma_n)! and the
+// J(p) index of delta = alpha - gamma (the monomial g^delta).
+struct TPair {
+  int a, gm, d;
+  double c;
+};
+
+std::vector<TPair> t_pairs(const sg_handle& H) {
+  std::map<std::vector<int>, int> idx;
+  for (int i = 0; i < H.P; ++i) idx[H.Jp[i]] = i;
+  auto fact = [](int k) {
+    double f = 1.0;
+    for (int t = 2; t <= k; ++t) f *= t;
+    return f;
+  };
+  std::vector<TPair> out;
+  for (int a = 0; a < H.P; ++a) {
+    const std::vector<int>& al = H.Jp[a];
+    std::vector<int> gm(H.M, 0), de(H.M);
+    for (;;) {
+      double c = 1.0;
+      for (int n = 0; n < H.M; ++n) {
+        de[n] = al[n] - gm[n];
+        c *= std::sqrt(fact(al[n]) / fact(gm[n])) / fact(de[n]);
+      }
+      out.push_back({a, idx.at(gm), idx.at(de), c});
+      int n = 0;
+      while (n < H.M && ++gm[n] > al[n]) gm[n++] = 0;
+      if (n == H.M) break;
+    }
+  }
+  return out;
+}
+
+// Monomial recursion over J(p): g^delta = g^(delta - e_n) g_n with n the first
+// nonzero index of delta; mdeg[d] is the first index of degree d (J(p) is graded),
+// padded with P up to index p + 2.
+void monomial_tables(sg_handle& H) {
+  std::map<std::vector<int>, int> idx;
+  for (int i = 0; i < H.P; ++i) idx[H.Jp[i]] = i;
+  const int p = H.prob.p;
+  H.mpar.assign(H.P, 0);
+  H.mvar.assign(H.P, 0);
+  H.mdeg.assign(p + 3, H.P);
+  for (int i = H.P - 1; i >= 0; --i) {
+    const std::vector<int>& d = H.Jp[i];
+    const int deg = std::accumulate(d.begin(), d.end(), 0);
+    H.mdeg[deg] = i;
+    if (deg == 0) continue;
+    int n = 0;
+    while (d[n] == 0) ++n;
+    std::vector<int> par = d;
+    par[n]--;
+    H.mpar[i] = idx.at(par);
+    H.mvar[i] = n;
+  }
+}
+
+// CSR of entry buckets, every row segment padded to kEntryUnroll entries, one
+// zero group past the end.
+void layout_csr(const std::vector<std::vector<std::pair<int, double>>>& b, std::vector<int>& ptr,
+                std::vector<Entry>& ent) {
+  ptr.assign(b.size() + 1, 0);
+  ent.clear();
+  for (size_t r = 0; r < b.size(); ++r) {
+    ptr[r] = (int)ent.size();
+    for (auto& e : b[r]) ent.push_back(Entry{e.first, 0, e.second});
+    while (ent.size() % kEntryUnroll) ent.push_back(Entry{0, 0, 0.0});
+  }
+  ptr[b.size()] = (int)ent.size();
+  for (int u = 0; u < kEntryUnroll; ++u) ent.push_back(Entry{0, 0, 0.0});
+}
+
+// rows of one step to row groups: longest first onto the least loaded group
+// with a free slot
+void assign_groups(const std::vector<int>& ptr, int groups, int rmax, std::vector<int>& lst) {
+  const int cnt = (int)ptr.size() - 1;
+  lst.assign((size_t)groups * rmax, -1);
+  std::vector<int> order(cnt);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return ptr[a + 1] - ptr[a] > ptr[b + 1] - ptr[b];
+  });
+  std::vector<long> load(groups, 0);
+  std::vector<int> used(groups, 0);
+  for (int r : order) {
+    int best = -1;
+    for (int gi = 0; gi < groups; ++gi)
+      if (used[gi] < rmax && (best < 0 || load[gi] < load[best])) best = gi;
+    lst[(size_t)best * rmax + used[best]++] = r;
+    load[best] += ptr[r + 1] - ptr[r];
+  }
+}
+
+// Sub-batch size: forced, else the largest of 64/32/16/8 whose LDS allows two
+// workgroups per CU, else the largest that fits at all.
+void plan_frowset(const sg_handle& H, FRowSetHost& f, int force_qb) {
+  int qb = 0;
+  const int cands[] = {64, 32, 16, 8};
+  for (size_t budget : {(size_t)80 * 1024, (size_t)160 * 1024}) {
+    for (int c : cands) {
+      if (force_qb && c != force_qb) continue;
+      if (fapply_lds_bytes(c, f.nrows, f.ncols, f.ngam, H.P, H.M) <= budget) {
+        qb = c;
+        break;
+      }
+    }
+    if (qb) break;
+  }
+  if (!qb)
+    throw Error(SG_ERR_UNSUPPORTED, "factored apply: no sub-batch size fits in LDS" +
+                                        std::string(force_qb ? " (forced)" : ""));
+  const int groups = 256 / qb;
+  const int rmax = std::max({1, (f.ngam + groups - 1) / groups, (f.nrows + groups - 1) / groups});
+  if (groups * rmax > kFGroupCap) throw Error(SG_ERR_INTERNAL, "factored apply: group table");
+  f.qb = qb;
+  f.rmax = rmax;
+  assign_groups(f.p1, groups, rmax, f.l1);
+  assign_groups(f.p2, groups, rmax, f.l2);
+}
+
+FRowSetHost build_frowset(const sg_handle& H, const std::vector<TPair>& T,
+                          const std::vector<int>& rows, const std::vector<int>& cols,
+                          int force_qb) {
+  FRowSetHost f;
+  f.rows = rows;
+  f.cols = cols;
+  f.nrows = (int)rows.size();
+  f.ncols = (int)cols.size();
+  std::vector<int> rslot(H.P, -1), cslot(H.P, -1), gslot(H.P, -1);
+  for (int t = 0; t < f.nrows; ++t) rslot[rows[t]] = t;
+  for (int t = 0; t < f.ncols; ++t) cslot[cols[t]] = t;
+  // gamma couples a column to a row only if gamma <= some column and <= some row
+  std::vector<char> fromc(H.P, 0), fromr(H.P, 0);
+  for (const TPair& t : T) {
+    if (cslot[t.a] >= 0) fromc[t.gm] = 1;
+    if (rslot[t.a] >= 0) fromr[t.gm] = 1;
+  }
+  for (int gm = 0; gm < H.P; ++gm)
+    if (fromc[gm] && fromr[gm]) {
+      gslot[gm] = (int)f.gam.size();
+      f.gam.push_back(gm);
+    }
+  f.ngam = (int)f.gam.size();
+  std::vector<std::vector<std::pair<int, double>>> b1(f.ngam), b2(f.nrows);
+  for (const TPair& t : T) {
+    if (gslot[t.gm] < 0) continue;
+    if (cslot[t.a] >= 0) b1[gslot[t.gm]].push_back({cslot[t.a] | (t.d << 16), t.c});
+    if (rslot[t.a] >= 0) b2[rslot[t.a]].push_back({gslot[t.gm] | (t.d << 16), t.c});
+  }
+  layout_csr(b1, f.p1, f.e1);
+  layout_csr(b2, f.p2, f.e2);
+  f.dcol.resize(f.nrows);
+  for (int r = 0; r < f.nrows; ++r) f.dcol[r] = cslot[rows[r]];
+  plan_frowset(H, f, force_qb);
+  return f;
+}
+
 void validate(const sg_problem& p) {
   auto bad = [](const std::string& m) { throw Error(SG_ERR_INVALID_ARG, m); };
   if (p.n < 4 || p.n > 4096 || (p.n & (p.n - 1))) bad("n must be a power of two in [4, 4096]");
@@ -260,16 +440,46 @@ void carve(const sg_handle& H, DevPtrs& D, Carver& c) {
     d.ent = c.take<Entry>(std::max<size_t>(rs.ent.size(), 1));
   };
   put_rowset(H.full, D.full);
+  if (H.factored_ok) {
+    D.mpar = c.take<int>(H.mpar.size());
+    D.mvar = c.take<int>(H.mvar.size());
+    D.mdeg = c.take<int>(H.mdeg.size());
+  }
+  auto put_frowset = [&](const FRowSetHost& f, FRowSetDev& d) {
+    d.nrows = f.nrows;
+    d.ncols = f.ncols;
+    d.ngam = f.ngam;
+    d.qb = f.qb;
+    d.rmax = f.rmax;
+    d.nmono = H.P;
+    d.pdeg = H.prob.p;
+    d.M = H.M;
+    d.rows = c.take<int>(std::max(f.nrows, 1));
+    d.cols = c.take<int>(std::max(f.ncols, 1));
+    d.l1 = c.take<int>(kFGroupCap);
+    d.l2 = c.take<int>(kFGroupCap);
+    d.dcol = c.take<int>(std::max(f.nrows, 1));
+    d.p1 = c.take<int>(f.p1.size());
+    d.p2 = c.take<int>(f.p2.size());
+    d.e1 = c.take<Entry>(f.e1.size());
+    d.e2 = c.take<Entry>(f.e2.size());
+    d.mpar = D.mpar;
+    d.mvar = D.mvar;
+    d.mdeg = D.mdeg;
+  };
+  if (H.factored_ok) put_frowset(H.ffull, D.ffull);
   for (int g = 0; g < 4; ++g) {
     const FSHost& fh = H.fs[g];
     FSDev& fd = D.fs[g];
     fd.split_idx.assign(fh.splits.size(), nullptr);
     fd.split_sid.assign(fh.splits.size(), nullptr);
     fd.partial.assign(fh.splits.size(), RowSetDev{});
+    fd.fpartial.assign(fh.splits.size(), FRowSetDev{});
     for (size_t s = 0; s < fh.splits.size(); ++s) {
       fd.split_idx[s] = c.take<int>(fh.splits[s].size());
       fd.split_sid[s] = c.take<int>(fh.splits[s].size());
       if (s >= 1) put_rowset(fh.partial[s], fd.partial[s]);
+      if (s >= 1 && H.factored_ok) put_frowset(fh.fpartial[s], fd.fpartial[s]);
     }
   }
   D.edge = c.take<double>((size_t)H.P * H.ntiles * kEdgeVals);
@@ -311,6 +521,20 @@ void upload_rowset(hipStream_t s, const RowSetHost& h, const RowSetDev& d) {
   upload(s, d.ent, h.ent);
 }
 
+void upload_frowset(hipStream_t s, const FRowSetHost& h, FRowSetDev& d) {
+  upload(s, d.rows, h.rows);
+  upload(s, d.cols, h.cols);
+  upload(s, d.l1, h.l1);
+  upload(s, d.l2, h.l2);
+  upload(s, d.dcol, h.dcol);
+  upload(s, d.p1, h.p1);
+  upload(s, d.p2, h.p2);
+  upload(s, d.e1, h.e1);
+  upload(s, d.e2, h.e2);
+  d.qb = h.qb;
+  d.rmax = h.rmax;
+}
+
 void check_launch() {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw Error(SG_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -344,7 +568,11 @@ void vcycle(sg_handle& H, hipStream_t s, int m, const int* smode, const double* 
 }
 
 void do_apply(sg_handle& H, hipStream_t s, const double* U, double* W) {
-  launch_apply(s, H.n, H.na, H.d.a, H.d.full, U, H.Nh, nullptr, 0.0, 1.0, W, H.d.edge);
+  if (H.use_factored)
+    launch_fapply(s, H.n, H.prob.mu, H.prob.a_min, H.d.g, H.d.ffull, U, H.Nh, nullptr, 0.0, 1.0,
+                  W, H.d.edge);
+  else
+    launch_apply(s, H.n, H.na, H.d.a, H.d.full, U, H.Nh, nullptr, 0.0, 1.0, W, H.d.edge);
 }
 
 void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double* r, double* z) {
@@ -368,8 +596,12 @@ void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double*
     if (sp == 0) {
       launch_gather_modes(s, m, fd.split_idx[0], H.Nh, r, H.d.fsT);
     } else {
-      launch_apply(s, H.n, H.na, H.d.a, fd.partial[sp], z, H.Nh, r, 1.0, -1.0, H.d.fsT,
-                   H.d.edge);
+      if (H.use_factored)
+        launch_fapply(s, H.n, H.prob.mu, H.prob.a_min, H.d.g, fd.fpartial[sp], z, H.Nh, r, 1.0,
+                      -1.0, H.d.fsT, H.d.edge);
+      else
+        launch_apply(s, H.n, H.na, H.d.a, fd.partial[sp], z, H.Nh, r, 1.0, -1.0, H.d.fsT,
+                     H.d.edge);
     }
     vcycle(H, s, m, kii ? fd.split_sid[sp] : nullptr, H.d.fsT, H.d.fsX);
     launch_scatter_modes(s, m, fd.split_idx[sp], H.Nh, H.d.fsX, z);
@@ -449,17 +681,28 @@ int setup_impl(const sg_problem* prob, const double* f_nodal, int force_kc, sg_h
     std::vector<int> all(H->P);
     std::iota(all.begin(), all.end(), 0);
     H->full = build_rowset(*H, all, all, force_kc);
+    H->factored_ok = prob->q >= 2 * prob->p;
+    H->use_factored = H->factored_ok;
+    std::vector<TPair> T;
+    if (H->factored_ok) {
+      T = t_pairs(*H);
+      monomial_tables(*H);
+      H->ffull = build_frowset(*H, T, all, all, 0);
+    }
     for (int g = 0; g < 4; ++g) {
       FSHost& fh = H->fs[g];
       fh.splits = make_splits(H->Jp, g);
       fh.partial.assign(fh.splits.size(), RowSetHost{});
+      fh.fpartial.assign(fh.splits.size(), FRowSetHost{});
       fh.sid.assign(fh.splits.size(), {});
       for (size_t sp = 0; sp < fh.splits.size(); ++sp)
         for (int i : fh.splits[sp]) fh.sid[sp].push_back(i + 1);
       std::vector<int> prev;
       for (size_t s = 0; s < fh.splits.size(); ++s) {
-        if (s >= 1)
+        if (s >= 1) {
           fh.partial[s] = build_rowset(*H, fh.splits[s], prev);
+          if (H->factored_ok) fh.fpartial[s] = build_frowset(*H, T, fh.splits[s], prev, 0);
+        }
         prev.insert(prev.end(), fh.splits[s].begin(), fh.splits[s].end());
       }
     }
@@ -527,11 +770,19 @@ int sg_bind(sg_handle* h, void* dev_workspace, size_t bytes, void* stream) {
     upload(s, D.Jq, H.Jq_flat);
     upload(s, D.f, H.f_nodal);
     upload_rowset(s, H.full, D.full);
+    if (H.factored_ok) {
+      upload(s, D.mpar, H.mpar);
+      upload(s, D.mvar, H.mvar);
+      upload(s, D.mdeg, H.mdeg);
+      upload_frowset(s, H.ffull, D.ffull);
+    }
     for (int g = 0; g < 4; ++g)
       for (size_t sp = 0; sp < H.fs[g].splits.size(); ++sp) {
         upload(s, D.fs[g].split_idx[sp], H.fs[g].splits[sp]);
         upload(s, D.fs[g].split_sid[sp], H.fs[g].sid[sp]);
         if (sp >= 1) upload_rowset(s, H.fs[g].partial[sp], D.fs[g].partial[sp]);
+        if (sp >= 1 && H.factored_ok)
+          upload_frowset(s, H.fs[g].fpartial[sp], D.fs[g].fpartial[sp]);
       }
     upload(s, D.all_sid, H.diag_sid);
     upload(s, D.diag_k, H.diag_k);
@@ -573,6 +824,47 @@ int sg_rhs(sg_handle* h, double* F, void* stream) {
     return SG_OK;
   } catch (const Error& e) {
     return fail(e.code, e.what());
+  }
+}
+
+int sg_set_apply(sg_handle* h, int kind, int points_per_batch, void* stream) {
+  if (!h) return fail(SG_ERR_INVALID_ARG, "null argument");
+  if (kind < SG_APPLY_AUTO || kind > SG_APPLY_FACTORED)
+    return fail(SG_ERR_INVALID_ARG, "unknown apply form");
+  const int qb = points_per_batch;
+  if (qb != 0 && qb != 8 && qb != 16 && qb != 32 && qb != 64)
+    return fail(SG_ERR_INVALID_ARG, "points_per_batch must be 0, 8, 16, 32 or 64");
+  sg_handle& H = *h;
+  if (kind == SG_APPLY_FACTORED && !H.factored_ok)
+    return fail(SG_ERR_UNSUPPORTED, "the factored apply needs q >= 2p");
+  try {
+    if (H.factored_ok && qb != H.fqb) {
+      // plan on copies first: a size that does not fit leaves the old plan in place
+      FRowSetHost full = H.ffull;
+      plan_frowset(H, full, qb);
+      std::vector<std::vector<FRowSetHost>> parts(4);
+      for (int g = 0; g < 4; ++g) {
+        parts[g] = H.fs[g].fpartial;
+        for (size_t sp = 1; sp < parts[g].size(); ++sp) plan_frowset(H, parts[g][sp], qb);
+      }
+      H.ffull = std::move(full);
+      for (int g = 0; g < 4; ++g) H.fs[g].fpartial = std::move(parts[g]);
+      H.fqb = qb;
+      if (H.bound) {
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        upload_frowset(s, H.ffull, H.d.ffull);
+        for (int g = 0; g < 4; ++g)
+          for (size_t sp = 1; sp < H.fs[g].fpartial.size(); ++sp)
+            upload_frowset(s, H.fs[g].fpartial[sp], H.d.fs[g].fpartial[sp]);
+        SG_HIP(hipStreamSynchronize(s));
+      }
+    }
+    H.use_factored = kind == SG_APPLY_AUTO ? H.factored_ok : kind == SG_APPLY_FACTORED;
+    return SG_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return fail(SG_ERR_INTERNAL, e.what());
   }
 }
 

@@ -91,6 +91,29 @@ struct RowSetDev {
   const Entry* ent;
 };
 
+// Factored apply (exact when q >= 2p): sum_k a_k(x) G_k = a_min I + w(x) T T^T with
+// w = exp(mu + |g|^2 / 2) and T_{alpha,gamma} = c_{alpha,gamma} g^{alpha-gamma} for
+// gamma <= alpha.  Step 1: V_gamma = sum_alpha T_{alpha,gamma} grad U_alpha over the
+// column modes; step 2: flux_beta = a_min grad U_beta + w sum_gamma T_{beta,gamma} V_gamma.
+// Entries: kj = (column slot | monomial index << 16), v = c_{alpha,gamma}.
+struct FRowSetDev {
+  int nrows, ncols, ngam;  // output rows, input columns, intermediate gamma slots
+  int qb, rmax;            // Gauss points per sub-batch (8/16/32/64), row slots per row group
+  int nmono, pdeg, M;      // monomials (= |J(p)|), chaos degree p, KL terms
+  const int* rows;         // [nrows] output mode ids (for rin)
+  const int* cols;         // [ncols] input mode ids
+  const int* l1;           // [groups][rmax] gamma slot of a step-1 row, or -1
+  const int* l2;           // [groups][rmax] output row slot of a step-2 row, or -1
+  const int* dcol;         // [nrows] column slot of the output mode, or -1
+  const int* p1;           // [ngam + 1] step-1 entry ranges
+  const int* p2;           // [nrows + 1] step-2 entry ranges
+  const Entry* e1;
+  const Entry* e2;
+  const int* mpar;         // [nmono] monomial of degree d-1 it extends (0 for degree <= 1)
+  const int* mvar;         // [nmono] KL variable it multiplies by
+  const int* mdeg;         // [pdeg + 2] first monomial of each degree
+};
+
 struct Level {
   int n;          // elements per side on this level
   int64_t N;      // (n-1)^2
@@ -107,6 +130,10 @@ void launch_apply(hipStream_t s, int n, int na, const double* a, const RowSetDev
                   const double* U, int64_t Nh, const double* rin, double beta, double sgn,
                   double* out, double* edge);
 size_t apply_lds_bytes(int maxcols, int kc, int maxent);
+size_t fapply_lds_bytes(int qb, int nrows, int ncols, int ngam, int nmono, int M);
+void launch_fapply(hipStream_t s, int n, double mu, double a_min, const double* g,
+                   const FRowSetDev& rs, const double* U, int64_t Nh, const double* rin,
+                   double beta, double sgn, double* out, double* edge);
 void launch_zero(hipStream_t s, double* x, int64_t n);
 void launch_gather_modes(hipStream_t s, int m, const int* modes, int64_t Nh, const double* src,
                          double* dst);

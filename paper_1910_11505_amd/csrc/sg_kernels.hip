@@ -483,6 +483,280 @@ void launch_apply(hipStream_t s, int n, int na, const double* a, const RowSetDev
 }
 
 // ---------------------------------------------------------------------------
+// Factored SG operator apply, exact when the coefficient degree q >= 2p.
+//
+// With y ~ N(0, I), shifting the Gaussian measure by g(x) and the Hermite
+// addition formula give, for the orthonormal chaos,
+//   sum_k a_k(x) [G_k]_{beta,alpha} = E[a psi_beta psi_alpha]
+//     = a_min delta_{beta,alpha} + w(x) sum_gamma T_{beta,gamma} T_{alpha,gamma},
+//   w = exp(mu + |g|^2 / 2),  T_{alpha,gamma} = prod_n sqrt(alpha_n!/gamma_n!)
+//                                             g_n^(alpha_n-gamma_n) / (alpha_n-gamma_n)!
+// for gamma <= alpha componentwise (zero otherwise).  The chaos projection of
+// eq. dataProjection is exact up to degree 2p, so this is the same matrix K.
+// Only g_n(x_q) (M values per Gauss point) is read instead of n_a coefficient
+// modes, and the per-point contraction costs 2 nnz(T) products instead of
+// nnz(G).
+//
+// One workgroup per 4x4-element tile; its 64 Gauss points are taken in
+// sub-batches of qb points (64: the whole tile, 32: 4x2 elements, 16: 2x2,
+// 8: 2x1).  Thread t handles point t % qb of the sub-batch for the rows of
+// row group t / qb.  Per sub-batch:
+//   1. nodal values of the column modes and g_n at the points -> LDS;
+//   2. reference gradients grad U_alpha -> LDS, w(x_q);
+//   3. monomials g^delta for every delta in J(p), degree by degree;
+//   4. V_gamma = sum_alpha c_{alpha,gamma} g^(alpha-gamma) grad U_alpha -> LDS;
+//   5. flux_beta = a_min grad U_beta + w sum_gamma c_{beta,gamma} g^(beta-gamma) V_gamma;
+//   6. element-node contributions (1/4) grad phi_a . flux_beta, summed over the
+//      element's four points by lane shuffles, added into the tile's 5x5 node
+//      sums in a fixed order (sub-batch, then local corner of the element).
+// The tile's nodes are then written as in the triple-product apply: owned
+// nodes to out, right/top edge and corner to the edge buffer for the fixup.
+// ---------------------------------------------------------------------------
+namespace {
+__host__ __device__ inline int fa_sub_w(int qb) { return qb <= 16 ? 2 : 4; }
+__host__ __device__ inline int fa_nodes(int qb) {
+  const int sw = fa_sub_w(qb), sh = qb / (4 * sw);
+  return (sw + 1) * (sh + 1);
+}
+__host__ __device__ inline int fa_even(int x) { return (x + 1) & ~1; }
+}  // namespace
+
+size_t fapply_lds_bytes(int qb, int nrows, int ncols, int ngam, int nmono, int M) {
+  const size_t node = fa_even(nrows * 25);
+  const size_t grad = (size_t)std::max(ncols, 1) * qb * 2;
+  const size_t vgam = (size_t)std::max(ngam, 1) * qb * 2;
+  const size_t mono = fa_even(std::max(nmono * qb, ncols * fa_nodes(qb)));
+  const size_t wg = fa_even(qb * (M + 1));
+  return 8 * (node + grad + vgam + mono + wg);
+}
+
+__device__ __forceinline__ void fapply_tile(double* smem, int tile, int n, double mu,
+                                            double a_min, const double* __restrict__ g,
+                                            const FRowSetDev& rs, const double* __restrict__ U,
+                                            int64_t Nh, const double* __restrict__ rin,
+                                            double beta, double sgn, double* __restrict__ out,
+                                            double* __restrict__ edge) {
+  const int nt = n / kTileE;
+  const int ntiles = nt * nt;
+  const int tx = tile % nt, ty = tile / nt;
+  const int x0 = tx * kTileE, y0 = ty * kTileE;
+  const int tid = threadIdx.x;
+  const int qb = rs.qb;
+  const int q = tid & (qb - 1);
+  const int grp = tid / qb;
+  const int64_t Nq = (int64_t)4 * n * n;
+  const int m = n - 1;
+  const int M = rs.M, ncols = rs.ncols, nrows = rs.nrows, rmax = rs.rmax;
+  const int sw = fa_sub_w(qb), sh = qb / (4 * sw), nnd = (sw + 1) * (sh + 1);
+  const int nsub = kTileQ / qb, subs_x = kTileE / sw;
+
+  double* sNode = smem;                                                  // [nrows][25]
+  double2* sG = reinterpret_cast<double2*>(smem + fa_even(nrows * 25));  // [ncols][qb]
+  double2* sV = sG + (size_t)max(ncols, 1) * qb;                         // [ngam][qb]
+  double* sM = reinterpret_cast<double*>(sV + (size_t)max(rs.ngam, 1) * qb);
+  double* sW = sM + fa_even(max(rs.nmono * qb, ncols * nnd));            // [qb]
+  double* sg = sW + qb;                                                  // [M][qb]
+
+  for (int i = tid; i < nrows * 25; i += 256) sNode[i] = 0.0;
+
+  const int* l1 = rs.l1 + grp * rmax;
+  const int* l2 = rs.l2 + grp * rmax;
+  const int ql = q & 3;
+  const double xi = gauss_pt(ql & 1), eta = gauss_pt(ql >> 1);
+  double gpx[4], gpy[4];
+#pragma unroll
+  for (int a4 = 0; a4 < 4; ++a4) ref_grad(a4, xi, eta, gpx[a4], gpy[a4]);
+
+  for (int sb = 0; sb < nsub; ++sb) {
+    const int ex0 = (sb % subs_x) * sw, ey0 = (sb / subs_x) * sh;
+    __syncthreads();  // the previous sub-batch is done with sG, sV and sM
+    // 1. nodal values of the column modes, g_n at the points
+    for (int base = tid; base < ncols * nnd; base += 256 * 4) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int idx = base + u * 256;
+        v[u] = 0.0;
+        if (idx < ncols * nnd) {
+          const int c = idx / nnd, nd = idx - c * nnd;
+          const int gx = x0 + ex0 + nd % (sw + 1), gy = y0 + ey0 + nd / (sw + 1);
+          if (gx >= 1 && gx <= m && gy >= 1 && gy <= m)
+            v[u] = U[(int64_t)rs.cols[c] * Nh + (int64_t)(gy - 1) * m + (gx - 1)];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (base + u * 256 < ncols * nnd) sM[base + u * 256] = v[u];
+    }
+    for (int idx = tid; idx < M * qb; idx += 256) {
+      const int nn = idx / qb, qq = idx - nn * qb;
+      const int el = qq >> 2;
+      const int elx = ex0 + el % sw, ely = ey0 + el / sw;
+      sg[idx] = g[(int64_t)nn * Nq + (int64_t)tile * kTileQ + (ely * kTileE + elx) * 4 + (qq & 3)];
+    }
+    __syncthreads();
+    // 2. reference gradients and w
+    for (int idx = tid; idx < ncols * qb; idx += 256) {
+      const int c = idx / qb, qq = idx - c * qb;
+      const int el = qq >> 2, qp = qq & 3;
+      const int lx = el % sw, ly = el / sw;
+      const double xq = gauss_pt(qp & 1), yq = gauss_pt(qp >> 1);
+      const double* u = sM + c * nnd;
+      const double u00 = u[ly * (sw + 1) + lx], u10 = u[ly * (sw + 1) + lx + 1];
+      const double u01 = u[(ly + 1) * (sw + 1) + lx], u11 = u[(ly + 1) * (sw + 1) + lx + 1];
+      sG[idx] = make_double2((1.0 - yq) * (u10 - u00) + yq * (u11 - u01),
+                             (1.0 - xq) * (u01 - u00) + xq * (u11 - u10));
+    }
+    if (tid < qb) {
+      double s2 = 0.0;
+      for (int nn = 0; nn < M; ++nn) s2 = fma(sg[nn * qb + tid], sg[nn * qb + tid], s2);
+      sW[tid] = exp(mu + 0.5 * s2);
+    }
+    __syncthreads();
+    // 3. monomials: degrees 0 and 1 directly, then degree by degree
+    for (int idx = tid; idx < rs.mdeg[2] * qb; idx += 256) {
+      const int d = idx / qb, qq = idx - d * qb;
+      sM[idx] = d == 0 ? 1.0 : sg[rs.mvar[d] * qb + qq];
+    }
+    for (int deg = 2; deg <= rs.pdeg; ++deg) {
+      __syncthreads();
+      const int d0 = rs.mdeg[deg], cnt = (rs.mdeg[deg + 1] - d0) * qb;
+      for (int idx = tid; idx < cnt; idx += 256) {
+        const int d = d0 + idx / qb, qq = idx % qb;
+        sM[d * qb + qq] = sM[rs.mpar[d] * qb + qq] * sg[rs.mvar[d] * qb + qq];
+      }
+    }
+    __syncthreads();
+    // 4. step 1: V_gamma for this group's gamma rows
+    for (int r = 0; r < rmax; ++r) {
+      const int s1 = l1[r];
+      if (s1 < 0) break;
+      double sx = 0.0, sy = 0.0;
+      const int b = rs.p1[s1], e = rs.p1[s1 + 1];
+      for (int t = b; t < e; t += kEntryUnroll) {
+        Entry en[kEntryUnroll];
+#pragma unroll
+        for (int u = 0; u < kEntryUnroll; ++u) en[u] = rs.e1[t + u];
+        double mv[kEntryUnroll];
+        double2 gg[kEntryUnroll];
+#pragma unroll
+        for (int u = 0; u < kEntryUnroll; ++u) {
+          mv[u] = sM[(en[u].kj >> 16) * qb + q];
+          gg[u] = sG[(en[u].kj & 0xffff) * qb + q];
+        }
+#pragma unroll
+        for (int u = 0; u < kEntryUnroll; ++u) {
+          const double c = en[u].v * mv[u];
+          sx = fma(c, gg[u].x, sx);
+          sy = fma(c, gg[u].y, sy);
+        }
+      }
+      sV[s1 * qb + q] = make_double2(sx, sy);
+    }
+    __syncthreads();
+    // 5.-6. step 2 and node sums, row by row
+    const double w = sW[q];
+    const int el = q >> 2;
+    const int nloc = (ey0 + el / sw + (ql >> 1)) * 5 + ex0 + el % sw + (ql & 1);
+    for (int r = 0; r < rmax; ++r) {
+      const int s2 = l2[r];
+      if (s2 < 0) break;
+      double sx = 0.0, sy = 0.0;
+      const int b = rs.p2[s2], e = rs.p2[s2 + 1];
+      for (int t = b; t < e; t += kEntryUnroll) {
+        Entry en[kEntryUnroll];
+#pragma unroll
+        for (int u = 0; u < kEntryUnroll; ++u) en[u] = rs.e2[t + u];
+        double mv[kEntryUnroll];
+        double2 vv[kEntryUnroll];
+#pragma unroll
+        for (int u = 0; u < kEntryUnroll; ++u) {
+          mv[u] = sM[(en[u].kj >> 16) * qb + q];
+          vv[u] = sV[(en[u].kj & 0xffff) * qb + q];
+        }
+#pragma unroll
+        for (int u = 0; u < kEntryUnroll; ++u) {
+          const double c = en[u].v * mv[u];
+          sx = fma(c, vv[u].x, sx);
+          sy = fma(c, vv[u].y, sy);
+        }
+      }
+      double flx = w * sx, fly = w * sy;
+      const int dc = rs.dcol[s2];
+      if (dc >= 0) {
+        const double2 gu = sG[dc * qb + q];
+        flx = fma(a_min, gu.x, flx);
+        fly = fma(a_min, gu.y, fly);
+      }
+      double c4[4];
+#pragma unroll
+      for (int a4 = 0; a4 < 4; ++a4) c4[a4] = 0.25 * (gpx[a4] * flx + gpy[a4] * fly);
+#pragma unroll
+      for (int a4 = 0; a4 < 4; ++a4) {
+        c4[a4] += __shfl_xor(c4[a4], 1);
+        c4[a4] += __shfl_xor(c4[a4], 2);
+      }
+      const double mine = (ql == 0) ? c4[0] : (ql == 1) ? c4[1] : (ql == 2) ? c4[2] : c4[3];
+      double* dst = sNode + s2 * 25 + nloc;
+      // the same local corner of distinct elements is a distinct node, so one
+      // phase per corner gives a fixed summation order without atomics; a row
+      // belongs to one group, whose lanes all sit in one wavefront
+#pragma unroll
+      for (int a4 = 0; a4 < 4; ++a4) {
+        if (ql == a4) *dst += mine;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+  }
+  __syncthreads();
+  // tile nodes: owned -> out, right/top edge and corner -> edge buffer
+  for (int idx = tid; idx < nrows * 25; idx += 256) {
+    const int slot = idx / 25, nd = idx - slot * 25;
+    const int nx = nd % 5, ny = nd / 5;
+    const double sum = sNode[idx];
+    if (nx <= 3 && ny <= 3) {
+      const int gx = x0 + nx, gy = y0 + ny;
+      if (gx >= 1 && gy >= 1) {
+        const int64_t node = (int64_t)(gy - 1) * m + (gx - 1);
+        double base = 0.0;
+        if (beta != 0.0) base = beta * rin[(int64_t)rs.rows[slot] * Nh + node];
+        out[(int64_t)slot * Nh + node] = base + sgn * sum;
+      }
+    } else {
+      const int e = (nx == 4 && ny == 4) ? 8 : (nx == 4 ? ny : 4 + nx);
+      edge[((int64_t)slot * ntiles + tile) * kEdgeVals + e] = sum;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void fapply_kernel(int n, double mu, double a_min,
+                                                     const double* __restrict__ g, FRowSetDev rs,
+                                                     const double* __restrict__ U, int64_t Nh,
+                                                     const double* __restrict__ rin, double beta,
+                                                     double sgn, double* __restrict__ out,
+                                                     double* __restrict__ edge) {
+  extern __shared__ double smem[];
+  fapply_tile(smem, blockIdx.x, n, mu, a_min, g, rs, U, Nh, rin, beta, sgn, out, edge);
+}
+
+void launch_fapply(hipStream_t s, int n, double mu, double a_min, const double* g,
+                   const FRowSetDev& rs, const double* U, int64_t Nh, const double* rin,
+                   double beta, double sgn, double* out, double* edge) {
+  const int nt = n / kTileE;
+  const int ntiles = nt * nt;
+  const size_t lds = fapply_lds_bytes(rs.qb, rs.nrows, rs.ncols, rs.ngam, rs.nmono, rs.M);
+  if (lds > 160 * 1024 || (rs.qb != 8 && rs.qb != 16 && rs.qb != 32 && rs.qb != 64))
+    throw Error(SG_ERR_INTERNAL, "factored apply: bad sub-batch plan");
+  hipLaunchKernelGGL(fapply_kernel, dim3(ntiles), dim3(256), lds, s, n, mu, a_min, g, rs, U, Nh,
+                     rin, beta, sgn, out, edge);
+  const int64_t total = (int64_t)rs.nrows * ntiles * 7;
+  hipLaunchKernelGGL(apply_fixup_kernel, dim3(cdiv(total, 256)), dim3(256), 0, s, n, rs.nrows,
+                     sgn, edge, out, Nh);
+}
+
+// ---------------------------------------------------------------------------
 // Mode gather/scatter for the field-split groups.
 // ---------------------------------------------------------------------------
 __global__ void gather_modes_kernel(int modes, const int* __restrict__ idx, int64_t Nh,

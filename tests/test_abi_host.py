@@ -110,3 +110,30 @@ def test_groupings_match_oracle(M, p, gname, gid):
         pos += 1 + sz
     assert got == make_groups(opc.multi_indices(M, p), gname)
     sg.sg_destroy(h)
+
+
+def test_set_apply_validation():
+    h = _setup()                                   # q = 2p: both forms available
+    sg.sg_set_apply(h, "factored", 16, stream=0)
+    sg.sg_set_apply(h, "triple", 0, stream=0)
+    sg.sg_set_apply(h, "auto", 0, stream=0)
+    for bad_kind, bad_qb in ((3, 0), (-1, 0), (0, 12), (2, 128)):
+        with pytest.raises(sg.SGError) as e:
+            sg.sg_set_apply(h, bad_kind, bad_qb, stream=0)
+        assert e.value.code == -1
+    sg.sg_destroy(h)
+    h = _setup(M=3, p=2, q=3)                      # q < 2p: factored form is not exact
+    with pytest.raises(sg.SGError) as e:
+        sg.sg_set_apply(h, "factored", 0, stream=0)
+    assert e.value.code == -2
+    sg.sg_set_apply(h, "triple", 0, stream=0)
+    sg.sg_destroy(h)
+
+
+def test_set_apply_oversized_batch_keeps_plan():
+    h = _setup(M=6, p=4, q=8, n=8)                 # P = 210: 64 points need > 160 KB of LDS
+    with pytest.raises(sg.SGError) as e:
+        sg.sg_set_apply(h, "factored", 64, stream=0)
+    assert e.value.code == -2
+    sg.sg_set_apply(h, "factored", 8, stream=0)
+    sg.sg_destroy(h)

@@ -42,6 +42,7 @@ def test_batch_matches_single_instance_solves(pc):
         for i, p in enumerate(PROBS):
             inst = sg.SGInstance(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma, p.corr_len, p.a_min,
                                  f_nodal=fs[i], stream=stream)
+            inst.set_apply("triple")        # the batched apply sums over coefficient modes
             Fi = inst.rhs()
             ui, info, _ = inst.solve(Fi, pc=pc, grouping="klvar", restart=20, tol=1e-8)
             torch.cuda.synchronize()

@@ -122,3 +122,32 @@ def test_sampled_apply_matches_full_apply():
     modes = [0, 2, 5]
     Ws = S.apply_at(U, modes, nodes)
     assert np.allclose(Ws, W[np.ix_(modes, nodes)], rtol=1e-13, atol=1e-13)
+
+
+def test_chaos_coefficient_matrix_factorises_when_q_is_2p():
+    """sum_k a_k(x) G_k = E[a psi psi^T] = a_min I + exp(mu + |g|^2/2) T T^T with the
+    Hermite translation matrix T_{alpha,gamma} = prod_n sqrt(alpha_n!/gamma_n!)
+    g_n^(alpha_n-gamma_n)/(alpha_n-gamma_n)! (gamma <= alpha), exact once q >= 2p;
+    for q < 2p the truncated projection differs."""
+    from math import factorial
+    rng = np.random.default_rng(5)
+    M, p, mu, a_min = 3, 2, 0.2, 0.01
+    Jp = pc.multi_indices(M, p)
+    g = 0.6 * rng.standard_normal((M, 3))
+    for q, exact in ((2 * p, True), (2 * p + 1, True), (2 * p - 1, False)):
+        Jq = pc.multi_indices(M, q)
+        a = coeff_modes(g, Jq, mu, a_min)
+        Gk, Gi, Gj, Gv = pc.triple_products(Jp, Jq)
+        for x in range(g.shape[1]):
+            C = np.zeros((len(Jp), len(Jp)))
+            np.add.at(C, (Gi, Gj), a[Gk, x] * Gv)
+            T = np.zeros((len(Jp), len(Jp)))
+            for i, al in enumerate(Jp):
+                for j, gm in enumerate(Jp):
+                    if all(gg <= aa for gg, aa in zip(gm, al)):
+                        T[i, j] = np.prod([np.sqrt(factorial(aa) / factorial(gg))
+                                           * g[n, x] ** (aa - gg) / factorial(aa - gg)
+                                           for n, (aa, gg) in enumerate(zip(al, gm))])
+            ref = a_min * np.eye(len(Jp)) + np.exp(mu + 0.5 * np.sum(g[:, x] ** 2)) * T @ T.T
+            err = np.abs(C - ref).max() / np.abs(ref).max()
+            assert (err < 1e-14) if exact else (err > 1e-6), (q, err)
