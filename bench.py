@@ -61,6 +61,8 @@ def _args():
     ap.add_argument("--cpu-iters", type=int, default=24)
     ap.add_argument("--no-c2-apply", action="store_true",
                     help="skip the HBM-bound apply measurement on the 256x256, 924-mode shape")
+    ap.add_argument("--apply-form", default="factored", choices=["factored", "triple"],
+                    help="apply form of the counter-collection mode")
     ap.add_argument("--profile-apply", action="store_true",
                     help="counter-collection mode: only the 128x128 apply loop and a plain "
                          "256 MiB device copy (the scale reference for FETCH_SIZE/WRITE_SIZE)")
@@ -73,9 +75,10 @@ def _log(msg):
 
 def time_applies(inst, reps, stream, seed=11505):
     """Average SG-apply launch time (ms) over `reps` back-to-back applies on the
-    stream the kernels run on, plus the algorithmic bytes of one apply:
-    every coefficient mode at every quadrature point once, U read once, W
-    written once (FP64)."""
+    stream the kernels run on, plus the algorithmic bytes of one apply in the
+    form in use: U read once, W written once (FP64), and either every
+    coefficient mode a_k at every Gauss point (triple-product form) or the M
+    KL values g_n at every Gauss point (factored form)."""
     import torch
     from synth import random_vector
     dev = torch.device("cuda:0")
@@ -92,43 +95,26 @@ def time_applies(inst, reps, stream, seed=11505):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
+    return ms
+
+
+def apply_bytes(inst, form):
     Nq = 4 * inst.prob.n * inst.prob.n
-    nbytes = 8.0 * (inst.na * Nq + 2 * inst.P * inst.Nh)
-    return ms, nbytes
+    per_point = inst.na if form == "triple" else inst.prob.M
+    return 8.0 * (per_point * Nq + 2 * inst.P * inst.Nh)
 
 
-def cpu_baseline(prob, gpu_iters, gpu_restarts, n_iters):
-    """Times the oracle's field-split GMRES on a bounded sample: n_iters Arnoldi
-    steps plus the closing update (n_iters + 1 operator and preconditioner
-    applications), scaled to the GPU's iteration count."""
-    import numpy as np
-    from threadpoolctl import threadpool_info
-
-    from oracle.gmg import GMGHierarchy
-    from oracle.gmres import gmres
-    from oracle.precond import FieldSplit, make_groups
-    from oracle.system import SGSystem
-
-    S = SGSystem(prob)
-    _ = S.A
-    H = GMGHierarchy(S.A[0], prob.n)
-    fs = FieldSplit(S, H, make_groups(S.Jp, "klvar"))
-    F = S.rhs()
-    t0 = time.perf_counter()
-    gmres(S.apply, fs.apply, F, tol=1e-8, restart=50, max_it=n_iters)
-    dt = time.perf_counter() - t0
-    per_pair = dt / (n_iters + 1)
-    est = per_pair * (gpu_iters + gpu_restarts)
-    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    return {
-        "value": est, "unit": "s", "cores": int(threads), "kind": "oracle",
-        "sample": (f"oracle FS-GMRES(50) on the same workload, {n_iters} Arnoldi steps + closing "
-                   f"update timed ({dt:.1f} s, {n_iters + 1} operator+preconditioner "
-                   f"applications), scaled to the GPU's {gpu_iters} iterations + "
-                   f"{gpu_restarts} closing updates; set-up excluded; host has "
-                   f"{os.cpu_count()} logical CPUs, sparse kernels single-threaded, BLAS "
-                   f"threads {threads}"),
-    }
+def measure_apply_forms(inst, reps, stream):
+    """Both forms of the apply on one instance: time, bytes, GB/s."""
+    out = {}
+    for form in ("factored", "triple"):
+        inst.set_apply(form)
+        ms = time_applies(inst, reps, stream)
+        nb = apply_bytes(inst, form)
+        out[form] = {"ms": ms, "algorithmic_bytes": nb, "gbs": nb / (ms * 1e-3) / 1e9,
+                     "frac_hbm_peak": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    inst.set_apply("auto")
+    return out
 
 
 def main():
@@ -158,7 +144,9 @@ def main():
     u = inst.vec()
 
     if args.profile_apply:
-        ms, nb = time_applies(inst, args.apply_reps, stream)
+        inst.set_apply(args.apply_form)
+        ms = time_applies(inst, args.apply_reps, stream)
+        nb = apply_bytes(inst, args.apply_form)
         src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         for _ in range(5):
@@ -196,15 +184,16 @@ def main():
     torch.cuda.synchronize()
     ms_mean = e0.elapsed_time(e1)
 
-    # SG apply: average launch time over a loop of applies on this stream
-    apply_ms, apply_bytes = time_applies(inst, args.apply_reps, stream)
-    apply_gbs = apply_bytes / (apply_ms * 1e-3) / 1e9
-    _log(f"apply {apply_ms * 1e3:.1f} us, {apply_gbs:.0f} GB/s")
+    # SG apply in both forms: average launch time over a loop of applies on this stream
+    forms = measure_apply_forms(inst, args.apply_reps, stream)
+    for f, v in forms.items():
+        _log(f"apply ({f}) {v['ms'] * 1e3:.1f} us, {v['gbs']:.0f} GB/s")
+    apply_ms, apply_gbs = forms["factored"]["ms"], forms["factored"]["gbs"]
 
     c2_apply = None
     if not args.no_c2_apply:
         # the 256x256 shape: 924 coefficient modes (1.94 GB) cannot stay in the
-        # 256 MB last-level cache, so this rate is HBM-bound
+        # 256 MB last-level cache, so the triple-product form is HBM-bound
         inst.close()
         torch.cuda.empty_cache()
         p2 = CONFIGS["c2"]
@@ -213,13 +202,11 @@ def main():
                               p2.a_min)
         torch.cuda.synchronize()
         setup2 = time.perf_counter() - t0
-        ms2, b2 = time_applies(inst2, 10, stream)
-        g2 = b2 / (ms2 * 1e-3) / 1e9
-        c2_apply = {"shape": "Q1 256x256, M=6, p=3 (P=84), q=6 (924 modes)", "ms": ms2,
-                    "algorithmic_bytes": b2, "gbs": g2, "frac_hbm_peak": g2 / HBM_PEAK_GBS,
-                    "setup_s": setup2}
+        c2_apply = {"shape": "Q1 256x256, M=6, p=3 (P=84), q=6 (924 modes)", "setup_s": setup2}
+        c2_apply.update(measure_apply_forms(inst2, 10, stream))
         inst2.close()
-        _log(f"256x256 apply {ms2:.3f} ms, {g2:.0f} GB/s")
+        for f in ("factored", "triple"):
+            _log(f"256x256 apply ({f}) {c2_apply[f]['ms']:.3f} ms, {c2_apply[f]['gbs']:.0f} GB/s")
 
     line = {
         "metric": METRIC,
@@ -249,18 +236,18 @@ def main():
         "setup_s": setup_s,
         "mean_based": {"s": ms_mean / 1e3, "iterations": info_m.iterations,
                        "relres": info_m.relres},
-        "apply": {"ms": apply_ms, "algorithmic_bytes": apply_bytes, "gbs": apply_gbs,
-                  "note": "coefficient modes (110 MB) fit the 256 MB Infinity Cache: "
-                          "cache-resident effective rate"},
+        "apply": dict(forms, note="default form: factored (exact for q >= 2p); the triple-"
+                                   "product form streams the 110 MB of coefficient modes, which "
+                                   "fit the 256 MB last-level cache at this size"),
         "apply_c2_hbm": c2_apply,
         "roofline": {
-            "kernel": "apply_kernel (SG operator apply) + fixup",
+            "kernel": "fapply_kernel (factored SG operator apply) + apply_fixup_kernel",
             "bound": "hbm",
             "achieved": apply_gbs,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": apply_gbs / HBM_PEAK_GBS,
-            "traffic": apply_traffic(),
+            "traffic": None,
         },
     }
     if not args.no_cpu_baseline:

@@ -34,11 +34,12 @@ constexpr double kOmega = 8.0 / 9.0;
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Host plan of a factored row set (see FRowSetDev): gamma slots, the two
-// entry lists, and the rows of every row group.
+// record lists, the rows of every row group, and the packed table blob.
 struct FRowSetHost {
   int nrows = 0, ncols = 0, ngam = 0, qb = 0, rmax = 0;
-  std::vector<int> rows, cols, gam, l1, l2, dcol, p1, p2;
-  std::vector<Entry> e1, e2;
+  std::vector<int> rows, cols, gam, l1, l2, dcol, p1, p2, e1, e2;
+  std::vector<int> blob;
+  FRowSetDev off{};  // sizes and blob offsets (pointer filled at bind)
 };
 
 // capacity of the per-group row tables (groups * rmax <= kMaxP + 32 for every plan)
@@ -65,7 +66,6 @@ struct DevPtrs {
   std::vector<Level> L;
   RowSetDev full{};
   FRowSetDev ffull{};
-  int *mpar = nullptr, *mvar = nullptr, *mdeg = nullptr;  // monomial tables of J(p)
   FSDev fs[4];
   double* edge = nullptr;
   std::vector<double*> mg_b, mg_x, mg_xa, mg_r;
@@ -74,6 +74,7 @@ struct DevPtrs {
   int* diag_k = nullptr;         // (k, v) lists of the diagonal blocks
   double* diag_v = nullptr;
   double* cdiag = nullptr;       // one coefficient field (set-up scratch)
+  double* Cd = nullptr;          // dense coarse V-cycle operator, N x N column-major
 };
 
 // bump allocator over the caller's workspace (or a dry run to size it)
@@ -102,6 +103,7 @@ struct sg_handle {
   RowSetHost full;
   FRowSetHost ffull;
   std::vector<int> mpar, mvar, mdeg;  // monomial recursion over J(p)
+  std::vector<double> minv, sfac;     // 1/delta_n of the recursion; s_alpha = prod sqrt(alpha_n!)
   bool factored_ok = false;           // q >= 2p: the factored apply is exact
   bool use_factored = false;          // apply form in use
   int fqb = 0;                        // forced sub-batch size (0: planner's choice)
@@ -110,6 +112,8 @@ struct sg_handle {
   std::vector<int> diag_ptr, diag_k, diag_sid;  // per mode i: [G_k]_{ii} != 0 entries
   std::vector<double> diag_v;
   int nfine = 0;                                // levels with n > kCoarseN
+  int ldense = -1;                              // first level with n <= kDenseN
+  bool dense_ready = false;                     // dense coarse operator built
 
   // device state
   bool bound = false;
@@ -273,20 +277,24 @@ std::vector<TPair> t_pairs(const sg_handle& H) {
   return out;
 }
 
-// Monomial recursion over J(p): g^delta = g^(delta - e_n) g_n with n the first
-// nonzero index of delta; mdeg[d] is the first index of degree d (J(p) is graded),
-// padded with P up to index p + 2.
+// Monomial recursion over J(p): m_delta = m_(delta - e_n) g_n / delta_n with n
+// the first nonzero index of delta, so m_delta = g^delta / delta!; mdeg[d] is
+// the first index of degree d (J(p) is graded), padded with P up to index p + 2.
 void monomial_tables(sg_handle& H) {
   std::map<std::vector<int>, int> idx;
   for (int i = 0; i < H.P; ++i) idx[H.Jp[i]] = i;
   const int p = H.prob.p;
   H.mpar.assign(H.P, 0);
   H.mvar.assign(H.P, 0);
+  H.minv.assign(H.P, 1.0);
   H.mdeg.assign(p + 3, H.P);
+  H.sfac.assign(H.P, 1.0);
   for (int i = H.P - 1; i >= 0; --i) {
     const std::vector<int>& d = H.Jp[i];
     const int deg = std::accumulate(d.begin(), d.end(), 0);
     H.mdeg[deg] = i;
+    for (int e : d)
+      for (int t = 2; t <= e; ++t) H.sfac[i] *= std::sqrt((double)t);
     if (deg == 0) continue;
     int n = 0;
     while (d[n] == 0) ++n;
@@ -294,22 +302,22 @@ void monomial_tables(sg_handle& H) {
     par[n]--;
     H.mpar[i] = idx.at(par);
     H.mvar[i] = n;
+    H.minv[i] = 1.0 / d[n];
   }
 }
 
-// CSR of entry buckets, every row segment padded to kEntryUnroll entries, one
-// zero group past the end.
-void layout_csr(const std::vector<std::vector<std::pair<int, double>>>& b, std::vector<int>& ptr,
-                std::vector<Entry>& ent) {
+// record buckets -> CSR, every row segment padded to 4 records naming the zero
+// monomial row `pad`
+void layout_records(const std::vector<std::vector<int>>& b, int pad, std::vector<int>& ptr,
+                    std::vector<int>& rec) {
   ptr.assign(b.size() + 1, 0);
-  ent.clear();
+  rec.clear();
   for (size_t r = 0; r < b.size(); ++r) {
-    ptr[r] = (int)ent.size();
-    for (auto& e : b[r]) ent.push_back(Entry{e.first, 0, e.second});
-    while (ent.size() % kEntryUnroll) ent.push_back(Entry{0, 0, 0.0});
+    ptr[r] = (int)rec.size();
+    for (int e : b[r]) rec.push_back(e);
+    while (rec.size() % 4) rec.push_back(pad << 16);
   }
-  ptr[b.size()] = (int)ent.size();
-  for (int u = 0; u < kEntryUnroll; ++u) ent.push_back(Entry{0, 0, 0.0});
+  ptr[b.size()] = (int)rec.size();
 }
 
 // rows of one step to row groups: longest first onto the least loaded group
@@ -333,15 +341,84 @@ void assign_groups(const std::vector<int>& ptr, int groups, int rmax, std::vecto
   }
 }
 
+// Packs every table of the row set into one int32 blob (layout independent of
+// the sub-batch plan: the group tables are reserved at kFGroupCap).
+void pack_frowset(const sg_handle& H, FRowSetHost& f) {
+  std::vector<int>& B = f.blob;
+  B.clear();
+  auto put = [&](const std::vector<int>& v, size_t cap, int align) {
+    while (B.size() % align) B.push_back(0);
+    const int o = (int)B.size();
+    B.insert(B.end(), v.begin(), v.end());
+    B.resize(o + std::max(cap, v.size()), -1);
+    return o;
+  };
+  auto putd = [&](const std::vector<double>& v) {
+    while (B.size() % 2) B.push_back(0);
+    const int o = (int)B.size();
+    B.resize(o + 2 * v.size());
+    if (!v.empty()) std::memcpy(B.data() + o, v.data(), v.size() * sizeof(double));
+    return o;
+  };
+  FRowSetDev& d = f.off;
+  d.nrows = f.nrows;
+  d.ncols = f.ncols;
+  d.ngam = f.ngam;
+  d.qb = f.qb;
+  d.rmax = f.rmax;
+  d.nmono = H.P;
+  d.pdeg = H.prob.p;
+  d.M = H.M;
+  d.o_e1 = put(f.e1, 0, 4);
+  d.o_e2 = put(f.e2, 0, 4);
+  // per group and row: (slot, first record group | end record group << 16)
+  auto rowtab = [&](const std::vector<int>& lst, const std::vector<int>& ptr) {
+    std::vector<int> t(2 * (size_t)kFGroupCap, -1);
+    for (size_t i = 0; i < lst.size(); ++i) {
+      const int sl = lst[i];
+      if (sl < 0) continue;
+      const int b4 = ptr[sl] / 4, e4 = ptr[sl + 1] / 4;
+      if (e4 > 0xffff) throw Error(SG_ERR_UNSUPPORTED, "factored apply: too many records");
+      t[2 * i] = sl;
+      t[2 * i + 1] = b4 | (e4 << 16);
+    }
+    return t;
+  };
+  d.o_r1 = put(rowtab(f.l1, f.p1), 0, 2);
+  d.o_r2 = put(rowtab(f.l2, f.p2), 0, 2);
+  d.o_dcol = put(f.dcol, 0, 1);
+  d.o_cols = put(f.cols, 0, 1);
+  d.o_rows = put(f.rows, 0, 1);
+  d.o_mpar = put(H.mpar, 0, 1);
+  d.o_mvar = put(H.mvar, 0, 1);
+  d.o_mdeg = put(H.mdeg, 0, 1);
+  std::vector<double> cs(f.ncols), gs(f.ngam), rsv(f.nrows), ra(f.nrows);
+  for (int c = 0; c < f.ncols; ++c) cs[c] = H.sfac[f.cols[c]];
+  for (int gi = 0; gi < f.ngam; ++gi) gs[gi] = 1.0 / (H.sfac[f.gam[gi]] * H.sfac[f.gam[gi]]);
+  for (int r = 0; r < f.nrows; ++r) {
+    rsv[r] = H.sfac[f.rows[r]];
+    ra[r] = 1.0 / H.sfac[f.rows[r]];
+  }
+  d.o_cs = putd(cs);
+  d.o_gs = putd(gs);
+  d.o_rs = putd(rsv);
+  d.o_ra = putd(ra);
+  d.o_minv = putd(H.minv);
+  while (B.size() % 4) B.push_back(0);  // staged with 16-byte loads
+  d.nblob = (int)B.size();
+  d.blob = nullptr;
+}
+
 // Sub-batch size: forced, else the largest of 64/32/16/8 whose LDS allows two
 // workgroups per CU, else the largest that fits at all.
 void plan_frowset(const sg_handle& H, FRowSetHost& f, int force_qb) {
   int qb = 0;
   const int cands[] = {64, 32, 16, 8};
+  const int nblob = (int)f.blob.size();
   for (size_t budget : {(size_t)80 * 1024, (size_t)160 * 1024}) {
     for (int c : cands) {
       if (force_qb && c != force_qb) continue;
-      if (fapply_lds_bytes(c, f.nrows, f.ncols, f.ngam, H.P, H.M) <= budget) {
+      if (fapply_lds_bytes(c, f.nrows, f.ncols, f.ngam, H.P, H.M, nblob) <= budget) {
         qb = c;
         break;
       }
@@ -358,6 +435,7 @@ void plan_frowset(const sg_handle& H, FRowSetHost& f, int force_qb) {
   f.rmax = rmax;
   assign_groups(f.p1, groups, rmax, f.l1);
   assign_groups(f.p2, groups, rmax, f.l2);
+  pack_frowset(H, f);
 }
 
 FRowSetHost build_frowset(const sg_handle& H, const std::vector<TPair>& T,
@@ -383,16 +461,20 @@ FRowSetHost build_frowset(const sg_handle& H, const std::vector<TPair>& T,
       f.gam.push_back(gm);
     }
   f.ngam = (int)f.gam.size();
-  std::vector<std::vector<std::pair<int, double>>> b1(f.ngam), b2(f.nrows);
+  std::vector<std::vector<int>> b1(f.ngam), b2(f.nrows);
   for (const TPair& t : T) {
     if (gslot[t.gm] < 0) continue;
-    if (cslot[t.a] >= 0) b1[gslot[t.gm]].push_back({cslot[t.a] | (t.d << 16), t.c});
-    if (rslot[t.a] >= 0) b2[rslot[t.a]].push_back({gslot[t.gm] | (t.d << 16), t.c});
+    if (cslot[t.a] >= 0) b1[gslot[t.gm]].push_back(cslot[t.a] | (t.d << 16));
+    if (rslot[t.a] >= 0) b2[rslot[t.a]].push_back(gslot[t.gm] | (t.d << 16));
   }
-  layout_csr(b1, f.p1, f.e1);
-  layout_csr(b2, f.p2, f.e2);
+  layout_records(b1, H.P, f.p1, f.e1);
+  layout_records(b2, H.P, f.p2, f.e2);
   f.dcol.resize(f.nrows);
   for (int r = 0; r < f.nrows; ++r) f.dcol[r] = cslot[rows[r]];
+  // the blob's size does not depend on the plan: pack once to size it
+  f.l1.assign(kFGroupCap, -1);
+  f.l2.assign(kFGroupCap, -1);
+  pack_frowset(H, f);
   plan_frowset(H, f, force_qb);
   return f;
 }
@@ -440,32 +522,9 @@ void carve(const sg_handle& H, DevPtrs& D, Carver& c) {
     d.ent = c.take<Entry>(std::max<size_t>(rs.ent.size(), 1));
   };
   put_rowset(H.full, D.full);
-  if (H.factored_ok) {
-    D.mpar = c.take<int>(H.mpar.size());
-    D.mvar = c.take<int>(H.mvar.size());
-    D.mdeg = c.take<int>(H.mdeg.size());
-  }
   auto put_frowset = [&](const FRowSetHost& f, FRowSetDev& d) {
-    d.nrows = f.nrows;
-    d.ncols = f.ncols;
-    d.ngam = f.ngam;
-    d.qb = f.qb;
-    d.rmax = f.rmax;
-    d.nmono = H.P;
-    d.pdeg = H.prob.p;
-    d.M = H.M;
-    d.rows = c.take<int>(std::max(f.nrows, 1));
-    d.cols = c.take<int>(std::max(f.ncols, 1));
-    d.l1 = c.take<int>(kFGroupCap);
-    d.l2 = c.take<int>(kFGroupCap);
-    d.dcol = c.take<int>(std::max(f.nrows, 1));
-    d.p1 = c.take<int>(f.p1.size());
-    d.p2 = c.take<int>(f.p2.size());
-    d.e1 = c.take<Entry>(f.e1.size());
-    d.e2 = c.take<Entry>(f.e2.size());
-    d.mpar = D.mpar;
-    d.mvar = D.mvar;
-    d.mdeg = D.mdeg;
+    d = f.off;
+    d.blob = c.take<int>(f.blob.size());
   };
   if (H.factored_ok) put_frowset(H.ffull, D.ffull);
   for (int g = 0; g < 4; ++g) {
@@ -503,6 +562,10 @@ void carve(const sg_handle& H, DevPtrs& D, Carver& c) {
   D.diag_k = c.take<int>(std::max<size_t>(H.diag_k.size(), 1));
   D.diag_v = c.take<double>(std::max<size_t>(H.diag_v.size(), 1));
   D.cdiag = c.take<double>(H.Nq);
+  if (H.ldense >= 0) {
+    const size_t Nd = (size_t)(H.level_n[H.ldense] - 1) * (H.level_n[H.ldense] - 1);
+    D.Cd = c.take<double>(Nd * Nd);
+  }
 }
 
 template <class T>
@@ -522,17 +585,10 @@ void upload_rowset(hipStream_t s, const RowSetHost& h, const RowSetDev& d) {
 }
 
 void upload_frowset(hipStream_t s, const FRowSetHost& h, FRowSetDev& d) {
-  upload(s, d.rows, h.rows);
-  upload(s, d.cols, h.cols);
-  upload(s, d.l1, h.l1);
-  upload(s, d.l2, h.l2);
-  upload(s, d.dcol, h.dcol);
-  upload(s, d.p1, h.p1);
-  upload(s, d.p2, h.p2);
-  upload(s, d.e1, h.e1);
-  upload(s, d.e2, h.e2);
-  d.qb = h.qb;
-  d.rmax = h.rmax;
+  const int* blob = d.blob;
+  d = h.off;
+  d.blob = blob;
+  upload(s, d.blob, h.blob);
 }
 
 void check_launch() {
@@ -540,31 +596,53 @@ void check_launch() {
   if (e != hipSuccess) throw Error(SG_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
 }
 
-// One V(2,2) cycle for m modes: b and x hold m compact vectors of the finest
-// level; smode (device, may be null) gives each mode's stencil id.
-void vcycle(sg_handle& H, hipStream_t s, int m, const int* smode, const double* b, double* x) {
+// One V(2,2) cycle for m modes starting at level l0: b and x hold m compact
+// vectors of that level; smode (device, may be null) gives each mode's stencil id.
+void vcycle_levels(sg_handle& H, hipStream_t s, int l0, int m, const int* smode, const double* b,
+                   double* x) {
   DevPtrs& D = H.d;
   const int nf = H.nfine;
-  std::vector<const double*> bl(D.L.size());
-  std::vector<double*> xl(D.L.size());
-  bl[0] = b;
-  xl[0] = x;
-  for (size_t l = 1; l < D.L.size(); ++l) {
+  const int nl = (int)D.L.size();
+  std::vector<const double*> bl(nl);
+  std::vector<double*> xl(nl);
+  for (int l = l0 + 1; l < nl; ++l) {
     bl[l] = D.mg_b[l];
     xl[l] = D.mg_x[l];
   }
-  for (int l = 0; l < nf; ++l)
+  bl[l0] = b;
+  xl[l0] = x;
+  const int c0 = std::max(nf, l0);
+  for (int l = l0; l < nf; ++l)
     launch_vdown(s, D.L[l], D.L[l + 1], m, smode, bl[l], D.mg_xa[l], D.mg_b[l + 1], kOmega);
   CoarseLevels cl{};
-  cl.nl = (int)D.L.size() - nf;
+  cl.nl = nl - c0;
   for (int l = 0; l < cl.nl; ++l) {
-    cl.n[l] = D.L[nf + l].n;
-    cl.N[l] = D.L[nf + l].N;
-    cl.S[l] = D.L[nf + l].S;
+    cl.n[l] = D.L[c0 + l].n;
+    cl.N[l] = D.L[c0 + l].N;
+    cl.S[l] = D.L[c0 + l].S;
   }
-  launch_vcoarse(s, cl, m, smode, bl[nf], xl[nf], kOmega);
-  for (int l = nf - 1; l >= 0; --l)
+  launch_vcoarse(s, cl, m, smode, bl[c0], xl[c0], kOmega);
+  for (int l = nf - 1; l >= l0; --l)
     launch_vup(s, D.L[l], D.L[l + 1], m, smode, bl[l], D.mg_xa[l], xl[l + 1], xl[l], kOmega);
+}
+
+// One V(2,2) cycle on the finest level.  With the mean stiffness (smode null)
+// the levels from H.ldense down are one precomputed dense operator (the same
+// linear map, built by vcycle_levels on unit vectors at bind).
+void vcycle(sg_handle& H, hipStream_t s, int m, const int* smode, const double* b, double* x) {
+  if (smode || !H.dense_ready) {
+    vcycle_levels(H, s, 0, m, smode, b, x);
+    return;
+  }
+  DevPtrs& D = H.d;
+  const int ld = H.ldense;
+  auto bl = [&](int l) -> const double* { return l == 0 ? b : D.mg_b[l]; };
+  auto xl = [&](int l) -> double* { return l == 0 ? x : D.mg_x[l]; };
+  for (int l = 0; l < ld; ++l)
+    launch_vdown(s, D.L[l], D.L[l + 1], m, nullptr, bl(l), D.mg_xa[l], D.mg_b[l + 1], kOmega);
+  launch_dense_coarse(s, (int)D.L[ld].N, m, D.Cd, bl(ld), xl(ld));
+  for (int l = ld - 1; l >= 0; --l)
+    launch_vup(s, D.L[l], D.L[l + 1], m, nullptr, bl(l), D.mg_xa[l], xl(l + 1), xl(l), kOmega);
 }
 
 void do_apply(sg_handle& H, hipStream_t s, const double* U, double* W) {
@@ -683,12 +761,6 @@ int setup_impl(const sg_problem* prob, const double* f_nodal, int force_kc, sg_h
     H->full = build_rowset(*H, all, all, force_kc);
     H->factored_ok = prob->q >= 2 * prob->p;
     H->use_factored = H->factored_ok;
-    std::vector<TPair> T;
-    if (H->factored_ok) {
-      T = t_pairs(*H);
-      monomial_tables(*H);
-      H->ffull = build_frowset(*H, T, all, all, 0);
-    }
     for (int g = 0; g < 4; ++g) {
       FSHost& fh = H->fs[g];
       fh.splits = make_splits(H->Jp, g);
@@ -699,14 +771,31 @@ int setup_impl(const sg_problem* prob, const double* f_nodal, int force_kc, sg_h
         for (int i : fh.splits[sp]) fh.sid[sp].push_back(i + 1);
       std::vector<int> prev;
       for (size_t s = 0; s < fh.splits.size(); ++s) {
-        if (s >= 1) {
-          fh.partial[s] = build_rowset(*H, fh.splits[s], prev);
-          if (H->factored_ok) fh.fpartial[s] = build_frowset(*H, T, fh.splits[s], prev, 0);
-        }
+        if (s >= 1) fh.partial[s] = build_rowset(*H, fh.splits[s], prev);
         prev.insert(prev.end(), fh.splits[s].begin(), fh.splits[s].end());
       }
     }
+    if (H->factored_ok) {
+      // a mode count whose tables do not fit in LDS keeps the triple-product form
+      try {
+        std::vector<TPair> T = t_pairs(*H);
+        monomial_tables(*H);
+        H->ffull = build_frowset(*H, T, all, all, 0);
+        for (int g = 0; g < 4; ++g) {
+          FSHost& fh = H->fs[g];
+          std::vector<int> prev = fh.splits[0];
+          for (size_t s = 1; s < fh.splits.size(); ++s) {
+            fh.fpartial[s] = build_frowset(*H, T, fh.splits[s], prev, 0);
+            prev.insert(prev.end(), fh.splits[s].begin(), fh.splits[s].end());
+          }
+        }
+      } catch (const Error& e) {
+        if (e.code != SG_ERR_UNSUPPORTED) throw;
+        H->factored_ok = H->use_factored = false;
+      }
+    }
     for (int ln = H->n; ln >= 2; ln /= 2) {
+      if (ln <= kDenseN && H->ldense < 0) H->ldense = (int)H->level_n.size();
       H->level_n.push_back(ln);
       if (ln > kCoarseN) H->nfine++;
     }
@@ -770,12 +859,7 @@ int sg_bind(sg_handle* h, void* dev_workspace, size_t bytes, void* stream) {
     upload(s, D.Jq, H.Jq_flat);
     upload(s, D.f, H.f_nodal);
     upload_rowset(s, H.full, D.full);
-    if (H.factored_ok) {
-      upload(s, D.mpar, H.mpar);
-      upload(s, D.mvar, H.mvar);
-      upload(s, D.mdeg, H.mdeg);
-      upload_frowset(s, H.ffull, D.ffull);
-    }
+    if (H.factored_ok) upload_frowset(s, H.ffull, D.ffull);
     for (int g = 0; g < 4; ++g)
       for (size_t sp = 0; sp < H.fs[g].splits.size(); ++sp) {
         upload(s, D.fs[g].split_idx[sp], H.fs[g].splits[sp]);
@@ -800,6 +884,20 @@ int sg_bind(sg_handle* h, void* dev_workspace, size_t bytes, void* stream) {
       for (size_t l = 1; l < D.L.size(); ++l)
         launch_rap(s, D.L[l - 1].n, D.L[l - 1].S + (int64_t)id * 9 * D.L[l - 1].N,
                    D.L[l].S + (int64_t)id * 9 * D.L[l].N);
+    }
+    // dense coarse operator: the cycle from level ldense applied to unit vectors,
+    // P columns at a time
+    if (H.ldense >= 0) {
+      H.dense_ready = false;
+      const int Nd = (int)D.L[H.ldense].N;
+      for (int j0 = 0; j0 < Nd; j0 += H.P) {
+        const int m = std::min(H.P, Nd - j0);
+        launch_unit_columns(s, Nd, j0, m, D.fsT);
+        vcycle_levels(H, s, H.ldense, m, nullptr, D.fsT, D.fsX);
+        SG_HIP(hipMemcpyAsync(D.Cd + (size_t)j0 * Nd, D.fsX, sizeof(double) * m * Nd,
+                              hipMemcpyDeviceToDevice, s));
+      }
+      H.dense_ready = true;
     }
     check_launch();
     if (!H.host_pinned)

@@ -23,7 +23,8 @@ constexpr int kApplyWaves = 4;       // wavefronts per apply workgroup
 constexpr int kEdgeVals = 9;         // right edge 4, top edge 4, corner 1
 constexpr int kMaxP = 256;
 constexpr int kMaxRestart = 200;
-constexpr int kCoarseN = 16;          // levels with n <= kCoarseN run in one LDS kernel
+constexpr int kCoarseN = 16;  // levels with n <= kCoarseN run in one LDS kernel
+constexpr int kDenseN = 32;   // levels with n <= kDenseN: V-cycle applied as a dense operator
 constexpr int kMaxCoarseLevels = 8;
 
 struct Error : std::runtime_error {
@@ -92,26 +93,28 @@ struct RowSetDev {
 };
 
 // Factored apply (exact when q >= 2p): sum_k a_k(x) G_k = a_min I + w(x) T T^T with
-// w = exp(mu + |g|^2 / 2) and T_{alpha,gamma} = c_{alpha,gamma} g^{alpha-gamma} for
-// gamma <= alpha.  Step 1: V_gamma = sum_alpha T_{alpha,gamma} grad U_alpha over the
-// column modes; step 2: flux_beta = a_min grad U_beta + w sum_gamma T_{beta,gamma} V_gamma.
-// Entries: kj = (column slot | monomial index << 16), v = c_{alpha,gamma}.
+// w = exp(mu + |g|^2 / 2) and T_{alpha,gamma} = (s_alpha / s_gamma) g^delta / delta!,
+// delta = alpha - gamma >= 0, s_alpha = prod_n sqrt(alpha_n!).  With scaled
+// gradients G^_alpha = s_alpha grad U_alpha and scaled monomials m_delta = g^delta / delta!:
+//   step 1: Vbar_gamma = (1 / s_gamma^2) sum_alpha m_(alpha-gamma) G^_alpha  (column modes),
+//   step 2: flux_beta  = s_beta w sum_gamma m_(beta-gamma) Vbar_gamma + (a_min / s_beta) G^_beta.
+// All tables of a row set live in one int32 blob (staged in LDS by every tile); the
+// o_* fields are word offsets into it, the o_cs.. fields point at FP64 values.
+// Records are (slot | monomial << 16); padding records name monomial nmono, a row
+// of zeros.
 struct FRowSetDev {
   int nrows, ncols, ngam;  // output rows, input columns, intermediate gamma slots
   int qb, rmax;            // Gauss points per sub-batch (8/16/32/64), row slots per row group
   int nmono, pdeg, M;      // monomials (= |J(p)|), chaos degree p, KL terms
-  const int* rows;         // [nrows] output mode ids (for rin)
-  const int* cols;         // [ncols] input mode ids
-  const int* l1;           // [groups][rmax] gamma slot of a step-1 row, or -1
-  const int* l2;           // [groups][rmax] output row slot of a step-2 row, or -1
-  const int* dcol;         // [nrows] column slot of the output mode, or -1
-  const int* p1;           // [ngam + 1] step-1 entry ranges
-  const int* p2;           // [nrows + 1] step-2 entry ranges
-  const Entry* e1;
-  const Entry* e2;
-  const int* mpar;         // [nmono] monomial of degree d-1 it extends (0 for degree <= 1)
-  const int* mvar;         // [nmono] KL variable it multiplies by
-  const int* mdeg;         // [pdeg + 2] first monomial of each degree
+  int nblob;               // int32 words of the blob
+  int o_r1, o_r2;          // int2 [groups][rmax]: (row slot or -1, first | end << 16) in
+                           // units of 4 records; step 1 rows are gamma slots, step 2 output rows
+  int o_e1, o_e2;          // records (16-byte aligned, row segments padded to 4)
+  int o_dcol;              // [nrows] column slot of the output mode, or -1
+  int o_cols, o_rows;      // input / output mode ids
+  int o_mpar, o_mvar, o_mdeg;  // monomial recursion: parent, KL variable, first of each degree
+  int o_cs, o_gs, o_rs, o_ra, o_minv;  // FP64: s_col, 1/s_gam^2, s_row, 1/s_row, 1/delta_var
+  const int* blob;
 };
 
 struct Level {
@@ -130,7 +133,10 @@ void launch_apply(hipStream_t s, int n, int na, const double* a, const RowSetDev
                   const double* U, int64_t Nh, const double* rin, double beta, double sgn,
                   double* out, double* edge);
 size_t apply_lds_bytes(int maxcols, int kc, int maxent);
-size_t fapply_lds_bytes(int qb, int nrows, int ncols, int ngam, int nmono, int M);
+constexpr int kDenseK = 1024;  // padded inner index of the dense coarse operator (>= 31^2)
+void launch_dense_coarse(hipStream_t s, int N, int m, const double* C, const double* B, double* X);
+void launch_unit_columns(hipStream_t s, int N, int j0, int m, double* out);
+size_t fapply_lds_bytes(int qb, int nrows, int ncols, int ngam, int nmono, int M, int nblob);
 void launch_fapply(hipStream_t s, int n, double mu, double a_min, const double* g,
                    const FRowSetDev& rs, const double* U, int64_t Nh, const double* rin,
                    double beta, double sgn, double* out, double* edge);

@@ -495,198 +495,289 @@ void launch_apply(hipStream_t s, int n, int na, const double* a, const RowSetDev
 // eq. dataProjection is exact up to degree 2p, so this is the same matrix K.
 // Only g_n(x_q) (M values per Gauss point) is read instead of n_a coefficient
 // modes, and the per-point contraction costs 2 nnz(T) products instead of
-// nnz(G).
+// nnz(G).  The factorials are folded into scaled gradients and monomials (see
+// FRowSetDev), so a record is one 32-bit (slot, monomial) word.
 //
 // One workgroup per 4x4-element tile; its 64 Gauss points are taken in
-// sub-batches of qb points (64: the whole tile, 32: 4x2 elements, 16: 2x2,
-// 8: 2x1).  Thread t handles point t % qb of the sub-batch for the rows of
-// row group t / qb.  Per sub-batch:
-//   1. nodal values of the column modes and g_n at the points -> LDS;
-//   2. reference gradients grad U_alpha -> LDS, w(x_q);
-//   3. monomials g^delta for every delta in J(p), degree by degree;
-//   4. V_gamma = sum_alpha c_{alpha,gamma} g^(alpha-gamma) grad U_alpha -> LDS;
-//   5. flux_beta = a_min grad U_beta + w sum_gamma c_{beta,gamma} g^(beta-gamma) V_gamma;
-//   6. element-node contributions (1/4) grad phi_a . flux_beta, summed over the
-//      element's four points by lane shuffles, added into the tile's 5x5 node
-//      sums in a fixed order (sub-batch, then local corner of the element).
-// The tile's nodes are then written as in the triple-product apply: owned
-// nodes to out, right/top edge and corner to the edge buffer for the fixup.
+// sub-batches of QB points (64: the whole tile, 32: 4x2 elements, 16: 2x2,
+// 8: 2x1).  Thread t handles point t % QB of the sub-batch for the rows of
+// row group t / QB.  Per sub-batch:
+//   1. nodal values of the column modes and g_n at the points -> LDS (loaded
+//      into registers during the previous sub-batch);
+//   2. scaled gradients G^_alpha, w(x_q), scaled monomials m_delta;
+//   3. step 1: Vbar_gamma -> LDS;
+//   4. step 2: flux_beta, then the element-node contributions (1/4) grad phi_a .
+//      flux_beta, summed over the element's four points by lane shuffles.
+// With QB = 64 a row group is one wavefront holding the whole tile: its
+// records are wave-uniform (scalar loads), and the 25 node sums of a row are
+// gathered across lanes and written at once (owned nodes to out, the right/
+// top edge and corner to the edge buffer for the fixup).  With smaller
+// sub-batches the node sums accumulate in LDS over the sub-batches in a fixed
+// order (sub-batch, then local corner of the element) and are written at the
+// end of the tile.
 // ---------------------------------------------------------------------------
 namespace {
-__host__ __device__ inline int fa_sub_w(int qb) { return qb <= 16 ? 2 : 4; }
+template <int QB>
+struct FaGeom {
+  static constexpr int SW = QB <= 16 ? 2 : 4;  // elements per sub-batch row
+  static constexpr int SH = QB / (4 * SW);     // element rows per sub-batch
+  static constexpr int NND = (SW + 1) * (SH + 1);
+  static constexpr int NSUB = kTileQ / QB;
+  static constexpr int SUBS_X = kTileE / SW;
+  static constexpr int LOG = QB == 8 ? 3 : QB == 16 ? 4 : QB == 32 ? 5 : 6;
+};
 __host__ __device__ inline int fa_nodes(int qb) {
-  const int sw = fa_sub_w(qb), sh = qb / (4 * sw);
+  const int sw = qb <= 16 ? 2 : 4, sh = qb / (4 * sw);
   return (sw + 1) * (sh + 1);
 }
 __host__ __device__ inline int fa_even(int x) { return (x + 1) & ~1; }
+constexpr int kFPre = 10;  // prefetch registers per thread (nodal values + g of a sub-batch)
+
+// LDS layout, in doubles: tables | node sums (QB < 64) | G^ [ncols][QB] |
+// Vbar [ngam][QB] (nodal values alias it) | m [P + 1][QB] | w [QB] | g [M][QB]
+struct FaLds {
+  int node, grad, vgam, mono, w, g, total;
+};
+__host__ __device__ inline FaLds fa_layout(int qb, int nrows, int ncols, int ngam, int nmono,
+                                           int M, int nblob) {
+  FaLds L;
+  L.node = fa_even(nblob) / 2;
+  L.grad = L.node + (qb == 64 ? 0 : fa_even(nrows * 25));
+  L.vgam = L.grad + (ncols > 1 ? ncols : 1) * qb * 2;
+  const int vsz = (ngam > 1 ? ngam : 1) * qb * 2, nsz = fa_even(ncols * fa_nodes(qb));
+  L.mono = L.vgam + (vsz > nsz ? vsz : nsz);
+  L.w = L.mono + fa_even((nmono + 1) * qb);
+  L.g = L.w + qb;
+  L.total = L.g + fa_even(M * qb);
+  return L;
+}
 }  // namespace
 
-size_t fapply_lds_bytes(int qb, int nrows, int ncols, int ngam, int nmono, int M) {
-  const size_t node = fa_even(nrows * 25);
-  const size_t grad = (size_t)std::max(ncols, 1) * qb * 2;
-  const size_t vgam = (size_t)std::max(ngam, 1) * qb * 2;
-  const size_t mono = fa_even(std::max(nmono * qb, ncols * fa_nodes(qb)));
-  const size_t wg = fa_even(qb * (M + 1));
-  return 8 * (node + grad + vgam + mono + wg);
+size_t fapply_lds_bytes(int qb, int nrows, int ncols, int ngam, int nmono, int M, int nblob) {
+  return 8 * (size_t)fa_layout(qb, nrows, ncols, ngam, nmono, M, nblob).total;
 }
 
+template <int QB>
 __device__ __forceinline__ void fapply_tile(double* smem, int tile, int n, double mu,
                                             double a_min, const double* __restrict__ g,
-                                            const FRowSetDev& rs, const double* __restrict__ U,
-                                            int64_t Nh, const double* __restrict__ rin,
-                                            double beta, double sgn, double* __restrict__ out,
+                                            const FRowSetDev& rs, const int* __restrict__ blob,
+                                            const double* __restrict__ U, int64_t Nh,
+                                            const double* __restrict__ rin, double beta,
+                                            double sgn, double* __restrict__ out,
                                             double* __restrict__ edge) {
+  using Geo = FaGeom<QB>;
+  constexpr int SW = Geo::SW, SH = Geo::SH, NND = Geo::NND, LOG = Geo::LOG;
   const int nt = n / kTileE;
   const int ntiles = nt * nt;
   const int tx = tile % nt, ty = tile / nt;
   const int x0 = tx * kTileE, y0 = ty * kTileE;
   const int tid = threadIdx.x;
-  const int qb = rs.qb;
-  const int q = tid & (qb - 1);
-  const int grp = tid / qb;
+  const int q = tid & (QB - 1);
+  const int grp = QB == 64 ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid >> LOG;
   const int64_t Nq = (int64_t)4 * n * n;
   const int m = n - 1;
-  const int M = rs.M, ncols = rs.ncols, nrows = rs.nrows, rmax = rs.rmax;
-  const int sw = fa_sub_w(qb), sh = qb / (4 * sw), nnd = (sw + 1) * (sh + 1);
-  const int nsub = kTileQ / qb, subs_x = kTileE / sw;
+  const int M = rs.M, ncols = rs.ncols, nrows = rs.nrows, rmax = rs.rmax, P = rs.nmono;
 
-  double* sNode = smem;                                                  // [nrows][25]
-  double2* sG = reinterpret_cast<double2*>(smem + fa_even(nrows * 25));  // [ncols][qb]
-  double2* sV = sG + (size_t)max(ncols, 1) * qb;                         // [ngam][qb]
-  double* sM = reinterpret_cast<double*>(sV + (size_t)max(rs.ngam, 1) * qb);
-  double* sW = sM + fa_even(max(rs.nmono * qb, ncols * nnd));            // [qb]
-  double* sg = sW + qb;                                                  // [M][qb]
+  const FaLds L = fa_layout(QB, nrows, ncols, rs.ngam, P, M, rs.nblob);
+  int* sB = reinterpret_cast<int*>(smem);
+  double* sNode = smem + L.node;                               // [nrows][25], QB < 64
+  double2* sG = reinterpret_cast<double2*>(smem + L.grad);     // [ncols][QB]
+  double2* sV = reinterpret_cast<double2*>(smem + L.vgam);     // [ngam][QB]
+  double* sN = smem + L.vgam;                                  // nodal values [ncols][NND]
+  double* sM = smem + L.mono;                                  // [P + 1][QB]
+  double* sW = smem + L.w;                                     // [QB]
+  double* sg = smem + L.g;                                     // [M][QB]
 
-  for (int i = tid; i < nrows * 25; i += 256) sNode[i] = 0.0;
+  const int* tcols = sB + rs.o_cols;
+  const int* tmpar = sB + rs.o_mpar;
+  const int* tmvar = sB + rs.o_mvar;
+  const int* tmdeg = sB + rs.o_mdeg;
+  const double* tcs = reinterpret_cast<const double*>(sB + rs.o_cs);
+  const double* tgs = reinterpret_cast<const double*>(sB + rs.o_gs);
+  const double* trs = reinterpret_cast<const double*>(sB + rs.o_rs);
+  const double* tra = reinterpret_cast<const double*>(sB + rs.o_ra);
+  const double* tminv = reinterpret_cast<const double*>(sB + rs.o_minv);
+  // row lists and records: wave-uniform global reads for QB = 64, LDS otherwise
+  const int2* rr1 = reinterpret_cast<const int2*>((QB == 64 ? blob : sB) + rs.o_r1) + grp * rmax;
+  const int2* rr2 = reinterpret_cast<const int2*>((QB == 64 ? blob : sB) + rs.o_r2) + grp * rmax;
+  const int* rdcol = (QB == 64 ? blob : sB) + rs.o_dcol;
+  const int4* re1 = reinterpret_cast<const int4*>((QB == 64 ? blob : sB) + rs.o_e1);
+  const int4* re2 = reinterpret_cast<const int4*>((QB == 64 ? blob : sB) + rs.o_e2);
 
-  const int* l1 = rs.l1 + grp * rmax;
-  const int* l2 = rs.l2 + grp * rmax;
+  // nodal values of the column modes, then g_n at the points, of sub-batch sb
+  const int nnod = ncols * NND, nitems = nnod + M * QB;
+  auto fetch = [&](const int* __restrict__ cols, int sb, int base, double* v) {
+    const int ex0 = (sb % Geo::SUBS_X) * SW, ey0 = (sb / Geo::SUBS_X) * SH;
+#pragma unroll
+    for (int u = 0; u < kFPre; ++u) {
+      const int idx = base + tid + u * 256;
+      double x = 0.0;
+      if (idx < nnod) {
+        const int c = idx / NND, nd = idx - c * NND;
+        const int gx = x0 + ex0 + nd % (SW + 1), gy = y0 + ey0 + nd / (SW + 1);
+        if (gx >= 1 && gx <= m && gy >= 1 && gy <= m)
+          x = U[(int64_t)cols[c] * Nh + (int64_t)(gy - 1) * m + (gx - 1)];
+      } else if (idx < nitems) {
+        const int j = idx - nnod, nn = j >> LOG, qq = j & (QB - 1);
+        const int el = qq >> 2;
+        const int elx = ex0 + el % SW, ely = ey0 + el / SW;
+        x = g[(int64_t)nn * Nq + (int64_t)tile * kTileQ + (ely * kTileE + elx) * 4 + (qq & 3)];
+      }
+      v[u] = x;
+    }
+  };
+  auto store = [&](int base, const double* v) {
+#pragma unroll
+    for (int u = 0; u < kFPre; ++u) {
+      const int idx = base + tid + u * 256;
+      if (idx < nnod) sN[idx] = v[u];
+      else if (idx < nitems) sg[idx - nnod] = v[u];
+    }
+  };
+  const bool prefetch = nitems <= kFPre * 256;
+  double pre[kFPre];
+  // the first sub-batch's loads overlap the table staging (column ids from global)
+  if (prefetch) fetch(blob + rs.o_cols, 0, 0, pre);
+  // tables -> LDS with 16-byte loads, eight in flight per thread (nblob % 4 == 0)
+  {
+    const int n4 = rs.nblob >> 2;
+    const int4* src = reinterpret_cast<const int4*>(blob);
+    int4* dst = reinterpret_cast<int4*>(sB);
+    for (int base = tid; base < n4; base += 256 * 8) {
+      int4 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = src[min(base + u * 256, n4 - 1)];  // clamped, no branch
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (base + u * 256 < n4) dst[base + u * 256] = v[u];
+    }
+  }
+  if (QB < 64)
+    for (int i = tid; i < nrows * 25; i += 256) sNode[i] = 0.0;
+  for (int i = tid; i < QB; i += 256) sM[P * QB + i] = 0.0;
+  __syncthreads();
+
   const int ql = q & 3;
   const double xi = gauss_pt(ql & 1), eta = gauss_pt(ql >> 1);
   double gpx[4], gpy[4];
 #pragma unroll
   for (int a4 = 0; a4 < 4; ++a4) ref_grad(a4, xi, eta, gpx[a4], gpy[a4]);
+  // QB = 64: lane l < 25 gathers node (l % 5, l / 5) from the lanes holding the
+  // corner contributions of its (up to) four elements
+  const int gnx = tid % 5, gny = (tid & 63) / 5;
+  int src[4];
+  bool has[4];
+#pragma unroll
+  for (int a4 = 0; a4 < 4; ++a4) {
+    const int ex = gnx - (a4 & 1), ey = gny - (a4 >> 1);
+    has[a4] = (tid & 63) < 25 && ex >= 0 && ex < 4 && ey >= 0 && ey < 4;
+    src[a4] = has[a4] ? ((ey * 4 + ex) * 4 + a4) * 4 : 0;  // byte index for ds_bpermute
+  }
 
-  for (int sb = 0; sb < nsub; ++sb) {
-    const int ex0 = (sb % subs_x) * sw, ey0 = (sb / subs_x) * sh;
-    __syncthreads();  // the previous sub-batch is done with sG, sV and sM
-    // 1. nodal values of the column modes, g_n at the points
-    for (int base = tid; base < ncols * nnd; base += 256 * 4) {
-      double v[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int idx = base + u * 256;
-        v[u] = 0.0;
-        if (idx < ncols * nnd) {
-          const int c = idx / nnd, nd = idx - c * nnd;
-          const int gx = x0 + ex0 + nd % (sw + 1), gy = y0 + ey0 + nd / (sw + 1);
-          if (gx >= 1 && gx <= m && gy >= 1 && gy <= m)
-            v[u] = U[(int64_t)rs.cols[c] * Nh + (int64_t)(gy - 1) * m + (gx - 1)];
-        }
+  for (int sb = 0; sb < Geo::NSUB; ++sb) {
+    const int ex0 = (sb % Geo::SUBS_X) * SW, ey0 = (sb / Geo::SUBS_X) * SH;
+    if (sb > 0) __syncthreads();  // the previous sub-batch is done with sV, sM and sg
+    if (prefetch) {
+      store(0, pre);
+    } else {
+      for (int base = 0; base < nitems; base += kFPre * 256) {
+        double v[kFPre];
+        fetch(tcols, sb, base, v);
+        store(base, v);
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (base + u * 256 < ncols * nnd) sM[base + u * 256] = v[u];
-    }
-    for (int idx = tid; idx < M * qb; idx += 256) {
-      const int nn = idx / qb, qq = idx - nn * qb;
-      const int el = qq >> 2;
-      const int elx = ex0 + el % sw, ely = ey0 + el / sw;
-      sg[idx] = g[(int64_t)nn * Nq + (int64_t)tile * kTileQ + (ely * kTileE + elx) * 4 + (qq & 3)];
     }
     __syncthreads();
-    // 2. reference gradients and w
-    for (int idx = tid; idx < ncols * qb; idx += 256) {
-      const int c = idx / qb, qq = idx - c * qb;
+    if (prefetch && sb + 1 < Geo::NSUB) fetch(tcols, sb + 1, 0, pre);  // in flight meanwhile
+    // scaled gradients, w, monomials of degree 0 and 1
+    for (int idx = tid; idx < ncols * QB; idx += 256) {
+      const int c = idx >> LOG, qq = idx & (QB - 1);
       const int el = qq >> 2, qp = qq & 3;
-      const int lx = el % sw, ly = el / sw;
+      const int lx = el % SW, ly = el / SW;
       const double xq = gauss_pt(qp & 1), yq = gauss_pt(qp >> 1);
-      const double* u = sM + c * nnd;
-      const double u00 = u[ly * (sw + 1) + lx], u10 = u[ly * (sw + 1) + lx + 1];
-      const double u01 = u[(ly + 1) * (sw + 1) + lx], u11 = u[(ly + 1) * (sw + 1) + lx + 1];
-      sG[idx] = make_double2((1.0 - yq) * (u10 - u00) + yq * (u11 - u01),
-                             (1.0 - xq) * (u01 - u00) + xq * (u11 - u10));
+      const double* u = sN + c * NND;
+      const double u00 = u[ly * (SW + 1) + lx], u10 = u[ly * (SW + 1) + lx + 1];
+      const double u01 = u[(ly + 1) * (SW + 1) + lx], u11 = u[(ly + 1) * (SW + 1) + lx + 1];
+      const double s = tcs[c];
+      sG[idx] = make_double2(s * ((1.0 - yq) * (u10 - u00) + yq * (u11 - u01)),
+                             s * ((1.0 - xq) * (u01 - u00) + xq * (u11 - u10)));
     }
-    if (tid < qb) {
+    if (tid < QB) {
       double s2 = 0.0;
-      for (int nn = 0; nn < M; ++nn) s2 = fma(sg[nn * qb + tid], sg[nn * qb + tid], s2);
+      for (int nn = 0; nn < M; ++nn) s2 = fma(sg[nn * QB + tid], sg[nn * QB + tid], s2);
       sW[tid] = exp(mu + 0.5 * s2);
     }
-    __syncthreads();
-    // 3. monomials: degrees 0 and 1 directly, then degree by degree
-    for (int idx = tid; idx < rs.mdeg[2] * qb; idx += 256) {
-      const int d = idx / qb, qq = idx - d * qb;
-      sM[idx] = d == 0 ? 1.0 : sg[rs.mvar[d] * qb + qq];
+    for (int idx = tid; idx < tmdeg[2] * QB; idx += 256) {
+      const int d = idx >> LOG, qq = idx & (QB - 1);
+      sM[idx] = d == 0 ? 1.0 : sg[tmvar[d] * QB + qq];
     }
     for (int deg = 2; deg <= rs.pdeg; ++deg) {
       __syncthreads();
-      const int d0 = rs.mdeg[deg], cnt = (rs.mdeg[deg + 1] - d0) * qb;
+      const int d0 = tmdeg[deg], cnt = (tmdeg[deg + 1] - d0) * QB;
       for (int idx = tid; idx < cnt; idx += 256) {
-        const int d = d0 + idx / qb, qq = idx % qb;
-        sM[d * qb + qq] = sM[rs.mpar[d] * qb + qq] * sg[rs.mvar[d] * qb + qq];
+        const int d = d0 + (idx >> LOG), qq = idx & (QB - 1);
+        sM[d * QB + qq] = sM[tmpar[d] * QB + qq] * sg[tmvar[d] * QB + qq] * tminv[d];
       }
     }
     __syncthreads();
-    // 4. step 1: V_gamma for this group's gamma rows
+    const double* mq = sM + q;
+    const double2* gq = sG + q;
+    double2* vq = sV + q;
+    // sum over records [4 b, 4 e) of m_(record) * X_(record slot) at this point;
+    // up to four record groups are loaded before the first is used
+    auto contract = [&](const int4* __restrict__ rec, const double2* __restrict__ xq, int b,
+                        int e, double& sx, double& sy) {
+      for (int t = b; t < e; t += 4) {
+        int4 E[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) E[u] = rec[min(t + u, e - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (t + u < e) {
+            const int ks[4] = {E[u].x, E[u].y, E[u].z, E[u].w};
+            double mv[4];
+            double2 xv[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              mv[k] = mq[(ks[k] >> 16) << LOG];
+              xv[k] = xq[(ks[k] & 0xffff) << LOG];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              sx = fma(mv[k], xv[k].x, sx);
+              sy = fma(mv[k], xv[k].y, sy);
+            }
+          }
+        }
+      }
+    };
+    // step 1: Vbar for this group's gamma rows (overwrites the nodal values)
     for (int r = 0; r < rmax; ++r) {
-      const int s1 = l1[r];
-      if (s1 < 0) break;
+      const int2 rw = rr1[r];
+      if (rw.x < 0) break;
       double sx = 0.0, sy = 0.0;
-      const int b = rs.p1[s1], e = rs.p1[s1 + 1];
-      for (int t = b; t < e; t += kEntryUnroll) {
-        Entry en[kEntryUnroll];
-#pragma unroll
-        for (int u = 0; u < kEntryUnroll; ++u) en[u] = rs.e1[t + u];
-        double mv[kEntryUnroll];
-        double2 gg[kEntryUnroll];
-#pragma unroll
-        for (int u = 0; u < kEntryUnroll; ++u) {
-          mv[u] = sM[(en[u].kj >> 16) * qb + q];
-          gg[u] = sG[(en[u].kj & 0xffff) * qb + q];
-        }
-#pragma unroll
-        for (int u = 0; u < kEntryUnroll; ++u) {
-          const double c = en[u].v * mv[u];
-          sx = fma(c, gg[u].x, sx);
-          sy = fma(c, gg[u].y, sy);
-        }
-      }
-      sV[s1 * qb + q] = make_double2(sx, sy);
+      contract(re1, gq, rw.y & 0xffff, (unsigned)rw.y >> 16, sx, sy);
+      const double sc = tgs[rw.x];
+      vq[rw.x << LOG] = make_double2(sx * sc, sy * sc);
     }
     __syncthreads();
-    // 5.-6. step 2 and node sums, row by row
+    // step 2 and the node contributions, row by row
     const double w = sW[q];
     const int el = q >> 2;
-    const int nloc = (ey0 + el / sw + (ql >> 1)) * 5 + ex0 + el % sw + (ql & 1);
+    const int nloc = (ey0 + el / SW + (ql >> 1)) * 5 + ex0 + el % SW + (ql & 1);
     for (int r = 0; r < rmax; ++r) {
-      const int s2 = l2[r];
-      if (s2 < 0) break;
+      const int2 rw = rr2[r];
+      if (rw.x < 0) break;
+      const int s2 = rw.x;
       double sx = 0.0, sy = 0.0;
-      const int b = rs.p2[s2], e = rs.p2[s2 + 1];
-      for (int t = b; t < e; t += kEntryUnroll) {
-        Entry en[kEntryUnroll];
-#pragma unroll
-        for (int u = 0; u < kEntryUnroll; ++u) en[u] = rs.e2[t + u];
-        double mv[kEntryUnroll];
-        double2 vv[kEntryUnroll];
-#pragma unroll
-        for (int u = 0; u < kEntryUnroll; ++u) {
-          mv[u] = sM[(en[u].kj >> 16) * qb + q];
-          vv[u] = sV[(en[u].kj & 0xffff) * qb + q];
-        }
-#pragma unroll
-        for (int u = 0; u < kEntryUnroll; ++u) {
-          const double c = en[u].v * mv[u];
-          sx = fma(c, vv[u].x, sx);
-          sy = fma(c, vv[u].y, sy);
-        }
-      }
-      double flx = w * sx, fly = w * sy;
-      const int dc = rs.dcol[s2];
+      contract(re2, vq, rw.y & 0xffff, (unsigned)rw.y >> 16, sx, sy);
+      const double sr = trs[s2] * w;
+      double flx = sr * sx, fly = sr * sy;
+      const int dc = rdcol[s2];
       if (dc >= 0) {
-        const double2 gu = sG[dc * qb + q];
-        flx = fma(a_min, gu.x, flx);
-        fly = fma(a_min, gu.y, fly);
+        const double2 gu = gq[dc << LOG];
+        const double am = a_min * tra[s2];
+        flx = fma(am, gu.x, flx);
+        fly = fma(am, gu.y, fly);
       }
       double c4[4];
 #pragma unroll
@@ -697,21 +788,52 @@ __device__ __forceinline__ void fapply_tile(double* smem, int tile, int n, doubl
         c4[a4] += __shfl_xor(c4[a4], 2);
       }
       const double mine = (ql == 0) ? c4[0] : (ql == 1) ? c4[1] : (ql == 2) ? c4[2] : c4[3];
-      double* dst = sNode + s2 * 25 + nloc;
-      // the same local corner of distinct elements is a distinct node, so one
-      // phase per corner gives a fixed summation order without atomics; a row
-      // belongs to one group, whose lanes all sit in one wavefront
+      if (QB == 64) {
+        // node (gnx, gny) = corner 3 of element (x-1, y-1) + corner 2 of (x, y-1)
+        //                 + corner 1 of (x-1, y) + corner 0 of (x, y), in that order
+        const long long bits = __double_as_longlong(mine);
+        const int lo = (int)bits, hi = (int)(bits >> 32);
+        double sum = 0.0;
 #pragma unroll
-      for (int a4 = 0; a4 < 4; ++a4) {
-        if (ql == a4) *dst += mine;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int k = 3; k >= 0; --k) {
+          const int l2 = __builtin_amdgcn_ds_bpermute(src[k], lo);
+          const int h2 = __builtin_amdgcn_ds_bpermute(src[k], hi);
+          const double v = __longlong_as_double(((long long)h2 << 32) | (unsigned)l2);
+          if (has[k]) sum += v;
+        }
+        if ((tid & 63) < 25) {
+          if (gnx <= 3 && gny <= 3) {
+            const int gx = x0 + gnx, gy = y0 + gny;
+            if (gx >= 1 && gy >= 1) {
+              const int64_t node = (int64_t)(gy - 1) * m + (gx - 1);
+              double base = 0.0;
+              if (beta != 0.0) base = beta * rin[(int64_t)blob[rs.o_rows + s2] * Nh + node];
+              out[(int64_t)s2 * Nh + node] = base + sgn * sum;
+            }
+          } else {
+            const int ei = (gnx == 4 && gny == 4) ? 8 : (gnx == 4 ? gny : 4 + gnx);
+            edge[((int64_t)s2 * ntiles + tile) * kEdgeVals + ei] = sum;
+          }
+        }
+      } else {
+        double* dst = sNode + s2 * 25 + nloc;
+        // the same local corner of distinct elements is a distinct node, so one
+        // phase per corner gives a fixed summation order without atomics; a row
+        // belongs to one group, whose lanes all sit in one wavefront
+#pragma unroll
+        for (int a4 = 0; a4 < 4; ++a4) {
+          if (ql == a4) *dst += mine;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
       }
     }
   }
+  if (QB == 64) return;
   __syncthreads();
   // tile nodes: owned -> out, right/top edge and corner -> edge buffer
+  const int* trows = sB + rs.o_rows;
   for (int idx = tid; idx < nrows * 25; idx += 256) {
     const int slot = idx / 25, nd = idx - slot * 25;
     const int nx = nd % 5, ny = nd / 5;
@@ -721,7 +843,7 @@ __device__ __forceinline__ void fapply_tile(double* smem, int tile, int n, doubl
       if (gx >= 1 && gy >= 1) {
         const int64_t node = (int64_t)(gy - 1) * m + (gx - 1);
         double base = 0.0;
-        if (beta != 0.0) base = beta * rin[(int64_t)rs.rows[slot] * Nh + node];
+        if (beta != 0.0) base = beta * rin[(int64_t)trows[slot] * Nh + node];
         out[(int64_t)slot * Nh + node] = base + sgn * sum;
       }
     } else {
@@ -731,14 +853,16 @@ __device__ __forceinline__ void fapply_tile(double* smem, int tile, int n, doubl
   }
 }
 
+template <int QB>
 __global__ __launch_bounds__(256) void fapply_kernel(int n, double mu, double a_min,
                                                      const double* __restrict__ g, FRowSetDev rs,
+                                                     const int* __restrict__ blob,
                                                      const double* __restrict__ U, int64_t Nh,
                                                      const double* __restrict__ rin, double beta,
                                                      double sgn, double* __restrict__ out,
                                                      double* __restrict__ edge) {
   extern __shared__ double smem[];
-  fapply_tile(smem, blockIdx.x, n, mu, a_min, g, rs, U, Nh, rin, beta, sgn, out, edge);
+  fapply_tile<QB>(smem, blockIdx.x, n, mu, a_min, g, rs, blob, U, Nh, rin, beta, sgn, out, edge);
 }
 
 void launch_fapply(hipStream_t s, int n, double mu, double a_min, const double* g,
@@ -746,11 +870,24 @@ void launch_fapply(hipStream_t s, int n, double mu, double a_min, const double* 
                    double beta, double sgn, double* out, double* edge) {
   const int nt = n / kTileE;
   const int ntiles = nt * nt;
-  const size_t lds = fapply_lds_bytes(rs.qb, rs.nrows, rs.ncols, rs.ngam, rs.nmono, rs.M);
-  if (lds > 160 * 1024 || (rs.qb != 8 && rs.qb != 16 && rs.qb != 32 && rs.qb != 64))
+  const size_t lds =
+      fapply_lds_bytes(rs.qb, rs.nrows, rs.ncols, rs.ngam, rs.nmono, rs.M, rs.nblob);
+  if (lds > 160 * 1024 || rs.ncols < 1 || rs.ncols > 65535 || rs.ngam > 65535 || rs.nblob % 4)
     throw Error(SG_ERR_INTERNAL, "factored apply: bad sub-batch plan");
-  hipLaunchKernelGGL(fapply_kernel, dim3(ntiles), dim3(256), lds, s, n, mu, a_min, g, rs, U, Nh,
-                     rin, beta, sgn, out, edge);
+  switch (rs.qb) {
+#define SG_FAPPLY_CASE(Q)                                                                    \
+  case Q:                                                                                    \
+    hipLaunchKernelGGL(fapply_kernel<Q>, dim3(ntiles), dim3(256), lds, s, n, mu, a_min, g,   \
+                       rs, rs.blob, U, Nh, rin, beta, sgn, out, edge);                       \
+    break;
+    SG_FAPPLY_CASE(8)
+    SG_FAPPLY_CASE(16)
+    SG_FAPPLY_CASE(32)
+    SG_FAPPLY_CASE(64)
+#undef SG_FAPPLY_CASE
+    default:
+      throw Error(SG_ERR_INTERNAL, "factored apply: bad sub-batch size");
+  }
   const int64_t total = (int64_t)rs.nrows * ntiles * 7;
   hipLaunchKernelGGL(apply_fixup_kernel, dim3(cdiv(total, 256)), dim3(256), 0, s, n, rs.nrows,
                      sgn, edge, out, Nh);
@@ -1180,23 +1317,51 @@ __device__ __forceinline__ void vcoarse_mode(double* lds, int mode, const Coarse
   const int nth = blockDim.x;
   int off[kMaxCoarseLevels];
   int tot = 0;
-  for (int l = 0; l < cl.nl; ++l) {
+#pragma unroll
+  for (int l = 0; l < kMaxCoarseLevels; ++l) {
     off[l] = tot;
-    tot += (int)cl.N[l];
+    if (l < cl.nl) tot += (int)cl.N[l];
   }
   double* S = lds;                 // 9 x tot
   double* B = S + 9 * tot;
   double* X = B + tot;
   double* T = X + tot;
   double* R = T + tot;
-  for (int l = 0; l < cl.nl; ++l) {
-    const int N = (int)cl.N[l];
-    const double* src = sel_stencil(cl.S[l], N, smode, mode);
-    for (int e = tid; e < 9 * N; e += nth) S[9 * off[l] + e] = src[e];
-  }
+  // stencils of every coarse level and the right-hand side -> LDS as one flat
+  // range, eight loads in flight per thread
   {
-    const int N = (int)cl.N[0];
-    for (int e = tid; e < N; e += nth) B[e] = bglob[(int64_t)mode * N + e];
+    const double* src[kMaxCoarseLevels];
+#pragma unroll
+    for (int l = 0; l < kMaxCoarseLevels; ++l)
+      src[l] = l < cl.nl ? sel_stencil(cl.S[l], cl.N[l], smode, mode) : cl.S[0];
+    const int N0 = (int)cl.N[0];
+    const int tot9 = 9 * tot, all = tot9 + N0;
+    for (int base = tid; base < all; base += nth * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = min(base + u * nth, all - 1);
+        if (e >= tot9) {
+          v[u] = bglob[(int64_t)mode * N0 + (e - tot9)];
+        } else {
+          const double* p = src[0];
+          int o = 0;
+#pragma unroll
+          for (int l = 1; l < kMaxCoarseLevels; ++l)
+            if (l < cl.nl && e >= 9 * off[l]) {
+              p = src[l];
+              o = 9 * off[l];
+            }
+          v[u] = p[e - o];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = base + u * nth;
+        if (e < tot9) S[e] = v[u];
+        else if (e < all) B[e - tot9] = v[u];
+      }
+    }
   }
   __syncthreads();
   // descend
@@ -1270,6 +1435,107 @@ __global__ __launch_bounds__(256) void vcoarse_kernel(CoarseLevels cl, const int
                                                       double* __restrict__ xglob, double omega) {
   extern __shared__ double lds[];
   vcoarse_mode(lds, blockIdx.x, cl, smode, bglob, xglob, omega);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse part of the V-cycle as a dense operator.  From a level with
+// n <= kDenseN down, one V(2,2) cycle with zero initial guess is a fixed linear
+// map x = C b of the level's (n-1)^2 unknowns; C is built once by running the
+// cycle's own kernels on unit vectors and then applied to a batch of modes as
+// X = C B (C, B, X column-major, leading dimension N).  One workgroup per
+// 16 x 16 output tile; the tile's 16 columns of B are staged in LDS; the four
+// wavefronts split the inner index and their partial tiles are summed in a
+// fixed order.
+// ---------------------------------------------------------------------------
+__global__ void unit_columns_kernel(int N, int j0, int m, double* __restrict__ out) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)N * m) return;
+  const int k = (int)(gid / N), i = (int)(gid - (int64_t)k * N);
+  out[gid] = (i == j0 + k) ? 1.0 : 0.0;
+}
+
+void launch_unit_columns(hipStream_t s, int N, int j0, int m, double* out) {
+  hipLaunchKernelGGL(unit_columns_kernel, dim3(cdiv((int64_t)N * m, 256)), dim3(256), 0, s, N, j0,
+                     m, out);
+}
+
+// One 512-thread workgroup per 16 x 16 output tile: the tile's 16 columns of B
+// (inner index padded to kDenseK) are staged in LDS, each of the 8 wavefronts
+// takes 128 inner indices (two batches of 64 matrix loads, the second in
+// flight while the first is used), and the 8 partial tiles are summed in a
+// fixed order.
+__global__ __launch_bounds__(512) void dense_coarse_kernel(int N, int m,
+                                                           const double* __restrict__ C,
+                                                           const double* __restrict__ B,
+                                                           double* __restrict__ X) {
+  extern __shared__ double smem[];
+  double* Bs = smem;                        // [kDenseK][16], rows >= N zero
+  double* red = smem + (size_t)kDenseK * 16;  // [8][256]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int r0 = blockIdx.x * 16, k0 = blockIdx.y * 16, ncol = min(16, m - k0);
+  const int r = lane & 15, cg = (lane >> 4) * 4;
+  const double* Cr = C + min(r0 + r, N - 1);
+  const int jw = wave * (kDenseK / 8);
+  constexpr int D = 32;  // matrix loads per batch; 4 batches, the next one in flight
+  double a[D], an[D];
+#pragma unroll
+  for (int u = 0; u < D; ++u) a[u] = Cr[(int64_t)min(jw + u, N - 1) * N];  // clamped
+  {
+    // thread t stages column t % 16, rows t / 16 + 32 s
+    const int c = tid & 15, j0 = tid >> 4;
+    const double* Bc = B + (int64_t)(k0 + min(c, ncol - 1)) * N;
+    double v[kDenseK / 32];
+#pragma unroll
+    for (int u = 0; u < kDenseK / 32; ++u) v[u] = Bc[min(j0 + 32 * u, N - 1)];
+#pragma unroll
+    for (int u = 0; u < kDenseK / 32; ++u) {
+      const int j = j0 + 32 * u;
+      Bs[j * 16 + c] = (c < ncol && j < N) ? v[u] : 0.0;
+    }
+  }
+  __syncthreads();
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const double* Bw = Bs + jw * 16 + cg;
+#pragma unroll
+  for (int bt = 0; bt < kDenseK / 8 / D; ++bt) {
+    if (bt + 1 < kDenseK / 8 / D) {
+#pragma unroll
+      for (int u = 0; u < D; ++u) an[u] = Cr[(int64_t)min(jw + (bt + 1) * D + u, N - 1) * N];
+    }
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      const double2 b01 = *reinterpret_cast<const double2*>(Bw + (bt * D + u) * 16);
+      const double2 b23 = *reinterpret_cast<const double2*>(Bw + (bt * D + u) * 16 + 2);
+      acc[0] = fma(a[u], b01.x, acc[0]);
+      acc[1] = fma(a[u], b01.y, acc[1]);
+      acc[2] = fma(a[u], b23.x, acc[2]);
+      acc[3] = fma(a[u], b23.y, acc[3]);
+    }
+#pragma unroll
+    for (int u = 0; u < D; ++u) a[u] = an[u];
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) red[wave * 256 + v * 64 + lane] = acc[v];
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double x = red[v * 64 + lane];
+#pragma unroll
+      for (int w = 1; w < 8; ++w) x += red[w * 256 + v * 64 + lane];
+      const int c = cg + v;
+      if (r0 + r < N && c < ncol) X[(int64_t)(k0 + c) * N + r0 + r] = x;
+    }
+  }
+}
+
+void launch_dense_coarse(hipStream_t s, int N, int m, const double* C, const double* B,
+                         double* X) {
+  if (N < 1 || N > kDenseK || m < 1) throw Error(SG_ERR_INTERNAL, "dense coarse operator: size");
+  const size_t lds = 8 * ((size_t)kDenseK * 16 + 8 * 256);
+  hipLaunchKernelGGL(dense_coarse_kernel, dim3(cdiv(N, 16), cdiv(m, 16)), dim3(512), lds, s, N, m,
+                     C, B, X);
 }
 
 size_t vcoarse_lds_bytes(const CoarseLevels& cl) {
@@ -1464,11 +1730,13 @@ __global__ __launch_bounds__(256) void bvcoarse_kernel(const BInst* __restrict__
     if (gated(Ss[w.inst], gate)) continue;
     CoarseLevels cl{};
     cl.nl = I.nlev - I.nfine;
-    for (int l = 0; l < cl.nl; ++l) {
-      cl.n[l] = I.L[I.nfine + l].n;
-      cl.N[l] = I.L[I.nfine + l].N;
-      cl.S[l] = I.L[I.nfine + l].S;
-    }
+#pragma unroll
+    for (int l = 0; l < kMaxCoarseLevels; ++l)
+      if (l < cl.nl) {
+        cl.n[l] = I.L[I.nfine + l].n;
+        cl.N[l] = I.L[I.nfine + l].N;
+        cl.S[l] = I.L[I.nfine + l].S;
+      }
     const double* b = I.nfine == 0 ? I.fsT : I.mg_b[I.nfine];
     double* x = I.nfine == 0 ? I.fsX : I.mg_x[I.nfine];
     vcoarse_mode(lds, w.local, cl, nullptr, b, x, 8.0 / 9.0);
