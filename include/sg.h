@@ -152,9 +152,12 @@ int sg_rhs(sg_handle* h, double* F, void* stream);
 int sg_apply(sg_handle* h, const double* U, double* W, void* stream);
 
 /* Chooses the apply form used by sg_apply, sg_residual, the field-split
- * preconditioner and sg_gmres_solve.  points_per_batch (FACTORED only): Gauss
- * points per sub-batch of a 4x4-element tile, 8, 16, 32 or 64, or 0 for the
- * planner's choice.  Re-uploads the plan on `stream` when the handle is bound
+ * preconditioner and sg_gmres_solve.  points_per_batch (FACTORED only): 0
+ * selects the register-resident kernel where it is compiled (chaos spaces of
+ * at most 35 modes: M <= 3 with p <= 4, M = 4 with p <= 3, M <= 6 with
+ * p <= 2), else the LDS tile kernel with the planner's sub-batch size;
+ * 8, 16, 32 or 64 select the LDS tile kernel with that many Gauss points per
+ * sub-batch of a 4x4-element tile.  Re-uploads the plan on `stream` when the handle is bound
  * and synchronises it.  Errors: INVALID_ARG (unknown kind or size),
  * UNSUPPORTED (FACTORED with q < 2p, or a size whose LDS exceeds 160 KB; the
  * previous plan stays in place).                                            */

@@ -105,8 +105,12 @@ struct sg_handle {
   std::vector<int> mpar, mvar, mdeg;  // monomial recursion over J(p)
   std::vector<double> minv, sfac;     // 1/delta_n of the recursion; s_alpha = prod sqrt(alpha_n!)
   bool factored_ok = false;           // q >= 2p: the factored apply is exact
-  bool use_factored = false;          // apply form in use
+  bool use_factored = false;          // apply form in use: factored ...
+  bool use_rapply = false;            // ... in registers (else the LDS tile kernel)
+  bool rapply_ok = false;             // register form compiled for (M, p) and P <= 64
   int fqb = 0;                        // forced sub-batch size (0: planner's choice)
+  RApplyRows rfull{};                 // register-form rows: whole operator
+  std::vector<RApplyRows> rpart[4];   // and the field-split blocks (index 0 unused)
   FSHost fs[4];
   std::vector<int> level_n;
   std::vector<int> diag_ptr, diag_k, diag_sid;  // per mode i: [G_k]_{ii} != 0 entries
@@ -646,7 +650,10 @@ void vcycle(sg_handle& H, hipStream_t s, int m, const int* smode, const double* 
 }
 
 void do_apply(sg_handle& H, hipStream_t s, const double* U, double* W) {
-  if (H.use_factored)
+  if (H.use_factored && H.use_rapply)
+    launch_rapply(s, H.M, H.prob.p, H.n, H.prob.mu, H.prob.a_min, H.d.g, H.rfull, U, H.Nh,
+                  nullptr, 0.0, 1.0, W, H.d.edge);
+  else if (H.use_factored)
     launch_fapply(s, H.n, H.prob.mu, H.prob.a_min, H.d.g, H.d.ffull, U, H.Nh, nullptr, 0.0, 1.0,
                   W, H.d.edge);
   else
@@ -674,7 +681,10 @@ void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double*
     if (sp == 0) {
       launch_gather_modes(s, m, fd.split_idx[0], H.Nh, r, H.d.fsT);
     } else {
-      if (H.use_factored)
+      if (H.use_factored && H.use_rapply)
+        launch_rapply(s, H.M, H.prob.p, H.n, H.prob.mu, H.prob.a_min, H.d.g, H.rpart[grouping][sp],
+                      z, H.Nh, r, 1.0, -1.0, H.d.fsT, H.d.edge);
+      else if (H.use_factored)
         launch_fapply(s, H.n, H.prob.mu, H.prob.a_min, H.d.g, fd.fpartial[sp], z, H.Nh, r, 1.0,
                       -1.0, H.d.fsT, H.d.edge);
       else
@@ -792,6 +802,34 @@ int setup_impl(const sg_problem* prob, const double* f_nodal, int force_kc, sg_h
       } catch (const Error& e) {
         if (e.code != SG_ERR_UNSUPPORTED) throw;
         H->factored_ok = H->use_factored = false;
+      }
+    }
+    // register form: the compiled chaos table must be this handle's J(p)
+    H->rapply_ok = H->factored_ok && H->P <= 64 && rapply_supported(H->M, prob->p) &&
+                   rapply_matches(H->M, prob->p, H->Jp);
+    H->use_rapply = H->rapply_ok;
+    if (H->rapply_ok) {
+      auto rows = [&](const std::vector<int>& outm, const std::vector<int>& colm) {
+        RApplyRows r{};
+        for (int c : colm) r.colmask |= uint64_t(1) << c;
+        std::memset(r.slot, -1, sizeof(r.slot));
+        for (size_t t = 0; t < outm.size(); ++t) {
+          r.rowmask |= uint64_t(1) << outm[t];
+          r.slot[outm[t]] = (signed char)t;
+          r.mode[t] = (unsigned char)outm[t];
+        }
+        r.nrows = (int)outm.size();
+        return r;
+      };
+      H->rfull = rows(all, all);
+      for (int g = 0; g < 4; ++g) {
+        FSHost& fh = H->fs[g];
+        H->rpart[g].assign(fh.splits.size(), RApplyRows{});
+        std::vector<int> prev = fh.splits[0];
+        for (size_t sp = 1; sp < fh.splits.size(); ++sp) {
+          H->rpart[g][sp] = rows(fh.splits[sp], prev);
+          prev.insert(prev.end(), fh.splits[sp].begin(), fh.splits[sp].end());
+        }
       }
     }
     for (int ln = H->n; ln >= 2; ln /= 2) {
@@ -958,6 +996,8 @@ int sg_set_apply(sg_handle* h, int kind, int points_per_batch, void* stream) {
       }
     }
     H.use_factored = kind == SG_APPLY_AUTO ? H.factored_ok : kind == SG_APPLY_FACTORED;
+    // the register form unless a sub-batch size of the LDS tile kernel was asked for
+    H.use_rapply = H.use_factored && H.rapply_ok && qb == 0;
     return SG_OK;
   } catch (const Error& e) {
     return fail(e.code, e.what());

@@ -117,6 +117,16 @@ struct FRowSetDev {
   const int* blob;
 };
 
+// Rows of the register-resident factored apply (P <= 35): column modes and
+// output modes as bit masks over J(p); slot[beta] is the output slot of mode
+// beta (compact output layout), mode[slot] its mode id.
+struct RApplyRows {
+  uint64_t colmask, rowmask;
+  int nrows;
+  signed char slot[64];
+  unsigned char mode[64];
+};
+
 struct Level {
   int n;          // elements per side on this level
   int64_t N;      // (n-1)^2
@@ -136,6 +146,13 @@ size_t apply_lds_bytes(int maxcols, int kc, int maxent);
 constexpr int kDenseK = 1024;  // padded inner index of the dense coarse operator (>= 31^2)
 void launch_dense_coarse(hipStream_t s, int N, int m, const double* C, const double* B, double* X);
 void launch_unit_columns(hipStream_t s, int N, int j0, int m, double* out);
+bool rapply_supported(int M, int p);
+bool rapply_matches(int M, int p, const std::vector<std::vector<int>>& Jp);
+void launch_rapply(hipStream_t s, int M, int p, int n, double mu, double a_min, const double* g,
+                   const RApplyRows& rr, const double* U, int64_t Nh, const double* rin,
+                   double beta, double sgn, double* out, double* edge);
+void launch_apply_fixup(hipStream_t s, int n, int nrows, double sgn, const double* edge,
+                        double* out, int64_t Nh);
 size_t fapply_lds_bytes(int qb, int nrows, int ncols, int ngam, int nmono, int M, int nblob);
 void launch_fapply(hipStream_t s, int n, double mu, double a_min, const double* g,
                    const FRowSetDev& rs, const double* U, int64_t Nh, const double* rin,

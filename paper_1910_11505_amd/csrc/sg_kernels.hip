@@ -447,6 +447,14 @@ __global__ void apply_fixup_kernel(int n, int nrows, double sgn, const double* _
   apply_fixup_item(gid, n, sgn, edge, out, Nh);
 }
 
+void launch_apply_fixup(hipStream_t s, int n, int nrows, double sgn, const double* edge,
+                        double* out, int64_t Nh) {
+  const int nt = n / kTileE;
+  const int64_t total = (int64_t)nrows * nt * nt * 7;
+  hipLaunchKernelGGL(apply_fixup_kernel, dim3(cdiv(total, 256)), dim3(256), 0, s, n, nrows, sgn,
+                     edge, out, Nh);
+}
+
 size_t apply_lds_bytes(int maxcols, int kc, int maxent) {
   size_t sa = std::max<size_t>({(size_t)kc * kTileQ, (size_t)maxcols * 25, (size_t)kApplyWaves * kTileQ});
   sa = (sa + 1) & ~size_t(1);  // keeps the entry records 16-byte aligned
@@ -724,8 +732,11 @@ __device__ __forceinline__ void fapply_tile(double* smem, int tile, int n, doubl
     double2* vq = sV + q;
     // sum over records [4 b, 4 e) of m_(record) * X_(record slot) at this point;
     // up to four record groups are loaded before the first is used
+    // (four independent accumulator pairs, one per record position of a group,
+    // summed in a fixed order at the end: FP64 FMA chains are latency-bound)
     auto contract = [&](const int4* __restrict__ rec, const double2* __restrict__ xq, int b,
                         int e, double& sx, double& sy) {
+      double ax[4] = {0.0, 0.0, 0.0, 0.0}, ay[4] = {0.0, 0.0, 0.0, 0.0};
       for (int t = b; t < e; t += 4) {
         int4 E[4];
 #pragma unroll
@@ -743,12 +754,14 @@ __device__ __forceinline__ void fapply_tile(double* smem, int tile, int n, doubl
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-              sx = fma(mv[k], xv[k].x, sx);
-              sy = fma(mv[k], xv[k].y, sy);
+              ax[k] = fma(mv[k], xv[k].x, ax[k]);
+              ay[k] = fma(mv[k], xv[k].y, ay[k]);
             }
           }
         }
       }
+      sx = (ax[0] + ax[1]) + (ax[2] + ax[3]);
+      sy = (ay[0] + ay[1]) + (ay[2] + ay[3]);
     };
     // step 1: Vbar for this group's gamma rows (overwrites the nodal values)
     for (int r = 0; r < rmax; ++r) {
@@ -1495,7 +1508,8 @@ __global__ __launch_bounds__(512) void dense_coarse_kernel(int N, int m,
     }
   }
   __syncthreads();
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  // two accumulator sets (even / odd inner index): eight independent FMA chains
+  double acc2[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
   const double* Bw = Bs + jw * 16 + cg;
 #pragma unroll
   for (int bt = 0; bt < kDenseK / 8 / D; ++bt) {
@@ -1507,14 +1521,18 @@ __global__ __launch_bounds__(512) void dense_coarse_kernel(int N, int m,
     for (int u = 0; u < D; ++u) {
       const double2 b01 = *reinterpret_cast<const double2*>(Bw + (bt * D + u) * 16);
       const double2 b23 = *reinterpret_cast<const double2*>(Bw + (bt * D + u) * 16 + 2);
-      acc[0] = fma(a[u], b01.x, acc[0]);
-      acc[1] = fma(a[u], b01.y, acc[1]);
-      acc[2] = fma(a[u], b23.x, acc[2]);
-      acc[3] = fma(a[u], b23.y, acc[3]);
+      double* ac = acc2[u & 1];
+      ac[0] = fma(a[u], b01.x, ac[0]);
+      ac[1] = fma(a[u], b01.y, ac[1]);
+      ac[2] = fma(a[u], b23.x, ac[2]);
+      ac[3] = fma(a[u], b23.y, ac[3]);
     }
 #pragma unroll
     for (int u = 0; u < D; ++u) a[u] = an[u];
   }
+  double acc[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) acc[v] = acc2[0][v] + acc2[1][v];
 #pragma unroll
   for (int v = 0; v < 4; ++v) red[wave * 256 + v * 64 + lane] = acc[v];
   __syncthreads();
