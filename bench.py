@@ -61,6 +61,10 @@ def _args():
     ap.add_argument("--cpu-iters", type=int, default=24)
     ap.add_argument("--no-c2-apply", action="store_true",
                     help="skip the HBM-bound apply measurement on the 256x256, 924-mode shape")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-stage comparison (learned workload, reduced training)")
+    ap.add_argument("--learned-pairs", type=int, default=640)
+    ap.add_argument("--learned-steps", type=int, default=1200)
     ap.add_argument("--apply-form", default="factored", choices=["factored", "triple"],
                     help="apply form of the counter-collection mode")
     ap.add_argument("--profile-apply", action="store_true",
@@ -115,6 +119,46 @@ def measure_apply_forms(inst, reps, stream):
                      "frac_hbm_peak": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     inst.set_apply("auto")
     return out
+
+
+def learned_comparison(npairs, steps):
+    """The learned workload (Q1 128x128, M=4, p=3, squared-exponential L_c=0.5,
+    sigma ~ U[0.3, 1.5], nodal-noise forcing) with a reduced training budget:
+    pairs from field-split GMRES(5) cycles, Adam training on the GPU, then
+    flexible GMRES(30) with the learned stage against field-split GMRES(50) on
+    two held-out problems, both to the FP64 true relative residual 1e-8."""
+    import numpy as np
+    import paper_1910_11505_amd as sg
+    from paper_1910_11505_amd import learned as L
+    from synth import CONFIGS, cnn_init
+    base = CONFIGS["c4"]
+    probe = L.make_instance(base)
+    P, Nh = probe.P, probe.Nh
+    probe.close()
+    net = sg.CNN(P, base.n, max_batch=16, c0=64, c1=64)
+    Ws, bs = cnn_init(P, 1, c0=64, c1=64)
+    net.set_params(Ws, bs)
+    store = L.PairStore(npairs, P, Nh)
+    t0 = time.perf_counter()
+    gen = L.generate_pairs(net, L.draw_problems(base, 400, 11505 + 4000), store, cycle=5,
+                           max_per_problem=16)
+    _log(f"learned: {gen['pairs']} pairs from {gen['problems']} problems in {gen['seconds']:.1f} s")
+    losses, train_s = L.train(net, store, steps, 16, 1e-3, lr_final=1e-4)
+    _log(f"learned: {steps} Adam steps in {train_s:.1f} s, loss {losses[-1][1]:.3g}")
+    rows = []
+    for prob, f in L.draw_problems(base, 2, 11505 + 4999):
+        c = L.compare(net, prob, f)
+        rows.append({"sigma": c.sigma, "fs_iterations": c.fs_iterations, "fs_s": c.fs_seconds,
+                     "learned_iterations": c.learned_iterations, "learned_s": c.learned_seconds,
+                     "fallbacks": c.fallbacks, "fs_relres": c.fs_relres,
+                     "learned_relres": c.learned_relres})
+        _log(f"learned: sigma {c.sigma:.2f} FS-GMRES(50) {c.fs_iterations} it {c.fs_seconds * 1e3:.1f} ms, "
+             f"learned FGMRES(30) {c.learned_iterations} it {c.learned_seconds * 1e3:.1f} ms")
+    net.close()
+    return {"pairs": gen["pairs"], "train_steps": steps, "train_s": train_s,
+            "final_loss": losses[-1][1], "pair_generation_s": gen["seconds"],
+            "time_ratio_fs_over_learned": float(np.mean([r["fs_s"] / r["learned_s"] for r in rows])),
+            "problems": rows, "total_s": time.perf_counter() - t0}
 
 
 def main():
@@ -208,6 +252,11 @@ def main():
         for f in ("factored", "triple"):
             _log(f"256x256 apply ({f}) {c2_apply[f]['ms']:.3f} ms, {c2_apply[f]['gbs']:.0f} GB/s")
 
+    learned = None
+    if not args.no_learned:
+        torch.cuda.empty_cache()
+        learned = learned_comparison(args.learned_pairs, args.learned_steps)
+
     line = {
         "metric": METRIC,
         "value": ms_fs / 1e3,
@@ -240,6 +289,7 @@ def main():
                                    "product form streams the 110 MB of coefficient modes, which "
                                    "fit the 256 MB last-level cache at this size"),
         "apply_c2_hbm": c2_apply,
+        "learned_vs_field_split": learned,
         "roofline": {
             "kernel": "fapply_kernel (factored SG operator apply) + apply_fixup_kernel",
             "bound": "hbm",

@@ -214,8 +214,10 @@ const char* sg_last_error(void);
  * Errors are reported through sg_cnn_last_error().
  * ------------------------------------------------------------------------- */
 typedef struct sg_cnn sg_cnn;
-/* P in [1, 63] modes, n grid (power of two in [16, 1024]), widths c0 = 32,
- * c1 = 64, max_batch in [1, 256] samples per training step.                */
+/* P in [1, 63] modes, n grid (power of two in [16, 1024]), hidden widths
+ * c0 = 32 or 64 (finest level; 64 passes more than 32 modes through the
+ * finest level), c1 = 64 (coarser levels), max_batch in [1, 256] samples per
+ * training step.                                                            */
 int    sg_cnn_create(int32_t P, int32_t n, int32_t c0, int32_t c1, int32_t max_batch, sg_cnn** out);
 /* number of weights (layers concatenated, each (9, c_out, c_in), tap =
  * 3(dy+1)+(dx+1)) and of biases                                              */

@@ -1376,7 +1376,7 @@ struct LaunchRec {
 
 enum {
   BK_APPLY = 0, BK_FIXUP, BK_VDOWN, BK_VUP, BK_VCOARSE, BK_GATHER, BK_VEC, BK_DOT, BK_REDUCE,
-  BK_GIVENS, BK_SOLVE, BK_INIT
+  BK_GIVENS, BK_SOLVE, BK_INIT, BK_FAPPLY, BK_RAPPLY
 };
 
 struct Plan {
@@ -1480,6 +1480,14 @@ Plan build_plan(sg_batch& B, int pc_kind, int grouping, const double* F, double*
     I.Nv = (int64_t)H.P * H.Nh;
     I.a = D.a;
     I.full = D.full;
+    I.form = H.use_factored ? (H.use_rapply ? 2 : 1) : 0;
+    I.M = H.M;
+    I.pdeg = H.prob.p;
+    I.mu = H.prob.mu;
+    I.amin = H.prob.a_min;
+    I.gq = D.g;
+    if (H.factored_ok) I.ffull = D.ffull;
+    if (H.rapply_ok) I.rfull = H.rfull;
     if (I.nlev > kMaxLevelsB) throw Error(SG_ERR_UNSUPPORTED, "batch: too many grid levels");
     for (int l = 0; l < I.nlev; ++l) {
       I.L[l] = D.L[l];
@@ -1499,6 +1507,8 @@ Plan build_plan(sg_batch& B, int pc_kind, int grouping, const double* F, double*
         I.split_idx[s] = D.fs[grouping].split_idx[s];
         I.split_m[s] = (int)fh.splits[s].size();
         if (s >= 1) I.part[s] = D.fs[grouping].partial[s];
+        if (s >= 1 && H.factored_ok) I.fpart[s] = D.fs[grouping].fpartial[s];
+        if (s >= 1 && H.rapply_ok) I.rpart[s] = H.rpart[grouping][s];
       }
     }
     I.edge = D.edge;
@@ -1539,22 +1549,38 @@ Plan build_plan(sg_batch& B, int pc_kind, int grouping, const double* F, double*
   // persistent launch per rows-per-wavefront class, then the edge fixup
   auto apply_recs = [&](int rowset, int src, int rin, int dst, double beta, double sgn, int gate,
                         std::vector<LaunchRec>& out) {
-    std::map<int, std::pair<std::vector<BItem>, size_t>> classes;
+    // class of an instance: (form, rows per wavefront | sub-batch size | M * 16 + p)
+    std::map<std::pair<int, int>, std::pair<std::vector<BItem>, size_t>> classes;
     std::vector<BItem> tfix;
     for (int i = 0; i < B.count; ++i) {
       const BInst& I = pl.inst[i];
       if (rowset > 0 && rowset >= I.nsplit) continue;
       const RowSetDev& rs = rowset == 0 ? I.full : I.part[rowset];
-      auto& cl = classes[rs.rmax];
+      std::pair<int, int> key;
+      size_t lds;
+      if (I.form == 2) {
+        const RApplyRows& rr = rowset == 0 ? I.rfull : I.rpart[rowset];
+        key = {2, I.M * 16 + I.pdeg};
+        lds = rapply_lds_bytes(I.P, rr.nrows);
+      } else if (I.form == 1) {
+        const FRowSetDev& f = rowset == 0 ? I.ffull : I.fpart[rowset];
+        key = {1, f.qb};
+        lds = fapply_lds_bytes(f.qb, f.nrows, f.ncols, f.ngam, f.nmono, f.M, f.nblob);
+      } else {
+        key = {0, rs.rmax};
+        lds = apply_lds_bytes(rs.maxcols, rs.kc, rs.maxent);
+      }
+      auto& cl = classes[key];
       const int nt = I.n / kTileE;
       for (int t = 0; t < nt * nt; ++t) cl.first.push_back({i, t});
-      cl.second = std::max(cl.second, apply_lds_bytes(rs.maxcols, rs.kc, rs.maxent));
+      cl.second = std::max(cl.second, lds);
       const int64_t fixn = (int64_t)rs.nrows * nt * nt * 7;
       for (int c = 0; c < cdivi(fixn, kVecChunk); ++c) tfix.push_back({i, c});
     }
     for (auto& kv : classes) {
-      LaunchRec r = rec(BK_APPLY, kv.second.first, gate);
-      r.a0 = kv.first;
+      const int kind = kv.first.first == 0 ? BK_APPLY : kv.first.first == 1 ? BK_FAPPLY : BK_RAPPLY;
+      LaunchRec r = rec(kind, kv.second.first, gate);
+      r.a0 = kv.first.second;
       r.a1 = rowset;
       r.a2 = src;
       r.a3 = rin;
@@ -1693,6 +1719,14 @@ void run_recs(sg_batch& B, hipStream_t s, const std::vector<LaunchRec>& recs, do
       case BK_APPLY:
         launch_bapply(s, r.a0, r.lds, B.dI, B.dS, it, r.count, r.a1, r.a2, r.a3, r.a4, r.d0, r.d1,
                       r.gate);
+        break;
+      case BK_FAPPLY:
+        launch_bfapply(s, r.a0, r.lds, B.dI, B.dS, it, r.count, r.a1, r.a2, r.a3, r.a4, r.d0,
+                       r.d1, r.gate);
+        break;
+      case BK_RAPPLY:
+        launch_brapply(s, r.a0 / 16, r.a0 % 16, r.lds, B.dI, B.dS, it, r.count, r.a1, r.a2,
+                       r.a3, r.a4, r.d0, r.d1, r.gate);
         break;
       case BK_FIXUP: launch_bfixup(s, B.dI, B.dS, it, r.count, r.a0, r.a1, r.d0, r.gate); break;
       case BK_VDOWN: launch_bvdown(s, B.dI, B.dS, it, r.count, r.a0, r.a1, r.gate); break;
@@ -1957,7 +1991,17 @@ int sg_batch_solve(sg_batch* b, const sg_solve_opts* o, const double* F, double*
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int key = kind * 16 + (kind == SG_PC_FS ? o->grouping : 0);
     auto itp = B.plans.find(key);
-    if (itp != B.plans.end() && (itp->second.inst[0].F != F || itp->second.inst[0].u != u)) {
+    // a plan is rebuilt when the buffers or an instance's apply form changed
+    auto forms_changed = [&](const Plan& pl) {
+      for (int i = 0; i < B.count; ++i) {
+        const sg_handle& Hi = *B.h[i];
+        const int f = Hi.use_factored ? (Hi.use_rapply ? 2 : 1) : 0;
+        if (pl.inst[i].form != f || (f == 1 && pl.inst[i].ffull.qb != Hi.d.ffull.qb)) return true;
+      }
+      return false;
+    };
+    if (itp != B.plans.end() && (itp->second.inst[0].F != F || itp->second.inst[0].u != u ||
+                                 forms_changed(itp->second))) {
       if (itp->second.gstep) (void)hipGraphExecDestroy(itp->second.gstep);
       if (itp->second.grestart) (void)hipGraphExecDestroy(itp->second.grestart);
       B.plans.erase(itp);

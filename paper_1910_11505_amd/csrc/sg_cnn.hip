@@ -565,7 +565,7 @@ void conv_forward(hipStream_t s, const sg_cnn_impl& C, int l, const bf16_t* X, v
     return;                                                                                  \
   }
   SG_CONV(32, 32, 0) SG_CONV(64, 32, 0) SG_CONV(32, 64, 0) SG_CONV(64, 64, 0)
-  SG_CONV(32, 32, 1) SG_CONV(32, 64, 1)
+  SG_CONV(32, 32, 1) SG_CONV(32, 64, 1) SG_CONV(64, 32, 1) SG_CONV(64, 64, 1)
 #undef SG_CONV
   throw Error(SG_ERR_UNSUPPORTED, "cnn: unsupported layer shape");
 }
@@ -732,7 +732,8 @@ int sg_cnn_create(int32_t P, int32_t n, int32_t c0, int32_t c1, int32_t max_batc
   *out = nullptr;
   if (P < 1 || P > 63) return cfail(SG_ERR_UNSUPPORTED, "P must be in [1, 63] for the network");
   if (n < 16 || n > 1024 || (n & (n - 1))) return cfail(SG_ERR_INVALID_ARG, "n must be a power of two in [16, 1024]");
-  if (c0 != 32 || c1 != 64) return cfail(SG_ERR_UNSUPPORTED, "hidden widths must be 32 and 64");
+  if ((c0 != 32 && c0 != 64) || c1 != 64)
+    return cfail(SG_ERR_UNSUPPORTED, "hidden widths: first level 32 or 64, coarser levels 64");
   if (max_batch < 1 || max_batch > 256) return cfail(SG_ERR_INVALID_ARG, "max_batch in [1, 256]");
   sg_cnn* C = new sg_cnn();
   C->P = P;

@@ -205,6 +205,12 @@ struct BInst {  // one instance of a batch, device-resident
   const double* a;
   RowSetDev full;
   RowSetDev part[kMaxSplitsB];
+  int form;                        // apply: 0 triple products, 1 factored tiles, 2 factored registers
+  int M, pdeg;
+  double mu, amin;
+  const double* gq;                // KL values at the Gauss points (tile order)
+  FRowSetDev ffull, fpart[kMaxSplitsB];
+  RApplyRows rfull, rpart[kMaxSplitsB];
   const int* split_idx[kMaxSplitsB];
   int split_m[kMaxSplitsB];
   Level L[kMaxLevelsB];
@@ -226,11 +232,39 @@ struct BItem {  // one work item of a persistent batched kernel
   int inst, local;
 };
 
+// device helpers of the batched kernels: gate test and buffer-id resolution
+__device__ inline bool gated(const BState& S, int gate) {
+  return gate == 0 ? (S.active == 0) : (S.done != 0);
+}
+
+__device__ inline double* bbuf(const BInst& I, const BState& S, int id) {
+  switch (id) {
+    case BUF_F: return const_cast<double*>(I.F);
+    case BUF_U: return I.u;
+    case BUF_VJ: return I.V + (int64_t)S.j * I.Nv;
+    case BUF_VJ1: return I.V + (int64_t)(S.j + 1) * I.Nv;
+    case BUF_V0: return I.V;
+    case BUF_W: return I.w;
+    case BUF_Z: return I.z;
+    case BUF_T: return I.t;
+    case BUF_FST: return I.fsT;
+    default: return I.fsX;
+  }
+}
+
+
 // gate: 0 = instances still in the current Arnoldi cycle, 1 = instances not done
 constexpr int kVecChunk = 4096;     // elements per item of the batched vector kernels
 void launch_bapply(hipStream_t s, int rmax, size_t lds, const BInst* I, const BState* st,
                    const BItem* items, int nitems, int rowset, int src, int rin, int dst,
                    double beta, double sgn, int gate);
+void launch_bfapply(hipStream_t s, int qb, size_t lds, const BInst* I, const BState* st,
+                    const BItem* items, int nitems, int rowset, int src, int rin, int dst,
+                    double beta, double sgn, int gate);
+void launch_brapply(hipStream_t s, int M, int p, size_t lds, const BInst* I, const BState* st,
+                    const BItem* items, int nitems, int rowset, int src, int rin, int dst,
+                    double beta, double sgn, int gate);
+size_t rapply_lds_bytes(int P, int nrows);
 void launch_bfixup(hipStream_t s, const BInst* I, const BState* st, const BItem* items, int nitems,
                    int rowset, int dst, double sgn, int gate);
 void launch_bvdown(hipStream_t s, const BInst* I, const BState* st, const BItem* items, int nitems,

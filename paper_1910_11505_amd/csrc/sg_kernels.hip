@@ -1602,25 +1602,6 @@ namespace sg {
 
 namespace {
 
-__device__ __forceinline__ bool gated(const BState& S, int gate) {
-  return gate == 0 ? (S.active == 0) : (S.done != 0);
-}
-
-__device__ __forceinline__ double* bbuf(const BInst& I, const BState& S, int id) {
-  switch (id) {
-    case BUF_F: return const_cast<double*>(I.F);
-    case BUF_U: return I.u;
-    case BUF_VJ: return I.V + (int64_t)S.j * I.Nv;
-    case BUF_VJ1: return I.V + (int64_t)(S.j + 1) * I.Nv;
-    case BUF_V0: return I.V;
-    case BUF_W: return I.w;
-    case BUF_Z: return I.z;
-    case BUF_T: return I.t;
-    case BUF_FST: return I.fsT;
-    default: return I.fsX;
-  }
-}
-
 }  // namespace
 
 template <int RMAX>
@@ -1657,6 +1638,45 @@ void launch_bapply(hipStream_t s, int rmax, size_t lds, const BInst* I, const BS
     default: throw Error(SG_ERR_INTERNAL, "batched apply: unsupported rows per wavefront");
   }
 #undef SG_BAPPLY
+}
+
+// factored apply over (instance, tile) items of instances sharing one sub-batch size
+template <int QB>
+__global__ __launch_bounds__(256) void bfapply_kernel(const BInst* __restrict__ Is,
+                                                      const BState* __restrict__ Ss,
+                                                      const BItem* __restrict__ items, int nitems,
+                                                      int rowset, int src, int rin, int dst,
+                                                      double beta, double sgn, int gate) {
+  extern __shared__ double smem[];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BItem w = items[it];
+    const BInst& I = Is[w.inst];
+    const BState& S = Ss[w.inst];
+    if (gated(S, gate)) continue;
+    __syncthreads();  // the previous item is done with the LDS
+    const FRowSetDev& rs = rowset == 0 ? I.ffull : I.fpart[rowset];
+    fapply_tile<QB>(smem, w.local, I.n, I.mu, I.amin, I.gq, rs, rs.blob, bbuf(I, S, src), I.Nh,
+                    rin >= 0 ? bbuf(I, S, rin) : nullptr, beta, sgn, bbuf(I, S, dst), I.edge);
+  }
+}
+
+void launch_bfapply(hipStream_t s, int qb, size_t lds, const BInst* I, const BState* st,
+                    const BItem* items, int nitems, int rowset, int src, int rin, int dst,
+                    double beta, double sgn, int gate) {
+  if (nitems <= 0) return;
+  if (lds > 160 * 1024) throw Error(SG_ERR_INTERNAL, "batched factored apply: LDS");
+  const int per_cu = std::max(1, (int)((160 * 1024) / std::max<size_t>(lds, 1)));
+  const int grid = std::min(nitems, 256 * std::min(per_cu, 4));
+  switch (qb) {
+#define SG_BFAPPLY(Q)                                                                          \
+  case Q:                                                                                      \
+    hipLaunchKernelGGL(bfapply_kernel<Q>, dim3(grid), dim3(256), lds, s, I, st, items, nitems, \
+                       rowset, src, rin, dst, beta, sgn, gate);                                \
+    break;
+    SG_BFAPPLY(8) SG_BFAPPLY(16) SG_BFAPPLY(32) SG_BFAPPLY(64)
+#undef SG_BFAPPLY
+    default: throw Error(SG_ERR_INTERNAL, "batched factored apply: sub-batch size");
+  }
 }
 
 // fixup items: local = chunk of kVecChunk fixup points of the row set

@@ -175,18 +175,16 @@ inline int r_cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 }  // namespace
 
 template <int M, int p>
-__global__ __launch_bounds__(64) void rapply_kernel(int n, double mu, double a_min,
-                                                    const double* __restrict__ g, RApplyRows rr,
-                                                    const double* __restrict__ U, int64_t Nh,
-                                                    const double* __restrict__ rin, double beta,
-                                                    double sgn, double* __restrict__ out,
-                                                    double* __restrict__ edge) {
+__device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, double mu,
+                                            double a_min, const double* __restrict__ g,
+                                            const RApplyRows& rr, const double* __restrict__ U,
+                                            int64_t Nh, const double* __restrict__ rin,
+                                            double beta, double sgn, double* __restrict__ out,
+                                            double* __restrict__ edge) {
   constexpr const RTab<M, p>& T = RTabHolder<M, p>::v;
   constexpr int P = RTab<M, p>::P;
-  extern __shared__ double smem[];
   double* sN = smem;             // [P][25] nodal values
   double* sC = smem + P * 25;    // [nrows][64] corner contributions
-  const int tile = blockIdx.x;
   const int nt = n / kTileE, ntiles = nt * nt;
   const int tx = tile % nt, ty = tile / nt;
   const int x0 = tx * kTileE, y0 = ty * kTileE;
@@ -317,6 +315,39 @@ __global__ __launch_bounds__(64) void rapply_kernel(int n, double mu, double a_m
   }
 }
 
+template <int M, int p>
+__global__ __launch_bounds__(64) void rapply_kernel(int n, double mu, double a_min,
+                                                    const double* __restrict__ g, RApplyRows rr,
+                                                    const double* __restrict__ U, int64_t Nh,
+                                                    const double* __restrict__ rin, double beta,
+                                                    double sgn, double* __restrict__ out,
+                                                    double* __restrict__ edge) {
+  extern __shared__ double smem[];
+  rapply_tile<M, p>(smem, blockIdx.x, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);
+}
+
+// (instance, tile) items of instances sharing one (M, p)
+template <int M, int p>
+__global__ __launch_bounds__(64) void brapply_kernel(const BInst* __restrict__ Is,
+                                                     const BState* __restrict__ Ss,
+                                                     const BItem* __restrict__ items, int nitems,
+                                                     int rowset, int src, int rin, int dst,
+                                                     double beta, double sgn, int gate) {
+  extern __shared__ double smem[];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BItem w = items[it];
+    const BInst& I = Is[w.inst];
+    const BState& S = Ss[w.inst];
+    if (gated(S, gate)) continue;
+    __syncthreads();  // the previous item is done with the LDS
+    const RApplyRows& rr = rowset == 0 ? I.rfull : I.rpart[rowset];
+    rapply_tile<M, p>(smem, w.local, I.n, I.mu, I.amin, I.gq, rr, bbuf(I, S, src), I.Nh,
+                      rin >= 0 ? bbuf(I, S, rin) : nullptr, beta, sgn, bbuf(I, S, dst), I.edge);
+  }
+}
+
+size_t rapply_lds_bytes(int P, int nrows) { return 8 * ((size_t)P * 25 + (size_t)nrows * 64); }
+
 #define SG_RAPPLY_LIST(X) \
   X(1, 1) X(1, 2) X(1, 3) X(1, 4) X(2, 1) X(2, 2) X(2, 3) X(2, 4) X(3, 1) X(3, 2) X(3, 3) \
   X(3, 4) X(4, 1) X(4, 2) X(4, 3) X(5, 1) X(5, 2) X(6, 1) X(6, 2)
@@ -351,7 +382,7 @@ void launch_rapply(hipStream_t s, int M, int p, int n, double mu, double a_min, 
   const int nt = n / kTileE, ntiles = nt * nt;
   const int P = (int)rc_binom(M + p, p);
   if (rr.nrows < 1 || rr.nrows > P) throw Error(SG_ERR_INTERNAL, "register apply: bad rows");
-  const size_t lds = 8 * ((size_t)P * 25 + (size_t)rr.nrows * 64);
+  const size_t lds = rapply_lds_bytes(P, rr.nrows);
 #define SG_RAPPLY_LAUNCH(MM, PP)                                                               \
   if (M == MM && p == PP) {                                                                    \
     hipLaunchKernelGGL((rapply_kernel<MM, PP>), dim3(ntiles), dim3(64), lds, s, n, mu, a_min, \
@@ -360,6 +391,20 @@ void launch_rapply(hipStream_t s, int M, int p, int n, double mu, double a_min, 
   SG_RAPPLY_LIST(SG_RAPPLY_LAUNCH) { throw Error(SG_ERR_INTERNAL, "register apply: (M, p)"); }
 #undef SG_RAPPLY_LAUNCH
   launch_apply_fixup(s, n, rr.nrows, sgn, edge, out, Nh);
+}
+
+void launch_brapply(hipStream_t s, int M, int p, size_t lds, const BInst* I, const BState* st,
+                    const BItem* items, int nitems, int rowset, int src, int rin, int dst,
+                    double beta, double sgn, int gate) {
+  if (nitems <= 0) return;
+  const int grid = std::min(nitems, 256 * 8);
+#define SG_BRAPPLY_LAUNCH(MM, PP)                                                             \
+  if (M == MM && p == PP) {                                                                   \
+    hipLaunchKernelGGL((brapply_kernel<MM, PP>), dim3(grid), dim3(64), lds, s, I, st, items, \
+                       nitems, rowset, src, rin, dst, beta, sgn, gate);                       \
+  } else
+  SG_RAPPLY_LIST(SG_BRAPPLY_LAUNCH) { throw Error(SG_ERR_INTERNAL, "batched register apply: (M, p)"); }
+#undef SG_BRAPPLY_LAUNCH
 }
 
 }  // namespace sg
