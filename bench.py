@@ -29,24 +29,24 @@ sys.path.insert(0, ROOT)
 METRIC = "GMRES time-to-relres-1e-8 (s) + SG apply HBM GB/s; learned-FGMRES vs field-split"
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per apply dispatch on the 128x128 workload from two rocprofv3 --pmc passes
-# (FETCH_SIZE, WRITE_SIZE), scaled by the same counters read on a plain 256 MiB copy
-# (factors 2.0 and 1.0).  Valid only for the apply source they were taken on: the
-# sha256 of the apply section of sg_kernels.hip is compared at run time.
-APPLY_TRAFFIC = {"src_sha256": "356e1f17047c438b59cd7d9250825722eed14474acf6d55cf211a16ab4711af8",
-                 "fetch_bytes": 67722.0 * 1024 * 2.0, "write_bytes": 28185.0 * 1024 * 1.0}
+# HBM bytes per apply dispatch (register-resident factored kernel plus fixup) on the
+# 128x128 workload from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE on
+# rapply_kernel<4,3>), scaled by the same counters read on a plain 256 MiB copy
+# (factors 2.0 and 1.0).  Valid only for the kernel source the counters were taken
+# on: the sha256 of sg_rapply.hip + sg_internal.h is compared at run time.
+APPLY_TRAFFIC = {"src_sha256": "533dc22eb53d33bc768f4d2a8db07240273c034c106834c545777a565bd8619e",
+                 "fetch_bytes": 3613.5625 * 1024 * 2.0, "write_bytes": 6937.0 * 1024 * 1.0}
 
 
 def apply_traffic():
-    """Measured HBM bytes per apply, or None once the apply source has changed."""
+    """Measured HBM bytes per apply, or None once the kernel source has changed."""
     import hashlib
-    path = os.path.join(ROOT, "paper_1910_11505_amd", "csrc", "sg_kernels.hip")
+    csrc = os.path.join(ROOT, "paper_1910_11505_amd", "csrc")
     try:
-        src = open(path).read()
-        sec = src[src.index("// SG operator apply."):src.index("// Folds the edge contributions")]
-    except (OSError, ValueError):
+        src = "".join(open(os.path.join(csrc, f)).read() for f in ("sg_rapply.hip", "sg_internal.h"))
+    except OSError:
         return None
-    if hashlib.sha256(sec.encode()).hexdigest() != APPLY_TRAFFIC["src_sha256"]:
+    if hashlib.sha256(src.encode()).hexdigest() != APPLY_TRAFFIC["src_sha256"]:
         return None
     return APPLY_TRAFFIC["fetch_bytes"] + APPLY_TRAFFIC["write_bytes"]
 
@@ -121,6 +121,40 @@ def measure_apply_forms(inst, reps, stream):
     return out
 
 
+def cpu_baseline(prob, gpu_iters, gpu_restarts, n_iters):
+    """Times the oracle's field-split GMRES on a bounded sample: n_iters Arnoldi
+    steps plus the closing update (n_iters + 1 operator and preconditioner
+    applications), scaled to the GPU's iteration count."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle.gmg import GMGHierarchy
+    from oracle.gmres import gmres
+    from oracle.precond import FieldSplit, make_groups
+    from oracle.system import SGSystem
+
+    S = SGSystem(prob)
+    _ = S.A
+    H = GMGHierarchy(S.A[0], prob.n)
+    fs = FieldSplit(S, H, make_groups(S.Jp, "klvar"))
+    F = S.rhs()
+    t0 = time.perf_counter()
+    gmres(S.apply, fs.apply, F, tol=1e-8, restart=50, max_it=n_iters)
+    dt = time.perf_counter() - t0
+    per_pair = dt / (n_iters + 1)
+    est = per_pair * (gpu_iters + gpu_restarts)
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    return {
+        "value": est, "unit": "s", "cores": int(threads), "kind": "oracle",
+        "sample": (f"oracle FS-GMRES(50) on the same workload, {n_iters} Arnoldi steps + closing "
+                   f"update timed ({dt:.1f} s, {n_iters + 1} operator+preconditioner "
+                   f"applications), scaled to the GPU's {gpu_iters} iterations + "
+                   f"{gpu_restarts} closing updates; set-up excluded; host has "
+                   f"{os.cpu_count()} logical CPUs, sparse kernels single-threaded, BLAS "
+                   f"threads {threads}"),
+    }
+
+
 def learned_comparison(npairs, steps):
     """The learned workload (Q1 128x128, M=4, p=3, squared-exponential L_c=0.5,
     sigma ~ U[0.3, 1.5], nodal-noise forcing) with a reduced training budget:
@@ -147,10 +181,10 @@ def learned_comparison(npairs, steps):
     _log(f"learned: {steps} Adam steps in {train_s:.1f} s, loss {losses[-1][1]:.3g}")
     rows = []
     for prob, f in L.draw_problems(base, 2, 11505 + 4999):
-        c = L.compare(net, prob, f)
+        c = L.compare(net, prob, f, max_it=1000)
         rows.append({"sigma": c.sigma, "fs_iterations": c.fs_iterations, "fs_s": c.fs_seconds,
                      "learned_iterations": c.learned_iterations, "learned_s": c.learned_seconds,
-                     "fallbacks": c.fallbacks, "fs_relres": c.fs_relres,
+                     "fallbacks": c.fallbacks, "fs_relres": c.fs_relres, "max_it": 1000,
                      "learned_relres": c.learned_relres})
         _log(f"learned: sigma {c.sigma:.2f} FS-GMRES(50) {c.fs_iterations} it {c.fs_seconds * 1e3:.1f} ms, "
              f"learned FGMRES(30) {c.learned_iterations} it {c.learned_seconds * 1e3:.1f} ms")
@@ -291,13 +325,13 @@ def main():
         "apply_c2_hbm": c2_apply,
         "learned_vs_field_split": learned,
         "roofline": {
-            "kernel": "fapply_kernel (factored SG operator apply) + apply_fixup_kernel",
+            "kernel": "rapply_kernel<4,3> (register-resident factored SG apply) + apply_fixup_kernel",
             "bound": "hbm",
             "achieved": apply_gbs,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": apply_gbs / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": apply_traffic(),
         },
     }
     if not args.no_cpu_baseline:

@@ -57,6 +57,15 @@ __host__ __device__ inline int64_t tiled_q(int n, int ex, int ey, int qx, int qy
   return t * kTileQ + el * 4 + qy * 2 + qx;
 }
 
+// Workgroup index -> tile index for one-tile-per-workgroup launches: the
+// hardware deals workgroups round-robin over the 8 XCDs (each with its own
+// L2), so consecutive workgroup ids are spread to give every XCD a contiguous
+// band of tiles, whose shared halo rows then stay in that XCD's L2.
+__host__ __device__ inline int xcd_tile(int wg, int ntiles) {
+  if (ntiles % 8) return wg;
+  return (wg & 7) * (ntiles >> 3) + (wg >> 3);
+}
+
 // ---- device-side descriptors -----------------------------------------------
 // A row set of the operator: output modes `rows`, their nonzero triple
 // products bucketed by coefficient-mode chunk, and the input columns whose

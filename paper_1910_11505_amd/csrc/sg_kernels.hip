@@ -875,7 +875,9 @@ __global__ __launch_bounds__(256) void fapply_kernel(int n, double mu, double a_
                                                      double sgn, double* __restrict__ out,
                                                      double* __restrict__ edge) {
   extern __shared__ double smem[];
-  fapply_tile<QB>(smem, blockIdx.x, n, mu, a_min, g, rs, blob, U, Nh, rin, beta, sgn, out, edge);
+  const int nt = n / kTileE;
+  fapply_tile<QB>(smem, xcd_tile(blockIdx.x, nt * nt), n, mu, a_min, g, rs, blob, U, Nh, rin,
+                  beta, sgn, out, edge);
 }
 
 void launch_fapply(hipStream_t s, int n, double mu, double a_min, const double* g,

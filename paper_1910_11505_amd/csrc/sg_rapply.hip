@@ -323,7 +323,9 @@ __global__ __launch_bounds__(64) void rapply_kernel(int n, double mu, double a_m
                                                     double sgn, double* __restrict__ out,
                                                     double* __restrict__ edge) {
   extern __shared__ double smem[];
-  rapply_tile<M, p>(smem, blockIdx.x, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);
+  const int nt = n / kTileE;
+  rapply_tile<M, p>(smem, xcd_tile(blockIdx.x, nt * nt), n, mu, a_min, g, rr, U, Nh, rin, beta,
+                    sgn, out, edge);
 }
 
 // (instance, tile) items of instances sharing one (M, p)

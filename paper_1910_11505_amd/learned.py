@@ -131,7 +131,7 @@ class Comparison:
 
 
 def compare(net: "sg.CNN", prob: Problem, f_nodal=None, tol=1e-8, fs_restart=50,
-            learned_restart=30, grouping="klvar", repeats: int = 1):
+            learned_restart=30, grouping="klvar", repeats: int = 1, max_it: int = 5000):
     """Plain field-split GMRES(fs_restart) against flexible GMRES(learned_restart)
     with the learned stage, both to the true relative residual tol."""
     import torch
@@ -140,11 +140,12 @@ def compare(net: "sg.CNN", prob: Problem, f_nodal=None, tol=1e-8, fs_restart=50,
     inst.attach(net, prob.sigma)
     out = {}
     for name, pc, restart in (("fs", "fs", fs_restart), ("learned", "learned", learned_restart)):
-        inst.solve(F, pc=pc, grouping=grouping, tol=tol, restart=restart)
+        inst.solve(F, pc=pc, grouping=grouping, tol=tol, restart=restart, max_it=max_it)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(repeats):
-            u, info, _ = inst.solve(F, pc=pc, grouping=grouping, tol=tol, restart=restart)
+            u, info, _ = inst.solve(F, pc=pc, grouping=grouping, tol=tol, restart=restart,
+                                    max_it=max_it)
         torch.cuda.synchronize()
         out[name] = (info, (time.perf_counter() - t0) / repeats)
     inst.attach(None, 0.0)
