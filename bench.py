@@ -61,6 +61,9 @@ def _args():
     ap.add_argument("--cpu-iters", type=int, default=24)
     ap.add_argument("--no-c2-apply", action="store_true",
                     help="skip the HBM-bound apply measurement on the 256x256, 924-mode shape")
+    ap.add_argument("--sigma-sweep", action="store_true",
+                    help="also solve the 256x256, P=84 sigma sweep (0.5, 1.0, 1.5) with the "
+                         "mean-based and field-split preconditioners")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-stage comparison (learned workload, reduced training)")
     ap.add_argument("--learned-pairs", type=int, default=640)
@@ -153,6 +156,44 @@ def cpu_baseline(prob, gpu_iters, gpu_restarts, n_iters):
                    f"{os.cpu_count()} logical CPUs, sparse kernels single-threaded, BLAS "
                    f"threads {threads}"),
     }
+
+
+def sigma_sweep(stream, max_it=2000):
+    """The 256x256 workload (L1-exponential covariance L_c=0.25, M=6, p=3, P=84,
+    q=6, f = 1 + 0.1 N(0,1) nodal noise) at sigma 0.5, 1.0, 1.5: mean-based and
+    field-split GMRES(50) to the FP64 true relative residual 1e-8 (capped at
+    max_it iterations)."""
+    import torch
+    import paper_1910_11505_amd as sg
+    from synth import CONFIGS, rhs_noisy
+    base = CONFIGS["c2"]
+    f = rhs_noisy(base.n, 11505 + 2000)
+    out = []
+    for sigma in (0.5, 1.0, 1.5):
+        p = base.with_(sigma=sigma)
+        inst = sg.SGInstance(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma, p.corr_len, p.a_min,
+                             f_nodal=f)
+        F = inst.rhs()
+        row = {"sigma": sigma}
+        for pc in ("mean", "fs"):
+            u = inst.vec()
+            inst.solve(F, pc=pc, grouping="klvar", restart=50, tol=1e-8, u=u, max_it=50)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            _, info, _ = inst.solve(F, pc=pc, grouping="klvar", restart=50, tol=1e-8, u=u,
+                                    max_it=max_it)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            row[pc] = {"s": e0.elapsed_time(e1) / 1e3, "iterations": info.iterations,
+                       "relres": info.relres, "status": info.status}
+            _log(f"256x256 sigma {sigma}: {pc} {info.iterations} it, relres {info.relres:.2e}, "
+                 f"{e0.elapsed_time(e1):.1f} ms")
+        inst.close()
+        torch.cuda.empty_cache()
+        out.append(row)
+    return out
 
 
 def learned_comparison(npairs, steps):
@@ -286,6 +327,7 @@ def main():
         for f in ("factored", "triple"):
             _log(f"256x256 apply ({f}) {c2_apply[f]['ms']:.3f} ms, {c2_apply[f]['gbs']:.0f} GB/s")
 
+    sweep = sigma_sweep(stream) if args.sigma_sweep else None
     learned = None
     if not args.no_learned:
         torch.cuda.empty_cache()
@@ -324,6 +366,7 @@ def main():
                                    "fit the 256 MB last-level cache at this size"),
         "apply_c2_hbm": c2_apply,
         "learned_vs_field_split": learned,
+        "sigma_sweep_256x256_p84": sweep,
         "roofline": {
             "kernel": "rapply_kernel<4,3> (register-resident factored SG apply) + apply_fixup_kernel",
             "bound": "hbm",

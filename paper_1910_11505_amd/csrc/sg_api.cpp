@@ -555,7 +555,8 @@ void carve(const sg_handle& H, DevPtrs& D, Carver& c) {
     const size_t sz = (size_t)H.P * D.L[l].N;
     if (l > 0) {
       D.mg_b[l] = c.take<double>(sz);
-      D.mg_x[l] = c.take<double>(sz);
+      // the dense operator below the finest level writes kDenseSlices partial results
+      D.mg_x[l] = c.take<double>((int)l == H.ldense ? kDenseSlices * sz : sz);
     }
     D.mg_xa[l] = c.take<double>(sz);
     D.mg_r[l] = c.take<double>(sz);
@@ -602,11 +603,14 @@ void check_launch() {
 
 // One V(2,2) cycle for m modes starting at level l0: b and x hold m compact
 // vectors of that level; smode (device, may be null) gives each mode's stencil id.
+// bmap / xmap (device, may be null; l0 must be a fused fine level): mode t reads
+// vector bmap[t] of b and writes vector xmap[t] of x.
 void vcycle_levels(sg_handle& H, hipStream_t s, int l0, int m, const int* smode, const double* b,
-                   double* x) {
+                   double* x, const int* bmap = nullptr, const int* xmap = nullptr) {
   DevPtrs& D = H.d;
   const int nf = H.nfine;
   const int nl = (int)D.L.size();
+  if ((bmap || xmap) && l0 >= nf) throw Error(SG_ERR_INTERNAL, "mode maps need a fused level");
   std::vector<const double*> bl(nl);
   std::vector<double*> xl(nl);
   for (int l = l0 + 1; l < nl; ++l) {
@@ -617,7 +621,8 @@ void vcycle_levels(sg_handle& H, hipStream_t s, int l0, int m, const int* smode,
   xl[l0] = x;
   const int c0 = std::max(nf, l0);
   for (int l = l0; l < nf; ++l)
-    launch_vdown(s, D.L[l], D.L[l + 1], m, smode, bl[l], D.mg_xa[l], D.mg_b[l + 1], kOmega);
+    launch_vdown(s, D.L[l], D.L[l + 1], m, smode, bl[l], D.mg_xa[l], D.mg_b[l + 1], kOmega,
+                 l == l0 ? bmap : nullptr);
   CoarseLevels cl{};
   cl.nl = nl - c0;
   for (int l = 0; l < cl.nl; ++l) {
@@ -627,15 +632,23 @@ void vcycle_levels(sg_handle& H, hipStream_t s, int l0, int m, const int* smode,
   }
   launch_vcoarse(s, cl, m, smode, bl[c0], xl[c0], kOmega);
   for (int l = nf - 1; l >= l0; --l)
-    launch_vup(s, D.L[l], D.L[l + 1], m, smode, bl[l], D.mg_xa[l], xl[l + 1], xl[l], kOmega);
+    launch_vup(s, D.L[l], D.L[l + 1], m, smode, bl[l], D.mg_xa[l], xl[l + 1], xl[l], kOmega,
+               l == l0 ? bmap : nullptr, l == l0 ? xmap : nullptr);
+}
+
+// Whether vcycle() can read and write through mode maps (the finest level is a
+// fused kernel pair or the dense operator).
+bool vcycle_maps_ok(const sg_handle& H, const int* smode) {
+  return H.nfine > 0 || (!smode && H.dense_ready);
 }
 
 // One V(2,2) cycle on the finest level.  With the mean stiffness (smode null)
 // the levels from H.ldense down are one precomputed dense operator (the same
 // linear map, built by vcycle_levels on unit vectors at bind).
-void vcycle(sg_handle& H, hipStream_t s, int m, const int* smode, const double* b, double* x) {
+void vcycle(sg_handle& H, hipStream_t s, int m, const int* smode, const double* b, double* x,
+            const int* bmap = nullptr, const int* xmap = nullptr) {
   if (smode || !H.dense_ready) {
-    vcycle_levels(H, s, 0, m, smode, b, x);
+    vcycle_levels(H, s, 0, m, smode, b, x, bmap, xmap);
     return;
   }
   DevPtrs& D = H.d;
@@ -643,10 +656,16 @@ void vcycle(sg_handle& H, hipStream_t s, int m, const int* smode, const double* 
   auto bl = [&](int l) -> const double* { return l == 0 ? b : D.mg_b[l]; };
   auto xl = [&](int l) -> double* { return l == 0 ? x : D.mg_x[l]; };
   for (int l = 0; l < ld; ++l)
-    launch_vdown(s, D.L[l], D.L[l + 1], m, nullptr, bl(l), D.mg_xa[l], D.mg_b[l + 1], kOmega);
-  launch_dense_coarse(s, (int)D.L[ld].N, m, D.Cd, bl(ld), xl(ld));
+    launch_vdown(s, D.L[l], D.L[l + 1], m, nullptr, bl(l), D.mg_xa[l], D.mg_b[l + 1], kOmega,
+                 l == 0 ? bmap : nullptr);
+  // below the finest level the operator runs in kDenseSlices inner-index
+  // slices whose partial results the next finer vup sums
+  const int slices = ld == 0 ? 1 : kDenseSlices;
+  launch_dense_coarse(s, (int)D.L[ld].N, m, D.Cd, bl(ld), xl(ld), ld == 0 ? bmap : nullptr,
+                      ld == 0 ? xmap : nullptr, slices);
   for (int l = ld - 1; l >= 0; --l)
-    launch_vup(s, D.L[l], D.L[l + 1], m, nullptr, bl(l), D.mg_xa[l], xl(l + 1), xl(l), kOmega);
+    launch_vup(s, D.L[l], D.L[l + 1], m, nullptr, bl(l), D.mg_xa[l], xl(l + 1), xl(l), kOmega,
+               l == 0 ? bmap : nullptr, l == 0 ? xmap : nullptr, l == ld - 1 ? slices : 1);
 }
 
 void do_apply(sg_handle& H, hipStream_t s, const double* U, double* W) {
@@ -678,7 +697,14 @@ void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double*
   const FSDev& fd = H.d.fs[grouping];
   for (size_t sp = 0; sp < fh.splits.size(); ++sp) {
     const int m = (int)fh.splits[sp].size();
+    const int* smode = kii ? fd.split_sid[sp] : nullptr;
+    const bool maps = vcycle_maps_ok(H, smode);
     if (sp == 0) {
+      // the gather is folded into the cycle's finest level when it can be
+      if (maps) {
+        vcycle(H, s, m, smode, r, z, fd.split_idx[0], fd.split_idx[0]);
+        continue;
+      }
       launch_gather_modes(s, m, fd.split_idx[0], H.Nh, r, H.d.fsT);
     } else {
       if (H.use_factored && H.use_rapply)
@@ -691,8 +717,12 @@ void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double*
         launch_apply(s, H.n, H.na, H.d.a, fd.partial[sp], z, H.Nh, r, 1.0, -1.0, H.d.fsT,
                      H.d.edge);
     }
-    vcycle(H, s, m, kii ? fd.split_sid[sp] : nullptr, H.d.fsT, H.d.fsX);
-    launch_scatter_modes(s, m, fd.split_idx[sp], H.Nh, H.d.fsX, z);
+    if (maps) {
+      vcycle(H, s, m, smode, H.d.fsT, z, nullptr, fd.split_idx[sp]);
+    } else {
+      vcycle(H, s, m, smode, H.d.fsT, H.d.fsX);
+      launch_scatter_modes(s, m, fd.split_idx[sp], H.Nh, H.d.fsX, z);
+    }
   }
 }
 
@@ -819,6 +849,18 @@ int setup_impl(const sg_problem* prob, const double* f_nodal, int force_kc, sg_h
           r.mode[t] = (unsigned char)outm[t];
         }
         r.nrows = (int)outm.size();
+        // gamma matters iff it lies below some column and below some output row
+        for (int gm = 0; gm < H->P; ++gm) {
+          auto below = [&](const std::vector<int>& set) {
+            for (int a : set) {
+              bool le = true;
+              for (int k = 0; k < H->M; ++k) le = le && H->Jp[gm][k] <= H->Jp[a][k];
+              if (le) return true;
+            }
+            return false;
+          };
+          if (below(colm) && below(outm)) r.gammask |= uint64_t(1) << gm;
+        }
         return r;
       };
       H->rfull = rows(all, all);
@@ -1068,7 +1110,7 @@ size_t krylov_layout(const sg_handle* h, int restart, bool flexible, KrylovWS* k
   K.z = c.take<double>(Nv);
   K.t = c.take<double>(Nv);
   K.x2 = c.take<double>(Nv);
-  K.partial = c.take<double>((size_t)K.nblk * (restart + 1));
+  K.partial = c.take<double>((size_t)std::max(K.nblk, gs_blocks(Nv)) * (restart + 1));
   K.hdev = c.take<double>(2 * (size_t)(restart + 1) + 4);
   K.ydev = c.take<double>(restart + 1);
   return c.off;
@@ -1120,8 +1162,7 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
     int fallbacks = 0;
     double* hp = H.host_pinned;
     auto norm2 = [&](const double* x, double* dst) {
-      launch_multidot(s, x, Nv, 1, x, Nv, K.partial, K.nblk);
-      launch_reduce(s, K.partial, K.nblk, 1, dst);
+      launch_gs_dot(s, x, Nv, 1, x, Nv, K.partial, dst);
     };
     auto fetch = [&](const double* src, int count) {
       SG_HIP(hipMemcpyAsync(hp, src, count * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1185,8 +1226,7 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
           cnn_apply_sg(H.cnn, s, K.x2, H.cnn_sigma, c, K.partial, K.nblk);
           do_apply(H, s, c, K.t);
           double* nn = K.hdev + 2 * (m + 1) + 1;
-          launch_multidot(s, K.x2, Nv, 1, K.t, Nv, K.partial, K.nblk);
-          launch_reduce(s, K.partial, K.nblk, 1, nn);
+          launch_gs_dot(s, K.x2, Nv, 1, K.t, Nv, K.partial, nn);
           norm2(K.t, nn + 1);
           fetch(nn, 2);
           const double rkc = hp[0], kc2 = hp[1];
@@ -1204,13 +1244,11 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
         double* h1 = K.hdev;
         double* h2 = K.hdev + (m + 1);
         double* nrm = K.hdev + 2 * (m + 1);
-        launch_multidot(s, K.V, Nv, j + 1, K.w, Nv, K.partial, K.nblk);
-        launch_reduce(s, K.partial, K.nblk, j + 1, h1);
-        launch_update(s, K.V, Nv, j + 1, h1, K.w, Nv, -1.0);
-        launch_multidot(s, K.V, Nv, j + 1, K.w, Nv, K.partial, K.nblk);
-        launch_reduce(s, K.partial, K.nblk, j + 1, h2);
-        launch_update(s, K.V, Nv, j + 1, h2, K.w, Nv, -1.0);
-        norm2(K.w, nrm);
+        // CGS2: h1 = V^T w, w -= V h1, h2 = V^T w (fused with that update),
+        // w -= V h2 and |w|^2 (fused with the second update)
+        launch_gs_dot(s, K.V, Nv, j + 1, K.w, Nv, K.partial, h1);
+        launch_gs_update_dot(s, K.V, Nv, j + 1, h1, K.w, Nv, -1.0, K.partial, h2);
+        launch_gs_update_norm(s, K.V, Nv, j + 1, h2, K.w, Nv, -1.0, K.partial, nrm);
         launch_scale_by_inv_norm(s, K.w, nrm, K.V + (int64_t)(j + 1) * Nv, Nv);
         check_launch();
         fetch(K.hdev, 2 * (m + 1) + 1);

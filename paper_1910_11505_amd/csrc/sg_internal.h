@@ -24,6 +24,7 @@ constexpr int kEdgeVals = 9;         // right edge 4, top edge 4, corner 1
 constexpr int kMaxP = 256;
 constexpr int kMaxRestart = 200;
 constexpr int kCoarseN = 16;  // levels with n <= kCoarseN run in one LDS kernel
+constexpr int kDenseSlices = 4;  // inner-index slices of the dense operator below the finest level
 constexpr int kDenseN = 32;   // levels with n <= kDenseN: V-cycle applied as a dense operator
 constexpr int kMaxCoarseLevels = 8;
 
@@ -126,11 +127,12 @@ struct FRowSetDev {
   const int* blob;
 };
 
-// Rows of the register-resident factored apply (P <= 35): column modes and
-// output modes as bit masks over J(p); slot[beta] is the output slot of mode
-// beta (compact output layout), mode[slot] its mode id.
+// Rows of the register-resident factored apply (P <= 35): column modes, output
+// modes and the intermediate gamma set as bit masks over J(p); slot[beta] is
+// the output slot of mode beta (compact output layout), mode[slot] its mode id.
 struct RApplyRows {
   uint64_t colmask, rowmask;
+  uint64_t gammask;  // gamma <= some column and <= some output row (step-1 rows that matter)
   int nrows;
   signed char slot[64];
   unsigned char mode[64];
@@ -153,7 +155,8 @@ void launch_apply(hipStream_t s, int n, int na, const double* a, const RowSetDev
                   double* out, double* edge);
 size_t apply_lds_bytes(int maxcols, int kc, int maxent);
 constexpr int kDenseK = 1024;  // padded inner index of the dense coarse operator (>= 31^2)
-void launch_dense_coarse(hipStream_t s, int N, int m, const double* C, const double* B, double* X);
+void launch_dense_coarse(hipStream_t s, int N, int m, const double* C, const double* B, double* X,
+                         const int* bmap = nullptr, const int* xmap = nullptr, int slices = 1);
 void launch_unit_columns(hipStream_t s, int N, int j0, int m, double* out);
 bool rapply_supported(int M, int p);
 bool rapply_matches(int M, int p, const std::vector<std::vector<int>>& Jp);
@@ -179,9 +182,11 @@ struct CoarseLevels {
   const double* S[kMaxCoarseLevels];
 };
 void launch_vdown(hipStream_t s, const Level& Lf, const Level& Lc, int modes, const int* smode,
-                  const double* b, double* x2, double* bc, double omega);
+                  const double* b, double* x2, double* bc, double omega,
+                  const int* bmap = nullptr);
 void launch_vup(hipStream_t s, const Level& Lf, const Level& Lc, int modes, const int* smode,
-                const double* b, const double* x2, const double* xc, double* x, double omega);
+                const double* b, const double* x2, const double* xc, double* x, double omega,
+                const int* bmap = nullptr, const int* xmap = nullptr, int xc_slices = 1);
 void launch_vcoarse(hipStream_t s, const CoarseLevels& cl, int modes, const int* smode,
                     const double* b, double* x, double omega);
 size_t vcoarse_lds_bytes(const CoarseLevels& cl);
@@ -194,6 +199,15 @@ void launch_multidot(hipStream_t s, const double* V, int64_t ldv, int nv, const 
 void launch_reduce(hipStream_t s, const double* partial, int nblk, int nv, double* out);
 void launch_update(hipStream_t s, const double* V, int64_t ldv, int nv, const double* h,
                    double* w, int64_t N, double sign);
+// Gram-Schmidt passes (one element per thread, partial sized nv * gs_blocks(N));
+// each ends with the reduction into out[0..nv) (out[0] for the norm)
+int gs_blocks(int64_t N);
+void launch_gs_dot(hipStream_t s, const double* V, int64_t ldv, int nv, const double* w, int64_t N,
+                   double* partial, double* out);
+void launch_gs_update_dot(hipStream_t s, const double* V, int64_t ldv, int nv, const double* h,
+                          double* w, int64_t N, double sign, double* partial, double* out);
+void launch_gs_update_norm(hipStream_t s, const double* V, int64_t ldv, int nv, const double* h,
+                           double* w, int64_t N, double sign, double* partial, double* out);
 void launch_combine(hipStream_t s, const double* V, int64_t ldv, int nv, const double* y,
                     double* out, int64_t N);
 void launch_scale_by_inv_norm(hipStream_t s, const double* w, const double* nrm2, double* v,

@@ -1021,6 +1021,187 @@ void launch_update(hipStream_t s, const double* V, int64_t ldv, int nv, const do
   hipLaunchKernelGGL(update_kernel, dim3(cdiv(N, 256)), dim3(256), 0, s, V, ldv, nv, h, w, N, sign);
 }
 
+// ---------------------------------------------------------------------------
+// Register-blocked Gram-Schmidt passes.  One element per thread (block b,
+// thread t: element b * kDotThreads + t), all of a thread's basis loads in
+// flight at once, and one reduction per block at the end instead of one per
+// basis vector.  Per-block partial sums go to partial[l * nblk + b] with
+// nblk = ceil(N / kDotThreads) and are summed by reduce_wide_kernel.
+// ---------------------------------------------------------------------------
+int gs_blocks(int64_t N) { return (int)std::max<int64_t>(1, cdiv(N, kDotThreads)); }
+
+// Sums NVB (a power of two <= 64) per-lane values over a wavefront and writes
+// the NVB totals to red[0..NVB).  A butterfly: at each exchange step a lane
+// keeps half of its values and adds the partner lane's copy of that half, so
+// the NVB sums cost NVB - 1 exchanges; after log2(NVB) steps lane L holds the
+// sum for index L >> (6 - log2 NVB) over its lane group, finished by plain
+// exchanges over the remaining lane bits.
+template <int HALF, int OFF, int NVB>
+__device__ __forceinline__ void wave_fold(double (&a)[NVB], int lane) {
+  if constexpr (HALF >= 1) {
+    const bool hi = (lane & OFF) != 0;
+#pragma unroll
+    for (int j = 0; j < HALF; ++j) {
+      const double send = hi ? a[j] : a[j + HALF];
+      const double keep = hi ? a[j + HALF] : a[j];
+      a[j] = keep + __shfl_xor(send, OFF);
+    }
+    wave_fold<HALF / 2, OFF / 2, NVB>(a, lane);
+  }
+}
+
+template <int NVB>
+__device__ __forceinline__ void wave_sums(double (&a)[NVB], double* __restrict__ red) {
+  constexpr int kShift = NVB == 1 ? 6 : NVB == 2 ? 5 : NVB == 4 ? 4 : NVB == 8 ? 3 : NVB == 16 ? 2 : NVB == 32 ? 1 : 0;
+  static_assert((1 << (6 - kShift)) == NVB, "NVB must be a power of two <= 64");
+  const int lane = threadIdx.x & 63;
+  wave_fold<NVB / 2, 32, NVB>(a, lane);
+  double v = a[0];
+#pragma unroll
+  for (int off = (1 << kShift) >> 1; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  if ((lane & ((1 << kShift) - 1)) == 0) red[lane >> kShift] = v;
+}
+
+// Combines the four wavefronts' totals (red[w * 64 + l]) into the block's partials.
+__device__ __forceinline__ void block_partials(const double* __restrict__ red, int nv,
+                                               double* __restrict__ partial, int nblk, int l0) {
+  __syncthreads();
+  const int l = threadIdx.x;
+  if (l < nv)
+    partial[(int64_t)(l0 + l) * nblk + blockIdx.x] = (red[l] + red[64 + l]) + (red[128 + l] + red[192 + l]);
+}
+
+// partial[(l0 + l) * nblk + b] = block b's part of V_{l0+l} . w, l < min(64, nv - l0),
+// with l0 = 64 * blockIdx.y
+template <int NVB>
+__global__ __launch_bounds__(kDotThreads) void gs_dot_kernel(const double* __restrict__ V,
+                                                            int64_t ldv, int nv,
+                                                            const double* __restrict__ w,
+                                                            int64_t N, double* __restrict__ partial,
+                                                            int nblk) {
+  __shared__ double red[4 * 64];
+  const int l0 = 64 * blockIdx.y;
+  const int cnt = min(nv - l0, NVB);
+  const int64_t i = (int64_t)blockIdx.x * kDotThreads + threadIdx.x;
+  const bool in = i < N;
+  const double wi = in ? w[i] : 0.0;
+  const double* Vb = V + (int64_t)l0 * ldv + i;
+  double a[NVB];
+#pragma unroll
+  for (int l = 0; l < NVB; ++l) a[l] = (l < cnt && in) ? Vb[(int64_t)l * ldv] : 0.0;
+#pragma unroll
+  for (int l = 0; l < NVB; ++l) a[l] *= wi;
+  wave_sums<NVB>(a, red + 64 * (threadIdx.x >> 6));
+  block_partials(red, cnt, partial, nblk, l0);
+}
+
+// w <- w + sign * sum_l h[l] V_l, then partial[l * nblk + b] = block b's part of
+// V_l . w (the new w), nv <= NVB <= 64: the basis values stay in registers
+// between the update and the dots, so V is read once for both.
+template <int NVB>
+__global__ __launch_bounds__(kDotThreads) void gs_update_dot_kernel(
+    const double* __restrict__ V, int64_t ldv, int nv, const double* __restrict__ h,
+    double* __restrict__ w, int64_t N, double sign, double* __restrict__ partial, int nblk) {
+  __shared__ double red[4 * 64];
+  const int64_t i = (int64_t)blockIdx.x * kDotThreads + threadIdx.x;
+  const bool in = i < N;
+  double a[NVB];
+#pragma unroll
+  for (int l = 0; l < NVB; ++l) a[l] = (l < nv && in) ? V[(int64_t)l * ldv + i] : 0.0;
+  double acc = 0.0;
+#pragma unroll
+  for (int l = 0; l < NVB; ++l)
+    if (l < nv) acc = fma(h[l], a[l], acc);
+  double wi = 0.0;
+  if (in) {
+    wi = w[i] + sign * acc;
+    w[i] = wi;
+  }
+#pragma unroll
+  for (int l = 0; l < NVB; ++l) a[l] *= wi;
+  wave_sums<NVB>(a, red + 64 * (threadIdx.x >> 6));
+  block_partials(red, nv, partial, nblk, 0);
+}
+
+// w <- w + sign * sum_l h[l] V_l, then partial[b] = block b's part of w . w
+__global__ __launch_bounds__(kDotThreads) void gs_update_norm_kernel(
+    const double* __restrict__ V, int64_t ldv, int nv, const double* __restrict__ h,
+    double* __restrict__ w, int64_t N, double sign, double* __restrict__ partial) {
+  __shared__ double red[4 * 64];
+  const int64_t i = (int64_t)blockIdx.x * kDotThreads + threadIdx.x;
+  double a[1] = {0.0};
+  if (i < N) {
+    double acc = 0.0;
+#pragma unroll 8
+    for (int l = 0; l < nv; ++l) acc = fma(h[l], V[(int64_t)l * ldv + i], acc);
+    const double wi = w[i] + sign * acc;
+    w[i] = wi;
+    a[0] = wi * wi;
+  }
+  wave_sums<1>(a, red + 64 * (threadIdx.x >> 6));
+  block_partials(red, 1, partial, gridDim.x, 0);
+}
+
+// out[l] = sum_b partial[l * nblk + b]: one block per l, four fixed strided
+// accumulators per thread, then the block tree
+__global__ __launch_bounds__(kDotThreads) void reduce_wide_kernel(const double* __restrict__ partial,
+                                                                 int nblk, double* __restrict__ out) {
+  __shared__ double red[4];
+  const double* p = partial + (int64_t)blockIdx.x * nblk;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int b = threadIdx.x;
+  for (; b + 3 * kDotThreads < nblk; b += 4 * kDotThreads) {
+    a0 += p[b];
+    a1 += p[b + kDotThreads];
+    a2 += p[b + 2 * kDotThreads];
+    a3 += p[b + 3 * kDotThreads];
+  }
+  for (; b < nblk; b += kDotThreads) a0 += p[b];
+  const double v = block_sum((a0 + a1) + (a2 + a3), red);
+  if (threadIdx.x == 0) out[blockIdx.x] = v;
+}
+
+void launch_gs_dot(hipStream_t s, const double* V, int64_t ldv, int nv, const double* w, int64_t N,
+                   double* partial, double* out) {
+  const int nblk = gs_blocks(N);
+  const int top = std::min(nv, 64);
+  dim3 grid(nblk, cdiv(nv, 64)), block(kDotThreads);
+#define SG_GS_DOT(B)                                                                          \
+  if (top <= B) {                                                                             \
+    hipLaunchKernelGGL(gs_dot_kernel<B>, grid, block, 0, s, V, ldv, nv, w, N, partial, nblk); \
+  } else
+  SG_GS_DOT(1) SG_GS_DOT(2) SG_GS_DOT(4) SG_GS_DOT(8) SG_GS_DOT(16) SG_GS_DOT(32) SG_GS_DOT(64) {}
+#undef SG_GS_DOT
+  hipLaunchKernelGGL(reduce_wide_kernel, dim3(nv), block, 0, s, partial, nblk, out);
+}
+
+void launch_gs_update_dot(hipStream_t s, const double* V, int64_t ldv, int nv, const double* h,
+                          double* w, int64_t N, double sign, double* partial, double* out) {
+  if (nv > 64) {
+    launch_update(s, V, ldv, nv, h, w, N, sign);
+    launch_gs_dot(s, V, ldv, nv, w, N, partial, out);
+    return;
+  }
+  const int nblk = gs_blocks(N);
+  dim3 grid(nblk), block(kDotThreads);
+#define SG_GS_UD(B)                                                                          \
+  if (nv <= B) {                                                                             \
+    hipLaunchKernelGGL(gs_update_dot_kernel<B>, grid, block, 0, s, V, ldv, nv, h, w, N, sign, \
+                       partial, nblk);                                                       \
+  } else
+  SG_GS_UD(1) SG_GS_UD(2) SG_GS_UD(4) SG_GS_UD(8) SG_GS_UD(16) SG_GS_UD(32) SG_GS_UD(64) {}
+#undef SG_GS_UD
+  hipLaunchKernelGGL(reduce_wide_kernel, dim3(nv), block, 0, s, partial, nblk, out);
+}
+
+void launch_gs_update_norm(hipStream_t s, const double* V, int64_t ldv, int nv, const double* h,
+                           double* w, int64_t N, double sign, double* partial, double* out) {
+  const int nblk = gs_blocks(N);
+  hipLaunchKernelGGL(gs_update_norm_kernel, dim3(nblk), dim3(kDotThreads), 0, s, V, ldv, nv, h, w,
+                     N, sign, partial);
+  hipLaunchKernelGGL(reduce_wide_kernel, dim3(1), dim3(kDotThreads), 0, s, partial, nblk, out);
+}
+
 // out = sum_l y[l] V_l
 __global__ void combine_kernel(const double* __restrict__ V, int64_t ldv, int nv,
                                const double* __restrict__ y, double* __restrict__ out, int64_t N) {
@@ -1107,7 +1288,7 @@ struct VDownLds {
 // be reused by the next item of a persistent workgroup.
 __device__ __forceinline__ void vdown_tile(VDownLds& L, int tile, int mode,
                                            const double* __restrict__ Sbase, int nf, int64_t Nf,
-                                           int64_t Nc, const int* smode,
+                                           int64_t Nc, const int* smode, const int* bmap,
                                            const double* __restrict__ bglob,
                                            double* __restrict__ x2out,
                                            double* __restrict__ bcout, double omega) {
@@ -1120,7 +1301,7 @@ __device__ __forceinline__ void vdown_tile(VDownLds& L, int tile, int mode,
   const int tpr = (nc + kTC - 1) / kTC;
   const int tx = tile % tpr, ty = tile / tpr;
   const double* S = sel_stencil(Sbase, Nf, smode, mode);
-  const double* b = bglob + (int64_t)mode * Nf;
+  const double* b = bglob + (int64_t)(bmap ? bmap[mode] : mode) * Nf;
   const int I0 = 1 + tx * kTC, J0 = 1 + ty * kTC;
   const int ox = 2 * I0 - 3, oy = 2 * J0 - 3;  // fine index of LDS (0,0)
   const int tid = threadIdx.x;
@@ -1188,11 +1369,13 @@ __device__ __forceinline__ void vdown_tile(VDownLds& L, int tile, int mode,
 
 __global__ __launch_bounds__(256) void vdown_kernel(const double* __restrict__ Sbase, int nf,
                                                     int64_t Nf, int64_t Nc, const int* smode,
+                                                    const int* bmap,
                                                     const double* __restrict__ bglob,
                                                     double* __restrict__ x2out,
                                                     double* __restrict__ bcout, double omega) {
   __shared__ VDownLds L;
-  vdown_tile(L, blockIdx.x, blockIdx.y, Sbase, nf, Nf, Nc, smode, bglob, x2out, bcout, omega);
+  vdown_tile(L, blockIdx.x, blockIdx.y, Sbase, nf, Nf, Nc, smode, bmap, bglob, x2out, bcout,
+             omega);
 }
 
 struct VUpLds {
@@ -1202,11 +1385,12 @@ struct VUpLds {
 // One (tile, mode) item of the up sweep; ends with a barrier.
 __device__ __forceinline__ void vup_tile(VUpLds& L, int tile, int mode,
                                          const double* __restrict__ Sbase, int nf, int64_t Nf,
-                                         int64_t Nc, const int* smode,
-                                         const double* __restrict__ bglob,
+                                         int64_t Nc, const int* smode, const int* bmap,
+                                         const int* xmap, const double* __restrict__ bglob,
                                          const double* __restrict__ x2glob,
                                          const double* __restrict__ xcglob,
-                                         double* __restrict__ xout, double omega) {
+                                         double* __restrict__ xout, double omega,
+                                         int64_t xcslab = 0) {
   double* sb = L.sb;
   double* sd = L.sd;
   double* sx3 = L.sx3;
@@ -1216,7 +1400,7 @@ __device__ __forceinline__ void vup_tile(VUpLds& L, int tile, int mode,
   const int tpr = (nc + kTC - 1) / kTC;
   const int tx = tile % tpr, ty = tile / tpr;
   const double* S = sel_stencil(Sbase, Nf, smode, mode);
-  const double* b = bglob + (int64_t)mode * Nf;
+  const double* b = bglob + (int64_t)(bmap ? bmap[mode] : mode) * Nf;
   const double* x2 = x2glob + (int64_t)mode * Nf;
   const double* xc = xcglob + (int64_t)mode * Nc;
   const int I0 = 1 + tx * kTC, J0 = 1 + ty * kTC;
@@ -1227,7 +1411,13 @@ __device__ __forceinline__ void vup_tile(VUpLds& L, int tile, int mode,
   auto gidx = [&](int fx, int fy) { return (int64_t)(fy - 1) * mf + (fx - 1); };
   for (int e = tid; e < kCE * kCE; e += 256) {
     const int cx = cx0 + e % kCE, cy = cy0 + e / kCE;
-    sc[e] = (cx >= 1 && cx <= mc && cy >= 1 && cy <= mc) ? xc[(int64_t)(cy - 1) * mc + (cx - 1)] : 0.0;
+    double v = 0.0;
+    if (cx >= 1 && cx <= mc && cy >= 1 && cy <= mc) {
+      const int64_t g = (int64_t)(cy - 1) * mc + (cx - 1);
+      v = xc[g];
+      if (xcslab) v = (v + xc[g + xcslab]) + (xc[g + 2 * xcslab] + xc[g + 3 * xcslab]);
+    }
+    sc[e] = v;
   }
   __syncthreads();
   for (int e = tid; e < kUE * kUE; e += 256) {
@@ -1277,7 +1467,7 @@ __device__ __forceinline__ void vup_tile(VUpLds& L, int tile, int mode,
 #pragma unroll
       for (int t = 0; t < 9; ++t)
         ax += S[t * Nf + g] * sx4[(ly + t / 3 - 1) * kUE + (lx + t % 3 - 1)];
-      xout[(int64_t)mode * Nf + g] = sx4[e] + omega * (sb[e] - ax) / sd[e];
+      xout[(int64_t)(xmap ? xmap[mode] : mode) * Nf + g] = sx4[e] + omega * (sb[e] - ax) / sd[e];
     }
   }
   __syncthreads();
@@ -1285,26 +1475,35 @@ __device__ __forceinline__ void vup_tile(VUpLds& L, int tile, int mode,
 
 __global__ __launch_bounds__(256) void vup_kernel(const double* __restrict__ Sbase, int nf,
                                                   int64_t Nf, int64_t Nc, const int* smode,
+                                                  const int* bmap, const int* xmap,
                                                   const double* __restrict__ bglob,
                                                   const double* __restrict__ x2glob,
                                                   const double* __restrict__ xcglob,
-                                                  double* __restrict__ xout, double omega) {
+                                                  double* __restrict__ xout, double omega,
+                                                  int64_t xcslab) {
   __shared__ VUpLds L;
-  vup_tile(L, blockIdx.x, blockIdx.y, Sbase, nf, Nf, Nc, smode, bglob, x2glob, xcglob, xout, omega);
+  vup_tile(L, blockIdx.x, blockIdx.y, Sbase, nf, Nf, Nc, smode, bmap, xmap, bglob, x2glob, xcglob,
+           xout, omega, xcslab);
 }
 
+// bmap / xmap (device, may be null): mode t reads b from vector bmap[t] and
+// writes x to vector xmap[t] of the full-length arrays (the field split's
+// gather and scatter folded into the finest level)
 void launch_vdown(hipStream_t s, const Level& Lf, const Level& Lc, int modes, const int* smode,
-                  const double* b, double* x2, double* bc, double omega) {
+                  const double* b, double* x2, double* bc, double omega, const int* bmap) {
   const int tpr = (Lf.n / 2 + kTC - 1) / kTC;
   hipLaunchKernelGGL(vdown_kernel, dim3(tpr * tpr, modes), dim3(256), 0, s, Lf.S, Lf.n, Lf.N, Lc.N,
-                     smode, b, x2, bc, omega);
+                     smode, bmap, b, x2, bc, omega);
 }
 
 void launch_vup(hipStream_t s, const Level& Lf, const Level& Lc, int modes, const int* smode,
-                const double* b, const double* x2, const double* xc, double* x, double omega) {
+                const double* b, const double* x2, const double* xc, double* x, double omega,
+                const int* bmap, const int* xmap, int xc_slices) {
+  if (xc_slices != 1 && xc_slices != kDenseSlices) throw Error(SG_ERR_INTERNAL, "vup: slices");
   const int tpr = (Lf.n / 2 + kTC - 1) / kTC;
+  const int64_t xcslab = xc_slices == 1 ? 0 : (int64_t)modes * Lc.N;
   hipLaunchKernelGGL(vup_kernel, dim3(tpr * tpr, modes), dim3(256), 0, s, Lf.S, Lf.n, Lf.N, Lc.N,
-                     smode, b, x2, xc, x, omega);
+                     smode, bmap, xmap, b, x2, xc, x, omega, xcslab);
 }
 
 // ---- coarse levels in LDS, one workgroup per mode --------------------------
@@ -1474,48 +1673,57 @@ void launch_unit_columns(hipStream_t s, int N, int j0, int m, double* out) {
                      m, out);
 }
 
-// One 512-thread workgroup per 16 x 16 output tile: the tile's 16 columns of B
-// (inner index padded to kDenseK) are staged in LDS, each of the 8 wavefronts
-// takes 128 inner indices (two batches of 64 matrix loads, the second in
-// flight while the first is used), and the 8 partial tiles are summed in a
-// fixed order.
+// One 512-thread workgroup per 16 x 16 output tile and slice of the inner
+// index: the slice's rows of the tile's 16 columns of B (zero past N) are
+// staged in LDS, each of the 8 wavefronts takes NB batches of 32 inner indices
+// (the next batch of matrix loads in flight while one is used), and the 8
+// partial tiles are summed in a fixed order.  With one slice (NB = 4, all
+// kDenseK inner indices) the tile goes to X; with four (NB = 1) slice z writes
+// its partial tile to X + z * xslab, and the four partial results are summed,
+// in slice order, by the kernel that reads X.
+template <int NB>
 __global__ __launch_bounds__(512) void dense_coarse_kernel(int N, int m,
                                                            const double* __restrict__ C,
                                                            const double* __restrict__ B,
-                                                           double* __restrict__ X) {
+                                                           double* __restrict__ X, int64_t xslab,
+                                                           const int* bmap, const int* xmap) {
+  constexpr int D = 32;            // matrix loads per batch
+  constexpr int KW = NB * D;       // inner indices per wavefront
+  constexpr int KB = 8 * KW;       // inner indices per workgroup
   extern __shared__ double smem[];
-  double* Bs = smem;                        // [kDenseK][16], rows >= N zero
-  double* red = smem + (size_t)kDenseK * 16;  // [8][256]
+  double* Bs = smem;               // [KB][16]
+  double* red = smem + (size_t)KB * 16;  // [8][256]
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int r0 = blockIdx.x * 16, k0 = blockIdx.y * 16, ncol = min(16, m - k0);
+  const int kbase = blockIdx.z * KB;
   const int r = lane & 15, cg = (lane >> 4) * 4;
   const double* Cr = C + min(r0 + r, N - 1);
-  const int jw = wave * (kDenseK / 8);
-  constexpr int D = 32;  // matrix loads per batch; 4 batches, the next one in flight
+  const int jw = kbase + wave * KW;
   double a[D], an[D];
 #pragma unroll
   for (int u = 0; u < D; ++u) a[u] = Cr[(int64_t)min(jw + u, N - 1) * N];  // clamped
   {
-    // thread t stages column t % 16, rows t / 16 + 32 s
+    // thread t stages column t % 16, slice rows t / 16 + 32 s
     const int c = tid & 15, j0 = tid >> 4;
-    const double* Bc = B + (int64_t)(k0 + min(c, ncol - 1)) * N;
-    double v[kDenseK / 32];
+    const int bc = k0 + min(c, ncol - 1);
+    const double* Bc = B + (int64_t)(bmap ? bmap[bc] : bc) * N;
+    double v[KB / 32];
 #pragma unroll
-    for (int u = 0; u < kDenseK / 32; ++u) v[u] = Bc[min(j0 + 32 * u, N - 1)];
+    for (int u = 0; u < KB / 32; ++u) v[u] = Bc[min(kbase + j0 + 32 * u, N - 1)];
 #pragma unroll
-    for (int u = 0; u < kDenseK / 32; ++u) {
+    for (int u = 0; u < KB / 32; ++u) {
       const int j = j0 + 32 * u;
-      Bs[j * 16 + c] = (c < ncol && j < N) ? v[u] : 0.0;
+      Bs[j * 16 + c] = (c < ncol && kbase + j < N) ? v[u] : 0.0;
     }
   }
   __syncthreads();
   // two accumulator sets (even / odd inner index): eight independent FMA chains
   double acc2[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
-  const double* Bw = Bs + jw * 16 + cg;
+  const double* Bw = Bs + (jw - kbase) * 16 + cg;
 #pragma unroll
-  for (int bt = 0; bt < kDenseK / 8 / D; ++bt) {
-    if (bt + 1 < kDenseK / 8 / D) {
+  for (int bt = 0; bt < NB; ++bt) {
+    if (bt + 1 < NB) {
 #pragma unroll
       for (int u = 0; u < D; ++u) an[u] = Cr[(int64_t)min(jw + (bt + 1) * D + u, N - 1) * N];
     }
@@ -1529,8 +1737,10 @@ __global__ __launch_bounds__(512) void dense_coarse_kernel(int N, int m,
       ac[2] = fma(a[u], b23.x, ac[2]);
       ac[3] = fma(a[u], b23.y, ac[3]);
     }
+    if (bt + 1 < NB) {
 #pragma unroll
-    for (int u = 0; u < D; ++u) a[u] = an[u];
+      for (int u = 0; u < D; ++u) a[u] = an[u];
+    }
   }
   double acc[4];
 #pragma unroll
@@ -1539,23 +1749,33 @@ __global__ __launch_bounds__(512) void dense_coarse_kernel(int N, int m,
   for (int v = 0; v < 4; ++v) red[wave * 256 + v * 64 + lane] = acc[v];
   __syncthreads();
   if (wave == 0) {
+    double* Xz = X + (int64_t)blockIdx.z * xslab;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       double x = red[v * 64 + lane];
 #pragma unroll
       for (int w = 1; w < 8; ++w) x += red[w * 256 + v * 64 + lane];
       const int c = cg + v;
-      if (r0 + r < N && c < ncol) X[(int64_t)(k0 + c) * N + r0 + r] = x;
+      if (r0 + r < N && c < ncol) Xz[(int64_t)(xmap ? xmap[k0 + c] : k0 + c) * N + r0 + r] = x;
     }
   }
 }
 
 void launch_dense_coarse(hipStream_t s, int N, int m, const double* C, const double* B,
-                         double* X) {
+                         double* X, const int* bmap, const int* xmap, int slices) {
   if (N < 1 || N > kDenseK || m < 1) throw Error(SG_ERR_INTERNAL, "dense coarse operator: size");
-  const size_t lds = 8 * ((size_t)kDenseK * 16 + 8 * 256);
-  hipLaunchKernelGGL(dense_coarse_kernel, dim3(cdiv(N, 16), cdiv(m, 16)), dim3(512), lds, s, N, m,
-                     C, B, X);
+  const int64_t xslab = (int64_t)m * N;
+  if (slices == 1) {
+    const size_t lds = 8 * ((size_t)kDenseK * 16 + 8 * 256);
+    hipLaunchKernelGGL(dense_coarse_kernel<4>, dim3(cdiv(N, 16), cdiv(m, 16), 1), dim3(512), lds,
+                       s, N, m, C, B, X, xslab, bmap, xmap);
+  } else if (slices == kDenseSlices && !xmap) {
+    const size_t lds = 8 * ((size_t)(kDenseK / kDenseSlices) * 16 + 8 * 256);
+    hipLaunchKernelGGL(dense_coarse_kernel<1>, dim3(cdiv(N, 16), cdiv(m, 16), kDenseSlices),
+                       dim3(512), lds, s, N, m, C, B, X, xslab, bmap, xmap);
+  } else {
+    throw Error(SG_ERR_INTERNAL, "dense coarse operator: slices");
+  }
 }
 
 size_t vcoarse_lds_bytes(const CoarseLevels& cl) {
@@ -1720,7 +1940,8 @@ __global__ __launch_bounds__(256) void bvdown_kernel(const BInst* __restrict__ I
     const Level& Lf = I.L[depth];
     const Level& Lc = I.L[depth + 1];
     const double* b = depth == 0 ? I.fsT : I.mg_b[depth];
-    vdown_tile(L, w.local / m, w.local % m, Lf.S, Lf.n, Lf.N, Lc.N, nullptr, b, I.mg_xa[depth],
+    vdown_tile(L, w.local / m, w.local % m, Lf.S, Lf.n, Lf.N, Lc.N, nullptr, nullptr, b,
+               I.mg_xa[depth],
                I.mg_b[depth + 1], 8.0 / 9.0);
   }
 }
@@ -1739,7 +1960,8 @@ __global__ __launch_bounds__(256) void bvup_kernel(const BInst* __restrict__ Is,
     const Level& Lc = I.L[depth + 1];
     const double* b = depth == 0 ? I.fsT : I.mg_b[depth];
     double* x = depth == 0 ? I.fsX : I.mg_x[depth];
-    vup_tile(L, w.local / m, w.local % m, Lf.S, Lf.n, Lf.N, Lc.N, nullptr, b, I.mg_xa[depth],
+    vup_tile(L, w.local / m, w.local % m, Lf.S, Lf.n, Lf.N, Lc.N, nullptr, nullptr, nullptr, b,
+             I.mg_xa[depth],
              I.mg_x[depth + 1], x, 8.0 / 9.0);
   }
 }

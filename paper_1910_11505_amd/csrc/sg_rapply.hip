@@ -219,6 +219,10 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
   double G[P][2];
 #pragma unroll
   for (int a = 0; a < P; ++a) {
+    if (!((colmask >> a) & 1)) {  // not a column of this block
+      G[a][0] = G[a][1] = 0.0;
+      continue;
+    }
     const double* u = sN + a * 25;
     const double u00 = u[ey * 5 + ex], u10 = u[ey * 5 + ex + 1];
     const double u01 = u[(ey + 1) * 5 + ex], u11 = u[(ey + 1) * 5 + ex + 1];
@@ -235,8 +239,12 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
   for (int d = 1; d < P; ++d) mono[d] = mono[T.par[d]] * gv[T.var[d]] * T.inv[d];
 
   // 3. step 1 in place
+  // gamma outside the block's set: never read by step 2, or zero (then no column
+  // lies above it, so its slot already holds zero)
+  const uint64_t gammask = rr.gammask;
 #pragma unroll
   for (int gm = 0; gm < P; ++gm) {
+    if (!((gammask >> gm) & 1)) continue;
     double sx = 0.0, sy = 0.0;
 #pragma unroll
     for (int t = T.p1[gm]; t < T.p1[gm + 1]; ++t) {

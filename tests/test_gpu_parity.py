@@ -158,6 +158,25 @@ def test_gmres_restart_and_max_it():
     assert info.iterations == 0 and info.status == 0
 
 
+def test_gmres_long_cycle_matches_oracle():
+    """One unpreconditioned GMRES cycle of 96 steps (restart 120): the Krylov
+    basis passes 64 vectors, so the Gram-Schmidt passes run both with the basis
+    held in registers (up to 64 vectors) and in 64-vector chunks past that."""
+    from oracle.gmres import gmres
+    S, H, G = pair("n16_m2p2")
+    K = S.assemble()
+    F = S.rhs()
+    xo, io = gmres(lambda v: K @ v, lambda v: v, F, tol=1e-8, restart=120)
+    assert io["iterations"] > 64
+    u, info, _ = G.solve(pc="none", grouping="klvar", tol=1e-8, restart=120)
+    ug = to_host(u)
+    assert info.status == 0 and info.restarts == 1   # one cycle, counted when it ends
+    assert abs(info.iterations - io["iterations"]) <= 1
+    relres = np.linalg.norm(F - K @ ug) / np.linalg.norm(F)
+    assert relres <= 1e-8 * (1 + 1e-6)
+    assert np.linalg.norm(ug - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
 @pytest.mark.parametrize("pc", ["mean", "fs"])
 def test_precond_large_P(pc):
     from oracle.precond import FieldSplit, make_groups
