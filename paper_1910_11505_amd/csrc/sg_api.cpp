@@ -125,11 +125,13 @@ struct sg_handle {
   size_t ws_bytes = 0;
   DevPtrs d;
   double* host_pinned = nullptr;  // small staging for Krylov scalars
+  hipEvent_t fetched = nullptr;   // marks the Krylov scalars' copy to host_pinned
   sg_cnn* cnn = nullptr;          // attached learned stage (not owned)
   double cnn_sigma = 0.0;
 
   ~sg_handle() {
     if (host_pinned) (void)hipHostFree(host_pinned);
+    if (fetched) (void)hipEventDestroy(fetched);
   }
 };
 
@@ -983,6 +985,7 @@ int sg_bind(sg_handle* h, void* dev_workspace, size_t bytes, void* stream) {
     if (!H.host_pinned)
       SG_HIP(hipHostMalloc((void**)&H.host_pinned, sizeof(double) * (4 * (kMaxRestart + 2) + 8),
                            hipHostMallocDefault));
+    if (!H.fetched) SG_HIP(hipEventCreateWithFlags(&H.fetched, hipEventDisableTiming));
     SG_HIP(hipStreamSynchronize(s));
     H.bound = true;
     return SG_OK;
@@ -1209,10 +1212,17 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
       g[0] = beta;
       launch_axpby(s, 1.0 / beta, K.t, 0.0, K.V, Nv);
       int kdone = 0;
+      // the next step's preconditioner and operator apply (which need only
+      // v_{j+1}, already on the device) are queued before the host waits for
+      // step j's Hessenberg column, so the device keeps working while the host
+      // updates the rotations; wasted once, when step j ends the solve
+      bool queued = false;
       for (int j = 0; j < m; ++j) {
         double* vj = K.V + (int64_t)j * Nv;
         double* zj = K.z;
-        if (learned) {
+        if (queued) {
+          queued = false;
+        } else if (learned) {
           // field split first, then the network's prediction c of the error
           // left in the field-split residual r = v - K P_FS^{-1} v, weighted by
           // alpha = <r, K c> / ||K c||^2 (the residual-minimising step), so the
@@ -1251,7 +1261,14 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
         launch_gs_update_norm(s, K.V, Nv, j + 1, h2, K.w, Nv, -1.0, K.partial, nrm);
         launch_scale_by_inv_norm(s, K.w, nrm, K.V + (int64_t)(j + 1) * Nv, Nv);
         check_launch();
-        fetch(K.hdev, 2 * (m + 1) + 1);
+        SG_HIP(hipMemcpyAsync(hp, K.hdev, (2 * (m + 1) + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        SG_HIP(hipEventRecord(H.fetched, s));
+        if (!learned && j + 1 < m && it + 1 < o->max_it) {
+          do_precond(H, s, o->pc, o->grouping, K.V + (int64_t)(j + 1) * Nv, K.z);
+          do_apply(H, s, K.z, K.w);
+          queued = true;
+        }
+        SG_HIP(hipEventSynchronize(H.fetched));
         for (int i = 0; i <= j; ++i) Hat(i, j) = hp[i] + hp[m + 1 + i];
         Hat(j + 1, j) = std::sqrt(hp[2 * (m + 1)]);
         if (!std::isfinite(Hat(j + 1, j))) {

@@ -1307,46 +1307,57 @@ __device__ __forceinline__ void vdown_tile(VDownLds& L, int tile, int mode,
   const int tid = threadIdx.x;
   auto inside = [&](int fx, int fy) { return fx >= 1 && fx <= mf && fy >= 1 && fy <= mf; };
   auto gidx = [&](int fx, int fy) { return (int64_t)(fy - 1) * mf + (fx - 1); };
-  for (int e = tid; e < kDE * kDE; e += 256) {
-    const int lx = e % kDE, ly = e / kDE, fx = ox + lx, fy = oy + ly;
-    double bv = 0.0, dv = 1.0;
-    if (inside(fx, fy)) {
-      const int64_t g = gidx(fx, fy);
-      bv = b[g];
-      dv = S[4 * Nf + g];
+  // a thread keeps the same local points (e = tid + 256 p) in every phase: their
+  // right-hand side and stencil rows are loaded once, all in flight together
+  constexpr int kNP = (kDE * kDE + 255) / 256;
+  double sv[kNP][9], bv[kNP];
+  int64_t gp[kNP];
+#pragma unroll
+  for (int p = 0; p < kNP; ++p) {
+    const int e = tid + 256 * p, lx = e % kDE, ly = e / kDE, fx = ox + lx, fy = oy + ly;
+    const bool in = e < kDE * kDE && inside(fx, fy);
+    gp[p] = in ? gidx(fx, fy) : -1;
+    bv[p] = in ? b[gp[p]] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) sv[p][t] = in ? S[t * Nf + gp[p]] : (t == 4 ? 1.0 : 0.0);
+  }
+#pragma unroll
+  for (int p = 0; p < kNP; ++p) {
+    const int e = tid + 256 * p;
+    if (e < kDE * kDE) {
+      sb[e] = bv[p];
+      sd[e] = sv[p][4];
+      sx1[e] = gp[p] >= 0 ? omega * bv[p] / sv[p][4] : 0.0;
     }
-    sb[e] = bv;
-    sd[e] = dv;
-    sx1[e] = inside(fx, fy) ? omega * bv / dv : 0.0;
   }
   __syncthreads();
   // x2 on [1, kDE-2)^2 local
-  for (int e = tid; e < kDE * kDE; e += 256) {
-    const int lx = e % kDE, ly = e / kDE, fx = ox + lx, fy = oy + ly;
+#pragma unroll
+  for (int p = 0; p < kNP; ++p) {
+    const int e = tid + 256 * p, lx = e % kDE, ly = e / kDE;
+    if (e >= kDE * kDE) continue;
     double v = 0.0;
-    if (lx >= 1 && lx < kDE - 1 && ly >= 1 && ly < kDE - 1 && inside(fx, fy)) {
-      const int64_t g = gidx(fx, fy);
+    if (lx >= 1 && lx < kDE - 1 && ly >= 1 && ly < kDE - 1 && gp[p] >= 0) {
       double ax = 0.0;
 #pragma unroll
-      for (int t = 0; t < 9; ++t)
-        ax += S[t * Nf + g] * sx1[(ly + t / 3 - 1) * kDE + (lx + t % 3 - 1)];
+      for (int t = 0; t < 9; ++t) ax += sv[p][t] * sx1[(ly + t / 3 - 1) * kDE + (lx + t % 3 - 1)];
       v = sx1[e] + omega * (sb[e] - ax) / sd[e];
     }
     sx2[e] = v;
   }
   __syncthreads();
   // r on [2, kDE-2)^2 local; owned x2 written out
-  for (int e = tid; e < kDE * kDE; e += 256) {
-    const int lx = e % kDE, ly = e / kDE, fx = ox + lx, fy = oy + ly;
+#pragma unroll
+  for (int p = 0; p < kNP; ++p) {
+    const int e = tid + 256 * p, lx = e % kDE, ly = e / kDE;
+    if (e >= kDE * kDE) continue;
     double v = 0.0;
-    if (lx >= 2 && lx < kDE - 2 && ly >= 2 && ly < kDE - 2 && inside(fx, fy)) {
-      const int64_t g = gidx(fx, fy);
+    if (lx >= 2 && lx < kDE - 2 && ly >= 2 && ly < kDE - 2 && gp[p] >= 0) {
       double ax = 0.0;
 #pragma unroll
-      for (int t = 0; t < 9; ++t)
-        ax += S[t * Nf + g] * sx2[(ly + t / 3 - 1) * kDE + (lx + t % 3 - 1)];
+      for (int t = 0; t < 9; ++t) ax += sv[p][t] * sx2[(ly + t / 3 - 1) * kDE + (lx + t % 3 - 1)];
       v = sb[e] - ax;
-      if (lx < kDE - 3 && ly < kDE - 3) x2out[(int64_t)mode * Nf + g] = sx2[e];
+      if (lx < kDE - 3 && ly < kDE - 3) x2out[(int64_t)mode * Nf + gp[p]] = sx2[e];
     }
     sr[e] = v;
   }
@@ -1409,65 +1420,81 @@ __device__ __forceinline__ void vup_tile(VUpLds& L, int tile, int mode,
   const int tid = threadIdx.x;
   auto inside = [&](int fx, int fy) { return fx >= 1 && fx <= mf && fy >= 1 && fy <= mf; };
   auto gidx = [&](int fx, int fy) { return (int64_t)(fy - 1) * mf + (fx - 1); };
-  for (int e = tid; e < kCE * kCE; e += 256) {
-    const int cx = cx0 + e % kCE, cy = cy0 + e / kCE;
-    double v = 0.0;
-    if (cx >= 1 && cx <= mc && cy >= 1 && cy <= mc) {
+  // the coarse correction, and for the thread's local points (e = tid + 256 p,
+  // the same in every phase) the right-hand side, the pre-smoothed x2 and the
+  // stencil rows, all loaded at once
+  constexpr int kNP = (kUE * kUE + 255) / 256;
+  static_assert(kCE * kCE <= 256, "one coarse value per thread");
+  double cv = 0.0;
+  {
+    const int cx = cx0 + tid % kCE, cy = cy0 + tid / kCE;
+    if (tid < kCE * kCE && cx >= 1 && cx <= mc && cy >= 1 && cy <= mc) {
       const int64_t g = (int64_t)(cy - 1) * mc + (cx - 1);
-      v = xc[g];
-      if (xcslab) v = (v + xc[g + xcslab]) + (xc[g + 2 * xcslab] + xc[g + 3 * xcslab]);
+      cv = xc[g];
+      if (xcslab) cv = (cv + xc[g + xcslab]) + (xc[g + 2 * xcslab] + xc[g + 3 * xcslab]);
     }
-    sc[e] = v;
   }
+  double sv[kNP][9], bv[kNP], xv[kNP];
+  int64_t gp[kNP];
+#pragma unroll
+  for (int p = 0; p < kNP; ++p) {
+    const int e = tid + 256 * p, lx = e % kUE, ly = e / kUE, fx = ox + lx, fy = oy + ly;
+    const bool in = e < kUE * kUE && inside(fx, fy);
+    gp[p] = in ? gidx(fx, fy) : -1;
+    bv[p] = in ? b[gp[p]] : 0.0;
+    xv[p] = in ? x2[gp[p]] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) sv[p][t] = in ? S[t * Nf + gp[p]] : (t == 4 ? 1.0 : 0.0);
+  }
+  if (tid < kCE * kCE) sc[tid] = cv;
   __syncthreads();
-  for (int e = tid; e < kUE * kUE; e += 256) {
-    const int lx = e % kUE, ly = e / kUE, fx = ox + lx, fy = oy + ly;
-    double bv = 0.0, dv = 1.0, x3 = 0.0;
-    if (inside(fx, fy)) {
-      const int64_t g = gidx(fx, fy);
-      bv = b[g];
-      dv = S[4 * Nf + g];
+#pragma unroll
+  for (int p = 0; p < kNP; ++p) {
+    const int e = tid + 256 * p, lx = e % kUE, ly = e / kUE, fx = ox + lx, fy = oy + ly;
+    if (e >= kUE * kUE) continue;
+    double x3 = 0.0;
+    if (gp[p] >= 0) {
       // bilinear interpolation from the coarse neighbours
       const int Ia = fx >> 1, Ib = (fx + 1) >> 1, Ja = fy >> 1, Jb = (fy + 1) >> 1;
       auto C = [&](int I, int J) { return sc[(J - cy0) * kCE + (I - cx0)]; };
-      double p;
+      double pr;
       if (fx & 1) {
-        if (fy & 1) p = 0.25 * C(Ia, Ja) + 0.25 * C(Ib, Ja) + 0.25 * C(Ia, Jb) + 0.25 * C(Ib, Jb);
-        else p = 0.5 * C(Ia, Ja) + 0.5 * C(Ib, Ja);
+        if (fy & 1) pr = 0.25 * C(Ia, Ja) + 0.25 * C(Ib, Ja) + 0.25 * C(Ia, Jb) + 0.25 * C(Ib, Jb);
+        else pr = 0.5 * C(Ia, Ja) + 0.5 * C(Ib, Ja);
       } else {
-        if (fy & 1) p = 0.5 * C(Ia, Ja) + 0.5 * C(Ia, Jb);
-        else p = C(Ia, Ja);
+        if (fy & 1) pr = 0.5 * C(Ia, Ja) + 0.5 * C(Ia, Jb);
+        else pr = C(Ia, Ja);
       }
-      x3 = x2[g] + p;
+      x3 = xv[p] + pr;
     }
-    sb[e] = bv;
-    sd[e] = dv;
+    sb[e] = bv[p];
+    sd[e] = sv[p][4];
     sx3[e] = x3;
   }
   __syncthreads();
-  for (int e = tid; e < kUE * kUE; e += 256) {
-    const int lx = e % kUE, ly = e / kUE, fx = ox + lx, fy = oy + ly;
+#pragma unroll
+  for (int p = 0; p < kNP; ++p) {
+    const int e = tid + 256 * p, lx = e % kUE, ly = e / kUE;
+    if (e >= kUE * kUE) continue;
     double v = 0.0;
-    if (lx >= 1 && lx < kUE - 1 && ly >= 1 && ly < kUE - 1 && inside(fx, fy)) {
-      const int64_t g = gidx(fx, fy);
+    if (lx >= 1 && lx < kUE - 1 && ly >= 1 && ly < kUE - 1 && gp[p] >= 0) {
       double ax = 0.0;
 #pragma unroll
-      for (int t = 0; t < 9; ++t)
-        ax += S[t * Nf + g] * sx3[(ly + t / 3 - 1) * kUE + (lx + t % 3 - 1)];
+      for (int t = 0; t < 9; ++t) ax += sv[p][t] * sx3[(ly + t / 3 - 1) * kUE + (lx + t % 3 - 1)];
       v = sx3[e] + omega * (sb[e] - ax) / sd[e];
     }
     sx4[e] = v;
   }
   __syncthreads();
-  for (int e = tid; e < kUE * kUE; e += 256) {
-    const int lx = e % kUE, ly = e / kUE, fx = ox + lx, fy = oy + ly;
-    if (lx >= 2 && lx < kUE - 2 && ly >= 2 && ly < kUE - 2 && inside(fx, fy)) {
-      const int64_t g = gidx(fx, fy);
+#pragma unroll
+  for (int p = 0; p < kNP; ++p) {
+    const int e = tid + 256 * p, lx = e % kUE, ly = e / kUE;
+    if (e >= kUE * kUE) continue;
+    if (lx >= 2 && lx < kUE - 2 && ly >= 2 && ly < kUE - 2 && gp[p] >= 0) {
       double ax = 0.0;
 #pragma unroll
-      for (int t = 0; t < 9; ++t)
-        ax += S[t * Nf + g] * sx4[(ly + t / 3 - 1) * kUE + (lx + t % 3 - 1)];
-      xout[(int64_t)(xmap ? xmap[mode] : mode) * Nf + g] = sx4[e] + omega * (sb[e] - ax) / sd[e];
+      for (int t = 0; t < 9; ++t) ax += sv[p][t] * sx4[(ly + t / 3 - 1) * kUE + (lx + t % 3 - 1)];
+      xout[(int64_t)(xmap ? xmap[mode] : mode) * Nf + gp[p]] = sx4[e] + omega * (sb[e] - ax) / sd[e];
     }
   }
   __syncthreads();

@@ -4,21 +4,24 @@
 // w T T^T, exact for q >= 2p; see FRowSetDev), with the chaos structure of
 // J(M, p) generated at compile time: every multi-index, monomial recursion
 // and (gamma <= alpha) pair is a constant, so the per-point contraction runs
-// entirely in registers with no index arithmetic.  One wavefront per
-// 4 x 4-element tile, one Gauss point per lane:
+// entirely in registers with no index arithmetic.  One workgroup of two
+// wavefronts per 4 x 4-element tile, one Gauss point per lane; both steps are
+// linear and act on each gradient component separately, so wavefront c
+// carries component c of every gradient:
 //   1. nodal values of the tile (5 x 5 nodes, every mode) -> LDS;
-//   2. per lane: scaled gradients G^_alpha = s_alpha grad U_alpha for the
-//      column modes (zero for the others), w(x_q), scaled monomials
-//      m_delta = g^delta / delta!;
+//   2. per lane: component c of the scaled gradients G^_alpha = s_alpha grad
+//      U_alpha for the column modes (zero for the others), w(x_q), scaled
+//      monomials m_delta = g^delta / delta!;
 //   3. step 1 in place, gamma in graded order: Vbar_gamma = s_gamma^-2
 //      sum_{alpha >= gamma} m_(alpha-gamma) G^_alpha (only alpha of higher
 //      degree or gamma itself are read, none of them overwritten yet);
 //   4. step 2 for the output rows: flux_beta = s_beta w sum_{gamma <= beta}
 //      m_(beta-gamma) Vbar_gamma + a_min grad U_beta (column rows only); the
-//      four corner contributions (1/4) grad phi_a . flux of each element are
-//      reduce-scattered over the element's four lanes -> LDS;
-//   5. the tile's 25 node sums per row, in a fixed order -> out (owned nodes)
-//      and the edge buffer (right/top edge, corner) for the fixup.
+//      four corner contributions (1/4) d_c phi_a flux_c of each element are
+//      reduce-scattered over the element's four lanes (quad permutations) ->
+//      LDS, one array per component (the nodal values are dead by then);
+//   5. the tile's 25 node sums per row (both components, fixed order) -> out
+//      (owned nodes) and the edge buffer (right/top edge, corner) for the fixup.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -174,6 +177,18 @@ inline int r_cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 }  // namespace
 
+// value of lane (lane ^ K) of the lane's quad, K = 1 or 2 (DPP quad permutation;
+// every lane of the wavefront active)
+template <int K>
+__device__ __forceinline__ double quad_xor(double v) {
+  constexpr int ctrl = K == 1 ? 0xB1 : 0x4E;  // quad_perm [1,0,3,2] / [2,3,0,1]
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+constexpr int kRThreads = 128;  // two wavefronts per tile
+
 template <int M, int p>
 __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, double mu,
                                             double a_min, const double* __restrict__ g,
@@ -183,22 +198,24 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
                                             double* __restrict__ edge) {
   constexpr const RTab<M, p>& T = RTabHolder<M, p>::v;
   constexpr int P = RTab<M, p>::P;
-  double* sN = smem;             // [P][25] nodal values
-  double* sC = smem + P * 25;    // [nrows][64] corner contributions
+  const int nrows = rr.nrows;
+  double* sN = smem;  // [P][25] nodal values (steps 1-2)
+  double* sC = smem;  // [2][nrows][64] corner contributions (steps 4-5)
   const int nt = n / kTileE, ntiles = nt * nt;
   const int tx = tile % nt, ty = tile / nt;
   const int x0 = tx * kTileE, y0 = ty * kTileE;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int comp = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int m = n - 1;
   const int64_t Nq = (int64_t)4 * n * n;
   const uint64_t colmask = rr.colmask, rowmask = rr.rowmask;
 
   // 1. nodal values of the column modes (all loads in flight at once)
-  constexpr int NL = (P * 25 + 63) / 64;
+  constexpr int NL = (P * 25 + kRThreads - 1) / kRThreads;
   double v[NL];
 #pragma unroll
   for (int u = 0; u < NL; ++u) {
-    const int idx = lane + 64 * u;
+    const int idx = tid + kRThreads * u;
     const int c = min(idx / 25, P - 1), nd = idx - (idx / 25) * 25;
     const int gx = x0 + nd % 5, gy = y0 + nd / 5;
     const bool ok = idx < P * 25 && ((colmask >> c) & 1) && gx >= 1 && gx <= m && gy >= 1 && gy <= m;
@@ -209,25 +226,29 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
   for (int nn = 0; nn < M; ++nn) gv[nn] = g[(int64_t)nn * Nq + (int64_t)tile * kTileQ + lane];
 #pragma unroll
   for (int u = 0; u < NL; ++u)
-    if (lane + 64 * u < P * 25) sN[lane + 64 * u] = v[u];
+    if (tid + kRThreads * u < P * 25) sN[tid + kRThreads * u] = v[u];
   __syncthreads();
 
-  // 2. gradients, w, monomials
+  // 2. gradient component c, w, monomials.  Component c of grad u at (xi, eta)
+  // is w0 (u_B - u_A) + w1 (u_D - u_C) over the element's corners:
+  //   x: (1 - eta)(u10 - u00) + eta (u11 - u01),  y: (1 - xi)(u01 - u00) + xi (u11 - u10)
   const int el = lane >> 2, ql = lane & 3;
   const int ex = el & 3, ey = el >> 2;
   const double xi = r_gauss_pt(ql & 1), eta = r_gauss_pt(ql >> 1);
-  double G[P][2];
+  const int o00 = ey * 5 + ex, o10 = o00 + 1, o01 = o00 + 5, o11 = o00 + 6;
+  const int oA = o00, oB = comp ? o01 : o10, oC = comp ? o10 : o01, oD = o11;
+  const double w0 = comp ? 1.0 - xi : 1.0 - eta, w1 = comp ? xi : eta;
+  double G[P], Gc[P];  // Gc: unscaled component, for the a_min term of column rows
 #pragma unroll
   for (int a = 0; a < P; ++a) {
     if (!((colmask >> a) & 1)) {  // not a column of this block
-      G[a][0] = G[a][1] = 0.0;
+      G[a] = Gc[a] = 0.0;
       continue;
     }
     const double* u = sN + a * 25;
-    const double u00 = u[ey * 5 + ex], u10 = u[ey * 5 + ex + 1];
-    const double u01 = u[(ey + 1) * 5 + ex], u11 = u[(ey + 1) * 5 + ex + 1];
-    G[a][0] = T.s[a] * ((1.0 - eta) * (u10 - u00) + eta * (u11 - u01));
-    G[a][1] = T.s[a] * ((1.0 - xi) * (u01 - u00) + xi * (u11 - u10));
+    const double d = w0 * (u[oB] - u[oA]) + w1 * (u[oD] - u[oC]);
+    G[a] = T.s[a] * d;
+    Gc[a] = d;
   }
   double s2 = 0.0;
 #pragma unroll
@@ -237,6 +258,7 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
   mono[0] = 1.0;
 #pragma unroll
   for (int d = 1; d < P; ++d) mono[d] = mono[T.par[d]] * gv[T.var[d]] * T.inv[d];
+  __syncthreads();  // both wavefronts are done with the nodal values
 
   // 3. step 1 in place
   // gamma outside the block's set: never read by step 2, or zero (then no column
@@ -245,69 +267,62 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
 #pragma unroll
   for (int gm = 0; gm < P; ++gm) {
     if (!((gammask >> gm) & 1)) continue;
-    double sx = 0.0, sy = 0.0;
+    double sx = 0.0;
 #pragma unroll
-    for (int t = T.p1[gm]; t < T.p1[gm + 1]; ++t) {
-      sx = fma(mono[T.d1[t]], G[T.a1[t]][0], sx);
-      sy = fma(mono[T.d1[t]], G[T.a1[t]][1], sy);
-    }
-    G[gm][0] = sx * T.is2[gm];
-    G[gm][1] = sy * T.is2[gm];
+    for (int t = T.p1[gm]; t < T.p1[gm + 1]; ++t) sx = fma(mono[T.d1[t]], G[T.a1[t]], sx);
+    G[gm] = sx * T.is2[gm];
   }
 
-  // 4. step 2 and the corner contributions of every output row
-  double gpx[4], gpy[4];
+  // 4. step 2 and the corner contributions of every output row.  Slot k of a
+  // lane holds the contribution to corner ql ^ k of its element, so the
+  // reduce-scatter (pairs two apart, then neighbours) needs no selects.
+  double gp[4];
 #pragma unroll
-  for (int a4 = 0; a4 < 4; ++a4) {
-    const int ax = a4 & 1, ay = a4 >> 1;
-    gpx[a4] = 0.25 * (ax ? 1.0 : -1.0) * (ay ? eta : 1.0 - eta);
-    gpy[a4] = 0.25 * (ay ? 1.0 : -1.0) * (ax ? xi : 1.0 - xi);
+  for (int k = 0; k < 4; ++k) {
+    const int a4 = ql ^ k, ax = a4 & 1, ay = a4 >> 1;
+    gp[k] = comp ? 0.25 * (ay ? 1.0 : -1.0) * (ax ? xi : 1.0 - xi)
+                 : 0.25 * (ax ? 1.0 : -1.0) * (ay ? eta : 1.0 - eta);
   }
+  double* sCc = sC + comp * nrows * 64;
 #pragma unroll
   for (int b = 0; b < P; ++b) {
     if (!((rowmask >> b) & 1)) continue;
-    double sx = 0.0, sy = 0.0;
+    double sx = 0.0;
 #pragma unroll
-    for (int t = T.p2[b]; t < T.p2[b + 1]; ++t) {
-      sx = fma(mono[T.d2[t]], G[T.g2[t]][0], sx);
-      sy = fma(mono[T.d2[t]], G[T.g2[t]][1], sy);
-    }
+    for (int t = T.p2[b]; t < T.p2[b + 1]; ++t) sx = fma(mono[T.d2[t]], G[T.g2[t]], sx);
     const double sr = T.s[b] * w;
-    double fx = sr * sx, fy = sr * sy;
-    if ((colmask >> b) & 1) {
-      // a_min grad U_beta from the nodal values (the gradient slot now holds Vbar)
-      const double* u = sN + b * 25;
-      const double u00 = u[ey * 5 + ex], u10 = u[ey * 5 + ex + 1];
-      const double u01 = u[(ey + 1) * 5 + ex], u11 = u[(ey + 1) * 5 + ex + 1];
-      fx = fma(a_min, (1.0 - eta) * (u10 - u00) + eta * (u11 - u01), fx);
-      fy = fma(a_min, (1.0 - xi) * (u01 - u00) + xi * (u11 - u10), fy);
-    }
-    double t4[4];
-#pragma unroll
-    for (int a4 = 0; a4 < 4; ++a4) t4[a4] = gpx[a4] * fx + gpy[a4] * fy;
-    // reduce-scatter over the element's four lanes: lane ql ends with corner ql
-    const bool hi2 = (ql & 2) != 0, hi1 = (ql & 1) != 0;
-    double k0 = hi2 ? t4[2] : t4[0], k1 = hi2 ? t4[3] : t4[1];
-    const double x0v = hi2 ? t4[0] : t4[2], x1v = hi2 ? t4[1] : t4[3];
-    k0 += __shfl_xor(x0v, 2);
-    k1 += __shfl_xor(x1v, 2);
-    double kk = hi1 ? k1 : k0;
-    kk += __shfl_xor(hi1 ? k0 : k1, 1);
-    sC[rr.slot[b] * 64 + lane] = kk;
+    double f = sr * sx;
+    if ((colmask >> b) & 1) f = fma(a_min, Gc[b], f);
+    const double k0 = gp[0] * f + quad_xor<2>(gp[2] * f);
+    const double k1 = gp[1] * f + quad_xor<2>(gp[3] * f);
+    sCc[rr.slot[b] * 64 + lane] = k0 + quad_xor<1>(k1);
   }
   __syncthreads();
 
-  // 5. node sums: corner 3 of (x-1, y-1), 2 of (x, y-1), 1 of (x-1, y), 0 of (x, y)
-  const int nrows = rr.nrows;
-  for (int idx = lane; idx < nrows * 25; idx += 64) {
+  // 5. node sums: corner 3 of (x-1, y-1), 2 of (x, y-1), 1 of (x-1, y), 0 of (x, y),
+  // each the x part plus the y part
+  for (int idx = tid; idx < nrows * 25; idx += kRThreads) {
     const int slot = idx / 25, nd = idx - slot * 25;
     const int nx = nd % 5, ny = nd / 5;
     const double* c = sC + slot * 64;
+    const double* cy = c + nrows * 64;
     double sum = 0.0;
-    if (nx >= 1 && ny >= 1) sum += c[((ny - 1) * 4 + nx - 1) * 4 + 3];
-    if (nx <= 3 && ny >= 1) sum += c[((ny - 1) * 4 + nx) * 4 + 2];
-    if (nx >= 1 && ny <= 3) sum += c[(ny * 4 + nx - 1) * 4 + 1];
-    if (nx <= 3 && ny <= 3) sum += c[(ny * 4 + nx) * 4 + 0];
+    if (nx >= 1 && ny >= 1) {
+      const int i = ((ny - 1) * 4 + nx - 1) * 4 + 3;
+      sum += c[i] + cy[i];
+    }
+    if (nx <= 3 && ny >= 1) {
+      const int i = ((ny - 1) * 4 + nx) * 4 + 2;
+      sum += c[i] + cy[i];
+    }
+    if (nx >= 1 && ny <= 3) {
+      const int i = (ny * 4 + nx - 1) * 4 + 1;
+      sum += c[i] + cy[i];
+    }
+    if (nx <= 3 && ny <= 3) {
+      const int i = (ny * 4 + nx) * 4;
+      sum += c[i] + cy[i];
+    }
     if (nx <= 3 && ny <= 3) {
       const int gx = x0 + nx, gy = y0 + ny;
       if (gx >= 1 && gy >= 1) {
@@ -324,7 +339,7 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
 }
 
 template <int M, int p>
-__global__ __launch_bounds__(64) void rapply_kernel(int n, double mu, double a_min,
+__global__ __launch_bounds__(kRThreads, 2) void rapply_kernel(int n, double mu, double a_min,
                                                     const double* __restrict__ g, RApplyRows rr,
                                                     const double* __restrict__ U, int64_t Nh,
                                                     const double* __restrict__ rin, double beta,
@@ -338,7 +353,7 @@ __global__ __launch_bounds__(64) void rapply_kernel(int n, double mu, double a_m
 
 // (instance, tile) items of instances sharing one (M, p)
 template <int M, int p>
-__global__ __launch_bounds__(64) void brapply_kernel(const BInst* __restrict__ Is,
+__global__ __launch_bounds__(kRThreads) void brapply_kernel(const BInst* __restrict__ Is,
                                                      const BState* __restrict__ Ss,
                                                      const BItem* __restrict__ items, int nitems,
                                                      int rowset, int src, int rin, int dst,
@@ -356,7 +371,10 @@ __global__ __launch_bounds__(64) void brapply_kernel(const BInst* __restrict__ I
   }
 }
 
-size_t rapply_lds_bytes(int P, int nrows) { return 8 * ((size_t)P * 25 + (size_t)nrows * 64); }
+// the nodal values and, after them, the corner contributions of both components
+size_t rapply_lds_bytes(int P, int nrows) {
+  return 8 * std::max((size_t)P * 25, (size_t)2 * nrows * 64);
+}
 
 #define SG_RAPPLY_LIST(X) \
   X(1, 1) X(1, 2) X(1, 3) X(1, 4) X(2, 1) X(2, 2) X(2, 3) X(2, 4) X(3, 1) X(3, 2) X(3, 3) \
@@ -395,7 +413,7 @@ void launch_rapply(hipStream_t s, int M, int p, int n, double mu, double a_min, 
   const size_t lds = rapply_lds_bytes(P, rr.nrows);
 #define SG_RAPPLY_LAUNCH(MM, PP)                                                               \
   if (M == MM && p == PP) {                                                                    \
-    hipLaunchKernelGGL((rapply_kernel<MM, PP>), dim3(ntiles), dim3(64), lds, s, n, mu, a_min, \
+    hipLaunchKernelGGL((rapply_kernel<MM, PP>), dim3(ntiles), dim3(kRThreads), lds, s, n, mu, a_min, \
                        g, rr, U, Nh, rin, beta, sgn, out, edge);                               \
   } else
   SG_RAPPLY_LIST(SG_RAPPLY_LAUNCH) { throw Error(SG_ERR_INTERNAL, "register apply: (M, p)"); }
@@ -410,7 +428,7 @@ void launch_brapply(hipStream_t s, int M, int p, size_t lds, const BInst* I, con
   const int grid = std::min(nitems, 256 * 8);
 #define SG_BRAPPLY_LAUNCH(MM, PP)                                                             \
   if (M == MM && p == PP) {                                                                   \
-    hipLaunchKernelGGL((brapply_kernel<MM, PP>), dim3(grid), dim3(64), lds, s, I, st, items, \
+    hipLaunchKernelGGL((brapply_kernel<MM, PP>), dim3(grid), dim3(kRThreads), lds, s, I, st, items, \
                        nitems, rowset, src, rin, dst, beta, sgn, gate);                       \
   } else
   SG_RAPPLY_LIST(SG_BRAPPLY_LAUNCH) { throw Error(SG_ERR_INTERNAL, "batched register apply: (M, p)"); }
