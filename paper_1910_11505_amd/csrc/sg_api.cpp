@@ -608,11 +608,13 @@ void check_launch() {
 // bmap / xmap (device, may be null; l0 must be a fused fine level): mode t reads
 // vector bmap[t] of b and writes vector xmap[t] of x.
 void vcycle_levels(sg_handle& H, hipStream_t s, int l0, int m, const int* smode, const double* b,
-                   double* x, const int* bmap = nullptr, const int* xmap = nullptr) {
+                   double* x, const int* bmap = nullptr, const int* xmap = nullptr,
+                   const EdgeFix& ef = EdgeFix{}) {
   DevPtrs& D = H.d;
   const int nf = H.nfine;
   const int nl = (int)D.L.size();
-  if ((bmap || xmap) && l0 >= nf) throw Error(SG_ERR_INTERNAL, "mode maps need a fused level");
+  if ((bmap || xmap || ef.edge) && l0 >= nf)
+    throw Error(SG_ERR_INTERNAL, "mode maps and edge sums need a fused level");
   std::vector<const double*> bl(nl);
   std::vector<double*> xl(nl);
   for (int l = l0 + 1; l < nl; ++l) {
@@ -624,7 +626,7 @@ void vcycle_levels(sg_handle& H, hipStream_t s, int l0, int m, const int* smode,
   const int c0 = std::max(nf, l0);
   for (int l = l0; l < nf; ++l)
     launch_vdown(s, D.L[l], D.L[l + 1], m, smode, bl[l], D.mg_xa[l], D.mg_b[l + 1], kOmega,
-                 l == l0 ? bmap : nullptr);
+                 l == l0 ? bmap : nullptr, l == l0 ? ef : EdgeFix{});
   CoarseLevels cl{};
   cl.nl = nl - c0;
   for (int l = 0; l < cl.nl; ++l) {
@@ -635,7 +637,7 @@ void vcycle_levels(sg_handle& H, hipStream_t s, int l0, int m, const int* smode,
   launch_vcoarse(s, cl, m, smode, bl[c0], xl[c0], kOmega);
   for (int l = nf - 1; l >= l0; --l)
     launch_vup(s, D.L[l], D.L[l + 1], m, smode, bl[l], D.mg_xa[l], xl[l + 1], xl[l], kOmega,
-               l == l0 ? bmap : nullptr, l == l0 ? xmap : nullptr);
+               l == l0 ? bmap : nullptr, l == l0 ? xmap : nullptr, 1, l == l0 ? ef : EdgeFix{});
 }
 
 // Whether vcycle() can read and write through mode maps (the finest level is a
@@ -644,22 +646,29 @@ bool vcycle_maps_ok(const sg_handle& H, const int* smode) {
   return H.nfine > 0 || (!smode && H.dense_ready);
 }
 
+// Whether vcycle()'s finest level is a vdown / vup pair, which can add an
+// apply's pending edge sums to the right-hand side as it reads it.
+bool vcycle_edges_ok(const sg_handle& H, const int* smode) {
+  return (!smode && H.dense_ready) ? H.ldense > 0 : H.nfine > 0;
+}
+
 // One V(2,2) cycle on the finest level.  With the mean stiffness (smode null)
 // the levels from H.ldense down are one precomputed dense operator (the same
 // linear map, built by vcycle_levels on unit vectors at bind).
 void vcycle(sg_handle& H, hipStream_t s, int m, const int* smode, const double* b, double* x,
-            const int* bmap = nullptr, const int* xmap = nullptr) {
+            const int* bmap = nullptr, const int* xmap = nullptr, const EdgeFix& ef = EdgeFix{}) {
   if (smode || !H.dense_ready) {
-    vcycle_levels(H, s, 0, m, smode, b, x, bmap, xmap);
+    vcycle_levels(H, s, 0, m, smode, b, x, bmap, xmap, ef);
     return;
   }
+  if (ef.edge && H.ldense == 0) throw Error(SG_ERR_INTERNAL, "edge sums need a fused level");
   DevPtrs& D = H.d;
   const int ld = H.ldense;
   auto bl = [&](int l) -> const double* { return l == 0 ? b : D.mg_b[l]; };
   auto xl = [&](int l) -> double* { return l == 0 ? x : D.mg_x[l]; };
   for (int l = 0; l < ld; ++l)
     launch_vdown(s, D.L[l], D.L[l + 1], m, nullptr, bl(l), D.mg_xa[l], D.mg_b[l + 1], kOmega,
-                 l == 0 ? bmap : nullptr);
+                 l == 0 ? bmap : nullptr, l == 0 ? ef : EdgeFix{});
   // below the finest level the operator runs in kDenseSlices inner-index
   // slices whose partial results the next finer vup sums
   const int slices = ld == 0 ? 1 : kDenseSlices;
@@ -667,18 +676,31 @@ void vcycle(sg_handle& H, hipStream_t s, int m, const int* smode, const double* 
                       ld == 0 ? xmap : nullptr, slices);
   for (int l = ld - 1; l >= 0; --l)
     launch_vup(s, D.L[l], D.L[l + 1], m, nullptr, bl(l), D.mg_xa[l], xl(l + 1), xl(l), kOmega,
-               l == 0 ? bmap : nullptr, l == 0 ? xmap : nullptr, l == ld - 1 ? slices : 1);
+               l == 0 ? bmap : nullptr, l == 0 ? xmap : nullptr, l == ld - 1 ? slices : 1,
+               l == 0 ? ef : EdgeFix{});
 }
 
-void do_apply(sg_handle& H, hipStream_t s, const double* U, double* W) {
+// The edge sums an apply with sign sgn leaves pending in H.d.edge.
+EdgeFix pending_edges(const sg_handle& H, double sgn) {
+  EdgeFix f;
+  f.edge = H.d.edge;
+  f.nt = H.n / kTileE;
+  f.sgn = sgn;
+  f.Nh = H.Nh;
+  f.m = H.n - 1;
+  return f;
+}
+
+// W = K U; with fixup false the edge sums stay pending (pending_edges(H, 1.0)).
+void do_apply(sg_handle& H, hipStream_t s, const double* U, double* W, bool fixup = true) {
   if (H.use_factored && H.use_rapply)
     launch_rapply(s, H.M, H.prob.p, H.n, H.prob.mu, H.prob.a_min, H.d.g, H.rfull, U, H.Nh,
-                  nullptr, 0.0, 1.0, W, H.d.edge);
+                  nullptr, 0.0, 1.0, W, H.d.edge, fixup);
   else if (H.use_factored)
     launch_fapply(s, H.n, H.prob.mu, H.prob.a_min, H.d.g, H.d.ffull, U, H.Nh, nullptr, 0.0, 1.0,
-                  W, H.d.edge);
+                  W, H.d.edge, fixup);
   else
-    launch_apply(s, H.n, H.na, H.d.a, H.d.full, U, H.Nh, nullptr, 0.0, 1.0, W, H.d.edge);
+    launch_apply(s, H.n, H.na, H.d.a, H.d.full, U, H.Nh, nullptr, 0.0, 1.0, W, H.d.edge, fixup);
 }
 
 void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double* r, double* z) {
@@ -701,6 +723,8 @@ void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double*
     const int m = (int)fh.splits[sp].size();
     const int* smode = kii ? fd.split_sid[sp] : nullptr;
     const bool maps = vcycle_maps_ok(H, smode);
+    // the off-diagonal apply's edge sums are added by the cycle's finest level
+    const bool defer = maps && vcycle_edges_ok(H, smode);
     if (sp == 0) {
       // the gather is folded into the cycle's finest level when it can be
       if (maps) {
@@ -711,16 +735,17 @@ void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double*
     } else {
       if (H.use_factored && H.use_rapply)
         launch_rapply(s, H.M, H.prob.p, H.n, H.prob.mu, H.prob.a_min, H.d.g, H.rpart[grouping][sp],
-                      z, H.Nh, r, 1.0, -1.0, H.d.fsT, H.d.edge);
+                      z, H.Nh, r, 1.0, -1.0, H.d.fsT, H.d.edge, !defer);
       else if (H.use_factored)
         launch_fapply(s, H.n, H.prob.mu, H.prob.a_min, H.d.g, fd.fpartial[sp], z, H.Nh, r, 1.0,
-                      -1.0, H.d.fsT, H.d.edge);
+                      -1.0, H.d.fsT, H.d.edge, !defer);
       else
         launch_apply(s, H.n, H.na, H.d.a, fd.partial[sp], z, H.Nh, r, 1.0, -1.0, H.d.fsT,
-                     H.d.edge);
+                     H.d.edge, !defer);
     }
     if (maps) {
-      vcycle(H, s, m, smode, H.d.fsT, z, nullptr, fd.split_idx[sp]);
+      vcycle(H, s, m, smode, H.d.fsT, z, nullptr, fd.split_idx[sp],
+             defer ? pending_edges(H, -1.0) : EdgeFix{});
     } else {
       vcycle(H, s, m, smode, H.d.fsT, H.d.fsX);
       launch_scatter_modes(s, m, fd.split_idx[sp], H.Nh, H.d.fsX, z);
@@ -1220,6 +1245,10 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
       for (int j = 0; j < m; ++j) {
         double* vj = K.V + (int64_t)j * Nv;
         double* zj = K.z;
+        // the main apply's edge sums are added by the first two Gram-Schmidt
+        // passes while they read w (they hold the basis in registers up to 64
+        // vectors)
+        const bool defer = !learned && j + 1 <= 64;
         if (queued) {
           queued = false;
         } else if (learned) {
@@ -1249,15 +1278,16 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
           }
         } else {
           do_precond(H, s, o->pc, o->grouping, vj, K.z);
-          do_apply(H, s, zj, K.w);
+          do_apply(H, s, zj, K.w, !defer);
         }
+        const EdgeFix ef = defer ? pending_edges(H, 1.0) : EdgeFix{};
         double* h1 = K.hdev;
         double* h2 = K.hdev + (m + 1);
         double* nrm = K.hdev + 2 * (m + 1);
         // CGS2: h1 = V^T w, w -= V h1, h2 = V^T w (fused with that update),
         // w -= V h2 and |w|^2 (fused with the second update)
-        launch_gs_dot(s, K.V, Nv, j + 1, K.w, Nv, K.partial, h1);
-        launch_gs_update_dot(s, K.V, Nv, j + 1, h1, K.w, Nv, -1.0, K.partial, h2);
+        launch_gs_dot(s, K.V, Nv, j + 1, K.w, Nv, K.partial, h1, ef);
+        launch_gs_update_dot(s, K.V, Nv, j + 1, h1, K.w, Nv, -1.0, K.partial, h2, ef);
         launch_gs_update_norm(s, K.V, Nv, j + 1, h2, K.w, Nv, -1.0, K.partial, nrm);
         launch_scale_by_inv_norm(s, K.w, nrm, K.V + (int64_t)(j + 1) * Nv, Nv);
         check_launch();
@@ -1265,7 +1295,7 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
         SG_HIP(hipEventRecord(H.fetched, s));
         if (!learned && j + 1 < m && it + 1 < o->max_it) {
           do_precond(H, s, o->pc, o->grouping, K.V + (int64_t)(j + 1) * Nv, K.z);
-          do_apply(H, s, K.z, K.w);
+          do_apply(H, s, K.z, K.w, !(j + 2 <= 64));
           queued = true;
         }
         SG_HIP(hipEventSynchronize(H.fetched));

@@ -150,9 +150,50 @@ void launch_coeff(hipStream_t s, int n, int M, int na, const double* g, const in
 void launch_fine_stencil(hipStream_t s, int n, const double* a0, double* S);
 void launch_rap(hipStream_t s, int nf, const double* Sf, double* Sc);
 void launch_rhs(hipStream_t s, int n, const double* f_nodal, double* F, int64_t total);
+// Edge sums of a tile-based operator apply not yet added to its output
+// (edge null: none pending).  A tile owns its 4 x 4 lower-left nodes; its
+// right/top edge and corner sums (kEdgeVals per tile and output vector) belong
+// to the neighbouring tiles' nodes.  The apply kernels either add them in a
+// fixup kernel or leave them to the kernel that reads the output next, which
+// adds them for output vector slot at interior node (gx, gy) (1-based) in the
+// fixup kernel's order, so both give the same bits.
+struct EdgeFix {
+  const double* edge = nullptr;
+  int nt = 0;         // tiles per side
+  double sgn = 1.0;   // sign the sums enter the output with
+  int64_t Nh = 0;     // vector length (node count) of one output vector
+  int m = 0;          // interior nodes per side
+};
+
+__device__ __forceinline__ double edge_fixed(double v, const EdgeFix& f, int slot, int gx, int gy) {
+  const int nx = gx & 3, ny = gy & 3;
+  if (nx && ny) return v;
+  const int nt = f.nt, tile = (gy >> 2) * nt + (gx >> 2);
+  const double* eb = f.edge + (int64_t)slot * nt * nt * kEdgeVals;
+  if (nx == 0) v += f.sgn * eb[(int64_t)(tile - 1) * kEdgeVals + ny];
+  if (ny == 0) v += f.sgn * eb[(int64_t)(tile - nt) * kEdgeVals + 4 + nx];
+  if (nx == 0 && ny == 0) v += f.sgn * eb[(int64_t)(tile - nt - 1) * kEdgeVals + 8];
+  return v;
+}
+
+// element i of a vector of output vectors (vector i / Nh, node i % Nh) with
+// its pending edge sums added
+__device__ __forceinline__ double w_fixed(const double* __restrict__ w, int64_t i, const EdgeFix& f) {
+  double v = w[i];
+  if (f.edge) {
+    const unsigned ii = (unsigned)i, nh = (unsigned)f.Nh, mm = (unsigned)f.m;
+    const unsigned slot = ii / nh, node = ii - slot * nh;
+    const unsigned gy = node / mm, gx = node - gy * mm;
+    v = edge_fixed(v, f, (int)slot, (int)gx + 1, (int)gy + 1);
+  }
+  return v;
+}
+
+// The apply launchers end with the edge fixup unless fixup is false (the
+// caller then hands the pending sums to the next reader as an EdgeFix).
 void launch_apply(hipStream_t s, int n, int na, const double* a, const RowSetDev& rs,
                   const double* U, int64_t Nh, const double* rin, double beta, double sgn,
-                  double* out, double* edge);
+                  double* out, double* edge, bool fixup = true);
 size_t apply_lds_bytes(int maxcols, int kc, int maxent);
 constexpr int kDenseK = 1024;  // padded inner index of the dense coarse operator (>= 31^2)
 void launch_dense_coarse(hipStream_t s, int N, int m, const double* C, const double* B, double* X,
@@ -162,13 +203,13 @@ bool rapply_supported(int M, int p);
 bool rapply_matches(int M, int p, const std::vector<std::vector<int>>& Jp);
 void launch_rapply(hipStream_t s, int M, int p, int n, double mu, double a_min, const double* g,
                    const RApplyRows& rr, const double* U, int64_t Nh, const double* rin,
-                   double beta, double sgn, double* out, double* edge);
+                   double beta, double sgn, double* out, double* edge, bool fixup = true);
 void launch_apply_fixup(hipStream_t s, int n, int nrows, double sgn, const double* edge,
                         double* out, int64_t Nh);
 size_t fapply_lds_bytes(int qb, int nrows, int ncols, int ngam, int nmono, int M, int nblob);
 void launch_fapply(hipStream_t s, int n, double mu, double a_min, const double* g,
                    const FRowSetDev& rs, const double* U, int64_t Nh, const double* rin,
-                   double beta, double sgn, double* out, double* edge);
+                   double beta, double sgn, double* out, double* edge, bool fixup = true);
 void launch_zero(hipStream_t s, double* x, int64_t n);
 void launch_gather_modes(hipStream_t s, int m, const int* modes, int64_t Nh, const double* src,
                          double* dst);
@@ -183,10 +224,11 @@ struct CoarseLevels {
 };
 void launch_vdown(hipStream_t s, const Level& Lf, const Level& Lc, int modes, const int* smode,
                   const double* b, double* x2, double* bc, double omega,
-                  const int* bmap = nullptr);
+                  const int* bmap = nullptr, const EdgeFix& ef = EdgeFix{});
 void launch_vup(hipStream_t s, const Level& Lf, const Level& Lc, int modes, const int* smode,
                 const double* b, const double* x2, const double* xc, double* x, double omega,
-                const int* bmap = nullptr, const int* xmap = nullptr, int xc_slices = 1);
+                const int* bmap = nullptr, const int* xmap = nullptr, int xc_slices = 1,
+                const EdgeFix& ef = EdgeFix{});
 void launch_vcoarse(hipStream_t s, const CoarseLevels& cl, int modes, const int* smode,
                     const double* b, double* x, double omega);
 size_t vcoarse_lds_bytes(const CoarseLevels& cl);
@@ -202,10 +244,12 @@ void launch_update(hipStream_t s, const double* V, int64_t ldv, int nv, const do
 // Gram-Schmidt passes (one element per thread, partial sized nv * gs_blocks(N));
 // each ends with the reduction into out[0..nv) (out[0] for the norm)
 int gs_blocks(int64_t N);
+// (ef: pending edge sums of the apply that wrote w, added as w is read)
 void launch_gs_dot(hipStream_t s, const double* V, int64_t ldv, int nv, const double* w, int64_t N,
-                   double* partial, double* out);
+                   double* partial, double* out, const EdgeFix& ef = EdgeFix{});
 void launch_gs_update_dot(hipStream_t s, const double* V, int64_t ldv, int nv, const double* h,
-                          double* w, int64_t N, double sign, double* partial, double* out);
+                          double* w, int64_t N, double sign, double* partial, double* out,
+                          const EdgeFix& ef = EdgeFix{});
 void launch_gs_update_norm(hipStream_t s, const double* V, int64_t ldv, int nv, const double* h,
                            double* w, int64_t N, double sign, double* partial, double* out);
 void launch_combine(hipStream_t s, const double* V, int64_t ldv, int nv, const double* y,

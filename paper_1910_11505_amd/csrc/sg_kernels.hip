@@ -463,7 +463,7 @@ size_t apply_lds_bytes(int maxcols, int kc, int maxent) {
 
 void launch_apply(hipStream_t s, int n, int na, const double* a, const RowSetDev& rs,
                   const double* U, int64_t Nh, const double* rin, double beta, double sgn,
-                  double* out, double* edge) {
+                  double* out, double* edge, bool fixup) {
   const int nt = n / kTileE;
   const int ntiles = nt * nt;
   const size_t lds = apply_lds_bytes(rs.maxcols, rs.kc, rs.maxent);
@@ -485,9 +485,7 @@ void launch_apply(hipStream_t s, int n, int na, const double* a, const RowSetDev
       throw Error(SG_ERR_INTERNAL, "apply: unsupported rows per wavefront");
   }
 #undef SG_APPLY_CASE
-  const int64_t total = (int64_t)rs.nrows * ntiles * 7;
-  hipLaunchKernelGGL(apply_fixup_kernel, dim3(cdiv(total, 256)), dim3(256), 0, s, n, rs.nrows,
-                     sgn, edge, out, Nh);
+  if (fixup) launch_apply_fixup(s, n, rs.nrows, sgn, edge, out, Nh);
 }
 
 // ---------------------------------------------------------------------------
@@ -882,7 +880,7 @@ __global__ __launch_bounds__(256) void fapply_kernel(int n, double mu, double a_
 
 void launch_fapply(hipStream_t s, int n, double mu, double a_min, const double* g,
                    const FRowSetDev& rs, const double* U, int64_t Nh, const double* rin,
-                   double beta, double sgn, double* out, double* edge) {
+                   double beta, double sgn, double* out, double* edge, bool fixup) {
   const int nt = n / kTileE;
   const int ntiles = nt * nt;
   const size_t lds =
@@ -903,9 +901,7 @@ void launch_fapply(hipStream_t s, int n, double mu, double a_min, const double* 
     default:
       throw Error(SG_ERR_INTERNAL, "factored apply: bad sub-batch size");
   }
-  const int64_t total = (int64_t)rs.nrows * ntiles * 7;
-  hipLaunchKernelGGL(apply_fixup_kernel, dim3(cdiv(total, 256)), dim3(256), 0, s, n, rs.nrows,
-                     sgn, edge, out, Nh);
+  if (fixup) launch_apply_fixup(s, n, rs.nrows, sgn, edge, out, Nh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1078,13 +1074,13 @@ __global__ __launch_bounds__(kDotThreads) void gs_dot_kernel(const double* __res
                                                             int64_t ldv, int nv,
                                                             const double* __restrict__ w,
                                                             int64_t N, double* __restrict__ partial,
-                                                            int nblk) {
+                                                            int nblk, EdgeFix ef) {
   __shared__ double red[4 * 64];
   const int l0 = 64 * blockIdx.y;
   const int cnt = min(nv - l0, NVB);
   const int64_t i = (int64_t)blockIdx.x * kDotThreads + threadIdx.x;
   const bool in = i < N;
-  const double wi = in ? w[i] : 0.0;
+  const double wi = in ? w_fixed(w, i, ef) : 0.0;
   const double* Vb = V + (int64_t)l0 * ldv + i;
   double a[NVB];
 #pragma unroll
@@ -1101,7 +1097,8 @@ __global__ __launch_bounds__(kDotThreads) void gs_dot_kernel(const double* __res
 template <int NVB>
 __global__ __launch_bounds__(kDotThreads) void gs_update_dot_kernel(
     const double* __restrict__ V, int64_t ldv, int nv, const double* __restrict__ h,
-    double* __restrict__ w, int64_t N, double sign, double* __restrict__ partial, int nblk) {
+    double* __restrict__ w, int64_t N, double sign, double* __restrict__ partial, int nblk,
+    EdgeFix ef) {
   __shared__ double red[4 * 64];
   const int64_t i = (int64_t)blockIdx.x * kDotThreads + threadIdx.x;
   const bool in = i < N;
@@ -1114,7 +1111,7 @@ __global__ __launch_bounds__(kDotThreads) void gs_update_dot_kernel(
     if (l < nv) acc = fma(h[l], a[l], acc);
   double wi = 0.0;
   if (in) {
-    wi = w[i] + sign * acc;
+    wi = w_fixed(w, i, ef) + sign * acc;
     w[i] = wi;
   }
 #pragma unroll
@@ -1162,13 +1159,13 @@ __global__ __launch_bounds__(kDotThreads) void reduce_wide_kernel(const double* 
 }
 
 void launch_gs_dot(hipStream_t s, const double* V, int64_t ldv, int nv, const double* w, int64_t N,
-                   double* partial, double* out) {
+                   double* partial, double* out, const EdgeFix& ef) {
   const int nblk = gs_blocks(N);
   const int top = std::min(nv, 64);
   dim3 grid(nblk, cdiv(nv, 64)), block(kDotThreads);
 #define SG_GS_DOT(B)                                                                          \
   if (top <= B) {                                                                             \
-    hipLaunchKernelGGL(gs_dot_kernel<B>, grid, block, 0, s, V, ldv, nv, w, N, partial, nblk); \
+    hipLaunchKernelGGL(gs_dot_kernel<B>, grid, block, 0, s, V, ldv, nv, w, N, partial, nblk, ef); \
   } else
   SG_GS_DOT(1) SG_GS_DOT(2) SG_GS_DOT(4) SG_GS_DOT(8) SG_GS_DOT(16) SG_GS_DOT(32) SG_GS_DOT(64) {}
 #undef SG_GS_DOT
@@ -1176,8 +1173,10 @@ void launch_gs_dot(hipStream_t s, const double* V, int64_t ldv, int nv, const do
 }
 
 void launch_gs_update_dot(hipStream_t s, const double* V, int64_t ldv, int nv, const double* h,
-                          double* w, int64_t N, double sign, double* partial, double* out) {
+                          double* w, int64_t N, double sign, double* partial, double* out,
+                          const EdgeFix& ef) {
   if (nv > 64) {
+    if (ef.edge) launch_apply_fixup(s, 4 * ef.nt, (int)(N / ef.Nh), ef.sgn, ef.edge, w, ef.Nh);
     launch_update(s, V, ldv, nv, h, w, N, sign);
     launch_gs_dot(s, V, ldv, nv, w, N, partial, out);
     return;
@@ -1187,7 +1186,7 @@ void launch_gs_update_dot(hipStream_t s, const double* V, int64_t ldv, int nv, c
 #define SG_GS_UD(B)                                                                          \
   if (nv <= B) {                                                                             \
     hipLaunchKernelGGL(gs_update_dot_kernel<B>, grid, block, 0, s, V, ldv, nv, h, w, N, sign, \
-                       partial, nblk);                                                       \
+                       partial, nblk, ef);                                                   \
   } else
   SG_GS_UD(1) SG_GS_UD(2) SG_GS_UD(4) SG_GS_UD(8) SG_GS_UD(16) SG_GS_UD(32) SG_GS_UD(64) {}
 #undef SG_GS_UD
@@ -1291,7 +1290,8 @@ __device__ __forceinline__ void vdown_tile(VDownLds& L, int tile, int mode,
                                            int64_t Nc, const int* smode, const int* bmap,
                                            const double* __restrict__ bglob,
                                            double* __restrict__ x2out,
-                                           double* __restrict__ bcout, double omega) {
+                                           double* __restrict__ bcout, double omega,
+                                           const EdgeFix& ef = EdgeFix{}) {
   double* sb = L.sb;
   double* sd = L.sd;
   double* sx1 = L.sx1;
@@ -1318,6 +1318,7 @@ __device__ __forceinline__ void vdown_tile(VDownLds& L, int tile, int mode,
     const bool in = e < kDE * kDE && inside(fx, fy);
     gp[p] = in ? gidx(fx, fy) : -1;
     bv[p] = in ? b[gp[p]] : 0.0;
+    if (in && ef.edge) bv[p] = edge_fixed(bv[p], ef, mode, fx, fy);
 #pragma unroll
     for (int t = 0; t < 9; ++t) sv[p][t] = in ? S[t * Nf + gp[p]] : (t == 4 ? 1.0 : 0.0);
   }
@@ -1383,10 +1384,11 @@ __global__ __launch_bounds__(256) void vdown_kernel(const double* __restrict__ S
                                                     const int* bmap,
                                                     const double* __restrict__ bglob,
                                                     double* __restrict__ x2out,
-                                                    double* __restrict__ bcout, double omega) {
+                                                    double* __restrict__ bcout, double omega,
+                                                    EdgeFix ef) {
   __shared__ VDownLds L;
   vdown_tile(L, blockIdx.x, blockIdx.y, Sbase, nf, Nf, Nc, smode, bmap, bglob, x2out, bcout,
-             omega);
+             omega, ef);
 }
 
 struct VUpLds {
@@ -1401,7 +1403,7 @@ __device__ __forceinline__ void vup_tile(VUpLds& L, int tile, int mode,
                                          const double* __restrict__ x2glob,
                                          const double* __restrict__ xcglob,
                                          double* __restrict__ xout, double omega,
-                                         int64_t xcslab = 0) {
+                                         int64_t xcslab = 0, const EdgeFix& ef = EdgeFix{}) {
   double* sb = L.sb;
   double* sd = L.sd;
   double* sx3 = L.sx3;
@@ -1442,6 +1444,7 @@ __device__ __forceinline__ void vup_tile(VUpLds& L, int tile, int mode,
     const bool in = e < kUE * kUE && inside(fx, fy);
     gp[p] = in ? gidx(fx, fy) : -1;
     bv[p] = in ? b[gp[p]] : 0.0;
+    if (in && ef.edge) bv[p] = edge_fixed(bv[p], ef, mode, fx, fy);
     xv[p] = in ? x2[gp[p]] : 0.0;
 #pragma unroll
     for (int t = 0; t < 9; ++t) sv[p][t] = in ? S[t * Nf + gp[p]] : (t == 4 ? 1.0 : 0.0);
@@ -1507,30 +1510,31 @@ __global__ __launch_bounds__(256) void vup_kernel(const double* __restrict__ Sba
                                                   const double* __restrict__ x2glob,
                                                   const double* __restrict__ xcglob,
                                                   double* __restrict__ xout, double omega,
-                                                  int64_t xcslab) {
+                                                  int64_t xcslab, EdgeFix ef) {
   __shared__ VUpLds L;
   vup_tile(L, blockIdx.x, blockIdx.y, Sbase, nf, Nf, Nc, smode, bmap, xmap, bglob, x2glob, xcglob,
-           xout, omega, xcslab);
+           xout, omega, xcslab, ef);
 }
 
 // bmap / xmap (device, may be null): mode t reads b from vector bmap[t] and
 // writes x to vector xmap[t] of the full-length arrays (the field split's
 // gather and scatter folded into the finest level)
 void launch_vdown(hipStream_t s, const Level& Lf, const Level& Lc, int modes, const int* smode,
-                  const double* b, double* x2, double* bc, double omega, const int* bmap) {
+                  const double* b, double* x2, double* bc, double omega, const int* bmap,
+                  const EdgeFix& ef) {
   const int tpr = (Lf.n / 2 + kTC - 1) / kTC;
   hipLaunchKernelGGL(vdown_kernel, dim3(tpr * tpr, modes), dim3(256), 0, s, Lf.S, Lf.n, Lf.N, Lc.N,
-                     smode, bmap, b, x2, bc, omega);
+                     smode, bmap, b, x2, bc, omega, ef);
 }
 
 void launch_vup(hipStream_t s, const Level& Lf, const Level& Lc, int modes, const int* smode,
                 const double* b, const double* x2, const double* xc, double* x, double omega,
-                const int* bmap, const int* xmap, int xc_slices) {
+                const int* bmap, const int* xmap, int xc_slices, const EdgeFix& ef) {
   if (xc_slices != 1 && xc_slices != kDenseSlices) throw Error(SG_ERR_INTERNAL, "vup: slices");
   const int tpr = (Lf.n / 2 + kTC - 1) / kTC;
   const int64_t xcslab = xc_slices == 1 ? 0 : (int64_t)modes * Lc.N;
   hipLaunchKernelGGL(vup_kernel, dim3(tpr * tpr, modes), dim3(256), 0, s, Lf.S, Lf.n, Lf.N, Lc.N,
-                     smode, bmap, xmap, b, x2, xc, x, omega, xcslab);
+                     smode, bmap, xmap, b, x2, xc, x, omega, xcslab, ef);
 }
 
 // ---- coarse levels in LDS, one workgroup per mode --------------------------

@@ -406,7 +406,7 @@ bool rapply_matches(int M, int p, const std::vector<std::vector<int>>& Jp) {
 
 void launch_rapply(hipStream_t s, int M, int p, int n, double mu, double a_min, const double* g,
                    const RApplyRows& rr, const double* U, int64_t Nh, const double* rin,
-                   double beta, double sgn, double* out, double* edge) {
+                   double beta, double sgn, double* out, double* edge, bool fixup) {
   const int nt = n / kTileE, ntiles = nt * nt;
   const int P = (int)rc_binom(M + p, p);
   if (rr.nrows < 1 || rr.nrows > P) throw Error(SG_ERR_INTERNAL, "register apply: bad rows");
@@ -418,7 +418,7 @@ void launch_rapply(hipStream_t s, int M, int p, int n, double mu, double a_min, 
   } else
   SG_RAPPLY_LIST(SG_RAPPLY_LAUNCH) { throw Error(SG_ERR_INTERNAL, "register apply: (M, p)"); }
 #undef SG_RAPPLY_LAUNCH
-  launch_apply_fixup(s, n, rr.nrows, sgn, edge, out, Nh);
+  if (fixup) launch_apply_fixup(s, n, rr.nrows, sgn, edge, out, Nh);
 }
 
 void launch_brapply(hipStream_t s, int M, int p, size_t lds, const BInst* I, const BState* st,
