@@ -29,13 +29,15 @@ sys.path.insert(0, ROOT)
 METRIC = "GMRES time-to-relres-1e-8 (s) + SG apply HBM GB/s; learned-FGMRES vs field-split"
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per apply dispatch (register-resident factored kernel plus fixup) on the
-# 128x128 workload from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE on
-# rapply_kernel<4,3>), scaled by the same counters read on a plain 256 MiB copy
-# (factors 2.0 and 1.0).  Valid only for the kernel source the counters were taken
-# on: the sha256 of sg_rapply.hip + sg_internal.h is compared at run time.
-APPLY_TRAFFIC = {"src_sha256": "533dc22eb53d33bc768f4d2a8db07240273c034c106834c545777a565bd8619e",
-                 "fetch_bytes": 3613.5625 * 1024 * 2.0, "write_bytes": 6937.0 * 1024 * 1.0}
+# HBM bytes of one whole apply (the register-resident factored kernel
+# rapply_kernel<4,3,true> plus apply_fixup_kernel) on the 128x128 workload from
+# two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each
+# scaled by the same counter read on a plain 256 MiB copy (factors 2.0 and 1.0).
+# Valid only for the kernel source the counters were taken on: the sha256 of
+# sg_rapply.hip + sg_internal.h is compared at run time.
+APPLY_TRAFFIC = {"src_sha256": "924a6feae7a9007f07922a9827bde9e6045a9749abb31cdcd7279f9d62590af9",
+                 "fetch_bytes": (3501.5625 + 4831.625) * 1024 * 2.0,
+                 "write_bytes": (6937.0 + 4377.4375) * 1024 * 1.0}
 
 
 def apply_traffic():
@@ -61,8 +63,8 @@ def _args():
     ap.add_argument("--cpu-iters", type=int, default=24)
     ap.add_argument("--no-c2-apply", action="store_true",
                     help="skip the HBM-bound apply measurement on the 256x256, 924-mode shape")
-    ap.add_argument("--sigma-sweep", action="store_true",
-                    help="also solve the 256x256, P=84 sigma sweep (0.5, 1.0, 1.5) with the "
+    ap.add_argument("--no-sigma-sweep", action="store_true",
+                    help="skip the 256x256, P=84 sigma sweep (0.5, 1.0, 1.5) with the "
                          "mean-based and field-split preconditioners")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-stage comparison (learned workload, reduced training)")
@@ -105,6 +107,33 @@ def time_applies(inst, reps, stream, seed=11505):
     return ms
 
 
+FP64_PEAK_TFLOPS = 78.6
+
+
+def chaos_pairs(M, p):
+    """nnz(T): the (gamma <= alpha) pairs over J(M, p), sum over alpha of prod (alpha_n + 1)."""
+    def rec(n, left):
+        if n == 0:
+            return [[]]
+        return [[a] + rest for a in range(left + 1) for rest in rec(n - 1, left - a)]
+    tot = 0
+    for alpha in rec(M, p):
+        prod = 1
+        for a in alpha:
+            prod *= a + 1
+        tot += prod
+    return tot
+
+
+def apply_flops(inst):
+    """FP64 flops of one factored apply of the whole operator, per Gauss point and
+    gradient component: 2 nnz(T) in each of the two contraction steps (one FMA per
+    pair), 6P for the scaled gradients, P for the step-1 scaling, 4P for the flux
+    scale and the a_min term, 7P for the four corner products and their reduction."""
+    Nq = 4 * inst.prob.n * inst.prob.n
+    return float(Nq * 2 * (4 * chaos_pairs(inst.prob.M, inst.prob.p) + 18 * inst.P))
+
+
 def apply_bytes(inst, form):
     Nq = 4 * inst.prob.n * inst.prob.n
     per_point = inst.na if form == "triple" else inst.prob.M
@@ -120,6 +149,10 @@ def measure_apply_forms(inst, reps, stream):
         nb = apply_bytes(inst, form)
         out[form] = {"ms": ms, "algorithmic_bytes": nb, "gbs": nb / (ms * 1e-3) / 1e9,
                      "frac_hbm_peak": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        if form == "factored":
+            fl = apply_flops(inst)
+            out[form].update({"fp64_flops": fl, "tflops": fl / (ms * 1e-3) / 1e12,
+                              "frac_fp64_peak": fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS})
     inst.set_apply("auto")
     return out
 
@@ -174,7 +207,9 @@ def sigma_sweep(stream, max_it=2000):
         inst = sg.SGInstance(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma, p.corr_len, p.a_min,
                              f_nodal=f)
         F = inst.rhs()
-        row = {"sigma": sigma}
+        ms_apply = time_applies(inst, 10, stream)
+        nb = apply_bytes(inst, "factored")
+        row = {"sigma": sigma, "apply_ms": ms_apply, "apply_gbs": nb / (ms_apply * 1e-3) / 1e9}
         for pc in ("mean", "fs"):
             u = inst.vec()
             inst.solve(F, pc=pc, grouping="klvar", restart=50, tol=1e-8, u=u, max_it=50)
@@ -327,7 +362,7 @@ def main():
         for f in ("factored", "triple"):
             _log(f"256x256 apply ({f}) {c2_apply[f]['ms']:.3f} ms, {c2_apply[f]['gbs']:.0f} GB/s")
 
-    sweep = sigma_sweep(stream) if args.sigma_sweep else None
+    sweep = None if args.no_sigma_sweep else sigma_sweep(stream)
     learned = None
     if not args.no_learned:
         torch.cuda.empty_cache()

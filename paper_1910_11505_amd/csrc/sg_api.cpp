@@ -1543,8 +1543,13 @@ size_t batch_layout(sg_batch& B, char* base) {
 
 // Builds the descriptors, work-item tables and launch sequences for one
 // preconditioner (mean-based, or field split with a grouping).
-Plan build_plan(sg_batch& B, int pc_kind, int grouping, const double* F, double* u) {
+// live (may be null): instances whose work items the plan holds; the others'
+// descriptors stay (items name instances by index) but none of their work is
+// launched, which is what their device gates would skip anyway
+Plan build_plan(sg_batch& B, int pc_kind, int grouping, const double* F, double* u,
+                const std::vector<char>* live = nullptr) {
   Plan pl;
+  auto skip = [&](int i) { return live && !(*live)[i]; };
   const int m = B.restart;
   int maxS = 0, maxfine = 0;
   pl.inst.resize(B.count);
@@ -1626,6 +1631,7 @@ Plan build_plan(sg_batch& B, int pc_kind, int grouping, const double* F, double*
   };
   std::vector<BItem> tvec, tdot;
   for (int i = 0; i < B.count; ++i) {
+    if (skip(i)) continue;
     const BInst& I = pl.inst[i];
     for (int c = 0; c < cdivi(I.Nv, kVecChunk); ++c) tvec.push_back({i, c});
     for (int b = 0; b < I.nblk; ++b) tdot.push_back({i, b});
@@ -1639,7 +1645,7 @@ Plan build_plan(sg_batch& B, int pc_kind, int grouping, const double* F, double*
     std::vector<BItem> tfix;
     for (int i = 0; i < B.count; ++i) {
       const BInst& I = pl.inst[i];
-      if (rowset > 0 && rowset >= I.nsplit) continue;
+      if (skip(i) || (rowset > 0 && rowset >= I.nsplit)) continue;
       const RowSetDev& rs = rowset == 0 ? I.full : I.part[rowset];
       std::pair<int, int> key;
       size_t lds;
@@ -1696,7 +1702,7 @@ Plan build_plan(sg_batch& B, int pc_kind, int grouping, const double* F, double*
       std::vector<std::vector<BItem>> tdepth(maxfine);
       for (int i = 0; i < B.count; ++i) {
         const BInst& I = pl.inst[i];
-        if (s >= I.nsplit) continue;
+        if (skip(i) || s >= I.nsplit) continue;
         const int ms = I.split_m[s];
         for (int c = 0; c < cdivi((int64_t)ms * I.Nh, kVecChunk); ++c) tsplit.push_back({i, c});
         for (int md = 0; md < ms; ++md) tcoarse.push_back({i, md});
@@ -2116,12 +2122,26 @@ int sg_batch_solve(sg_batch* b, const sg_solve_opts* o, const double* F, double*
     }
     run_recs(B, s, pl.start, o->tol);
     check_launch();
+    // Once a quarter of the instances still running at the last (re)build
+    // have finished, the step and restart are rebuilt over the remaining ones
+    // (items uploaded, graphs captured again), so the persistent kernels stop
+    // walking the work of finished instances.  The full plan stays cached for
+    // the next solve, which uploads its items again.
+    Plan* cur = &pl;
+    std::unique_ptr<Plan> compact;
+    auto drop_compact = [&]() {
+      if (!compact) return;
+      if (compact->gstep) (void)hipGraphExecDestroy(compact->gstep);
+      if (compact->grestart) (void)hipGraphExecDestroy(compact->grestart);
+      compact.reset();
+    };
+    int live_at_build = B.count;
     const int m = B.restart;
     const int max_cycles = o->max_it + 1;
     for (int cycle = 0; cycle < max_cycles; ++cycle) {
       for (int j = 0; j < m; ++j) {
-        if (graphs) SG_HIP(hipGraphLaunch(pl.gstep, s));
-        else run_recs(B, s, pl.step, o->tol);
+        if (graphs) SG_HIP(hipGraphLaunch(cur->gstep, s));
+        else run_recs(B, s, cur->step, o->tol);
         if ((j + 1) % 10 == 0 && j + 1 < m) {
           SG_HIP(hipMemcpyAsync(B.hS, B.dS, sizeof(BState) * B.count, hipMemcpyDeviceToHost, s));
           SG_HIP(hipStreamSynchronize(s));
@@ -2130,15 +2150,29 @@ int sg_batch_solve(sg_batch* b, const sg_solve_opts* o, const double* F, double*
           if (!any) break;
         }
       }
-      if (graphs) SG_HIP(hipGraphLaunch(pl.grestart, s));
-      else run_recs(B, s, pl.restart, o->tol);
+      if (graphs) SG_HIP(hipGraphLaunch(cur->grestart, s));
+      else run_recs(B, s, cur->restart, o->tol);
       SG_HIP(hipMemcpyAsync(B.hS, B.dS, sizeof(BState) * B.count, hipMemcpyDeviceToHost, s));
       SG_HIP(hipStreamSynchronize(s));
       check_launch();
-      bool all = true;
-      for (int i = 0; i < B.count; ++i) all = all && B.hS[i].done;
-      if (all) break;
+      std::vector<char> live(B.count);
+      int nlive = 0;
+      for (int i = 0; i < B.count; ++i) nlive += (live[i] = !B.hS[i].done);
+      if (nlive == 0) break;
+      if (graphs && 4 * nlive <= 3 * live_at_build) {
+        std::unique_ptr<Plan> next(new Plan(build_plan(B, kind, o->grouping, F, u, &live)));
+        SG_HIP(hipMemcpyAsync(B.dItems, next->items.data(), next->items.size() * sizeof(BItem),
+                              hipMemcpyHostToDevice, s));
+        SG_HIP(hipStreamSynchronize(s));
+        next->gstep = capture(B, s, next->step, o->tol);
+        next->grestart = capture(B, s, next->restart, o->tol);
+        drop_compact();
+        compact = std::move(next);
+        cur = compact.get();
+        live_at_build = nlive;
+      }
     }
+    drop_compact();
     for (int i = 0; i < B.count; ++i) {
       const BState& st = B.hS[i];
       sg_solve_info& inf = infos[i];

@@ -182,14 +182,16 @@ inline int r_cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 template <int K>
 __device__ __forceinline__ double quad_xor(double v) {
   constexpr int ctrl = K == 1 ? 0xB1 : 0x4E;  // quad_perm [1,0,3,2] / [2,3,0,1]
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 
 constexpr int kRThreads = 128;  // two wavefronts per tile
 
-template <int M, int p>
+// FULL: every mode is a row and a column, in order (the whole operator); the
+// masks and slot tables are then compile-time constants.
+template <int M, int p, bool FULL = false>
 __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, double mu,
                                             double a_min, const double* __restrict__ g,
                                             const RApplyRows& rr, const double* __restrict__ U,
@@ -198,7 +200,8 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
                                             double* __restrict__ edge) {
   constexpr const RTab<M, p>& T = RTabHolder<M, p>::v;
   constexpr int P = RTab<M, p>::P;
-  const int nrows = rr.nrows;
+  constexpr uint64_t kAll = P >= 64 ? ~0ull : ((1ull << P) - 1);
+  const int nrows = FULL ? P : rr.nrows;
   double* sN = smem;  // [P][25] nodal values (steps 1-2)
   double* sC = smem;  // [2][nrows][64] corner contributions (steps 4-5)
   const int nt = n / kTileE, ntiles = nt * nt;
@@ -208,7 +211,9 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
   const int comp = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int m = n - 1;
   const int64_t Nq = (int64_t)4 * n * n;
-  const uint64_t colmask = rr.colmask, rowmask = rr.rowmask;
+  // (the column and gamma masks stay run-time values: known, the unrolled
+  // gradient and step-1 code is scheduled with more values live than fit)
+  const uint64_t colmask = rr.colmask, rowmask = FULL ? kAll : rr.rowmask;
 
   // 1. nodal values of the column modes (all loads in flight at once)
   constexpr int NL = (P * 25 + kRThreads - 1) / kRThreads;
@@ -272,6 +277,8 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
     for (int t = T.p1[gm]; t < T.p1[gm + 1]; ++t) sx = fma(mono[T.d1[t]], G[T.a1[t]], sx);
     G[gm] = sx * T.is2[gm];
   }
+  // keep the scheduler from interleaving the phases (register pressure)
+  __builtin_amdgcn_sched_barrier(0);
 
   // 4. step 2 and the corner contributions of every output row.  Slot k of a
   // lane holds the contribution to corner ql ^ k of its element, so the
@@ -295,7 +302,8 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
     if ((colmask >> b) & 1) f = fma(a_min, Gc[b], f);
     const double k0 = gp[0] * f + quad_xor<2>(gp[2] * f);
     const double k1 = gp[1] * f + quad_xor<2>(gp[3] * f);
-    sCc[rr.slot[b] * 64 + lane] = k0 + quad_xor<1>(k1);
+    sCc[(FULL ? b : rr.slot[b]) * 64 + lane] = k0 + quad_xor<1>(k1);
+    __builtin_amdgcn_sched_barrier(0);
   }
   __syncthreads();
 
@@ -328,7 +336,7 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
       if (gx >= 1 && gy >= 1) {
         const int64_t node = (int64_t)(gy - 1) * m + (gx - 1);
         double base = 0.0;
-        if (beta != 0.0) base = beta * rin[(int64_t)rr.mode[slot] * Nh + node];
+        if (beta != 0.0) base = beta * rin[(int64_t)(FULL ? slot : rr.mode[slot]) * Nh + node];
         out[(int64_t)slot * Nh + node] = base + sgn * sum;
       }
     } else {
@@ -338,7 +346,7 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
   }
 }
 
-template <int M, int p>
+template <int M, int p, bool FULL>
 __global__ __launch_bounds__(kRThreads, 2) void rapply_kernel(int n, double mu, double a_min,
                                                     const double* __restrict__ g, RApplyRows rr,
                                                     const double* __restrict__ U, int64_t Nh,
@@ -347,8 +355,8 @@ __global__ __launch_bounds__(kRThreads, 2) void rapply_kernel(int n, double mu, 
                                                     double* __restrict__ edge) {
   extern __shared__ double smem[];
   const int nt = n / kTileE;
-  rapply_tile<M, p>(smem, xcd_tile(blockIdx.x, nt * nt), n, mu, a_min, g, rr, U, Nh, rin, beta,
-                    sgn, out, edge);
+  rapply_tile<M, p, FULL>(smem, xcd_tile(blockIdx.x, nt * nt), n, mu, a_min, g, rr, U, Nh, rin,
+                          beta, sgn, out, edge);
 }
 
 // (instance, tile) items of instances sharing one (M, p)
@@ -411,10 +419,17 @@ void launch_rapply(hipStream_t s, int M, int p, int n, double mu, double a_min, 
   const int P = (int)rc_binom(M + p, p);
   if (rr.nrows < 1 || rr.nrows > P) throw Error(SG_ERR_INTERNAL, "register apply: bad rows");
   const size_t lds = rapply_lds_bytes(P, rr.nrows);
-#define SG_RAPPLY_LAUNCH(MM, PP)                                                               \
-  if (M == MM && p == PP) {                                                                    \
-    hipLaunchKernelGGL((rapply_kernel<MM, PP>), dim3(ntiles), dim3(kRThreads), lds, s, n, mu, a_min, \
-                       g, rr, U, Nh, rin, beta, sgn, out, edge);                               \
+  const uint64_t all = P >= 64 ? ~0ull : ((1ull << P) - 1);
+  bool full = rr.nrows == P && rr.colmask == all && rr.rowmask == all && rr.gammask == all;
+  for (int b = 0; full && b < P; ++b) full = rr.slot[b] == b && rr.mode[b] == b;
+#define SG_RAPPLY_LAUNCH(MM, PP)                                                              \
+  if (M == MM && p == PP) {                                                                   \
+    if (full)                                                                                 \
+      hipLaunchKernelGGL((rapply_kernel<MM, PP, true>), dim3(ntiles), dim3(kRThreads), lds, s, \
+                         n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);              \
+    else                                                                                      \
+      hipLaunchKernelGGL((rapply_kernel<MM, PP, false>), dim3(ntiles), dim3(kRThreads), lds,  \
+                         s, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);           \
   } else
   SG_RAPPLY_LIST(SG_RAPPLY_LAUNCH) { throw Error(SG_ERR_INTERNAL, "register apply: (M, p)"); }
 #undef SG_RAPPLY_LAUNCH

@@ -1,7 +1,9 @@
 """Batched solves: many uneven instances advanced together by the persistent
 kernels under HIP-graph capture must reproduce the single-instance solver
-(same algorithm, same reduction trees: iteration counts equal, solutions to
-1e-12) and meet the FP64 true relative residual 1e-8 checked by the oracle."""
+(same algorithm, with dot-product trees of their own: iteration counts equal,
+solutions to 1e-12) and meet the FP64 true relative residual 1e-8 checked by
+the oracle.  Instances finish at different restarts, so the solves also run
+on the plans rebuilt over the instances still running."""
 import numpy as np
 import pytest
 
