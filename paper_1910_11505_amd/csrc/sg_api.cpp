@@ -1663,7 +1663,11 @@ Plan build_plan(sg_batch& B, int pc_kind, int grouping, const double* F, double*
       }
       auto& cl = classes[key];
       const int nt = I.n / kTileE;
-      for (int t = 0; t < nt * nt; ++t) cl.first.push_back({i, t});
+      // XCD-aware order: a persistent workgroup's items keep its XCD (grid and
+      // per-instance tile counts are multiples of 8 at the workload sizes), so
+      // each XCD walks a contiguous band of tiles and their shared halo lines
+      // stay in one L2
+      for (int t = 0; t < nt * nt; ++t) cl.first.push_back({i, xcd_tile(t, nt * nt)});
       cl.second = std::max(cl.second, lds);
       const int64_t fixn = (int64_t)rs.nrows * nt * nt * 7;
       for (int c = 0; c < cdivi(fixn, kVecChunk); ++c) tfix.push_back({i, c});

@@ -304,18 +304,28 @@ __device__ inline bool gated(const BState& S, int gate) {
   return gate == 0 ? (S.active == 0) : (S.done != 0);
 }
 
+// A pointer into device memory read from a descriptor table.  Such pointers
+// are generic, so the compiler would access them with flat instructions, whose
+// waits also cover LDS traffic; obtained this way (an integer to a
+// global-address-space pointer, which no cast round trip folds away) the
+// accesses through it are global loads and stores.
+template <class T>
+__device__ __forceinline__ T* gptr(T* p) {
+  return (T*)(__attribute__((address_space(1))) T*)(uintptr_t)p;
+}
+
 __device__ inline double* bbuf(const BInst& I, const BState& S, int id) {
   switch (id) {
-    case BUF_F: return const_cast<double*>(I.F);
-    case BUF_U: return I.u;
-    case BUF_VJ: return I.V + (int64_t)S.j * I.Nv;
-    case BUF_VJ1: return I.V + (int64_t)(S.j + 1) * I.Nv;
-    case BUF_V0: return I.V;
-    case BUF_W: return I.w;
-    case BUF_Z: return I.z;
-    case BUF_T: return I.t;
-    case BUF_FST: return I.fsT;
-    default: return I.fsX;
+    case BUF_F: return gptr(const_cast<double*>(I.F));
+    case BUF_U: return gptr(I.u);
+    case BUF_VJ: return gptr(I.V + (int64_t)S.j * I.Nv);
+    case BUF_VJ1: return gptr(I.V + (int64_t)(S.j + 1) * I.Nv);
+    case BUF_V0: return gptr(I.V);
+    case BUF_W: return gptr(I.w);
+    case BUF_Z: return gptr(I.z);
+    case BUF_T: return gptr(I.t);
+    case BUF_FST: return gptr(I.fsT);
+    default: return gptr(I.fsX);
   }
 }
 

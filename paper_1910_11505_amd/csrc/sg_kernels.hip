@@ -1864,14 +1864,25 @@ __global__ __launch_bounds__(256) void bapply_kernel(const BInst* __restrict__ I
                                                      int rowset, int src, int rin, int dst,
                                                      double beta, double sgn, int gate) {
   extern __shared__ double smem[];
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  // one workgroup per item (grid = nitems)
+  {
+    const int it = blockIdx.x;
+    if (it >= nitems) return;
     const BItem w = items[it];
     const BInst& I = Is[w.inst];
     const BState& S = Ss[w.inst];
-    if (gated(S, gate)) continue;
-    const RowSetDev& rs = rowset == 0 ? I.full : I.part[rowset];
-    apply_tile<RMAX>(smem, w.local, I.n, I.na, I.a, rs, bbuf(I, S, src), I.Nh,
-                     rin >= 0 ? bbuf(I, S, rin) : nullptr, beta, sgn, bbuf(I, S, dst), I.edge);
+    if (gated(S, gate)) return;
+    // a copy, so the tile code reads the descriptor from registers, not memory
+    RowSetDev rs = rowset == 0 ? I.full : I.part[rowset];
+    rs.rows = gptr(rs.rows);
+    rs.cols = gptr(rs.cols);
+    rs.cpass = gptr(rs.cpass);
+    rs.wrows = gptr(rs.wrows);
+    rs.ptr = gptr(rs.ptr);
+    rs.ent = gptr(rs.ent);
+    apply_tile<RMAX>(smem, w.local, I.n, I.na, gptr(I.a), rs, bbuf(I, S, src), I.Nh,
+                     rin >= 0 ? bbuf(I, S, rin) : nullptr, beta, sgn, bbuf(I, S, dst),
+                     gptr(I.edge));
   }
 }
 
@@ -1879,8 +1890,9 @@ void launch_bapply(hipStream_t s, int rmax, size_t lds, const BInst* I, const BS
                    const BItem* items, int nitems, int rowset, int src, int rin, int dst,
                    double beta, double sgn, int gate) {
   if (nitems <= 0) return;
-  const int per_cu = std::max(1, (int)((160 * 1024) / std::max<size_t>(lds, 1)));
-  const int grid = std::min(nitems, 256 * std::min(per_cu, 4));
+  // one workgroup per item (the loop in the kernel is then a single pass): the
+  // hardware schedules the tiles exactly as in a single-instance launch
+  const int grid = nitems;
 #define SG_BAPPLY(R)                                                                       \
   case R:                                                                                  \
     hipLaunchKernelGGL(bapply_kernel<R>, dim3(grid), dim3(256), lds, s, I, st, items, nitems, \
@@ -1900,17 +1912,18 @@ __global__ __launch_bounds__(256) void bfapply_kernel(const BInst* __restrict__ 
                                                       const BItem* __restrict__ items, int nitems,
                                                       int rowset, int src, int rin, int dst,
                                                       double beta, double sgn, int gate) {
+  // one workgroup per item (grid = nitems)
   extern __shared__ double smem[];
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const BItem w = items[it];
-    const BInst& I = Is[w.inst];
-    const BState& S = Ss[w.inst];
-    if (gated(S, gate)) continue;
-    __syncthreads();  // the previous item is done with the LDS
-    const FRowSetDev& rs = rowset == 0 ? I.ffull : I.fpart[rowset];
-    fapply_tile<QB>(smem, w.local, I.n, I.mu, I.amin, I.gq, rs, rs.blob, bbuf(I, S, src), I.Nh,
-                    rin >= 0 ? bbuf(I, S, rin) : nullptr, beta, sgn, bbuf(I, S, dst), I.edge);
-  }
+  if ((int)blockIdx.x >= nitems) return;
+  const BItem w = items[blockIdx.x];
+  const BInst& I = Is[w.inst];
+  const BState& S = Ss[w.inst];
+  if (gated(S, gate)) return;
+  // a copy, so the tile code reads the descriptor from registers, not memory
+  const FRowSetDev rs = rowset == 0 ? I.ffull : I.fpart[rowset];
+  fapply_tile<QB>(smem, w.local, I.n, I.mu, I.amin, gptr(I.gq), rs, gptr(rs.blob),
+                  bbuf(I, S, src), I.Nh, rin >= 0 ? bbuf(I, S, rin) : nullptr, beta, sgn,
+                  bbuf(I, S, dst), gptr(I.edge));
 }
 
 void launch_bfapply(hipStream_t s, int qb, size_t lds, const BInst* I, const BState* st,
@@ -1918,8 +1931,9 @@ void launch_bfapply(hipStream_t s, int qb, size_t lds, const BInst* I, const BSt
                     double beta, double sgn, int gate) {
   if (nitems <= 0) return;
   if (lds > 160 * 1024) throw Error(SG_ERR_INTERNAL, "batched factored apply: LDS");
-  const int per_cu = std::max(1, (int)((160 * 1024) / std::max<size_t>(lds, 1)));
-  const int grid = std::min(nitems, 256 * std::min(per_cu, 4));
+  // one workgroup per item (the loop in the kernel is then a single pass): the
+  // hardware schedules the tiles exactly as in a single-instance launch
+  const int grid = nitems;
   switch (qb) {
 #define SG_BFAPPLY(Q)                                                                          \
   case Q:                                                                                      \
@@ -1936,24 +1950,27 @@ void launch_bfapply(hipStream_t s, int qb, size_t lds, const BInst* I, const BSt
 __global__ void bfixup_kernel(const BInst* __restrict__ Is, const BState* __restrict__ Ss,
                               const BItem* __restrict__ items, int nitems, int rowset, int dst,
                               double sgn, int gate) {
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  // one workgroup per item (grid = nitems)
+  {
+    const int it = blockIdx.x;
+    if (it >= nitems) return;
     const BItem w = items[it];
     const BInst& I = Is[w.inst];
     const BState& S = Ss[w.inst];
-    if (gated(S, gate)) continue;
+    if (gated(S, gate)) return;
     const RowSetDev& rs = rowset == 0 ? I.full : I.part[rowset];
     const int nt = I.n / kTileE;
     const int64_t total = (int64_t)rs.nrows * nt * nt * 7;
     const int64_t g0 = (int64_t)w.local * kVecChunk;
     for (int64_t g = g0 + threadIdx.x; g < std::min<int64_t>(total, g0 + kVecChunk); g += blockDim.x)
-      apply_fixup_item(g, I.n, sgn, I.edge, bbuf(I, S, dst), I.Nh);
+      apply_fixup_item(g, I.n, sgn, gptr(I.edge), bbuf(I, S, dst), I.Nh);
   }
 }
 
 void launch_bfixup(hipStream_t s, const BInst* I, const BState* st, const BItem* items, int nitems,
                    int rowset, int dst, double sgn, int gate) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(bfixup_kernel, dim3(std::min(nitems, 2048)), dim3(256), 0, s, I, st, items,
+  hipLaunchKernelGGL(bfixup_kernel, dim3(nitems), dim3(256), 0, s, I, st, items,
                      nitems, rowset, dst, sgn, gate);
 }
 
@@ -1963,17 +1980,19 @@ __global__ __launch_bounds__(256) void bvdown_kernel(const BInst* __restrict__ I
                                                      const BItem* __restrict__ items, int nitems,
                                                      int depth, int split, int gate) {
   __shared__ VDownLds L;
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  // one workgroup per item (grid = nitems)
+  {
+    const int it = blockIdx.x;
+    if (it >= nitems) return;
     const BItem w = items[it];
     const BInst& I = Is[w.inst];
-    if (gated(Ss[w.inst], gate)) continue;
+    if (gated(Ss[w.inst], gate)) return;
     const int m = I.split_m[split];
     const Level& Lf = I.L[depth];
     const Level& Lc = I.L[depth + 1];
-    const double* b = depth == 0 ? I.fsT : I.mg_b[depth];
-    vdown_tile(L, w.local / m, w.local % m, Lf.S, Lf.n, Lf.N, Lc.N, nullptr, nullptr, b,
-               I.mg_xa[depth],
-               I.mg_b[depth + 1], 8.0 / 9.0);
+    const double* b = gptr(depth == 0 ? I.fsT : I.mg_b[depth]);
+    vdown_tile(L, w.local / m, w.local % m, gptr(Lf.S), Lf.n, Lf.N, Lc.N, nullptr, nullptr, b,
+               gptr(I.mg_xa[depth]), gptr(I.mg_b[depth + 1]), 8.0 / 9.0);
   }
 }
 
@@ -1982,32 +2001,34 @@ __global__ __launch_bounds__(256) void bvup_kernel(const BInst* __restrict__ Is,
                                                    const BItem* __restrict__ items, int nitems,
                                                    int depth, int split, int gate) {
   __shared__ VUpLds L;
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  // one workgroup per item (grid = nitems)
+  {
+    const int it = blockIdx.x;
+    if (it >= nitems) return;
     const BItem w = items[it];
     const BInst& I = Is[w.inst];
-    if (gated(Ss[w.inst], gate)) continue;
+    if (gated(Ss[w.inst], gate)) return;
     const int m = I.split_m[split];
     const Level& Lf = I.L[depth];
     const Level& Lc = I.L[depth + 1];
-    const double* b = depth == 0 ? I.fsT : I.mg_b[depth];
-    double* x = depth == 0 ? I.fsX : I.mg_x[depth];
-    vup_tile(L, w.local / m, w.local % m, Lf.S, Lf.n, Lf.N, Lc.N, nullptr, nullptr, nullptr, b,
-             I.mg_xa[depth],
-             I.mg_x[depth + 1], x, 8.0 / 9.0);
+    const double* b = gptr(depth == 0 ? I.fsT : I.mg_b[depth]);
+    double* x = gptr(depth == 0 ? I.fsX : I.mg_x[depth]);
+    vup_tile(L, w.local / m, w.local % m, gptr(Lf.S), Lf.n, Lf.N, Lc.N, nullptr, nullptr, nullptr,
+             b, gptr(I.mg_xa[depth]), gptr(I.mg_x[depth + 1]), x, 8.0 / 9.0);
   }
 }
 
 void launch_bvdown(hipStream_t s, const BInst* I, const BState* st, const BItem* items, int nitems,
                    int depth, int split, int gate) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(bvdown_kernel, dim3(std::min(nitems, 2048)), dim3(256), 0, s, I, st, items,
+  hipLaunchKernelGGL(bvdown_kernel, dim3(nitems), dim3(256), 0, s, I, st, items,
                      nitems, depth, split, gate);
 }
 
 void launch_bvup(hipStream_t s, const BInst* I, const BState* st, const BItem* items, int nitems,
                  int depth, int split, int gate) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(bvup_kernel, dim3(std::min(nitems, 2048)), dim3(256), 0, s, I, st, items,
+  hipLaunchKernelGGL(bvup_kernel, dim3(nitems), dim3(256), 0, s, I, st, items,
                      nitems, depth, split, gate);
 }
 
@@ -2017,10 +2038,13 @@ __global__ __launch_bounds__(256) void bvcoarse_kernel(const BInst* __restrict__
                                                        const BItem* __restrict__ items,
                                                        int nitems, int split, int gate) {
   extern __shared__ double lds[];
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  // one workgroup per item (grid = nitems)
+  {
+    const int it = blockIdx.x;
+    if (it >= nitems) return;
     const BItem w = items[it];
     const BInst& I = Is[w.inst];
-    if (gated(Ss[w.inst], gate)) continue;
+    if (gated(Ss[w.inst], gate)) return;
     CoarseLevels cl{};
     cl.nl = I.nlev - I.nfine;
 #pragma unroll
@@ -2028,10 +2052,10 @@ __global__ __launch_bounds__(256) void bvcoarse_kernel(const BInst* __restrict__
       if (l < cl.nl) {
         cl.n[l] = I.L[I.nfine + l].n;
         cl.N[l] = I.L[I.nfine + l].N;
-        cl.S[l] = I.L[I.nfine + l].S;
+        cl.S[l] = gptr(I.L[I.nfine + l].S);
       }
-    const double* b = I.nfine == 0 ? I.fsT : I.mg_b[I.nfine];
-    double* x = I.nfine == 0 ? I.fsX : I.mg_x[I.nfine];
+    const double* b = gptr(I.nfine == 0 ? I.fsT : I.mg_b[I.nfine]);
+    double* x = gptr(I.nfine == 0 ? I.fsX : I.mg_x[I.nfine]);
     vcoarse_mode(lds, w.local, cl, nullptr, b, x, 8.0 / 9.0);
   }
 }
@@ -2039,7 +2063,7 @@ __global__ __launch_bounds__(256) void bvcoarse_kernel(const BInst* __restrict__
 void launch_bvcoarse(hipStream_t s, size_t lds, const BInst* I, const BState* st,
                      const BItem* items, int nitems, int split, int gate) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(bvcoarse_kernel, dim3(std::min(nitems, 2048)), dim3(256), lds, s, I, st,
+  hipLaunchKernelGGL(bvcoarse_kernel, dim3(nitems), dim3(256), lds, s, I, st,
                      items, nitems, split, gate);
 }
 
@@ -2048,20 +2072,23 @@ void launch_bvcoarse(hipStream_t s, size_t lds, const BInst* I, const BState* st
 __global__ void bgather_kernel(const BInst* __restrict__ Is, const BState* __restrict__ Ss,
                                const BItem* __restrict__ items, int nitems, int split, int buf,
                                int scatter, int gate) {
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  // one workgroup per item (grid = nitems)
+  {
+    const int it = blockIdx.x;
+    if (it >= nitems) return;
     const BItem w = items[it];
     const BInst& I = Is[w.inst];
     const BState& S = Ss[w.inst];
-    if (gated(S, gate)) continue;
+    if (gated(S, gate)) return;
     const int64_t total = (int64_t)I.split_m[split] * I.Nh;
-    const int* idx = I.split_idx[split];
+    const int* idx = gptr(I.split_idx[split]);
     double* full = bbuf(I, S, buf);
     const int64_t g0 = (int64_t)w.local * kVecChunk;
     for (int64_t g = g0 + threadIdx.x; g < std::min<int64_t>(total, g0 + kVecChunk); g += blockDim.x) {
       const int t = (int)(g / I.Nh);
       const int64_t f = (int64_t)idx[t] * I.Nh + (g - (int64_t)t * I.Nh);
-      if (scatter) full[f] = I.fsX[g];
-      else I.fsT[g] = full[f];
+      if (scatter) full[f] = gptr(I.fsX)[g];
+      else gptr(I.fsT)[g] = full[f];
     }
   }
 }
@@ -2069,7 +2096,7 @@ __global__ void bgather_kernel(const BInst* __restrict__ Is, const BState* __res
 void launch_bgather(hipStream_t s, const BInst* I, const BState* st, const BItem* items,
                     int nitems, int split, int buf, int scatter, int gate) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(bgather_kernel, dim3(std::min(nitems, 2048)), dim3(256), 0, s, I, st, items,
+  hipLaunchKernelGGL(bgather_kernel, dim3(nitems), dim3(256), 0, s, I, st, items,
                      nitems, split, buf, scatter, gate);
 }
 
@@ -2077,11 +2104,14 @@ void launch_bgather(hipStream_t s, const BInst* I, const BState* st, const BItem
 __global__ void bvec_kernel(const BInst* __restrict__ Is, const BState* __restrict__ Ss,
                             const BItem* __restrict__ items, int nitems, int op, int xb, int yb,
                             int ob, double a, double b, int gate) {
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  // one workgroup per item (grid = nitems)
+  {
+    const int it = blockIdx.x;
+    if (it >= nitems) return;
     const BItem w = items[it];
     const BInst& I = Is[w.inst];
     const BState& S = Ss[w.inst];
-    if (gated(S, gate)) continue;
+    if (gated(S, gate)) return;
     const int64_t g0 = (int64_t)w.local * kVecChunk;
     const int64_t g1 = std::min<int64_t>(I.Nv, g0 + kVecChunk);
     const int m = I.m;
@@ -2092,24 +2122,32 @@ __global__ void bvec_kernel(const BInst* __restrict__ Is, const BState* __restri
       for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x)
         o[g] = (b == 0.0) ? (a == 0.0 ? 0.0 : a * x[g]) : a * x[g] + b * y[g];
     } else if (op == BV_UPDATE1 || op == BV_UPDATE2) {
-      const double* h = I.hv + (op == BV_UPDATE1 ? 0 : m + 1);
+      const double* h = gptr(I.hv + (op == BV_UPDATE1 ? 0 : m + 1));
+      const double* V = gptr(I.V);
+      double* wv = gptr(I.w);
       for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
         double acc = 0.0;
-        for (int l = 0; l <= S.j; ++l) acc = fma(h[l], I.V[(int64_t)l * I.Nv + g], acc);
-        I.w[g] -= acc;
+        for (int l = 0; l <= S.j; ++l) acc = fma(h[l], V[(int64_t)l * I.Nv + g], acc);
+        wv[g] -= acc;
       }
     } else if (op == BV_SCALE_NEXT) {
-      const double nn = sqrt(I.hv[2 * m + 2]);
-      double* v = I.V + (int64_t)(S.j + 1) * I.Nv;
-      for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) v[g] = nn > 0.0 ? I.w[g] / nn : 0.0;
+      const double nn = sqrt(gptr(I.hv)[2 * m + 2]);
+      double* v = gptr(I.V + (int64_t)(S.j + 1) * I.Nv);
+      const double* wv = gptr(I.w);
+      for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) v[g] = nn > 0.0 ? wv[g] / nn : 0.0;
     } else if (op == BV_COMBINE) {
+      const double* y = gptr(I.y);
+      const double* V = gptr(I.V);
+      double* t = gptr(I.t);
       for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
         double acc = 0.0;
-        for (int l = 0; l < S.kdone; ++l) acc = fma(I.y[l], I.V[(int64_t)l * I.Nv + g], acc);
-        I.t[g] = acc;
+        for (int l = 0; l < S.kdone; ++l) acc = fma(y[l], V[(int64_t)l * I.Nv + g], acc);
+        t[g] = acc;
       }
     } else {  // BV_START: V_0 = t / beta
-      for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) I.V[g] = I.t[g] / S.beta;
+      double* V = gptr(I.V);
+      const double* t = gptr(I.t);
+      for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) V[g] = t[g] / S.beta;
     }
   }
 }
@@ -2117,34 +2155,57 @@ __global__ void bvec_kernel(const BInst* __restrict__ Is, const BState* __restri
 void launch_bvec(hipStream_t s, const BInst* I, const BState* st, const BItem* items, int nitems,
                  int op, int x, int y, int out, double a, double b, int gate) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(bvec_kernel, dim3(std::min(nitems, 2048)), dim3(256), 0, s, I, st, items,
+  hipLaunchKernelGGL(bvec_kernel, dim3(nitems), dim3(256), 0, s, I, st, items,
                      nitems, op, x, y, out, a, b, gate);
 }
 
 // dots: items (inst, block b < nblk); self_buf < 0: V_l . w for l <= j, else buf . buf
+// partial[l * nblk + b] = item b's slice of V_l . x (x = w, l <= j), or of x . x
+// for a named buffer.  The basis is taken 16 vectors at a time: for each
+// element of the slice the 16 loads are in flight together, and the 16 sums
+// are reduced once per chunk (wavefront butterfly, then the four wavefronts).
 __global__ __launch_bounds__(256) void bmultidot_kernel(const BInst* __restrict__ Is,
                                                         const BState* __restrict__ Ss,
                                                         const BItem* __restrict__ items,
                                                         int nitems, int self_buf, int gate) {
-  __shared__ double red[4];
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  constexpr int C = 16;
+  __shared__ double red[4 * 64];
+  // one workgroup per item (grid = nitems)
+  {
+    const int it = blockIdx.x;
+    if (it >= nitems) return;
     const BItem w = items[it];
     const BInst& I = Is[w.inst];
     const BState& S = Ss[w.inst];
-    if (gated(S, gate)) continue;
+    if (gated(S, gate)) return;
     const int nblk = I.nblk;
     const int64_t per = (I.Nv + nblk - 1) / nblk;
     const int64_t lo = (int64_t)w.local * per;
     const int64_t hi = std::min<int64_t>(I.Nv, lo + per);
-    const double* x = self_buf >= 0 ? bbuf(I, S, self_buf) : I.w;
+    const double* x = self_buf >= 0 ? bbuf(I, S, self_buf) : gptr(I.w);
+    const double* Vb = self_buf >= 0 ? x : gptr(I.V);
     const int nv = self_buf >= 0 ? 1 : S.j + 1;
-    for (int l = 0; l < nv; ++l) {
-      const double* v = self_buf >= 0 ? x : I.V + (int64_t)l * I.Nv;
-      double acc = 0.0;
-      for (int64_t i = lo + threadIdx.x; i < hi; i += 256) acc = fma(v[i], x[i], acc);
-      const double sm = block_sum(acc, red);
-      if (threadIdx.x == 0) I.partial[(int64_t)l * nblk + w.local] = sm;
+    for (int l0 = 0; l0 < nv; l0 += C) {
+      const int cnt = min(C, nv - l0);
+      double acc[C];
+#pragma unroll
+      for (int l = 0; l < C; ++l) acc[l] = 0.0;
+      for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+        const double xi = x[i];
+        double v[C];
+#pragma unroll
+        for (int l = 0; l < C; ++l) v[l] = l < cnt ? Vb[(int64_t)(l0 + l) * I.Nv + i] : 0.0;
+#pragma unroll
+        for (int l = 0; l < C; ++l) acc[l] = fma(v[l], xi, acc[l]);
+      }
+      wave_sums<C>(acc, red + 64 * (threadIdx.x >> 6));
       __syncthreads();
+      if (threadIdx.x < cnt) {
+        const int l = threadIdx.x;
+        gptr(I.partial)[(int64_t)(l0 + l) * nblk + w.local] =
+            (red[l] + red[64 + l]) + (red[128 + l] + red[192 + l]);
+      }
+      __syncthreads();  // red is reused
     }
   }
 }
@@ -2152,7 +2213,7 @@ __global__ __launch_bounds__(256) void bmultidot_kernel(const BInst* __restrict_
 void launch_bmultidot(hipStream_t s, const BInst* I, const BState* st, const BItem* items,
                       int nitems, int self_buf, int gate) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(bmultidot_kernel, dim3(std::min(nitems, 2048)), dim3(256), 0, s, I, st, items,
+  hipLaunchKernelGGL(bmultidot_kernel, dim3(nitems), dim3(256), 0, s, I, st, items,
                      nitems, self_buf, gate);
 }
 
@@ -2164,11 +2225,11 @@ __global__ void breduce_kernel(const BInst* __restrict__ Is, const BState* __res
   if (gated(S, gate)) return;
   const int m = I.m;
   const int nv = which == 2 ? 1 : S.j + 1;
-  double* out = I.hv + (which == 0 ? 0 : which == 1 ? m + 1 : 2 * m + 2);
+  double* out = gptr(I.hv + (which == 0 ? 0 : which == 1 ? m + 1 : 2 * m + 2));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int l = wave; l < nv; l += blockDim.x / 64) {
     double acc = 0.0;
-    for (int b = lane; b < I.nblk; b += 64) acc += I.partial[(int64_t)l * I.nblk + b];
+    for (int b = lane; b < I.nblk; b += 64) acc += gptr(I.partial)[(int64_t)l * I.nblk + b];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
     if (lane == 0) out[l] = acc;

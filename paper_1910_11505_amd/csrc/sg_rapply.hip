@@ -367,15 +367,19 @@ __global__ __launch_bounds__(kRThreads) void brapply_kernel(const BInst* __restr
                                                      int rowset, int src, int rin, int dst,
                                                      double beta, double sgn, int gate) {
   extern __shared__ double smem[];
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  // one workgroup per item (grid = nitems)
+  {
+    const int it = blockIdx.x;
+    if (it >= nitems) return;
     const BItem w = items[it];
     const BInst& I = Is[w.inst];
     const BState& S = Ss[w.inst];
-    if (gated(S, gate)) continue;
-    __syncthreads();  // the previous item is done with the LDS
-    const RApplyRows& rr = rowset == 0 ? I.rfull : I.rpart[rowset];
-    rapply_tile<M, p>(smem, w.local, I.n, I.mu, I.amin, I.gq, rr, bbuf(I, S, src), I.Nh,
-                      rin >= 0 ? bbuf(I, S, rin) : nullptr, beta, sgn, bbuf(I, S, dst), I.edge);
+    if (gated(S, gate)) return;
+    // a copy, so the tile code reads the descriptor from registers, not memory
+    const RApplyRows rr = rowset == 0 ? I.rfull : I.rpart[rowset];
+    rapply_tile<M, p>(smem, w.local, I.n, I.mu, I.amin, gptr(I.gq), rr, bbuf(I, S, src), I.Nh,
+                      rin >= 0 ? bbuf(I, S, rin) : nullptr, beta, sgn, bbuf(I, S, dst),
+                      gptr(I.edge));
   }
 }
 
@@ -440,7 +444,7 @@ void launch_brapply(hipStream_t s, int M, int p, size_t lds, const BInst* I, con
                     const BItem* items, int nitems, int rowset, int src, int rin, int dst,
                     double beta, double sgn, int gate) {
   if (nitems <= 0) return;
-  const int grid = std::min(nitems, 256 * 8);
+  const int grid = nitems;  // one workgroup per item, as in a single-instance launch
 #define SG_BRAPPLY_LAUNCH(MM, PP)                                                             \
   if (M == MM && p == PP) {                                                                   \
     hipLaunchKernelGGL((brapply_kernel<MM, PP>), dim3(grid), dim3(kRThreads), lds, s, I, st, items, \
