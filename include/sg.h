@@ -254,8 +254,8 @@ int    sg_attach_cnn(sg_handle* h, sg_cnn* c, double sigma);
 
 /* ---------------------------------------------------------------------------
  * Batched solves: many instances of uneven grid size, KL dimension, degree
- * and sigma solved together.  Persistent kernels walk device work-item tables
- * that cover every instance; per-instance Krylov state stays on the device,
+ * and sigma solved together.  Each step kernel is one launch over a device
+ * work-item table that covers every instance; per-instance Krylov state stays on the device,
  * so one Arnoldi step of all instances (and the restart step) is captured
  * once in a HIP graph and replayed.  Instances advance in lockstep; converged
  * instances are masked.  Not part of the paper.

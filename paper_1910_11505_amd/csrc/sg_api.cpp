@@ -1434,8 +1434,9 @@ void sg_destroy(sg_handle* h) { delete h; }
 
 // ===========================================================================
 // Batched solves: many instances of uneven size advanced in lockstep by
-// persistent kernels over device work-item tables; one Arnoldi step of every
-// instance and the restart step are each captured once in a HIP graph.
+// kernels over device work-item tables (one launch per step kernel covers every
+// instance); one Arnoldi step of every instance and the restart step are each
+// captured once in a HIP graph.
 // ===========================================================================
 #include <fstream>
 #include <map>
@@ -1637,7 +1638,7 @@ Plan build_plan(sg_batch& B, int pc_kind, int grouping, const double* F, double*
     for (int b = 0; b < I.nblk; ++b) tdot.push_back({i, b});
   }
   // operator launches for a row set (0 = full, s = partial of split s): one
-  // persistent launch per rows-per-wavefront class, then the edge fixup
+  // launch per rows-per-wavefront class, then the edge fixup
   auto apply_recs = [&](int rowset, int src, int rin, int dst, double beta, double sgn, int gate,
                         std::vector<LaunchRec>& out) {
     // class of an instance: (form, rows per wavefront | sub-batch size | M * 16 + p)
@@ -1663,10 +1664,9 @@ Plan build_plan(sg_batch& B, int pc_kind, int grouping, const double* F, double*
       }
       auto& cl = classes[key];
       const int nt = I.n / kTileE;
-      // XCD-aware order: a persistent workgroup's items keep its XCD (grid and
-      // per-instance tile counts are multiples of 8 at the workload sizes), so
-      // each XCD walks a contiguous band of tiles and their shared halo lines
-      // stay in one L2
+      // XCD-aware order: workgroup w runs on XCD w mod 8 and per-instance tile
+      // counts are multiples of 8 at the workload sizes, so each XCD walks a
+      // contiguous band of tiles and their shared halo lines stay in one L2
       for (int t = 0; t < nt * nt; ++t) cl.first.push_back({i, xcd_tile(t, nt * nt)});
       cl.second = std::max(cl.second, lds);
       const int64_t fixn = (int64_t)rs.nrows * nt * nt * 7;
@@ -2128,7 +2128,7 @@ int sg_batch_solve(sg_batch* b, const sg_solve_opts* o, const double* F, double*
     check_launch();
     // Once a quarter of the instances still running at the last (re)build
     // have finished, the step and restart are rebuilt over the remaining ones
-    // (items uploaded, graphs captured again), so the persistent kernels stop
+    // (items uploaded, graphs captured again), so the step kernels stop
     // walking the work of finished instances.  The full plan stays cached for
     // the next solve, which uploads its items again.
     Plan* cur = &pl;

@@ -295,7 +295,7 @@ struct BState {  // per-instance solver state, device-resident
   double beta, nF, est, target;
 };
 
-struct BItem {  // one work item of a persistent batched kernel
+struct BItem {  // one work item (one workgroup) of a batched kernel
   int inst, local;
 };
 
