@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # scaled by the same counter read on a plain 256 MiB copy (factors 2.0 and 1.0).
 # Valid only for the kernel source the counters were taken on: the sha256 of
 # sg_rapply.hip + sg_internal.h is compared at run time.
-APPLY_TRAFFIC = {"src_sha256": "924a6feae7a9007f07922a9827bde9e6045a9749abb31cdcd7279f9d62590af9",
+APPLY_TRAFFIC = {"src_sha256": "a62128bacc29807c3a03195a36dd58fa37a02f1031cec3bb9b3ae5f3f49a1380",
                  "fetch_bytes": (3501.5625 + 4831.625) * 1024 * 2.0,
                  "write_bytes": (6937.0 + 4377.4375) * 1024 * 1.0}
 
