@@ -22,6 +22,9 @@ SMALL = {
     "n8_m2p2q6": Problem(n=8, M=2, p=2, q=6, cov="sqexp", sigma=1.3, corr_len=0.4),
     # P = 210: only the small sub-batches fit in LDS
     "n8_m6p4": Problem(n=8, M=6, p=4, q=8, cov="exp_l1", sigma=0.7, corr_len=0.6),
+    # finest level above the dense coarse operator: the field split's blocks
+    # leave their edge sums to the cycle's first level
+    "n64_m3p2": Problem(n=64, M=3, p=2, q=4, cov="exp_l1", sigma=0.9, corr_len=0.4),
 }
 _cache = {}
 
@@ -73,6 +76,33 @@ def test_field_split_through_both_forms(name, grouping):
     G.set_apply("auto", 0)
     for form, z in out.items():
         assert relmax(z, ref) < 1e-12, form
+
+
+@pytest.mark.parametrize("form,qb", [("triple", 0), ("factored", 8), ("factored", 32),
+                                     ("factored", 0)])
+def test_deferred_edge_sums_every_form(form, qb):
+    """64x64: each off-diagonal block of the field split leaves its edge sums to
+    the V-cycle's finest level, and the Arnoldi apply to the Gram-Schmidt
+    passes; both through every apply form, against the oracle."""
+    from oracle.gmg import GMGHierarchy
+    from oracle.gmres import gmres
+    from oracle.precond import FieldSplit, make_groups
+    S, G = pair("n64_m3p2")
+    G.set_apply(form, qb)
+    try:
+        fs = FieldSplit(S, GMGHierarchy(S.A[0], S.n), make_groups(S.Jp, "klvar"))
+        r = random_vector(S.P * S.Nh, 205)
+        z = to_host(G.precond(to_dev(r), "fs", "klvar"))
+        assert relmax(z, fs.apply(r)) < 1e-12
+        K = S.assemble()
+        F = S.rhs()
+        xo, io = gmres(lambda v: K @ v, fs.apply, F, tol=1e-8, restart=50)
+        u, info, _ = G.solve(pc="fs", grouping="klvar", tol=1e-8, restart=50)
+        assert info.status == 0 and abs(info.iterations - io["iterations"]) <= 1
+        ug = to_host(u)
+        assert np.linalg.norm(ug - xo) <= 1e-10 * np.linalg.norm(xo)
+    finally:
+        G.set_apply("auto", 0)
 
 
 def test_factored_rejected_for_truncated_coefficient():
