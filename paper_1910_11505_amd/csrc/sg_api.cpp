@@ -666,7 +666,14 @@ void vcycle(sg_handle& H, hipStream_t s, int m, const int* smode, const double* 
   const int ld = H.ldense;
   auto bl = [&](int l) -> const double* { return l == 0 ? b : D.mg_b[l]; };
   auto xl = [&](int l) -> double* { return l == 0 ? x : D.mg_x[l]; };
-  for (int l = 0; l < ld; ++l)
+  // the two finest levels in one kernel each way when both are above the dense
+  // operator and the launches are small enough to be latency-bound
+  const bool two = ld >= 2 && H.n % 4 == 0 && two_level_pays(D.L[2], m);
+  const int lf = two ? 2 : 0;  // first level run by the one-level kernels
+  if (two)
+    launch_vdown2(s, D.L[0], D.L[1], D.L[2], m, b, D.mg_xa[0], D.mg_b[1], D.mg_xa[1], D.mg_b[2],
+                  kOmega, bmap, ef);
+  for (int l = lf; l < ld; ++l)
     launch_vdown(s, D.L[l], D.L[l + 1], m, nullptr, bl(l), D.mg_xa[l], D.mg_b[l + 1], kOmega,
                  l == 0 ? bmap : nullptr, l == 0 ? ef : EdgeFix{});
   // below the finest level the operator runs in kDenseSlices inner-index
@@ -674,10 +681,13 @@ void vcycle(sg_handle& H, hipStream_t s, int m, const int* smode, const double* 
   const int slices = ld == 0 ? 1 : kDenseSlices;
   launch_dense_coarse(s, (int)D.L[ld].N, m, D.Cd, bl(ld), xl(ld), ld == 0 ? bmap : nullptr,
                       ld == 0 ? xmap : nullptr, slices);
-  for (int l = ld - 1; l >= 0; --l)
+  for (int l = ld - 1; l >= lf; --l)
     launch_vup(s, D.L[l], D.L[l + 1], m, nullptr, bl(l), D.mg_xa[l], xl(l + 1), xl(l), kOmega,
                l == 0 ? bmap : nullptr, l == 0 ? xmap : nullptr, l == ld - 1 ? slices : 1,
                l == 0 ? ef : EdgeFix{});
+  if (two)
+    launch_vup2(s, D.L[0], D.L[1], D.L[2], m, b, D.mg_xa[0], D.mg_b[1], D.mg_xa[1], xl(2),
+                ld == 2 ? slices : 1, x, kOmega, bmap, xmap, ef);
 }
 
 // The edge sums an apply with sign sgn leaves pending in H.d.edge.

@@ -229,6 +229,21 @@ void launch_vup(hipStream_t s, const Level& Lf, const Level& Lc, int modes, cons
                 const double* b, const double* x2, const double* xc, double* x, double omega,
                 const int* bmap = nullptr, const int* xmap = nullptr, int xc_slices = 1,
                 const EdgeFix& ef = EdgeFix{});
+// Levels l and l+1 of the cycle in one kernel each way (mean stiffness,
+// L0.n a multiple of 4; L1, L2 the next two levels), used where
+// two_level_pays(L2, modes).  down writes level l's
+// pre-smoothed x2_0, level l+1's right-hand side b1 and pre-smoothed x2_1, and
+// level l+2's right-hand side b2; up reads those and level l+2's correction
+// (xc_slices partial results) and writes level l's corrected x.
+bool two_level_pays(const Level& L2, int modes);
+void launch_vdown2(hipStream_t s, const Level& L0, const Level& L1, const Level& L2, int modes,
+                   const double* b, double* x2_0, double* b1, double* x2_1, double* b2,
+                   double omega, const int* bmap = nullptr, const EdgeFix& ef = EdgeFix{});
+void launch_vup2(hipStream_t s, const Level& L0, const Level& L1, const Level& L2, int modes,
+                 const double* b, const double* x2_0, const double* b1, const double* x2_1,
+                 const double* xc2, int xc_slices, double* x, double omega,
+                 const int* bmap = nullptr, const int* xmap = nullptr,
+                 const EdgeFix& ef = EdgeFix{});
 void launch_vcoarse(hipStream_t s, const CoarseLevels& cl, int modes, const int* smode,
                     const double* b, double* x, double omega);
 size_t vcoarse_lds_bytes(const CoarseLevels& cl);

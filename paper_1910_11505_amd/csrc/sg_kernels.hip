@@ -1516,6 +1516,413 @@ __global__ __launch_bounds__(256) void vup_kernel(const double* __restrict__ Sba
            xout, omega, xcslab, ef);
 }
 
+// ---------------------------------------------------------------------------
+// Two fine levels of the V-cycle in one pass each way (levels l and l+1, the
+// mean stiffness).  A workgroup takes the T2 x T2 nodes of one level-(l+2)
+// tile and recomputes the halos it needs instead of reading them from a
+// neighbour, so every value it produces is the one the one-level kernels
+// produce (same formulas, same order):
+//   down: level l on (4 T2 + 15)^2 nodes (its (4 T2)^2 own nodes plus the halo
+//         whose residual restricts onto the (2 T2 + 5)^2 level-(l+1) nodes),
+//         then level l+1 as vdown_kernel does, writing level l's pre-smoothed
+//         x, level l+1's right-hand side and pre-smoothed x, and level l+2's
+//         right-hand side;
+//   up:   level l+1's prolong-add and post-smoothing on (2 T2 + 7)^2 nodes (own
+//         nodes plus the halo that level l interpolates from), then level l's
+//         on (4 T2 + 4)^2 nodes, writing level l's (4 T2)^2 own nodes.
+// ---------------------------------------------------------------------------
+template <int T2, int NT>
+struct V2Geom {
+  static constexpr int kT2 = T2;            // level-(l+2) nodes per tile side
+  static constexpr int kD1 = 2 * T2 + 5;    // level-(l+1) extent, down
+  static constexpr int kD0 = 2 * kD1 + 5;   // level-l extent, down
+  static constexpr int kU0 = 4 * T2 + 4;    // level-l extent, up
+  static constexpr int kU1 = 2 * T2 + 7;    // level-(l+1) extent, up
+  static constexpr int kU2 = T2 + 5;        // level-(l+2) extent, up
+  static constexpr int kV2Threads = NT;
+  static constexpr size_t down_lds() { return 8 * (5 * (size_t)kD0 * kD0 + 5 * (size_t)kD1 * kD1); }
+  static constexpr size_t up_lds() {
+    return 8 * (4 * (size_t)kU0 * kU0 + 5 * (size_t)kU1 * kU1 + (size_t)kU2 * kU2);
+  }
+};
+
+template <int T2, int NT>
+__global__ __launch_bounds__(NT) void vdown2_kernel(
+    const double* __restrict__ S0, const double* __restrict__ S1, int n0, int64_t N0, int64_t N1,
+    int64_t N2, const int* bmap, const double* __restrict__ bglob, double* __restrict__ x2out0,
+    double* __restrict__ b1out, double* __restrict__ x2out1, double* __restrict__ b2out,
+    double omega, EdgeFix ef) {
+  using Gm = V2Geom<T2, NT>;
+  constexpr int kT2 = Gm::kT2, kD0 = Gm::kD0, kD1 = Gm::kD1, kV2Threads = NT;
+  extern __shared__ double smem[];
+  constexpr int A0 = kD0 * kD0, A1 = kD1 * kD1;
+  double* sb0 = smem;
+  double* sd0 = sb0 + A0;
+  double* sx1 = sd0 + A0;
+  double* sx2 = sx1 + A0;
+  double* sr0 = sx2 + A0;
+  double* sb1 = sr0 + A0;
+  double* sd1 = sb1 + A1;
+  double* sy1 = sd1 + A1;
+  double* sy2 = sy1 + A1;
+  double* sr1 = sy2 + A1;
+  const int mode = blockIdx.y, tid = threadIdx.x;
+  const int m0 = n0 - 1, m1 = n0 / 2 - 1, n2 = n0 / 4, m2 = n2 - 1;
+  const int tpr = (n2 + kT2 - 1) / kT2;
+  const int tx = blockIdx.x % tpr, ty = blockIdx.x / tpr;
+  const int I0 = 1 + tx * kT2, J0 = 1 + ty * kT2;       // level l+2, first node
+  const int o1x = 2 * I0 - 3, o1y = 2 * J0 - 3;          // level l+1 index of local (0,0)
+  const int o0x = 2 * o1x - 3, o0y = 2 * o1y - 3;        // level l index of local (0,0)
+  const double* b = bglob + (int64_t)(bmap ? bmap[mode] : mode) * N0;
+  auto in0 = [&](int x, int y) { return x >= 1 && x <= m0 && y >= 1 && y <= m0; };
+  auto in1 = [&](int x, int y) { return x >= 1 && x <= m1 && y >= 1 && y <= m1; };
+  // every global load of both levels at once: level l's right-hand side and
+  // stencil rows for the thread's points (e = tid + 512 p), level l+1's rows
+  constexpr int kP0 = (A0 + kV2Threads - 1) / kV2Threads;
+  static_assert(A1 <= kV2Threads, "one level-(l+1) point per thread");
+  double sv[kP0][9], bv[kP0], tv[9];
+  int64_t gp[kP0];
+#pragma unroll
+  for (int p = 0; p < kP0; ++p) {
+    const int e = tid + kV2Threads * p, lx = e % kD0, ly = e / kD0;
+    const int fx = o0x + lx, fy = o0y + ly;
+    const bool in = e < A0 && in0(fx, fy);
+    gp[p] = in ? (int64_t)(fy - 1) * m0 + (fx - 1) : -1;
+    bv[p] = in ? b[gp[p]] : 0.0;
+    if (in && ef.edge) bv[p] = edge_fixed(bv[p], ef, mode, fx, fy);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) sv[p][t] = in ? S0[t * N0 + gp[p]] : (t == 4 ? 1.0 : 0.0);
+  }
+  const int l1x = tid % kD1, l1y = tid / kD1;
+  const int k1x = o1x + l1x, k1y = o1y + l1y;
+  const bool p1 = tid < A1, inp1 = p1 && in1(k1x, k1y);
+  const int64_t g1 = inp1 ? (int64_t)(k1y - 1) * m1 + (k1x - 1) : -1;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) tv[t] = inp1 ? S1[t * N1 + g1] : (t == 4 ? 1.0 : 0.0);
+  // level l: x1 = omega b / d
+#pragma unroll
+  for (int p = 0; p < kP0; ++p) {
+    const int e = tid + kV2Threads * p;
+    if (e < A0) {
+      sb0[e] = bv[p];
+      sd0[e] = sv[p][4];
+      sx1[e] = gp[p] >= 0 ? omega * bv[p] / sv[p][4] : 0.0;
+    }
+  }
+  __syncthreads();
+  // level l: x2 on [1, kD0-1)^2
+#pragma unroll
+  for (int p = 0; p < kP0; ++p) {
+    const int e = tid + kV2Threads * p, lx = e % kD0, ly = e / kD0;
+    if (e >= A0) continue;
+    double v = 0.0;
+    if (lx >= 1 && lx < kD0 - 1 && ly >= 1 && ly < kD0 - 1 && gp[p] >= 0) {
+      double ax = 0.0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) ax += sv[p][t] * sx1[(ly + t / 3 - 1) * kD0 + (lx + t % 3 - 1)];
+      v = sx1[e] + omega * (sb0[e] - ax) / sd0[e];
+    }
+    sx2[e] = v;
+  }
+  __syncthreads();
+  // level l: residual on [2, kD0-2)^2; own x2 (local [6, 38)^2) written out
+#pragma unroll
+  for (int p = 0; p < kP0; ++p) {
+    const int e = tid + kV2Threads * p, lx = e % kD0, ly = e / kD0;
+    if (e >= A0) continue;
+    double v = 0.0;
+    if (lx >= 2 && lx < kD0 - 2 && ly >= 2 && ly < kD0 - 2 && gp[p] >= 0) {
+      double ax = 0.0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) ax += sv[p][t] * sx2[(ly + t / 3 - 1) * kD0 + (lx + t % 3 - 1)];
+      v = sb0[e] - ax;
+      if (lx >= 6 && lx < 6 + 4 * kT2 && ly >= 6 && ly < 6 + 4 * kT2)
+        x2out0[(int64_t)mode * N0 + gp[p]] = sx2[e];
+    }
+    sr0[e] = v;
+  }
+  __syncthreads();
+  // level l+1: right-hand side by restriction, then x1 = omega b / d; own
+  // right-hand side (local [2, 18)^2) written out
+  if (p1) {
+    double bb = 0.0;
+    if (inp1) {
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const double wgt = (dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0);
+          bb += wgt * sr0[(2 * k1y + dy - o0y) * kD0 + (2 * k1x + dx - o0x)];
+        }
+      if (l1x >= 2 && l1x < 2 + 2 * kT2 && l1y >= 2 && l1y < 2 + 2 * kT2)
+        b1out[(int64_t)mode * N1 + g1] = bb;
+    }
+    sb1[tid] = bb;
+    sd1[tid] = tv[4];
+    sy1[tid] = inp1 ? omega * bb / tv[4] : 0.0;
+  }
+  __syncthreads();
+  if (p1) {
+    double v = 0.0;
+    if (l1x >= 1 && l1x < kD1 - 1 && l1y >= 1 && l1y < kD1 - 1 && inp1) {
+      double ax = 0.0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) ax += tv[t] * sy1[(l1y + t / 3 - 1) * kD1 + (l1x + t % 3 - 1)];
+      v = sy1[tid] + omega * (sb1[tid] - ax) / sd1[tid];
+    }
+    sy2[tid] = v;
+  }
+  __syncthreads();
+  if (p1) {
+    double v = 0.0;
+    if (l1x >= 2 && l1x < kD1 - 2 && l1y >= 2 && l1y < kD1 - 2 && inp1) {
+      double ax = 0.0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) ax += tv[t] * sy2[(l1y + t / 3 - 1) * kD1 + (l1x + t % 3 - 1)];
+      v = sb1[tid] - ax;
+      if (l1x < kD1 - 3 && l1y < kD1 - 3) x2out1[(int64_t)mode * N1 + g1] = sy2[tid];
+    }
+    sr1[tid] = v;
+  }
+  __syncthreads();
+  // level l+2: right-hand side of the tile's nodes
+  if (tid < kT2 * kT2) {
+    const int I = I0 + tid % kT2, J = J0 + tid / kT2;
+    if (I <= m2 && J <= m2) {
+      double acc = 0.0;
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const double wgt = (dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0);
+          acc += wgt * sr1[(2 * J + dy - o1y) * kD1 + (2 * I + dx - o1x)];
+        }
+      b2out[(int64_t)mode * N2 + (int64_t)(J - 1) * m2 + (I - 1)] = acc;
+    }
+  }
+}
+
+template <int T2, int NT>
+__global__ __launch_bounds__(NT) void vup2_kernel(
+    const double* __restrict__ S0, const double* __restrict__ S1, int n0, int64_t N0, int64_t N1,
+    int64_t N2, const int* bmap, const int* xmap, const double* __restrict__ bglob,
+    const double* __restrict__ x2in0, const double* __restrict__ b1in,
+    const double* __restrict__ x2in1, const double* __restrict__ xc2, int64_t xcslab,
+    double* __restrict__ xout, double omega, EdgeFix ef) {
+  using Gm = V2Geom<T2, NT>;
+  constexpr int kT2 = Gm::kT2, kU0 = Gm::kU0, kU1 = Gm::kU1, kU2 = Gm::kU2, kV2Threads = NT;
+  extern __shared__ double smem[];
+  constexpr int A0 = kU0 * kU0, A1 = kU1 * kU1, A2 = kU2 * kU2;
+  double* sb0 = smem;
+  double* sd0 = sb0 + A0;
+  double* sx3 = sd0 + A0;
+  double* sx4 = sx3 + A0;
+  double* sb1 = sx4 + A0;
+  double* sd1 = sb1 + A1;
+  double* sy3 = sd1 + A1;
+  double* sy4 = sy3 + A1;
+  double* sy5 = sy4 + A1;
+  double* sc = sy5 + A1;
+  const int mode = blockIdx.y, tid = threadIdx.x;
+  const int m0 = n0 - 1, m1 = n0 / 2 - 1, n2 = n0 / 4, m2 = n2 - 1;
+  const int tpr = (n2 + kT2 - 1) / kT2;
+  const int tx = blockIdx.x % tpr, ty = blockIdx.x / tpr;
+  const int I0 = 1 + tx * kT2, J0 = 1 + ty * kT2;
+  const int o0x = 4 * I0 - 5, o0y = 4 * J0 - 5;          // level l index of local (0,0)
+  const int o1x = 2 * I0 - 5, o1y = 2 * J0 - 5;          // level l+1
+  const int o2x = I0 - 3, o2y = J0 - 3;                  // level l+2
+  const double* b = bglob + (int64_t)(bmap ? bmap[mode] : mode) * N0;
+  const double* x20 = x2in0 + (int64_t)mode * N0;
+  const double* b1 = b1in + (int64_t)mode * N1;
+  const double* x21 = x2in1 + (int64_t)mode * N1;
+  const double* xc = xc2 + (int64_t)mode * N2;
+  auto in0 = [&](int x, int y) { return x >= 1 && x <= m0 && y >= 1 && y <= m0; };
+  auto in1 = [&](int x, int y) { return x >= 1 && x <= m1 && y >= 1 && y <= m1; };
+  static_assert(A2 <= kV2Threads, "one coarse value per thread");
+  // every global load at once: the coarse correction, level l+1's and level
+  // l's right-hand sides, pre-smoothed values and stencil rows
+  double cv = 0.0;
+  {
+    const int cx = o2x + tid % kU2, cy = o2y + tid / kU2;
+    if (tid < A2 && cx >= 1 && cx <= m2 && cy >= 1 && cy <= m2) {
+      const int64_t g = (int64_t)(cy - 1) * m2 + (cx - 1);
+      cv = xc[g];
+      if (xcslab) cv = (cv + xc[g + xcslab]) + (xc[g + 2 * xcslab] + xc[g + 3 * xcslab]);
+    }
+  }
+  constexpr int kP1 = (A1 + kV2Threads - 1) / kV2Threads;
+  constexpr int kP0 = (A0 + kV2Threads - 1) / kV2Threads;
+  double tv[kP1][9], b1v[kP1], x1v[kP1];
+  int64_t g1p[kP1];
+#pragma unroll
+  for (int p = 0; p < kP1; ++p) {
+    const int e = tid + kV2Threads * p, kx = o1x + e % kU1, ky = o1y + e / kU1;
+    const bool in = e < A1 && in1(kx, ky);
+    g1p[p] = in ? (int64_t)(ky - 1) * m1 + (kx - 1) : -1;
+    b1v[p] = in ? b1[g1p[p]] : 0.0;
+    x1v[p] = in ? x21[g1p[p]] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) tv[p][t] = in ? S1[t * N1 + g1p[p]] : (t == 4 ? 1.0 : 0.0);
+  }
+  double sv[kP0][9], bv[kP0], xv[kP0];
+  int64_t gp[kP0];
+#pragma unroll
+  for (int p = 0; p < kP0; ++p) {
+    const int e = tid + kV2Threads * p, fx = o0x + e % kU0, fy = o0y + e / kU0;
+    const bool in = e < A0 && in0(fx, fy);
+    gp[p] = in ? (int64_t)(fy - 1) * m0 + (fx - 1) : -1;
+    bv[p] = in ? b[gp[p]] : 0.0;
+    if (in && ef.edge) bv[p] = edge_fixed(bv[p], ef, mode, fx, fy);
+    xv[p] = in ? x20[gp[p]] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) sv[p][t] = in ? S0[t * N0 + gp[p]] : (t == 4 ? 1.0 : 0.0);
+  }
+  if (tid < A2) sc[tid] = cv;
+  __syncthreads();
+  // bilinear interpolation from a coarser level held in LDS (origin ocx, ocy)
+  auto interp = [&](const double* c, int ext, int ocx, int ocy, int fx, int fy) {
+    const int Ia = fx >> 1, Ib = (fx + 1) >> 1, Ja = fy >> 1, Jb = (fy + 1) >> 1;
+    auto C = [&](int I, int J) { return c[(J - ocy) * ext + (I - ocx)]; };
+    double pr;
+    if (fx & 1) {
+      if (fy & 1) pr = 0.25 * C(Ia, Ja) + 0.25 * C(Ib, Ja) + 0.25 * C(Ia, Jb) + 0.25 * C(Ib, Jb);
+      else pr = 0.5 * C(Ia, Ja) + 0.5 * C(Ib, Ja);
+    } else {
+      if (fy & 1) pr = 0.5 * C(Ia, Ja) + 0.5 * C(Ia, Jb);
+      else pr = C(Ia, Ja);
+    }
+    return pr;
+  };
+  // level l+1: prolong-add, then two post-smoothing sweeps
+#pragma unroll
+  for (int p = 0; p < kP1; ++p) {
+    const int e = tid + kV2Threads * p;
+    if (e >= A1) continue;
+    const int kx = o1x + e % kU1, ky = o1y + e / kU1;
+    sb1[e] = b1v[p];
+    sd1[e] = tv[p][4];
+    sy3[e] = g1p[p] >= 0 ? x1v[p] + interp(sc, kU2, o2x, o2y, kx, ky) : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < kP1; ++p) {
+    const int e = tid + kV2Threads * p, lx = e % kU1, ly = e / kU1;
+    if (e >= A1) continue;
+    double v = 0.0;
+    if (lx >= 1 && lx < kU1 - 1 && ly >= 1 && ly < kU1 - 1 && g1p[p] >= 0) {
+      double ax = 0.0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) ax += tv[p][t] * sy3[(ly + t / 3 - 1) * kU1 + (lx + t % 3 - 1)];
+      v = sy3[e] + omega * (sb1[e] - ax) / sd1[e];
+    }
+    sy4[e] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < kP1; ++p) {
+    const int e = tid + kV2Threads * p, lx = e % kU1, ly = e / kU1;
+    if (e >= A1) continue;
+    double v = 0.0;
+    if (lx >= 2 && lx < kU1 - 2 && ly >= 2 && ly < kU1 - 2 && g1p[p] >= 0) {
+      double ax = 0.0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) ax += tv[p][t] * sy4[(ly + t / 3 - 1) * kU1 + (lx + t % 3 - 1)];
+      v = sy4[e] + omega * (sb1[e] - ax) / sd1[e];
+    }
+    sy5[e] = v;  // level l+1's correction (zero outside the domain)
+  }
+  __syncthreads();
+  // level l: prolong-add from level l+1, then two post-smoothing sweeps
+#pragma unroll
+  for (int p = 0; p < kP0; ++p) {
+    const int e = tid + kV2Threads * p;
+    if (e >= A0) continue;
+    const int fx = o0x + e % kU0, fy = o0y + e / kU0;
+    sb0[e] = bv[p];
+    sd0[e] = sv[p][4];
+    sx3[e] = gp[p] >= 0 ? xv[p] + interp(sy5, kU1, o1x, o1y, fx, fy) : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < kP0; ++p) {
+    const int e = tid + kV2Threads * p, lx = e % kU0, ly = e / kU0;
+    if (e >= A0) continue;
+    double v = 0.0;
+    if (lx >= 1 && lx < kU0 - 1 && ly >= 1 && ly < kU0 - 1 && gp[p] >= 0) {
+      double ax = 0.0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) ax += sv[p][t] * sx3[(ly + t / 3 - 1) * kU0 + (lx + t % 3 - 1)];
+      v = sx3[e] + omega * (sb0[e] - ax) / sd0[e];
+    }
+    sx4[e] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < kP0; ++p) {
+    const int e = tid + kV2Threads * p, lx = e % kU0, ly = e / kU0;
+    if (e >= A0) continue;
+    if (lx >= 2 && lx < kU0 - 2 && ly >= 2 && ly < kU0 - 2 && gp[p] >= 0) {
+      double ax = 0.0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) ax += sv[p][t] * sx4[(ly + t / 3 - 1) * kU0 + (lx + t % 3 - 1)];
+      xout[(int64_t)(xmap ? xmap[mode] : mode) * N0 + gp[p]] = sx4[e] + omega * (sb0[e] - ax) / sd0[e];
+    }
+  }
+}
+
+// The two-level kernels pay off where a one-level launch is latency-bound:
+// few workgroups, each waiting on its own chain of barriers.  The tile size
+// follows the launch's size in 8 x 8 tiles (W8 workgroups): below 128, 4 x 4
+// tiles (31^2 level-l nodes per 256-thread workgroup down, 20^2 up: four times
+// the workgroups, shorter chains); below 512, 8 x 8 tiles (47^2 and 36^2, 512
+// threads); from 512 on the one-level kernels, which compute no halo twice,
+// are faster (measured at 128x128: W8 = 48, 96 / 160, 256 / 560).
+namespace {
+int64_t two_level_w8(const Level& L2, int modes) {
+  const int t8 = (L2.n + 7) / 8;
+  return (int64_t)t8 * t8 * modes;
+}
+}  // namespace
+
+bool two_level_pays(const Level& L2, int modes) { return two_level_w8(L2, modes) < 512; }
+
+void launch_vdown2(hipStream_t s, const Level& L0, const Level& L1, const Level& L2, int modes,
+                   const double* b, double* x2_0, double* b1, double* x2_1, double* b2,
+                   double omega, const int* bmap, const EdgeFix& ef) {
+  if (L0.n % 4 || L1.n * 2 != L0.n || L2.n * 4 != L0.n)
+    throw Error(SG_ERR_INTERNAL, "two-level V-cycle: grid sizes");
+  if (two_level_w8(L2, modes) < 128) {
+    const int tpr = (L2.n + 3) / 4;
+    const size_t lds = V2Geom<4, 256>::down_lds();
+    hipLaunchKernelGGL((vdown2_kernel<4, 256>), dim3(tpr * tpr, modes), dim3(256), lds, s, L0.S,
+                       L1.S, L0.n, L0.N, L1.N, L2.N, bmap, b, x2_0, b1, x2_1, b2, omega, ef);
+  } else {
+    const int tpr = (L2.n + 7) / 8;
+    const size_t lds = V2Geom<8, 512>::down_lds();
+    hipLaunchKernelGGL((vdown2_kernel<8, 512>), dim3(tpr * tpr, modes), dim3(512), lds, s, L0.S,
+                       L1.S, L0.n, L0.N, L1.N, L2.N, bmap, b, x2_0, b1, x2_1, b2, omega, ef);
+  }
+}
+
+void launch_vup2(hipStream_t s, const Level& L0, const Level& L1, const Level& L2, int modes,
+                 const double* b, const double* x2_0, const double* b1, const double* x2_1,
+                 const double* xc2, int xc_slices, double* x, double omega, const int* bmap,
+                 const int* xmap, const EdgeFix& ef) {
+  if (L0.n % 4 || L1.n * 2 != L0.n || L2.n * 4 != L0.n)
+    throw Error(SG_ERR_INTERNAL, "two-level V-cycle: grid sizes");
+  if (xc_slices != 1 && xc_slices != kDenseSlices) throw Error(SG_ERR_INTERNAL, "vup2: slices");
+  const int64_t xcslab = xc_slices == 1 ? 0 : (int64_t)modes * L2.N;
+  if (two_level_w8(L2, modes) < 128) {
+    const int tpr = (L2.n + 3) / 4;
+    const size_t lds = V2Geom<4, 256>::up_lds();
+    hipLaunchKernelGGL((vup2_kernel<4, 256>), dim3(tpr * tpr, modes), dim3(256), lds, s, L0.S,
+                       L1.S, L0.n, L0.N, L1.N, L2.N, bmap, xmap, b, x2_0, b1, x2_1, xc2, xcslab,
+                       x, omega, ef);
+  } else {
+    const int tpr = (L2.n + 7) / 8;
+    const size_t lds = V2Geom<8, 512>::up_lds();
+    hipLaunchKernelGGL((vup2_kernel<8, 512>), dim3(tpr * tpr, modes), dim3(512), lds, s, L0.S,
+                       L1.S, L0.n, L0.N, L1.N, L2.N, bmap, xmap, b, x2_0, b1, x2_1, xc2, xcslab,
+                       x, omega, ef);
+  }
+}
+
 // bmap / xmap (device, may be null): mode t reads b from vector bmap[t] and
 // writes x to vector xmap[t] of the full-length arrays (the field split's
 // gather and scatter folded into the finest level)

@@ -177,6 +177,38 @@ def test_gmres_long_cycle_matches_oracle():
     assert np.linalg.norm(ug - xo) <= 1e-10 * np.linalg.norm(xo)
 
 
+TWO_LEVEL = {
+    # 256x256: two-level kernels on levels 0-1 (8 x 8 tiles for the mean cycle's
+    # 6 modes, 4 x 4 for the split of 1 mode), one-level kernels on level 2,
+    # then the dense operator in slices
+    "n256_m2p2": Problem(n=256, M=2, p=2, q=4, cov="exp_l1", sigma=0.8, corr_len=0.3),
+    # 128x128, 10 modes: 8 x 8 tiles for the mean cycle, 4 x 4 for the splits
+    "n128_m3p2": Problem(n=128, M=3, p=2, q=4, cov="sqexp", sigma=1.0, corr_len=0.5),
+    # 128x128, 56 modes: the mean cycle runs the one-level kernels
+    "n128_m5p3": Problem(n=128, M=5, p=3, q=6, cov="exp_l1", sigma=0.6, corr_len=0.5),
+}
+
+
+@pytest.mark.parametrize("name", list(TWO_LEVEL))
+@pytest.mark.parametrize("pc", ["mean", "fs"])
+def test_precond_two_level(name, pc):
+    """Fine levels in one kernel each way at both tile sizes, or one level at a
+    time, against the oracle's V-cycles."""
+    need_gpu()
+    from oracle.system import SGSystem
+    from oracle.gmg import GMGHierarchy
+    from oracle.precond import FieldSplit, make_groups
+    prob = TWO_LEVEL[name]
+    S = SGSystem(prob)
+    G = instance(prob)
+    print(f"[precond two-level {name}] P={S.P} N_h={S.Nh}", flush=True)
+    r = random_vector(S.P * S.Nh, 301)
+    z = to_host(G.precond(to_dev(r), pc, "klvar"))
+    ref = FieldSplit(S, GMGHierarchy(S.A[0], S.n), make_groups(S.Jp, "mean" if pc == "mean" else "klvar")).apply(r)
+    assert relmax(z, ref) < 1e-12
+    G.close()
+
+
 @pytest.mark.parametrize("pc", ["mean", "fs"])
 def test_precond_large_P(pc):
     from oracle.precond import FieldSplit, make_groups
