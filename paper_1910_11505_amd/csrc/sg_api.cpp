@@ -1295,11 +1295,11 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
         double* h2 = K.hdev + (m + 1);
         double* nrm = K.hdev + 2 * (m + 1);
         // CGS2: h1 = V^T w, w -= V h1, h2 = V^T w (fused with that update),
-        // w -= V h2 and |w|^2 (fused with the second update)
+        // w -= V h2 and |w|^2 (fused with the second update), v_{j+1} = w / |w|
         launch_gs_dot(s, K.V, Nv, j + 1, K.w, Nv, K.partial, h1, ef);
         launch_gs_update_dot(s, K.V, Nv, j + 1, h1, K.w, Nv, -1.0, K.partial, h2, ef);
-        launch_gs_update_norm(s, K.V, Nv, j + 1, h2, K.w, Nv, -1.0, K.partial, nrm);
-        launch_scale_by_inv_norm(s, K.w, nrm, K.V + (int64_t)(j + 1) * Nv, Nv);
+        launch_gs_update_norm_scale(s, K.V, Nv, j + 1, h2, K.w, Nv, -1.0, K.partial, nrm,
+                                    K.V + (int64_t)(j + 1) * Nv);
         check_launch();
         SG_HIP(hipMemcpyAsync(hp, K.hdev, (2 * (m + 1) + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
         SG_HIP(hipEventRecord(H.fetched, s));

@@ -265,8 +265,10 @@ void launch_gs_dot(hipStream_t s, const double* V, int64_t ldv, int nv, const do
 void launch_gs_update_dot(hipStream_t s, const double* V, int64_t ldv, int nv, const double* h,
                           double* w, int64_t N, double sign, double* partial, double* out,
                           const EdgeFix& ef = EdgeFix{});
-void launch_gs_update_norm(hipStream_t s, const double* V, int64_t ldv, int nv, const double* h,
-                           double* w, int64_t N, double sign, double* partial, double* out);
+// w <- w + sign V h, |w|^2 -> *nrm2 and vnext = w / |w| (zero when |w| = 0)
+void launch_gs_update_norm_scale(hipStream_t s, const double* V, int64_t ldv, int nv,
+                                 const double* h, double* w, int64_t N, double sign,
+                                 double* partial, double* nrm2, double* vnext);
 void launch_combine(hipStream_t s, const double* V, int64_t ldv, int nv, const double* y,
                     double* out, int64_t N);
 void launch_scale_by_inv_norm(hipStream_t s, const double* w, const double* nrm2, double* v,

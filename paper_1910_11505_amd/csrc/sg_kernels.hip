@@ -1120,23 +1120,49 @@ __global__ __launch_bounds__(kDotThreads) void gs_update_dot_kernel(
   block_partials(red, nv, partial, nblk, 0);
 }
 
-// w <- w + sign * sum_l h[l] V_l, then partial[b] = block b's part of w . w
+// w <- w + sign * sum_l h[l] V_l, then partial[b] = block b's part of w . w;
+// a grid-stride loop over at most kNormBlocks blocks, so the norm's partials
+// are few enough for every block of the scaling kernel to sum them itself
+constexpr int kNormBlocks = 1024;
 __global__ __launch_bounds__(kDotThreads) void gs_update_norm_kernel(
     const double* __restrict__ V, int64_t ldv, int nv, const double* __restrict__ h,
     double* __restrict__ w, int64_t N, double sign, double* __restrict__ partial) {
   __shared__ double red[4 * 64];
-  const int64_t i = (int64_t)blockIdx.x * kDotThreads + threadIdx.x;
   double a[1] = {0.0};
-  if (i < N) {
+  for (int64_t i = (int64_t)blockIdx.x * kDotThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kDotThreads) {
     double acc = 0.0;
 #pragma unroll 8
     for (int l = 0; l < nv; ++l) acc = fma(h[l], V[(int64_t)l * ldv + i], acc);
     const double wi = w[i] + sign * acc;
     w[i] = wi;
-    a[0] = wi * wi;
+    a[0] = fma(wi, wi, a[0]);
   }
   wave_sums<1>(a, red + 64 * (threadIdx.x >> 6));
   block_partials(red, 1, partial, gridDim.x, 0);
+}
+
+// v = w / |w| with |w|^2 = sum_b partial[b] (b < nblk), summed by every block
+// in the same fixed order; block 0 stores |w|^2 in *nrm2
+__global__ __launch_bounds__(kDotThreads) void scale_norm_kernel(const double* __restrict__ w,
+                                                                const double* __restrict__ partial,
+                                                                int nblk, double* __restrict__ nrm2,
+                                                                double* __restrict__ v, int64_t N) {
+  __shared__ double red[4];
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int b = threadIdx.x;
+  for (; b + 3 * kDotThreads < nblk; b += 4 * kDotThreads) {
+    a0 += partial[b];
+    a1 += partial[b + kDotThreads];
+    a2 += partial[b + 2 * kDotThreads];
+    a3 += partial[b + 3 * kDotThreads];
+  }
+  for (; b < nblk; b += kDotThreads) a0 += partial[b];
+  const double nn2 = block_sum((a0 + a1) + (a2 + a3), red);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *nrm2 = nn2;
+  const double nn = sqrt(nn2);
+  const int64_t i = (int64_t)blockIdx.x * kDotThreads + threadIdx.x;
+  if (i < N) v[i] = nn > 0.0 ? w[i] / nn : 0.0;
 }
 
 // out[l] = sum_b partial[l * nblk + b]: one block per l, four fixed strided
@@ -1193,12 +1219,14 @@ void launch_gs_update_dot(hipStream_t s, const double* V, int64_t ldv, int nv, c
   hipLaunchKernelGGL(reduce_wide_kernel, dim3(nv), block, 0, s, partial, nblk, out);
 }
 
-void launch_gs_update_norm(hipStream_t s, const double* V, int64_t ldv, int nv, const double* h,
-                           double* w, int64_t N, double sign, double* partial, double* out) {
-  const int nblk = gs_blocks(N);
-  hipLaunchKernelGGL(gs_update_norm_kernel, dim3(nblk), dim3(kDotThreads), 0, s, V, ldv, nv, h, w,
-                     N, sign, partial);
-  hipLaunchKernelGGL(reduce_wide_kernel, dim3(1), dim3(kDotThreads), 0, s, partial, nblk, out);
+void launch_gs_update_norm_scale(hipStream_t s, const double* V, int64_t ldv, int nv,
+                                 const double* h, double* w, int64_t N, double sign,
+                                 double* partial, double* nrm2, double* vnext) {
+  const int nb = std::min(gs_blocks(N), kNormBlocks);
+  hipLaunchKernelGGL(gs_update_norm_kernel, dim3(nb), dim3(kDotThreads), 0, s, V, ldv, nv, h, w, N,
+                     sign, partial);
+  hipLaunchKernelGGL(scale_norm_kernel, dim3(gs_blocks(N)), dim3(kDotThreads), 0, s, w, partial, nb,
+                     nrm2, vnext, N);
 }
 
 // out = sum_l y[l] V_l
