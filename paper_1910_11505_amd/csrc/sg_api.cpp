@@ -872,16 +872,16 @@ int setup_impl(const sg_problem* prob, const double* f_nodal, int force_kc, sg_h
       }
     }
     // register form: the compiled chaos table must be this handle's J(p)
-    H->rapply_ok = H->factored_ok && H->P <= 64 && rapply_supported(H->M, prob->p) &&
+    H->rapply_ok = H->factored_ok && H->P <= kRMax && rapply_supported(H->M, prob->p) &&
                    rapply_matches(H->M, prob->p, H->Jp);
     H->use_rapply = H->rapply_ok;
     if (H->rapply_ok) {
       auto rows = [&](const std::vector<int>& outm, const std::vector<int>& colm) {
         RApplyRows r{};
-        for (int c : colm) r.colmask |= uint64_t(1) << c;
+        for (int c : colm) rset(r.colmask, c);
         std::memset(r.slot, -1, sizeof(r.slot));
         for (size_t t = 0; t < outm.size(); ++t) {
-          r.rowmask |= uint64_t(1) << outm[t];
+          rset(r.rowmask, outm[t]);
           r.slot[outm[t]] = (signed char)t;
           r.mode[t] = (unsigned char)outm[t];
         }
@@ -896,7 +896,7 @@ int setup_impl(const sg_problem* prob, const double* f_nodal, int force_kc, sg_h
             }
             return false;
           };
-          if (below(colm) && below(outm)) r.gammask |= uint64_t(1) << gm;
+          if (below(colm) && below(outm)) rset(r.gammask, gm);
         }
         return r;
       };
@@ -1554,6 +1554,13 @@ size_t batch_layout(sg_batch& B, char* base) {
 
 // Builds the descriptors, work-item tables and launch sequences for one
 // preconditioner (mean-based, or field split with a grouping).
+// apply form of an instance in batched solves: 2 register-resident (the
+// small-space kernel, P <= 35), 1 factored in LDS tiles, 0 triple products
+int batch_form(const sg_handle& H) {
+  if (!H.use_factored) return 0;
+  return H.use_rapply && H.P <= 35 ? 2 : 1;
+}
+
 // live (may be null): instances whose work items the plan holds; the others'
 // descriptors stay (items name instances by index) but none of their work is
 // launched, which is what their device gates would skip anyway
@@ -1581,7 +1588,7 @@ Plan build_plan(sg_batch& B, int pc_kind, int grouping, const double* F, double*
     I.Nv = (int64_t)H.P * H.Nh;
     I.a = D.a;
     I.full = D.full;
-    I.form = H.use_factored ? (H.use_rapply ? 2 : 1) : 0;
+    I.form = batch_form(H);
     I.M = H.M;
     I.pdeg = H.prob.p;
     I.mu = H.prob.mu;
@@ -2100,7 +2107,7 @@ int sg_batch_solve(sg_batch* b, const sg_solve_opts* o, const double* F, double*
     auto forms_changed = [&](const Plan& pl) {
       for (int i = 0; i < B.count; ++i) {
         const sg_handle& Hi = *B.h[i];
-        const int f = Hi.use_factored ? (Hi.use_rapply ? 2 : 1) : 0;
+        const int f = batch_form(Hi);
         if (pl.inst[i].form != f || (f == 1 && pl.inst[i].ffull.qb != Hi.d.ffull.qb)) return true;
       }
       return false;

@@ -130,13 +130,18 @@ struct FRowSetDev {
 // Rows of the register-resident factored apply (P <= 35): column modes, output
 // modes and the intermediate gamma set as bit masks over J(p); slot[beta] is
 // the output slot of mode beta (compact output layout), mode[slot] its mode id.
+constexpr int kRMax = 128;  // modes of the register-resident apply (masks of two words)
 struct RApplyRows {
-  uint64_t colmask, rowmask;
-  uint64_t gammask;  // gamma <= some column and <= some output row (step-1 rows that matter)
+  uint64_t colmask[2], rowmask[2];
+  uint64_t gammask[2];  // gamma <= some column and <= some output row (step-1 rows that matter)
   int nrows;
-  signed char slot[64];
-  unsigned char mode[64];
+  signed char slot[kRMax];
+  unsigned char mode[kRMax];
 };
+__host__ __device__ inline bool rbit(const uint64_t (&m)[2], int i) {
+  return ((m[i >> 6] >> (i & 63)) & 1) != 0;
+}
+__host__ inline void rset(uint64_t (&m)[2], int i) { m[i >> 6] |= uint64_t(1) << (i & 63); }
 
 struct Level {
   int n;          // elements per side on this level

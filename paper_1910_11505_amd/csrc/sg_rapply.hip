@@ -1,4 +1,5 @@
-// Register-resident factored SG apply for small chaos spaces (P <= 35).
+// Register-resident factored SG apply for small chaos spaces (P <= 35, and a
+// variant with the monomials in LDS for 35 < P <= 84).
 //
 // The same operator as the factored tile kernel (sum_k a_k G_k = a_min I +
 // w T T^T, exact for q >= 2p; see FRowSetDev), with the chaos structure of
@@ -200,6 +201,7 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
                                             double* __restrict__ edge) {
   constexpr const RTab<M, p>& T = RTabHolder<M, p>::v;
   constexpr int P = RTab<M, p>::P;
+  static_assert(P <= 64, "one mask word");
   constexpr uint64_t kAll = P >= 64 ? ~0ull : ((1ull << P) - 1);
   const int nrows = FULL ? P : rr.nrows;
   double* sN = smem;  // [P][25] nodal values (steps 1-2)
@@ -213,7 +215,7 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
   const int64_t Nq = (int64_t)4 * n * n;
   // (the column and gamma masks stay run-time values: known, the unrolled
   // gradient and step-1 code is scheduled with more values live than fit)
-  const uint64_t colmask = rr.colmask, rowmask = FULL ? kAll : rr.rowmask;
+  const uint64_t colmask = rr.colmask[0], rowmask = FULL ? kAll : rr.rowmask[0];
 
   // 1. nodal values of the column modes (all loads in flight at once)
   constexpr int NL = (P * 25 + kRThreads - 1) / kRThreads;
@@ -268,7 +270,7 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
   // 3. step 1 in place
   // gamma outside the block's set: never read by step 2, or zero (then no column
   // lies above it, so its slot already holds zero)
-  const uint64_t gammask = rr.gammask;
+  const uint64_t gammask = rr.gammask[0];
 #pragma unroll
   for (int gm = 0; gm < P; ++gm) {
     if (!((gammask >> gm) & 1)) continue;
@@ -383,6 +385,188 @@ __global__ __launch_bounds__(kRThreads) void brapply_kernel(const BInst* __restr
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same operator for larger chaos spaces (35 < P <= 84).  The scaled
+// gradients stay in registers (one component per wavefront, as above); the P
+// monomials of each point move to LDS, lane-major so a wavefront's read of one
+// of them is 64 consecutive doubles; the a_min term is recomputed from the
+// nodal values, which stay in LDS; and the output rows are taken in chunks of
+// kRChunk, their corner contributions reduced to node sums chunk by chunk.
+// ---------------------------------------------------------------------------
+constexpr int kRChunk = 16;
+
+template <int M, int p, bool FULL>
+__device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, double mu,
+                                                double a_min, const double* __restrict__ g,
+                                                const RApplyRows& rr,
+                                                const double* __restrict__ U, int64_t Nh,
+                                                const double* __restrict__ rin, double beta,
+                                                double sgn, double* __restrict__ out,
+                                                double* __restrict__ edge) {
+  constexpr const RTab<M, p>& T = RTabHolder<M, p>::v;
+  constexpr int P = RTab<M, p>::P;
+  static_assert(P <= kRMax, "two mask words");
+  double* sN = smem;            // [P][25] nodal values
+  double* sM = sN + P * 25;     // [P][64] scaled monomials of the tile's points
+  double* sC = sM + P * 64;     // [2][kRChunk][64] corner contributions of a row chunk
+  const int nt = n / kTileE, ntiles = nt * nt;
+  const int tx = tile % nt, ty = tile / nt;
+  const int x0 = tx * kTileE, y0 = ty * kTileE;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int comp = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int m = n - 1;
+  const int64_t Nq = (int64_t)4 * n * n;
+  // the masks stay run-time values even for the full set: compile-time ones
+  // let the scheduler hoist the monomial reads and spill
+  auto col = [&](int a) { return rbit(rr.colmask, a); };
+  auto row = [&](int b) { return rbit(rr.rowmask, b); };
+
+  // 1. nodal values of the column modes (all loads in flight at once)
+  constexpr int NL = (P * 25 + kRThreads - 1) / kRThreads;
+  double v[NL];
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int idx = tid + kRThreads * u;
+    const int c = min(idx / 25, P - 1), nd = idx - (idx / 25) * 25;
+    const int gx = x0 + nd % 5, gy = y0 + nd / 5;
+    const bool ok = idx < P * 25 && col(c) && gx >= 1 && gx <= m && gy >= 1 && gy <= m;
+    v[u] = ok ? U[(int64_t)c * Nh + (int64_t)(gy - 1) * m + (gx - 1)] : 0.0;
+  }
+  double gv[M];
+#pragma unroll
+  for (int nn = 0; nn < M; ++nn) gv[nn] = g[(int64_t)nn * Nq + (int64_t)tile * kTileQ + lane];
+#pragma unroll
+  for (int u = 0; u < NL; ++u)
+    if (tid + kRThreads * u < P * 25) sN[tid + kRThreads * u] = v[u];
+
+  // 2. monomials (both wavefronts compute them; wavefront c stores those of
+  // parity c), then gradient component c and w
+  {
+    double mono[P];
+    mono[0] = 1.0;
+#pragma unroll
+    for (int d = 1; d < P; ++d) mono[d] = mono[T.par[d]] * gv[T.var[d]] * T.inv[d];
+#pragma unroll
+    for (int d = 0; d < P; ++d)
+      if ((d & 1) == comp) sM[d * 64 + lane] = mono[d];
+  }
+  __syncthreads();
+  const int el = lane >> 2, ql = lane & 3;
+  const int ex = el & 3, ey = el >> 2;
+  const double xi = r_gauss_pt(ql & 1), eta = r_gauss_pt(ql >> 1);
+  const int o00 = ey * 5 + ex, o10 = o00 + 1, o01 = o00 + 5, o11 = o00 + 6;
+  const int oA = o00, oB = comp ? o01 : o10, oC = comp ? o10 : o01, oD = o11;
+  const double w0 = comp ? 1.0 - xi : 1.0 - eta, w1 = comp ? xi : eta;
+  auto grad = [&](int a) {
+    const double* u = sN + a * 25;
+    return w0 * (u[oB] - u[oA]) + w1 * (u[oD] - u[oC]);
+  };
+  double G[P];
+#pragma unroll
+  for (int a = 0; a < P; ++a) G[a] = col(a) ? T.s[a] * grad(a) : 0.0;
+  double s2 = 0.0;
+#pragma unroll
+  for (int nn = 0; nn < M; ++nn) s2 = fma(gv[nn], gv[nn], s2);
+  const double w = exp(mu + 0.5 * s2);
+
+  // 3. step 1 in place (gamma outside the block's set: never read, or zero)
+#pragma unroll
+  for (int gm = 0; gm < P; ++gm) {
+    if (!rbit(rr.gammask, gm)) continue;
+    double sx = 0.0;
+#pragma unroll
+    for (int t = T.p1[gm]; t < T.p1[gm + 1]; ++t) sx = fma(sM[T.d1[t] * 64 + lane], G[T.a1[t]], sx);
+    G[gm] = sx * T.is2[gm];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+
+  // 4. step 2 by chunks of rows; slot k of a lane holds the contribution to
+  // corner ql ^ k (see rapply_tile); after each chunk the node sums
+  double gp[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int a4 = ql ^ k, ax = a4 & 1, ay = a4 >> 1;
+    gp[k] = comp ? 0.25 * (ay ? 1.0 : -1.0) * (ax ? xi : 1.0 - xi)
+                 : 0.25 * (ax ? 1.0 : -1.0) * (ay ? eta : 1.0 - eta);
+  }
+  double* sCc = sC + comp * kRChunk * 64;
+  const double* sCy = sC + kRChunk * 64;
+#pragma unroll
+  for (int b0 = 0; b0 < P; b0 += kRChunk) {
+#pragma unroll
+    for (int b = b0; b < (b0 + kRChunk < P ? b0 + kRChunk : P); ++b) {
+      if (!row(b)) continue;
+      double sx = 0.0;
+#pragma unroll
+      for (int t = T.p2[b]; t < T.p2[b + 1]; ++t) sx = fma(sM[T.d2[t] * 64 + lane], G[T.g2[t]], sx);
+      double f = (T.s[b] * w) * sx;
+      if (col(b)) f = fma(a_min, grad(b), f);
+      const double k0 = gp[0] * f + quad_xor<2>(gp[2] * f);
+      const double k1 = gp[1] * f + quad_xor<2>(gp[3] * f);
+      sCc[(b - b0) * 64 + lane] = k0 + quad_xor<1>(k1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+    // node sums of the chunk's rows: corner 3 of (x-1, y-1), 2 of (x, y-1),
+    // 1 of (x-1, y), 0 of (x, y), each the x part plus the y part
+    for (int idx = tid; idx < kRChunk * 25; idx += kRThreads) {
+      const int bl = idx / 25, nd = idx - bl * 25, b = b0 + bl;
+      if (b >= P || !row(b)) continue;
+      const int slot = FULL ? b : rr.slot[b];
+      const int nx = nd % 5, ny = nd / 5;
+      const double* c = sC + bl * 64;
+      const double* cy = sCy + bl * 64;
+      double sum = 0.0;
+      if (nx >= 1 && ny >= 1) {
+        const int i = ((ny - 1) * 4 + nx - 1) * 4 + 3;
+        sum += c[i] + cy[i];
+      }
+      if (nx <= 3 && ny >= 1) {
+        const int i = ((ny - 1) * 4 + nx) * 4 + 2;
+        sum += c[i] + cy[i];
+      }
+      if (nx >= 1 && ny <= 3) {
+        const int i = (ny * 4 + nx - 1) * 4 + 1;
+        sum += c[i] + cy[i];
+      }
+      if (nx <= 3 && ny <= 3) {
+        const int i = (ny * 4 + nx) * 4;
+        sum += c[i] + cy[i];
+      }
+      if (nx <= 3 && ny <= 3) {
+        const int gx = x0 + nx, gy = y0 + ny;
+        if (gx >= 1 && gy >= 1) {
+          const int64_t node = (int64_t)(gy - 1) * m + (gx - 1);
+          double base = 0.0;
+          if (beta != 0.0) base = beta * rin[(int64_t)(FULL ? slot : rr.mode[slot]) * Nh + node];
+          out[(int64_t)slot * Nh + node] = base + sgn * sum;
+        }
+      } else {
+        const int e = (nx == 4 && ny == 4) ? 8 : (nx == 4 ? ny : 4 + nx);
+        edge[((int64_t)slot * ntiles + tile) * kEdgeVals + e] = sum;
+      }
+    }
+    __syncthreads();  // the next chunk reuses the corner buffer
+  }
+}
+
+template <int M, int p, bool FULL>
+__global__ __launch_bounds__(kRThreads) void rapply_big_kernel(
+    int n, double mu, double a_min, const double* __restrict__ g, RApplyRows rr,
+    const double* __restrict__ U, int64_t Nh, const double* __restrict__ rin, double beta,
+    double sgn, double* __restrict__ out, double* __restrict__ edge) {
+  extern __shared__ double smem[];
+  const int nt = n / kTileE;
+  rapply_big_tile<M, p, FULL>(smem, xcd_tile(blockIdx.x, nt * nt), n, mu, a_min, g, rr, U, Nh,
+                              rin, beta, sgn, out, edge);
+}
+
+size_t rapply_big_lds_bytes(int P) {
+  return 8 * ((size_t)P * 25 + (size_t)P * 64 + (size_t)2 * kRChunk * 64);
+}
+
+#define SG_RAPPLY_BIG_LIST(X) X(4, 4) X(5, 3) X(6, 3)
+
 // the nodal values and, after them, the corner contributions of both components
 size_t rapply_lds_bytes(int P, int nrows) {
   return 8 * std::max((size_t)P * 25, (size_t)2 * nrows * 64);
@@ -395,6 +579,7 @@ size_t rapply_lds_bytes(int P, int nrows) {
 bool rapply_supported(int M, int p) {
 #define SG_RAPPLY_SUP(MM, PP) if (M == MM && p == PP) return true;
   SG_RAPPLY_LIST(SG_RAPPLY_SUP)
+  SG_RAPPLY_BIG_LIST(SG_RAPPLY_SUP)
 #undef SG_RAPPLY_SUP
   return false;
 }
@@ -412,6 +597,7 @@ static bool rapply_check(const std::vector<std::vector<int>>& Jp) {
 bool rapply_matches(int M, int p, const std::vector<std::vector<int>>& Jp) {
 #define SG_RAPPLY_CHK(MM, PP) if (M == MM && p == PP) return rapply_check<MM, PP>(Jp);
   SG_RAPPLY_LIST(SG_RAPPLY_CHK)
+  SG_RAPPLY_BIG_LIST(SG_RAPPLY_CHK)
 #undef SG_RAPPLY_CHK
   return false;
 }
@@ -422,10 +608,32 @@ void launch_rapply(hipStream_t s, int M, int p, int n, double mu, double a_min, 
   const int nt = n / kTileE, ntiles = nt * nt;
   const int P = (int)rc_binom(M + p, p);
   if (rr.nrows < 1 || rr.nrows > P) throw Error(SG_ERR_INTERNAL, "register apply: bad rows");
+  if (P > kRMax) throw Error(SG_ERR_INTERNAL, "register apply: P");
+  bool full = rr.nrows == P;
+  for (int b = 0; full && b < P; ++b)
+    full = rbit(rr.colmask, b) && rbit(rr.rowmask, b) && rbit(rr.gammask, b) && rr.slot[b] == b &&
+           rr.mode[b] == b;
+#define SG_RAPPLY_BIG_LAUNCH(MM, PP)                                                           \
+  if (M == MM && p == PP) {                                                                    \
+    const size_t blds = rapply_big_lds_bytes(P);                                               \
+    static const bool attr_ok =                                                                \
+        hipFuncSetAttribute((const void*)rapply_big_kernel<MM, PP, true>,                      \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)blds) == hipSuccess && \
+        hipFuncSetAttribute((const void*)rapply_big_kernel<MM, PP, false>,                     \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)blds) == hipSuccess; \
+    if (!attr_ok) throw Error(SG_ERR_HIP, "register apply: LDS size attribute");               \
+    if (full)                                                                                  \
+      hipLaunchKernelGGL((rapply_big_kernel<MM, PP, true>), dim3(ntiles), dim3(kRThreads),    \
+                         blds, s, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);      \
+    else                                                                                       \
+      hipLaunchKernelGGL((rapply_big_kernel<MM, PP, false>), dim3(ntiles), dim3(kRThreads),   \
+                         blds, s, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);      \
+    if (fixup) launch_apply_fixup(s, n, rr.nrows, sgn, edge, out, Nh);                         \
+    return;                                                                                    \
+  }
+  SG_RAPPLY_BIG_LIST(SG_RAPPLY_BIG_LAUNCH)
+#undef SG_RAPPLY_BIG_LAUNCH
   const size_t lds = rapply_lds_bytes(P, rr.nrows);
-  const uint64_t all = P >= 64 ? ~0ull : ((1ull << P) - 1);
-  bool full = rr.nrows == P && rr.colmask == all && rr.rowmask == all && rr.gammask == all;
-  for (int b = 0; full && b < P; ++b) full = rr.slot[b] == b && rr.mode[b] == b;
 #define SG_RAPPLY_LAUNCH(MM, PP)                                                              \
   if (M == MM && p == PP) {                                                                   \
     if (full)                                                                                 \

@@ -18,6 +18,9 @@ SMALL = {
     "n16_m2p2": Problem(n=16, M=2, p=2, q=4, cov="exp_l1", sigma=0.8, corr_len=0.5),
     "n16_m4p3": Problem(n=16, M=4, p=3, q=6, cov="sqexp", sigma=1.0, corr_len=0.5),
     "n8_m6p3": Problem(n=8, M=6, p=3, q=6, cov="exp_l1", sigma=1.0, corr_len=0.25),
+    # P = 56 and 70: the register form with the monomials in LDS
+    "n16_m5p3": Problem(n=16, M=5, p=3, q=6, cov="sqexp", sigma=0.9, corr_len=0.5),
+    "n16_m4p4": Problem(n=16, M=4, p=4, q=8, cov="exp_l1", sigma=0.7, corr_len=0.6),
     # q > 2p: the factored form is still exact
     "n8_m2p2q6": Problem(n=8, M=2, p=2, q=6, cov="sqexp", sigma=1.3, corr_len=0.4),
     # P = 210: only the small sub-batches fit in LDS
@@ -60,7 +63,7 @@ def test_apply_form(name, form, qb):
         G.set_apply("auto", 0)
 
 
-@pytest.mark.parametrize("name", ["n16_m4p3", "n8_m6p3"])
+@pytest.mark.parametrize("name", ["n16_m4p3", "n8_m6p3", "n16_m5p3", "n16_m4p4"])
 @pytest.mark.parametrize("grouping", ["klvar", "permode", "fg", "klvar_meansep"])
 def test_field_split_through_both_forms(name, grouping):
     """The field split's off-diagonal block applies K_{g_s, g_<s} z in both forms."""
