@@ -1554,11 +1554,11 @@ size_t batch_layout(sg_batch& B, char* base) {
 
 // Builds the descriptors, work-item tables and launch sequences for one
 // preconditioner (mean-based, or field split with a grouping).
-// apply form of an instance in batched solves: 2 register-resident (the
-// small-space kernel, P <= 35), 1 factored in LDS tiles, 0 triple products
+// apply form of an instance in batched solves: 2 register-resident, 1 factored
+// in LDS tiles, 0 triple products
 int batch_form(const sg_handle& H) {
   if (!H.use_factored) return 0;
-  return H.use_rapply && H.P <= 35 ? 2 : 1;
+  return H.use_rapply ? 2 : 1;
 }
 
 // live (may be null): instances whose work items the plan holds; the others'

@@ -131,6 +131,7 @@ struct FRowSetDev {
 // modes and the intermediate gamma set as bit masks over J(p); slot[beta] is
 // the output slot of mode beta (compact output layout), mode[slot] its mode id.
 constexpr int kRMax = 128;  // modes of the register-resident apply (masks of two words)
+constexpr int kRSmall = 35;  // ... whose monomials also stay in registers (above: in LDS)
 struct RApplyRows {
   uint64_t colmask[2], rowmask[2];
   uint64_t gammask[2];  // gamma <= some column and <= some output row (step-1 rows that matter)

@@ -416,10 +416,15 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
   const int comp = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int m = n - 1;
   const int64_t Nq = (int64_t)4 * n * n;
-  // the masks stay run-time values even for the full set: compile-time ones
-  // let the scheduler hoist the monomial reads and spill
-  auto col = [&](int a) { return rbit(rr.colmask, a); };
-  auto row = [&](int b) { return rbit(rr.rowmask, b); };
+  // the masks stay run-time values even for the full set (compile-time ones
+  // let the scheduler hoist the monomial reads and spill); they are read once
+  // into uniform registers, not per test, where the compiler would narrow each
+  // test to an unaligned vector load of the descriptor
+  const uint64_t cm[2] = {rr.colmask[0], rr.colmask[1]};
+  const uint64_t rm[2] = {rr.rowmask[0], rr.rowmask[1]};
+  const uint64_t gmk[2] = {rr.gammask[0], rr.gammask[1]};
+  auto col = [&](int a) { return rbit(cm, a); };
+  auto row = [&](int b) { return rbit(rm, b); };
 
   // 1. nodal values of the column modes (all loads in flight at once)
   constexpr int NL = (P * 25 + kRThreads - 1) / kRThreads;
@@ -472,7 +477,7 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
   // 3. step 1 in place (gamma outside the block's set: never read, or zero)
 #pragma unroll
   for (int gm = 0; gm < P; ++gm) {
-    if (!rbit(rr.gammask, gm)) continue;
+    if (!rbit(gmk, gm)) continue;
     double sx = 0.0;
 #pragma unroll
     for (int t = T.p1[gm]; t < T.p1[gm + 1]; ++t) sx = fma(sM[T.d1[t] * 64 + lane], G[T.a1[t]], sx);
@@ -561,14 +566,36 @@ __global__ __launch_bounds__(kRThreads) void rapply_big_kernel(
                               rin, beta, sgn, out, edge);
 }
 
+// (instance, tile) items of instances sharing one (M, p), P > kRSmall
+template <int M, int p>
+__global__ __launch_bounds__(kRThreads) void brapply_big_kernel(
+    const BInst* __restrict__ Is, const BState* __restrict__ Ss, const BItem* __restrict__ items,
+    int nitems, int rowset, int src, int rin, int dst, double beta, double sgn, int gate) {
+  extern __shared__ double smem[];
+  const int it = blockIdx.x;  // one workgroup per item (grid = nitems)
+  if (it >= nitems) return;
+  const BItem w = items[it];
+  const BInst& I = Is[w.inst];
+  const BState& S = Ss[w.inst];
+  if (gated(S, gate)) return;
+  // read in place: the tile code loads the masks once into uniform registers,
+  // the slot and mode tables only in the node sums
+  const RApplyRows& rr = rowset == 0 ? I.rfull : I.rpart[rowset];
+  rapply_big_tile<M, p, false>(smem, w.local, I.n, I.mu, I.amin, gptr(I.gq), rr, bbuf(I, S, src),
+                               I.Nh, rin >= 0 ? bbuf(I, S, rin) : nullptr, beta, sgn,
+                               bbuf(I, S, dst), gptr(I.edge));
+}
+
 size_t rapply_big_lds_bytes(int P) {
   return 8 * ((size_t)P * 25 + (size_t)P * 64 + (size_t)2 * kRChunk * 64);
 }
 
 #define SG_RAPPLY_BIG_LIST(X) X(4, 4) X(5, 3) X(6, 3)
 
-// the nodal values and, after them, the corner contributions of both components
+// P <= kRSmall: the nodal values and, after them, the corner contributions of
+// both components; above, the layout of rapply_big_tile
 size_t rapply_lds_bytes(int P, int nrows) {
+  if (P > kRSmall) return rapply_big_lds_bytes(P);
   return 8 * std::max((size_t)P * 25, (size_t)2 * nrows * 64);
 }
 
@@ -653,6 +680,19 @@ void launch_brapply(hipStream_t s, int M, int p, size_t lds, const BInst* I, con
                     double beta, double sgn, int gate) {
   if (nitems <= 0) return;
   const int grid = nitems;  // one workgroup per item, as in a single-instance launch
+#define SG_BRAPPLY_BIG_LAUNCH(MM, PP)                                                          \
+  if (M == MM && p == PP) {                                                                    \
+    static const bool attr_ok =                                                                \
+        hipFuncSetAttribute((const void*)brapply_big_kernel<MM, PP>,                           \
+                            hipFuncAttributeMaxDynamicSharedMemorySize,                         \
+                            (int)rapply_big_lds_bytes(rc_binom(MM + PP, PP))) == hipSuccess;   \
+    if (!attr_ok) throw Error(SG_ERR_HIP, "batched register apply: LDS size attribute");      \
+    hipLaunchKernelGGL((brapply_big_kernel<MM, PP>), dim3(grid), dim3(kRThreads), lds, s, I,   \
+                       st, items, nitems, rowset, src, rin, dst, beta, sgn, gate);             \
+    return;                                                                                    \
+  }
+  SG_RAPPLY_BIG_LIST(SG_BRAPPLY_BIG_LAUNCH)
+#undef SG_BRAPPLY_BIG_LAUNCH
 #define SG_BRAPPLY_LAUNCH(MM, PP)                                                             \
   if (M == MM && p == PP) {                                                                   \
     hipLaunchKernelGGL((brapply_kernel<MM, PP>), dim3(grid), dim3(kRThreads), lds, s, I, st, items, \

@@ -22,7 +22,7 @@ PROBS = [
     Problem(n=64, M=2, p=1, q=2, cov="exp_l1", sigma=0.6, corr_len=0.25),
     Problem(n=32, M=4, p=2, q=4, cov="exp_l1", sigma=1.1, corr_len=0.6),
     Problem(n=8, M=2, p=2, q=4, cov="exp_l1", sigma=0.7, corr_len=0.9),
-    # P = 56 modes: factored tile kernel (beyond the register-resident sizes)
+    # P = 56 modes: the register form with its monomials in LDS
     Problem(n=16, M=5, p=3, q=6, cov="exp_l1", sigma=0.5, corr_len=0.7),
 ]
 
@@ -33,17 +33,18 @@ def _make(stream_obj, autotune=False):
     return sg.Batch(probs, f_nodal=fs, restart=20, autotune=autotune, stream=stream_obj), fs
 
 
-@pytest.mark.parametrize("form", ["auto", "triple"])
+@pytest.mark.parametrize("form,qb", [("auto", 0), ("factored", 8), ("triple", 0)])
 @pytest.mark.parametrize("pc", ["fs", "mean"])
-def test_batch_matches_single_instance_solves(pc, form):
-    """Every apply form: register-resident and factored-tile instances (auto) or
-    the triple-product sum, batched exactly as the single-instance solver runs it."""
+def test_batch_matches_single_instance_solves(pc, form, qb):
+    """Every apply form: register-resident (auto), factored LDS tiles of 8 points
+    per sub-batch, or the triple-product sum, batched exactly as the
+    single-instance solver runs it."""
     need_gpu()
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         B, fs = _make(stream)
         for i in range(len(PROBS)):
-            sg.sg_set_apply(B.handle(i), form, 0, stream)
+            sg.sg_set_apply(B.handle(i), form, qb, stream)
         F = B.rhs()
         u, infos = B.solve(F, pc=pc, grouping="klvar", tol=1e-8)
         torch.cuda.synchronize()
@@ -51,7 +52,7 @@ def test_batch_matches_single_instance_solves(pc, form):
         for i, p in enumerate(PROBS):
             inst = sg.SGInstance(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma, p.corr_len, p.a_min,
                                  f_nodal=fs[i], stream=stream)
-            inst.set_apply(form)
+            inst.set_apply(form, qb)
             Fi = inst.rhs()
             ui, info, _ = inst.solve(Fi, pc=pc, grouping="klvar", restart=20, tol=1e-8)
             torch.cuda.synchronize()
