@@ -394,6 +394,7 @@ __global__ __launch_bounds__(kRThreads) void brapply_kernel(const BInst* __restr
 // kRChunk, their corner contributions reduced to node sums chunk by chunk.
 // ---------------------------------------------------------------------------
 constexpr int kRChunk = 16;
+constexpr int kRFence = 4;  // whole operator: step-2 rows scheduled together between fences
 
 template <int M, int p, bool FULL>
 __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, double mu,
@@ -416,15 +417,17 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
   const int comp = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int m = n - 1;
   const int64_t Nq = (int64_t)4 * n * n;
-  // the masks stay run-time values even for the full set (compile-time ones
-  // let the scheduler hoist the monomial reads and spill); they are read once
-  // into uniform registers, not per test, where the compiler would narrow each
-  // test to an unaligned vector load of the descriptor
+  // The column and gamma masks stay run-time values even for the whole
+  // operator: known, they let the compiler move step-1 arithmetic into step 2
+  // and spill.  Only the row side (step 2) is compile-time there, so its rows
+  // carry no branches and can be scheduled a few at a time.  The masks are read
+  // once into uniform registers, not per test, where the compiler would narrow
+  // each test to an unaligned vector load of the descriptor.
   const uint64_t cm[2] = {rr.colmask[0], rr.colmask[1]};
   const uint64_t rm[2] = {rr.rowmask[0], rr.rowmask[1]};
   const uint64_t gmk[2] = {rr.gammask[0], rr.gammask[1]};
   auto col = [&](int a) { return rbit(cm, a); };
-  auto row = [&](int b) { return rbit(rm, b); };
+  auto row = [&](int b) { return FULL || rbit(rm, b); };
 
   // 1. nodal values of the column modes (all loads in flight at once)
   constexpr int NL = (P * 25 + kRThreads - 1) / kRThreads;
@@ -494,6 +497,16 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
     gp[k] = comp ? 0.25 * (ay ? 1.0 : -1.0) * (ax ? xi : 1.0 - xi)
                  : 0.25 * (ax ? 1.0 : -1.0) * (ay ? eta : 1.0 - eta);
   }
+  // the a_min term re-reads the nodal values through offsets the compiler
+  // cannot equate with those of the gradient loop (else it keeps all P
+  // unscaled gradients alive through step 1)
+  int opq = 0;
+  asm volatile("" : "+v"(opq));
+  const int pA = oA + opq, pB = oB + opq, pC = oC + opq, pD = oD + opq;
+  auto grad2 = [&](int a) {
+    const double* u = sN + a * 25;
+    return w0 * (u[pB] - u[pA]) + w1 * (u[pD] - u[pC]);
+  };
   double* sCc = sC + comp * kRChunk * 64;
   const double* sCy = sC + kRChunk * 64;
 #pragma unroll
@@ -505,11 +518,11 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
 #pragma unroll
       for (int t = T.p2[b]; t < T.p2[b + 1]; ++t) sx = fma(sM[T.d2[t] * 64 + lane], G[T.g2[t]], sx);
       double f = (T.s[b] * w) * sx;
-      if (col(b)) f = fma(a_min, grad(b), f);
+      if (FULL || col(b)) f = fma(a_min, grad2(b), f);
       const double k0 = gp[0] * f + quad_xor<2>(gp[2] * f);
       const double k1 = gp[1] * f + quad_xor<2>(gp[3] * f);
       sCc[(b - b0) * 64 + lane] = k0 + quad_xor<1>(k1);
-      __builtin_amdgcn_sched_barrier(0);
+      if (!FULL || b % kRFence == kRFence - 1) __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
     // node sums of the chunk's rows: corner 3 of (x-1, y-1), 2 of (x, y-1),
