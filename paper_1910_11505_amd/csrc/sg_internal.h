@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -139,6 +140,7 @@ struct RApplyRows {
   signed char slot[kRMax];
   unsigned char mode[kRMax];
 };
+static_assert(offsetof(RApplyRows, slot) % 4 == 0, "slot table read as 32-bit words");
 __host__ __device__ inline bool rbit(const uint64_t (&m)[2], int i) {
   return ((m[i >> 6] >> (i & 63)) & 1) != 0;
 }

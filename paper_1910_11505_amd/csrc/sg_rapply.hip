@@ -190,6 +190,28 @@ __device__ __forceinline__ double quad_xor(double v) {
 
 constexpr int kRThreads = 128;  // two wavefronts per tile
 
+// Quadrature point, within its element, carried by a lane of wavefront c: lane
+// bit 0 is the xi index and bit 1 the eta index for c = 0, the other way round
+// for c = 1.  The contribution of a point's flux f to corner (ax, ay) of its
+// element is s E f / 4, with (component x) s = -1, +1 for ax = 0, 1 and E =
+// 1 - eta, eta for ay = 0, 1 (component y: x and y swapped), so a corner sum
+// is a sign times one of two partial sums.  With this lane order both
+// components build the partial sum with the lane two apart and apply the sign
+// difference with the neighbour lane.
+__device__ __forceinline__ int r_lane_qp(int lane, int comp) {
+  const int q = lane & 3;
+  return comp ? ((q & 1) << 1) | (q >> 1) : q;
+}
+// weights of a lane's flux: wc for the corner the lane ends up holding, wo for
+// the one its partner two apart holds
+__device__ __forceinline__ void r_corner_weights(int comp, int ql, double xi, double eta,
+                                                 double& wc, double& wo) {
+  const int qx = ql & 1, qy = ql >> 1;
+  const double s4 = 0.25 * ((comp ? qy : qx) ? 1.0 : -1.0);
+  wc = s4 * (comp ? (qx ? xi : 1.0 - xi) : (qy ? eta : 1.0 - eta));
+  wo = s4 * (comp ? (qx ? 1.0 - xi : xi) : (qy ? 1.0 - eta : eta));
+}
+
 // FULL: every mode is a row and a column, in order (the whole operator); the
 // masks and slot tables are then compile-time constants.
 template <int M, int p, bool FULL = false>
@@ -211,11 +233,20 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
   const int x0 = tx * kTileE, y0 = ty * kTileE;
   const int tid = threadIdx.x, lane = tid & 63;
   const int comp = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int qp = r_lane_qp(lane, comp), pt = (lane & ~3) | qp;  // the lane's Gauss point
   const int m = n - 1;
   const int64_t Nq = (int64_t)4 * n * n;
   // (the column and gamma masks stay run-time values: known, the unrolled
   // gradient and step-1 code is scheduled with more values live than fit)
   const uint64_t colmask = rr.colmask[0], rowmask = FULL ? kAll : rr.rowmask[0];
+  // output slot of each row, read once as whole words (uniform registers)
+  uint32_t slotw[(P + 3) / 4];
+#pragma unroll
+  for (int k = 0; k < (P + 3) / 4; ++k)
+    slotw[k] = FULL ? 0u : reinterpret_cast<const uint32_t*>(rr.slot)[k];
+  auto slot_of = [&](int b) {
+    return FULL ? b : (int)(signed char)(slotw[b >> 2] >> (8 * (b & 3)));
+  };
 
   // 1. nodal values of the column modes (all loads in flight at once)
   constexpr int NL = (P * 25 + kRThreads - 1) / kRThreads;
@@ -230,7 +261,7 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
   }
   double gv[M];
 #pragma unroll
-  for (int nn = 0; nn < M; ++nn) gv[nn] = g[(int64_t)nn * Nq + (int64_t)tile * kTileQ + lane];
+  for (int nn = 0; nn < M; ++nn) gv[nn] = g[(int64_t)nn * Nq + (int64_t)tile * kTileQ + pt];
 #pragma unroll
   for (int u = 0; u < NL; ++u)
     if (tid + kRThreads * u < P * 25) sN[tid + kRThreads * u] = v[u];
@@ -239,7 +270,7 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
   // 2. gradient component c, w, monomials.  Component c of grad u at (xi, eta)
   // is w0 (u_B - u_A) + w1 (u_D - u_C) over the element's corners:
   //   x: (1 - eta)(u10 - u00) + eta (u11 - u01),  y: (1 - xi)(u01 - u00) + xi (u11 - u10)
-  const int el = lane >> 2, ql = lane & 3;
+  const int el = lane >> 2, ql = qp;
   const int ex = el & 3, ey = el >> 2;
   const double xi = r_gauss_pt(ql & 1), eta = r_gauss_pt(ql >> 1);
   const int o00 = ey * 5 + ex, o10 = o00 + 1, o01 = o00 + 5, o11 = o00 + 6;
@@ -282,16 +313,11 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
   // keep the scheduler from interleaving the phases (register pressure)
   __builtin_amdgcn_sched_barrier(0);
 
-  // 4. step 2 and the corner contributions of every output row.  Slot k of a
-  // lane holds the contribution to corner ql ^ k of its element, so the
-  // reduce-scatter (pairs two apart, then neighbours) needs no selects.
-  double gp[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int a4 = ql ^ k, ax = a4 & 1, ay = a4 >> 1;
-    gp[k] = comp ? 0.25 * (ay ? 1.0 : -1.0) * (ax ? xi : 1.0 - xi)
-                 : 0.25 * (ax ? 1.0 : -1.0) * (ay ? eta : 1.0 - eta);
-  }
+  // 4. step 2 and the corner contributions of every output row: the partial
+  // sum with the lane two apart, then the signed sum with the neighbour lane
+  // (see r_lane_qp); lane j of an element ends with its corner r_lane_qp(j, c)
+  double wc, wo;
+  r_corner_weights(comp, ql, xi, eta, wc, wo);
   double* sCc = sC + comp * nrows * 64;
 #pragma unroll
   for (int b = 0; b < P; ++b) {
@@ -301,16 +327,15 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
     for (int t = T.p2[b]; t < T.p2[b + 1]; ++t) sx = fma(mono[T.d2[t]], G[T.g2[t]], sx);
     const double sr = T.s[b] * w;
     double f = sr * sx;
-    if ((colmask >> b) & 1) f = fma(a_min, Gc[b], f);
-    const double k0 = gp[0] * f + quad_xor<2>(gp[2] * f);
-    const double k1 = gp[1] * f + quad_xor<2>(gp[3] * f);
-    sCc[(FULL ? b : rr.slot[b]) * 64 + lane] = k0 + quad_xor<1>(k1);
+    if (FULL || ((colmask >> b) & 1)) f = fma(a_min, Gc[b], f);
+    const double t = wc * f + quad_xor<2>(wo * f);
+    sCc[slot_of(b) * 64 + lane] = t - quad_xor<1>(t);
     __builtin_amdgcn_sched_barrier(0);
   }
   __syncthreads();
 
   // 5. node sums: corner 3 of (x-1, y-1), 2 of (x, y-1), 1 of (x-1, y), 0 of (x, y),
-  // each the x part plus the y part
+  // each the x part plus the y part (whose lanes hold corners 1 and 2 swapped)
   for (int idx = tid; idx < nrows * 25; idx += kRThreads) {
     const int slot = idx / 25, nd = idx - slot * 25;
     const int nx = nd % 5, ny = nd / 5;
@@ -318,16 +343,16 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
     const double* cy = c + nrows * 64;
     double sum = 0.0;
     if (nx >= 1 && ny >= 1) {
-      const int i = ((ny - 1) * 4 + nx - 1) * 4 + 3;
-      sum += c[i] + cy[i];
+      const int i = ((ny - 1) * 4 + nx - 1) * 4;
+      sum += c[i + 3] + cy[i + 3];
     }
     if (nx <= 3 && ny >= 1) {
-      const int i = ((ny - 1) * 4 + nx) * 4 + 2;
-      sum += c[i] + cy[i];
+      const int i = ((ny - 1) * 4 + nx) * 4;
+      sum += c[i + 2] + cy[i + 1];
     }
     if (nx >= 1 && ny <= 3) {
-      const int i = (ny * 4 + nx - 1) * 4 + 1;
-      sum += c[i] + cy[i];
+      const int i = (ny * 4 + nx - 1) * 4;
+      sum += c[i + 1] + cy[i + 2];
     }
     if (nx <= 3 && ny <= 3) {
       const int i = (ny * 4 + nx) * 4;
@@ -377,8 +402,9 @@ __global__ __launch_bounds__(kRThreads) void brapply_kernel(const BInst* __restr
     const BInst& I = Is[w.inst];
     const BState& S = Ss[w.inst];
     if (gated(S, gate)) return;
-    // a copy, so the tile code reads the descriptor from registers, not memory
-    const RApplyRows rr = rowset == 0 ? I.rfull : I.rpart[rowset];
+    // read in place: the tile code loads the masks and slot words once into
+    // uniform registers, the mode table only in the node sums
+    const RApplyRows& rr = rowset == 0 ? I.rfull : I.rpart[rowset];
     rapply_tile<M, p>(smem, w.local, I.n, I.mu, I.amin, gptr(I.gq), rr, bbuf(I, S, src), I.Nh,
                       rin >= 0 ? bbuf(I, S, rin) : nullptr, beta, sgn, bbuf(I, S, dst),
                       gptr(I.edge));
@@ -415,6 +441,7 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
   const int x0 = tx * kTileE, y0 = ty * kTileE;
   const int tid = threadIdx.x, lane = tid & 63;
   const int comp = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int qp = r_lane_qp(lane, comp), pt = (lane & ~3) | qp;  // the lane's Gauss point
   const int m = n - 1;
   const int64_t Nq = (int64_t)4 * n * n;
   // The column and gamma masks stay run-time values even for the whole
@@ -442,7 +469,7 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
   }
   double gv[M];
 #pragma unroll
-  for (int nn = 0; nn < M; ++nn) gv[nn] = g[(int64_t)nn * Nq + (int64_t)tile * kTileQ + lane];
+  for (int nn = 0; nn < M; ++nn) gv[nn] = g[(int64_t)nn * Nq + (int64_t)tile * kTileQ + pt];
 #pragma unroll
   for (int u = 0; u < NL; ++u)
     if (tid + kRThreads * u < P * 25) sN[tid + kRThreads * u] = v[u];
@@ -456,10 +483,10 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
     for (int d = 1; d < P; ++d) mono[d] = mono[T.par[d]] * gv[T.var[d]] * T.inv[d];
 #pragma unroll
     for (int d = 0; d < P; ++d)
-      if ((d & 1) == comp) sM[d * 64 + lane] = mono[d];
+      if ((d & 1) == comp) sM[d * 64 + pt] = mono[d];
   }
   __syncthreads();
-  const int el = lane >> 2, ql = lane & 3;
+  const int el = lane >> 2, ql = qp;
   const int ex = el & 3, ey = el >> 2;
   const double xi = r_gauss_pt(ql & 1), eta = r_gauss_pt(ql >> 1);
   const int o00 = ey * 5 + ex, o10 = o00 + 1, o01 = o00 + 5, o11 = o00 + 6;
@@ -483,20 +510,15 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
     if (!rbit(gmk, gm)) continue;
     double sx = 0.0;
 #pragma unroll
-    for (int t = T.p1[gm]; t < T.p1[gm + 1]; ++t) sx = fma(sM[T.d1[t] * 64 + lane], G[T.a1[t]], sx);
+    for (int t = T.p1[gm]; t < T.p1[gm + 1]; ++t) sx = fma(sM[T.d1[t] * 64 + pt], G[T.a1[t]], sx);
     G[gm] = sx * T.is2[gm];
   }
   __builtin_amdgcn_sched_barrier(0);
 
-  // 4. step 2 by chunks of rows; slot k of a lane holds the contribution to
-  // corner ql ^ k (see rapply_tile); after each chunk the node sums
-  double gp[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int a4 = ql ^ k, ax = a4 & 1, ay = a4 >> 1;
-    gp[k] = comp ? 0.25 * (ay ? 1.0 : -1.0) * (ax ? xi : 1.0 - xi)
-                 : 0.25 * (ax ? 1.0 : -1.0) * (ay ? eta : 1.0 - eta);
-  }
+  // 4. step 2 by chunks of rows, corner sums as in rapply_tile; after each
+  // chunk the node sums
+  double wc, wo;
+  r_corner_weights(comp, ql, xi, eta, wc, wo);
   // the a_min term re-reads the nodal values through offsets the compiler
   // cannot equate with those of the gradient loop (else it keeps all P
   // unscaled gradients alive through step 1)
@@ -516,12 +538,11 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
       if (!row(b)) continue;
       double sx = 0.0;
 #pragma unroll
-      for (int t = T.p2[b]; t < T.p2[b + 1]; ++t) sx = fma(sM[T.d2[t] * 64 + lane], G[T.g2[t]], sx);
+      for (int t = T.p2[b]; t < T.p2[b + 1]; ++t) sx = fma(sM[T.d2[t] * 64 + pt], G[T.g2[t]], sx);
       double f = (T.s[b] * w) * sx;
       if (FULL || col(b)) f = fma(a_min, grad2(b), f);
-      const double k0 = gp[0] * f + quad_xor<2>(gp[2] * f);
-      const double k1 = gp[1] * f + quad_xor<2>(gp[3] * f);
-      sCc[(b - b0) * 64 + lane] = k0 + quad_xor<1>(k1);
+      const double t = wc * f + quad_xor<2>(wo * f);
+      sCc[(b - b0) * 64 + lane] = t - quad_xor<1>(t);
       if (!FULL || b % kRFence == kRFence - 1) __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
@@ -536,16 +557,16 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
       const double* cy = sCy + bl * 64;
       double sum = 0.0;
       if (nx >= 1 && ny >= 1) {
-        const int i = ((ny - 1) * 4 + nx - 1) * 4 + 3;
-        sum += c[i] + cy[i];
+        const int i = ((ny - 1) * 4 + nx - 1) * 4;
+        sum += c[i + 3] + cy[i + 3];
       }
       if (nx <= 3 && ny >= 1) {
-        const int i = ((ny - 1) * 4 + nx) * 4 + 2;
-        sum += c[i] + cy[i];
+        const int i = ((ny - 1) * 4 + nx) * 4;
+        sum += c[i + 2] + cy[i + 1];
       }
       if (nx >= 1 && ny <= 3) {
-        const int i = (ny * 4 + nx - 1) * 4 + 1;
-        sum += c[i] + cy[i];
+        const int i = (ny * 4 + nx - 1) * 4;
+        sum += c[i + 1] + cy[i + 2];
       }
       if (nx <= 3 && ny <= 3) {
         const int i = (ny * 4 + nx) * 4;
