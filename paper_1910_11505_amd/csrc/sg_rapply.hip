@@ -212,6 +212,41 @@ __device__ __forceinline__ void r_corner_weights(int comp, int ql, double xi, do
   wo = s4 * (comp ? (qx ? 1.0 - xi : xi) : (qy ? 1.0 - eta : eta));
 }
 
+// One of a tile's 25 nodes in the node sums: the lanes of the corner slots it
+// adds (corner 3 of element (x-1, y-1), 2 of (x, y-1), 1 of (x-1, y), 0 of
+// (x, y); -1 where the element lies outside the tile; the y part holds corners
+// 1 and 2 swapped, see r_lane_qp), and where the sum goes: an owned node of
+// the output, or a right/top edge or corner value of the edge buffer.
+struct RNode {
+  int i3, i2, i1, i0;
+  bool owned, write;
+  int64_t node;
+  int e;
+};
+__device__ __forceinline__ RNode r_node(int nd, int x0, int y0, int m) {
+  const int nx = nd % 5, ny = nd / 5;
+  RNode q;
+  q.i3 = nx >= 1 && ny >= 1 ? ((ny - 1) * 4 + nx - 1) * 4 + 3 : -1;
+  q.i2 = nx <= 3 && ny >= 1 ? ((ny - 1) * 4 + nx) * 4 + 2 : -1;
+  q.i1 = nx >= 1 && ny <= 3 ? (ny * 4 + nx - 1) * 4 + 1 : -1;
+  q.i0 = nx <= 3 && ny <= 3 ? (ny * 4 + nx) * 4 : -1;
+  q.owned = nx <= 3 && ny <= 3;
+  const int gx = x0 + nx, gy = y0 + ny;
+  q.write = q.owned && gx >= 1 && gy >= 1;
+  q.node = (int64_t)(gy - 1) * m + (gx - 1);
+  q.e = (nx == 4 && ny == 4) ? 8 : (nx == 4 ? ny : 4 + nx);
+  return q;
+}
+// the node's sum over its corners in a fixed order, each the x part plus the y part
+__device__ __forceinline__ double r_node_sum(const RNode& q, const double* c, const double* cy) {
+  double sum = 0.0;
+  if (q.i3 >= 0) sum += c[q.i3] + cy[q.i3];
+  if (q.i2 >= 0) sum += c[q.i2] + cy[q.i2 - 1];
+  if (q.i1 >= 0) sum += c[q.i1] + cy[q.i1 + 1];
+  if (q.i0 >= 0) sum += c[q.i0] + cy[q.i0];
+  return sum;
+}
+
 // FULL: every mode is a row and a column, in order (the whole operator); the
 // masks and slot tables are then compile-time constants.
 template <int M, int p, bool FULL = false>
@@ -277,12 +312,10 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
   const int oA = o00, oB = comp ? o01 : o10, oC = comp ? o10 : o01, oD = o11;
   const double w0 = comp ? 1.0 - xi : 1.0 - eta, w1 = comp ? xi : eta;
   double G[P], Gc[P];  // Gc: unscaled component, for the a_min term of column rows
+  // no test of the column mask: the nodal values of other modes were stored as
+  // zeros, so their gradients are zero, and no branch separates the modes' reads
 #pragma unroll
   for (int a = 0; a < P; ++a) {
-    if (!((colmask >> a) & 1)) {  // not a column of this block
-      G[a] = Gc[a] = 0.0;
-      continue;
-    }
     const double* u = sN + a * 25;
     const double d = w0 * (u[oB] - u[oA]) + w1 * (u[oD] - u[oC]);
     G[a] = T.s[a] * d;
@@ -334,41 +367,22 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
   }
   __syncthreads();
 
-  // 5. node sums: corner 3 of (x-1, y-1), 2 of (x, y-1), 1 of (x-1, y), 0 of (x, y),
-  // each the x part plus the y part (whose lanes hold corners 1 and 2 swapped)
-  for (int idx = tid; idx < nrows * 25; idx += kRThreads) {
-    const int slot = idx / 25, nd = idx - slot * 25;
-    const int nx = nd % 5, ny = nd / 5;
-    const double* c = sC + slot * 64;
-    const double* cy = c + nrows * 64;
-    double sum = 0.0;
-    if (nx >= 1 && ny >= 1) {
-      const int i = ((ny - 1) * 4 + nx - 1) * 4;
-      sum += c[i + 3] + cy[i + 3];
-    }
-    if (nx <= 3 && ny >= 1) {
-      const int i = ((ny - 1) * 4 + nx) * 4;
-      sum += c[i + 2] + cy[i + 1];
-    }
-    if (nx >= 1 && ny <= 3) {
-      const int i = (ny * 4 + nx - 1) * 4;
-      sum += c[i + 1] + cy[i + 2];
-    }
-    if (nx <= 3 && ny <= 3) {
-      const int i = (ny * 4 + nx) * 4;
-      sum += c[i] + cy[i];
-    }
-    if (nx <= 3 && ny <= 3) {
-      const int gx = x0 + nx, gy = y0 + ny;
-      if (gx >= 1 && gy >= 1) {
-        const int64_t node = (int64_t)(gy - 1) * m + (gx - 1);
-        double base = 0.0;
-        if (beta != 0.0) base = beta * rin[(int64_t)(FULL ? slot : rr.mode[slot]) * Nh + node];
-        out[(int64_t)slot * Nh + node] = base + sgn * sum;
+  // 5. node sums: thread t takes node t % 25 of slots t / 25, t / 25 + 5, ...
+  // (threads 125-127 have none), so a node's geometry is worked out once
+  if (tid < 125) {
+    const RNode q = r_node(tid % 25, x0, y0, m);
+    for (int slot = tid / 25; slot < nrows; slot += 5) {
+      const double* c = sC + slot * 64;
+      const double sum = r_node_sum(q, c, c + nrows * 64);
+      if (q.owned) {
+        if (q.write) {
+          double base = 0.0;
+          if (beta != 0.0) base = beta * rin[(int64_t)(FULL ? slot : rr.mode[slot]) * Nh + q.node];
+          out[(int64_t)slot * Nh + q.node] = base + sgn * sum;
+        }
+      } else {
+        edge[((int64_t)slot * ntiles + tile) * kEdgeVals + q.e] = sum;
       }
-    } else {
-      const int e = (nx == 4 && ny == 4) ? 8 : (nx == 4 ? ny : 4 + nx);
-      edge[((int64_t)slot * ntiles + tile) * kEdgeVals + e] = sum;
     }
   }
 }
@@ -531,6 +545,7 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
   };
   double* sCc = sC + comp * kRChunk * 64;
   const double* sCy = sC + kRChunk * 64;
+  const RNode nq = r_node(tid % 25, x0, y0, m);
 #pragma unroll
   for (int b0 = 0; b0 < P; b0 += kRChunk) {
 #pragma unroll
@@ -546,45 +561,24 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
       if (!FULL || b % kRFence == kRFence - 1) __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
-    // node sums of the chunk's rows: corner 3 of (x-1, y-1), 2 of (x, y-1),
-    // 1 of (x-1, y), 0 of (x, y), each the x part plus the y part
-    for (int idx = tid; idx < kRChunk * 25; idx += kRThreads) {
-      const int bl = idx / 25, nd = idx - bl * 25, b = b0 + bl;
-      if (b >= P || !row(b)) continue;
-      const int slot = FULL ? b : rr.slot[b];
-      const int nx = nd % 5, ny = nd / 5;
-      const double* c = sC + bl * 64;
-      const double* cy = sCy + bl * 64;
-      double sum = 0.0;
-      if (nx >= 1 && ny >= 1) {
-        const int i = ((ny - 1) * 4 + nx - 1) * 4;
-        sum += c[i + 3] + cy[i + 3];
-      }
-      if (nx <= 3 && ny >= 1) {
-        const int i = ((ny - 1) * 4 + nx) * 4;
-        sum += c[i + 2] + cy[i + 1];
-      }
-      if (nx >= 1 && ny <= 3) {
-        const int i = (ny * 4 + nx - 1) * 4;
-        sum += c[i + 1] + cy[i + 2];
-      }
-      if (nx <= 3 && ny <= 3) {
-        const int i = (ny * 4 + nx) * 4;
-        sum += c[i] + cy[i];
-      }
-      if (nx <= 3 && ny <= 3) {
-        const int gx = x0 + nx, gy = y0 + ny;
-        if (gx >= 1 && gy >= 1) {
-          const int64_t node = (int64_t)(gy - 1) * m + (gx - 1);
-          double base = 0.0;
-          if (beta != 0.0) base = beta * rin[(int64_t)(FULL ? slot : rr.mode[slot]) * Nh + node];
-          out[(int64_t)slot * Nh + node] = base + sgn * sum;
+    // node sums of the chunk's rows (as in rapply_tile: node tid % 25 of rows
+    // tid / 25, tid / 25 + 5, ... of the chunk)
+    if (tid < 125)
+      for (int bl = tid / 25; bl < kRChunk && b0 + bl < P; bl += 5) {
+        const int b = b0 + bl;
+        if (!row(b)) continue;
+        const int slot = FULL ? b : rr.slot[b];
+        const double sum = r_node_sum(nq, sC + bl * 64, sCy + bl * 64);
+        if (nq.owned) {
+          if (nq.write) {
+            double base = 0.0;
+            if (beta != 0.0) base = beta * rin[(int64_t)(FULL ? slot : rr.mode[slot]) * Nh + nq.node];
+            out[(int64_t)slot * Nh + nq.node] = base + sgn * sum;
+          }
+        } else {
+          edge[((int64_t)slot * ntiles + tile) * kEdgeVals + nq.e] = sum;
         }
-      } else {
-        const int e = (nx == 4 && ny == 4) ? 8 : (nx == 4 ? ny : 4 + nx);
-        edge[((int64_t)slot * ntiles + tile) * kEdgeVals + e] = sum;
       }
-    }
     __syncthreads();  // the next chunk reuses the corner buffer
   }
 }
