@@ -212,6 +212,33 @@ __device__ __forceinline__ void r_corner_weights(int comp, int ql, double xi, do
   wo = s4 * (comp ? (qx ? 1.0 - xi : xi) : (qy ? 1.0 - eta : eta));
 }
 
+// Gradient component c at a lane's Gauss point from one nodal value per lane.
+// Each lane of an element reads the corner (qx, qy) of its own point; in the
+// lane order of r_lane_qp the neighbour lane then holds the other end of the
+// lane's element edge along direction c, and the lane two apart the parallel
+// edge, so with d = u - u[lane ^ 1]
+//   x: (1 - eta)(u10 - u00) + eta (u11 - u01) = ga d + gb d[lane ^ 2]
+//   y: (1 - xi)(u01 - u00) + xi (u11 - u10)   = ga d + gb d[lane ^ 2]
+// with the edge weights and the sign of d folded into ga and gb.
+struct RGrad {
+  int oc;  // the lane's corner in the tile's 5x5 node block
+  double ga, gb;
+};
+__device__ __forceinline__ RGrad r_grad_setup(int comp, int ql, int el, double xi, double eta) {
+  const int qx = ql & 1, qy = ql >> 1;
+  RGrad r;
+  r.oc = (el >> 2) * 5 + (el & 3) + qx + 5 * qy;
+  const double s = (comp ? qy : qx) ? 1.0 : -1.0;
+  r.ga = s * (comp ? (qx ? xi : 1.0 - xi) : (qy ? eta : 1.0 - eta));
+  r.gb = s * (comp ? (qx ? 1.0 - xi : xi) : (qy ? 1.0 - eta : eta));
+  return r;
+}
+__device__ __forceinline__ double r_grad(const RGrad& r, const double* u) {
+  const double v = u[r.oc];
+  const double d = v - quad_xor<1>(v);
+  return r.ga * d + r.gb * quad_xor<2>(d);
+}
+
 // One of a tile's 25 nodes in the node sums: the lanes of the corner slots it
 // adds (corner 3 of element (x-1, y-1), 2 of (x, y-1), 1 of (x-1, y), 0 of
 // (x, y); -1 where the element lies outside the tile; the y part holds corners
@@ -302,22 +329,16 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
     if (tid + kRThreads * u < P * 25) sN[tid + kRThreads * u] = v[u];
   __syncthreads();
 
-  // 2. gradient component c, w, monomials.  Component c of grad u at (xi, eta)
-  // is w0 (u_B - u_A) + w1 (u_D - u_C) over the element's corners:
-  //   x: (1 - eta)(u10 - u00) + eta (u11 - u01),  y: (1 - xi)(u01 - u00) + xi (u11 - u10)
+  // 2. gradient component c (r_grad), w, monomials
   const int el = lane >> 2, ql = qp;
-  const int ex = el & 3, ey = el >> 2;
   const double xi = r_gauss_pt(ql & 1), eta = r_gauss_pt(ql >> 1);
-  const int o00 = ey * 5 + ex, o10 = o00 + 1, o01 = o00 + 5, o11 = o00 + 6;
-  const int oA = o00, oB = comp ? o01 : o10, oC = comp ? o10 : o01, oD = o11;
-  const double w0 = comp ? 1.0 - xi : 1.0 - eta, w1 = comp ? xi : eta;
+  const RGrad rg = r_grad_setup(comp, ql, el, xi, eta);
   double G[P], Gc[P];  // Gc: unscaled component, for the a_min term of column rows
   // no test of the column mask: the nodal values of other modes were stored as
   // zeros, so their gradients are zero, and no branch separates the modes' reads
 #pragma unroll
   for (int a = 0; a < P; ++a) {
-    const double* u = sN + a * 25;
-    const double d = w0 * (u[oB] - u[oA]) + w1 * (u[oD] - u[oC]);
+    const double d = r_grad(rg, sN + a * 25);
     G[a] = T.s[a] * d;
     Gc[a] = d;
   }
@@ -501,18 +522,12 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
   }
   __syncthreads();
   const int el = lane >> 2, ql = qp;
-  const int ex = el & 3, ey = el >> 2;
   const double xi = r_gauss_pt(ql & 1), eta = r_gauss_pt(ql >> 1);
-  const int o00 = ey * 5 + ex, o10 = o00 + 1, o01 = o00 + 5, o11 = o00 + 6;
-  const int oA = o00, oB = comp ? o01 : o10, oC = comp ? o10 : o01, oD = o11;
-  const double w0 = comp ? 1.0 - xi : 1.0 - eta, w1 = comp ? xi : eta;
-  auto grad = [&](int a) {
-    const double* u = sN + a * 25;
-    return w0 * (u[oB] - u[oA]) + w1 * (u[oD] - u[oC]);
-  };
+  const RGrad rg = r_grad_setup(comp, ql, el, xi, eta);
+  // (non-column modes: zero nodal values, zero gradients; no branch)
   double G[P];
 #pragma unroll
-  for (int a = 0; a < P; ++a) G[a] = col(a) ? T.s[a] * grad(a) : 0.0;
+  for (int a = 0; a < P; ++a) G[a] = T.s[a] * r_grad(rg, sN + a * 25);
   double s2 = 0.0;
 #pragma unroll
   for (int nn = 0; nn < M; ++nn) s2 = fma(gv[nn], gv[nn], s2);
@@ -538,11 +553,9 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
   // unscaled gradients alive through step 1)
   int opq = 0;
   asm volatile("" : "+v"(opq));
-  const int pA = oA + opq, pB = oB + opq, pC = oC + opq, pD = oD + opq;
-  auto grad2 = [&](int a) {
-    const double* u = sN + a * 25;
-    return w0 * (u[pB] - u[pA]) + w1 * (u[pD] - u[pC]);
-  };
+  RGrad rg2 = rg;
+  rg2.oc += opq;
+  auto grad2 = [&](int a) { return r_grad(rg2, sN + a * 25); };
   double* sCc = sC + comp * kRChunk * 64;
   const double* sCy = sC + kRChunk * 64;
   const RNode nq = r_node(tid % 25, x0, y0, m);
