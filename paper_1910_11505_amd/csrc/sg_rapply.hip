@@ -264,13 +264,19 @@ __device__ __forceinline__ RNode r_node(int nd, int x0, int y0, int m) {
   q.e = (nx == 4 && ny == 4) ? 8 : (nx == 4 ? ny : 4 + nx);
   return q;
 }
-// the node's sum over its corners in a fixed order, each the x part plus the y part
+// the node's sum over its corners in a fixed order, each the x part plus the y
+// part; all eight reads are issued (absent corners read slot 0 and add +0.0,
+// which leaves the sum's bits unchanged), so they wait once, not per corner
 __device__ __forceinline__ double r_node_sum(const RNode& q, const double* c, const double* cy) {
+  const int j3 = q.i3 >= 0 ? q.i3 : 0, j2 = q.i2 >= 0 ? q.i2 : 1;
+  const int j1 = q.i1 >= 0 ? q.i1 : 0, j0 = q.i0 >= 0 ? q.i0 : 0;
+  const double a3 = c[j3] + cy[j3], a2 = c[j2] + cy[j2 - 1];
+  const double a1 = c[j1] + cy[j1 + 1], a0 = c[j0] + cy[j0];
   double sum = 0.0;
-  if (q.i3 >= 0) sum += c[q.i3] + cy[q.i3];
-  if (q.i2 >= 0) sum += c[q.i2] + cy[q.i2 - 1];
-  if (q.i1 >= 0) sum += c[q.i1] + cy[q.i1 + 1];
-  if (q.i0 >= 0) sum += c[q.i0] + cy[q.i0];
+  sum += q.i3 >= 0 ? a3 : 0.0;
+  sum += q.i2 >= 0 ? a2 : 0.0;
+  sum += q.i1 >= 0 ? a1 : 0.0;
+  sum += q.i0 >= 0 ? a0 : 0.0;
   return sum;
 }
 
@@ -392,7 +398,10 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
   // (threads 125-127 have none), so a node's geometry is worked out once
   if (tid < 125) {
     const RNode q = r_node(tid % 25, x0, y0, m);
-    for (int slot = tid / 25; slot < nrows; slot += 5) {
+#pragma unroll
+    for (int k = 0; k < (P + 4) / 5; ++k) {
+      const int slot = tid / 25 + 5 * k;
+      if (slot >= nrows) break;
       const double* c = sC + slot * 64;
       const double sum = r_node_sum(q, c, c + nrows * 64);
       if (q.owned) {
@@ -577,8 +586,10 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
     // node sums of the chunk's rows (as in rapply_tile: node tid % 25 of rows
     // tid / 25, tid / 25 + 5, ... of the chunk)
     if (tid < 125)
-      for (int bl = tid / 25; bl < kRChunk && b0 + bl < P; bl += 5) {
-        const int b = b0 + bl;
+#pragma unroll
+      for (int k = 0; k < (kRChunk + 4) / 5; ++k) {
+        const int bl = tid / 25 + 5 * k, b = b0 + bl;
+        if (bl >= kRChunk || b >= P) break;
         if (!row(b)) continue;
         const int slot = FULL ? b : rr.slot[b];
         const double sum = r_node_sum(nq, sC + bl * 64, sCy + bl * 64);
