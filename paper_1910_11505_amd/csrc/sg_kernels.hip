@@ -420,11 +420,13 @@ __global__ __launch_bounds__(256) void apply_kernel(int n, int na, const double*
 __device__ __forceinline__ void apply_fixup_item(int64_t gid, int n, double sgn,
                                                  const double* __restrict__ edge,
                                                  double* __restrict__ out, int64_t Nh) {
+  // item counts stay below 2^31 (checked at launch): 32-bit unsigned division
   const int nt = n / kTileE, ntiles = nt * nt, m = n - 1;
-  const int j = (int)(gid % 7);
-  const int64_t rt = gid / 7;
-  const int tile = (int)(rt % ntiles);
-  const int slot = (int)(rt / ntiles);
+  const unsigned g = (unsigned)gid;
+  const int j = (int)(g % 7u);
+  const unsigned rt = g / 7u;
+  const int tile = (int)(rt % (unsigned)ntiles);
+  const int slot = (int)(rt / (unsigned)ntiles);
   const int tx = tile % nt, ty = tile / nt;
   const int nx = j < 4 ? 0 : j - 3;  // (0,0..3) then (1..3,0)
   const int ny = j < 4 ? j : 0;
@@ -451,6 +453,7 @@ void launch_apply_fixup(hipStream_t s, int n, int nrows, double sgn, const doubl
                         double* out, int64_t Nh) {
   const int nt = n / kTileE;
   const int64_t total = (int64_t)nrows * nt * nt * 7;
+  if (total >= (int64_t)1 << 31) throw Error(SG_ERR_UNSUPPORTED, "apply fixup: too many edge values");
   hipLaunchKernelGGL(apply_fixup_kernel, dim3(cdiv(total, 256)), dim3(256), 0, s, n, nrows, sgn,
                      edge, out, Nh);
 }
