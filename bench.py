@@ -37,8 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # scaled by the same counter read on a plain 256 MiB copy (factors 2.0 and 1.0).
 # Valid only for the kernel source the counters were taken on: the sha256 of
 # sg_rapply.hip + sg_internal.h is compared at run time.
-APPLY_TRAFFIC = {"src_sha256": "57a1c9a6302bc037c9155e88e237385f2ff19ff69d02d33e9efc5b901b2e16db",
-                 "fetch_bytes": (3486.5625 + 4831.625) * 1024 * 2.0,
+APPLY_TRAFFIC = {"src_sha256": "d1566cb54004f4b03c6b37e69a75842572093921ae4cd2146ea6ab823738f877",
+                 "fetch_bytes": (3493.0625 + 4827.125) * 1024 * 2.0,
                  "write_bytes": (6937.0 + 4377.4375) * 1024 * 1.0}
 
 
