@@ -457,11 +457,15 @@ __global__ __launch_bounds__(kRThreads) void brapply_kernel(const BInst* __restr
 
 // ---------------------------------------------------------------------------
 // The same operator for larger chaos spaces (35 < P <= 84).  The scaled
-// gradients stay in registers (one component per wavefront, as above); the P
-// monomials of each point move to LDS, lane-major so a wavefront's read of one
-// of them is 64 consecutive doubles; the a_min term is recomputed from the
-// nodal values, which stay in LDS; and the output rows are taken in chunks of
-// kRChunk, their corner contributions reduced to node sums chunk by chunk.
+// gradients stay in registers (one component per wavefront, as above).  Of the
+// monomials only those of degree below p stay in registers: an output gamma of
+// degree d in step 1 needs m_delta with |delta| <= p - d, and a row beta of
+// step 2 needs a degree-p monomial only for its gamma = 0 term, so each
+// degree-p monomial enters one product per step and is formed there from its
+// parent (the same two products, in the same order, as the recurrence).  The
+// a_min term is recomputed from the nodal values, which stay in LDS, and the
+// output rows are taken in chunks of kRChunk, their corner contributions
+// reduced to node sums chunk by chunk.
 // ---------------------------------------------------------------------------
 constexpr int kRChunk = 16;
 constexpr int kRFence = 4;  // whole operator: step-2 rows scheduled together between fences
@@ -477,9 +481,9 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
   constexpr const RTab<M, p>& T = RTabHolder<M, p>::v;
   constexpr int P = RTab<M, p>::P;
   static_assert(P <= kRMax, "two mask words");
+  constexpr int PL = rc_binom(M + p - 1, p - 1);  // monomials of degree below p
   double* sN = smem;            // [P][25] nodal values
-  double* sM = sN + P * 25;     // [P][64] scaled monomials of the tile's points
-  double* sC = sM + P * 64;     // [2][kRChunk][64] corner contributions of a row chunk
+  double* sC = sN + P * 25;     // [2][kRChunk][64] corner contributions of a row chunk
   const int nt = n / kTileE, ntiles = nt * nt;
   const int tx = tile % nt, ty = tile / nt;
   const int x0 = tx * kTileE, y0 = ty * kTileE;
@@ -518,17 +522,13 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
   for (int u = 0; u < NL; ++u)
     if (tid + kRThreads * u < P * 25) sN[tid + kRThreads * u] = v[u];
 
-  // 2. monomials (both wavefronts compute them; wavefront c stores those of
-  // parity c), then gradient component c and w
-  {
-    double mono[P];
-    mono[0] = 1.0;
+  // 2. monomials of degree below p (graded order: the first PL), then
+  // gradient component c and w
+  double mono[PL];
+  mono[0] = 1.0;
 #pragma unroll
-    for (int d = 1; d < P; ++d) mono[d] = mono[T.par[d]] * gv[T.var[d]] * T.inv[d];
-#pragma unroll
-    for (int d = 0; d < P; ++d)
-      if ((d & 1) == comp) sM[d * 64 + pt] = mono[d];
-  }
+  for (int d = 1; d < PL; ++d) mono[d] = mono[T.par[d]] * gv[T.var[d]] * T.inv[d];
+  auto mv = [&](int d) { return d < PL ? mono[d] : mono[T.par[d]] * gv[T.var[d]] * T.inv[d]; };
   __syncthreads();
   const int el = lane >> 2, ql = qp;
   const double xi = r_gauss_pt(ql & 1), eta = r_gauss_pt(ql >> 1);
@@ -548,7 +548,7 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
     if (!rbit(gmk, gm)) continue;
     double sx = 0.0;
 #pragma unroll
-    for (int t = T.p1[gm]; t < T.p1[gm + 1]; ++t) sx = fma(sM[T.d1[t] * 64 + pt], G[T.a1[t]], sx);
+    for (int t = T.p1[gm]; t < T.p1[gm + 1]; ++t) sx = fma(mv(T.d1[t]), G[T.a1[t]], sx);
     G[gm] = sx * T.is2[gm];
   }
   __builtin_amdgcn_sched_barrier(0);
@@ -565,6 +565,15 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
   RGrad rg2 = rg;
   rg2.oc += opq;
   auto grad2 = [&](int a) { return r_grad(rg2, sN + a * 25); };
+  // step 2 forms its degree-p monomials from copies of g that the compiler
+  // cannot equate with g (else it keeps step 1's products alive until step 2)
+  double gv2[M];
+#pragma unroll
+  for (int nn = 0; nn < M; ++nn) {
+    gv2[nn] = gv[nn];
+    asm volatile("" : "+v"(gv2[nn]));
+  }
+  auto mv2 = [&](int d) { return d < PL ? mono[d] : mono[T.par[d]] * gv2[T.var[d]] * T.inv[d]; };
   double* sCc = sC + comp * kRChunk * 64;
   const double* sCy = sC + kRChunk * 64;
   const RNode nq = r_node(tid % 25, x0, y0, m);
@@ -575,7 +584,7 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
       if (!row(b)) continue;
       double sx = 0.0;
 #pragma unroll
-      for (int t = T.p2[b]; t < T.p2[b + 1]; ++t) sx = fma(sM[T.d2[t] * 64 + pt], G[T.g2[t]], sx);
+      for (int t = T.p2[b]; t < T.p2[b + 1]; ++t) sx = fma(mv2(T.d2[t]), G[T.g2[t]], sx);
       double f = (T.s[b] * w) * sx;
       if (FULL || col(b)) f = fma(a_min, grad2(b), f);
       const double t = wc * f + quad_xor<2>(wo * f);
@@ -607,8 +616,11 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
   }
 }
 
+// Two wavefronts per SIMD (four tiles per CU: 33 KB of LDS each at P = 84):
+// at P = 70 and 84 that spills 60-76 bytes per lane, measured faster than one
+// wavefront per SIMD without spills.
 template <int M, int p, bool FULL>
-__global__ __launch_bounds__(kRThreads) void rapply_big_kernel(
+__global__ __launch_bounds__(kRThreads, 2) void rapply_big_kernel(
     int n, double mu, double a_min, const double* __restrict__ g, RApplyRows rr,
     const double* __restrict__ U, int64_t Nh, const double* __restrict__ rin, double beta,
     double sgn, double* __restrict__ out, double* __restrict__ edge) {
@@ -620,7 +632,7 @@ __global__ __launch_bounds__(kRThreads) void rapply_big_kernel(
 
 // (instance, tile) items of instances sharing one (M, p), P > kRSmall
 template <int M, int p>
-__global__ __launch_bounds__(kRThreads) void brapply_big_kernel(
+__global__ __launch_bounds__(kRThreads, 2) void brapply_big_kernel(
     const BInst* __restrict__ Is, const BState* __restrict__ Ss, const BItem* __restrict__ items,
     int nitems, int rowset, int src, int rin, int dst, double beta, double sgn, int gate) {
   extern __shared__ double smem[];
@@ -639,7 +651,7 @@ __global__ __launch_bounds__(kRThreads) void brapply_big_kernel(
 }
 
 size_t rapply_big_lds_bytes(int P) {
-  return 8 * ((size_t)P * 25 + (size_t)P * 64 + (size_t)2 * kRChunk * 64);
+  return 8 * ((size_t)P * 25 + (size_t)2 * kRChunk * 64);
 }
 
 #define SG_RAPPLY_BIG_LIST(X) X(4, 4) X(5, 3) X(6, 3)
