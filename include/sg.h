@@ -153,15 +153,20 @@ int sg_apply(sg_handle* h, const double* U, double* W, void* stream);
 
 /* Chooses the apply form used by sg_apply, sg_residual, the field-split
  * preconditioner and sg_gmres_solve.  points_per_batch (FACTORED only): 0
- * selects the register-resident kernel where it is compiled (chaos spaces of
- * at most 35 modes: M <= 3 with p <= 4, M = 4 with p <= 3, M <= 6 with
- * p <= 2), else the LDS tile kernel with the planner's sub-batch size;
+ * selects the register-resident kernel where it is compiled (every M <= 6
+ * with p <= 4), else the LDS tile kernel with the planner's sub-batch size;
  * 8, 16, 32 or 64 select the LDS tile kernel with that many Gauss points per
  * sub-batch of a 4x4-element tile.  Re-uploads the plan on `stream` when the handle is bound
  * and synchronises it.  Errors: INVALID_ARG (unknown kind or size),
  * UNSUPPORTED (FACTORED with q < 2p, or a size whose LDS exceeds 160 KB; the
  * previous plan stays in place).                                            */
 int sg_set_apply(sg_handle* h, int kind, int points_per_batch, void* stream);
+
+/* The apply form in use (an inspection call for tests and tools): *form = 2
+ * for the register-resident factored kernel, 1 for the factored LDS tile
+ * kernel (*points_per_batch: its Gauss points per sub-batch), 0 for the
+ * triple-product form.  Host only.  Errors: INVALID_ARG (null argument).    */
+int sg_apply_form(const sg_handle* h, int* form, int* points_per_batch);
 
 /* z = P^{-1} r for pc in {SG_PC_NONE, SG_PC_MEAN, SG_PC_FS} and a grouping
  * (Sec. 3, eqs. P_preconditioner / P_group).  r, z: device, P*N_h, must not

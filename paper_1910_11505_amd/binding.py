@@ -71,6 +71,7 @@ def load_library():
         "sg_rhs": (I32, [HP, VP, VP]),
         "sg_apply": (I32, [HP, VP, VP, VP]),
         "sg_set_apply": (I32, [HP, I32, I32, VP]),
+        "sg_apply_form": (I32, [HP, P(ctypes.c_int32), P(ctypes.c_int32)]),
         "sg_precond_apply": (I32, [HP, I32, I32, VP, VP, VP]),
         "sg_gmres_workspace_bytes": (SZ, [HP, P(SolveOpts)]),
         "sg_gmres_solve": (I32, [HP, P(SolveOpts), VP, VP, VP, SZ, VP, ctypes.c_int32,
@@ -176,6 +177,14 @@ def sg_apply(h, U, W, stream=None):
 
 
 APPLY = {"auto": 0, "triple": 1, "factored": 2}
+
+
+def sg_apply_form(h):
+    """(form, points per sub-batch): form 2 register-resident, 1 factored LDS
+    tiles, 0 triple products."""
+    f, q = ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().sg_apply_form(h, ctypes.byref(f), ctypes.byref(q)))
+    return f.value, q.value
 
 
 def sg_set_apply(h, kind="auto", points_per_batch=0, stream=None):
@@ -328,6 +337,10 @@ class SGInstance:
         W = self.vec() if W is None else W
         sg_apply(self.h, U, W, self.stream)
         return W
+
+    def apply_form(self):
+        """(form, points per sub-batch) in use; see sg_apply_form."""
+        return sg_apply_form(self.h)
 
     def set_apply(self, kind="auto", points_per_batch=0):
         """Apply form: "auto" (factored when q >= 2p), "triple" or "factored"."""

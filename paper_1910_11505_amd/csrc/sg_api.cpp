@@ -879,10 +879,10 @@ int setup_impl(const sg_problem* prob, const double* f_nodal, int force_kc, sg_h
       auto rows = [&](const std::vector<int>& outm, const std::vector<int>& colm) {
         RApplyRows r{};
         for (int c : colm) rset(r.colmask, c);
-        std::memset(r.slot, -1, sizeof(r.slot));
+        std::memset(r.slot, 0xFF, sizeof(r.slot));
         for (size_t t = 0; t < outm.size(); ++t) {
           rset(r.rowmask, outm[t]);
-          r.slot[outm[t]] = (signed char)t;
+          r.slot[outm[t]] = (unsigned char)t;
           r.mode[t] = (unsigned char)outm[t];
         }
         r.nrows = (int)outm.size();
@@ -1041,6 +1041,13 @@ int sg_rhs(sg_handle* h, double* F, void* stream) {
   } catch (const Error& e) {
     return fail(e.code, e.what());
   }
+}
+
+int sg_apply_form(const sg_handle* h, int* form, int* points_per_batch) {
+  if (!h || !form || !points_per_batch) return fail(SG_ERR_INVALID_ARG, "null argument");
+  *form = !h->use_factored ? 0 : h->use_rapply ? 2 : 1;
+  *points_per_batch = *form == 1 ? h->ffull.qb : 0;
+  return SG_OK;
 }
 
 int sg_set_apply(sg_handle* h, int kind, int points_per_batch, void* stream) {

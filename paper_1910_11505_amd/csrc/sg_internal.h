@@ -128,23 +128,25 @@ struct FRowSetDev {
   const int* blob;
 };
 
-// Rows of the register-resident factored apply (P <= 35): column modes, output
-// modes and the intermediate gamma set as bit masks over J(p); slot[beta] is
-// the output slot of mode beta (compact output layout), mode[slot] its mode id.
-constexpr int kRMax = 128;  // modes of the register-resident apply (masks of two words)
-constexpr int kRSmall = 35;  // ... whose monomials also stay in registers (above: in LDS)
+// Rows of the register-resident factored apply: column modes, output modes
+// and the intermediate gamma set as bit masks over J(p); slot[beta] is the
+// output slot of mode beta (compact output layout; 0xFF: not an output row),
+// mode[slot] its mode id.
+constexpr int kRMax = 256;            // modes of the register-resident apply
+constexpr int kRMaskW = kRMax / 64;   // mask words
+constexpr int kRSmall = 35;  // ... whose monomials all stay in registers
 struct RApplyRows {
-  uint64_t colmask[2], rowmask[2];
-  uint64_t gammask[2];  // gamma <= some column and <= some output row (step-1 rows that matter)
+  uint64_t colmask[kRMaskW], rowmask[kRMaskW];
+  uint64_t gammask[kRMaskW];  // gamma <= some column and <= some output row (step-1 rows that matter)
   int nrows;
-  signed char slot[kRMax];
+  unsigned char slot[kRMax];
   unsigned char mode[kRMax];
 };
 static_assert(offsetof(RApplyRows, slot) % 4 == 0, "slot table read as 32-bit words");
-__host__ __device__ inline bool rbit(const uint64_t (&m)[2], int i) {
+__host__ __device__ inline bool rbit(const uint64_t (&m)[kRMaskW], int i) {
   return ((m[i >> 6] >> (i & 63)) & 1) != 0;
 }
-__host__ inline void rset(uint64_t (&m)[2], int i) { m[i >> 6] |= uint64_t(1) << (i & 63); }
+__host__ inline void rset(uint64_t (&m)[kRMaskW], int i) { m[i >> 6] |= uint64_t(1) << (i & 63); }
 
 struct Level {
   int n;          // elements per side on this level

@@ -39,6 +39,23 @@ constexpr int rc_binom(int n, int k) {
   return (int)r;
 }
 
+// position of multi-index a in J(p) ordered by degree, descending
+// lexicographic inside a degree: the indices of lower degree, then for each
+// position i those of the same degree that agree before i and are larger at i
+// (compositions of the remainder over the later positions)
+constexpr int rc_rank(const int* a, int M) {
+  int d = 0;
+  for (int n = 0; n < M; ++n) d += a[n];
+  int idx = d == 0 ? 0 : rc_binom(M + d - 1, d - 1);
+  int rem = d;
+  for (int i = 0; i < M - 1; ++i) {
+    const int k = M - i - 1;
+    for (int v = a[i] + 1; v <= rem; ++v) idx += rc_binom(rem - v + k - 1, k - 1);
+    rem -= a[i];
+  }
+  return idx;
+}
+
 template <int M, int p>
 constexpr int rc_pairs() {
   // number of (gamma <= alpha) pairs over J(p): sum over alpha of prod (alpha_n + 1)
@@ -101,14 +118,7 @@ constexpr RTab<M, p> rc_make() {
       for (int n = i + 2; n < M; ++n) cur[n] = 0;
     }
   }
-  auto find = [&](const int* v) {
-    for (int i = 0; i < P; ++i) {
-      bool eq = true;
-      for (int n = 0; n < M; ++n) eq = eq && T.J[i][n] == v[n];
-      if (eq) return i;
-    }
-    return -1;
-  };
+  auto find = [&](const int* v) { return rc_rank(v, M); };
   // sqrt(k!) for k <= 6
   const double sq[7] = {1.0, 1.0, 1.4142135623730951, 2.449489742783178, 4.898979485566356,
                         10.954451150103322, 26.832815729997478};
@@ -168,6 +178,42 @@ constexpr RTab<M, p> rc_make() {
 template <int M, int p>
 struct RTabHolder {
   static constexpr RTab<M, p> v = rc_make<M, p>();
+};
+
+// Step-1 pairs (gamma, delta) of each degree-p mode alpha with gamma of degree
+// below p, grouped by alpha (the pairs of the gamma-grouped table with that
+// alpha, in the same gamma order).
+template <int M, int p>
+struct RTabTop {
+  static constexpr int P = RTab<M, p>::P;
+  static constexpr int PN = rc_binom(M + p - 1, p - 1);  // modes of degree below p
+  static constexpr int NT = RTab<M, p>::NT;
+  int pq[P - PN + 1] = {}, qg[NT] = {}, qd[NT] = {};
+};
+
+template <int M, int p>
+constexpr RTabTop<M, p> rc_make_top() {
+  constexpr const RTab<M, p>& T = RTabHolder<M, p>::v;
+  RTabTop<M, p> Q{};
+  constexpr int P = RTabTop<M, p>::P, PN = RTabTop<M, p>::PN;
+  int k = 0;
+  for (int a = PN; a < P; ++a) {
+    Q.pq[a - PN] = k;
+    for (int gm = 0; gm < PN; ++gm)
+      for (int t = T.p1[gm]; t < T.p1[gm + 1]; ++t)
+        if (T.a1[t] == a) {
+          Q.qg[k] = gm;
+          Q.qd[k] = T.d1[t];
+          ++k;
+        }
+  }
+  Q.pq[P - PN] = k;
+  return Q;
+}
+
+template <int M, int p>
+struct RTabTopHolder {
+  static constexpr RTabTop<M, p> v = rc_make_top<M, p>();
 };
 
 __device__ __forceinline__ double r_gauss_pt(int i) {
@@ -313,7 +359,7 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
   for (int k = 0; k < (P + 3) / 4; ++k)
     slotw[k] = FULL ? 0u : reinterpret_cast<const uint32_t*>(rr.slot)[k];
   auto slot_of = [&](int b) {
-    return FULL ? b : (int)(signed char)(slotw[b >> 2] >> (8 * (b & 3)));
+    return FULL ? b : (int)((slotw[b >> 2] >> (8 * (b & 3))) & 0xFFu);
   };
 
   // 1. nodal values of the column modes (all loads in flight at once)
@@ -480,7 +526,7 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
                                                 double* __restrict__ edge) {
   constexpr const RTab<M, p>& T = RTabHolder<M, p>::v;
   constexpr int P = RTab<M, p>::P;
-  static_assert(P <= kRMax, "two mask words");
+  static_assert(P <= kRMax, "mask words");
   constexpr int PL = rc_binom(M + p - 1, p - 1);  // monomials of degree below p
   double* sN = smem;            // [P][25] nodal values
   double* sC = sN + P * 25;     // [2][kRChunk][64] corner contributions of a row chunk
@@ -498,9 +544,13 @@ __device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, d
   // carry no branches and can be scheduled a few at a time.  The masks are read
   // once into uniform registers, not per test, where the compiler would narrow
   // each test to an unaligned vector load of the descriptor.
-  const uint64_t cm[2] = {rr.colmask[0], rr.colmask[1]};
-  const uint64_t rm[2] = {rr.rowmask[0], rr.rowmask[1]};
-  const uint64_t gmk[2] = {rr.gammask[0], rr.gammask[1]};
+  uint64_t cm[kRMaskW], rm[kRMaskW], gmk[kRMaskW];
+#pragma unroll
+  for (int k = 0; k < kRMaskW; ++k) {
+    cm[k] = rr.colmask[k];
+    rm[k] = rr.rowmask[k];
+    gmk[k] = rr.gammask[k];
+  }
   auto col = [&](int a) { return rbit(cm, a); };
   auto row = [&](int b) { return FULL || rbit(rm, b); };
 
@@ -630,6 +680,213 @@ __global__ __launch_bounds__(kRThreads, 2) void rapply_big_kernel(
                               rin, beta, sgn, out, edge);
 }
 
+// ---------------------------------------------------------------------------
+// The same operator for P = 126 and 210 (p = 4), where even the gradients do
+// not fit a lane.  Only the modes of degree below p keep their gradient (then
+// Vbar) in registers, and only the monomials of degree below p - 1; degree
+// p - 1 and p monomials are formed where used, from their parents.  Step 1
+// first sums the pairs with alpha of degree below p in place, then streams the
+// degree-p modes: each one's gradient is recomputed from the nodal values (one
+// read and two DPP exchanges) and added to every Vbar_gamma below it.  A
+// degree-p gamma's Vbar is its own scaled gradient (only delta = 0), so step 2
+// recomputes it for the row's gamma = beta term.  Node sums as in
+// rapply_big_tile.
+// ---------------------------------------------------------------------------
+template <int M, int p, bool FULL>
+__device__ __forceinline__ void rapply_huge_tile(double* smem, int tile, int n, double mu,
+                                                 double a_min, const double* __restrict__ g,
+                                                 const RApplyRows& rr,
+                                                 const double* __restrict__ U, int64_t Nh,
+                                                 const double* __restrict__ rin, double beta,
+                                                 double sgn, double* __restrict__ out,
+                                                 double* __restrict__ edge) {
+  constexpr const RTab<M, p>& T = RTabHolder<M, p>::v;
+  constexpr const RTabTop<M, p>& Q = RTabTopHolder<M, p>::v;
+  constexpr int P = RTab<M, p>::P;
+  constexpr int PN = RTabTop<M, p>::PN;           // modes of degree below p
+  constexpr int PL = rc_binom(M + p - 2, p - 2);  // monomials of degree below p - 1
+  static_assert(P <= kRMax && p >= 2, "mask words, degree");
+  double* sN = smem;            // [P][25] nodal values
+  double* sC = sN + P * 25;     // [2][kRChunk][64] corner contributions of a row chunk
+  const int nt = n / kTileE, ntiles = nt * nt;
+  const int tx = tile % nt, ty = tile / nt;
+  const int x0 = tx * kTileE, y0 = ty * kTileE;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int comp = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int qp = r_lane_qp(lane, comp), pt = (lane & ~3) | qp;  // the lane's Gauss point
+  const int m = n - 1;
+  const int64_t Nq = (int64_t)4 * n * n;
+  // masks: run-time, read once into uniform registers (see rapply_big_tile);
+  // every gamma is computed (no gamma mask: a Vbar no row reads is harmless)
+  uint64_t cm[kRMaskW], rm[kRMaskW];
+#pragma unroll
+  for (int k = 0; k < kRMaskW; ++k) {
+    cm[k] = rr.colmask[k];
+    rm[k] = rr.rowmask[k];
+  }
+  auto col = [&](int a) { return rbit(cm, a); };
+  auto row = [&](int b) { return FULL || rbit(rm, b); };
+
+  // 1. nodal values of the column modes (zeros elsewhere), in two halves so
+  // that at most half of them are in flight per thread
+  constexpr int NL = (P * 25 + kRThreads - 1) / kRThreads;
+  constexpr int NLH = (NL + 1) / 2;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    double v[NLH];
+#pragma unroll
+    for (int u = 0; u < NLH; ++u) {
+      const int idx = tid + kRThreads * (h * NLH + u);
+      const int c = min(idx / 25, P - 1), nd = idx - (idx / 25) * 25;
+      const int gx = x0 + nd % 5, gy = y0 + nd / 5;
+      const bool ok = idx < P * 25 && col(c) && gx >= 1 && gx <= m && gy >= 1 && gy <= m;
+      v[u] = ok ? U[(int64_t)c * Nh + (int64_t)(gy - 1) * m + (gx - 1)] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < NLH; ++u) {
+      const int idx = tid + kRThreads * (h * NLH + u);
+      if (idx < P * 25) sN[idx] = v[u];
+    }
+  }
+  double gv[M];
+#pragma unroll
+  for (int nn = 0; nn < M; ++nn) gv[nn] = g[(int64_t)nn * Nq + (int64_t)tile * kTileQ + pt];
+
+  // 2. monomials of degree below p - 1 (graded order: the first PL); degree
+  // p - 1 (indices PL .. PN-1) and p (PN ..) formed from their parents, the
+  // same products in the same order as the recurrence
+  double mono[PL];
+  mono[0] = 1.0;
+#pragma unroll
+  for (int d = 1; d < PL; ++d) mono[d] = mono[T.par[d]] * gv[T.var[d]] * T.inv[d];
+  auto mono_of = [&](int d, const double* gg) {
+    if (d < PL) return mono[d];
+    if (d < PN) return mono[T.par[d]] * gg[T.var[d]] * T.inv[d];
+    const int q = T.par[d];
+    return mono[T.par[q]] * gg[T.var[q]] * T.inv[q] * gg[T.var[d]] * T.inv[d];
+  };
+  __syncthreads();
+  const int el = lane >> 2, ql = qp;
+  const double xi = r_gauss_pt(ql & 1), eta = r_gauss_pt(ql >> 1);
+  const RGrad rg = r_grad_setup(comp, ql, el, xi, eta);
+  double G[PN];
+#pragma unroll
+  for (int a = 0; a < PN; ++a) G[a] = T.s[a] * r_grad(rg, sN + a * 25);
+  double s2 = 0.0;
+#pragma unroll
+  for (int nn = 0; nn < M; ++nn) s2 = fma(gv[nn], gv[nn], s2);
+  const double w = exp(mu + 0.5 * s2);
+
+  // 3a. step 1 over the pairs with alpha of degree below p, in place (unscaled)
+#pragma unroll
+  for (int gm = 0; gm < PN; ++gm) {
+    double sx = 0.0;
+#pragma unroll
+    for (int t = T.p1[gm]; t < T.p1[gm + 1]; ++t)
+      if (T.a1[t] < PN) sx = fma(mono_of(T.d1[t], gv), G[T.a1[t]], sx);
+    G[gm] = sx;
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // 3b. the degree-p modes, one at a time
+#pragma unroll
+  for (int a = PN; a < P; ++a) {
+    const double ga = T.s[a] * r_grad(rg, sN + a * 25);
+#pragma unroll
+    for (int k = Q.pq[a - PN]; k < Q.pq[a - PN + 1]; ++k)
+      G[Q.qg[k]] = fma(mono_of(Q.qd[k], gv), ga, G[Q.qg[k]]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int gm = 0; gm < PN; ++gm) G[gm] *= T.is2[gm];
+
+  // 4. step 2 by chunks of rows, corner sums and node sums as in rapply_big_tile
+  double wc, wo;
+  r_corner_weights(comp, ql, xi, eta, wc, wo);
+  int opq = 0;
+  asm volatile("" : "+v"(opq));
+  RGrad rg2 = rg;
+  rg2.oc += opq;
+  double gv2[M];
+#pragma unroll
+  for (int nn = 0; nn < M; ++nn) {
+    gv2[nn] = gv[nn];
+    asm volatile("" : "+v"(gv2[nn]));
+  }
+  double* sCc = sC + comp * kRChunk * 64;
+  const double* sCy = sC + kRChunk * 64;
+  const RNode nq = r_node(tid % 25, x0, y0, m);
+#pragma unroll
+  for (int b0 = 0; b0 < P; b0 += kRChunk) {
+#pragma unroll
+    for (int b = b0; b < (b0 + kRChunk < P ? b0 + kRChunk : P); ++b) {
+      if (!row(b)) continue;
+      double sx = 0.0;
+#pragma unroll
+      for (int t = T.p2[b]; t < T.p2[b + 1]; ++t)
+        if (T.g2[t] < PN) sx = fma(mono_of(T.d2[t], gv2), G[T.g2[t]], sx);
+      // the unscaled gradient of the row's mode: the a_min term, and for a
+      // degree-p row its own Vbar (gamma = beta, the list's last pair)
+      const double db = r_grad(rg2, sN + b * 25);
+      if (b >= PN) sx += (T.is2[b] * T.s[b]) * db;
+      double f = (T.s[b] * w) * sx;
+      if (FULL || col(b)) f = fma(a_min, db, f);
+      const double t = wc * f + quad_xor<2>(wo * f);
+      sCc[(b - b0) * 64 + lane] = t - quad_xor<1>(t);
+      if (!FULL || b % kRFence == kRFence - 1) __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+    if (tid < 125)
+#pragma unroll
+      for (int k = 0; k < (kRChunk + 4) / 5; ++k) {
+        const int bl = tid / 25 + 5 * k, b = b0 + bl;
+        if (bl >= kRChunk || b >= P) break;
+        if (!row(b)) continue;
+        const int slot = FULL ? b : rr.slot[b];
+        const double sum = r_node_sum(nq, sC + bl * 64, sCy + bl * 64);
+        if (nq.owned) {
+          if (nq.write) {
+            double base = 0.0;
+            if (beta != 0.0) base = beta * rin[(int64_t)(FULL ? slot : rr.mode[slot]) * Nh + nq.node];
+            out[(int64_t)slot * Nh + nq.node] = base + sgn * sum;
+          }
+        } else {
+          edge[((int64_t)slot * ntiles + tile) * kEdgeVals + nq.e] = sum;
+        }
+      }
+    __syncthreads();  // the next chunk reuses the corner buffer
+  }
+}
+
+template <int M, int p, bool FULL>
+__global__ __launch_bounds__(kRThreads) void rapply_huge_kernel(
+    int n, double mu, double a_min, const double* __restrict__ g, RApplyRows rr,
+    const double* __restrict__ U, int64_t Nh, const double* __restrict__ rin, double beta,
+    double sgn, double* __restrict__ out, double* __restrict__ edge) {
+  extern __shared__ double smem[];
+  const int nt = n / kTileE;
+  rapply_huge_tile<M, p, FULL>(smem, xcd_tile(blockIdx.x, nt * nt), n, mu, a_min, g, rr, U, Nh,
+                               rin, beta, sgn, out, edge);
+}
+
+template <int M, int p>
+__global__ __launch_bounds__(kRThreads) void brapply_huge_kernel(
+    const BInst* __restrict__ Is, const BState* __restrict__ Ss, const BItem* __restrict__ items,
+    int nitems, int rowset, int src, int rin, int dst, double beta, double sgn, int gate) {
+  extern __shared__ double smem[];
+  const int it = blockIdx.x;  // one workgroup per item (grid = nitems)
+  if (it >= nitems) return;
+  const BItem w = items[it];
+  const BInst& I = Is[w.inst];
+  const BState& S = Ss[w.inst];
+  if (gated(S, gate)) return;
+  const RApplyRows& rr = rowset == 0 ? I.rfull : I.rpart[rowset];
+  rapply_huge_tile<M, p, false>(smem, w.local, I.n, I.mu, I.amin, gptr(I.gq), rr,
+                                bbuf(I, S, src), I.Nh, rin >= 0 ? bbuf(I, S, rin) : nullptr,
+                                beta, sgn, bbuf(I, S, dst), gptr(I.edge));
+}
+
+#define SG_RAPPLY_HUGE_LIST(X) X(5, 4) X(6, 4)
+
 // (instance, tile) items of instances sharing one (M, p), P > kRSmall
 template <int M, int p>
 __global__ __launch_bounds__(kRThreads, 2) void brapply_big_kernel(
@@ -671,6 +928,7 @@ bool rapply_supported(int M, int p) {
 #define SG_RAPPLY_SUP(MM, PP) if (M == MM && p == PP) return true;
   SG_RAPPLY_LIST(SG_RAPPLY_SUP)
   SG_RAPPLY_BIG_LIST(SG_RAPPLY_SUP)
+  SG_RAPPLY_HUGE_LIST(SG_RAPPLY_SUP)
 #undef SG_RAPPLY_SUP
   return false;
 }
@@ -689,6 +947,7 @@ bool rapply_matches(int M, int p, const std::vector<std::vector<int>>& Jp) {
 #define SG_RAPPLY_CHK(MM, PP) if (M == MM && p == PP) return rapply_check<MM, PP>(Jp);
   SG_RAPPLY_LIST(SG_RAPPLY_CHK)
   SG_RAPPLY_BIG_LIST(SG_RAPPLY_CHK)
+  SG_RAPPLY_HUGE_LIST(SG_RAPPLY_CHK)
 #undef SG_RAPPLY_CHK
   return false;
 }
@@ -724,6 +983,26 @@ void launch_rapply(hipStream_t s, int M, int p, int n, double mu, double a_min, 
   }
   SG_RAPPLY_BIG_LIST(SG_RAPPLY_BIG_LAUNCH)
 #undef SG_RAPPLY_BIG_LAUNCH
+#define SG_RAPPLY_HUGE_LAUNCH(MM, PP)                                                          \
+  if (M == MM && p == PP) {                                                                    \
+    const size_t blds = rapply_big_lds_bytes(P);                                               \
+    static const bool attr_ok =                                                                \
+        hipFuncSetAttribute((const void*)rapply_huge_kernel<MM, PP, true>,                     \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)blds) == hipSuccess && \
+        hipFuncSetAttribute((const void*)rapply_huge_kernel<MM, PP, false>,                    \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)blds) == hipSuccess; \
+    if (!attr_ok) throw Error(SG_ERR_HIP, "register apply: LDS size attribute");               \
+    if (full)                                                                                  \
+      hipLaunchKernelGGL((rapply_huge_kernel<MM, PP, true>), dim3(ntiles), dim3(kRThreads),   \
+                         blds, s, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);      \
+    else                                                                                       \
+      hipLaunchKernelGGL((rapply_huge_kernel<MM, PP, false>), dim3(ntiles), dim3(kRThreads),  \
+                         blds, s, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);      \
+    if (fixup) launch_apply_fixup(s, n, rr.nrows, sgn, edge, out, Nh);                         \
+    return;                                                                                    \
+  }
+  SG_RAPPLY_HUGE_LIST(SG_RAPPLY_HUGE_LAUNCH)
+#undef SG_RAPPLY_HUGE_LAUNCH
   const size_t lds = rapply_lds_bytes(P, rr.nrows);
 #define SG_RAPPLY_LAUNCH(MM, PP)                                                              \
   if (M == MM && p == PP) {                                                                   \
@@ -757,6 +1036,19 @@ void launch_brapply(hipStream_t s, int M, int p, size_t lds, const BInst* I, con
   }
   SG_RAPPLY_BIG_LIST(SG_BRAPPLY_BIG_LAUNCH)
 #undef SG_BRAPPLY_BIG_LAUNCH
+#define SG_BRAPPLY_HUGE_LAUNCH(MM, PP)                                                         \
+  if (M == MM && p == PP) {                                                                    \
+    static const bool attr_ok =                                                                \
+        hipFuncSetAttribute((const void*)brapply_huge_kernel<MM, PP>,                          \
+                            hipFuncAttributeMaxDynamicSharedMemorySize,                         \
+                            (int)rapply_big_lds_bytes(rc_binom(MM + PP, PP))) == hipSuccess;   \
+    if (!attr_ok) throw Error(SG_ERR_HIP, "batched register apply: LDS size attribute");      \
+    hipLaunchKernelGGL((brapply_huge_kernel<MM, PP>), dim3(grid), dim3(kRThreads), lds, s, I,  \
+                       st, items, nitems, rowset, src, rin, dst, beta, sgn, gate);             \
+    return;                                                                                    \
+  }
+  SG_RAPPLY_HUGE_LIST(SG_BRAPPLY_HUGE_LAUNCH)
+#undef SG_BRAPPLY_HUGE_LAUNCH
 #define SG_BRAPPLY_LAUNCH(MM, PP)                                                             \
   if (M == MM && p == PP) {                                                                   \
     hipLaunchKernelGGL((brapply_kernel<MM, PP>), dim3(grid), dim3(kRThreads), lds, s, I, st, items, \

@@ -23,8 +23,10 @@ SMALL = {
     "n16_m4p4": Problem(n=16, M=4, p=4, q=8, cov="exp_l1", sigma=0.7, corr_len=0.6),
     # q > 2p: the factored form is still exact
     "n8_m2p2q6": Problem(n=8, M=2, p=2, q=6, cov="sqexp", sigma=1.3, corr_len=0.4),
-    # P = 210: only the small sub-batches fit in LDS
+    # P = 210 and 126: the register form with the degree-p modes streamed (the
+    # LDS-tile form: only the small sub-batches fit)
     "n8_m6p4": Problem(n=8, M=6, p=4, q=8, cov="exp_l1", sigma=0.7, corr_len=0.6),
+    "n8_m5p4": Problem(n=8, M=5, p=4, q=8, cov="sqexp", sigma=0.8, corr_len=0.5),
     # finest level above the dense coarse operator: the field split's blocks
     # leave their edge sums to the cycle's first level
     "n64_m3p2": Problem(n=64, M=3, p=2, q=4, cov="exp_l1", sigma=0.9, corr_len=0.4),
@@ -53,6 +55,9 @@ def test_apply_form(name, form, qb):
     except sg.SGError as e:
         assert e.code == -2 and qb != 0, (name, qb, e)   # the planner's own choice always fits
         pytest.skip(f"{qb} points per sub-batch do not fit in LDS for P={S.P}")
+    if form == "factored" and qb == 0 and S.prob.M <= 6 and S.prob.p <= 4:
+        # every chaos space up to M = 6, p = 4 has a register-resident kernel
+        assert G.apply_form() == (2, 0), (name, G.apply_form())
     try:
         U = random_vector(S.P * S.Nh, 201)
         W = to_host(G.apply(to_dev(U)))
@@ -63,7 +68,8 @@ def test_apply_form(name, form, qb):
         G.set_apply("auto", 0)
 
 
-@pytest.mark.parametrize("name", ["n16_m4p3", "n8_m6p3", "n16_m5p3", "n16_m4p4"])
+@pytest.mark.parametrize("name", ["n16_m4p3", "n8_m6p3", "n16_m5p3", "n16_m4p4", "n8_m5p4",
+                                  "n8_m6p4"])
 @pytest.mark.parametrize("grouping", ["klvar", "permode", "fg", "klvar_meansep"])
 def test_field_split_through_both_forms(name, grouping):
     """The field split's off-diagonal block applies K_{g_s, g_<s} z in both forms."""
