@@ -716,15 +716,18 @@ __device__ __forceinline__ void rapply_huge_tile(double* smem, int tile, int n, 
   const int qp = r_lane_qp(lane, comp), pt = (lane & ~3) | qp;  // the lane's Gauss point
   const int m = n - 1;
   const int64_t Nq = (int64_t)4 * n * n;
-  // masks: run-time, read once into uniform registers (see rapply_big_tile);
-  // every gamma is computed (no gamma mask: a Vbar no row reads is harmless)
-  uint64_t cm[kRMaskW], rm[kRMaskW];
+  // masks: run-time, read once into uniform registers (see rapply_big_tile).
+  // A block skips the degree-p modes that are not columns (their nodal values,
+  // hence gradients, are zero) and the step-1a sums of gammas no output row
+  // reads; their registers keep values nothing uses.
+  uint64_t cm[kRMaskW], rm[kRMaskW], gmk[kRMaskW];
 #pragma unroll
   for (int k = 0; k < kRMaskW; ++k) {
     cm[k] = rr.colmask[k];
     rm[k] = rr.rowmask[k];
+    gmk[k] = rr.gammask[k];
   }
-  auto col = [&](int a) { return rbit(cm, a); };
+  auto col = [&](int a) { return FULL || rbit(cm, a); };
   auto row = [&](int b) { return FULL || rbit(rm, b); };
 
   // 1. nodal values of the column modes (zeros elsewhere), in two halves so
@@ -780,6 +783,7 @@ __device__ __forceinline__ void rapply_huge_tile(double* smem, int tile, int n, 
   // 3a. step 1 over the pairs with alpha of degree below p, in place (unscaled)
 #pragma unroll
   for (int gm = 0; gm < PN; ++gm) {
+    if (!FULL && !rbit(gmk, gm)) continue;
     double sx = 0.0;
 #pragma unroll
     for (int t = T.p1[gm]; t < T.p1[gm + 1]; ++t)
@@ -790,6 +794,7 @@ __device__ __forceinline__ void rapply_huge_tile(double* smem, int tile, int n, 
   // 3b. the degree-p modes, one at a time
 #pragma unroll
   for (int a = PN; a < P; ++a) {
+    if (!col(a)) continue;
     const double ga = T.s[a] * r_grad(rg, sN + a * 25);
 #pragma unroll
     for (int k = Q.pq[a - PN]; k < Q.pq[a - PN + 1]; ++k)
