@@ -1504,6 +1504,8 @@ struct sg_batch {
   BItem* dItems = nullptr;
   size_t item_cap = 0;
   BState* hS = nullptr;  // pinned
+  char* tail_ws = nullptr;  // Krylov workspace of the instances finishing one at a time
+  size_t tail_bytes = 0;
   std::map<int, Plan> plans;
   ~sg_batch() {
     for (auto& kv : plans) {
@@ -1518,6 +1520,7 @@ struct sg_batch {
 namespace {
 
 constexpr size_t kBatchItemCap = 1 << 24;  // work items of all tables of one plan
+constexpr int kBatchTail = 4;  // instances left when a solve continues them one at a time
 
 int cdivi(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
@@ -1556,6 +1559,16 @@ size_t batch_layout(sg_batch& B, char* base) {
   B.dS = c.take<BState>(B.count);
   B.dItems = c.take<BItem>(kBatchItemCap);
   B.item_cap = kBatchItemCap;
+  // the Krylov workspace the last few instances of a solve use when they
+  // continue one at a time (the largest single-instance need)
+  size_t tail = 0;
+  for (int i = 0; i < B.count; ++i)
+    tail = std::max(tail, krylov_layout(B.h[i], B.restart, false, nullptr, nullptr));
+  char* tw = c.take<char>(tail);
+  if (base) {
+    B.tail_ws = tw;
+    B.tail_bytes = tail;
+  }
   return c.off;
 }
 
@@ -2164,6 +2177,8 @@ int sg_batch_solve(sg_batch* b, const sg_solve_opts* o, const double* F, double*
       compact.reset();
     };
     int live_at_build = B.count;
+    std::vector<sg_solve_info> tail_info(B.count);
+    std::vector<char> handed(B.count, 0);
     const int m = B.restart;
     const int max_cycles = o->max_it + 1;
     for (int cycle = 0; cycle < max_cycles; ++cycle) {
@@ -2187,6 +2202,26 @@ int sg_batch_solve(sg_batch* b, const sg_solve_opts* o, const double* F, double*
       int nlive = 0;
       for (int i = 0; i < B.count; ++i) nlive += (live[i] = !B.hS[i].done);
       if (nlive == 0) break;
+      // The last few instances continue one at a time with the single-instance
+      // solver from their current iterate (a restart boundary, so the same
+      // method): with so few left, lockstep launches cost more than their own
+      // kernels.
+      if (nlive <= kBatchTail && nlive < B.count) {
+        for (int i = 0; i < B.count; ++i) {
+          if (!live[i] || o->max_it - B.hS[i].it < 1) continue;
+          sg_solve_opts oi = *o;
+          oi.use_x0 = 1;
+          oi.max_it = o->max_it - B.hS[i].it;
+          const int rc = sg_gmres_solve(B.h[i], &oi, F + B.voff[i], u + B.voff[i], B.tail_ws,
+                                        B.tail_bytes, nullptr, 0, &tail_info[i], stream);
+          if (rc != SG_OK) {
+            drop_compact();
+            return rc;
+          }
+          handed[i] = 1;
+        }
+        break;
+      }
       if (graphs && 4 * nlive <= 3 * live_at_build) {
         std::unique_ptr<Plan> next(new Plan(build_plan(B, kind, o->grouping, F, u, &live)));
         SG_HIP(hipMemcpyAsync(B.dItems, next->items.data(), next->items.size() * sizeof(BItem),
@@ -2205,6 +2240,12 @@ int sg_batch_solve(sg_batch* b, const sg_solve_opts* o, const double* F, double*
       const BState& st = B.hS[i];
       sg_solve_info& inf = infos[i];
       std::memset(&inf, 0, sizeof(inf));
+      if (handed[i]) {  // lockstep part, then the one-at-a-time part
+        inf = tail_info[i];
+        inf.iterations += st.it;
+        inf.restarts += st.restarts;
+        continue;
+      }
       inf.status = st.done ? st.status : SG_NOT_CONVERGED;
       inf.iterations = st.it;
       inf.restarts = st.restarts;
