@@ -287,11 +287,13 @@ int    sg_batch_handle(sg_batch* b, int32_t i, sg_handle** h);
 /* solves every instance from zero with opts (pc SG_PC_MEAN or SG_PC_FS, any
  * grouping, restart equal to the bound value); F, u packed device vectors;
  * infos: count entries.  Graph capture needs a non-null stream (the null
- * stream runs the same launch sequences eagerly).  At a restart that leaves
- * at most four (and not all) instances running, those continue one at a
- * time through sg_gmres_solve from their current iterate, in a Krylov area
- * the batch workspace reserves for the largest instance; their infos add
- * both parts.  Synchronous.                                                */
+ * stream runs the same launch sequences eagerly).  On a non-null stream,
+ * instances of at least 2^20 unknowns (P*N_h) are solved one at a time by
+ * sg_gmres_solve on a second stream, from a host thread, beside the lockstep
+ * batch of the others.  At a restart that leaves at most four lockstep
+ * instances running, those continue one at a time through sg_gmres_solve
+ * from their current iterate; their infos add both parts.  The batch
+ * workspace reserves the Krylov areas of both.  Synchronous.               */
 int    sg_batch_solve(sg_batch* b, const sg_solve_opts* opts, const double* F, double* u,
                       sg_solve_info* infos, void* stream);
 void   sg_batch_destroy(sg_batch* b);

@@ -4,7 +4,9 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <functional>
 #include <memory>
+#include <thread>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -1504,7 +1506,9 @@ struct sg_batch {
   BItem* dItems = nullptr;
   size_t item_cap = 0;
   BState* hS = nullptr;  // pinned
-  char* tail_ws = nullptr;  // Krylov workspace of the instances finishing one at a time
+  char* solo_ws = nullptr;  // Krylov workspace of the instances solved one at a time
+  size_t solo_bytes = 0;
+  char* tail_ws = nullptr;  // ... of the lockstep instances that finish one at a time
   size_t tail_bytes = 0;
   std::map<int, Plan> plans;
   ~sg_batch() {
@@ -1521,6 +1525,10 @@ namespace {
 
 constexpr size_t kBatchItemCap = 1 << 24;  // work items of all tables of one plan
 constexpr int kBatchTail = 4;  // instances left when a solve continues them one at a time
+// instances with at least this many unknowns fill the chip with their own
+// kernels: a batched solve on a stream runs them one at a time beside the
+// lockstep batch of the others
+constexpr int64_t kBatchSoloUnknowns = int64_t(1) << 20;
 
 int cdivi(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
@@ -1559,13 +1567,20 @@ size_t batch_layout(sg_batch& B, char* base) {
   B.dS = c.take<BState>(B.count);
   B.dItems = c.take<BItem>(kBatchItemCap);
   B.item_cap = kBatchItemCap;
-  // the Krylov workspace the last few instances of a solve use when they
-  // continue one at a time (the largest single-instance need)
-  size_t tail = 0;
-  for (int i = 0; i < B.count; ++i)
-    tail = std::max(tail, krylov_layout(B.h[i], B.restart, false, nullptr, nullptr));
+  // Krylov workspaces for the instances a solve runs one at a time: the
+  // largest instance's need, and the largest below the solo size (the tail of
+  // the lockstep batch, which may run beside the solo instances)
+  size_t solo = 0, tail = 0;
+  for (int i = 0; i < B.count; ++i) {
+    const size_t kb = krylov_layout(B.h[i], B.restart, false, nullptr, nullptr);
+    solo = std::max(solo, kb);
+    if ((int64_t)B.h[i]->P * B.h[i]->Nh < kBatchSoloUnknowns) tail = std::max(tail, kb);
+  }
+  char* sw = c.take<char>(solo);
   char* tw = c.take<char>(tail);
   if (base) {
+    B.solo_ws = sw;
+    B.solo_bytes = solo;
     B.tail_ws = tw;
     B.tail_bytes = tail;
   }
@@ -2147,27 +2162,62 @@ int sg_batch_solve(sg_batch* b, const sg_solve_opts* o, const double* F, double*
                           hipMemcpyHostToDevice, s));
     SG_HIP(hipMemcpyAsync(B.dItems, pl.items.data(), pl.items.size() * sizeof(BItem),
                           hipMemcpyHostToDevice, s));
+    // one Arnoldi step and the restart are captured once per plan (needs a
+    // non-null stream; on the null stream the same sequences run eagerly)
+    const bool graphs = (s != nullptr);
+    // instances whose kernels fill the chip run one at a time through the
+    // single-instance solver on a second stream, beside the lockstep batch of
+    // the others (on a stream only; all of them, if every instance is large)
+    std::vector<char> solo(B.count, 0);
+    int nsolo = 0;
+    if (graphs)
+      for (int i = 0; i < B.count; ++i)
+        if ((int64_t)B.h[i]->P * B.h[i]->Nh >= kBatchSoloUnknowns) nsolo += (solo[i] = 1);
     for (int i = 0; i < B.count; ++i) {
       BState st{};
       st.max_it = o->max_it;
+      if (solo[i]) {  // gated off in every batched kernel
+        st.done = 1;
+        st.status = SG_NOT_CONVERGED;
+      }
       B.hS[i] = st;
     }
     SG_HIP(hipMemcpyAsync(B.dS, B.hS, sizeof(BState) * B.count, hipMemcpyHostToDevice, s));
     SG_HIP(hipStreamSynchronize(s));
-    // one Arnoldi step and the restart are captured once per plan (needs a
-    // non-null stream; on the null stream the same sequences run eagerly)
-    const bool graphs = (s != nullptr);
-    if (graphs && !pl.gstep) {
-      pl.gstep = capture(B, s, pl.step, o->tol);
-      pl.grestart = capture(B, s, pl.restart, o->tol);
+    // the solo instances' solves, on a thread of their own (joined on every
+    // way out of this call)
+    std::vector<sg_solve_info> solo_info(B.count);
+    int solo_rc = SG_OK;
+    std::string solo_err;
+    hipStream_t s2 = nullptr;
+    std::thread solo_thread;
+    struct Joiner {
+      std::thread& t;
+      hipStream_t& st;
+      ~Joiner() {
+        if (t.joinable()) t.join();
+        if (st) (void)hipStreamDestroy(st);
+      }
+    } joiner{solo_thread, s2};
+    if (nsolo > 0) {
+      SG_HIP(hipStreamCreate(&s2));
+      solo_thread = std::thread([&]() {
+        for (int i = 0; i < B.count && solo_rc == SG_OK; ++i) {
+          if (!solo[i]) continue;
+          sg_solve_opts oi = *o;
+          oi.use_x0 = 0;
+          solo_rc = sg_gmres_solve(B.h[i], &oi, F + B.voff[i], u + B.voff[i], B.solo_ws,
+                                   B.solo_bytes, nullptr, 0, &solo_info[i], s2);
+          if (solo_rc != SG_OK) solo_err = sg_last_error();
+        }
+      });
     }
-    run_recs(B, s, pl.start, o->tol);
-    check_launch();
     // Once a quarter of the instances still running at the last (re)build
     // have finished, the step and restart are rebuilt over the remaining ones
     // (items uploaded, graphs captured again), so the step kernels stop
     // walking the work of finished instances.  The full plan stays cached for
-    // the next solve, which uploads its items again.
+    // the next solve, which uploads its items again.  With solo instances the
+    // lockstep starts from such a plan over the others.
     Plan* cur = &pl;
     std::unique_ptr<Plan> compact;
     auto drop_compact = [&]() {
@@ -2176,12 +2226,32 @@ int sg_batch_solve(sg_batch* b, const sg_solve_opts* o, const double* F, double*
       if (compact->grestart) (void)hipGraphExecDestroy(compact->grestart);
       compact.reset();
     };
-    int live_at_build = B.count;
+    struct Dropper {
+      std::function<void()> f;
+      ~Dropper() { f(); }
+    } dropper{drop_compact};
+    std::vector<char> inbatch(B.count);
+    for (int i = 0; i < B.count; ++i) inbatch[i] = !solo[i];
+    int live_at_build = B.count - nsolo;
+    if (nsolo > 0 && nsolo < B.count) {
+      compact.reset(new Plan(build_plan(B, kind, o->grouping, F, u, &inbatch)));
+      SG_HIP(hipMemcpyAsync(B.dItems, compact->items.data(), compact->items.size() * sizeof(BItem),
+                            hipMemcpyHostToDevice, s));
+      SG_HIP(hipStreamSynchronize(s));
+      compact->gstep = capture(B, s, compact->step, o->tol);
+      compact->grestart = capture(B, s, compact->restart, o->tol);
+      cur = compact.get();
+    } else if (graphs && !pl.gstep) {
+      pl.gstep = capture(B, s, pl.step, o->tol);
+      pl.grestart = capture(B, s, pl.restart, o->tol);
+    }
+    if (nsolo < B.count) run_recs(B, s, cur->start, o->tol);
+    check_launch();
     std::vector<sg_solve_info> tail_info(B.count);
     std::vector<char> handed(B.count, 0);
     const int m = B.restart;
     const int max_cycles = o->max_it + 1;
-    for (int cycle = 0; cycle < max_cycles; ++cycle) {
+    for (int cycle = 0; cycle < max_cycles && nsolo < B.count; ++cycle) {
       for (int j = 0; j < m; ++j) {
         if (graphs) SG_HIP(hipGraphLaunch(cur->gstep, s));
         else run_recs(B, s, cur->step, o->tol);
@@ -2200,24 +2270,24 @@ int sg_batch_solve(sg_batch* b, const sg_solve_opts* o, const double* F, double*
       check_launch();
       std::vector<char> live(B.count);
       int nlive = 0;
-      for (int i = 0; i < B.count; ++i) nlive += (live[i] = !B.hS[i].done);
+      for (int i = 0; i < B.count; ++i) nlive += (live[i] = !solo[i] && !B.hS[i].done);
       if (nlive == 0) break;
       // The last few instances continue one at a time with the single-instance
       // solver from their current iterate (a restart boundary, so the same
       // method): with so few left, lockstep launches cost more than their own
       // kernels.
-      if (nlive <= kBatchTail && nlive < B.count) {
+      if (nlive <= kBatchTail && nlive < B.count - nsolo) {
         for (int i = 0; i < B.count; ++i) {
           if (!live[i] || o->max_it - B.hS[i].it < 1) continue;
           sg_solve_opts oi = *o;
           oi.use_x0 = 1;
           oi.max_it = o->max_it - B.hS[i].it;
-          const int rc = sg_gmres_solve(B.h[i], &oi, F + B.voff[i], u + B.voff[i], B.tail_ws,
-                                        B.tail_bytes, nullptr, 0, &tail_info[i], stream);
-          if (rc != SG_OK) {
-            drop_compact();
-            return rc;
-          }
+          // (the solo instances' Krylov area, unless they are running)
+          char* kws = nsolo > 0 ? B.tail_ws : B.solo_ws;
+          const size_t kbytes = nsolo > 0 ? B.tail_bytes : B.solo_bytes;
+          const int rc = sg_gmres_solve(B.h[i], &oi, F + B.voff[i], u + B.voff[i], kws, kbytes,
+                                        nullptr, 0, &tail_info[i], stream);
+          if (rc != SG_OK) return rc;
           handed[i] = 1;
         }
         break;
@@ -2235,11 +2305,16 @@ int sg_batch_solve(sg_batch* b, const sg_solve_opts* o, const double* F, double*
         live_at_build = nlive;
       }
     }
-    drop_compact();
+    if (solo_thread.joinable()) solo_thread.join();
+    if (solo_rc != SG_OK) return fail(solo_rc, "solo instance: " + solo_err);
     for (int i = 0; i < B.count; ++i) {
       const BState& st = B.hS[i];
       sg_solve_info& inf = infos[i];
       std::memset(&inf, 0, sizeof(inf));
+      if (solo[i]) {
+        inf = solo_info[i];
+        continue;
+      }
       if (handed[i]) {  // lockstep part, then the one-at-a-time part
         inf = tail_info[i];
         inf.iterations += st.it;

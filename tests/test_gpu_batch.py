@@ -65,6 +65,38 @@ def test_batch_matches_single_instance_solves(pc, form, qb):
         B.close()
 
 
+def test_batch_large_instance_beside_the_lockstep():
+    """An instance of at least 2^20 unknowns (128x128, P = 70) is solved by the
+    single-instance solver on a stream of its own while the others advance in
+    lockstep (the lockstep tail then continues one at a time as well); every
+    instance still matches its own single-instance solve."""
+    need_gpu()
+    probs_py = PROBS[:3] + [Problem(n=128, M=4, p=4, q=8, cov="exp_l1", sigma=0.6, corr_len=0.5)]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        probs = [make_problem(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma, p.corr_len, p.a_min)
+                 for p in probs_py]
+        fs = [rhs_noisy(p.n, 300 + i) for i, p in enumerate(probs_py)]
+        B = sg.Batch(probs, f_nodal=fs, restart=20, autotune=False, stream=stream)
+        F = B.rhs()
+        u, infos = B.solve(F, pc="fs", grouping="klvar", tol=1e-8)
+        torch.cuda.synchronize()
+        ub = u.cpu().numpy()
+        for i, p in enumerate(probs_py):
+            inst = sg.SGInstance(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma, p.corr_len, p.a_min,
+                                 f_nodal=fs[i], stream=stream)
+            Fi = inst.rhs()
+            ui, info, _ = inst.solve(Fi, pc="fs", grouping="klvar", restart=20, tol=1e-8)
+            torch.cuda.synchronize()
+            o0, o1 = B.offsets[i], B.offsets[i + 1]
+            assert infos[i].status == 0, (i, infos[i].status)
+            assert infos[i].iterations == info.iterations, (i, infos[i].iterations, info.iterations)
+            uref = ui.cpu().numpy()
+            assert np.linalg.norm(ub[o0:o1] - uref) <= 1e-12 * np.linalg.norm(uref)
+            inst.close()
+        B.close()
+
+
 def test_batch_true_residual_by_oracle():
     need_gpu()
     from oracle.system import SGSystem
