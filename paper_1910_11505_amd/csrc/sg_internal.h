@@ -134,7 +134,7 @@ struct FRowSetDev {
 // mode[slot] its mode id.
 constexpr int kRMax = 256;            // modes of the register-resident apply
 constexpr int kRMaskW = kRMax / 64;   // mask words
-constexpr int kRSmall = 35;  // ... whose monomials all stay in registers
+constexpr int kRSmall = 35;  // ... whose gradients and monomials all stay in registers
 struct RApplyRows {
   uint64_t colmask[kRMaskW], rowmask[kRMaskW];
   uint64_t gammask[kRMaskW];  // gamma <= some column and <= some output row (step-1 rows that matter)

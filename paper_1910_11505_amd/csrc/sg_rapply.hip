@@ -1,5 +1,6 @@
-// Register-resident factored SG apply for small chaos spaces (P <= 35, and a
-// variant with the monomials in LDS for 35 < P <= 84).
+// Register-resident factored SG apply: every chaos space with M <= 6, p <= 4
+// (rapply_tile for P <= 35 as described here; rapply_stream_tile, further
+// down, for 35 < P <= 210).
 //
 // The same operator as the factored tile kernel (sum_k a_k G_k = a_min I +
 // w T T^T, exact for q >= 2p; see FRowSetDev), with the chaos structure of
@@ -219,8 +220,6 @@ struct RTabTopHolder {
 __device__ __forceinline__ double r_gauss_pt(int i) {
   return i ? 0.78867513459481288225 : 0.21132486540518711775;
 }
-
-inline int r_cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 }  // namespace
 
@@ -502,198 +501,34 @@ __global__ __launch_bounds__(kRThreads) void brapply_kernel(const BInst* __restr
 }
 
 // ---------------------------------------------------------------------------
-// The same operator for larger chaos spaces (35 < P <= 84).  The scaled
-// gradients stay in registers (one component per wavefront, as above).  Of the
-// monomials only those of degree below p stay in registers: an output gamma of
-// degree d in step 1 needs m_delta with |delta| <= p - d, and a row beta of
-// step 2 needs a degree-p monomial only for its gamma = 0 term, so each
-// degree-p monomial enters one product per step and is formed there from its
-// parent (the same two products, in the same order, as the recurrence).  The
-// a_min term is recomputed from the nodal values, which stay in LDS, and the
-// output rows are taken in chunks of kRChunk, their corner contributions
-// reduced to node sums chunk by chunk.
+// The same operator for larger chaos spaces (35 < P <= 210), where the P
+// gradients and P monomials of a point no longer fit a lane together.  It
+// rests on the degree structure of the contraction: a step-1 output gamma of
+// degree d needs m_delta with |delta| <= p - d, and a step-2 row beta needs a
+// degree-p monomial only for its gamma = 0 term, so a degree-p mode alpha
+// enters step 1 only through the Vbar_gamma below it and step 2 only through
+// its own row (Vbar_alpha is its scaled gradient alone).
+//  - Only the modes of degree below p keep their gradient (then Vbar) in
+//    registers, and only the monomials of degree below p - 1; degree p - 1
+//    and p monomials are formed where used from their parents (the same
+//    products, in the same order, as the recurrence).
+//  - Step 1 first sums the pairs with alpha of degree below p in place, then
+//    streams the degree-p modes: each one's gradient is recomputed from the
+//    nodal values (one read and two DPP exchanges) and added to every
+//    Vbar_gamma below it (the pairs grouped by alpha, RTabTop).
+//  - Step 2 recomputes a degree-p row's gradient for its gamma = beta term
+//    and, for every row, the a_min term's gradient, through an offset the
+//    compiler cannot equate with the gradient loop's; its monomials come from
+//    copies of g it cannot equate with step 1's (either way it would keep
+//    step-1 values alive through step 2 and spill).
+//  - Output rows go in chunks of kRChunk: corner sums to LDS, barrier, node
+//    sums, barrier.  For the whole operator the rows carry no branches and are
+//    scheduled kRFence at a time between fences.
 // ---------------------------------------------------------------------------
 constexpr int kRChunk = 16;
-constexpr int kRFence = 4;  // whole operator: step-2 rows scheduled together between fences
-
+constexpr int kRFence = 4;
 template <int M, int p, bool FULL>
-__device__ __forceinline__ void rapply_big_tile(double* smem, int tile, int n, double mu,
-                                                double a_min, const double* __restrict__ g,
-                                                const RApplyRows& rr,
-                                                const double* __restrict__ U, int64_t Nh,
-                                                const double* __restrict__ rin, double beta,
-                                                double sgn, double* __restrict__ out,
-                                                double* __restrict__ edge) {
-  constexpr const RTab<M, p>& T = RTabHolder<M, p>::v;
-  constexpr int P = RTab<M, p>::P;
-  static_assert(P <= kRMax, "mask words");
-  constexpr int PL = rc_binom(M + p - 1, p - 1);  // monomials of degree below p
-  double* sN = smem;            // [P][25] nodal values
-  double* sC = sN + P * 25;     // [2][kRChunk][64] corner contributions of a row chunk
-  const int nt = n / kTileE, ntiles = nt * nt;
-  const int tx = tile % nt, ty = tile / nt;
-  const int x0 = tx * kTileE, y0 = ty * kTileE;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int comp = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int qp = r_lane_qp(lane, comp), pt = (lane & ~3) | qp;  // the lane's Gauss point
-  const int m = n - 1;
-  const int64_t Nq = (int64_t)4 * n * n;
-  // The column and gamma masks stay run-time values even for the whole
-  // operator: known, they let the compiler move step-1 arithmetic into step 2
-  // and spill.  Only the row side (step 2) is compile-time there, so its rows
-  // carry no branches and can be scheduled a few at a time.  The masks are read
-  // once into uniform registers, not per test, where the compiler would narrow
-  // each test to an unaligned vector load of the descriptor.
-  uint64_t cm[kRMaskW], rm[kRMaskW], gmk[kRMaskW];
-#pragma unroll
-  for (int k = 0; k < kRMaskW; ++k) {
-    cm[k] = rr.colmask[k];
-    rm[k] = rr.rowmask[k];
-    gmk[k] = rr.gammask[k];
-  }
-  auto col = [&](int a) { return rbit(cm, a); };
-  auto row = [&](int b) { return FULL || rbit(rm, b); };
-
-  // 1. nodal values of the column modes (all loads in flight at once)
-  constexpr int NL = (P * 25 + kRThreads - 1) / kRThreads;
-  double v[NL];
-#pragma unroll
-  for (int u = 0; u < NL; ++u) {
-    const int idx = tid + kRThreads * u;
-    const int c = min(idx / 25, P - 1), nd = idx - (idx / 25) * 25;
-    const int gx = x0 + nd % 5, gy = y0 + nd / 5;
-    const bool ok = idx < P * 25 && col(c) && gx >= 1 && gx <= m && gy >= 1 && gy <= m;
-    v[u] = ok ? U[(int64_t)c * Nh + (int64_t)(gy - 1) * m + (gx - 1)] : 0.0;
-  }
-  double gv[M];
-#pragma unroll
-  for (int nn = 0; nn < M; ++nn) gv[nn] = g[(int64_t)nn * Nq + (int64_t)tile * kTileQ + pt];
-#pragma unroll
-  for (int u = 0; u < NL; ++u)
-    if (tid + kRThreads * u < P * 25) sN[tid + kRThreads * u] = v[u];
-
-  // 2. monomials of degree below p (graded order: the first PL), then
-  // gradient component c and w
-  double mono[PL];
-  mono[0] = 1.0;
-#pragma unroll
-  for (int d = 1; d < PL; ++d) mono[d] = mono[T.par[d]] * gv[T.var[d]] * T.inv[d];
-  auto mv = [&](int d) { return d < PL ? mono[d] : mono[T.par[d]] * gv[T.var[d]] * T.inv[d]; };
-  __syncthreads();
-  const int el = lane >> 2, ql = qp;
-  const double xi = r_gauss_pt(ql & 1), eta = r_gauss_pt(ql >> 1);
-  const RGrad rg = r_grad_setup(comp, ql, el, xi, eta);
-  // (non-column modes: zero nodal values, zero gradients; no branch)
-  double G[P];
-#pragma unroll
-  for (int a = 0; a < P; ++a) G[a] = T.s[a] * r_grad(rg, sN + a * 25);
-  double s2 = 0.0;
-#pragma unroll
-  for (int nn = 0; nn < M; ++nn) s2 = fma(gv[nn], gv[nn], s2);
-  const double w = exp(mu + 0.5 * s2);
-
-  // 3. step 1 in place (gamma outside the block's set: never read, or zero)
-#pragma unroll
-  for (int gm = 0; gm < P; ++gm) {
-    if (!rbit(gmk, gm)) continue;
-    double sx = 0.0;
-#pragma unroll
-    for (int t = T.p1[gm]; t < T.p1[gm + 1]; ++t) sx = fma(mv(T.d1[t]), G[T.a1[t]], sx);
-    G[gm] = sx * T.is2[gm];
-  }
-  __builtin_amdgcn_sched_barrier(0);
-
-  // 4. step 2 by chunks of rows, corner sums as in rapply_tile; after each
-  // chunk the node sums
-  double wc, wo;
-  r_corner_weights(comp, ql, xi, eta, wc, wo);
-  // the a_min term re-reads the nodal values through offsets the compiler
-  // cannot equate with those of the gradient loop (else it keeps all P
-  // unscaled gradients alive through step 1)
-  int opq = 0;
-  asm volatile("" : "+v"(opq));
-  RGrad rg2 = rg;
-  rg2.oc += opq;
-  auto grad2 = [&](int a) { return r_grad(rg2, sN + a * 25); };
-  // step 2 forms its degree-p monomials from copies of g that the compiler
-  // cannot equate with g (else it keeps step 1's products alive until step 2)
-  double gv2[M];
-#pragma unroll
-  for (int nn = 0; nn < M; ++nn) {
-    gv2[nn] = gv[nn];
-    asm volatile("" : "+v"(gv2[nn]));
-  }
-  auto mv2 = [&](int d) { return d < PL ? mono[d] : mono[T.par[d]] * gv2[T.var[d]] * T.inv[d]; };
-  double* sCc = sC + comp * kRChunk * 64;
-  const double* sCy = sC + kRChunk * 64;
-  const RNode nq = r_node(tid % 25, x0, y0, m);
-#pragma unroll
-  for (int b0 = 0; b0 < P; b0 += kRChunk) {
-#pragma unroll
-    for (int b = b0; b < (b0 + kRChunk < P ? b0 + kRChunk : P); ++b) {
-      if (!row(b)) continue;
-      double sx = 0.0;
-#pragma unroll
-      for (int t = T.p2[b]; t < T.p2[b + 1]; ++t) sx = fma(mv2(T.d2[t]), G[T.g2[t]], sx);
-      double f = (T.s[b] * w) * sx;
-      if (FULL || col(b)) f = fma(a_min, grad2(b), f);
-      const double t = wc * f + quad_xor<2>(wo * f);
-      sCc[(b - b0) * 64 + lane] = t - quad_xor<1>(t);
-      if (!FULL || b % kRFence == kRFence - 1) __builtin_amdgcn_sched_barrier(0);
-    }
-    __syncthreads();
-    // node sums of the chunk's rows (as in rapply_tile: node tid % 25 of rows
-    // tid / 25, tid / 25 + 5, ... of the chunk)
-    if (tid < 125)
-#pragma unroll
-      for (int k = 0; k < (kRChunk + 4) / 5; ++k) {
-        const int bl = tid / 25 + 5 * k, b = b0 + bl;
-        if (bl >= kRChunk || b >= P) break;
-        if (!row(b)) continue;
-        const int slot = FULL ? b : rr.slot[b];
-        const double sum = r_node_sum(nq, sC + bl * 64, sCy + bl * 64);
-        if (nq.owned) {
-          if (nq.write) {
-            double base = 0.0;
-            if (beta != 0.0) base = beta * rin[(int64_t)(FULL ? slot : rr.mode[slot]) * Nh + nq.node];
-            out[(int64_t)slot * Nh + nq.node] = base + sgn * sum;
-          }
-        } else {
-          edge[((int64_t)slot * ntiles + tile) * kEdgeVals + nq.e] = sum;
-        }
-      }
-    __syncthreads();  // the next chunk reuses the corner buffer
-  }
-}
-
-// Two wavefronts per SIMD (four tiles per CU: 33 KB of LDS each at P = 84):
-// at P = 70 and 84 that spills 60-76 bytes per lane, measured faster than one
-// wavefront per SIMD without spills.
-template <int M, int p, bool FULL>
-__global__ __launch_bounds__(kRThreads, 2) void rapply_big_kernel(
-    int n, double mu, double a_min, const double* __restrict__ g, RApplyRows rr,
-    const double* __restrict__ U, int64_t Nh, const double* __restrict__ rin, double beta,
-    double sgn, double* __restrict__ out, double* __restrict__ edge) {
-  extern __shared__ double smem[];
-  const int nt = n / kTileE;
-  rapply_big_tile<M, p, FULL>(smem, xcd_tile(blockIdx.x, nt * nt), n, mu, a_min, g, rr, U, Nh,
-                              rin, beta, sgn, out, edge);
-}
-
-// ---------------------------------------------------------------------------
-// The same operator for P = 126 and 210 (p = 4), where even the gradients do
-// not fit a lane.  Only the modes of degree below p keep their gradient (then
-// Vbar) in registers, and only the monomials of degree below p - 1; degree
-// p - 1 and p monomials are formed where used, from their parents.  Step 1
-// first sums the pairs with alpha of degree below p in place, then streams the
-// degree-p modes: each one's gradient is recomputed from the nodal values (one
-// read and two DPP exchanges) and added to every Vbar_gamma below it.  A
-// degree-p gamma's Vbar is its own scaled gradient (only delta = 0), so step 2
-// recomputes it for the row's gamma = beta term.  Node sums as in
-// rapply_big_tile.
-// ---------------------------------------------------------------------------
-template <int M, int p, bool FULL>
-__device__ __forceinline__ void rapply_huge_tile(double* smem, int tile, int n, double mu,
+__device__ __forceinline__ void rapply_stream_tile(double* smem, int tile, int n, double mu,
                                                  double a_min, const double* __restrict__ g,
                                                  const RApplyRows& rr,
                                                  const double* __restrict__ U, int64_t Nh,
@@ -716,10 +551,14 @@ __device__ __forceinline__ void rapply_huge_tile(double* smem, int tile, int n, 
   const int qp = r_lane_qp(lane, comp), pt = (lane & ~3) | qp;  // the lane's Gauss point
   const int m = n - 1;
   const int64_t Nq = (int64_t)4 * n * n;
-  // masks: run-time, read once into uniform registers (see rapply_big_tile).
-  // A block skips the degree-p modes that are not columns (their nodal values,
-  // hence gradients, are zero) and the step-1a sums of gammas no output row
-  // reads; their registers keep values nothing uses.
+  // Masks: the column and gamma masks stay run-time values (known, they let
+  // the compiler move step-1 arithmetic into step 2 and spill), the row side is
+  // compile-time for the whole operator.  They are read once into uniform
+  // registers, not per test, where the compiler would narrow each test to an
+  // unaligned vector load of the descriptor.  A block skips the degree-p modes
+  // that are not columns (their nodal values, hence gradients, are zero) and
+  // the step-1a sums of gammas no output row reads; their registers keep
+  // values nothing uses.
   uint64_t cm[kRMaskW], rm[kRMaskW], gmk[kRMaskW];
 #pragma unroll
   for (int k = 0; k < kRMaskW; ++k) {
@@ -804,7 +643,7 @@ __device__ __forceinline__ void rapply_huge_tile(double* smem, int tile, int n, 
 #pragma unroll
   for (int gm = 0; gm < PN; ++gm) G[gm] *= T.is2[gm];
 
-  // 4. step 2 by chunks of rows, corner sums and node sums as in rapply_big_tile
+  // 4. step 2 by chunks of rows; corner sums as in rapply_tile
   double wc, wo;
   r_corner_weights(comp, ql, xi, eta, wc, wo);
   int opq = 0;
@@ -863,18 +702,18 @@ __device__ __forceinline__ void rapply_huge_tile(double* smem, int tile, int n, 
 }
 
 template <int M, int p, bool FULL>
-__global__ __launch_bounds__(kRThreads) void rapply_huge_kernel(
+__global__ __launch_bounds__(kRThreads) void rapply_stream_kernel(
     int n, double mu, double a_min, const double* __restrict__ g, RApplyRows rr,
     const double* __restrict__ U, int64_t Nh, const double* __restrict__ rin, double beta,
     double sgn, double* __restrict__ out, double* __restrict__ edge) {
   extern __shared__ double smem[];
   const int nt = n / kTileE;
-  rapply_huge_tile<M, p, FULL>(smem, xcd_tile(blockIdx.x, nt * nt), n, mu, a_min, g, rr, U, Nh,
+  rapply_stream_tile<M, p, FULL>(smem, xcd_tile(blockIdx.x, nt * nt), n, mu, a_min, g, rr, U, Nh,
                                rin, beta, sgn, out, edge);
 }
 
 template <int M, int p>
-__global__ __launch_bounds__(kRThreads) void brapply_huge_kernel(
+__global__ __launch_bounds__(kRThreads) void brapply_stream_kernel(
     const BInst* __restrict__ Is, const BState* __restrict__ Ss, const BItem* __restrict__ items,
     int nitems, int rowset, int src, int rin, int dst, double beta, double sgn, int gate) {
   extern __shared__ double smem[];
@@ -885,43 +724,21 @@ __global__ __launch_bounds__(kRThreads) void brapply_huge_kernel(
   const BState& S = Ss[w.inst];
   if (gated(S, gate)) return;
   const RApplyRows& rr = rowset == 0 ? I.rfull : I.rpart[rowset];
-  rapply_huge_tile<M, p, false>(smem, w.local, I.n, I.mu, I.amin, gptr(I.gq), rr,
+  rapply_stream_tile<M, p, false>(smem, w.local, I.n, I.mu, I.amin, gptr(I.gq), rr,
                                 bbuf(I, S, src), I.Nh, rin >= 0 ? bbuf(I, S, rin) : nullptr,
                                 beta, sgn, bbuf(I, S, dst), gptr(I.edge));
 }
 
-#define SG_RAPPLY_HUGE_LIST(X) X(5, 4) X(6, 4)
+#define SG_RAPPLY_STREAM_LIST(X) X(5, 3) X(4, 4) X(6, 3) X(5, 4) X(6, 4)
 
-// (instance, tile) items of instances sharing one (M, p), P > kRSmall
-template <int M, int p>
-__global__ __launch_bounds__(kRThreads, 2) void brapply_big_kernel(
-    const BInst* __restrict__ Is, const BState* __restrict__ Ss, const BItem* __restrict__ items,
-    int nitems, int rowset, int src, int rin, int dst, double beta, double sgn, int gate) {
-  extern __shared__ double smem[];
-  const int it = blockIdx.x;  // one workgroup per item (grid = nitems)
-  if (it >= nitems) return;
-  const BItem w = items[it];
-  const BInst& I = Is[w.inst];
-  const BState& S = Ss[w.inst];
-  if (gated(S, gate)) return;
-  // read in place: the tile code loads the masks once into uniform registers,
-  // the slot and mode tables only in the node sums
-  const RApplyRows& rr = rowset == 0 ? I.rfull : I.rpart[rowset];
-  rapply_big_tile<M, p, false>(smem, w.local, I.n, I.mu, I.amin, gptr(I.gq), rr, bbuf(I, S, src),
-                               I.Nh, rin >= 0 ? bbuf(I, S, rin) : nullptr, beta, sgn,
-                               bbuf(I, S, dst), gptr(I.edge));
-}
-
-size_t rapply_big_lds_bytes(int P) {
+size_t rapply_stream_lds_bytes(int P) {
   return 8 * ((size_t)P * 25 + (size_t)2 * kRChunk * 64);
 }
 
-#define SG_RAPPLY_BIG_LIST(X) X(4, 4) X(5, 3) X(6, 3)
-
 // P <= kRSmall: the nodal values and, after them, the corner contributions of
-// both components; above, the layout of rapply_big_tile
+// both components; above, the layout of rapply_stream_tile
 size_t rapply_lds_bytes(int P, int nrows) {
-  if (P > kRSmall) return rapply_big_lds_bytes(P);
+  if (P > kRSmall) return rapply_stream_lds_bytes(P);
   return 8 * std::max((size_t)P * 25, (size_t)2 * nrows * 64);
 }
 
@@ -932,8 +749,7 @@ size_t rapply_lds_bytes(int P, int nrows) {
 bool rapply_supported(int M, int p) {
 #define SG_RAPPLY_SUP(MM, PP) if (M == MM && p == PP) return true;
   SG_RAPPLY_LIST(SG_RAPPLY_SUP)
-  SG_RAPPLY_BIG_LIST(SG_RAPPLY_SUP)
-  SG_RAPPLY_HUGE_LIST(SG_RAPPLY_SUP)
+  SG_RAPPLY_STREAM_LIST(SG_RAPPLY_SUP)
 #undef SG_RAPPLY_SUP
   return false;
 }
@@ -951,8 +767,7 @@ static bool rapply_check(const std::vector<std::vector<int>>& Jp) {
 bool rapply_matches(int M, int p, const std::vector<std::vector<int>>& Jp) {
 #define SG_RAPPLY_CHK(MM, PP) if (M == MM && p == PP) return rapply_check<MM, PP>(Jp);
   SG_RAPPLY_LIST(SG_RAPPLY_CHK)
-  SG_RAPPLY_BIG_LIST(SG_RAPPLY_CHK)
-  SG_RAPPLY_HUGE_LIST(SG_RAPPLY_CHK)
+  SG_RAPPLY_STREAM_LIST(SG_RAPPLY_CHK)
 #undef SG_RAPPLY_CHK
   return false;
 }
@@ -968,46 +783,26 @@ void launch_rapply(hipStream_t s, int M, int p, int n, double mu, double a_min, 
   for (int b = 0; full && b < P; ++b)
     full = rbit(rr.colmask, b) && rbit(rr.rowmask, b) && rbit(rr.gammask, b) && rr.slot[b] == b &&
            rr.mode[b] == b;
-#define SG_RAPPLY_BIG_LAUNCH(MM, PP)                                                           \
+#define SG_RAPPLY_STREAM_LAUNCH(MM, PP)                                                          \
   if (M == MM && p == PP) {                                                                    \
-    const size_t blds = rapply_big_lds_bytes(P);                                               \
+    const size_t blds = rapply_stream_lds_bytes(P);                                               \
     static const bool attr_ok =                                                                \
-        hipFuncSetAttribute((const void*)rapply_big_kernel<MM, PP, true>,                      \
+        hipFuncSetAttribute((const void*)rapply_stream_kernel<MM, PP, true>,                     \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)blds) == hipSuccess && \
-        hipFuncSetAttribute((const void*)rapply_big_kernel<MM, PP, false>,                     \
+        hipFuncSetAttribute((const void*)rapply_stream_kernel<MM, PP, false>,                    \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)blds) == hipSuccess; \
     if (!attr_ok) throw Error(SG_ERR_HIP, "register apply: LDS size attribute");               \
     if (full)                                                                                  \
-      hipLaunchKernelGGL((rapply_big_kernel<MM, PP, true>), dim3(ntiles), dim3(kRThreads),    \
+      hipLaunchKernelGGL((rapply_stream_kernel<MM, PP, true>), dim3(ntiles), dim3(kRThreads),   \
                          blds, s, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);      \
     else                                                                                       \
-      hipLaunchKernelGGL((rapply_big_kernel<MM, PP, false>), dim3(ntiles), dim3(kRThreads),   \
+      hipLaunchKernelGGL((rapply_stream_kernel<MM, PP, false>), dim3(ntiles), dim3(kRThreads),  \
                          blds, s, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);      \
     if (fixup) launch_apply_fixup(s, n, rr.nrows, sgn, edge, out, Nh);                         \
     return;                                                                                    \
   }
-  SG_RAPPLY_BIG_LIST(SG_RAPPLY_BIG_LAUNCH)
-#undef SG_RAPPLY_BIG_LAUNCH
-#define SG_RAPPLY_HUGE_LAUNCH(MM, PP)                                                          \
-  if (M == MM && p == PP) {                                                                    \
-    const size_t blds = rapply_big_lds_bytes(P);                                               \
-    static const bool attr_ok =                                                                \
-        hipFuncSetAttribute((const void*)rapply_huge_kernel<MM, PP, true>,                     \
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)blds) == hipSuccess && \
-        hipFuncSetAttribute((const void*)rapply_huge_kernel<MM, PP, false>,                    \
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)blds) == hipSuccess; \
-    if (!attr_ok) throw Error(SG_ERR_HIP, "register apply: LDS size attribute");               \
-    if (full)                                                                                  \
-      hipLaunchKernelGGL((rapply_huge_kernel<MM, PP, true>), dim3(ntiles), dim3(kRThreads),   \
-                         blds, s, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);      \
-    else                                                                                       \
-      hipLaunchKernelGGL((rapply_huge_kernel<MM, PP, false>), dim3(ntiles), dim3(kRThreads),  \
-                         blds, s, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);      \
-    if (fixup) launch_apply_fixup(s, n, rr.nrows, sgn, edge, out, Nh);                         \
-    return;                                                                                    \
-  }
-  SG_RAPPLY_HUGE_LIST(SG_RAPPLY_HUGE_LAUNCH)
-#undef SG_RAPPLY_HUGE_LAUNCH
+  SG_RAPPLY_STREAM_LIST(SG_RAPPLY_STREAM_LAUNCH)
+#undef SG_RAPPLY_STREAM_LAUNCH
   const size_t lds = rapply_lds_bytes(P, rr.nrows);
 #define SG_RAPPLY_LAUNCH(MM, PP)                                                              \
   if (M == MM && p == PP) {                                                                   \
@@ -1028,32 +823,19 @@ void launch_brapply(hipStream_t s, int M, int p, size_t lds, const BInst* I, con
                     double beta, double sgn, int gate) {
   if (nitems <= 0) return;
   const int grid = nitems;  // one workgroup per item, as in a single-instance launch
-#define SG_BRAPPLY_BIG_LAUNCH(MM, PP)                                                          \
+#define SG_BRAPPLY_STREAM_LAUNCH(MM, PP)                                                         \
   if (M == MM && p == PP) {                                                                    \
     static const bool attr_ok =                                                                \
-        hipFuncSetAttribute((const void*)brapply_big_kernel<MM, PP>,                           \
+        hipFuncSetAttribute((const void*)brapply_stream_kernel<MM, PP>,                          \
                             hipFuncAttributeMaxDynamicSharedMemorySize,                         \
-                            (int)rapply_big_lds_bytes(rc_binom(MM + PP, PP))) == hipSuccess;   \
+                            (int)rapply_stream_lds_bytes(rc_binom(MM + PP, PP))) == hipSuccess;   \
     if (!attr_ok) throw Error(SG_ERR_HIP, "batched register apply: LDS size attribute");      \
-    hipLaunchKernelGGL((brapply_big_kernel<MM, PP>), dim3(grid), dim3(kRThreads), lds, s, I,   \
+    hipLaunchKernelGGL((brapply_stream_kernel<MM, PP>), dim3(grid), dim3(kRThreads), lds, s, I,  \
                        st, items, nitems, rowset, src, rin, dst, beta, sgn, gate);             \
     return;                                                                                    \
   }
-  SG_RAPPLY_BIG_LIST(SG_BRAPPLY_BIG_LAUNCH)
-#undef SG_BRAPPLY_BIG_LAUNCH
-#define SG_BRAPPLY_HUGE_LAUNCH(MM, PP)                                                         \
-  if (M == MM && p == PP) {                                                                    \
-    static const bool attr_ok =                                                                \
-        hipFuncSetAttribute((const void*)brapply_huge_kernel<MM, PP>,                          \
-                            hipFuncAttributeMaxDynamicSharedMemorySize,                         \
-                            (int)rapply_big_lds_bytes(rc_binom(MM + PP, PP))) == hipSuccess;   \
-    if (!attr_ok) throw Error(SG_ERR_HIP, "batched register apply: LDS size attribute");      \
-    hipLaunchKernelGGL((brapply_huge_kernel<MM, PP>), dim3(grid), dim3(kRThreads), lds, s, I,  \
-                       st, items, nitems, rowset, src, rin, dst, beta, sgn, gate);             \
-    return;                                                                                    \
-  }
-  SG_RAPPLY_HUGE_LIST(SG_BRAPPLY_HUGE_LAUNCH)
-#undef SG_BRAPPLY_HUGE_LAUNCH
+  SG_RAPPLY_STREAM_LIST(SG_BRAPPLY_STREAM_LAUNCH)
+#undef SG_BRAPPLY_STREAM_LAUNCH
 #define SG_BRAPPLY_LAUNCH(MM, PP)                                                             \
   if (M == MM && p == PP) {                                                                   \
     hipLaunchKernelGGL((brapply_kernel<MM, PP>), dim3(grid), dim3(kRThreads), lds, s, I, st, items, \

@@ -151,6 +151,7 @@ def test_full_size_apply_sampled(cfg):
     ref = S.apply_at(U, modes, nodes)
     for form in ("auto", "triple"):
         G.set_apply(form, 0)
+        assert G.apply_form()[0] == (2 if form == "auto" else 0), (form, G.apply_form())
         W = to_host(G.apply(to_dev(U))).reshape(S.P, S.Nh)
         got = W[np.ix_(modes, nodes)]
         assert relmax(got, ref) < 1e-12, form
@@ -170,6 +171,7 @@ def test_full_size_largest_instance_sampled():
     nodes = _sample_nodes(prob.n, rng, 4)
     modes = [0, 1, 57, 209]
     ref = S.apply_at(U, modes, nodes)
+    assert G.apply_form() == (2, 0)     # the register-resident kernel, 4096 tiles
     W = to_host(G.apply(to_dev(U))).reshape(S.P, S.Nh)
     assert relmax(W[np.ix_(modes, nodes)], ref) < 1e-12
     G.close()
