@@ -37,8 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # scaled by the same counter read on a plain 256 MiB copy (factors 2.0 and 1.0).
 # Valid only for the kernel source the counters were taken on: the sha256 of
 # sg_rapply.hip + sg_internal.h is compared at run time.
-APPLY_TRAFFIC = {"src_sha256": "3bb1f36578f8b47c69fbec52d68102a546d9270f6ae06411e5e2b6cdc752cfef",
-                 "fetch_bytes": (3490.359375 + 4827.125) * 1024 * 2.0,
+APPLY_TRAFFIC = {"src_sha256": "9522d5ef5540fb0de6083b4c1cb75e255b26b748331664ba3b926e389c2840dc",
+                 "fetch_bytes": (3493.375 + 4827.125) * 1024 * 2.0,
                  "write_bytes": (6937.0 + 4377.4375) * 1024 * 1.0}
 
 
