@@ -1095,7 +1095,7 @@ __global__ __launch_bounds__(kDotThreads) void gs_dot_kernel(const double* __res
 }
 
 // w <- w + sign * sum_l h[l] V_l, then partial[l * nblk + b] = block b's part of
-// V_l . w (the new w), nv <= NVB <= 64: the basis values stay in registers
+// V_l . w (the new w), nv <= NVB <= 32: the basis values stay in registers
 // between the update and the dots, so V is read once for both.
 template <int NVB>
 __global__ __launch_bounds__(kDotThreads) void gs_update_dot_kernel(
@@ -1121,6 +1121,84 @@ __global__ __launch_bounds__(kDotThreads) void gs_update_dot_kernel(
   for (int l = 0; l < NVB; ++l) a[l] *= wi;
   wave_sums<NVB>(a, red + 64 * (threadIdx.x >> 6));
   block_partials(red, nv, partial, nblk, 0);
+}
+
+// partial[(l0 + l) * gridDim.x + b] = block b's part of V_{l0+l} . w with
+// l0 = kStreamVecs * blockIdx.y: a grid-stride loop over at most kStreamBlocks
+// blocks keeps kStreamVecs dot products per thread in registers, so a block
+// reduces once over many elements and the partials to sum are few.  Used for
+// nv > kStreamVecs, where it moves more bytes per second than one element per
+// thread with all nv values in registers.
+constexpr int kStreamBlocks = 512;
+constexpr int kStreamVecs = 16;
+__global__ __launch_bounds__(kDotThreads) void gs_dot_stream_kernel(
+    const double* __restrict__ V, int64_t ldv, int nv, const double* __restrict__ w, int64_t N,
+    double* __restrict__ partial, EdgeFix ef) {
+  __shared__ double red[4 * 64];
+  const int l0 = kStreamVecs * blockIdx.y;
+  const int cnt = min(nv - l0, kStreamVecs);
+  const double* Vb = V + (int64_t)l0 * ldv;
+  double acc[kStreamVecs];
+#pragma unroll
+  for (int l = 0; l < kStreamVecs; ++l) acc[l] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kDotThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kDotThreads) {
+    const double wi = w_fixed(w, i, ef);
+    double a[kStreamVecs];
+#pragma unroll
+    for (int l = 0; l < kStreamVecs; ++l) a[l] = l < cnt ? Vb[(int64_t)l * ldv + i] : 0.0;
+#pragma unroll
+    for (int l = 0; l < kStreamVecs; ++l) acc[l] = fma(a[l], wi, acc[l]);
+  }
+  wave_sums<kStreamVecs>(acc, red + 64 * (threadIdx.x >> 6));
+  block_partials(red, cnt, partial, gridDim.x, l0);
+}
+
+// The update-and-dots pass for 32 < nv <= 64 with each element shared by a lane
+// pair: the even lane holds V_0..V_31, the odd lane V_32..V_63, so a lane keeps
+// 32 basis values in registers rather than 64 and three times as many
+// wavefronts stay resident.  The two halves of sum_l h[l] V_l meet in one
+// exchange (a + b and b + a round alike, so both lanes hold the same new w);
+// a five-step butterfly over the other lane bits leaves lane L with the block
+// wavefront's sum for basis vector 32 * (L & 1) + (L >> 1).  A block of
+// 2 * kDotThreads threads covers kDotThreads elements, so the partials keep the
+// one-lane layout partial[l * nblk + b], nblk = gs_blocks(N).
+constexpr int kPairThreads = 2 * kDotThreads;
+__global__ __launch_bounds__(kPairThreads) void gs_update_dot_pair_kernel(
+    const double* __restrict__ V, int64_t ldv, int nv, const double* __restrict__ h,
+    double* __restrict__ w, int64_t N, double sign, double* __restrict__ partial, int nblk,
+    EdgeFix ef) {
+  __shared__ double red[8 * 64];
+  const int lane = threadIdx.x & 63;
+  const int q = lane & 1;
+  const int lb = 32 * q;
+  const int64_t i = (int64_t)blockIdx.x * kDotThreads + (threadIdx.x >> 1);
+  const bool in = i < N;
+  double a[32];
+#pragma unroll
+  for (int l = 0; l < 32; ++l) a[l] = (lb + l < nv && in) ? V[(int64_t)(lb + l) * ldv + i] : 0.0;
+  double acc = 0.0;
+#pragma unroll
+  for (int l = 0; l < 32; ++l) {
+    const double h0 = h[l];
+    const double h1 = 32 + l < nv ? h[32 + l] : 0.0;
+    acc = fma(q ? h1 : h0, a[l], acc);
+  }
+  acc += __shfl_xor(acc, 1);
+  double wi = 0.0;
+  if (in) {
+    wi = w_fixed(w, i, ef) + sign * acc;
+    if (q == 0) w[i] = wi;
+  }
+#pragma unroll
+  for (int l = 0; l < 32; ++l) a[l] *= wi;
+  wave_fold<16, 32, 32>(a, lane);
+  red[64 * (threadIdx.x >> 6) + 32 * q + (lane >> 1)] = a[0];
+  __syncthreads();
+  const int l = threadIdx.x;
+  if (l < nv)
+    partial[(int64_t)l * nblk + blockIdx.x] = ((red[l] + red[64 + l]) + (red[128 + l] + red[192 + l])) +
+                                              ((red[256 + l] + red[320 + l]) + (red[384 + l] + red[448 + l]));
 }
 
 // w <- w + sign * sum_l h[l] V_l, then partial[b] = block b's part of w . w;
@@ -1189,6 +1267,13 @@ __global__ __launch_bounds__(kDotThreads) void reduce_wide_kernel(const double* 
 
 void launch_gs_dot(hipStream_t s, const double* V, int64_t ldv, int nv, const double* w, int64_t N,
                    double* partial, double* out, const EdgeFix& ef) {
+  if (nv > kStreamVecs) {
+    const int nb = std::min(gs_blocks(N), kStreamBlocks);
+    hipLaunchKernelGGL(gs_dot_stream_kernel, dim3(nb, cdiv(nv, kStreamVecs)), dim3(kDotThreads), 0,
+                       s, V, ldv, nv, w, N, partial, ef);
+    hipLaunchKernelGGL(reduce_wide_kernel, dim3(nv), dim3(kDotThreads), 0, s, partial, nb, out);
+    return;
+  }
   const int nblk = gs_blocks(N);
   const int top = std::min(nv, 64);
   dim3 grid(nblk, cdiv(nv, 64)), block(kDotThreads);
@@ -1196,7 +1281,7 @@ void launch_gs_dot(hipStream_t s, const double* V, int64_t ldv, int nv, const do
   if (top <= B) {                                                                             \
     hipLaunchKernelGGL(gs_dot_kernel<B>, grid, block, 0, s, V, ldv, nv, w, N, partial, nblk, ef); \
   } else
-  SG_GS_DOT(1) SG_GS_DOT(2) SG_GS_DOT(4) SG_GS_DOT(8) SG_GS_DOT(16) SG_GS_DOT(32) SG_GS_DOT(64) {}
+  SG_GS_DOT(1) SG_GS_DOT(2) SG_GS_DOT(4) SG_GS_DOT(8) SG_GS_DOT(16) {}
 #undef SG_GS_DOT
   hipLaunchKernelGGL(reduce_wide_kernel, dim3(nv), block, 0, s, partial, nblk, out);
 }
@@ -1212,12 +1297,18 @@ void launch_gs_update_dot(hipStream_t s, const double* V, int64_t ldv, int nv, c
   }
   const int nblk = gs_blocks(N);
   dim3 grid(nblk), block(kDotThreads);
+  if (nv > 32) {
+    hipLaunchKernelGGL(gs_update_dot_pair_kernel, grid, dim3(kPairThreads), 0, s, V, ldv, nv, h, w,
+                       N, sign, partial, nblk, ef);
+    hipLaunchKernelGGL(reduce_wide_kernel, dim3(nv), block, 0, s, partial, nblk, out);
+    return;
+  }
 #define SG_GS_UD(B)                                                                          \
   if (nv <= B) {                                                                             \
     hipLaunchKernelGGL(gs_update_dot_kernel<B>, grid, block, 0, s, V, ldv, nv, h, w, N, sign, \
                        partial, nblk, ef);                                                   \
   } else
-  SG_GS_UD(1) SG_GS_UD(2) SG_GS_UD(4) SG_GS_UD(8) SG_GS_UD(16) SG_GS_UD(32) SG_GS_UD(64) {}
+  SG_GS_UD(1) SG_GS_UD(2) SG_GS_UD(4) SG_GS_UD(8) SG_GS_UD(16) SG_GS_UD(32) {}
 #undef SG_GS_UD
   hipLaunchKernelGGL(reduce_wide_kernel, dim3(nv), block, 0, s, partial, nblk, out);
 }
