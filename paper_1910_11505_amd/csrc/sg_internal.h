@@ -211,9 +211,13 @@ void launch_dense_coarse(hipStream_t s, int N, int m, const double* C, const dou
 void launch_unit_columns(hipStream_t s, int N, int j0, int m, double* out);
 bool rapply_supported(int M, int p);
 bool rapply_matches(int M, int p, const std::vector<std::vector<int>>& Jp);
+// kv > 0: rr is block kv of the field split by first KL variable (rows the modes
+// whose first variable is kv, columns those below it; checked by the caller),
+// which a kernel with that block's pairs compiled in serves when 35 < P
 void launch_rapply(hipStream_t s, int M, int p, int n, double mu, double a_min, const double* g,
                    const RApplyRows& rr, const double* U, int64_t Nh, const double* rin,
-                   double beta, double sgn, double* out, double* edge, bool fixup = true);
+                   double beta, double sgn, double* out, double* edge, bool fixup = true,
+                   int kv = 0);
 void launch_apply_fixup(hipStream_t s, int n, int nrows, double sgn, const double* edge,
                         double* out, int64_t Nh);
 size_t fapply_lds_bytes(int qb, int nrows, int ncols, int ngam, int nmono, int M, int nblob);

@@ -527,7 +527,112 @@ __global__ __launch_bounds__(kRThreads) void brapply_kernel(const BInst* __restr
 // ---------------------------------------------------------------------------
 constexpr int kRChunk = 16;
 constexpr int kRFence = 4;
-template <int M, int p, bool FULL>
+
+// Field-split blocks known at compile time.  With the splits taken by the
+// first KL variable a mode depends on (the mean with variable 0), the block of
+// split V >= 1 has the modes whose first variable is V as rows and those whose
+// first variable is below V as columns; which gammas it reads (below a row and
+// below a column) follows.  A block kernel built on these tables drops every
+// pair, gradient and row chunk the block does not need at compile time, where
+// run-time masks can only skip whole modes.
+// (internal linkage like the other tables, so that device code folds their
+// reads instead of loading a symbol the host could rewrite)
+namespace {
+template <int M, int p>
+struct RSel {
+  static constexpr int P = RTab<M, p>::P;
+  static constexpr int NT = RTab<M, p>::NT;
+  int row[P] = {}, col[P] = {}, gam[P] = {};
+  int chunk[(P + kRChunk - 1) / kRChunk] = {};
+  // the block's own pair lists (the whole operator's, filtered):
+  // step 1a: each gamma below p that the block reads, with its column alphas below p
+  int n1 = 0, g1[P] = {}, p1[P + 1] = {}, a1[NT] = {}, d1[NT] = {};
+  // step 1b: each column mode of degree p, with the gammas the block reads below it
+  int nq = 0, qa[P] = {}, pq[P + 1] = {}, qg[NT] = {}, qd[NT] = {};
+  // step 2: each row, with the gammas below p the block reads
+  int p2[P + 1] = {}, g2[NT] = {}, d2[NT] = {};
+};
+
+template <int M, int p, int V>
+constexpr RSel<M, p> rc_make_sel() {
+  const RTab<M, p>& T = RTabHolder<M, p>::v;
+  constexpr int P = RTab<M, p>::P;
+  RSel<M, p> S{};
+  int first[P] = {};
+  for (int i = 0; i < P; ++i) {
+    first[i] = 0;
+    for (int n = M - 1; n >= 0; --n)
+      if (T.J[i][n] != 0) first[i] = n;
+  }
+  for (int i = 0; i < P; ++i) {
+    S.row[i] = first[i] == V;
+    S.col[i] = first[i] < V;
+    if (S.row[i]) S.chunk[i / kRChunk] = 1;
+  }
+  for (int g = 0; g < P; ++g) {
+    bool br = false, bc = false;
+    for (int i = 0; i < P; ++i) {
+      bool le = true;
+      for (int n = 0; n < M; ++n) le = le && T.J[g][n] <= T.J[i][n];
+      if (le) {
+        br = br || S.row[i];
+        bc = bc || S.col[i];
+      }
+    }
+    S.gam[g] = br && bc;
+  }
+  const RTabTop<M, p>& Q = RTabTopHolder<M, p>::v;
+  constexpr int PN = RTabTop<M, p>::PN;
+  int k = 0;
+  for (int g = 0; g < PN; ++g) {
+    if (!S.gam[g]) continue;
+    S.g1[S.n1] = g;
+    S.p1[S.n1] = k;
+    for (int t = T.p1[g]; t < T.p1[g + 1]; ++t)
+      if (T.a1[t] < PN && S.col[T.a1[t]]) {
+        S.a1[k] = T.a1[t];
+        S.d1[k] = T.d1[t];
+        ++k;
+      }
+    ++S.n1;
+  }
+  S.p1[S.n1] = k;
+  k = 0;
+  for (int a = PN; a < P; ++a) {
+    if (!S.col[a]) continue;
+    S.qa[S.nq] = a;
+    S.pq[S.nq] = k;
+    for (int t = Q.pq[a - PN]; t < Q.pq[a - PN + 1]; ++t)
+      if (S.gam[Q.qg[t]]) {
+        S.qg[k] = Q.qg[t];
+        S.qd[k] = Q.qd[t];
+        ++k;
+      }
+    ++S.nq;
+  }
+  S.pq[S.nq] = k;
+  k = 0;
+  for (int b = 0; b < P; ++b) {
+    S.p2[b] = k;
+    if (!S.row[b]) continue;
+    for (int t = T.p2[b]; t < T.p2[b + 1]; ++t)
+      if (T.g2[t] < PN && S.gam[T.g2[t]]) {
+        S.g2[k] = T.g2[t];
+        S.d2[k] = T.d2[t];
+        ++k;
+      }
+  }
+  S.p2[P] = k;
+  return S;
+}
+
+template <int M, int p, int V>
+struct RSelHolder {
+  static constexpr RSel<M, p> v = rc_make_sel<M, p, V>();
+};
+}  // namespace
+
+template <int M, int p, bool FULL, int V = 0>
 __device__ __forceinline__ void rapply_stream_tile(double* smem, int tile, int n, double mu,
                                                  double a_min, const double* __restrict__ g,
                                                  const RApplyRows& rr,
@@ -541,6 +646,11 @@ __device__ __forceinline__ void rapply_stream_tile(double* smem, int tile, int n
   constexpr int PN = RTabTop<M, p>::PN;           // modes of degree below p
   constexpr int PL = rc_binom(M + p - 2, p - 2);  // monomials of degree below p - 1
   static_assert(P <= kRMax && p >= 2, "mask words, degree");
+  static_assert(V >= 0 && V < M && !(FULL && V > 0), "block selector");
+  // V > 0: the block of split V, rows, columns and gammas known at compile time
+  constexpr bool SEL = V > 0;
+  constexpr const RSel<M, p>& S = RSelHolder<M, p, SEL ? V : 1>::v;
+  constexpr int SN1 = S.n1, SNQ = S.nq;
   double* sN = smem;            // [P][25] nodal values
   double* sC = sN + P * 25;     // [2][kRChunk][64] corner contributions of a row chunk
   const int nt = n / kTileE, ntiles = nt * nt;
@@ -613,35 +723,60 @@ __device__ __forceinline__ void rapply_stream_tile(double* smem, int tile, int n
   const RGrad rg = r_grad_setup(comp, ql, el, xi, eta);
   double G[PN];
 #pragma unroll
-  for (int a = 0; a < PN; ++a) G[a] = T.s[a] * r_grad(rg, sN + a * 25);
+  for (int a = 0; a < PN; ++a) G[a] = (!SEL || S.col[a]) ? T.s[a] * r_grad(rg, sN + a * 25) : 0.0;
   double s2 = 0.0;
 #pragma unroll
   for (int nn = 0; nn < M; ++nn) s2 = fma(gv[nn], gv[nn], s2);
   const double w = exp(mu + 0.5 * s2);
 
   // 3a. step 1 over the pairs with alpha of degree below p, in place (unscaled)
+  if constexpr (SEL) {
+    // the block's gammas in ascending order: each reads only G[alpha],
+    // alpha >= gamma, not yet overwritten
 #pragma unroll
-  for (int gm = 0; gm < PN; ++gm) {
-    if (!FULL && !rbit(gmk, gm)) continue;
-    double sx = 0.0;
+    for (int i = 0; i < SN1; ++i) {
+      double sx = 0.0;
 #pragma unroll
-    for (int t = T.p1[gm]; t < T.p1[gm + 1]; ++t)
-      if (T.a1[t] < PN) sx = fma(mono_of(T.d1[t], gv), G[T.a1[t]], sx);
-    G[gm] = sx;
+      for (int t = S.p1[i]; t < S.p1[i + 1]; ++t) sx = fma(mono_of(S.d1[t], gv), G[S.a1[t]], sx);
+      G[S.g1[i]] = sx;
+    }
+  } else {
+#pragma unroll
+    for (int gm = 0; gm < PN; ++gm) {
+      if (!FULL && !rbit(gmk, gm)) continue;
+      double sx = 0.0;
+#pragma unroll
+      for (int t = T.p1[gm]; t < T.p1[gm + 1]; ++t)
+        if (T.a1[t] < PN) sx = fma(mono_of(T.d1[t], gv), G[T.a1[t]], sx);
+      G[gm] = sx;
+    }
   }
   __builtin_amdgcn_sched_barrier(0);
   // 3b. the degree-p modes, one at a time
+  if constexpr (SEL) {
 #pragma unroll
-  for (int a = PN; a < P; ++a) {
-    if (!col(a)) continue;
-    const double ga = T.s[a] * r_grad(rg, sN + a * 25);
+    for (int i = 0; i < SNQ; ++i) {
+      const double ga = T.s[S.qa[i]] * r_grad(rg, sN + S.qa[i] * 25);
 #pragma unroll
-    for (int k = Q.pq[a - PN]; k < Q.pq[a - PN + 1]; ++k)
-      G[Q.qg[k]] = fma(mono_of(Q.qd[k], gv), ga, G[Q.qg[k]]);
-    __builtin_amdgcn_sched_barrier(0);
+      for (int k = S.pq[i]; k < S.pq[i + 1]; ++k)
+        G[S.qg[k]] = fma(mono_of(S.qd[k], gv), ga, G[S.qg[k]]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int i = 0; i < SN1; ++i) G[S.g1[i]] *= T.is2[S.g1[i]];
+  } else {
+#pragma unroll
+    for (int a = PN; a < P; ++a) {
+      if (!col(a)) continue;
+      const double ga = T.s[a] * r_grad(rg, sN + a * 25);
+#pragma unroll
+      for (int k = Q.pq[a - PN]; k < Q.pq[a - PN + 1]; ++k)
+        G[Q.qg[k]] = fma(mono_of(Q.qd[k], gv), ga, G[Q.qg[k]]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int gm = 0; gm < PN; ++gm) G[gm] *= T.is2[gm];
   }
-#pragma unroll
-  for (int gm = 0; gm < PN; ++gm) G[gm] *= T.is2[gm];
 
   // 4. step 2 by chunks of rows; corner sums as in rapply_tile
   double wc, wo;
@@ -661,22 +796,35 @@ __device__ __forceinline__ void rapply_stream_tile(double* smem, int tile, int n
   const RNode nq = r_node(tid % 25, x0, y0, m);
 #pragma unroll
   for (int b0 = 0; b0 < P; b0 += kRChunk) {
+    if (SEL && !S.chunk[b0 / kRChunk]) continue;
 #pragma unroll
     for (int b = b0; b < (b0 + kRChunk < P ? b0 + kRChunk : P); ++b) {
-      if (!row(b)) continue;
+      if (SEL ? !S.row[b] : !row(b)) continue;
       double sx = 0.0;
+      if constexpr (SEL) {
 #pragma unroll
-      for (int t = T.p2[b]; t < T.p2[b + 1]; ++t)
-        if (T.g2[t] < PN) sx = fma(mono_of(T.d2[t], gv2), G[T.g2[t]], sx);
-      // the unscaled gradient of the row's mode: the a_min term, and for a
-      // degree-p row its own Vbar (gamma = beta, the list's last pair)
-      const double db = r_grad(rg2, sN + b * 25);
-      if (b >= PN) sx += (T.is2[b] * T.s[b]) * db;
-      double f = (T.s[b] * w) * sx;
-      if (FULL || col(b)) f = fma(a_min, db, f);
+        for (int t = S.p2[b]; t < S.p2[b + 1]; ++t) sx = fma(mono_of(S.d2[t], gv2), G[S.g2[t]], sx);
+      } else {
+#pragma unroll
+        for (int t = T.p2[b]; t < T.p2[b + 1]; ++t)
+          if (T.g2[t] < PN) sx = fma(mono_of(T.d2[t], gv2), G[T.g2[t]], sx);
+      }
+      double f;
+      if constexpr (SEL) {
+        // a compile-time block's rows are never its columns: no a_min term,
+        // and a degree-p row's own Vbar (its gradient) is zero
+        f = (T.s[b] * w) * sx;
+      } else {
+        // the unscaled gradient of the row's mode: the a_min term, and for a
+        // degree-p row its own Vbar (gamma = beta, the list's last pair)
+        const double db = r_grad(rg2, sN + b * 25);
+        if (b >= PN) sx += (T.is2[b] * T.s[b]) * db;
+        f = (T.s[b] * w) * sx;
+        if (FULL || col(b)) f = fma(a_min, db, f);
+      }
       const double t = wc * f + quad_xor<2>(wo * f);
       sCc[(b - b0) * 64 + lane] = t - quad_xor<1>(t);
-      if (!FULL || b % kRFence == kRFence - 1) __builtin_amdgcn_sched_barrier(0);
+      if ((!FULL && !SEL) || b % kRFence == kRFence - 1) __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
     if (tid < 125)
@@ -701,14 +849,14 @@ __device__ __forceinline__ void rapply_stream_tile(double* smem, int tile, int n
   }
 }
 
-template <int M, int p, bool FULL>
+template <int M, int p, bool FULL, int V = 0>
 __global__ __launch_bounds__(kRThreads) void rapply_stream_kernel(
     int n, double mu, double a_min, const double* __restrict__ g, RApplyRows rr,
     const double* __restrict__ U, int64_t Nh, const double* __restrict__ rin, double beta,
     double sgn, double* __restrict__ out, double* __restrict__ edge) {
   extern __shared__ double smem[];
   const int nt = n / kTileE;
-  rapply_stream_tile<M, p, FULL>(smem, xcd_tile(blockIdx.x, nt * nt), n, mu, a_min, g, rr, U, Nh,
+  rapply_stream_tile<M, p, FULL, V>(smem, xcd_tile(blockIdx.x, nt * nt), n, mu, a_min, g, rr, U, Nh,
                                rin, beta, sgn, out, edge);
 }
 
@@ -728,6 +876,45 @@ __global__ __launch_bounds__(kRThreads) void brapply_stream_kernel(
                                 bbuf(I, S, src), I.Nh, rin >= 0 ? bbuf(I, S, rin) : nullptr,
                                 beta, sgn, bbuf(I, S, dst), gptr(I.edge));
 }
+
+// The compile-time block kernel of split kv (1 <= kv < M) of one (M, p).  Each
+// (M, p) is instantiated in a translation unit of its own (sg_rapply_blocks_*)
+// so that the block kernels compile beside the rest of the library.
+template <int M, int p, int V = 1>
+void launch_rblock(hipStream_t s, int kv, int n, double mu, double a_min, const double* g,
+                   const RApplyRows& rr, const double* U, int64_t Nh, const double* rin,
+                   double beta, double sgn, double* out, double* edge) {
+  if constexpr (V < M) {
+    if (kv != V) {
+      launch_rblock<M, p, V + 1>(s, kv, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);
+      return;
+    }
+    const int nt = n / kTileE;
+    const size_t lds = 8 * ((size_t)25 * RTab<M, p>::P + 2 * kRChunk * 64);
+    static const bool attr_ok =
+        hipFuncSetAttribute((const void*)rapply_stream_kernel<M, p, false, V>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
+    if (!attr_ok) throw Error(SG_ERR_HIP, "register apply: LDS size attribute");
+    hipLaunchKernelGGL((rapply_stream_kernel<M, p, false, V>), dim3(nt * nt), dim3(kRThreads), lds,
+                       s, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);
+  } else {
+    throw Error(SG_ERR_INTERNAL, "register apply: block split");
+  }
+}
+
+#define SG_RBLOCK_DECL(MM, PP)                                                                  \
+  template void launch_rblock<MM, PP, 1>(hipStream_t, int, int, double, double, const double*,  \
+                                         const RApplyRows&, const double*, int64_t,             \
+                                         const double*, double, double, double*, double*);
+
+#ifndef SG_RAPPLY_BLOCK_TU
+#define SG_RBLOCK_EXTERN(MM, PP) extern SG_RBLOCK_DECL(MM, PP)
+SG_RBLOCK_EXTERN(5, 3)
+SG_RBLOCK_EXTERN(4, 4)
+SG_RBLOCK_EXTERN(6, 3)
+SG_RBLOCK_EXTERN(5, 4)
+SG_RBLOCK_EXTERN(6, 4)
+#undef SG_RBLOCK_EXTERN
 
 #define SG_RAPPLY_STREAM_LIST(X) X(5, 3) X(4, 4) X(6, 3) X(5, 4) X(6, 4)
 
@@ -774,7 +961,7 @@ bool rapply_matches(int M, int p, const std::vector<std::vector<int>>& Jp) {
 
 void launch_rapply(hipStream_t s, int M, int p, int n, double mu, double a_min, const double* g,
                    const RApplyRows& rr, const double* U, int64_t Nh, const double* rin,
-                   double beta, double sgn, double* out, double* edge, bool fixup) {
+                   double beta, double sgn, double* out, double* edge, bool fixup, int kv) {
   const int nt = n / kTileE, ntiles = nt * nt;
   const int P = (int)rc_binom(M + p, p);
   if (rr.nrows < 1 || rr.nrows > P) throw Error(SG_ERR_INTERNAL, "register apply: bad rows");
@@ -792,7 +979,9 @@ void launch_rapply(hipStream_t s, int M, int p, int n, double mu, double a_min, 
         hipFuncSetAttribute((const void*)rapply_stream_kernel<MM, PP, false>,                    \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)blds) == hipSuccess; \
     if (!attr_ok) throw Error(SG_ERR_HIP, "register apply: LDS size attribute");               \
-    if (full)                                                                                  \
+    if (!full && kv > 0)                                                                       \
+      launch_rblock<MM, PP>(s, kv, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);     \
+    else if (full)                                                                             \
       hipLaunchKernelGGL((rapply_stream_kernel<MM, PP, true>), dim3(ntiles), dim3(kRThreads),   \
                          blds, s, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);      \
     else                                                                                       \
@@ -844,5 +1033,7 @@ void launch_brapply(hipStream_t s, int M, int p, size_t lds, const BInst* I, con
   SG_RAPPLY_LIST(SG_BRAPPLY_LAUNCH) { throw Error(SG_ERR_INTERNAL, "batched register apply: (M, p)"); }
 #undef SG_BRAPPLY_LAUNCH
 }
+
+#endif  // SG_RAPPLY_BLOCK_TU
 
 }  // namespace sg
