@@ -37,8 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # scaled by the same counter read on a plain 256 MiB copy (factors 2.0 and 1.0).
 # Valid only for the kernel source the counters were taken on: the sha256 of
 # sg_rapply.hip + sg_internal.h is compared at run time.
-APPLY_TRAFFIC = {"src_sha256": "15363824156a022d126eaf926ce7acc12457f69c8dea406978420cce014cee44",
-                 "fetch_bytes": (3493.375 + 4827.125) * 1024 * 2.0,
+APPLY_TRAFFIC = {"src_sha256": "1458506e69837c61a55ef6c73334bcb701fb23ec61a927e8b5627158f302a983",
+                 "fetch_bytes": (3493.390625 + 4827.125) * 1024 * 2.0,
                  "write_bytes": (6937.0 + 4377.4375) * 1024 * 1.0}
 
 

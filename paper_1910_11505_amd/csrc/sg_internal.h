@@ -213,7 +213,7 @@ bool rapply_supported(int M, int p);
 bool rapply_matches(int M, int p, const std::vector<std::vector<int>>& Jp);
 // kv > 0: rr is block kv of the field split by first KL variable (rows the modes
 // whose first variable is kv, columns those below it; checked by the caller),
-// which a kernel with that block's pairs compiled in serves when 35 < P
+// which a kernel with that block's pairs compiled in serves
 void launch_rapply(hipStream_t s, int M, int p, int n, double mu, double a_min, const double* g,
                    const RApplyRows& rr, const double* U, int64_t Nh, const double* rin,
                    double beta, double sgn, double* out, double* edge, bool fixup = true,

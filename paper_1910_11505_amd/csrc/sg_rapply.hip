@@ -325,208 +325,8 @@ __device__ __forceinline__ double r_node_sum(const RNode& q, const double* c, co
   return sum;
 }
 
-// FULL: every mode is a row and a column, in order (the whole operator); the
-// masks and slot tables are then compile-time constants.
-template <int M, int p, bool FULL = false>
-__device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, double mu,
-                                            double a_min, const double* __restrict__ g,
-                                            const RApplyRows& rr, const double* __restrict__ U,
-                                            int64_t Nh, const double* __restrict__ rin,
-                                            double beta, double sgn, double* __restrict__ out,
-                                            double* __restrict__ edge) {
-  constexpr const RTab<M, p>& T = RTabHolder<M, p>::v;
-  constexpr int P = RTab<M, p>::P;
-  static_assert(P <= 64, "one mask word");
-  constexpr uint64_t kAll = P >= 64 ? ~0ull : ((1ull << P) - 1);
-  const int nrows = FULL ? P : rr.nrows;
-  double* sN = smem;  // [P][25] nodal values (steps 1-2)
-  double* sC = smem;  // [2][nrows][64] corner contributions (steps 4-5)
-  const int nt = n / kTileE, ntiles = nt * nt;
-  const int tx = tile % nt, ty = tile / nt;
-  const int x0 = tx * kTileE, y0 = ty * kTileE;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int comp = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int qp = r_lane_qp(lane, comp), pt = (lane & ~3) | qp;  // the lane's Gauss point
-  const int m = n - 1;
-  const int64_t Nq = (int64_t)4 * n * n;
-  // (the column and gamma masks stay run-time values: known, the unrolled
-  // gradient and step-1 code is scheduled with more values live than fit)
-  const uint64_t colmask = rr.colmask[0], rowmask = FULL ? kAll : rr.rowmask[0];
-  // output slot of each row, read once as whole words (uniform registers)
-  uint32_t slotw[(P + 3) / 4];
-#pragma unroll
-  for (int k = 0; k < (P + 3) / 4; ++k)
-    slotw[k] = FULL ? 0u : reinterpret_cast<const uint32_t*>(rr.slot)[k];
-  auto slot_of = [&](int b) {
-    return FULL ? b : (int)((slotw[b >> 2] >> (8 * (b & 3))) & 0xFFu);
-  };
-
-  // 1. nodal values of the column modes (all loads in flight at once)
-  constexpr int NL = (P * 25 + kRThreads - 1) / kRThreads;
-  double v[NL];
-#pragma unroll
-  for (int u = 0; u < NL; ++u) {
-    const int idx = tid + kRThreads * u;
-    const int c = min(idx / 25, P - 1), nd = idx - (idx / 25) * 25;
-    const int gx = x0 + nd % 5, gy = y0 + nd / 5;
-    const bool ok = idx < P * 25 && ((colmask >> c) & 1) && gx >= 1 && gx <= m && gy >= 1 && gy <= m;
-    v[u] = ok ? U[(int64_t)c * Nh + (int64_t)(gy - 1) * m + (gx - 1)] : 0.0;
-  }
-  double gv[M];
-#pragma unroll
-  for (int nn = 0; nn < M; ++nn) gv[nn] = g[(int64_t)nn * Nq + (int64_t)tile * kTileQ + pt];
-#pragma unroll
-  for (int u = 0; u < NL; ++u)
-    if (tid + kRThreads * u < P * 25) sN[tid + kRThreads * u] = v[u];
-  __syncthreads();
-
-  // 2. gradient component c (r_grad), w, monomials
-  const int el = lane >> 2, ql = qp;
-  const double xi = r_gauss_pt(ql & 1), eta = r_gauss_pt(ql >> 1);
-  const RGrad rg = r_grad_setup(comp, ql, el, xi, eta);
-  double G[P], Gc[P];  // Gc: unscaled component, for the a_min term of column rows
-  // no test of the column mask: the nodal values of other modes were stored as
-  // zeros, so their gradients are zero, and no branch separates the modes' reads
-#pragma unroll
-  for (int a = 0; a < P; ++a) {
-    const double d = r_grad(rg, sN + a * 25);
-    G[a] = T.s[a] * d;
-    Gc[a] = d;
-  }
-  double s2 = 0.0;
-#pragma unroll
-  for (int nn = 0; nn < M; ++nn) s2 = fma(gv[nn], gv[nn], s2);
-  const double w = exp(mu + 0.5 * s2);
-  double mono[P];
-  mono[0] = 1.0;
-#pragma unroll
-  for (int d = 1; d < P; ++d) mono[d] = mono[T.par[d]] * gv[T.var[d]] * T.inv[d];
-  __syncthreads();  // both wavefronts are done with the nodal values
-
-  // 3. step 1 in place
-  // gamma outside the block's set: never read by step 2, or zero (then no column
-  // lies above it, so its slot already holds zero)
-  const uint64_t gammask = rr.gammask[0];
-#pragma unroll
-  for (int gm = 0; gm < P; ++gm) {
-    if (!((gammask >> gm) & 1)) continue;
-    double sx = 0.0;
-#pragma unroll
-    for (int t = T.p1[gm]; t < T.p1[gm + 1]; ++t) sx = fma(mono[T.d1[t]], G[T.a1[t]], sx);
-    G[gm] = sx * T.is2[gm];
-  }
-  // keep the scheduler from interleaving the phases (register pressure)
-  __builtin_amdgcn_sched_barrier(0);
-
-  // 4. step 2 and the corner contributions of every output row: the partial
-  // sum with the lane two apart, then the signed sum with the neighbour lane
-  // (see r_lane_qp); lane j of an element ends with its corner r_lane_qp(j, c)
-  double wc, wo;
-  r_corner_weights(comp, ql, xi, eta, wc, wo);
-  double* sCc = sC + comp * nrows * 64;
-#pragma unroll
-  for (int b = 0; b < P; ++b) {
-    if (!((rowmask >> b) & 1)) continue;
-    double sx = 0.0;
-#pragma unroll
-    for (int t = T.p2[b]; t < T.p2[b + 1]; ++t) sx = fma(mono[T.d2[t]], G[T.g2[t]], sx);
-    const double sr = T.s[b] * w;
-    double f = sr * sx;
-    if (FULL || ((colmask >> b) & 1)) f = fma(a_min, Gc[b], f);
-    const double t = wc * f + quad_xor<2>(wo * f);
-    sCc[slot_of(b) * 64 + lane] = t - quad_xor<1>(t);
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  __syncthreads();
-
-  // 5. node sums: thread t takes node t % 25 of slots t / 25, t / 25 + 5, ...
-  // (threads 125-127 have none), so a node's geometry is worked out once
-  if (tid < 125) {
-    const RNode q = r_node(tid % 25, x0, y0, m);
-#pragma unroll
-    for (int k = 0; k < (P + 4) / 5; ++k) {
-      const int slot = tid / 25 + 5 * k;
-      if (slot >= nrows) break;
-      const double* c = sC + slot * 64;
-      const double sum = r_node_sum(q, c, c + nrows * 64);
-      if (q.owned) {
-        if (q.write) {
-          double base = 0.0;
-          if (beta != 0.0) base = beta * rin[(int64_t)(FULL ? slot : rr.mode[slot]) * Nh + q.node];
-          out[(int64_t)slot * Nh + q.node] = base + sgn * sum;
-        }
-      } else {
-        edge[((int64_t)slot * ntiles + tile) * kEdgeVals + q.e] = sum;
-      }
-    }
-  }
-}
-
-template <int M, int p, bool FULL>
-__global__ __launch_bounds__(kRThreads, 2) void rapply_kernel(int n, double mu, double a_min,
-                                                    const double* __restrict__ g, RApplyRows rr,
-                                                    const double* __restrict__ U, int64_t Nh,
-                                                    const double* __restrict__ rin, double beta,
-                                                    double sgn, double* __restrict__ out,
-                                                    double* __restrict__ edge) {
-  extern __shared__ double smem[];
-  const int nt = n / kTileE;
-  rapply_tile<M, p, FULL>(smem, xcd_tile(blockIdx.x, nt * nt), n, mu, a_min, g, rr, U, Nh, rin,
-                          beta, sgn, out, edge);
-}
-
-// (instance, tile) items of instances sharing one (M, p)
-template <int M, int p>
-__global__ __launch_bounds__(kRThreads) void brapply_kernel(const BInst* __restrict__ Is,
-                                                     const BState* __restrict__ Ss,
-                                                     const BItem* __restrict__ items, int nitems,
-                                                     int rowset, int src, int rin, int dst,
-                                                     double beta, double sgn, int gate) {
-  extern __shared__ double smem[];
-  // one workgroup per item (grid = nitems)
-  {
-    const int it = blockIdx.x;
-    if (it >= nitems) return;
-    const BItem w = items[it];
-    const BInst& I = Is[w.inst];
-    const BState& S = Ss[w.inst];
-    if (gated(S, gate)) return;
-    // read in place: the tile code loads the masks and slot words once into
-    // uniform registers, the mode table only in the node sums
-    const RApplyRows& rr = rowset == 0 ? I.rfull : I.rpart[rowset];
-    rapply_tile<M, p>(smem, w.local, I.n, I.mu, I.amin, gptr(I.gq), rr, bbuf(I, S, src), I.Nh,
-                      rin >= 0 ? bbuf(I, S, rin) : nullptr, beta, sgn, bbuf(I, S, dst),
-                      gptr(I.edge));
-  }
-}
-
-// ---------------------------------------------------------------------------
-// The same operator for larger chaos spaces (35 < P <= 210), where the P
-// gradients and P monomials of a point no longer fit a lane together.  It
-// rests on the degree structure of the contraction: a step-1 output gamma of
-// degree d needs m_delta with |delta| <= p - d, and a step-2 row beta needs a
-// degree-p monomial only for its gamma = 0 term, so a degree-p mode alpha
-// enters step 1 only through the Vbar_gamma below it and step 2 only through
-// its own row (Vbar_alpha is its scaled gradient alone).
-//  - Only the modes of degree below p keep their gradient (then Vbar) in
-//    registers, and only the monomials of degree below p - 1; degree p - 1
-//    and p monomials are formed where used from their parents (the same
-//    products, in the same order, as the recurrence).
-//  - Step 1 first sums the pairs with alpha of degree below p in place, then
-//    streams the degree-p modes: each one's gradient is recomputed from the
-//    nodal values (one read and two DPP exchanges) and added to every
-//    Vbar_gamma below it (the pairs grouped by alpha, RTabTop).
-//  - Step 2 recomputes a degree-p row's gradient for its gamma = beta term
-//    and, for every row, the a_min term's gradient, through an offset the
-//    compiler cannot equate with the gradient loop's; its monomials come from
-//    copies of g it cannot equate with step 1's (either way it would keep
-//    step-1 values alive through step 2 and spill).
-//  - Output rows go in chunks of kRChunk: corner sums to LDS, barrier, node
-//    sums, barrier.  For the whole operator the rows carry no branches and are
-//    scheduled kRFence at a time between fences.
-// ---------------------------------------------------------------------------
-constexpr int kRChunk = 16;
-constexpr int kRFence = 4;
+constexpr int kRChunk = 16;  // output rows per corner-sum chunk of the streamed tile
+constexpr int kRFence = 4;   // rows between its scheduling fences
 
 // Field-split blocks known at compile time.  With the splits taken by the
 // first KL variable a mode depends on (the mean with variable 0), the block of
@@ -632,6 +432,216 @@ struct RSelHolder {
 };
 }  // namespace
 
+// FULL: every mode is a row and a column, in order (the whole operator); the
+// masks and slot tables are then compile-time constants.
+template <int M, int p, bool FULL = false, int V = 0>
+__device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, double mu,
+                                            double a_min, const double* __restrict__ g,
+                                            const RApplyRows& rr, const double* __restrict__ U,
+                                            int64_t Nh, const double* __restrict__ rin,
+                                            double beta, double sgn, double* __restrict__ out,
+                                            double* __restrict__ edge) {
+  constexpr const RTab<M, p>& T = RTabHolder<M, p>::v;
+  constexpr int P = RTab<M, p>::P;
+  static_assert(P <= 64, "one mask word");
+  constexpr uint64_t kAll = P >= 64 ? ~0ull : ((1ull << P) - 1);
+  const int nrows = FULL ? P : rr.nrows;
+  double* sN = smem;  // [P][25] nodal values (steps 1-2)
+  double* sC = smem;  // [2][nrows][64] corner contributions (steps 4-5)
+  const int nt = n / kTileE, ntiles = nt * nt;
+  const int tx = tile % nt, ty = tile / nt;
+  const int x0 = tx * kTileE, y0 = ty * kTileE;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int comp = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int qp = r_lane_qp(lane, comp), pt = (lane & ~3) | qp;  // the lane's Gauss point
+  const int m = n - 1;
+  const int64_t Nq = (int64_t)4 * n * n;
+  // (the column and gamma masks stay run-time values: known, the unrolled
+  // gradient and step-1 code is scheduled with more values live than fit)
+  const uint64_t colmask = rr.colmask[0], rowmask = FULL ? kAll : rr.rowmask[0];
+  // output slot of each row, read once as whole words (uniform registers)
+  uint32_t slotw[(P + 3) / 4];
+#pragma unroll
+  for (int k = 0; k < (P + 3) / 4; ++k)
+    slotw[k] = FULL ? 0u : reinterpret_cast<const uint32_t*>(rr.slot)[k];
+  auto slot_of = [&](int b) {
+    return FULL ? b : (int)((slotw[b >> 2] >> (8 * (b & 3))) & 0xFFu);
+  };
+
+  // 1. nodal values of the column modes (all loads in flight at once)
+  constexpr int NL = (P * 25 + kRThreads - 1) / kRThreads;
+  double v[NL];
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int idx = tid + kRThreads * u;
+    const int c = min(idx / 25, P - 1), nd = idx - (idx / 25) * 25;
+    const int gx = x0 + nd % 5, gy = y0 + nd / 5;
+    const bool ok = idx < P * 25 && ((colmask >> c) & 1) && gx >= 1 && gx <= m && gy >= 1 && gy <= m;
+    v[u] = ok ? U[(int64_t)c * Nh + (int64_t)(gy - 1) * m + (gx - 1)] : 0.0;
+  }
+  double gv[M];
+#pragma unroll
+  for (int nn = 0; nn < M; ++nn) gv[nn] = g[(int64_t)nn * Nq + (int64_t)tile * kTileQ + pt];
+#pragma unroll
+  for (int u = 0; u < NL; ++u)
+    if (tid + kRThreads * u < P * 25) sN[tid + kRThreads * u] = v[u];
+  __syncthreads();
+
+  // 2. gradient component c (r_grad), w, monomials
+  const int el = lane >> 2, ql = qp;
+  const double xi = r_gauss_pt(ql & 1), eta = r_gauss_pt(ql >> 1);
+  const RGrad rg = r_grad_setup(comp, ql, el, xi, eta);
+  // V > 0: the field-split block of split V, rows, columns and gammas known at
+  // compile time (RSel); its rows are never its columns
+  static_assert(V >= 0 && (V == 0 || (V < M && !FULL)), "block selector");
+  constexpr bool SEL = V > 0;
+  constexpr const RSel<M, p>& S = RSelHolder<M, p, V>::v;
+  double G[P], Gc[P];  // Gc: unscaled component, for the a_min term of column rows
+  // no test of the run-time column mask: the nodal values of other modes were
+  // stored as zeros, so their gradients are zero, and no branch separates the
+  // modes' reads
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    const double d = (!SEL || S.col[a]) ? r_grad(rg, sN + a * 25) : 0.0;
+    G[a] = T.s[a] * d;
+    Gc[a] = d;
+  }
+  double s2 = 0.0;
+#pragma unroll
+  for (int nn = 0; nn < M; ++nn) s2 = fma(gv[nn], gv[nn], s2);
+  const double w = exp(mu + 0.5 * s2);
+  double mono[P];
+  mono[0] = 1.0;
+#pragma unroll
+  for (int d = 1; d < P; ++d) mono[d] = mono[T.par[d]] * gv[T.var[d]] * T.inv[d];
+  __syncthreads();  // both wavefronts are done with the nodal values
+
+  // 3. step 1 in place
+  // gamma outside the block's set: never read by step 2, or zero (then no column
+  // lies above it, so its slot already holds zero)
+  const uint64_t gammask = rr.gammask[0];
+#pragma unroll
+  for (int gm = 0; gm < P; ++gm) {
+    if (SEL ? !S.gam[gm] : !((gammask >> gm) & 1)) continue;
+    double sx = 0.0;
+#pragma unroll
+    for (int t = T.p1[gm]; t < T.p1[gm + 1]; ++t)
+      if (!SEL || S.col[T.a1[t]]) sx = fma(mono[T.d1[t]], G[T.a1[t]], sx);
+    G[gm] = sx * T.is2[gm];
+  }
+  // keep the scheduler from interleaving the phases (register pressure)
+  __builtin_amdgcn_sched_barrier(0);
+
+  // 4. step 2 and the corner contributions of every output row: the partial
+  // sum with the lane two apart, then the signed sum with the neighbour lane
+  // (see r_lane_qp); lane j of an element ends with its corner r_lane_qp(j, c)
+  double wc, wo;
+  r_corner_weights(comp, ql, xi, eta, wc, wo);
+  double* sCc = sC + comp * nrows * 64;
+#pragma unroll
+  for (int b = 0; b < P; ++b) {
+    if (SEL ? !S.row[b] : !((rowmask >> b) & 1)) continue;
+    double sx = 0.0;
+#pragma unroll
+    for (int t = T.p2[b]; t < T.p2[b + 1]; ++t)
+      if (!SEL || S.gam[T.g2[t]]) sx = fma(mono[T.d2[t]], G[T.g2[t]], sx);
+    const double sr = T.s[b] * w;
+    double f = sr * sx;
+    if (FULL || (!SEL && ((colmask >> b) & 1))) f = fma(a_min, Gc[b], f);
+    const double t = wc * f + quad_xor<2>(wo * f);
+    sCc[slot_of(b) * 64 + lane] = t - quad_xor<1>(t);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  __syncthreads();
+
+  // 5. node sums: thread t takes node t % 25 of slots t / 25, t / 25 + 5, ...
+  // (threads 125-127 have none), so a node's geometry is worked out once
+  if (tid < 125) {
+    const RNode q = r_node(tid % 25, x0, y0, m);
+#pragma unroll
+    for (int k = 0; k < (P + 4) / 5; ++k) {
+      const int slot = tid / 25 + 5 * k;
+      if (slot >= nrows) break;
+      const double* c = sC + slot * 64;
+      const double sum = r_node_sum(q, c, c + nrows * 64);
+      if (q.owned) {
+        if (q.write) {
+          double base = 0.0;
+          if (beta != 0.0) base = beta * rin[(int64_t)(FULL ? slot : rr.mode[slot]) * Nh + q.node];
+          out[(int64_t)slot * Nh + q.node] = base + sgn * sum;
+        }
+      } else {
+        edge[((int64_t)slot * ntiles + tile) * kEdgeVals + q.e] = sum;
+      }
+    }
+  }
+}
+
+template <int M, int p, bool FULL, int V = 0>
+__global__ __launch_bounds__(kRThreads, 2) void rapply_kernel(int n, double mu, double a_min,
+                                                    const double* __restrict__ g, RApplyRows rr,
+                                                    const double* __restrict__ U, int64_t Nh,
+                                                    const double* __restrict__ rin, double beta,
+                                                    double sgn, double* __restrict__ out,
+                                                    double* __restrict__ edge) {
+  extern __shared__ double smem[];
+  const int nt = n / kTileE;
+  rapply_tile<M, p, FULL, V>(smem, xcd_tile(blockIdx.x, nt * nt), n, mu, a_min, g, rr, U, Nh, rin,
+                          beta, sgn, out, edge);
+}
+
+// (instance, tile) items of instances sharing one (M, p)
+template <int M, int p>
+__global__ __launch_bounds__(kRThreads) void brapply_kernel(const BInst* __restrict__ Is,
+                                                     const BState* __restrict__ Ss,
+                                                     const BItem* __restrict__ items, int nitems,
+                                                     int rowset, int src, int rin, int dst,
+                                                     double beta, double sgn, int gate) {
+  extern __shared__ double smem[];
+  // one workgroup per item (grid = nitems)
+  {
+    const int it = blockIdx.x;
+    if (it >= nitems) return;
+    const BItem w = items[it];
+    const BInst& I = Is[w.inst];
+    const BState& S = Ss[w.inst];
+    if (gated(S, gate)) return;
+    // read in place: the tile code loads the masks and slot words once into
+    // uniform registers, the mode table only in the node sums
+    const RApplyRows& rr = rowset == 0 ? I.rfull : I.rpart[rowset];
+    rapply_tile<M, p>(smem, w.local, I.n, I.mu, I.amin, gptr(I.gq), rr, bbuf(I, S, src), I.Nh,
+                      rin >= 0 ? bbuf(I, S, rin) : nullptr, beta, sgn, bbuf(I, S, dst),
+                      gptr(I.edge));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The same operator for larger chaos spaces (35 < P <= 210), where the P
+// gradients and P monomials of a point no longer fit a lane together.  It
+// rests on the degree structure of the contraction: a step-1 output gamma of
+// degree d needs m_delta with |delta| <= p - d, and a step-2 row beta needs a
+// degree-p monomial only for its gamma = 0 term, so a degree-p mode alpha
+// enters step 1 only through the Vbar_gamma below it and step 2 only through
+// its own row (Vbar_alpha is its scaled gradient alone).
+//  - Only the modes of degree below p keep their gradient (then Vbar) in
+//    registers, and only the monomials of degree below p - 1; degree p - 1
+//    and p monomials are formed where used from their parents (the same
+//    products, in the same order, as the recurrence).
+//  - Step 1 first sums the pairs with alpha of degree below p in place, then
+//    streams the degree-p modes: each one's gradient is recomputed from the
+//    nodal values (one read and two DPP exchanges) and added to every
+//    Vbar_gamma below it (the pairs grouped by alpha, RTabTop).
+//  - Step 2 recomputes a degree-p row's gradient for its gamma = beta term
+//    and, for every row, the a_min term's gradient, through an offset the
+//    compiler cannot equate with the gradient loop's; its monomials come from
+//    copies of g it cannot equate with step 1's (either way it would keep
+//    step-1 values alive through step 2 and spill).
+//  - Output rows go in chunks of kRChunk: corner sums to LDS, barrier, node
+//    sums, barrier.  For the whole operator the rows carry no branches and are
+//    scheduled kRFence at a time between fences.
+// ---------------------------------------------------------------------------
+
+
 template <int M, int p, bool FULL, int V = 0>
 __device__ __forceinline__ void rapply_stream_tile(double* smem, int tile, int n, double mu,
                                                  double a_min, const double* __restrict__ g,
@@ -649,7 +659,7 @@ __device__ __forceinline__ void rapply_stream_tile(double* smem, int tile, int n
   static_assert(V >= 0 && V < M && !(FULL && V > 0), "block selector");
   // V > 0: the block of split V, rows, columns and gammas known at compile time
   constexpr bool SEL = V > 0;
-  constexpr const RSel<M, p>& S = RSelHolder<M, p, SEL ? V : 1>::v;
+  constexpr const RSel<M, p>& S = RSelHolder<M, p, V>::v;
   constexpr int SN1 = S.n1, SNQ = S.nq;
   double* sN = smem;            // [P][25] nodal values
   double* sC = sN + P * 25;     // [2][kRChunk][64] corner contributions of a row chunk
@@ -890,13 +900,20 @@ void launch_rblock(hipStream_t s, int kv, int n, double mu, double a_min, const 
       return;
     }
     const int nt = n / kTileE;
-    const size_t lds = 8 * ((size_t)25 * RTab<M, p>::P + 2 * kRChunk * 64);
-    static const bool attr_ok =
-        hipFuncSetAttribute((const void*)rapply_stream_kernel<M, p, false, V>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
-    if (!attr_ok) throw Error(SG_ERR_HIP, "register apply: LDS size attribute");
-    hipLaunchKernelGGL((rapply_stream_kernel<M, p, false, V>), dim3(nt * nt), dim3(kRThreads), lds,
-                       s, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);
+    constexpr int P = RTab<M, p>::P;
+    if constexpr (P > kRSmall) {
+      const size_t lds = 8 * ((size_t)25 * P + 2 * kRChunk * 64);
+      static const bool attr_ok =
+          hipFuncSetAttribute((const void*)rapply_stream_kernel<M, p, false, V>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
+      if (!attr_ok) throw Error(SG_ERR_HIP, "register apply: LDS size attribute");
+      hipLaunchKernelGGL((rapply_stream_kernel<M, p, false, V>), dim3(nt * nt), dim3(kRThreads),
+                         lds, s, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);
+    } else {
+      const size_t lds = 8 * (size_t)std::max(25 * P, 2 * rr.nrows * 64);
+      hipLaunchKernelGGL((rapply_kernel<M, p, false, V>), dim3(nt * nt), dim3(kRThreads), lds, s,
+                         n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);
+    }
   } else {
     throw Error(SG_ERR_INTERNAL, "register apply: block split");
   }
@@ -907,16 +924,16 @@ void launch_rblock(hipStream_t s, int kv, int n, double mu, double a_min, const 
                                          const RApplyRows&, const double*, int64_t,             \
                                          const double*, double, double, double*, double*);
 
+#define SG_RAPPLY_STREAM_LIST(X) X(5, 3) X(4, 4) X(6, 3) X(5, 4) X(6, 4)
+#define SG_RAPPLY_LIST(X) \
+  X(1, 1) X(1, 2) X(1, 3) X(1, 4) X(2, 1) X(2, 2) X(2, 3) X(2, 4) X(3, 1) X(3, 2) X(3, 3) \
+  X(3, 4) X(4, 1) X(4, 2) X(4, 3) X(5, 1) X(5, 2) X(6, 1) X(6, 2)
+
 #ifndef SG_RAPPLY_BLOCK_TU
 #define SG_RBLOCK_EXTERN(MM, PP) extern SG_RBLOCK_DECL(MM, PP)
-SG_RBLOCK_EXTERN(5, 3)
-SG_RBLOCK_EXTERN(4, 4)
-SG_RBLOCK_EXTERN(6, 3)
-SG_RBLOCK_EXTERN(5, 4)
-SG_RBLOCK_EXTERN(6, 4)
+SG_RAPPLY_STREAM_LIST(SG_RBLOCK_EXTERN)
+SG_RAPPLY_LIST(SG_RBLOCK_EXTERN)
 #undef SG_RBLOCK_EXTERN
-
-#define SG_RAPPLY_STREAM_LIST(X) X(5, 3) X(4, 4) X(6, 3) X(5, 4) X(6, 4)
 
 size_t rapply_stream_lds_bytes(int P) {
   return 8 * ((size_t)P * 25 + (size_t)2 * kRChunk * 64);
@@ -929,9 +946,6 @@ size_t rapply_lds_bytes(int P, int nrows) {
   return 8 * std::max((size_t)P * 25, (size_t)2 * nrows * 64);
 }
 
-#define SG_RAPPLY_LIST(X) \
-  X(1, 1) X(1, 2) X(1, 3) X(1, 4) X(2, 1) X(2, 2) X(2, 3) X(2, 4) X(3, 1) X(3, 2) X(3, 3) \
-  X(3, 4) X(4, 1) X(4, 2) X(4, 3) X(5, 1) X(5, 2) X(6, 1) X(6, 2)
 
 bool rapply_supported(int M, int p) {
 #define SG_RAPPLY_SUP(MM, PP) if (M == MM && p == PP) return true;
@@ -998,6 +1012,8 @@ void launch_rapply(hipStream_t s, int M, int p, int n, double mu, double a_min, 
     if (full)                                                                                 \
       hipLaunchKernelGGL((rapply_kernel<MM, PP, true>), dim3(ntiles), dim3(kRThreads), lds, s, \
                          n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);              \
+    else if (kv > 0)                                                                          \
+      launch_rblock<MM, PP>(s, kv, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);    \
     else                                                                                      \
       hipLaunchKernelGGL((rapply_kernel<MM, PP, false>), dim3(ntiles), dim3(kRThreads), lds,  \
                          s, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);           \
