@@ -70,6 +70,8 @@ def _args():
                          "mean-based and field-split preconditioners")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-stage comparison (learned workload, reduced training)")
+    ap.add_argument("--fs-large", action="store_true",
+                    help="also time field-split iterations on the 256x256, P=210 instance")
     ap.add_argument("--learned-pairs", type=int, default=640)
     ap.add_argument("--learned-steps", type=int, default=1200)
     ap.add_argument("--apply-form", default="factored", choices=["factored", "triple"],
@@ -191,6 +193,37 @@ def cpu_baseline(prob, gpu_iters, gpu_restarts, n_iters):
                    f"{os.cpu_count()} logical CPUs, sparse kernels single-threaded, BLAS "
                    f"threads {threads}"),
     }
+
+
+def fs_large(stream, iters=60):
+    """The largest instance of the 64-instance uneven workload (Q1 256x256,
+    M=6, p=4, P=210, q=8, sigma 1.27, which stagnates under the field split):
+    `iters` field-split GMRES(50) iterations with the blocks of the split by
+    first KL variable, timed with HIP events after 10 untimed ones."""
+    import torch
+    import paper_1910_11505_amd as sg
+    from synth import batched_instances, rhs_noisy
+    prob, seed = max(batched_instances(64), key=lambda ps: (ps[0].n, ps[0].p, ps[0].M, ps[0].sigma))
+    inst = sg.SGInstance(prob.n, prob.M, prob.p, prob.q, prob.cov, prob.mu, prob.sigma,
+                         prob.corr_len, prob.a_min, f_nodal=rhs_noisy(prob.n, seed), stream=stream)
+    try:
+        F = inst.rhs()
+        inst.solve(F, pc="fs", grouping="klvar", restart=50, tol=1e-8, max_it=10)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        _, info, _ = inst.solve(F, pc="fs", grouping="klvar", restart=50, tol=1e-8, max_it=iters)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        out = {"shape": f"Q1 {prob.n}x{prob.n}, M={prob.M}, p={prob.p} (P={inst.P}), q={prob.q}, "
+                        f"sigma={prob.sigma:.2f}",
+               "iterations": info.iterations, "ms": ms, "ms_per_iteration": ms / max(info.iterations, 1)}
+        _log(f"field split {out['shape']}: {info.iterations} it, {out['ms_per_iteration']:.2f} ms/it")
+        return out
+    finally:
+        inst.close()
 
 
 def sigma_sweep(stream, max_it=2000):
@@ -365,6 +398,7 @@ def main():
             _log(f"256x256 apply ({f}) {c2_apply[f]['ms']:.3f} ms, {c2_apply[f]['gbs']:.0f} GB/s")
 
     sweep = None if args.no_sigma_sweep else sigma_sweep(stream)
+    large = fs_large(stream) if args.fs_large else None
     learned = None
     if not args.no_learned:
         torch.cuda.empty_cache()
@@ -404,6 +438,7 @@ def main():
         "apply_c2_hbm": c2_apply,
         "learned_vs_field_split": learned,
         "sigma_sweep_256x256_p84": sweep,
+        "fs_large_256x256_p210": large,
         # The factored apply does 2 nnz(T) multiply-adds per Gauss point and
         # gradient component on 8 (M + 2P N_h / N_q) bytes per point: 15.2 flop/B
         # here, above the 9.8 flop/B ridge of the FP64 vector peak over HBM, so
