@@ -275,7 +275,7 @@ def learned_comparison(npairs, steps):
     import numpy as np
     import paper_1910_11505_amd as sg
     from paper_1910_11505_amd import learned as L
-    from synth import CONFIGS, cnn_init
+    from synth import CONFIGS, cnn_init, learned_problems
     base = CONFIGS["c4"]
     probe = L.make_instance(base)
     P, Nh = probe.P, probe.Nh
@@ -285,13 +285,13 @@ def learned_comparison(npairs, steps):
     net.set_params(Ws, bs)
     store = L.PairStore(npairs, P, Nh)
     t0 = time.perf_counter()
-    gen = L.generate_pairs(net, L.draw_problems(base, 400, 11505 + 4000), store, cycle=5,
+    gen = L.generate_pairs(net, learned_problems(base, 400, 11505 + 4000), store, cycle=5,
                            max_per_problem=16)
     _log(f"learned: {gen['pairs']} pairs from {gen['problems']} problems in {gen['seconds']:.1f} s")
     losses, train_s = L.train(net, store, steps, 16, 1e-3, lr_final=1e-4)
     _log(f"learned: {steps} Adam steps in {train_s:.1f} s, loss {losses[-1][1]:.3g}")
     rows = []
-    for prob, f in L.draw_problems(base, 2, 11505 + 4999):
+    for prob, f in learned_problems(base, 2, 11505 + 4999):
         c = L.compare(net, prob, f, max_it=1000)
         rows.append({"sigma": c.sigma, "fs_iterations": c.fs_iterations, "fs_s": c.fs_seconds,
                      "learned_iterations": c.learned_iterations, "learned_s": c.learned_seconds,

@@ -128,8 +128,11 @@ typedef struct sg_handle sg_handle;
  * *out receives a new handle (free with sg_destroy).  No device work.      */
 int sg_setup(const sg_problem* prob, const double* f_nodal, sg_handle** out);
 
-/* Sizes: P modes, N_h = (n-1)^2 unknowns per mode, n_a coefficient modes,
- * nnz_G nonzero triple products (any pointer may be NULL).                 */
+/* Sizes of the discrete system (Sec. 2.2): P = |J(p)| = (M+p)!/(M!p!) chaos
+ * modes of u, N_h = (n-1)^2 unknowns per mode (Q1, Dirichlet nodes
+ * eliminated), n_a = |J(q)| coefficient modes of eq. dataProjection, nnz_G
+ * nonzero triple products [G_k]_{ij} (eq. K_matrix).  Any pointer may be
+ * NULL.  Host only.  Errors: INVALID_ARG (null handle).                    */
 int sg_sizes(const sg_handle* h, int64_t* P, int64_t* N_h, int64_t* n_a, int64_t* nnz_G);
 
 /* Device bytes sg_bind needs (coefficient modes a_k at every quadrature
@@ -174,7 +177,9 @@ int sg_apply_form(const sg_handle* h, int* form, int* points_per_batch);
 int sg_precond_apply(sg_handle* h, int pc, int grouping, const double* r, double* z,
                      void* stream);
 
-/* r = F - K u (device, P*N_h each; r must not alias F or u)                */
+/* r = F - K u, the residual of the SG system K u = F (Sec. 2.2, eq.
+ * stochastic_matrix), with K applied as by sg_apply.  F, u, r: device,
+ * P*N_h each; r must not alias F or u.  Errors: NOT_BOUND, INVALID_ARG.   */
 int sg_residual(sg_handle* h, const double* F, const double* u, double* r, void* stream);
 
 /* Device bytes of the Krylov workspace sg_gmres_solve needs for `opts`.    */
@@ -191,7 +196,10 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* opts, const double* F, dou
                    void* krylov_ws, size_t ws_bytes, double* resid_hist, int32_t hist_len,
                    sg_solve_info* info, void* stream);
 
-/* Copies a set-up table to host memory (for verification):
+/* Copies a set-up table to host memory (for verification against the
+ * definitions of Sec. 2.1 and 2.2: the KL eigenpairs of eqs. KL_gamma /
+ * standard_deviation, the coefficient modes of eq. dataProjection, the
+ * stiffness of eq. A_q, the groupings of eq. P_group):
  *  SG_EXPORT_COEFF  a_k(x_q), n_a x 4n^2 values, q = 4e + 2qy + qx,
  *                   e = ey*n + ex (synchronous)
  *  SG_EXPORT_KL     lambda_1..lambda_M (host table)

@@ -13,8 +13,11 @@ Element stiffness with coefficient values c_q at the four points:
 Load vector: F = M_h f_h with the consistent Q1 mass matrix.
 
 Pins (tests/test_oracle_fem.py): the constant-coefficient 9-point stencil
-(8/3, -1/3), symmetry, F = h^2 for f = 1, and O(h^2) convergence of u(1/2,1/2)
-to the series solution of the unit-square Poisson problem.
+(8/3, -1/3), symmetry, F = h^2 for f = 1, the closed form of F for nodal
+forcing x^2 y^2 (consistent, not lumped, mass), F for random nodal forcing
+against an element-by-element 3x3 Gauss quadrature of f_h phi_j, and O(h^2)
+convergence of u(1/2,1/2) to the series solution of the unit-square Poisson
+problem.
 """
 from __future__ import annotations
 

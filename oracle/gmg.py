@@ -12,7 +12,7 @@ V-cycle on A_0 with the following reading:
 * smoother: damped Jacobi x <- x + omega D^{-1} (b - A x), omega = 8/9,
   two sweeps before and two after the coarse correction, starting from x = 0.
 
-Pins (tests/test_oracle_gmg.py): the V-cycle used as a stationary iteration
+Pins (tests/test_oracle_precond.py): the V-cycle used as a stationary iteration
 converges to the direct solve with a contraction factor below 0.2 on the
 Poisson stencil; it is linear and symmetric; R A P reproduces the rediscretised
 constant-coefficient stencil scaled by the grid ratio.

@@ -19,20 +19,11 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import binding as sg
-from synth import Problem, rhs_noisy
 
 
-def draw_problems(base: Problem, count: int, seed: int, sigma_range=(0.3, 1.5)):
-    """Seeded problem instances: sigma ~ U[sigma_range], forcing 1 + 0.1 N(0,1)."""
-    rng = np.random.default_rng(seed)
-    out = []
-    for i in range(count):
-        sigma = float(rng.uniform(*sigma_range))
-        out.append((base.with_(sigma=sigma), rhs_noisy(base.n, seed * 1000 + i + 1)))
-    return out
-
-
-def make_instance(prob: Problem, f_nodal=None, device="cuda:0"):
+def make_instance(prob, f_nodal=None, device="cuda:0"):
+    """A bound instance for a problem description `prob` (any object with the
+    fields n, M, p, q, cov, mu, sigma, corr_len, a_min)."""
     return sg.SGInstance(prob.n, prob.M, prob.p, prob.q, prob.cov, prob.mu, prob.sigma,
                          prob.corr_len, prob.a_min, f_nodal=f_nodal, device=device)
 
@@ -130,7 +121,7 @@ class Comparison:
     extra: dict = field(default_factory=dict)
 
 
-def compare(net: "sg.CNN", prob: Problem, f_nodal=None, tol=1e-8, fs_restart=50,
+def compare(net: "sg.CNN", prob, f_nodal=None, tol=1e-8, fs_restart=50,
             learned_restart=30, grouping="klvar", repeats: int = 1, max_it: int = 5000):
     """Plain field-split GMRES(fs_restart) against flexible GMRES(learned_restart)
     with the learned stage, both to the true relative residual tol."""

@@ -128,3 +128,14 @@ def cnn_init(P: int, seed: int, c0: int = 32, c1: int = 64):
         Ws.append(W)
         bs.append(np.zeros(co, dtype=np.float32))
     return Ws, bs
+
+
+def learned_problems(base: Problem, count: int, seed: int, sigma_range=(0.3, 1.5)):
+    """Seeded draws for the learned-stage workload: sigma ~ U[sigma_range] and
+    forcing 1 + 0.1 N(0,1) at the nodes, the rest of `base` unchanged."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        sigma = float(rng.uniform(*sigma_range))
+        out.append((base.with_(sigma=sigma), rhs_noisy(base.n, seed * 1000 + i + 1)))
+    return out
