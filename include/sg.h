@@ -154,6 +154,20 @@ int sg_rhs(sg_handle* h, double* F, void* stream);
  * in the form chosen by sg_set_apply.  U, W: device, P*N_h, must not alias. */
 int sg_apply(sg_handle* h, const double* U, double* W, void* stream);
 
+/* W = K U exactly as sg_apply (same kernels, same bits), for callers that
+ * cannot allocate device memory or touch the handle's scratch while the call
+ * runs (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  The apply's only scratch, the edge sums of its 4x4
+ * element tiles (9 values per tile and mode: 8 * 9 * P * (n/4)^2 bytes), lives
+ * in a fixed library-owned device array of 64 MiB per GPU, held from the first
+ * call on that GPU until the process ends; this call allocates nothing.
+ * Every call on one GPU shares that array, so calls that overlap in time on
+ * one GPU (any handles, any streams) race; the array's content is left from
+ * the last call and never read before being written.  U, W: device, P*N_h,
+ * must not alias.  Errors: INVALID_ARG, NOT_BOUND, UNSUPPORTED (edge sums
+ * above 64 MiB, e.g. n = 256 with P > 227), HIP.                          */
+int sg_apply_noalloc(sg_handle* h, const double* U, double* W, void* stream);
+
 /* Chooses the apply form used by sg_apply, sg_residual, the field-split
  * preconditioner and sg_gmres_solve.  points_per_batch (FACTORED only): 0
  * selects the register-resident kernel where it is compiled (every M <= 6

@@ -70,6 +70,7 @@ def load_library():
         "sg_bind": (I32, [HP, VP, SZ, VP]),
         "sg_rhs": (I32, [HP, VP, VP]),
         "sg_apply": (I32, [HP, VP, VP, VP]),
+        "sg_apply_noalloc": (I32, [HP, VP, VP, VP]),
         "sg_set_apply": (I32, [HP, I32, I32, VP]),
         "sg_apply_form": (I32, [HP, P(ctypes.c_int32), P(ctypes.c_int32)]),
         "sg_precond_apply": (I32, [HP, I32, I32, VP, VP, VP]),
@@ -264,6 +265,10 @@ def sg_cnn_get_params(c, w, b):
 def sg_cnn_make_pair(c, r, ustar, u, R_out, T_out, stream=None):
     _ccheck(load_library().sg_cnn_make_pair(c, _ptr(r), _ptr(ustar), _ptr(u), _ptr(R_out),
                                             _ptr(T_out), _stream(stream)))
+
+
+def sg_apply_noalloc(h, U, W, stream=None):
+    _check(load_library().sg_apply_noalloc(h, _ptr(U), _ptr(W), _stream(stream)))
 
 
 def sg_residual(h, F, u, r, stream=None):

@@ -6,6 +6,7 @@
 #include <map>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <thread>
 #include <numeric>
 #include <string>
@@ -705,15 +706,50 @@ EdgeFix pending_edges(const sg_handle& H, double sgn) {
 }
 
 // W = K U; with fixup false the edge sums stay pending (pending_edges(H, 1.0)).
-void do_apply(sg_handle& H, hipStream_t s, const double* U, double* W, bool fixup = true) {
+// `edge` (default: the handle's own) receives the tiles' edge sums, P * ntiles
+// * kEdgeVals values, every one written by the apply before the fixup reads it.
+void do_apply(sg_handle& H, hipStream_t s, const double* U, double* W, bool fixup = true,
+              double* edge = nullptr) {
+  if (!edge) edge = H.d.edge;
   if (H.use_factored && H.use_rapply)
     launch_rapply(s, H.M, H.prob.p, H.n, H.prob.mu, H.prob.a_min, H.d.g, H.rfull, U, H.Nh,
-                  nullptr, 0.0, 1.0, W, H.d.edge, fixup);
+                  nullptr, 0.0, 1.0, W, edge, fixup);
   else if (H.use_factored)
     launch_fapply(s, H.n, H.prob.mu, H.prob.a_min, H.d.g, H.d.ffull, U, H.Nh, nullptr, 0.0, 1.0,
-                  W, H.d.edge, fixup);
+                  W, edge, fixup);
   else
-    launch_apply(s, H.n, H.na, H.d.a, H.d.full, U, H.Nh, nullptr, 0.0, 1.0, W, H.d.edge, fixup);
+    launch_apply(s, H.n, H.na, H.d.a, H.d.full, U, H.Nh, nullptr, 0.0, 1.0, W, edge, fixup);
+}
+
+// ---- the apply without allocation ------------------------------------------
+// sg_apply_noalloc keeps the apply's edge sums (its only scratch) in this
+// file-scope device array instead of the handle's workspace.  Each device holds
+// its own copy until the process ends.  In host code `scratch` names a host
+// stand-in, not device memory: its device address is looked up once per device
+// (hipGetSymbolAddress, with that device current) and only that address is
+// handed to kernels.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// The current device's address of `scratch` (looked up on first use there).
+double* noalloc_scratch() {
+  int dev = 0;
+  SG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    throw Error(SG_ERR_UNSUPPORTED, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      throw Error(SG_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch_dev[dev];
 }
 
 void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double* r, double* z) {
@@ -1115,6 +1151,25 @@ int sg_apply(sg_handle* h, const double* U, double* W, void* stream) {
   if (!h->bound) return fail(SG_ERR_NOT_BOUND, "handle not bound");
   try {
     do_apply(*h, reinterpret_cast<hipStream_t>(stream), U, W);
+    check_launch();
+    return SG_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  }
+}
+
+int sg_apply_noalloc(sg_handle* h, const double* U, double* W, void* stream) {
+  if (!h || !U || !W) return fail(SG_ERR_INVALID_ARG, "null argument");
+  if (U == W) return fail(SG_ERR_INVALID_ARG, "U and W must not alias");
+  const size_t need = (size_t)h->P * h->ntiles * kEdgeVals * sizeof(double);
+  if (need > kNoAllocScratchBytes)
+    return fail(SG_ERR_UNSUPPORTED, "sg_apply_noalloc: the edge sums need " + std::to_string(need) +
+                                        " bytes, above the fixed scratch of " +
+                                        std::to_string(kNoAllocScratchBytes) + " bytes");
+  if (!h->bound) return fail(SG_ERR_NOT_BOUND, "handle not bound");
+  try {
+    double* edge = noalloc_scratch();
+    do_apply(*h, reinterpret_cast<hipStream_t>(stream), U, W, true, edge);
     check_launch();
     return SG_OK;
   } catch (const Error& e) {
