@@ -186,8 +186,13 @@ int sg_set_apply(sg_handle* h, int kind, int points_per_batch, void* stream);
 int sg_apply_form(const sg_handle* h, int* form, int* points_per_batch);
 
 /* z = P^{-1} r for pc in {SG_PC_NONE, SG_PC_MEAN, SG_PC_FS} and a grouping
- * (Sec. 3, eqs. P_preconditioner / P_group).  r, z: device, P*N_h, must not
- * alias.                                                                    */
+ * (Sec. 3, eqs. P_preconditioner / P_group), optionally with SG_PC_DIAG_KII.
+ * pc = SG_PC_LEARNED (| SG_PC_DIAG_KII) applies one learned stage of the
+ * attached network (see sg_solve_opts; not part of the paper):
+ * z = P_FS^{-1} r + alpha c, c the network's prediction for
+ * r1 = r - K P_FS^{-1} r, alpha = <r1, K c>/||K c||^2 (0 when not finite).
+ * r, z: device, P*N_h, must not alias.  Errors: INVALID_ARG (unknown pc or
+ * grouping; SG_PC_LEARNED without an attached network), NOT_BOUND.       */
 int sg_precond_apply(sg_handle* h, int pc, int grouping, const double* r, double* z,
                      void* stream);
 

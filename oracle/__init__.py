@@ -21,6 +21,7 @@ Modules
   gmres    restarted (flexible) GMRES with right preconditioning (Sec. 3)
   mc       Monte Carlo / collocation reference statistics        (Sec. 2)
   cnn      mode-channel CNN forward/backward/Adam reference
+  learned  the learned stage's composition with the field split
 
 Parity status of each function is stated in its module docstring; every
 function here is pinned by a `-m "not gpu"` test against closed forms,

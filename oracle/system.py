@@ -16,7 +16,10 @@
 
 apply(U) evaluates K U through the Kronecker identity
 (G (x) A) vec(U) = vec(A U G^T) applied to each term of the definition; it is
-pinned against the explicitly assembled K on small sizes.
+pinned against the explicitly assembled K on small sizes.  apply_pointwise(U)
+and apply_at(U, ...) evaluate the same blocks from their per-point
+coefficients c_ij(x_q) = sum_k [G_k]_{ij} a_k(x_q) without forming any A_k
+(large grids); both are pinned against apply(U).
 """
 from __future__ import annotations
 
@@ -113,6 +116,59 @@ class SGSystem:
         for k, v in zip(self.Gk[m], self.Gv[m]):
             out = out + v * self.A[k]
         return out
+
+    def apply_pointwise(self, U: np.ndarray, chunk: int = 2048, workers: int = 8) -> np.ndarray:
+        """K U for one or more vectors (rows of U) straight from the definition
+        of the blocks, K_ij = stiffness with coefficient c_ij(x_q) = sum_k
+        [G_k]_{ij} a_k(x_q) (eq. A_q with the coefficient of block (i, j)), for
+        grids where assembling every A_k is impractical:
+            (K U)_i(node) = sum over the node's elements and Gauss points of
+                            (1/4) grad phi_node(x_q) . sum_j c_ij(x_q) grad U_j(x_q).
+        Elements are taken in chunks of `chunk` (to bound memory), computed by
+        `workers` threads; the node sums are added in chunk order."""
+        from concurrent.futures import ThreadPoolExecutor
+        n, P, Nh = self.n, self.P, self.Nh
+        Us = np.atleast_2d(U).reshape(-1, P, Nh)
+        nv = Us.shape[0]
+        g2i = fem.grid_to_interior(n)
+        inner = g2i >= 0
+        Ug = np.zeros((nv, P, (n + 1) ** 2))
+        Ug[:, :, inner] = Us[:, :, g2i[inner]]
+        nodes = fem.element_nodes(n)
+        Gref = fem.ref_grads()                                   # (q, a, 2)
+        # row j*P + i of Cmap gives c_ij (column index j outermost, so that the
+        # coefficients multiplying grad U_j are contiguous)
+        Cmap = sp.csr_matrix((self.Gv, (self.Gj * P + self.Gi, self.Gk)), shape=(P * P, self.na))
+
+        def element_sums(e0):
+            e1 = min(n * n, e0 + chunk)
+            ne = e1 - e0
+            nd = nodes[e0:e1]                                    # (ne, 4)
+            aq = coeff_modes(self.g[:, 4 * e0:4 * e1], self.Jq, self.prob.mu, self.prob.a_min)
+            C = (Cmap @ aq).reshape(P, P, ne * 4)                # C[j, i] = c_ij at each point
+            out = np.empty((nv, ne, 4, P))
+            tmp = np.empty((P, ne * 4))
+            for v in range(nv):
+                ue = Ug[v][:, nd]                                # (P, ne, 4 corners)
+                grad = np.einsum("pea,qad->pdeq", ue, Gref).reshape(P, 2, ne * 4)
+                flux = np.zeros((2, P, ne * 4))
+                for j in range(P):
+                    for d in range(2):
+                        np.multiply(C[j], grad[j, d], out=tmp)
+                        flux[d] += tmp
+                flux = flux.reshape(2, P, ne, 4)
+                out[v] = 0.25 * np.einsum("dieq,qad->eai", flux, Gref)   # (ne, corner, i)
+            return e0, nd, out
+
+        W = np.zeros((nv, (n + 1) ** 2, P))
+        with ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
+            for e0, nd, contrib in ex.map(element_sums, range(0, n * n, chunk)):
+                for v in range(nv):
+                    for a in range(4):
+                        np.add.at(W[v], nd[:, a], contrib[v, :, a, :])
+        out = W[:, inner, :].transpose(0, 2, 1)                 # interior nodes in unknown order
+        out = out.reshape(nv, P * Nh)
+        return out[0] if np.ndim(U) == 1 else out
 
     def apply_at(self, U: np.ndarray, modes, nodes) -> np.ndarray:
         """(K U) at selected (mode, interior node) pairs, straight from the

@@ -78,6 +78,7 @@ struct DevPtrs {
   double* diag_v = nullptr;
   double* cdiag = nullptr;       // one coefficient field (set-up scratch)
   double* Cd = nullptr;          // dense coarse V-cycle operator, N x N column-major
+  double* stage = nullptr;       // learned stage of sg_precond_apply: dot partials, 4 scalars
 };
 
 // bump allocator over the caller's workspace (or a dry run to size it)
@@ -573,6 +574,10 @@ void carve(const sg_handle& H, DevPtrs& D, Carver& c) {
   D.diag_k = c.take<int>(std::max<size_t>(H.diag_k.size(), 1));
   D.diag_v = c.take<double>(std::max<size_t>(H.diag_v.size(), 1));
   D.cdiag = c.take<double>(H.Nq);
+  {
+    const int64_t Nv = (int64_t)H.P * H.Nh;
+    D.stage = c.take<double>((size_t)std::max(dot_blocks(Nv), gs_blocks(Nv)) + 4);
+  }
   if (H.ldense >= 0) {
     const size_t Nd = (size_t)(H.level_n[H.ldense] - 1) * (H.level_n[H.ldense] - 1);
     D.Cd = c.take<double>(Nd * Nd);
@@ -800,6 +805,30 @@ void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double*
       launch_scatter_modes(s, m, fd.split_idx[sp], H.Nh, H.d.fsX, z);
     }
   }
+}
+
+// One application of the learned stage (the network is not part of the paper):
+//   z0 = P_FS^{-1} v (fs_pc: the field split, with or without K_ii blocks),
+//   r1 = v - K z0, c = N(r1) (the attached network's error prediction),
+//   z = z0 + alpha c with alpha = <r1, K c> / ||K c||^2, the step that
+//   minimises ||v - K z|| along c; alpha = 0 (z = z0) when the prediction is
+//   not finite.  The field split is thus both the fallback and the judge: the
+//   stage's residual never exceeds the field split's.
+// Scratch: r1, c, kc (vectors), partial (dot partials), dots (3 scalars; dots[2]
+// receives alpha).  w (nullable) receives K z (for the Arnoldi step).
+void learned_stage(sg_handle& H, hipStream_t s, int fs_pc, int grouping, const double* v, double* z,
+                   double* w, double* r1, double* c, double* kc, double* partial, int nblk,
+                   double* dots) {
+  const int64_t Nv = (int64_t)H.P * H.Nh;
+  do_precond(H, s, fs_pc, grouping, v, z);
+  double* kz = w ? w : kc;
+  do_apply(H, s, z, kz);
+  launch_sub(s, v, kz, r1, Nv);
+  cnn_apply_sg(H.cnn, s, r1, H.cnn_sigma, c, partial, nblk);
+  do_apply(H, s, c, kc);
+  launch_gs_dot(s, r1, Nv, 1, kc, Nv, partial, dots);
+  launch_gs_dot(s, kc, Nv, 1, kc, Nv, partial, dots + 1);
+  launch_stage_alpha(s, dots, c, kc, z, w, Nv);
 }
 
 bool valid_pc(int pc, bool allow_learned = false) {
@@ -1197,10 +1226,23 @@ int sg_precond_apply(sg_handle* h, int pc, int grouping, const double* r, double
   if (!h || !r || !z) return fail(SG_ERR_INVALID_ARG, "null argument");
   if (r == z) return fail(SG_ERR_INVALID_ARG, "r and z must not alias");
   if (!h->bound) return fail(SG_ERR_NOT_BOUND, "handle not bound");
-  if (!valid_pc(pc)) return fail(SG_ERR_INVALID_ARG, "unknown preconditioner");
+  if (!valid_pc(pc, true)) return fail(SG_ERR_INVALID_ARG, "unknown preconditioner");
   if (grouping < 0 || grouping > 3) return fail(SG_ERR_INVALID_ARG, "unknown grouping");
+  const bool learned = (pc & 0xff) == SG_PC_LEARNED;
+  if (learned && !h->cnn) return fail(SG_ERR_INVALID_ARG, "learned stage needs an attached network");
   try {
-    do_precond(*h, reinterpret_cast<hipStream_t>(stream), pc, grouping, r, z);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (learned) {
+      // the preconditioner's own scratch is free once z0 is formed
+      sg_handle& H = *h;
+      const int64_t Nv = (int64_t)H.P * H.Nh;
+      const int nb = std::max(dot_blocks(Nv), gs_blocks(Nv));
+      learned_stage(H, s, (pc & ~0xff) | SG_PC_FS, grouping, r, z, nullptr, H.d.fsT, H.d.fsX,
+                    H.d.mg_xa[0], H.d.stage, dot_blocks(Nv), H.d.stage + nb);
+      check_launch();
+      return SG_OK;
+    }
+    do_precond(*h, s, pc, grouping, r, z);
     check_launch();
     return SG_OK;
   } catch (const Error& e) {
@@ -1346,24 +1388,8 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
           // stage's residual never exceeds the field split's; alpha = 0 (plain
           // field split) when the prediction is not finite
           zj = K.Z + (int64_t)j * Nv;
-          double* c = K.z;
-          do_precond(H, s, fs_pc, o->grouping, vj, zj);
-          do_apply(H, s, zj, K.w);
-          launch_sub(s, vj, K.w, K.x2, Nv);
-          cnn_apply_sg(H.cnn, s, K.x2, H.cnn_sigma, c, K.partial, K.nblk);
-          do_apply(H, s, c, K.t);
-          double* nn = K.hdev + 2 * (m + 1) + 1;
-          launch_gs_dot(s, K.x2, Nv, 1, K.t, Nv, K.partial, nn);
-          norm2(K.t, nn + 1);
-          fetch(nn, 2);
-          const double rkc = hp[0], kc2 = hp[1];
-          const double alpha = (std::isfinite(rkc) && std::isfinite(kc2) && kc2 > 0.0) ? rkc / kc2 : 0.0;
-          if (alpha != 0.0) {
-            launch_axpby(s, alpha, c, 1.0, zj, Nv);
-            launch_axpby(s, alpha, K.t, 1.0, K.w, Nv);
-          } else {
-            ++fallbacks;
-          }
+          learned_stage(H, s, fs_pc, o->grouping, vj, zj, K.w, K.x2, K.z, K.t, K.partial, K.nblk,
+                        K.hdev + 2 * (m + 1) + 1);
         } else {
           do_precond(H, s, o->pc, o->grouping, vj, K.z);
           do_apply(H, s, zj, K.w, !defer);
@@ -1379,7 +1405,9 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
         launch_gs_update_norm_scale(s, K.V, Nv, j + 1, h2, K.w, Nv, -1.0, K.partial, nrm,
                                     K.V + (int64_t)(j + 1) * Nv);
         check_launch();
-        SG_HIP(hipMemcpyAsync(hp, K.hdev, (2 * (m + 1) + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        // the Hessenberg column and the norm; for the learned stage also its alpha
+        SG_HIP(hipMemcpyAsync(hp, K.hdev, (2 * (m + 1) + (learned ? 4 : 1)) * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
         SG_HIP(hipEventRecord(H.fetched, s));
         if (!learned && j + 1 < m && it + 1 < o->max_it) {
           do_precond(H, s, o->pc, o->grouping, K.V + (int64_t)(j + 1) * Nv, K.z);
@@ -1387,6 +1415,7 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
           queued = true;
         }
         SG_HIP(hipEventSynchronize(H.fetched));
+        if (learned && hp[2 * (m + 1) + 3] == 0.0) ++fallbacks;
         for (int i = 0; i <= j; ++i) Hat(i, j) = hp[i] + hp[m + 1 + i];
         Hat(j + 1, j) = std::sqrt(hp[2 * (m + 1)]);
         if (!std::isfinite(Hat(j + 1, j))) {

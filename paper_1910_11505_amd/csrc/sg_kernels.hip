@@ -1372,6 +1372,27 @@ void launch_sub(hipStream_t s, const double* a, const double* b, double* out, in
   hipLaunchKernelGGL(sub_kernel, dim3(cdiv(N, 256)), dim3(256), 0, s, a, b, out, N);
 }
 
+// The learned stage's step weight: alpha = dots[0] / dots[1] (<r, Kc> / ||Kc||^2)
+// when both are finite and dots[1] > 0, else 0 (dots[2] receives alpha); then
+// z += alpha c and, when w is given, w += alpha Kc.  With alpha = 0 nothing is
+// written, so a non-finite prediction leaves z (and w) as they were.
+__global__ void stage_alpha_kernel(double* __restrict__ dots, const double* __restrict__ c,
+                                   const double* __restrict__ kc, double* __restrict__ z,
+                                   double* __restrict__ w, int64_t N) {
+  const double num = dots[0], den = dots[1];
+  const double alpha = (isfinite(num) && isfinite(den) && den > 0.0) ? num / den : 0.0;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) dots[2] = alpha;
+  if (alpha == 0.0 || i >= N) return;
+  z[i] = fma(alpha, c[i], z[i]);
+  if (w) w[i] = fma(alpha, kc[i], w[i]);
+}
+
+void launch_stage_alpha(hipStream_t s, double* dots, const double* c, const double* kc, double* z,
+                        double* w, int64_t N) {
+  hipLaunchKernelGGL(stage_alpha_kernel, dim3(cdiv(N, 256)), dim3(256), 0, s, dots, c, kc, z, w, N);
+}
+
 
 // ===========================================================================
 // Fused multigrid V-cycle kernels.

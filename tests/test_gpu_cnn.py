@@ -1,7 +1,12 @@
 """GPU parity of the learned stage's network: forward, loss, gradients and the
 Adam step of the HIP kernels (through the C ABI) against the CNN oracle in
 device numerics (bf16 weights/activations, FP32 accumulation).  Bars: outputs
-and loss 1e-2 relative (norm), gradients 3e-2 relative per layer (norm)."""
+and loss 1e-2 relative (norm); weight and bias gradients 2e-3 relative per
+layer (norm).  Measured on the learned workload's network (128 x 128, 35
+modes, 64-wide finest level): outputs 3e-3, gradients at most 1.2e-3 (first
+layer).  The gap to FP32 rounding comes from the bf16 rounding of the masked
+output gradients, where the device's FP32 sums and the oracle's FP64 sums
+round a few values to neighbouring bf16 numbers."""
 import numpy as np
 import pytest
 
@@ -18,15 +23,15 @@ def _bf16_bits(x):
     return (ocnn.bf16(x).view(np.uint32) >> 16).astype(np.uint16)
 
 
-def _case(P, n, B, seed):
+def _case(P, n, B, seed, c0=32):
     rng = np.random.default_rng(seed)
     Nh = (n - 1) ** 2
     R = ocnn.bf16(rng.standard_normal((B, P, Nh)))
     T = ocnn.bf16(0.1 * rng.standard_normal((B, P, Nh)))
     sig = rng.uniform(0.3, 1.5, B).astype(np.float32)
-    Ws, bs = cnn_init(P, seed + 1)
+    Ws, bs = cnn_init(P, seed + 1, c0=c0)
     bs = [(0.05 * rng.standard_normal(b.shape)).astype(np.float32) for b in bs]
-    layers = cnn_layers(P)
+    layers = cnn_layers(P, c0)
     CI0, CO = layers[0][0], layers[-1][1]
     X0 = np.zeros((B, n, n, CI0))
     Tt = np.zeros((B, n, n, CO))
@@ -37,8 +42,8 @@ def _case(P, n, B, seed):
     return R, T, sig, Ws, bs, X0, Tt
 
 
-def _net(P, n, B, Ws, bs):
-    net = sg.CNN(P, n, max_batch=B)
+def _net(P, n, B, Ws, bs, c0=32):
+    net = sg.CNN(P, n, max_batch=B, c0=c0)
     net.set_params(Ws, bs)
     return net
 
@@ -47,32 +52,40 @@ def _dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dtype).cuda()
 
 
-@pytest.mark.parametrize("P,n,B", [(3, 16, 2), (35, 32, 2)])
-def test_forward_loss_and_gradients(P, n, B):
+@pytest.mark.parametrize("P,n,B,c0", [(3, 16, 2, 32), (35, 32, 2, 32), (35, 128, 2, 64)])
+def test_forward_loss_and_gradients(P, n, B, c0):
+    """(35, 128, 2, 64) is the network of the learned workload (128 x 128 grid,
+    35 modes, 64-wide finest level)."""
     need_gpu()
-    R, T, sig, Ws, bs, X0, Tt = _case(P, n, B, 7)
-    net = _net(P, n, B, Ws, bs)
+    print(f"[cnn parity P={P} n={n} B={B} c0={c0}]", flush=True)
+    R, T, sig, Ws, bs, X0, Tt = _case(P, n, B, 7, c0)
+    net = _net(P, n, B, Ws, bs, c0)
     Rd = torch.from_numpy(_bf16_bits(R).view(np.int16)).cuda()
     Td = torch.from_numpy(_bf16_bits(T).view(np.int16)).cuda()
     sd = _dev(sig, torch.float32)
-    CO = cnn_layers(P)[-1][1]
+    CO = cnn_layers(P, c0)[-1][1]
     Y = torch.zeros(B * n * n * CO, dtype=torch.float32, device="cuda")
     loss = sg.sg_cnn_run(net.c, Rd, Td, sd, np.arange(B), 1, Y_out=Y)
     Yg = Y.cpu().numpy().reshape(B, n, n, CO)
     Yo, cache = ocnn.forward(Ws, bs, X0, exact=False)
     Lo, dY = ocnn.loss_and_grad(Yo, Tt, P, n)
-    assert np.linalg.norm(Yg - Yo) <= 1e-2 * np.linalg.norm(Yo)
-    assert abs(loss - Lo) <= 1e-2 * abs(Lo)
+    ey = np.linalg.norm(Yg - Yo) / np.linalg.norm(Yo)
+    el = abs(loss - Lo) / abs(Lo)
     dWo, dbo = ocnn.backward(Ws, cache, dY, exact=False)
     dw, db = net.get_grads()
     ow = ob = 0
+    ews, ebs = [], []
     for l, (W, b) in enumerate(zip(dWo, dbo)):
         gw = dw[ow: ow + W.size].reshape(W.shape)
         gb = db[ob: ob + b.size]
         ow += W.size
         ob += b.size
-        assert np.linalg.norm(gw - W) <= 3e-2 * np.linalg.norm(W), l
-        assert np.linalg.norm(gb - b) <= 3e-2 * np.linalg.norm(b) + 1e-12, l
+        ews.append(np.linalg.norm(gw - W) / np.linalg.norm(W))
+        ebs.append(np.linalg.norm(gb - b) / max(np.linalg.norm(b), 1e-30))
+    print(f"[cnn parity] output {ey:.2e} loss {el:.2e} weight grads max {max(ews):.2e} "
+          f"bias grads max {max(ebs):.2e} per layer {np.round(ews, 6).tolist()}", flush=True)
+    assert ey <= 1e-2 and el <= 1e-2
+    assert max(ews) <= 2e-3 and max(ebs) <= 2e-3
     net.close()
 
 

@@ -1,0 +1,74 @@
+"""One learned-stage application through the C ABI (sg_precond_apply with
+SG_PC_LEARNED) against the oracle's composition z = P_FS^{-1} v + alpha c
+(oracle.learned.stage), with the field split (A_0 or K_ii blocks) from the
+oracle, alpha from the oracle, and the network's prediction c taken from the
+GPU: the same kernels the stage runs (field split, residual, network in SG
+units), called one by one through the C ABI.  Bar: 1e-12 relative (max-norm)."""
+import numpy as np
+import pytest
+
+import paper_1910_11505_amd as sg
+from synth import Problem, cnn_init, random_vector
+
+from gpu_common import instance, need_gpu, relmax, to_dev, to_host, torch
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "n16_m3p2": Problem(n=16, M=3, p=2, q=4, cov="sqexp", sigma=1.2, corr_len=0.5),
+    "n32_m4p3": Problem(n=32, M=4, p=3, q=6, cov="sqexp", sigma=0.7, corr_len=0.5),
+}
+
+
+def _kii_solver(S):
+    from oracle import fem
+    from oracle.gmg import GMGHierarchy
+    hs = []
+    for i in range(S.P):
+        m = (S.Gi == i) & (S.Gj == i)
+        c = np.zeros(S.a.shape[1])
+        for k, v in zip(S.Gk[m], S.Gv[m]):
+            c += v * S.a[k]
+        hs.append(GMGHierarchy(fem.stiffness(S.n, c), S.n))
+    return lambda t, i: hs[i].vcycle(t)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("kii", [False, True])
+@pytest.mark.parametrize("c0", [32, 64])
+def test_learned_stage_matches_oracle(name, kii, c0):
+    need_gpu()
+    from oracle.gmg import GMGHierarchy
+    from oracle.learned import stage
+    from oracle.precond import FieldSplit, make_groups
+    from oracle.system import SGSystem
+    prob = CASES[name]
+    print(f"[learned stage {name} kii={kii} c0={c0}]", flush=True)
+    G = instance(prob)
+    net = sg.CNN(G.P, prob.n, max_batch=1, c0=c0, c1=64)
+    Ws, bs = cnn_init(G.P, 3, c0=c0, c1=64)
+    bs = [(0.01 * np.random.default_rng(4).standard_normal(b.shape)).astype(np.float32) for b in bs]
+    net.set_params(Ws, bs)
+    G.attach(net, prob.sigma)
+    v = random_vector(G.nvec, 41)
+    vd = to_dev(v)
+    fs_name = "fs_kii" if kii else "fs"
+    z = to_host(G.precond(vd, "learned_kii" if kii else "learned", "klvar"))
+    # the GPU's own prediction, from the same kernels the stage runs
+    z0 = G.precond(vd, fs_name, "klvar")
+    r1 = G.vec()
+    sg.sg_residual(G.h, vd, z0, r1, G.stream)
+    c = G.vec()
+    sg.sg_cnn_apply(net.c, r1, prob.sigma, c, G.stream)
+    c = to_host(c)
+    assert np.all(np.isfinite(c)) and np.abs(c).max() > 0
+    S = SGSystem(prob)
+    fs = FieldSplit(S, GMGHierarchy(S.A[0], prob.n), make_groups(S.Jp, "klvar"),
+                    block_solve=_kii_solver(S) if kii else None)
+    zo, alpha, _ = stage(S.apply, fs.apply, v, c)
+    print(f"[learned stage {name}] alpha {alpha:.3e}", flush=True)
+    assert alpha != 0.0
+    assert relmax(z, zo) < 1e-12
+    G.attach(None, 0.0)
+    net.close()
+    G.close()

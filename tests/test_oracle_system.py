@@ -151,3 +151,18 @@ def test_chaos_coefficient_matrix_factorises_when_q_is_2p():
             ref = a_min * np.eye(len(Jp)) + np.exp(mu + 0.5 * np.sum(g[:, x] ** 2)) * T @ T.T
             err = np.abs(C - ref).max() / np.abs(ref).max()
             assert (err < 1e-14) if exact else (err > 1e-6), (q, err)
+
+
+@pytest.mark.parametrize("prob", [
+    Problem(n=8, M=2, p=2, q=4, cov="exp_l1", sigma=0.8, corr_len=0.5),
+    Problem(n=8, M=3, p=2, q=3, cov="sqexp", sigma=1.1, corr_len=0.4),
+])
+def test_pointwise_apply_matches_kronecker_apply(prob):
+    S = SGSystem(prob)
+    rng = np.random.default_rng(21)
+    U = rng.standard_normal((2, S.P * S.Nh))
+    W = S.apply_pointwise(U, chunk=7)
+    for v in range(2):
+        ref = S.apply(U[v])
+        assert np.abs(W[v] - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert np.array_equal(S.apply_pointwise(U[0], chunk=7), W[0])
