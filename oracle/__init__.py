@@ -18,6 +18,7 @@ Modules
   system   coefficient chaos modes, A_k, K = sum G_k (x) A_k, F (Sec. 2.2)
   gmg      geometric multigrid V-cycle on the mean stiffness     (Sec. 3)
   precond  mean-based and field-split block Gauss-Seidel         (Sec. 3)
+  sgmg     multigrid on the full SG system, field-split smoother (Sec. 3)
   gmres    restarted (flexible) GMRES with right preconditioning (Sec. 3)
   mc       Monte Carlo / collocation reference statistics        (Sec. 2)
   cnn      mode-channel CNN forward/backward/Adam reference

@@ -1,0 +1,122 @@
+"""Pins for oracle.sgmg: multigrid on the full SG system with the field-split
+smoother (paper Sec. 3, eqs. level_solver and P_group; trends of Tabs.
+sigma_variation and mesh_variation)."""
+import numpy as np
+import pytest
+
+from oracle.gmres import gmres
+from oracle.precond import make_groups
+from oracle.sgmg import FullSGMultigrid, level_g, level_system
+from oracle.system import SGSystem
+from synth import Problem
+
+
+def _sys(n=8, M=2, p=2, sigma=0.8, cov="exp_l1", lc=0.5):
+    return SGSystem(Problem(n=n, M=M, p=p, q=2 * p, cov=cov, sigma=sigma, corr_len=lc))
+
+
+def test_finest_level_kl_values_are_the_systems_own():
+    S = _sys(n=16, M=3, cov="sqexp")
+    assert np.abs(level_g(S, 16) - S.g).max() <= 1e-15 * np.abs(S.g).max()
+
+
+def test_coarse_kl_values_by_direct_evaluation():
+    # an independent evaluation of one coarse Gauss point: locate the fine
+    # element by a search and interpolate the fine 1D eigenvector linearly
+    from oracle import kl
+    S = _sys(n=16, M=3)
+    lam1, E = kl.kl_1d(16, S.prob.cov, S.prob.corr_len)
+    g4 = level_g(S, 4)
+    gp = (1 - 1 / np.sqrt(3)) / 2, (1 + 1 / np.sqrt(3)) / 2
+    for (ex, ey, qx, qy) in [(0, 0, 0, 0), (3, 1, 1, 0), (2, 3, 1, 1)]:
+        x1, x2 = (ex + gp[qx]) / 4, (ey + gp[qy]) / 4
+        q = 4 * (ey * 4 + ex) + 2 * qy + qx
+        for m, (r, s) in enumerate(S.pairs):
+            def e(col, x):
+                j = max(k for k in range(16) if k / 16 <= x)
+                w = (x - j / 16) * 16
+                return (1 - w) * E[j, col] + w * E[j + 1, col]
+            ref = np.sqrt(S.lam[m]) * e(r, x1) * e(s, x2)
+            assert abs(g4[m, q] - ref) <= 1e-14
+
+
+def test_sigma_zero_rediscretisation_is_galerkin_and_cgc_annihilates():
+    S = _sys(n=8, sigma=0.0)
+    mg = FullSGMultigrid(S, grouping="mean", pre=0, post=0)
+    Kf, Kc, Pr = mg.K[0], mg.K[1], mg.Pr[0]
+    G = (Pr.T @ Kf @ Pr).toarray()
+    assert np.abs(G - Kc.toarray()).max() <= 1e-13 * np.abs(Kc).max()
+    r = np.random.default_rng(1).standard_normal(Kf.shape[0])
+    z = mg.vcycle(r)                        # coarse-grid correction only
+    assert np.abs(Pr.T @ (r - Kf @ z)).max() <= 1e-12 * np.abs(Pr.T @ r).max()
+
+
+def test_one_level_hierarchy_is_the_exact_inverse():
+    S = _sys(n=4, M=3, p=2, sigma=1.2)
+    mg = FullSGMultigrid(S)
+    K = S.assemble().toarray()
+    r = np.random.default_rng(2).standard_normal(K.shape[0])
+    z = mg.vcycle(r)
+    assert np.abs(K @ z - r).max() <= 1e-12 * np.abs(r).max()
+
+
+@pytest.mark.parametrize("grouping", ["mean", "klvar", "permode"])
+def test_smoother_on_a_single_node_residual(grouping):
+    S = _sys(n=8, M=2, p=2, sigma=1.0)
+    mg = FullSGMultigrid(S, grouping=grouping)
+    K = mg.K[0].toarray()
+    Nh, P = S.Nh, S.P
+    node = 3 * 7 + 4
+    rng = np.random.default_rng(3)
+    r = np.zeros(P * Nh)
+    r[np.arange(P) * Nh + node] = rng.standard_normal(P)
+    z = mg.smooth(0, r, np.zeros_like(r))
+    # the same step written out: forward block substitution over the splits,
+    # each split's nodal blocks inverted with numpy.linalg.solve
+    ref = np.zeros_like(r)
+    for g in make_groups(S.Jp, grouping):
+        rows = np.concatenate([np.arange(i * Nh, (i + 1) * Nh) for i in g])
+        t = r[rows] - K[rows] @ ref
+        for nd in range(Nh):
+            idx = [i * Nh + nd for i in g]
+            D = K[np.ix_(idx, idx)]
+            ref[idx] = mg.omega * np.linalg.solve(D, t[[a * Nh + nd for a in range(len(g))]])
+    assert np.abs(z - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_vcycle_contracts_as_a_stationary_iteration():
+    S = _sys(n=16, M=3, p=2, sigma=0.5, cov="sqexp")
+    mg = FullSGMultigrid(S, grouping="mean")
+    K = mg.K[0]
+    F = S.rhs()
+    x = np.zeros_like(F)
+    r0 = np.linalg.norm(F)
+    for _ in range(8):
+        x = x + mg.vcycle(F - K @ x)
+    rate = (np.linalg.norm(F - K @ x) / r0) ** (1 / 8)
+    assert rate < 0.3, rate
+
+
+def _iters(n, sigma, grouping, M=4, p=3):
+    S = SGSystem(Problem(n=n, M=M, p=p, q=2 * p, cov="exp_l1", sigma=sigma, corr_len=0.25))
+    mg = FullSGMultigrid(S, grouping=grouping)
+    K = mg.K[0]
+    _, info = gmres(lambda v: K @ v, mg.vcycle, S.rhs(), tol=1e-8, restart=50, max_it=200)
+    assert info["converged"]
+    return info["iterations"]
+
+
+def test_paper_trend_in_sigma():
+    # Tab. sigma_variation: the leading-digit grouping (G-M-Fg-I) stays flat
+    # in sigma (6 -> 9 iterations), one split per mode (G-M-F-I) degrades
+    # (6 -> 23).  Here M = 4, p = 3: the leading-digit rule gives one split.
+    fg = [_iters(16, s, "fg") for s in (0.5, 1.0, 1.5)]
+    pm = [_iters(16, s, "permode") for s in (0.5, 1.5)]
+    assert max(fg) <= 10 and max(fg) - min(fg) <= 2, fg
+    assert pm[1] >= 2 * pm[0], pm
+
+
+def test_paper_trend_in_the_mesh():
+    # Tab. mesh_variation: multigrid iteration counts do not grow with the mesh
+    its = [_iters(n, 0.8, "fg", M=2, p=3) for n in (8, 16, 32)]
+    assert max(its) - min(its) <= 1, its
