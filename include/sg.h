@@ -55,7 +55,14 @@ enum { SG_COV_EXP_L1 = 0, SG_COV_SQEXP = 1 };
  * stiffness A_0 per mode), field split (forward block Gauss-Seidel over
  * ordered splits of the modes, eqs. P_preconditioner / P_group, with the
  * same V-cycle for every diagonal block) */
-enum { SG_PC_NONE = 0, SG_PC_MEAN = 1, SG_PC_FS = 2, SG_PC_LEARNED = 3 };
+enum { SG_PC_NONE = 0, SG_PC_MEAN = 1, SG_PC_FS = 2, SG_PC_LEARNED = 3, SG_PC_MG = 4 };
+/* SG_PC_MG: one multigrid V(1,1) cycle on the full SG system K (Sec. 3, the
+ * paper's G-M-F-I / G-M-Fg-I family; needs sg_mg_bind): levels n, n/2, ..., 4
+ * rediscretised with the KL values at each level's Gauss points, the
+ * field-split level iteration of eq. level_solver as the smoother with the
+ * bound grouping's splits (each split's diagonal block approximated by its
+ * nodal blocks, inverted exactly, damping 8/9), bilinear transfers, and a
+ * direct solve on the 4 x 4 grid.                                          */
 /* flag OR-ed into SG_PC_MEAN or SG_PC_FS: the V(2,2) cycle of mode i runs on
  * that mode's own diagonal block K_ii = sum_k [G_k]_{ii} A_k (the paper's
  * diagonal blocks of eq. P_preconditioner) instead of the mean stiffness A_0 */
@@ -195,6 +202,22 @@ int sg_apply_form(const sg_handle* h, int* form, int* points_per_batch);
  * grouping; SG_PC_LEARNED without an attached network), NOT_BOUND.       */
 int sg_precond_apply(sg_handle* h, int pc, int grouping, const double* r, double* z,
                      void* stream);
+
+/* Multigrid on the full SG system (SG_PC_MG; Sec. 3, eqs. level_solver and
+ * P_group).  sg_mg_workspace_bytes: device bytes for `grouping` (the splits
+ * of the smoother; SG_GROUP_FG is the paper's G-M-Fg-I, SG_GROUP_PERMODE its
+ * G-M-F-I), 0 for a bad argument.  sg_mg_bind builds the hierarchy in a
+ * caller-owned, 256-byte aligned workspace on a bound handle: the KL values
+ * of every coarser level, the nodal blocks of every split on every level but
+ * the coarsest (K applied to probe vectors, one mode and one of four node
+ * colours at a time, then inverted in place), and the coarsest level's K
+ * (column by column) inverted on the host.  Synchronises `stream`.  The
+ * workspace must outlive the multigrid's use; binding again replaces the
+ * hierarchy.  SG_PC_MG calls must pass the bound grouping.  Errors:
+ * INVALID_ARG, NOT_BOUND (handle), UNSUPPORTED (the triple-product apply
+ * form, i.e. q < 2p, or a split of more than 128 modes), WORKSPACE, HIP.  */
+size_t sg_mg_workspace_bytes(const sg_handle* h, int grouping);
+int sg_mg_bind(sg_handle* h, int grouping, void* ws, size_t bytes, void* stream);
 
 /* r = F - K u, the residual of the SG system K u = F (Sec. 2.2, eq.
  * stochastic_matrix), with K applied as by sg_apply.  F, u, r: device,

@@ -12,6 +12,7 @@ from .binding import (  # noqa: F401
     sg_set_apply, sg_apply_form,
     sg_precond_apply, sg_gmres_workspace_bytes, sg_gmres_solve, sg_export,
     sg_destroy, sg_last_error, SGInstance, CNN, sg_residual, Batch, sg_autotune_apply,
+    sg_mg_workspace_bytes, sg_mg_bind,
     sg_cnn_create, sg_cnn_param_counts, sg_cnn_workspace_bytes, sg_cnn_bind, sg_cnn_set_params,
     sg_cnn_get_params, sg_cnn_make_pair, sg_cnn_run, sg_cnn_get_grads, sg_cnn_apply,
     sg_cnn_destroy, sg_cnn_last_error, sg_attach_cnn,

@@ -13,7 +13,7 @@ from dataclasses import dataclass
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 COV = {"exp_l1": 0, "sqexp": 1}
-PC = {"none": 0, "mean": 1, "fs": 2, "learned": 3, "mean_kii": 0x101, "fs_kii": 0x102,
+PC = {"none": 0, "mean": 1, "fs": 2, "learned": 3, "mg": 4, "mean_kii": 0x101, "fs_kii": 0x102,
       "learned_kii": 0x103}
 GROUPING = {"klvar": 0, "klvar_meansep": 1, "permode": 2, "fg": 3}
 EXPORT = {"coeff": 0, "kl": 1, "gq": 2, "stencil": 3, "groups": 4}
@@ -89,6 +89,8 @@ def load_library():
         "sg_cnn_get_params": (I32, [HP, VP, VP]),
         "sg_cnn_make_pair": (I32, [HP, VP, VP, VP, VP, VP, VP]),
         "sg_residual": (I32, [HP, VP, VP, VP, VP]),
+        "sg_mg_workspace_bytes": (SZ, [HP, I32]),
+        "sg_mg_bind": (I32, [HP, I32, VP, SZ, VP]),
         "sg_cnn_run": (I32, [HP, VP, VP, VP, VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
                              ctypes.c_int32, VP, ctypes.POINTER(ctypes.c_double), VP]),
         "sg_cnn_get_grads": (I32, [HP, VP, VP]),
@@ -271,6 +273,16 @@ def sg_apply_noalloc(h, U, W, stream=None):
     _check(load_library().sg_apply_noalloc(h, _ptr(U), _ptr(W), _stream(stream)))
 
 
+def sg_mg_workspace_bytes(h, grouping) -> int:
+    grouping = GROUPING[grouping] if isinstance(grouping, str) else int(grouping)
+    return int(load_library().sg_mg_workspace_bytes(h, grouping))
+
+
+def sg_mg_bind(h, grouping, ws, nbytes, stream=None):
+    grouping = GROUPING[grouping] if isinstance(grouping, str) else int(grouping)
+    _check(load_library().sg_mg_bind(h, grouping, _ptr(ws), nbytes, _stream(stream)))
+
+
 def sg_residual(h, F, u, r, stream=None):
     _check(load_library().sg_residual(h, _ptr(F), _ptr(u), _ptr(r), _stream(stream)))
 
@@ -384,6 +396,18 @@ class SGInstance:
         r = self.vec() if r is None else r
         sg_residual(self.h, F, u, r, self.stream)
         return r
+
+    def bind_mg(self, grouping="fg"):
+        """Builds the full-system multigrid (pc="mg") for `grouping` in a device
+        workspace owned by this instance."""
+        import torch
+        nb = sg_mg_workspace_bytes(self.h, grouping)
+        if nb == 0:
+            raise SGError(-1, "bad grouping for the full-system multigrid")
+        self.mg_ws = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.mg_ws.data_ptr()) % 256
+        sg_mg_bind(self.h, grouping, self.mg_ws.data_ptr() + off, nb, self.stream)
+        self.mg_grouping = grouping
 
     def attach(self, net, sigma):
         """Attaches a bound CNN (see CNN) for pc="learned" solves."""

@@ -95,6 +95,25 @@ struct Carver {
 
 }  // namespace
 
+// Multigrid on the full SG system (sg_mg_bind): per level its grid, KL values
+// at its Gauss points and edge buffer (level 0: the handle's own), right-hand
+// side and correction (level 0: the caller's), work vectors, and the inverted
+// nodal blocks of every split; the coarsest level's dense inverse.
+struct MGLevel {
+  int n = 0;
+  int64_t N = 0;
+  double *g = nullptr, *edge = nullptr, *b = nullptr, *z = nullptr;
+  double *res = nullptr, *dz = nullptr, *t = nullptr;
+  std::vector<double*> Dinv;
+};
+struct MGState {
+  bool bound = false;
+  int grouping = -1;
+  std::vector<MGLevel> L;
+  double* Cinv = nullptr;  // coarsest level: K^{-1}, column-major Nc x Nc
+  int Nc = 0;
+};
+
 struct sg_handle {
   sg_problem prob{};
   int n = 0, M = 0, P = 0, na = 0, nt = 0, ntiles = 0;
@@ -133,6 +152,7 @@ struct sg_handle {
   hipEvent_t fetched = nullptr;   // marks the Krylov scalars' copy to host_pinned
   sg_cnn* cnn = nullptr;          // attached learned stage (not owned)
   double cnn_sigma = 0.0;
+  MGState mg;                     // full-system multigrid (sg_mg_bind)
 
   ~sg_handle() {
     if (host_pinned) (void)hipHostFree(host_pinned);
@@ -757,6 +777,181 @@ double* noalloc_scratch() {
   return g_scratch_dev[dev];
 }
 
+// ---- multigrid on the full SG system ----------------------------------------
+// (Sec. 3: one V-cycle on K preconditions GMRES; every level carries the whole
+// SG operator, the smoother is the field-split level iteration of eq.
+// level_solver, the coarsest level is solved directly.)  Levels n, n/2, ..., 4
+// are rediscretised: the operator-apply kernels run on each level's grid with
+// the KL values at that level's Gauss points.  The smoother's split blocks are
+// the nodal blocks of K restricted to each split's modes, inverted exactly.
+constexpr int kMGPre = 1, kMGPost = 1;
+constexpr int kMGCoarseN = 4;
+
+// g_m at the Gauss points of the nl-element grid, tile order: the 1D
+// eigenvectors of the finest grid (P1) interpolated linearly at the level's
+// Gauss abscissae, g_m = sqrt(lambda_m) e_r(x_1) e_s(x_2).
+std::vector<double> mg_level_g(const sg_handle& H, int nl) {
+  const int n = H.n, ratio = n / nl;
+  const int64_t Nq = (int64_t)4 * nl * nl;
+  const double gp[2] = {0.5 * (1.0 - 1.0 / std::sqrt(3.0)), 0.5 * (1.0 + 1.0 / std::sqrt(3.0))};
+  std::vector<double> out((size_t)H.M * Nq);
+  auto e_at = [&](const std::vector<double>& e, int el, int q) {
+    const double t = (el + gp[q]) * ratio;
+    const int i = std::min((int)std::floor(t), n - 1);
+    const double f = t - i;
+    return (1.0 - f) * e[i] + f * e[i + 1];
+  };
+  for (int m = 0; m < H.M; ++m) {
+    const auto& er = H.kl.e1[H.kl.pairs[m].first];
+    const auto& es = H.kl.e1[H.kl.pairs[m].second];
+    const double sq = std::sqrt(H.kl.lam[m]);
+    for (int ey = 0; ey < nl; ++ey)
+      for (int ex = 0; ex < nl; ++ex)
+        for (int qy = 0; qy < 2; ++qy)
+          for (int qx = 0; qx < 2; ++qx)
+            out[(size_t)m * Nq + tiled_q(nl, ex, ey, qx, qy)] = sq * e_at(es, ey, qy) * e_at(er, ex, qx);
+  }
+  return out;
+}
+
+// Carves (or, with base == nullptr, sizes) the multigrid workspace.
+size_t mg_layout(const sg_handle& H, int grouping, MGState& st, char* base) {
+  Carver c{base};
+  const auto& splits = H.fs[grouping].splits;
+  size_t maxm = 0;
+  for (const auto& g : splits) maxm = std::max(maxm, g.size());
+  st.L.clear();
+  for (int nl = H.n;; nl /= 2) {
+    MGLevel L;
+    L.n = nl;
+    L.N = (int64_t)(nl - 1) * (nl - 1);
+    const size_t PN = (size_t)H.P * L.N;
+    const bool last = nl <= kMGCoarseN;
+    if (nl != H.n) {
+      L.g = c.take<double>((size_t)H.M * 4 * nl * nl);
+      L.edge = c.take<double>((size_t)H.P * (nl / kTileE) * (nl / kTileE) * kEdgeVals);
+      L.b = c.take<double>(PN);
+      L.z = c.take<double>(PN);
+    }
+    L.res = c.take<double>(PN);
+    L.dz = c.take<double>(PN);
+    L.t = c.take<double>(maxm * L.N);
+    if (!last)
+      for (const auto& g : splits) L.Dinv.push_back(c.take<double>(g.size() * g.size() * L.N));
+    st.L.push_back(L);
+    if (last) break;
+  }
+  st.Nc = (int)(H.P * st.L.back().N);
+  st.Cinv = c.take<double>((size_t)st.Nc * st.Nc);
+  return c.off;
+}
+
+// out = beta rin + sgn K_l U on level l (the whole operator)
+void mg_apply(sg_handle& H, hipStream_t s, int l, const double* U, const double* rin, double beta,
+              double sgn, double* out) {
+  const MGLevel& L = H.mg.L[l];
+  const double* g = l ? L.g : H.d.g;
+  double* edge = l ? L.edge : H.d.edge;
+  if (!H.use_factored) throw Error(SG_ERR_UNSUPPORTED, "full-system multigrid needs the factored apply");
+  if (H.use_rapply)
+    launch_rapply(s, H.M, H.prob.p, L.n, H.prob.mu, H.prob.a_min, g, H.rfull, U, L.N, rin, beta,
+                  sgn, out, edge, true);
+  else
+    launch_fapply(s, L.n, H.prob.mu, H.prob.a_min, g, H.d.ffull, U, L.N, rin, beta, sgn, out, edge,
+                  true);
+}
+
+// out (the split's rows, compact) = rin_{g_sp} - K_{g_sp, g_<sp} U on level l
+void mg_partial(sg_handle& H, hipStream_t s, int l, int sp, const double* U, const double* rin,
+                double* out) {
+  const MGLevel& L = H.mg.L[l];
+  const int gr = H.mg.grouping;
+  const double* g = l ? L.g : H.d.g;
+  double* edge = l ? L.edge : H.d.edge;
+  if (H.use_rapply)
+    launch_rapply(s, H.M, H.prob.p, L.n, H.prob.mu, H.prob.a_min, g, H.rpart[gr][sp], U, L.N, rin,
+                  1.0, -1.0, out, edge, true, H.rkv[gr][sp]);
+  else
+    launch_fapply(s, L.n, H.prob.mu, H.prob.a_min, g, H.d.fs[gr].fpartial[sp], U, L.N, rin, 1.0,
+                  -1.0, out, edge, true);
+}
+
+// One level iteration z <- z + P_FS^{-1}(b - K z) (eq. level_solver); with
+// zero_start the residual is b itself and the correction is written to z.
+void mg_smooth(sg_handle& H, hipStream_t s, int l, const double* b, double* z, bool zero_start) {
+  const MGLevel& L = H.mg.L[l];
+  const FSHost& fh = H.fs[H.mg.grouping];
+  const FSDev& fd = H.d.fs[H.mg.grouping];
+  const double* res = b;
+  double* dz = z;
+  if (!zero_start) {
+    mg_apply(H, s, l, z, b, 1.0, -1.0, L.res);
+    res = L.res;
+    dz = L.dz;
+  }
+  for (size_t sp = 0; sp < fh.splits.size(); ++sp) {
+    const int mm = (int)fh.splits[sp].size();
+    if (sp == 0) {
+      launch_mg_block(s, L.Dinv[0], mm, L.N, res, fd.split_idx[0], fd.split_idx[0], kOmega, dz);
+    } else {
+      mg_partial(H, s, l, (int)sp, dz, res, L.t);
+      launch_mg_block(s, L.Dinv[sp], mm, L.N, L.t, nullptr, fd.split_idx[sp], kOmega, dz);
+    }
+  }
+  if (!zero_start) launch_mg_axpy(s, L.dz, z, (int64_t)H.P * L.N);
+}
+
+// z = V(b) on level l (V(kMGPre, kMGPost) from z = 0)
+void mg_vcycle(sg_handle& H, hipStream_t s, int l, const double* b, double* z) {
+  const int last = (int)H.mg.L.size() - 1;
+  if (l == last) {
+    launch_mg_dense(s, H.mg.Cinv, b, z, H.mg.Nc);
+    return;
+  }
+  MGLevel& L = H.mg.L[l];
+  MGLevel& C = H.mg.L[l + 1];
+  for (int k = 0; k < kMGPre; ++k) mg_smooth(H, s, l, b, z, k == 0);
+  mg_apply(H, s, l, z, b, 1.0, -1.0, L.res);
+  launch_mg_restrict(s, L.res, C.b, L.n, H.P);
+  mg_vcycle(H, s, l + 1, C.b, C.z);
+  launch_mg_prolong_add(s, C.z, z, L.n, H.P);
+  for (int k = 0; k < kMGPost; ++k) mg_smooth(H, s, l, b, z, false);
+}
+
+// In-place inverse of a dense n x n column-major matrix (Gauss-Jordan with
+// partial pivoting; element (i, j) at A[j*n + i]); false when singular.
+bool dense_inverse(std::vector<double>& A, int n) {
+  std::vector<int> piv(n);
+  std::vector<double> f(n);
+  for (int k = 0; k < n; ++k) {
+    double* ck = &A[(size_t)k * n];
+    int p = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(ck[i]) > std::fabs(ck[p])) p = i;
+    if (ck[p] == 0.0) return false;
+    piv[k] = p;
+    if (p != k)
+      for (int j = 0; j < n; ++j) std::swap(A[(size_t)j * n + k], A[(size_t)j * n + p]);
+    const double d = 1.0 / ck[k];
+    ck[k] = 1.0;
+    for (int j = 0; j < n; ++j) A[(size_t)j * n + k] *= d;   // row k
+    for (int i = 0; i < n; ++i) f[i] = (i == k) ? 0.0 : ck[i];
+    for (int i = 0; i < n; ++i)
+      if (i != k) ck[i] = 0.0;
+    for (int j = 0; j < n; ++j) {
+      double* cj = &A[(size_t)j * n];
+      const double akj = cj[k];
+      if (akj == 0.0) continue;
+      for (int i = 0; i < n; ++i) cj[i] -= f[i] * akj;
+    }
+  }
+  // undo the row swaps as column swaps, in reverse order
+  for (int k = n - 1; k >= 0; --k)
+    if (piv[k] != k)
+      for (int i = 0; i < n; ++i) std::swap(A[(size_t)k * n + i], A[(size_t)piv[k] * n + i]);
+  return true;
+}
+
 void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double* r, double* z) {
   const int64_t Nv = (int64_t)H.P * H.Nh;
   const bool kii = (pc & SG_PC_DIAG_KII) != 0;
@@ -767,6 +962,13 @@ void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double*
   }
   if (kind == SG_PC_MEAN) {
     vcycle(H, s, H.P, kii ? H.d.all_sid : nullptr, r, z);
+    return;
+  }
+  if (kind == SG_PC_MG) {
+    if (!H.mg.bound) throw Error(SG_ERR_NOT_BOUND, "full-system multigrid not bound (sg_mg_bind)");
+    if (grouping != H.mg.grouping)
+      throw Error(SG_ERR_INVALID_ARG, "grouping differs from the one the multigrid was bound with");
+    mg_vcycle(H, s, 0, r, z);
     return;
   }
   if (kind != SG_PC_FS) throw Error(SG_ERR_INVALID_ARG, "unknown preconditioner");
@@ -833,8 +1035,10 @@ void learned_stage(sg_handle& H, hipStream_t s, int fs_pc, int grouping, const d
 
 bool valid_pc(int pc, bool allow_learned = false) {
   const int kind = pc & 0xff, flags = pc & ~0xff;
-  if (kind < SG_PC_NONE || kind > (allow_learned ? SG_PC_LEARNED : SG_PC_FS)) return false;
+  if (kind < SG_PC_NONE || kind > SG_PC_MG) return false;
+  if (kind == SG_PC_LEARNED && !allow_learned) return false;
   if (flags & ~SG_PC_DIAG_KII) return false;
+  if (kind == SG_PC_MG && flags) return false;
   return true;
 }
 
@@ -1244,6 +1448,81 @@ int sg_precond_apply(sg_handle* h, int pc, int grouping, const double* r, double
     }
     do_precond(*h, s, pc, grouping, r, z);
     check_launch();
+    return SG_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  }
+}
+
+size_t sg_mg_workspace_bytes(const sg_handle* h, int grouping) {
+  if (!h || grouping < 0 || grouping > 3) return 0;
+  MGState st;
+  return mg_layout(*h, grouping, st, nullptr);
+}
+
+int sg_mg_bind(sg_handle* h, int grouping, void* ws, size_t bytes, void* stream) {
+  if (!h || !ws) return fail(SG_ERR_INVALID_ARG, "null argument");
+  if (!h->bound) return fail(SG_ERR_NOT_BOUND, "handle not bound");
+  if (grouping < 0 || grouping > 3) return fail(SG_ERR_INVALID_ARG, "unknown grouping");
+  if (!h->use_factored)
+    return fail(SG_ERR_UNSUPPORTED, "full-system multigrid needs the factored apply (q >= 2p)");
+  for (const auto& g : h->fs[grouping].splits)
+    if (mg_block_pad((int)g.size()) == 0)
+      return fail(SG_ERR_UNSUPPORTED, "full-system multigrid: a split of more than 128 modes");
+  if (bytes < sg_mg_workspace_bytes(h, grouping)) return fail(SG_ERR_WORKSPACE, "multigrid workspace too small");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(SG_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  try {
+    sg_handle& H = *h;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    H.mg.bound = false;
+    mg_layout(H, grouping, H.mg, static_cast<char*>(ws));
+    H.mg.grouping = grouping;
+    const auto& splits = H.fs[grouping].splits;
+    const FSDev& fd = H.d.fs[grouping];
+    std::vector<int> split_of(H.P), pos_of(H.P);
+    for (size_t sp = 0; sp < splits.size(); ++sp)
+      for (size_t a = 0; a < splits[sp].size(); ++a) {
+        split_of[splits[sp][a]] = (int)sp;
+        pos_of[splits[sp][a]] = (int)a;
+      }
+    for (size_t l = 1; l < H.mg.L.size(); ++l) upload(s, H.mg.L[l].g, mg_level_g(H, H.mg.L[l].n));
+    const int last = (int)H.mg.L.size() - 1;
+    // nodal blocks: apply K to one mode on one node colour at a time
+    for (int l = 0; l < last; ++l) {
+      MGLevel& L = H.mg.L[l];
+      double* U = L.res;
+      double* W = L.dz;
+      launch_zero(s, U, (int64_t)H.P * L.N);
+      for (int colour = 0; colour < 4; ++colour)
+        for (int j = 0; j < H.P; ++j) {
+          launch_mg_mark(s, U + (int64_t)j * L.N, L.n, colour, 1.0);
+          mg_apply(H, s, l, U, nullptr, 0.0, 1.0, W);
+          const int sp = split_of[j];
+          launch_mg_gather(s, W, L.n, colour, fd.split_idx[sp], (int)splits[sp].size(), pos_of[j],
+                           L.Dinv[sp]);
+          launch_mg_mark(s, U + (int64_t)j * L.N, L.n, colour, 0.0);
+        }
+      for (size_t sp = 0; sp < splits.size(); ++sp)
+        launch_mg_invert(s, L.Dinv[sp], (int)splits[sp].size(), L.N);
+      check_launch();
+    }
+    // coarsest level: K column by column, inverted on the host
+    {
+      MGLevel& L = H.mg.L[last];
+      const int Nc = H.mg.Nc;
+      for (int col = 0; col < Nc; ++col) {
+        launch_mg_unit(s, L.res, Nc, col);
+        mg_apply(H, s, last, L.res, nullptr, 0.0, 1.0, H.mg.Cinv + (int64_t)col * Nc);
+      }
+      check_launch();
+      std::vector<double> A((size_t)Nc * Nc);
+      SG_HIP(hipMemcpyAsync(A.data(), H.mg.Cinv, A.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      SG_HIP(hipStreamSynchronize(s));
+      if (!dense_inverse(A, Nc)) throw Error(SG_ERR_INTERNAL, "coarsest multigrid level is singular");
+      SG_HIP(hipMemcpyAsync(H.mg.Cinv, A.data(), A.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    SG_HIP(hipStreamSynchronize(s));
+    H.mg.bound = true;
     return SG_OK;
   } catch (const Error& e) {
     return fail(e.code, e.what());

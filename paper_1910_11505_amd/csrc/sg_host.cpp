@@ -240,6 +240,7 @@ KL karhunen_loeve(int n, int cov, double corr_len, double sigma, int M) {
   }
   chosen.resize(M);
   KL kl;
+  kl.e1 = E;
   const int Nq = 4 * n * n;
   kl.gq.assign((size_t)M * Nq, 0.0);
   const double g0 = 0.5 * (1.0 - 1.0 / std::sqrt(3.0)), g1 = 0.5 * (1.0 + 1.0 / std::sqrt(3.0));

@@ -46,6 +46,7 @@ struct KL {
   std::vector<double> lam;               // M eigenvalues (with sigma^2)
   std::vector<std::pair<int, int>> pairs;
   std::vector<double> gq;                // M x Nq, canonical q order
+  std::vector<std::vector<double>> e1;   // 1D eigenvectors (n+1 nodal values) of the pairs' factors
 };
 KL karhunen_loeve(int n, int cov, double corr_len, double sigma, int M);
 
@@ -291,6 +292,19 @@ void launch_axpby(hipStream_t s, double a, const double* x, double b, double* y,
 void launch_sub(hipStream_t s, const double* a, const double* b, double* out, int64_t N);
 void launch_stage_alpha(hipStream_t s, double* dots, const double* c, const double* kc, double* z,
                         double* w, int64_t N);
+// multigrid on the full SG system (sg_mg.hip)
+void launch_mg_mark(hipStream_t s, double* u, int n, int colour, double val);
+void launch_mg_gather(hipStream_t s, const double* W, int n, int colour, const int* modes, int mm,
+                      int b, double* D);
+int mg_block_pad(int mm);  // padded block size of the inversion kernel, 0 if mm > 128
+void launch_mg_invert(hipStream_t s, double* D, int mm, int64_t N);
+void launch_mg_block(hipStream_t s, const double* Dinv, int mm, int64_t N, const double* t,
+                     const int* tmap, const int* modes, double omega, double* dz);
+void launch_mg_restrict(hipStream_t s, const double* rf, double* rc, int nf, int P);
+void launch_mg_prolong_add(hipStream_t s, const double* zc, double* zf, int nf, int P);
+void launch_mg_dense(hipStream_t s, const double* C, const double* b, double* x, int Nc);
+void launch_mg_axpy(hipStream_t s, const double* x, double* y, int64_t n);
+void launch_mg_unit(hipStream_t s, double* u, int64_t n, int64_t idx);
 
 // ---- batched solves (sg_batch.cpp, batched kernels in sg_kernels.hip) ------
 constexpr int kMaxSplitsB = 12;

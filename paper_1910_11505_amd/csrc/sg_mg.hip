@@ -1,0 +1,262 @@
+// HIP kernels (gfx950) of the multigrid V-cycle on the full stochastic-
+// Galerkin system (Sec. 3: multigrid on K with the field-split level
+// iteration of eq. level_solver as the smoother, the G-M-F-I / G-M-Fg-I
+// family).  Every level carries the whole SG operator, applied by the
+// operator-apply kernels on that level's grid; these kernels add:
+//  * the nodal split blocks: probe vectors for the apply (one mode, one of
+//    four node colours), the gather of the probed columns, and the in-place
+//    inversion of every node's |g| x |g| block;
+//  * the smoother's block step dz_{g}(node) = omega D_node^{-1} t(node);
+//  * the transfers (bilinear prolongation, restriction by its transpose) for
+//    all modes at once, and the dense solve of the coarsest level.
+// Vectors are mode-major (entry i*N + node, node = (iy-1)(n-1) + (ix-1)).
+// Nodal blocks are stored pair-major, entry (a*m + b)*N + node, so that a
+// thread per node reads consecutive addresses.  No atomics: every output is
+// written by one thread, every sum in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "sg_internal.h"
+
+namespace sg {
+
+namespace {
+
+inline int mg_cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// colour of an interior node: (ix mod 2) + 2 (iy mod 2); two nodes of one
+// colour are at least two grid steps apart in x or in y, so the 9-point
+// couplings of K never join them
+__device__ __forceinline__ int node_colour(int64_t node, int m) {
+  const int ix = (int)(node % m) + 1, iy = (int)(node / m) + 1;
+  return (ix & 1) + 2 * (iy & 1);
+}
+
+__global__ void mg_mark_kernel(double* __restrict__ u, int m, int colour, double val, int64_t N) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node < N && node_colour(node, m) == colour) u[node] = val;
+}
+
+// D[(a*mm + b)*N + node] = W[modes[a]*N + node] for the nodes of one colour
+__global__ void mg_gather_kernel(const double* __restrict__ W, int m, int colour,
+                                 const int* __restrict__ modes, int mm, int b,
+                                 double* __restrict__ D, int64_t N) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = blockIdx.y;
+  if (node >= N || node_colour(node, m) != colour) return;
+  D[((int64_t)a * mm + b) * N + node] = W[(int64_t)modes[a] * N + node];
+}
+
+// In-place inverse of every node's mm x mm block (symmetric positive definite:
+// Gauss-Jordan without pivoting), padded to MP x MP with the identity.  One
+// workgroup per node, thread i holds row i in registers; step k broadcasts
+// the scaled pivot row through LDS.  Steps past mm leave the identity padding
+// unchanged, so only mm steps run.
+template <int MP>
+__global__ __launch_bounds__(MP < 64 ? 64 : MP) __attribute__((amdgpu_waves_per_eu(1, 2))) void mg_invert_kernel(double* __restrict__ D,
+                                                                     int mm, int64_t N) {
+  __shared__ double prow[MP];
+  const int64_t node = blockIdx.x;
+  const int i = threadIdx.x;
+  double a[MP];
+#pragma unroll
+  for (int j = 0; j < MP; ++j)
+    a[j] = (i < mm && j < mm) ? D[((int64_t)i * mm + j) * N + node] : (i == j ? 1.0 : 0.0);
+  // the step loop stays rolled; a[k] is picked by selects over the unrolled
+  // column loop, so the row never leaves the registers
+#pragma unroll 1
+  for (int k = 0; k < mm; ++k) {
+    double f = 0.0;
+#pragma unroll
+    for (int j = 0; j < MP; ++j) f = (j == k) ? a[j] : f;
+    if (i == k) {
+      const double piv = 1.0 / f;
+#pragma unroll
+      for (int j = 0; j < MP; ++j) {
+        a[j] = (j == k) ? piv : a[j] * piv;
+        prow[j] = a[j];
+      }
+    }
+    __syncthreads();
+    if (i != k && i < MP) {
+#pragma unroll
+      for (int j = 0; j < MP; ++j) a[j] = (j == k ? 0.0 : a[j]) - f * prow[j];
+    }
+    __syncthreads();
+  }
+  if (i < mm)
+#pragma unroll
+    for (int j = 0; j < MP; ++j)
+      if (j < mm) D[((int64_t)i * mm + j) * N + node] = a[j];
+}
+
+// dz[modes[a]*N + node] = omega * sum_b Dinv[(a*mm + b)*N + node] t_b(node),
+// t_b = t[(tmap ? tmap[b] : b)*N + node]
+__global__ __launch_bounds__(256) void mg_block_kernel(const double* __restrict__ Dinv, int mm,
+                                                       const double* __restrict__ t,
+                                                       const int* __restrict__ tmap,
+                                                       const int* __restrict__ modes, double omega,
+                                                       double* __restrict__ dz, int64_t N) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = blockIdx.y;
+  if (node >= N) return;
+  const double* row = Dinv + (int64_t)a * mm * N + node;
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  int b = 0;
+  for (; b + 4 <= mm; b += 4) {
+    const int64_t t0 = (int64_t)(tmap ? tmap[b] : b) * N, t1 = (int64_t)(tmap ? tmap[b + 1] : b + 1) * N;
+    const int64_t t2 = (int64_t)(tmap ? tmap[b + 2] : b + 2) * N, t3 = (int64_t)(tmap ? tmap[b + 3] : b + 3) * N;
+    acc0 = fma(row[(int64_t)b * N], t[t0 + node], acc0);
+    acc1 = fma(row[(int64_t)(b + 1) * N], t[t1 + node], acc1);
+    acc2 = fma(row[(int64_t)(b + 2) * N], t[t2 + node], acc2);
+    acc3 = fma(row[(int64_t)(b + 3) * N], t[t3 + node], acc3);
+  }
+  for (; b < mm; ++b)
+    acc0 = fma(row[(int64_t)b * N], t[(int64_t)(tmap ? tmap[b] : b) * N + node], acc0);
+  dz[(int64_t)modes[a] * N + node] = omega * ((acc0 + acc1) + (acc2 + acc3));
+}
+
+// rc = R rf, R = P^T of bilinear interpolation: each interior coarse node
+// gathers its fine counterpart (weight 1), the four edge neighbours (1/2) and
+// the four diagonal neighbours (1/4); all nine are interior fine nodes
+__global__ void mg_restrict_kernel(const double* __restrict__ rf, double* __restrict__ rc, int nf,
+                                   int64_t Nc, int64_t Nf) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int mode = blockIdx.y;
+  if (c >= Nc) return;
+  const int mc = nf / 2 - 1, mf = nf - 1;
+  const int X = (int)(c % mc) + 1, Y = (int)(c / mc) + 1;
+  const double* r = rf + (int64_t)mode * Nf;
+  double acc = 0.0;
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy) {
+    const double wy = dy ? 0.5 : 1.0;
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const double w = wy * (dx ? 0.5 : 1.0);
+      acc = fma(w, r[(int64_t)(2 * Y + dy - 1) * mf + (2 * X + dx - 1)], acc);
+    }
+  }
+  rc[(int64_t)mode * Nc + c] = acc;
+}
+
+// zf += P zc: bilinear interpolation of the coarse interior values (boundary
+// values zero)
+__global__ void mg_prolong_add_kernel(const double* __restrict__ zc, double* __restrict__ zf,
+                                      int nf, int64_t Nc, int64_t Nf) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int mode = blockIdx.y;
+  if (f >= Nf) return;
+  const int mc = nf / 2 - 1, mf = nf - 1;
+  const int fx = (int)(f % mf) + 1, fy = (int)(f / mf) + 1;
+  const double* z = zc + (int64_t)mode * Nc;
+  // 1D stencils: even fine index -> one coarse node, odd -> its two neighbours
+  int xs[2], ys[2];
+  double wx[2], wy[2];
+  int nx, ny;
+  if (fx & 1) { xs[0] = (fx - 1) / 2; xs[1] = (fx + 1) / 2; wx[0] = wx[1] = 0.5; nx = 2; }
+  else { xs[0] = fx / 2; wx[0] = 1.0; nx = 1; }
+  if (fy & 1) { ys[0] = (fy - 1) / 2; ys[1] = (fy + 1) / 2; wy[0] = wy[1] = 0.5; ny = 2; }
+  else { ys[0] = fy / 2; wy[0] = 1.0; ny = 1; }
+  double acc = 0.0;
+  for (int b = 0; b < ny; ++b) {
+    if (ys[b] < 1 || ys[b] > mc) continue;
+    for (int a = 0; a < nx; ++a) {
+      if (xs[a] < 1 || xs[a] > mc) continue;
+      acc = fma(wy[b] * wx[a], z[(int64_t)(ys[b] - 1) * mc + (xs[a] - 1)], acc);
+    }
+  }
+  zf[(int64_t)mode * Nf + f] += acc;
+}
+
+// x = C b, C column-major Nc x Nc (the coarsest level's inverse)
+__global__ void mg_dense_kernel(const double* __restrict__ C, const double* __restrict__ b,
+                                double* __restrict__ x, int Nc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Nc) return;
+  double acc0 = 0.0, acc1 = 0.0;
+  int j = 0;
+  for (; j + 2 <= Nc; j += 2) {
+    acc0 = fma(C[(int64_t)j * Nc + i], b[j], acc0);
+    acc1 = fma(C[(int64_t)(j + 1) * Nc + i], b[j + 1], acc1);
+  }
+  if (j < Nc) acc0 = fma(C[(int64_t)j * Nc + i], b[j], acc0);
+  x[i] = acc0 + acc1;
+}
+
+__global__ void mg_unit_kernel(double* __restrict__ u, int64_t n, int64_t idx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) u[i] = (i == idx) ? 1.0 : 0.0;
+}
+
+__global__ void mg_axpy_kernel(const double* __restrict__ x, double* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += x[i];
+}
+
+}  // namespace
+
+void launch_mg_mark(hipStream_t s, double* u, int n, int colour, double val) {
+  const int64_t N = (int64_t)(n - 1) * (n - 1);
+  hipLaunchKernelGGL(mg_mark_kernel, dim3(mg_cdiv(N, 256)), dim3(256), 0, s, u, n - 1, colour, val, N);
+}
+
+void launch_mg_gather(hipStream_t s, const double* W, int n, int colour, const int* modes, int mm,
+                      int b, double* D) {
+  const int64_t N = (int64_t)(n - 1) * (n - 1);
+  hipLaunchKernelGGL(mg_gather_kernel, dim3(mg_cdiv(N, 256), mm), dim3(256), 0, s, W, n - 1, colour,
+                     modes, mm, b, D, N);
+}
+
+int mg_block_pad(int mm) {
+  for (int mp : {16, 32, 48, 64, 96, 128})
+    if (mm <= mp) return mp;
+  return 0;
+}
+
+void launch_mg_invert(hipStream_t s, double* D, int mm, int64_t N) {
+  const int mp = mg_block_pad(mm);
+  const int threads = std::max(64, mp);
+  switch (mp) {
+#define SG_MG_INV(MP)                                                                        \
+  case MP:                                                                                   \
+    hipLaunchKernelGGL(mg_invert_kernel<MP>, dim3((unsigned)N), dim3(threads), 0, s, D, mm, N); \
+    return;
+    SG_MG_INV(16) SG_MG_INV(32) SG_MG_INV(48) SG_MG_INV(64) SG_MG_INV(96) SG_MG_INV(128)
+#undef SG_MG_INV
+    default:
+      throw Error(SG_ERR_UNSUPPORTED, "full-system multigrid: a split of more than 128 modes");
+  }
+}
+
+void launch_mg_block(hipStream_t s, const double* Dinv, int mm, int64_t N, const double* t,
+                     const int* tmap, const int* modes, double omega, double* dz) {
+  hipLaunchKernelGGL(mg_block_kernel, dim3(mg_cdiv(N, 256), mm), dim3(256), 0, s, Dinv, mm, t, tmap,
+                     modes, omega, dz, N);
+}
+
+void launch_mg_restrict(hipStream_t s, const double* rf, double* rc, int nf, int P) {
+  const int64_t Nf = (int64_t)(nf - 1) * (nf - 1), Nc = (int64_t)(nf / 2 - 1) * (nf / 2 - 1);
+  hipLaunchKernelGGL(mg_restrict_kernel, dim3(mg_cdiv(Nc, 256), P), dim3(256), 0, s, rf, rc, nf, Nc, Nf);
+}
+
+void launch_mg_prolong_add(hipStream_t s, const double* zc, double* zf, int nf, int P) {
+  const int64_t Nf = (int64_t)(nf - 1) * (nf - 1), Nc = (int64_t)(nf / 2 - 1) * (nf / 2 - 1);
+  hipLaunchKernelGGL(mg_prolong_add_kernel, dim3(mg_cdiv(Nf, 256), P), dim3(256), 0, s, zc, zf, nf,
+                     Nc, Nf);
+}
+
+void launch_mg_dense(hipStream_t s, const double* C, const double* b, double* x, int Nc) {
+  hipLaunchKernelGGL(mg_dense_kernel, dim3(mg_cdiv(Nc, 256)), dim3(256), 0, s, C, b, x, Nc);
+}
+
+void launch_mg_unit(hipStream_t s, double* u, int64_t n, int64_t idx) {
+  hipLaunchKernelGGL(mg_unit_kernel, dim3(mg_cdiv(n, 256)), dim3(256), 0, s, u, n, idx);
+}
+
+void launch_mg_axpy(hipStream_t s, const double* x, double* y, int64_t n) {
+  hipLaunchKernelGGL(mg_axpy_kernel, dim3(mg_cdiv(n, 256)), dim3(256), 0, s, x, y, n);
+}
+
+}  // namespace sg
