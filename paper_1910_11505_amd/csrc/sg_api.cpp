@@ -837,7 +837,7 @@ size_t mg_layout(const sg_handle& H, int grouping, MGState& st, char* base) {
     L.dz = c.take<double>(PN);
     L.t = c.take<double>(maxm * L.N);
     if (!last)
-      for (const auto& g : splits) L.Dinv.push_back(c.take<double>(g.size() * g.size() * L.N));
+      for (const auto& g : splits) L.Dinv.push_back(c.take<double>(mg_block_doubles((int)g.size()) * L.N));
     st.L.push_back(L);
     if (last) break;
   }

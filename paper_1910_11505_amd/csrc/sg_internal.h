@@ -297,6 +297,7 @@ void launch_mg_mark(hipStream_t s, double* u, int n, int colour, double val);
 void launch_mg_gather(hipStream_t s, const double* W, int n, int colour, const int* modes, int mm,
                       int b, double* D);
 int mg_block_pad(int mm);  // padded block size of the inversion kernel, 0 if mm > 128
+size_t mg_block_doubles(int mm);  // doubles per node of one split's block storage
 void launch_mg_invert(hipStream_t s, double* D, int mm, int64_t N);
 void launch_mg_block(hipStream_t s, const double* Dinv, int mm, int64_t N, const double* t,
                      const int* tmap, const int* modes, double omega, double* dz);

@@ -10,8 +10,10 @@
 //  * the transfers (bilinear prolongation, restriction by its transpose) for
 //    all modes at once, and the dense solve of the coarsest level.
 // Vectors are mode-major (entry i*N + node, node = (iy-1)(n-1) + (ix-1)).
-// Nodal blocks are stored pair-major, entry (a*m + b)*N + node, so that a
-// thread per node reads consecutive addresses.  No atomics: every output is
+// Nodal blocks are stored pair-major (a thread per node reads consecutive
+// addresses): the probed blocks in full, entry (a*m + b)*N + node, their
+// inverses as the upper triangle of the block padded to a compiled size,
+// packed row by row.  No atomics: every output is
 // written by one thread, every sum in a fixed order.
 #include <hip/hip_runtime.h>
 
@@ -48,8 +50,17 @@ __global__ void mg_gather_kernel(const double* __restrict__ W, int m, int colour
   D[((int64_t)a * mm + b) * N + node] = W[(int64_t)modes[a] * N + node];
 }
 
-// In-place inverse of every node's mm x mm block (symmetric positive definite:
-// Gauss-Jordan without pivoting), padded to MP x MP with the identity.  One
+// index of pair (a, b), a <= b < MP, in the row-by-row packing of an MP x MP
+// upper triangle
+template <int MP>
+__host__ __device__ constexpr int64_t packed_pair(int a, int b) {
+  return (int64_t)a * MP - (int64_t)a * (a - 1) / 2 + (b - a);
+}
+
+// Inverse of every node's mm x mm block (symmetric positive definite:
+// Gauss-Jordan without pivoting), padded to MP x MP with the identity.  Reads
+// the full block, entry (a*mm + b)*N + node, and writes the inverse's upper
+// triangle packed into the same array.  One
 // workgroup per node, thread i holds row i in registers; step k broadcasts
 // the scaled pivot row through LDS.  Steps past mm leave the identity padding
 // unchanged, so only mm steps run.
@@ -85,36 +96,47 @@ __global__ __launch_bounds__(MP < 64 ? 64 : MP) __attribute__((amdgpu_waves_per_
     }
     __syncthreads();
   }
-  if (i < mm)
+  // the inverse is symmetric: row i keeps its entries j >= i, packed row by
+  // row over the padded size (pair (i, j) at packed_pair<MP>(i, j)); the
+  // padding rows hold the identity
+  if (i < MP) {
 #pragma unroll
     for (int j = 0; j < MP; ++j)
-      if (j < mm) D[((int64_t)i * mm + j) * N + node] = a[j];
+      if (j >= i) D[packed_pair<MP>(i, j) * N + node] = a[j];
+  }
 }
 
-// dz[modes[a]*N + node] = omega * sum_b Dinv[(a*mm + b)*N + node] t_b(node),
-// t_b = t[(tmap ? tmap[b] : b)*N + node]
-__global__ __launch_bounds__(256) void mg_block_kernel(const double* __restrict__ Dinv, int mm,
+
+// dz[modes[a]*N + node] = omega * sum_b Dinv_ab(node) t_b(node), Dinv the
+// symmetric inverse, its upper triangle packed over the padded size mp
+// (pair-major); t_b = t[(tmap ? tmap[b] : b)*N + node].  One thread per (node,
+// output row); the row index varies fastest over the grid, so the rows of one
+// range of nodes run back to back and the second read of every pair (once
+// for row a, once for row b) is served by the caches.
+__global__ __launch_bounds__(256) void mg_block_kernel(const double* __restrict__ Dinv, int mm, int mp,
                                                        const double* __restrict__ t,
                                                        const int* __restrict__ tmap,
                                                        const int* __restrict__ modes, double omega,
                                                        double* __restrict__ dz, int64_t N) {
-  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int a = blockIdx.y;
+  const int a = blockIdx.x;
+  const int64_t node = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
   if (node >= N) return;
-  const double* row = Dinv + (int64_t)a * mm * N + node;
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  double acc0 = 0.0, acc1 = 0.0;
+  // b < a: pair (b, a) in row b's segment; b >= a: row a's own segment
+  int64_t pr = a;  // packed index of pair (0, a)
   int b = 0;
-  for (; b + 4 <= mm; b += 4) {
-    const int64_t t0 = (int64_t)(tmap ? tmap[b] : b) * N, t1 = (int64_t)(tmap ? tmap[b + 1] : b + 1) * N;
-    const int64_t t2 = (int64_t)(tmap ? tmap[b + 2] : b + 2) * N, t3 = (int64_t)(tmap ? tmap[b + 3] : b + 3) * N;
-    acc0 = fma(row[(int64_t)b * N], t[t0 + node], acc0);
-    acc1 = fma(row[(int64_t)(b + 1) * N], t[t1 + node], acc1);
-    acc2 = fma(row[(int64_t)(b + 2) * N], t[t2 + node], acc2);
-    acc3 = fma(row[(int64_t)(b + 3) * N], t[t3 + node], acc3);
+  for (; b < a; ++b) {
+    const double tb = t[(int64_t)(tmap ? tmap[b] : b) * N + node];
+    if (b & 1) acc1 = fma(Dinv[pr * N + node], tb, acc1);
+    else acc0 = fma(Dinv[pr * N + node], tb, acc0);
+    pr += mp - b - 1;  // from (b, a) to (b + 1, a)
   }
-  for (; b < mm; ++b)
-    acc0 = fma(row[(int64_t)b * N], t[(int64_t)(tmap ? tmap[b] : b) * N + node], acc0);
-  dz[(int64_t)modes[a] * N + node] = omega * ((acc0 + acc1) + (acc2 + acc3));
+  for (; b < mm; ++b, ++pr) {
+    const double tb = t[(int64_t)(tmap ? tmap[b] : b) * N + node];
+    if (b & 1) acc1 = fma(Dinv[pr * N + node], tb, acc1);
+    else acc0 = fma(Dinv[pr * N + node], tb, acc0);
+  }
+  dz[(int64_t)modes[a] * N + node] = omega * (acc0 + acc1);
 }
 
 // rc = R rf, R = P^T of bilinear interpolation: each interior coarse node
@@ -170,19 +192,37 @@ __global__ void mg_prolong_add_kernel(const double* __restrict__ zc, double* __r
   zf[(int64_t)mode * Nf + f] += acc;
 }
 
-// x = C b, C column-major Nc x Nc (the coarsest level's inverse)
-__global__ void mg_dense_kernel(const double* __restrict__ C, const double* __restrict__ b,
-                                double* __restrict__ x, int Nc) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Nc) return;
-  double acc0 = 0.0, acc1 = 0.0;
-  int j = 0;
-  for (; j + 2 <= Nc; j += 2) {
-    acc0 = fma(C[(int64_t)j * Nc + i], b[j], acc0);
-    acc1 = fma(C[(int64_t)(j + 1) * Nc + i], b[j + 1], acc1);
+// x = C b, C column-major Nc x Nc (the coarsest level's inverse): a
+// workgroup takes 64 rows, its 16 wavefronts split the columns, partial sums
+// meet in LDS in a fixed order
+constexpr int kDenseSplit = 16;
+__global__ __launch_bounds__(64 * kDenseSplit) void mg_dense_kernel(const double* __restrict__ C,
+                                                                   const double* __restrict__ b,
+                                                                   double* __restrict__ x, int Nc) {
+  __shared__ double part[kDenseSplit][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const int per = (Nc + kDenseSplit - 1) / kDenseSplit;
+  const int j0 = w * per, j1 = min(Nc, j0 + per);
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  if (i < Nc) {
+    int j = j0;
+    for (; j + 4 <= j1; j += 4) {
+      acc0 = fma(C[(int64_t)j * Nc + i], b[j], acc0);
+      acc1 = fma(C[(int64_t)(j + 1) * Nc + i], b[j + 1], acc1);
+      acc2 = fma(C[(int64_t)(j + 2) * Nc + i], b[j + 2], acc2);
+      acc3 = fma(C[(int64_t)(j + 3) * Nc + i], b[j + 3], acc3);
+    }
+    for (; j < j1; ++j) acc0 = fma(C[(int64_t)j * Nc + i], b[j], acc0);
   }
-  if (j < Nc) acc0 = fma(C[(int64_t)j * Nc + i], b[j], acc0);
-  x[i] = acc0 + acc1;
+  part[w][lane] = (acc0 + acc1) + (acc2 + acc3);
+  __syncthreads();
+  if (w == 0 && i < Nc) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kDenseSplit; ++k) s += part[k][lane];
+    x[i] = s;
+  }
 }
 
 __global__ void mg_unit_kernel(double* __restrict__ u, int64_t n, int64_t idx) {
@@ -210,9 +250,14 @@ void launch_mg_gather(hipStream_t s, const double* W, int n, int colour, const i
 }
 
 int mg_block_pad(int mm) {
-  for (int mp : {16, 32, 48, 64, 96, 128})
+  for (int mp : {16, 32, 35, 48, 56, 64, 70, 84, 96, 128})
     if (mm <= mp) return mp;
   return 0;
+}
+
+size_t mg_block_doubles(int mm) {
+  const size_t mp = (size_t)mg_block_pad(mm);
+  return std::max((size_t)mm * mm, mp * (mp + 1) / 2);
 }
 
 void launch_mg_invert(hipStream_t s, double* D, int mm, int64_t N) {
@@ -223,7 +268,8 @@ void launch_mg_invert(hipStream_t s, double* D, int mm, int64_t N) {
   case MP:                                                                                   \
     hipLaunchKernelGGL(mg_invert_kernel<MP>, dim3((unsigned)N), dim3(threads), 0, s, D, mm, N); \
     return;
-    SG_MG_INV(16) SG_MG_INV(32) SG_MG_INV(48) SG_MG_INV(64) SG_MG_INV(96) SG_MG_INV(128)
+    SG_MG_INV(16) SG_MG_INV(32) SG_MG_INV(35) SG_MG_INV(48) SG_MG_INV(56) SG_MG_INV(64)
+    SG_MG_INV(70) SG_MG_INV(84) SG_MG_INV(96) SG_MG_INV(128)
 #undef SG_MG_INV
     default:
       throw Error(SG_ERR_UNSUPPORTED, "full-system multigrid: a split of more than 128 modes");
@@ -232,8 +278,8 @@ void launch_mg_invert(hipStream_t s, double* D, int mm, int64_t N) {
 
 void launch_mg_block(hipStream_t s, const double* Dinv, int mm, int64_t N, const double* t,
                      const int* tmap, const int* modes, double omega, double* dz) {
-  hipLaunchKernelGGL(mg_block_kernel, dim3(mg_cdiv(N, 256), mm), dim3(256), 0, s, Dinv, mm, t, tmap,
-                     modes, omega, dz, N);
+  hipLaunchKernelGGL(mg_block_kernel, dim3(mm, mg_cdiv(N, 256)), dim3(256), 0, s, Dinv, mm,
+                     mg_block_pad(mm), t, tmap, modes, omega, dz, N);
 }
 
 void launch_mg_restrict(hipStream_t s, const double* rf, double* rc, int nf, int P) {
@@ -248,7 +294,8 @@ void launch_mg_prolong_add(hipStream_t s, const double* zc, double* zf, int nf, 
 }
 
 void launch_mg_dense(hipStream_t s, const double* C, const double* b, double* x, int Nc) {
-  hipLaunchKernelGGL(mg_dense_kernel, dim3(mg_cdiv(Nc, 256)), dim3(256), 0, s, C, b, x, Nc);
+  hipLaunchKernelGGL(mg_dense_kernel, dim3(mg_cdiv(Nc, 64)), dim3(64 * kDenseSplit), 0, s, C, b, x,
+                     Nc);
 }
 
 void launch_mg_unit(hipStream_t s, double* u, int64_t n, int64_t idx) {
