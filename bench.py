@@ -1,21 +1,27 @@
 #!/usr/bin/env python3
-"""Benchmark: FP64 field-split GMRES(50) time-to-relres-1e-8 on one MI355X.
+"""Benchmark: FP64 SG-GMRES(50) time to relres 1e-8 on one MI355X, 256x256 sigma sweep.
 
-One step = one complete solve of the stochastic-Galerkin system of the
-field-split workload (Q1 128x128, squared-exponential covariance with
-L_c = 0.5, sigma = 1.0, M = 4 KL terms, chaos degree p = 3 (P = 35 modes),
-coefficient degree q = 6 (210 modes), f = 1): every GMRES iteration runs the
-field-split block Gauss-Seidel preconditioner (one split per KL variable,
-V(2,2) multigrid on the mean stiffness) and the matrix-free SG apply, and the
-true FP64 residual is recomputed at the end.  Inputs are resident in device
-memory before the timed region; set-up (sg_setup / sg_bind) is reported
-separately.
+One step = one pass of the hot path over the 256x256 workload (Q1 256x256
+elements, L1-exponential covariance with L_c = 0.25, mu = 0, a_min = 0.01,
+M = 6 KL terms, chaos degree p = 3 (P = 84 modes), coefficient degree q = 6
+(924 modes), f = 1 + 0.1 N(0,1) at the nodes): for each sigma in {0.5, 1.0,
+1.5}, three complete GMRES(50) solves to the FP64 true relative residual
+1e-8, with
+  * the mean-based preconditioner (one V(2,2) cycle on A_0 per mode),
+  * the field split (block Gauss-Seidel, one split per KL variable, V(2,2)
+    on A_0 per mode),
+  * one V(1,1) cycle of multigrid on the full SG system with the field-split
+    level smoother (leading-digit grouping: the paper's G-M-Fg-I family).
+Every iteration runs the matrix-free SG apply, the preconditioner and CGS2
+Arnoldi on the device; inputs are resident in device memory before the timed
+region; set-up (sg_setup / sg_bind / sg_mg_bind) is reported separately.
 
-Prints one JSON line.  Also reported: the mean-based solve on the same system,
-the SG apply's achieved FP64 rate against the FP64 vector roofline (its
-algorithmic intensity lies above the ridge; the HBM rate is reported beside it;
-HIP events on the stream the kernels run on), and the CPU oracle timed on a
-bounded sample.
+Prints one JSON line.  Also reported: per-solve iterations and times, the SG
+apply's achieved FP64 rate against the FP64 vector roofline (HIP events on
+the stream the kernels run on; the HBM rate beside it), the 128x128 field
+split of the earlier headline, the 64-instance batched workload, the learned
+stage against the field split with the network's BF16 rates, and the CPU
+oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -30,27 +36,37 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GMRES time-to-relres-1e-8 (s) + SG apply HBM GB/s; learned-FGMRES vs field-split"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2500.0
+SIGMAS = (0.5, 1.0, 1.5)
+PCS = ("mean", "fs", "mg")
+MG_GROUPING = "fg"
 
-# HBM bytes of one whole apply (the register-resident factored kernel
-# rapply_kernel<4,3,true> plus apply_fixup_kernel) on the 128x128 workload from
-# two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each
-# scaled by the same counter read on a plain 256 MiB copy (factors 2.0 and 1.0).
-# Valid only for the kernel source the counters were taken on: the sha256 of
-# sg_rapply.hip + sg_internal.h is compared at run time.
-APPLY_TRAFFIC = {"src_sha256": "1458506e69837c61a55ef6c73334bcb701fb23ec61a927e8b5627158f302a983",
-                 "fetch_bytes": (3493.390625 + 4827.125) * 1024 * 2.0,
-                 "write_bytes": (6937.0 + 4377.4375) * 1024 * 1.0}
+# HBM bytes of one whole apply on the 256x256, P=84 workload (the register
+# kernel rapply_stream_kernel<6,3,true,0> plus apply_fixup_kernel) from two
+# rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
+# scaled by the same counter read on a plain 256 MiB device copy.  Valid only
+# for the kernel source the counters were taken on: the sha256 of
+# sg_rapply.hip + sg_kernels.hip + sg_internal.h is compared at run time.
+APPLY_TRAFFIC = {"src_sha256": "fe7a296002f4dc37440831f3f8db4ce6e9b6524b6f3a716aedd8df8b8c3da464",
+                 "fetch_bytes": (29555.57 + 48464.78) * 1024 * 2.0,
+                 "write_bytes": (71257.69 + 42606.45) * 1024 * 1.0}
+
+
+def _src_hash():
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1910_11505_amd", "csrc")
+    try:
+        src = "".join(open(os.path.join(csrc, f)).read()
+                      for f in ("sg_rapply.hip", "sg_kernels.hip", "sg_internal.h"))
+    except OSError:
+        return None
+    return hashlib.sha256(src.encode()).hexdigest()
 
 
 def apply_traffic():
     """Measured HBM bytes per apply, or None once the kernel source has changed."""
-    import hashlib
-    csrc = os.path.join(ROOT, "paper_1910_11505_amd", "csrc")
-    try:
-        src = "".join(open(os.path.join(csrc, f)).read() for f in ("sg_rapply.hip", "sg_internal.h"))
-    except OSError:
-        return None
-    if hashlib.sha256(src.encode()).hexdigest() != APPLY_TRAFFIC["src_sha256"]:
+    if APPLY_TRAFFIC is None or _src_hash() != APPLY_TRAFFIC["src_sha256"]:
         return None
     return APPLY_TRAFFIC["fetch_bytes"] + APPLY_TRAFFIC["write_bytes"]
 
@@ -60,58 +76,25 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--apply-reps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=24)
-    ap.add_argument("--no-c2-apply", action="store_true",
-                    help="skip the HBM-bound apply measurement on the 256x256, 924-mode shape")
-    ap.add_argument("--no-sigma-sweep", action="store_true",
-                    help="skip the 256x256, P=84 sigma sweep (0.5, 1.0, 1.5) with the "
-                         "mean-based and field-split preconditioners")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 128x128 context solves")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batched workload")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-stage comparison (learned workload, reduced training)")
-    ap.add_argument("--fs-large", action="store_true",
-                    help="also time field-split iterations on the 256x256, P=210 instance")
     ap.add_argument("--learned-pairs", type=int, default=640)
     ap.add_argument("--learned-steps", type=int, default=1200)
-    ap.add_argument("--apply-form", default="factored", choices=["factored", "triple"],
-                    help="apply form of the counter-collection mode")
+    ap.add_argument("--learned-draws", type=int, default=4)
     ap.add_argument("--profile-apply", action="store_true",
-                    help="counter-collection mode: only the 128x128 apply loop and a plain "
+                    help="counter-collection mode: only the 256x256 P=84 apply loop and a plain "
                          "256 MiB device copy (the scale reference for FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--profile-step", action="store_true",
+                    help="kernel-trace mode: set-up, warm-up and timed steps only")
     return ap.parse_args()
 
 
 def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-def time_applies(inst, reps, stream, seed=11505):
-    """Average SG-apply launch time (ms) over `reps` back-to-back applies on the
-    stream the kernels run on, plus the algorithmic bytes of one apply in the
-    form in use: U read once, W written once (FP64), and either every
-    coefficient mode a_k at every Gauss point (triple-product form) or the M
-    KL values g_n at every Gauss point (factored form)."""
-    import torch
-    from synth import random_vector
-    dev = torch.device("cuda:0")
-    U = torch.from_numpy(random_vector(inst.nvec, seed)).to(dev)
-    W = inst.vec()
-    for _ in range(3):
-        inst.apply(U, W)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        inst.apply(U, W)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    return ms
-
-
-FP64_PEAK_TFLOPS = 78.6
 
 
 def chaos_pairs(M, p):
@@ -129,149 +112,223 @@ def chaos_pairs(M, p):
     return tot
 
 
-def apply_flops(inst):
+def apply_flops(prob, P):
     """FP64 flops of one factored apply of the whole operator, per Gauss point and
     gradient component: 2 nnz(T) in each of the two contraction steps (one FMA per
     pair), 6P for the scaled gradients, P for the step-1 scaling, 4P for the flux
     scale and the a_min term, 7P for the four corner products and their reduction."""
-    Nq = 4 * inst.prob.n * inst.prob.n
-    return float(Nq * 2 * (4 * chaos_pairs(inst.prob.M, inst.prob.p) + 18 * inst.P))
+    Nq = 4 * prob.n * prob.n
+    return float(Nq * 2 * (4 * chaos_pairs(prob.M, prob.p) + 18 * P))
 
 
-def apply_bytes(inst, form):
-    Nq = 4 * inst.prob.n * inst.prob.n
-    per_point = inst.na if form == "triple" else inst.prob.M
-    return 8.0 * (per_point * Nq + 2 * inst.P * inst.Nh)
+def apply_bytes(prob, P, Nh):
+    """Algorithmic bytes of the factored apply: the M KL values at every Gauss
+    point, U read once and W written once (FP64)."""
+    return 8.0 * (prob.M * 4 * prob.n * prob.n + 2 * P * Nh)
 
 
-def measure_apply_forms(inst, reps, stream):
-    """Both forms of the apply on one instance: time, bytes, GB/s."""
-    out = {}
-    for form in ("factored", "triple"):
-        inst.set_apply(form)
-        ms = time_applies(inst, reps, stream)
-        nb = apply_bytes(inst, form)
-        out[form] = {"ms": ms, "algorithmic_bytes": nb, "gbs": nb / (ms * 1e-3) / 1e9,
-                     "frac_hbm_peak": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
-        if form == "factored":
-            fl = apply_flops(inst)
-            out[form].update({"fp64_flops": fl, "tflops": fl / (ms * 1e-3) / 1e12,
-                              "frac_fp64_peak": fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS})
-    inst.set_apply("auto")
-    return out
+def time_applies(inst, reps, stream, seed=11505):
+    """Average time (ms) of one sg_apply (the register kernel and its edge fixup)
+    over `reps` back-to-back applies, HIP events on the stream they run on."""
+    import torch
+    from synth import random_vector
+    U = torch.from_numpy(random_vector(inst.nvec, seed)).to(inst.device)
+    W = inst.vec()
+    for _ in range(3):
+        inst.apply(U, W)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        inst.apply(U, W)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
 
 
-def cpu_baseline(prob, gpu_iters, gpu_restarts, n_iters):
-    """Times the oracle's field-split GMRES on a bounded sample: n_iters Arnoldi
-    steps plus the closing update (n_iters + 1 operator and preconditioner
-    applications), scaled to the GPU's iteration count."""
+def make_c2(sigma):
+    import paper_1910_11505_amd as sg
+    from synth import CONFIGS, rhs_noisy
+    p = CONFIGS["c2"].with_(sigma=sigma)
+    inst = sg.SGInstance(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma, p.corr_len, p.a_min,
+                         f_nodal=rhs_noisy(p.n, 11505 + 2000))
+    return p, inst
+
+
+def run_step(insts, Fs, us, stream, record=None):
+    """One step: the nine solves of the sweep.  With `record`, per-solve times
+    (HIP events) and infos are appended."""
+    import torch
+    for (sigma, inst), F, u in zip(insts, Fs, us):
+        for pc in PCS:
+            if record is not None:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            _, info, _ = inst.solve(F, pc=pc, grouping=MG_GROUPING if pc == "mg" else "klvar",
+                                    restart=50, tol=1e-8, u=u[pc], max_it=3000)
+            if record is not None:
+                e1.record(stream)
+                record.append((sigma, pc, info, e0, e1))
+
+
+def cpu_baseline(total_iterations, total_restarts):
+    """Times the oracle on a bounded sample of the same workload (sigma = 1.0):
+    one mean-based GMRES iteration of the oracle (the SG apply evaluated from
+    the block coefficients, SGSystem.apply_pointwise, and one V(2,2) cycle on
+    A_0 per mode), scaled to the step's iteration and restart counts."""
     import numpy as np
-    from threadpoolctl import threadpool_info
 
+    from oracle import fem
     from oracle.gmg import GMGHierarchy
     from oracle.gmres import gmres
-    from oracle.precond import FieldSplit, make_groups
-    from oracle.system import SGSystem
+    from oracle.system import SGSystem, coeff_modes
+    from synth import CONFIGS, rhs_noisy
 
-    S = SGSystem(prob)
-    _ = S.A
-    H = GMGHierarchy(S.A[0], prob.n)
-    fs = FieldSplit(S, H, make_groups(S.Jp, "klvar"))
+    prob = CONFIGS["c2"].with_(sigma=1.0)
+    S = SGSystem(prob, rhs_noisy(prob.n, 11505 + 2000))
+    a0 = coeff_modes(S.g, S.Jq[:1], prob.mu, prob.a_min)[0]
+    H = GMGHierarchy(fem.stiffness(prob.n, a0), prob.n)
+    P, Nh = S.P, S.Nh
+
+    def mean_pc(v):
+        return np.concatenate([H.vcycle(v[i * Nh:(i + 1) * Nh]) for i in range(P)])
+
+    workers = min(8, os.cpu_count() or 1)
     F = S.rhs()
     t0 = time.perf_counter()
-    gmres(S.apply, fs.apply, F, tol=1e-8, restart=50, max_it=n_iters)
+    gmres(lambda v: S.apply_pointwise(v, workers=workers), mean_pc, F, tol=1e-8, restart=50,
+          max_it=1)
     dt = time.perf_counter() - t0
-    per_pair = dt / (n_iters + 1)
-    est = per_pair * (gpu_iters + gpu_restarts)
-    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    # one Arnoldi step and the closing update: two operator applies, two cycles
+    per_pair = dt / 2
+    est = per_pair * (total_iterations + total_restarts)
     return {
-        "value": est, "unit": "s", "cores": int(threads), "kind": "oracle",
-        "sample": (f"oracle FS-GMRES(50) on the same workload, {n_iters} Arnoldi steps + closing "
-                   f"update timed ({dt:.1f} s, {n_iters + 1} operator+preconditioner "
-                   f"applications), scaled to the GPU's {gpu_iters} iterations + "
-                   f"{gpu_restarts} closing updates; set-up excluded; host has "
-                   f"{os.cpu_count()} logical CPUs, sparse kernels single-threaded, BLAS "
-                   f"threads {threads}"),
+        "value": est, "unit": "s", "cores": workers, "kind": "oracle",
+        "sample": (f"oracle mean-based GMRES(50) on the 256x256 P=84 workload at sigma=1.0: one "
+                   f"Arnoldi step and the closing update timed ({dt:.1f} s: two operator applies "
+                   f"from the block coefficients on {workers} threads, two V(2,2) cycles per mode), "
+                   f"scaled to the step's {total_iterations} iterations + {total_restarts} closing "
+                   f"updates of all nine solves (field-split and multigrid iterations priced as "
+                   f"mean-based ones, so a lower bound); set-up excluded; host has "
+                   f"{os.cpu_count()} logical CPUs"),
     }
 
 
-def fs_large(stream, iters=60):
-    """The largest instance of the 64-instance uneven workload (Q1 256x256,
-    M=6, p=4, P=210, q=8, sigma 1.27, which stagnates under the field split):
-    `iters` field-split GMRES(50) iterations with the blocks of the split by
-    first KL variable, timed with HIP events after 10 untimed ones."""
+def c1_context(stream):
+    """The 128x128 field-split workload (squared-exponential L_c = 0.5, sigma = 1,
+    M = 4, p = 3, q = 6, f = 1): field-split, mean-based and multigrid solves."""
     import torch
     import paper_1910_11505_amd as sg
-    from synth import batched_instances, rhs_noisy
-    prob, seed = max(batched_instances(64), key=lambda ps: (ps[0].n, ps[0].p, ps[0].M, ps[0].sigma))
-    inst = sg.SGInstance(prob.n, prob.M, prob.p, prob.q, prob.cov, prob.mu, prob.sigma,
-                         prob.corr_len, prob.a_min, f_nodal=rhs_noisy(prob.n, seed), stream=stream)
-    try:
-        F = inst.rhs()
-        inst.solve(F, pc="fs", grouping="klvar", restart=50, tol=1e-8, max_it=10)
+    from synth import CONFIGS
+    p = CONFIGS["c1"]
+    inst = sg.SGInstance(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma, p.corr_len, p.a_min)
+    F = inst.rhs()
+    u = inst.vec()
+    out = {}
+    for pc in ("fs", "mean", "mg"):
+        if pc == "mg":
+            inst.bind_mg(MG_GROUPING)
+        g = MG_GROUPING if pc == "mg" else "klvar"
+        inst.solve(F, pc=pc, grouping=g, restart=50, tol=1e-8, u=u)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        _, info, _ = inst.solve(F, pc="fs", grouping="klvar", restart=50, tol=1e-8, max_it=iters)
+        reps = 5
+        for _ in range(reps):
+            _, info, _ = inst.solve(F, pc=pc, grouping=g, restart=50, tol=1e-8, u=u)
         e1.record(stream)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        out = {"shape": f"Q1 {prob.n}x{prob.n}, M={prob.M}, p={prob.p} (P={inst.P}), q={prob.q}, "
-                        f"sigma={prob.sigma:.2f}",
-               "iterations": info.iterations, "ms": ms, "ms_per_iteration": ms / max(info.iterations, 1)}
-        _log(f"field split {out['shape']}: {info.iterations} it, {out['ms_per_iteration']:.2f} ms/it")
-        return out
-    finally:
-        inst.close()
-
-
-def sigma_sweep(stream, max_it=2000):
-    """The 256x256 workload (L1-exponential covariance L_c=0.25, M=6, p=3, P=84,
-    q=6, f = 1 + 0.1 N(0,1) nodal noise) at sigma 0.5, 1.0, 1.5: mean-based and
-    field-split GMRES(50) to the FP64 true relative residual 1e-8 (capped at
-    max_it iterations)."""
-    import torch
-    import paper_1910_11505_amd as sg
-    from synth import CONFIGS, rhs_noisy
-    base = CONFIGS["c2"]
-    f = rhs_noisy(base.n, 11505 + 2000)
-    out = []
-    for sigma in (0.5, 1.0, 1.5):
-        p = base.with_(sigma=sigma)
-        inst = sg.SGInstance(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma, p.corr_len, p.a_min,
-                             f_nodal=f)
-        F = inst.rhs()
-        ms_apply = time_applies(inst, 10, stream)
-        nb = apply_bytes(inst, "factored")
-        row = {"sigma": sigma, "apply_ms": ms_apply, "apply_gbs": nb / (ms_apply * 1e-3) / 1e9}
-        for pc in ("mean", "fs"):
-            u = inst.vec()
-            inst.solve(F, pc=pc, grouping="klvar", restart=50, tol=1e-8, u=u, max_it=50)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            _, info, _ = inst.solve(F, pc=pc, grouping="klvar", restart=50, tol=1e-8, u=u,
-                                    max_it=max_it)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            row[pc] = {"s": e0.elapsed_time(e1) / 1e3, "iterations": info.iterations,
-                       "relres": info.relres, "status": info.status}
-            _log(f"256x256 sigma {sigma}: {pc} {info.iterations} it, relres {info.relres:.2e}, "
-                 f"{e0.elapsed_time(e1):.1f} ms")
-        inst.close()
-        torch.cuda.empty_cache()
-        out.append(row)
+        out[pc] = {"s": e0.elapsed_time(e1) / reps / 1e3, "iterations": info.iterations,
+                   "relres": info.relres}
+        _log(f"128x128 P=35: {pc} {info.iterations} it, {out[pc]['s'] * 1e3:.2f} ms")
+    inst.close()
     return out
 
 
-def learned_comparison(npairs, steps):
+def batched_workload():
+    """The 64-instance uneven workload (n in {64,128,256}, M in 2..6, p in 2..4,
+    sigma ~ U[0.3,1.5], L_c ~ U[0.2,1.0], q = 2p, nodal-noise forcing): one
+    batched field-split GMRES(50) solve to 1e-8 (max 1000 iterations per
+    instance), switching to K_ii cycles where the A_0 blocks stagnate."""
+    import torch
+    import paper_1910_11505_amd as sg
+    from paper_1910_11505_amd.binding import make_problem
+    from synth import batched_instances, rhs_noisy
+    inst = batched_instances(64)
+    probs = [make_problem(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma, p.corr_len, p.a_min)
+             for p, _ in inst]
+    fs = [rhs_noisy(p.n, seed) for p, seed in inst]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        B = sg.Batch(probs, f_nodal=fs, restart=50, stream=stream)
+        F = B.rhs()
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        u, infos = B.solve(F, pc="fs_switch", grouping="klvar", tol=1e-8, max_it=1000)
+        torch.cuda.synchronize()
+        solve_s = time.perf_counter() - t0
+        unknowns = int(B.offsets[-1])
+        B.close()
+    del B, F, u
+    torch.cuda.empty_cache()
+    conv = sum(1 for i in infos if i.status == 0)
+    out = {"instances": len(infos), "converged": conv, "solve_s": solve_s, "setup_s": setup_s,
+           "iterations_total": int(sum(i.iterations for i in infos)),
+           "switched_to_kii": int(sum(i.fallbacks for i in infos)),
+           "worst_relres": float(max(i.relres for i in infos)), "unknowns": unknowns}
+    _log(f"batched: {conv}/{len(infos)} converged in {solve_s:.2f} s (set-up {setup_s:.1f} s), "
+         f"{out['switched_to_kii']} switched to K_ii cycles")
+    return out
+
+
+def cnn_rates(net, store, batch, stream):
+    """The network's BF16 convolution rates: forward (inference) and one Adam
+    training step (forward, data and weight gradients) on `batch` stored
+    pairs, HIP events; flops = 2 * 9 * c_in * c_out per output pixel and layer
+    (forward), three times that for a training step."""
+    import numpy as np
+    import torch
+    import paper_1910_11505_amd as sg
+    from synth import cnn_layers
+    layers = cnn_layers(net.P, 64, 64)
+    fl = 0.0
+    for ci, co, _, lvl in layers:
+        S = net.n >> lvl
+        fl += 2.0 * 9 * ci * co * S * S
+    fl *= batch
+    idx = np.arange(min(batch, store.count), dtype=np.int32)
+    out = {}
+    for mode, name, mult in ((0, "forward", 1.0), (1, "forward_backward", 3.0)):
+        for _ in range(3):
+            sg.sg_cnn_run(net.c, store.R, store.T, store.sig, idx, mode, want_loss=False)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record(stream)
+        for _ in range(reps):
+            sg.sg_cnn_run(net.c, store.R, store.T, store.sig, idx, mode, want_loss=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tf = mult * fl / (ms * 1e-3) / 1e12
+        out[name] = {"ms": ms, "tflops": tf, "frac_bf16_peak": tf / BF16_PEAK_TFLOPS,
+                     "flops": mult * fl, "batch": batch}
+    return out
+
+
+def learned_comparison(npairs, steps, draws, stream):
     """The learned workload (Q1 128x128, M=4, p=3, squared-exponential L_c=0.5,
     sigma ~ U[0.3, 1.5], nodal-noise forcing) with a reduced training budget:
-    pairs from field-split GMRES(5) cycles, Adam training on the GPU, then
-    flexible GMRES(30) with the learned stage against field-split GMRES(50) on
-    two held-out problems, both to the FP64 true relative residual 1e-8."""
+    pairs from field-split GMRES(5) cycles (K_ii blocks), Adam training on the
+    GPU, then flexible GMRES(30) with the learned stage (K_ii field split
+    inside) against field-split GMRES(50) with K_ii blocks on held-out draws,
+    both to the FP64 true relative residual 1e-8."""
     import numpy as np
     import paper_1910_11505_amd as sg
     from paper_1910_11505_amd import learned as L
@@ -286,24 +343,45 @@ def learned_comparison(npairs, steps):
     store = L.PairStore(npairs, P, Nh)
     t0 = time.perf_counter()
     gen = L.generate_pairs(net, learned_problems(base, 400, 11505 + 4000), store, cycle=5,
-                           max_per_problem=16)
+                           max_per_problem=16, pc="fs_kii")
     _log(f"learned: {gen['pairs']} pairs from {gen['problems']} problems in {gen['seconds']:.1f} s")
     losses, train_s = L.train(net, store, steps, 16, 1e-3, lr_final=1e-4)
     _log(f"learned: {steps} Adam steps in {train_s:.1f} s, loss {losses[-1][1]:.3g}")
+    rates = cnn_rates(net, store, 16, stream)
+    _log(f"cnn: forward {rates['forward']['tflops']:.1f} TFLOP/s, "
+         f"forward+backward {rates['forward_backward']['tflops']:.1f} TFLOP/s")
     rows = []
-    for prob, f in learned_problems(base, 2, 11505 + 4999):
-        c = L.compare(net, prob, f, max_it=1000)
+    for prob, f in learned_problems(base, draws, 11505 + 4999):
+        c = L.compare(net, prob, f, max_it=3000, fs_pc="fs_kii", learned_pc="learned_kii")
         rows.append({"sigma": c.sigma, "fs_iterations": c.fs_iterations, "fs_s": c.fs_seconds,
                      "learned_iterations": c.learned_iterations, "learned_s": c.learned_seconds,
-                     "fallbacks": c.fallbacks, "fs_relres": c.fs_relres, "max_it": 1000,
+                     "fallbacks": c.fallbacks, "fs_relres": c.fs_relres,
                      "learned_relres": c.learned_relres})
         _log(f"learned: sigma {c.sigma:.2f} FS-GMRES(50) {c.fs_iterations} it {c.fs_seconds * 1e3:.1f} ms, "
              f"learned FGMRES(30) {c.learned_iterations} it {c.learned_seconds * 1e3:.1f} ms")
     net.close()
     return {"pairs": gen["pairs"], "train_steps": steps, "train_s": train_s,
             "final_loss": losses[-1][1], "pair_generation_s": gen["seconds"],
-            "time_ratio_fs_over_learned": float(np.mean([r["fs_s"] / r["learned_s"] for r in rows])),
-            "problems": rows, "total_s": time.perf_counter() - t0}
+            "field_split": "K_ii blocks (SG_PC_DIAG_KII) in both solvers",
+            "time_ratio_fs_over_learned": float(np.median([r["fs_s"] / r["learned_s"] for r in rows])),
+            "iteration_ratio_fs_over_learned": float(np.median(
+                [r["fs_iterations"] / max(r["learned_iterations"], 1) for r in rows])),
+            "problems": rows, "cnn": rates, "total_s": time.perf_counter() - t0}
+
+
+def profile_apply(stream):
+    import torch
+    p, inst = make_c2(1.0)
+    ms = time_applies(inst, 30, stream)
+    src = torch.ones(32 << 20, dtype=torch.float64, device=inst.device)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile": "apply", "apply_ms": ms,
+                      "apply_algorithmic_bytes": apply_bytes(p, inst.P, inst.Nh),
+                      "copy_bytes_each_way": src.numel() * 8, "copies": 5,
+                      "src_sha256": _src_hash()}), flush=True)
 
 
 def main():
@@ -315,154 +393,144 @@ def main():
     import numpy as np
     import torch
 
-    import paper_1910_11505_amd as sg
-    from synth import CONFIGS
-
-    prob = CONFIGS["c1"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-
-    t0 = time.perf_counter()
-    inst = sg.SGInstance(prob.n, prob.M, prob.p, prob.q, prob.cov, prob.mu, prob.sigma,
-                         prob.corr_len, prob.a_min)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    _log(f"set-up {setup_s:.2f} s (P={inst.P}, n_a={inst.na})")
-    F = inst.rhs()
-    u = inst.vec()
-
     if args.profile_apply:
-        inst.set_apply(args.apply_form)
-        ms = time_applies(inst, args.apply_reps, stream)
-        nb = apply_bytes(inst, args.apply_form)
-        src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"profile": "apply", "apply_ms": ms, "apply_algorithmic_bytes": nb,
-                          "copy_bytes_each_way": src.numel() * 8, "copies": 5}), flush=True)
+        profile_apply(stream)
         return
 
-    def solve(pc):
-        return inst.solve(F, pc=pc, grouping="klvar", restart=50, tol=1e-8, u=u)
+    # ---- set-up: three handles of the sweep, each with its multigrid -------
+    t0 = time.perf_counter()
+    insts = []
+    for sigma in SIGMAS:
+        prob, inst = make_c2(sigma)
+        insts.append((sigma, inst))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _, inst in insts:
+        inst.bind_mg(MG_GROUPING)
+    torch.cuda.synchronize()
+    mg_setup_s = time.perf_counter() - t0
+    P, Nh = insts[0][1].P, insts[0][1].Nh
+    _log(f"set-up {setup_s:.2f} s, multigrid set-up {mg_setup_s:.2f} s (P={P}, N_h={Nh})")
+    Fs = [inst.rhs() for _, inst in insts]
+    us = [{pc: inst.vec() for pc in PCS} for _, inst in insts]
 
     for _ in range(args.warmup):
-        solve("fs")
+        run_step(insts, Fs, us, stream)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    infos = []
     for _ in range(args.steps):
-        _, info, _ = solve("fs")
-        infos.append((info.iterations, info.restarts, info.relres, info.status))
+        run_step(insts, Fs, us, stream)
     e1.record(stream)
     torch.cuda.synchronize()
-    ms_fs = e0.elapsed_time(e1) / args.steps
-    it_fs, rs_fs, relres_fs, st_fs = infos[-1]
-    _log(f"field-split solve {ms_fs:.2f} ms, {it_fs} iterations, relres {relres_fs:.3e}")
+    ms_step = e0.elapsed_time(e1) / args.steps
+    _log(f"step (nine solves) {ms_step:.1f} ms")
+    if args.profile_step:
+        return
 
-    # mean-based preconditioner on the same system (context)
-    solve("mean")
+    # one more step with per-solve events (not part of the timed region)
+    rec = []
+    run_step(insts, Fs, us, stream, record=rec)
     torch.cuda.synchronize()
-    e0.record(stream)
-    _, info_m, _ = solve("mean")
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_mean = e0.elapsed_time(e1)
+    sweep = {}
+    tot_it = tot_rs = 0
+    for sigma, pc, info, a, b in rec:
+        row = sweep.setdefault(str(sigma), {})
+        row[pc] = {"s": a.elapsed_time(b) / 1e3, "iterations": info.iterations,
+                   "restarts": info.restarts, "relres": info.relres, "status": info.status}
+        tot_it += info.iterations
+        tot_rs += info.restarts
+        _log(f"sigma {sigma}: {pc} {info.iterations} it, relres {info.relres:.2e}, "
+             f"{a.elapsed_time(b):.1f} ms")
+    statuses = [r["status"] for v in sweep.values() for r in v.values()]
 
-    # SG apply in both forms: average launch time over a loop of applies on this stream
-    forms = measure_apply_forms(inst, args.apply_reps, stream)
-    for f, v in forms.items():
-        _log(f"apply ({f}) {v['ms'] * 1e3:.1f} us, {v['gbs']:.0f} GB/s")
-    apply_ms, apply_gbs = forms["factored"]["ms"], forms["factored"]["gbs"]
-
-    c2_apply = None
-    if not args.no_c2_apply:
-        # the 256x256 shape: 924 coefficient modes (1.94 GB) cannot stay in the
-        # 256 MB last-level cache, so the triple-product form is HBM-bound
+    # ---- the SG apply on the same workload: achieved rates ------------------
+    applies = {}
+    nb = apply_bytes(prob, P, Nh)
+    fl = apply_flops(prob, P)
+    for sigma, inst in insts:
+        ms = time_applies(inst, args.apply_reps, stream)
+        applies[str(sigma)] = {"ms": ms, "gbs": nb / (ms * 1e-3) / 1e9,
+                               "tflops": fl / (ms * 1e-3) / 1e12}
+    ms_apply = float(np.mean([a["ms"] for a in applies.values()]))
+    tflops = fl / (ms_apply * 1e-3) / 1e12
+    _log(f"apply {ms_apply * 1e3:.1f} us: {tflops:.1f} TFLOP/s, {nb / (ms_apply * 1e-3) / 1e9:.0f} GB/s")
+    for _, inst in insts:
         inst.close()
-        torch.cuda.empty_cache()
-        p2 = CONFIGS["c2"]
-        t0 = time.perf_counter()
-        inst2 = sg.SGInstance(p2.n, p2.M, p2.p, p2.q, p2.cov, p2.mu, p2.sigma, p2.corr_len,
-                              p2.a_min)
-        torch.cuda.synchronize()
-        setup2 = time.perf_counter() - t0
-        c2_apply = {"shape": "Q1 256x256, M=6, p=3 (P=84), q=6 (924 modes)", "setup_s": setup2}
-        c2_apply.update(measure_apply_forms(inst2, 10, stream))
-        inst2.close()
-        for f in ("factored", "triple"):
-            _log(f"256x256 apply ({f}) {c2_apply[f]['ms']:.3f} ms, {c2_apply[f]['gbs']:.0f} GB/s")
+    del insts, Fs, us
+    torch.cuda.empty_cache()
 
-    sweep = None if args.no_sigma_sweep else sigma_sweep(stream)
-    large = fs_large(stream) if args.fs_large else None
+    c1 = None if args.no_c1 else c1_context(stream)
+    torch.cuda.empty_cache()
+    batched = None if args.no_batched else batched_workload()
     learned = None
     if not args.no_learned:
         torch.cuda.empty_cache()
-        learned = learned_comparison(args.learned_pairs, args.learned_steps)
+        learned = learned_comparison(args.learned_pairs, args.learned_steps, args.learned_draws,
+                                     stream)
 
     line = {
         "metric": METRIC,
-        "value": ms_fs / 1e3,
+        "value": ms_step / 1e3,
         "unit": "s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_fs,
+        "ms_per_step": ms_step,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": ("field-split SG-GMRES(50) to relres 1e-8: Q1 128x128 elements, "
-                         "squared-exponential covariance L_c=0.5, sigma=1.0, mu=0, a_min=0.01, "
-                         "M=4, p=3 (P=35), q=6 (210 coefficient modes), f=1, one split per KL "
-                         "variable, V(2,2) on the mean stiffness"),
-            "n": prob.n, "M": prob.M, "p": prob.p, "q": prob.q, "P": inst.P,
-            "n_a": inst.na, "unknowns": inst.nvec,
+            "workload": ("256x256 sigma sweep, nine SG-GMRES(50) solves to the FP64 true "
+                         "relative residual 1e-8 per step: sigma in {0.5, 1.0, 1.5} x {mean-based, "
+                         "field split (one split per KL variable, V(2,2) on A_0), multigrid on the "
+                         "full SG system (V(1,1), leading-digit field-split smoother)}; Q1 256x256 "
+                         "elements, L1-exponential covariance L_c=0.25, mu=0, a_min=0.01, M=6, "
+                         "p=3 (P=84), q=6 (924 coefficient modes), f = 1 + 0.1 N(0,1) at the nodes"),
+            "n": prob.n, "M": prob.M, "p": prob.p, "q": prob.q, "P": P, "unknowns": P * Nh,
+            "sigmas": list(SIGMAS), "preconditioners": list(PCS),
         },
-        "iterations": it_fs,
-        "restarts": rs_fs,
-        "relres": relres_fs,
-        "status": st_fs,
+        "all_converged": all(s == 0 for s in statuses),
         "setup_s": setup_s,
-        "mean_based": {"s": ms_mean / 1e3, "iterations": info_m.iterations,
-                       "relres": info_m.relres},
-        "apply": dict(forms, note="default form: factored (exact for q >= 2p); the triple-"
-                                   "product form streams the 110 MB of coefficient modes, which "
-                                   "fit the 256 MB last-level cache at this size"),
-        "apply_c2_hbm": c2_apply,
+        "mg_setup_s": mg_setup_s,
+        "sweep": sweep,
+        "apply_256x256_p84": {"per_sigma": applies, "algorithmic_bytes": nb, "fp64_flops": fl},
+        "solves_128x128_p35": c1,
+        "batched_64": batched,
         "learned_vs_field_split": learned,
-        "sigma_sweep_256x256_p84": sweep,
-        "fs_large_256x256_p210": large,
         # The factored apply does 2 nnz(T) multiply-adds per Gauss point and
-        # gradient component on 8 (M + 2P N_h / N_q) bytes per point: 15.2 flop/B
-        # here, above the 9.8 flop/B ridge of the FP64 vector peak over HBM, so
-        # its ceiling is the FP64 vector peak (256 CUs x 4 SIMDs x 16 lanes x
-        # 2 flop x 2.4 GHz); the HBM figures are kept beside it.
+        # gradient component in each contraction step on 8 (M + 2P N_h/N_q)
+        # bytes per point: 17.5 flop/B here, above the 9.8 flop/B ridge of the
+        # FP64 vector peak over HBM, so its ceiling is the FP64 vector peak
+        # (256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz); HBM figures beside.
         "roofline": {
-            "kernel": "rapply_kernel<4,3> (register-resident factored SG apply) + apply_fixup_kernel",
+            "kernel": ("one sg_apply on the 256x256 P=84 workload: rapply_stream_kernel<6,3,true,0> "
+                       "(register-resident factored SG apply) + apply_fixup_kernel"),
             "bound": "alu",
-            "achieved": forms["factored"]["tflops"],
+            "achieved": tflops,
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": forms["factored"]["tflops"] / FP64_PEAK_TFLOPS,
+            "frac": tflops / FP64_PEAK_TFLOPS,
             "traffic": apply_traffic(),
-            "flops_per_launch": forms["factored"]["fp64_flops"],
-            "algorithmic_bytes_per_launch": forms["factored"]["algorithmic_bytes"],
-            "flop_per_byte": forms["factored"]["fp64_flops"] / forms["factored"]["algorithmic_bytes"],
+            "flops_per_launch": fl,
+            "algorithmic_bytes_per_launch": nb,
+            "flop_per_byte": fl / nb,
             "ridge_flop_per_byte": FP64_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS,
-            "hbm_gbs": apply_gbs,
-            "hbm_frac": apply_gbs / HBM_PEAK_GBS,
+            "hbm_gbs": nb / (ms_apply * 1e-3) / 1e9,
+            "hbm_frac": nb / (ms_apply * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "ms_per_launch": ms_apply,
         },
     }
     if not args.no_cpu_baseline:
         _log("timing the oracle sample")
-        line["cpu_baseline"] = cpu_baseline(prob, it_fs, rs_fs, args.cpu_iters)
+        line["cpu_baseline"] = cpu_baseline(tot_it, tot_rs)
     print(json.dumps(line), flush=True)
 
 

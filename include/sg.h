@@ -67,6 +67,13 @@ enum { SG_PC_NONE = 0, SG_PC_MEAN = 1, SG_PC_FS = 2, SG_PC_LEARNED = 3, SG_PC_MG
  * that mode's own diagonal block K_ii = sum_k [G_k]_{ii} A_k (the paper's
  * diagonal blocks of eq. P_preconditioner) instead of the mean stiffness A_0 */
 enum { SG_PC_DIAG_KII = 0x100 };
+/* flag OR-ed into SG_PC_MEAN or SG_PC_FS for sg_gmres_solve and
+ * sg_batch_solve: start with the A_0 cycles and switch to the K_ii cycles of
+ * SG_PC_DIAG_KII, at a restart, once a whole cycle has left the true residual
+ * above a fifth of its value at the cycle's start (the A_0 diagonal blocks
+ * are not a contraction at large sigma); sg_solve_info.fallbacks then
+ * counts 1.                                                                */
+enum { SG_PC_SWITCH_KII = 0x200 };
 
 /* splits of the modes for SG_PC_FS:
  *  KLVAR         split n = modes whose first nonzero index is n; mean in split 1
@@ -335,7 +342,8 @@ int    sg_batch_rhs(sg_batch* b, double* F, void* stream);
 /* the bound handle of instance i (for single-instance calls; owned by b)   */
 int    sg_batch_handle(sg_batch* b, int32_t i, sg_handle** h);
 /* solves every instance from zero with opts (pc SG_PC_MEAN or SG_PC_FS, any
- * grouping, restart equal to the bound value); F, u packed device vectors;
+ * grouping, restart equal to the bound value; SG_PC_SWITCH_KII applies to
+ * the one-at-a-time solves below, the lockstep part keeps the A_0 cycles); F, u packed device vectors;
  * infos: count entries.  Graph capture needs a non-null stream (the null
  * stream runs the same launch sequences eagerly).  On a non-null stream,
  * instances of at least 2^20 unknowns (P*N_h) are solved one at a time by

@@ -1033,14 +1033,21 @@ void learned_stage(sg_handle& H, hipStream_t s, int fs_pc, int grouping, const d
   launch_stage_alpha(s, dots, c, kc, z, w, Nv);
 }
 
-bool valid_pc(int pc, bool allow_learned = false) {
+// allow_solve: the flags of a whole solve (the learned stage, the switch to
+// K_ii cycles) are allowed too
+bool valid_pc(int pc, bool allow_learned = false, bool allow_solve = false) {
   const int kind = pc & 0xff, flags = pc & ~0xff;
   if (kind < SG_PC_NONE || kind > SG_PC_MG) return false;
   if (kind == SG_PC_LEARNED && !allow_learned) return false;
-  if (flags & ~SG_PC_DIAG_KII) return false;
+  if (flags & ~(SG_PC_DIAG_KII | SG_PC_SWITCH_KII)) return false;
+  if ((flags & SG_PC_SWITCH_KII) &&
+      (!allow_solve || (kind != SG_PC_MEAN && kind != SG_PC_FS) || (flags & SG_PC_DIAG_KII)))
+    return false;
   if (kind == SG_PC_MG && flags) return false;
   return true;
 }
+
+constexpr double kSwitchRatio = 0.2;  // SG_PC_SWITCH_KII: least reduction of a cycle
 
 }  // namespace
 
@@ -1582,7 +1589,7 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
   if (o->restart < 1 || o->restart > kMaxRestart) return fail(SG_ERR_INVALID_ARG, "restart out of range");
   if (o->max_it < 1) return fail(SG_ERR_INVALID_ARG, "max_it must be positive");
   if (!(o->tol > 0.0)) return fail(SG_ERR_INVALID_ARG, "tol must be positive");
-  if (!valid_pc(o->pc, true)) return fail(SG_ERR_INVALID_ARG, "unknown preconditioner");
+  if (!valid_pc(o->pc, true, true)) return fail(SG_ERR_INVALID_ARG, "unknown preconditioner");
   if (is_learned(o) && !h->cnn) return fail(SG_ERR_INVALID_ARG, "learned stage needs an attached network");
   if (o->grouping < 0 || o->grouping > 3) return fail(SG_ERR_INVALID_ARG, "unknown grouping");
   if (ws_bytes < sg_gmres_workspace_bytes(h, o)) return fail(SG_ERR_WORKSPACE, "Krylov workspace too small");
@@ -1596,6 +1603,9 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
     const bool learned = is_learned(o);
     krylov_layout(h, m, learned, &K, static_cast<char*>(krylov_ws));
     const int fs_pc = (o->pc & ~0xff) | SG_PC_FS;
+    // the preconditioner in use (SG_PC_SWITCH_KII may add SG_PC_DIAG_KII at a restart)
+    int pc = o->pc & ~SG_PC_SWITCH_KII;
+    int switches = 0;
     int fallbacks = 0;
     double* hp = H.host_pinned;
     auto norm2 = [&](const double* x, double* dst) {
@@ -1670,7 +1680,7 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
           learned_stage(H, s, fs_pc, o->grouping, vj, zj, K.w, K.x2, K.z, K.t, K.partial, K.nblk,
                         K.hdev + 2 * (m + 1) + 1);
         } else {
-          do_precond(H, s, o->pc, o->grouping, vj, K.z);
+          do_precond(H, s, pc, o->grouping, vj, K.z);
           do_apply(H, s, zj, K.w, !defer);
         }
         const EdgeFix ef = defer ? pending_edges(H, 1.0) : EdgeFix{};
@@ -1689,7 +1699,7 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
                               hipMemcpyDeviceToHost, s));
         SG_HIP(hipEventRecord(H.fetched, s));
         if (!learned && j + 1 < m && it + 1 < o->max_it) {
-          do_precond(H, s, o->pc, o->grouping, K.V + (int64_t)(j + 1) * Nv, K.z);
+          do_precond(H, s, pc, o->grouping, K.V + (int64_t)(j + 1) * Nv, K.z);
           do_apply(H, s, K.z, K.w, !(j + 2 <= 64));
           queued = true;
         }
@@ -1742,20 +1752,26 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
         launch_axpby(s, 1.0, K.t, 1.0, u, Nv);
       } else {
         launch_combine(s, K.V, Nv, kdone, K.ydev, K.t, Nv);
-        do_precond(H, s, o->pc, o->grouping, K.t, K.z);
+        do_precond(H, s, pc, o->grouping, K.t, K.z);
         launch_axpby(s, 1.0, K.z, 1.0, u, Nv);
       }
       do_apply(H, s, u, K.w);
       launch_sub(s, F, K.w, K.t, Nv);
       norm2(K.t, K.hdev);
       fetch(K.hdev, 1);
+      const double beta_prev = beta;
       beta = std::sqrt(hp[0]);
       ++restarts;
       if (!std::isfinite(beta)) broke = true;
+      if ((o->pc & SG_PC_SWITCH_KII) && !(pc & SG_PC_DIAG_KII) && beta > target &&
+          beta > kSwitchRatio * beta_prev) {
+        pc |= SG_PC_DIAG_KII;
+        ++switches;
+      }
     }
     info->iterations = it;
     info->restarts = restarts;
-    info->fallbacks = fallbacks;
+    info->fallbacks = fallbacks + switches;
     info->relres = beta / nF;
     info->relres_est = est / nF;
     info->status = (beta <= target) ? SG_CONVERGED : (broke ? SG_BREAKDOWN : SG_NOT_CONVERGED);
@@ -2505,7 +2521,7 @@ int sg_batch_solve(sg_batch* b, const sg_solve_opts* o, const double* F, double*
   if (!b->bound) return fail(SG_ERR_NOT_BOUND, "batch not bound");
   if (o->restart != b->restart) return fail(SG_ERR_INVALID_ARG, "restart must match the bound value");
   const int kind = o->pc & 0xff;
-  if ((kind != SG_PC_MEAN && kind != SG_PC_FS) || (o->pc & ~0xff))
+  if ((kind != SG_PC_MEAN && kind != SG_PC_FS) || (o->pc & ~(0xff | SG_PC_SWITCH_KII)))
     return fail(SG_ERR_UNSUPPORTED, "batched solves take the mean-based or field-split preconditioner");
   if (o->grouping < 0 || o->grouping > 3) return fail(SG_ERR_INVALID_ARG, "unknown grouping");
   if (o->use_x0) return fail(SG_ERR_UNSUPPORTED, "batched solves start from zero");

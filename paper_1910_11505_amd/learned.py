@@ -122,15 +122,17 @@ class Comparison:
 
 
 def compare(net: "sg.CNN", prob, f_nodal=None, tol=1e-8, fs_restart=50,
-            learned_restart=30, grouping="klvar", repeats: int = 1, max_it: int = 5000):
+            learned_restart=30, grouping="klvar", repeats: int = 1, max_it: int = 5000,
+            fs_pc="fs", learned_pc="learned"):
     """Plain field-split GMRES(fs_restart) against flexible GMRES(learned_restart)
-    with the learned stage, both to the true relative residual tol."""
+    with the learned stage, both to the true relative residual tol (fs_pc and
+    learned_pc choose A_0 or K_ii diagonal blocks)."""
     import torch
     inst = make_instance(prob, f_nodal)
     F = inst.rhs()
     inst.attach(net, prob.sigma)
     out = {}
-    for name, pc, restart in (("fs", "fs", fs_restart), ("learned", "learned", learned_restart)):
+    for name, pc, restart in (("fs", fs_pc, fs_restart), ("learned", learned_pc, learned_restart)):
         inst.solve(F, pc=pc, grouping=grouping, tol=tol, restart=restart, max_it=max_it)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
