@@ -74,6 +74,13 @@ enum { SG_PC_DIAG_KII = 0x100 };
  * are not a contraction at large sigma); sg_solve_info.fallbacks then
  * counts 1.                                                                */
 enum { SG_PC_SWITCH_KII = 0x200 };
+/* inner iterations of the diagonal-block solves (the paper's G-F-I: eq.
+ * level_solver applied to each diagonal block): pc | (k << SG_PC_INNER_SHIFT)
+ * with 2 <= k <= 255 makes every block solve of SG_PC_MEAN, SG_PC_FS (and
+ * the field split inside SG_PC_LEARNED) run k Richardson steps
+ * x <- x + V(t - B x) from x = 0, V the V(2,2) cycle on the block's operator
+ * B (A_0, or K_ii with SG_PC_DIAG_KII); 0 or 1 = one cycle.               */
+enum { SG_PC_INNER_SHIFT = 16 };
 
 /* splits of the modes for SG_PC_FS:
  *  KLVAR         split n = modes whose first nonzero index is n; mean in split 1

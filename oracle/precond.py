@@ -19,10 +19,16 @@ Split choices (grouping):
                  a group opens a new split iff (g, ..., g) is in J(p),
                  otherwise it joins the preceding split.
 
+Inner iterations (the paper's G-F-I, eq. level_solver applied to each
+diagonal block with i_max > 1): richardson_block_solve gives the block solve
+x_0 = 0, x_{k+1} = x_k + V_i(t - B_i x_k), k < i_max, with B_i the block's
+operator (A_0, or the true diagonal block K_ii) and V_i one V-cycle on it.
+
 Pins (tests/test_oracle_precond.py): the fg splits of the paper's example
 (sizes 5, 4, 6); with exact block solves FS inverts a block-lower-triangular K
 exactly; FS with one split equals mean-based; mean-based with A_0^{-1} equals
-I (x) A_0^{-1}.
+I (x) A_0^{-1}; the Richardson block solve is one V-cycle for i_max = 1 and
+converges to the block's direct solve as i_max grows.
 """
 from __future__ import annotations
 
@@ -96,3 +102,14 @@ class FieldSplit:
                 Z[i] = self.solve(T[t], i)
             done[grp] = True
         return Z.reshape(-1)
+
+
+def richardson_block_solve(blocks, vcycles, i_max: int):
+    """block_solve(t, i) running i_max Richardson steps on block i:
+    x <- x + vcycles[i](t - blocks[i] @ x) from x = 0."""
+    def solve(t, i):
+        x = vcycles[i](t)
+        for _ in range(i_max - 1):
+            x = x + vcycles[i](t - blocks[i] @ x)
+        return x
+    return solve

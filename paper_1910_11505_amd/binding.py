@@ -18,6 +18,16 @@ PC = {"none": 0, "mean": 1, "fs": 2, "learned": 3, "mg": 4, "mean_kii": 0x101, "
 GROUPING = {"klvar": 0, "klvar_meansep": 1, "permode": 2, "fg": 3}
 EXPORT = {"coeff": 0, "kl": 1, "gq": 2, "stencil": 3, "groups": 4}
 STATUS = {0: "converged", 1: "not_converged", 2: "breakdown"}
+PC_INNER_SHIFT = 16
+
+
+def pc_code(pc) -> int:
+    """A preconditioner code from a name of PC, optionally ":k" for k inner
+    iterations of the diagonal-block solves (e.g. "fs_kii:3"), or an int."""
+    if isinstance(pc, str):
+        name, _, k = pc.partition(":")
+        return PC[name] | ((int(k) if k else 0) << PC_INNER_SHIFT)
+    return int(pc)
 
 
 class SGError(RuntimeError):
@@ -196,7 +206,7 @@ def sg_set_apply(h, kind="auto", points_per_batch=0, stream=None):
 
 
 def sg_precond_apply(h, pc, grouping, r, z, stream=None):
-    pc = PC[pc] if isinstance(pc, str) else int(pc)
+    pc = pc_code(pc)
     grouping = GROUPING[grouping] if isinstance(grouping, str) else int(grouping)
     _check(load_library().sg_precond_apply(h, pc, grouping, _ptr(r), _ptr(z), _stream(stream)))
 
@@ -374,7 +384,7 @@ class SGInstance:
         import torch
         F = self.rhs() if F is None else F
         u = self.vec() if u is None else u
-        opts = SolveOpts(restart, max_it, PC[pc], GROUPING[grouping], 1 if use_x0 else 0, tol)
+        opts = SolveOpts(restart, max_it, pc_code(pc), GROUPING[grouping], 1 if use_x0 else 0, tol)
         nb = sg_gmres_workspace_bytes(self.h, opts)
         if self._kws is None or self._kws.numel() < nb + 256:
             self._kws = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
@@ -530,7 +540,7 @@ class Batch:
 
     def solve(self, F, u=None, pc="fs", grouping="klvar", tol=1e-8, max_it=5000):
         u = self.vec() if u is None else u
-        opts = SolveOpts(self.restart, max_it, PC[pc], GROUPING[grouping], 0, tol)
+        opts = SolveOpts(self.restart, max_it, pc_code(pc), GROUPING[grouping], 0, tol)
         infos = (SolveInfo * self.count)()
         _check(load_library().sg_batch_solve(self.b, ctypes.byref(opts), F.data_ptr(), u.data_ptr(),
                                              infos, _stream(self.stream)))

@@ -73,6 +73,7 @@ struct DevPtrs {
   double* edge = nullptr;
   std::vector<double*> mg_b, mg_x, mg_xa, mg_r;
   double *fsT = nullptr, *fsX = nullptr;
+  double *fsR = nullptr, *fsD = nullptr;  // inner iterations of the diagonal blocks
   int* all_sid = nullptr;        // mode + 1 for every mode
   int* diag_k = nullptr;         // (k, v) lists of the diagonal blocks
   double* diag_v = nullptr;
@@ -590,6 +591,8 @@ void carve(const sg_handle& H, DevPtrs& D, Carver& c) {
   }
   D.fsT = c.take<double>((size_t)H.P * H.Nh);
   D.fsX = c.take<double>((size_t)H.P * H.Nh);
+  D.fsR = c.take<double>((size_t)H.P * H.Nh);
+  D.fsD = c.take<double>((size_t)H.P * H.Nh);
   D.all_sid = c.take<int>(H.P);
   D.diag_k = c.take<int>(std::max<size_t>(H.diag_k.size(), 1));
   D.diag_v = c.take<double>(std::max<size_t>(H.diag_v.size(), 1));
@@ -952,10 +955,52 @@ bool dense_inverse(std::vector<double>& A, int n) {
   return true;
 }
 
+// x = B_t^{-1}-approximation of the compact block right-hand side b for the m
+// modes of a split: `inner` Richardson steps x <- x + V(b - B x) from x = 0
+// (eq. level_solver on each diagonal block), B the A_0 or K_ii stencil.
+void block_solve(sg_handle& H, hipStream_t s, int m, const int* smode, int inner, const double* b,
+                 double* x) {
+  vcycle(H, s, m, smode, b, x);
+  for (int k = 1; k < inner; ++k) {
+    launch_stencil_residual(s, H.n, H.d.L[0].S, smode, m, b, x, H.d.fsR);
+    vcycle(H, s, m, smode, H.d.fsR, H.d.fsD);
+    launch_axpby(s, 1.0, H.d.fsD, 1.0, x, (int64_t)m * H.Nh);
+  }
+}
+
 void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double* r, double* z) {
   const int64_t Nv = (int64_t)H.P * H.Nh;
   const bool kii = (pc & SG_PC_DIAG_KII) != 0;
+  const int inner = std::max(1, (pc >> SG_PC_INNER_SHIFT) & 0xff);
   const int kind = pc & 0xff;
+  if (inner > 1 && (kind == SG_PC_MEAN || kind == SG_PC_FS)) {
+    // the blocks' inner iterations run on compact copies of each split
+    const int g = kind == SG_PC_MEAN ? -1 : grouping;
+    if (g > 3) throw Error(SG_ERR_INVALID_ARG, "unknown grouping");
+    if (g < 0) {
+      block_solve(H, s, H.P, kii ? H.d.all_sid : nullptr, inner, r, z);
+      return;
+    }
+    const FSHost& fh = H.fs[g];
+    const FSDev& fd = H.d.fs[g];
+    for (size_t sp = 0; sp < fh.splits.size(); ++sp) {
+      const int m = (int)fh.splits[sp].size();
+      if (sp == 0)
+        launch_gather_modes(s, m, fd.split_idx[0], H.Nh, r, H.d.fsT);
+      else if (H.use_factored && H.use_rapply)
+        launch_rapply(s, H.M, H.prob.p, H.n, H.prob.mu, H.prob.a_min, H.d.g, H.rpart[g][sp], z,
+                      H.Nh, r, 1.0, -1.0, H.d.fsT, H.d.edge, true, H.rkv[g][sp]);
+      else if (H.use_factored)
+        launch_fapply(s, H.n, H.prob.mu, H.prob.a_min, H.d.g, fd.fpartial[sp], z, H.Nh, r, 1.0,
+                      -1.0, H.d.fsT, H.d.edge, true);
+      else
+        launch_apply(s, H.n, H.na, H.d.a, fd.partial[sp], z, H.Nh, r, 1.0, -1.0, H.d.fsT,
+                     H.d.edge, true);
+      block_solve(H, s, m, kii ? fd.split_sid[sp] : nullptr, inner, H.d.fsT, H.d.fsX);
+      launch_scatter_modes(s, m, fd.split_idx[sp], H.Nh, H.d.fsX, z);
+    }
+    return;
+  }
   if (kind == SG_PC_NONE) {
     SG_HIP(hipMemcpyAsync(z, r, Nv * sizeof(double), hipMemcpyDeviceToDevice, s));
     return;
@@ -1036,9 +1081,12 @@ void learned_stage(sg_handle& H, hipStream_t s, int fs_pc, int grouping, const d
 // allow_solve: the flags of a whole solve (the learned stage, the switch to
 // K_ii cycles) are allowed too
 bool valid_pc(int pc, bool allow_learned = false, bool allow_solve = false) {
-  const int kind = pc & 0xff, flags = pc & ~0xff;
+  const int kind = pc & 0xff, inner = (pc >> SG_PC_INNER_SHIFT) & 0xff;
+  const int flags = pc & ~0xff & ~(0xff << SG_PC_INNER_SHIFT);
   if (kind < SG_PC_NONE || kind > SG_PC_MG) return false;
   if (kind == SG_PC_LEARNED && !allow_learned) return false;
+  if (pc < 0 || (inner > 1 && kind != SG_PC_MEAN && kind != SG_PC_FS && kind != SG_PC_LEARNED))
+    return false;
   if (flags & ~(SG_PC_DIAG_KII | SG_PC_SWITCH_KII)) return false;
   if ((flags & SG_PC_SWITCH_KII) &&
       (!allow_solve || (kind != SG_PC_MEAN && kind != SG_PC_FS) || (flags & SG_PC_DIAG_KII)))

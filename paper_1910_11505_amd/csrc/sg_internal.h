@@ -290,6 +290,8 @@ void launch_scale_by_inv_norm(hipStream_t s, const double* w, const double* nrm2
                               int64_t N);
 void launch_axpby(hipStream_t s, double a, const double* x, double b, double* y, int64_t N);
 void launch_sub(hipStream_t s, const double* a, const double* b, double* out, int64_t N);
+void launch_stencil_residual(hipStream_t s, int n, const double* S, const int* smode, int m,
+                             const double* b, const double* x, double* out);
 void launch_stage_alpha(hipStream_t s, double* dots, const double* c, const double* kc, double* z,
                         double* w, int64_t N);
 // multigrid on the full SG system (sg_mg.hip)

@@ -1372,6 +1372,40 @@ void launch_sub(hipStream_t s, const double* a, const double* b, double* out, in
   hipLaunchKernelGGL(sub_kernel, dim3(cdiv(N, 256)), dim3(256), 0, s, a, b, out, N);
 }
 
+// out_t = b_t - B_t x_t for m modes stored compactly (entry t*N + node), B_t
+// the 9-point stencil of id smode[t] (0: the mean stiffness A_0; i+1: the
+// diagonal block K_ii) on the finest level, planes s = 3(dy+1) + (dx+1)
+__global__ void stencil_residual_kernel(int n, const double* __restrict__ S,
+                                        const int* __restrict__ smode,
+                                        const double* __restrict__ b,
+                                        const double* __restrict__ x, double* __restrict__ out,
+                                        int64_t N) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  if (node >= N) return;
+  const int m = n - 1;
+  const int ix = (int)(node % m), iy = (int)(node / m);
+  const double* St = S + (int64_t)(smode ? smode[t] : 0) * 9 * N;
+  const double* xt = x + (int64_t)t * N;
+  double acc = 0.0;
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int jx = ix + dx, jy = iy + dy;
+      if (jx < 0 || jx >= m || jy < 0 || jy >= m) continue;
+      acc = fma(St[(int64_t)(3 * (dy + 1) + (dx + 1)) * N + node], xt[(int64_t)jy * m + jx], acc);
+    }
+  out[(int64_t)t * N + node] = b[(int64_t)t * N + node] - acc;
+}
+
+void launch_stencil_residual(hipStream_t s, int n, const double* S, const int* smode, int m,
+                             const double* b, const double* x, double* out) {
+  const int64_t N = (int64_t)(n - 1) * (n - 1);
+  hipLaunchKernelGGL(stencil_residual_kernel, dim3(cdiv(N, 256), m), dim3(256), 0, s, n, S, smode,
+                     b, x, out, N);
+}
+
 // The learned stage's step weight: alpha = dots[0] / dots[1] (<r, Kc> / ||Kc||^2)
 // when both are finite and dots[1] > 0, else 0 (dots[2] receives alpha); then
 // z += alpha c and, when w is given, w += alpha Kc.  With alpha = 0 nothing is

@@ -138,3 +138,19 @@ def test_one_split_is_mean_based_and_exact_mean_is_kron_inverse():
     z3 = FieldSplit(S, H, make_groups(S.Jp, "mean"), block_solve=lambda t, i: spla.spsolve(A0, t)).apply(r)
     ref = np.linalg.solve(np.kron(np.eye(S.P), S.A[0].toarray()), r)
     assert np.allclose(z3, ref, atol=1e-12)
+
+
+def test_richardson_block_solve_is_one_cycle_then_converges_to_the_block_inverse():
+    from oracle.precond import richardson_block_solve
+    S = SGSystem(Problem(n=16, M=2, p=2, q=4, cov="exp_l1", sigma=1.0, corr_len=0.5))
+    i = 3
+    Kii = S.block(i, i).tocsr()
+    H = GMGHierarchy(Kii, 16)
+    t = np.random.default_rng(4).standard_normal(S.Nh)
+    one = richardson_block_solve({i: Kii}, {i: H.vcycle}, 1)(t, i)
+    assert np.array_equal(one, H.vcycle(t))
+    ref = spla.spsolve(Kii.tocsc(), t)
+    errs = [np.linalg.norm(richardson_block_solve({i: Kii}, {i: H.vcycle}, k)(t, i) - ref)
+            for k in (1, 2, 4, 30)]
+    assert all(b < 0.5 * a for a, b in zip(errs, errs[1:])), errs
+    assert errs[-1] <= 1e-12 * np.linalg.norm(ref)
