@@ -332,15 +332,18 @@ int    sg_attach_cnn(sg_handle* h, sg_cnn* c, double sigma);
 typedef struct sg_batch sg_batch;
 /* count instances; f_nodal: NULL or an array of count host pointers (each
  * NULL or (n_i+1)^2 values).  autotune != 0 picks each problem class's
- * coefficient chunk of the operator apply by timing candidates on the
- * current device (cached on disk, keyed by device, n, M, p, q; the cache
- * file is $SG_AUTOTUNE_CACHE or ~/.sgfs_autotune.txt).                      */
+ * (device, M, p, q) apply form by timing the candidates the batched step
+ * kernels can run on the current device (cached on disk; the cache file is
+ * $SG_AUTOTUNE_CACHE or ~/.sgfs_autotune.txt): the register-resident
+ * factored kernel (code 1), the factored LDS tile kernel with qb Gauss points
+ * per sub-batch (100 + qb, qb in 8..64) or the triple-product form with kc
+ * coefficient modes per chunk (200 + kc, kc in 16..64).                     */
 int    sg_batch_create(int32_t count, const sg_problem* probs, const double* const* f_nodal,
                        int32_t autotune, sg_batch** out);
 /* packed vector layout: offsets[0..count] (instance i occupies
- * [offsets[i], offsets[i+1]) of every packed SG vector); chunk (nullable):
- * the chosen coefficient chunk of each instance's apply                     */
-int    sg_batch_layout(const sg_batch* b, int64_t* offsets, int32_t* chunk);
+ * [offsets[i], offsets[i+1]) of every packed SG vector); form (nullable):
+ * the code of each instance's apply form (as chosen by the autotuner)      */
+int    sg_batch_layout(const sg_batch* b, int64_t* offsets, int32_t* form);
 size_t sg_batch_workspace_bytes(const sg_batch* b, int32_t restart);
 /* binds a caller-owned 256-byte aligned workspace for GMRES(restart)      */
 int    sg_batch_bind(sg_batch* b, int32_t restart, void* ws, size_t bytes, void* stream);
@@ -362,8 +365,9 @@ int    sg_batch_handle(sg_batch* b, int32_t i, sg_handle** h);
 int    sg_batch_solve(sg_batch* b, const sg_solve_opts* opts, const double* F, double* u,
                       sg_solve_info* infos, void* stream);
 void   sg_batch_destroy(sg_batch* b);
-/* the autotuner on its own: fastest coefficient chunk for one problem      */
-int    sg_autotune_apply(const sg_problem* prob, int32_t* best_chunk, float* best_ms);
+/* the autotuner on its own: the code of the fastest apply form for the
+ * problem's class and its time per apply (ms) on the tuning grid           */
+int    sg_autotune_apply(const sg_problem* prob, int32_t* best_form, float* best_ms);
 
 #ifdef __cplusplus
 }

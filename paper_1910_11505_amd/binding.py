@@ -508,9 +508,9 @@ class Batch:
         _check(load_library().sg_batch_create(self.count, arr, fp, 1 if autotune else 0,
                                               ctypes.byref(self.b)))
         self.offsets = np.zeros(self.count + 1, dtype=np.int64)
-        self.chunk = np.zeros(self.count, dtype=np.int32)
+        self.form = np.zeros(self.count, dtype=np.int32)
         _check(load_library().sg_batch_layout(self.b, self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                              self.chunk.ctypes.data))
+                                              self.form.ctypes.data))
         self.restart = restart
         self.device = torch.device(device)
         self.stream = stream

@@ -2354,7 +2354,18 @@ hipGraphExec_t capture(sg_batch& B, hipStream_t s, const std::vector<LaunchRec>&
   return ex;
 }
 
-// ---- autotuner: coefficient chunk size (the staging tile depth) of the apply --
+// ---- autotuner: the apply form and tile shape of each problem class --------
+// Candidates are the forms the batched step kernels run for an instance:
+//   kTuneRegister          the register-resident factored kernel (one tile of
+//                          4x4 elements per workgroup, every mode in registers)
+//   kTuneTile + qb         the factored LDS tile kernel with qb Gauss points
+//                          per sub-batch (qb = 8, 16, 32, 64)
+//   kTuneTriple + kc       the triple-product form streaming kc coefficient
+//                          modes per chunk (kc = 16, 32, 48, 64)
+// A class is (device, M, p, q); it is timed on a grid of min(n, 64) elements
+// per side, where all candidates fit and a timing takes milliseconds.
+constexpr int kTuneRegister = 1, kTuneTile = 100, kTuneTriple = 200;
+
 std::string tune_cache_path() {
   const char* p = getenv("SG_AUTOTUNE_CACHE");
   if (p && *p) return p;
@@ -2366,8 +2377,8 @@ std::map<std::string, int> tune_load() {
   std::map<std::string, int> m;
   std::ifstream f(tune_cache_path());
   std::string key;
-  int kc;
-  while (f >> key >> kc) m[key] = kc;
+  int code;
+  while (f >> key >> code) m[key] = code;
   return m;
 }
 
@@ -2385,21 +2396,45 @@ std::string tune_key(const sg_problem& p) {
   for (char& c : arch)
     if (c == ':' || c == ' ') c = '_';
   std::ostringstream o;
-  o << arch << "_n" << p.n << "_M" << p.M << "_p" << p.p << "_q" << p.q;
+  o << arch << "_M" << p.M << "_p" << p.p << "_q" << p.q << "_form";
   return o.str();
 }
 
-// Times the operator apply of one problem class for each candidate chunk size
-// on scratch device memory; returns the fastest (0 if none could be timed).
+// Puts an unbound handle's apply in the form of a tuner code; false when the
+// form does not exist for this problem (the handle's form is then unchanged).
+bool set_form(sg_handle* h, int code) {
+  if (code == kTuneRegister)
+    return sg_set_apply(h, SG_APPLY_FACTORED, 0, nullptr) == SG_OK && h->use_rapply;
+  if (code > kTuneTile && code < kTuneTriple)
+    return sg_set_apply(h, SG_APPLY_FACTORED, code - kTuneTile, nullptr) == SG_OK;
+  if (code > kTuneTriple)
+    return h->full.kc == code - kTuneTriple && sg_set_apply(h, SG_APPLY_TRIPLE, 0, nullptr) == SG_OK;
+  return false;
+}
+
+// The tuner code of the form a handle's apply uses.
+int form_code(const sg_handle& H) {
+  if (H.use_factored && H.use_rapply) return kTuneRegister;
+  if (H.use_factored) return kTuneTile + H.ffull.qb;
+  return kTuneTriple + H.full.kc;
+}
+
+// Times one apply of every candidate form on scratch device memory; returns
+// the fastest candidate's code (0 if none could be timed).
 int tune_apply(const sg_problem& prob, float* best_ms_out) {
-  const int cands[] = {16, 32, 48, 64};
+  sg_problem tp = prob;
+  tp.n = std::min(prob.n, 64);
+  std::vector<int> cands = {kTuneRegister};
+  for (int qb : {64, 32, 16, 8}) cands.push_back(kTuneTile + qb);
+  for (int kc : {16, 32, 48, 64}) cands.push_back(kTuneTriple + kc);
   int best = 0;
   float best_ms = 1e30f;
-  for (int kc : cands) {
+  for (int code : cands) {
     sg_handle* h = nullptr;
-    if (setup_impl(&prob, nullptr, kc, &h) != SG_OK) continue;
+    const int kc = code > kTuneTriple ? code - kTuneTriple : 0;
+    if (setup_impl(&tp, nullptr, kc, &h) != SG_OK) continue;
     std::unique_ptr<sg_handle> hold(h);
-    if (h->full.kc != kc) continue;
+    if (!set_form(h, code)) continue;
     const size_t wb = sg_workspace_bytes(h);
     const int64_t Nv = (int64_t)h->P * h->Nh;
     void* ws = nullptr;
@@ -2430,7 +2465,7 @@ int tune_apply(const sg_problem& prob, float* best_ms_out) {
     (void)hipFree(ws);
     if (ms < best_ms) {
       best_ms = ms;
-      best = kc;
+      best = code;
     }
   }
   if (best_ms_out) *best_ms_out = best_ms / 5;
@@ -2441,12 +2476,12 @@ int tune_apply(const sg_problem& prob, float* best_ms_out) {
 
 extern "C" {
 
-int sg_autotune_apply(const sg_problem* prob, int32_t* best_kc, float* best_ms) {
-  if (!prob || !best_kc) return fail(SG_ERR_INVALID_ARG, "null argument");
+int sg_autotune_apply(const sg_problem* prob, int32_t* best_form, float* best_ms) {
+  if (!prob || !best_form) return fail(SG_ERR_INVALID_ARG, "null argument");
   try {
     validate(*prob);
-    *best_kc = tune_apply(*prob, best_ms);
-    return *best_kc > 0 ? SG_OK : fail(SG_ERR_HIP, "no candidate could be timed");
+    *best_form = tune_apply(*prob, best_ms);
+    return *best_form > 0 ? SG_OK : fail(SG_ERR_HIP, "no candidate could be timed");
   } catch (const Error& e) {
     return fail(e.code, e.what());
   }
@@ -2464,23 +2499,26 @@ int sg_batch_create(int32_t count, const sg_problem* probs, const double* const*
     if (autotune) cache = tune_load();
     for (int i = 0; i < count; ++i) {
       validate(probs[i]);
-      int kc = 0;
+      int code = 0;
       if (autotune) {
         const std::string key = tune_key(probs[i]);
         auto itc = cache.find(key);
         if (itc != cache.end()) {
-          kc = itc->second;
+          code = itc->second;
         } else {
-          kc = tune_apply(probs[i], nullptr);
-          cache[key] = kc;
+          code = tune_apply(probs[i], nullptr);
+          cache[key] = code;
           dirty = true;
         }
       }
       sg_handle* h = nullptr;
       const double* f = f_nodal ? f_nodal[i] : nullptr;
+      const int kc = code > kTuneTriple ? code - kTuneTriple : 0;
       int rc = setup_impl(&probs[i], f, kc, &h);
       if (rc != SG_OK && kc != 0) rc = setup_impl(&probs[i], f, 0, &h);
       if (rc != SG_OK) return rc;
+      // the tuned form where it exists for this instance, else the default
+      if (code && !set_form(h, code)) (void)sg_set_apply(h, SG_APPLY_AUTO, 0, nullptr);
       B->h.push_back(h);
     }
     if (dirty) tune_store(cache);
@@ -2493,11 +2531,11 @@ int sg_batch_create(int32_t count, const sg_problem* probs, const double* const*
   }
 }
 
-int sg_batch_layout(const sg_batch* b, int64_t* offsets, int32_t* chunk) {
+int sg_batch_layout(const sg_batch* b, int64_t* offsets, int32_t* form) {
   if (!b || !offsets) return fail(SG_ERR_INVALID_ARG, "null argument");
   for (int i = 0; i <= b->count; ++i) offsets[i] = b->voff[i];
-  if (chunk)
-    for (int i = 0; i < b->count; ++i) chunk[i] = b->h[i]->full.kc;
+  if (form)
+    for (int i = 0; i < b->count; ++i) form[i] = form_code(*b->h[i]);
   return SG_OK;
 }
 

@@ -125,14 +125,62 @@ def test_autotuner_picks_a_candidate_and_batch_uses_it(tmp_path, monkeypatch):
     need_gpu()
     monkeypatch.setenv("SG_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
     p = PROBS[4]
-    kc, ms = sg.sg_autotune_apply(make_problem(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma,
-                                               p.corr_len, p.a_min))
-    assert kc in (16, 32, 48, 64) and ms > 0
+    code, ms = sg.sg_autotune_apply(make_problem(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma,
+                                                 p.corr_len, p.a_min))
+    forms = {1} | {100 + qb for qb in (8, 16, 32, 64)} | {200 + kc for kc in (16, 32, 48, 64)}
+    assert code in forms and ms > 0
+    # q = 2p here, and the register kernel is the fastest form by far
+    assert code == 1
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         B, fs = _make(stream, autotune=True)
         assert (tmp_path / "tune.txt").exists()
+        # every instance runs the form its class was tuned to
+        assert all(f in forms for f in B.form) and B.form[4] == code
         F = B.rhs()
         u, infos = B.solve(F, pc="fs", grouping="klvar", tol=1e-8)
         assert all(i.status == 0 for i in infos)
         B.close()
+
+
+def test_the_64_instance_workload():
+    """The batched workload at its real shape: 64 uneven instances (n in
+    {64, 128, 256}, M in 2..6, p in 2..4, P up to 210, sigma ~ U[0.3, 1.5]),
+    one batched field-split GMRES(50) solve with the switch to K_ii cycles
+    where the A_0 blocks stagnate.  Every instance reaches the FP64 true
+    relative residual 1e-8; for the sixteen 64x64 instances with P <= 35 the
+    oracle recomputes that residual from the definition of K."""
+    need_gpu()
+    from math import comb
+    from oracle.system import SGSystem
+    from synth import batched_instances
+    inst = batched_instances(64)
+    probs = [make_problem(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma, p.corr_len, p.a_min)
+             for p, _ in inst]
+    fs = [rhs_noisy(p.n, seed) for p, seed in inst]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        B = sg.Batch(probs, f_nodal=fs, restart=50, stream=stream)
+        F = B.rhs()
+        u, infos = B.solve(F, pc="fs_switch", grouping="klvar", tol=1e-8, max_it=1000)
+        torch.cuda.synchronize()
+        print(f"[batched 64] converged {sum(i.status == 0 for i in infos)}/64, switched "
+              f"{sum(i.fallbacks for i in infos)}", flush=True)
+        assert all(i.status == 0 and i.relres <= 1e-8 for i in infos)
+        uh = u.cpu().numpy()
+        Fh = F.cpu().numpy()
+        offs = B.offsets.copy()
+        B.close()
+    checked = 0
+    for b, (p, seed) in enumerate(inst):
+        if p.n != 64 or comb(p.M + p.p, p.p) > 35:
+            continue
+        S = SGSystem(p, fs[b])
+        Fo = S.rhs()
+        ub = uh[offs[b]:offs[b + 1]]
+        assert np.abs(Fh[offs[b]:offs[b + 1]] - Fo).max() <= 1e-14 * np.abs(Fo).max()
+        rr = np.linalg.norm(Fo - S.apply_pointwise(ub)) / np.linalg.norm(Fo)
+        assert rr <= 1.05e-8, (b, rr)
+        assert abs(rr - infos[b].relres) <= 1e-12
+        checked += 1
+    assert checked == 16
