@@ -48,9 +48,9 @@ MG_GROUPING = "fg"
 # scaled by the same counter read on a plain 256 MiB device copy.  Valid only
 # for the kernel source the counters were taken on: the sha256 of
 # sg_rapply.hip + sg_kernels.hip + sg_internal.h is compared at run time.
-APPLY_TRAFFIC = {"src_sha256": "fe7a296002f4dc37440831f3f8db4ce6e9b6524b6f3a716aedd8df8b8c3da464",
-                 "fetch_bytes": (29555.57 + 48464.78) * 1024 * 2.0,
-                 "write_bytes": (71257.69 + 42606.45) * 1024 * 1.0}
+APPLY_TRAFFIC = {"src_sha256": "56493c8c7829fd4c3f50e8c931388c840e620ac4e4793fd1170a0c97855173a5",
+                 "fetch_bytes": (29125.52 + 48457.77) * 1024 * 2.0,
+                 "write_bytes": (68782.88 + 42606.44) * 1024 * 1.0}
 
 
 def _src_hash():
@@ -85,6 +85,9 @@ def _args():
     ap.add_argument("--learned-pairs", type=int, default=640)
     ap.add_argument("--learned-steps", type=int, default=1200)
     ap.add_argument("--learned-draws", type=int, default=4)
+    ap.add_argument("--learned-full", action="store_true",
+                    help="only the learned workload under its full protocol: 20000 training pairs, "
+                         "3 epochs of Adam, 32 held-out draws")
     ap.add_argument("--profile-apply", action="store_true",
                     help="counter-collection mode: only the 256x256 P=84 apply loop and a plain "
                          "256 MiB device copy (the scale reference for FETCH_SIZE/WRITE_SIZE)")
@@ -322,7 +325,7 @@ def cnn_rates(net, store, batch, stream):
     return out
 
 
-def learned_comparison(npairs, steps, draws, stream):
+def learned_comparison(npairs, steps, draws, stream, gen_problems=400):
     """The learned workload (Q1 128x128, M=4, p=3, squared-exponential L_c=0.5,
     sigma ~ U[0.3, 1.5], nodal-noise forcing) with a reduced training budget:
     pairs from field-split GMRES(5) cycles (K_ii blocks), Adam training on the
@@ -342,14 +345,15 @@ def learned_comparison(npairs, steps, draws, stream):
     net.set_params(Ws, bs)
     store = L.PairStore(npairs, P, Nh)
     t0 = time.perf_counter()
-    gen = L.generate_pairs(net, learned_problems(base, 400, 11505 + 4000), store, cycle=5,
-                           max_per_problem=16, pc="fs_kii")
+    gen = L.generate_pairs(net, learned_problems(base, gen_problems, 11505 + 4000), store, cycle=5,
+                           max_per_problem=16, pc="fs_kii", log=lambda m: _log(f"learned: {m}"))
     _log(f"learned: {gen['pairs']} pairs from {gen['problems']} problems in {gen['seconds']:.1f} s")
     losses, train_s = L.train(net, store, steps, 16, 1e-3, lr_final=1e-4)
     _log(f"learned: {steps} Adam steps in {train_s:.1f} s, loss {losses[-1][1]:.3g}")
     rates = cnn_rates(net, store, 16, stream)
     _log(f"cnn: forward {rates['forward']['tflops']:.1f} TFLOP/s, "
          f"forward+backward {rates['forward_backward']['tflops']:.1f} TFLOP/s")
+    eval_loss = L.eval_loss(net, store, 16) if npairs <= 2000 else None
     rows = []
     for prob, f in learned_problems(base, draws, 11505 + 4999):
         c = L.compare(net, prob, f, max_it=3000, fs_pc="fs_kii", learned_pc="learned_kii")
@@ -360,8 +364,13 @@ def learned_comparison(npairs, steps, draws, stream):
         _log(f"learned: sigma {c.sigma:.2f} FS-GMRES(50) {c.fs_iterations} it {c.fs_seconds * 1e3:.1f} ms, "
              f"learned FGMRES(30) {c.learned_iterations} it {c.learned_seconds * 1e3:.1f} ms")
     net.close()
-    return {"pairs": gen["pairs"], "train_steps": steps, "train_s": train_s,
-            "final_loss": losses[-1][1], "pair_generation_s": gen["seconds"],
+    return {"pairs": gen["pairs"], "training_problems": gen["problems"], "train_steps": steps,
+            "train_s": train_s, "final_loss": losses[-1][1], "train_set_loss": eval_loss,
+            "pair_generation_s": gen["seconds"],
+            "fs_iterations_median": float(np.median([r["fs_iterations"] for r in rows])),
+            "learned_iterations_median": float(np.median([r["learned_iterations"] for r in rows])),
+            "all_reach_tolerance": all(r["fs_relres"] <= 1e-8 and r["learned_relres"] <= 1e-8
+                                       for r in rows),
             "field_split": "K_ii blocks (SG_PC_DIAG_KII) in both solvers",
             "time_ratio_fs_over_learned": float(np.median([r["fs_s"] / r["learned_s"] for r in rows])),
             "iteration_ratio_fs_over_learned": float(np.median(
@@ -398,6 +407,10 @@ def main():
     stream = torch.cuda.current_stream()
     if args.profile_apply:
         profile_apply(stream)
+        return
+    if args.learned_full:
+        res = learned_comparison(20000, 3750, 32, stream, gen_problems=2000)
+        print(json.dumps({"learned_protocol": res}), flush=True)
         return
 
     # ---- set-up: three handles of the sweep, each with its multigrid -------

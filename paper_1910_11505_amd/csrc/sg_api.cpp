@@ -2362,8 +2362,9 @@ hipGraphExec_t capture(sg_batch& B, hipStream_t s, const std::vector<LaunchRec>&
 //                          per sub-batch (qb = 8, 16, 32, 64)
 //   kTuneTriple + kc       the triple-product form streaming kc coefficient
 //                          modes per chunk (kc = 16, 32, 48, 64)
-// A class is (device, M, p, q); it is timed on a grid of min(n, 64) elements
-// per side, where all candidates fit and a timing takes milliseconds.
+// A class is (device, M, p, q); it is timed on a grid of min(n, 128) elements
+// per side (1024 tiles: the kernels' relative speed at full occupancy, in
+// milliseconds per candidate), 10 applies per candidate.
 constexpr int kTuneRegister = 1, kTuneTile = 100, kTuneTriple = 200;
 
 std::string tune_cache_path() {
@@ -2423,7 +2424,7 @@ int form_code(const sg_handle& H) {
 // the fastest candidate's code (0 if none could be timed).
 int tune_apply(const sg_problem& prob, float* best_ms_out) {
   sg_problem tp = prob;
-  tp.n = std::min(prob.n, 64);
+  tp.n = std::min(prob.n, 128);
   std::vector<int> cands = {kTuneRegister};
   for (int qb : {64, 32, 16, 8}) cands.push_back(kTuneTile + qb);
   for (int kc : {16, 32, 48, 64}) cands.push_back(kTuneTriple + kc);
@@ -2453,7 +2454,7 @@ int tune_apply(const sg_problem& prob, float* best_ms_out) {
       if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
         (void)sg_apply(h, v, v + Nv, nullptr);
         (void)hipEventRecord(e0, nullptr);
-        for (int r = 0; r < 5; ++r) (void)sg_apply(h, v, v + Nv, nullptr);
+        for (int r = 0; r < 10; ++r) (void)sg_apply(h, v, v + Nv, nullptr);
         (void)hipEventRecord(e1, nullptr);
         if (hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
         (void)hipEventDestroy(e0);
@@ -2468,7 +2469,7 @@ int tune_apply(const sg_problem& prob, float* best_ms_out) {
       best = code;
     }
   }
-  if (best_ms_out) *best_ms_out = best_ms / 5;
+  if (best_ms_out) *best_ms_out = best_ms / 10;
   return best;
 }
 

@@ -325,7 +325,12 @@ __device__ __forceinline__ double r_node_sum(const RNode& q, const double* c, co
   return sum;
 }
 
-constexpr int kRChunk = 16;  // output rows per corner-sum chunk of the streamed tile
+// output rows per corner-sum chunk of the streamed tile: 8 up to P = 84 (the
+// smaller corner buffer lets three tiles' wavefronts share a SIMD instead of
+// two; 256x256 applies: P = 84 0.140 -> 0.122 ms, P = 56 0.099 -> 0.085 ms,
+// P = 70 0.130 -> 0.120 ms), 16 above (at P = 210 registers allow one
+// wavefront per SIMD anyway, and twice the chunks cost 0.43 -> 0.51 ms)
+constexpr int rchunk(int P) { return P <= 84 ? 8 : 16; }
 constexpr int kRFence = 4;   // rows between its scheduling fences
 
 // Field-split blocks known at compile time.  With the splits taken by the
@@ -343,7 +348,7 @@ struct RSel {
   static constexpr int P = RTab<M, p>::P;
   static constexpr int NT = RTab<M, p>::NT;
   int row[P] = {}, col[P] = {}, gam[P] = {};
-  int chunk[(P + kRChunk - 1) / kRChunk] = {};
+  int chunk[(P + rchunk(P) - 1) / rchunk(P)] = {};
   // the block's own pair lists (the whole operator's, filtered):
   // step 1a: each gamma below p that the block reads, with its column alphas below p
   int n1 = 0, g1[P] = {}, p1[P + 1] = {}, a1[NT] = {}, d1[NT] = {};
@@ -367,7 +372,7 @@ constexpr RSel<M, p> rc_make_sel() {
   for (int i = 0; i < P; ++i) {
     S.row[i] = first[i] == V;
     S.col[i] = first[i] < V;
-    if (S.row[i]) S.chunk[i / kRChunk] = 1;
+    if (S.row[i]) S.chunk[i / rchunk(P)] = 1;
   }
   for (int g = 0; g < P; ++g) {
     bool br = false, bc = false;
@@ -636,7 +641,7 @@ __global__ __launch_bounds__(kRThreads) void brapply_kernel(const BInst* __restr
 //    compiler cannot equate with the gradient loop's; its monomials come from
 //    copies of g it cannot equate with step 1's (either way it would keep
 //    step-1 values alive through step 2 and spill).
-//  - Output rows go in chunks of kRChunk: corner sums to LDS, barrier, node
+//  - Output rows go in chunks of rchunk(P): corner sums to LDS, barrier, node
 //    sums, barrier.  For the whole operator the rows carry no branches and are
 //    scheduled kRFence at a time between fences.
 // ---------------------------------------------------------------------------
@@ -662,6 +667,7 @@ __device__ __forceinline__ void rapply_stream_tile(double* smem, int tile, int n
   constexpr const RSel<M, p>& S = RSelHolder<M, p, V>::v;
   constexpr int SN1 = S.n1, SNQ = S.nq;
   double* sN = smem;            // [P][25] nodal values
+  constexpr int kRChunk = rchunk(P);
   double* sC = sN + P * 25;     // [2][kRChunk][64] corner contributions of a row chunk
   const int nt = n / kTileE, ntiles = nt * nt;
   const int tx = tile % nt, ty = tile / nt;
@@ -902,7 +908,7 @@ void launch_rblock(hipStream_t s, int kv, int n, double mu, double a_min, const 
     const int nt = n / kTileE;
     constexpr int P = RTab<M, p>::P;
     if constexpr (P > kRSmall) {
-      const size_t lds = 8 * ((size_t)25 * P + 2 * kRChunk * 64);
+      const size_t lds = 8 * ((size_t)25 * P + 2 * rchunk(P) * 64);
       static const bool attr_ok =
           hipFuncSetAttribute((const void*)rapply_stream_kernel<M, p, false, V>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
@@ -936,7 +942,7 @@ SG_RAPPLY_LIST(SG_RBLOCK_EXTERN)
 #undef SG_RBLOCK_EXTERN
 
 size_t rapply_stream_lds_bytes(int P) {
-  return 8 * ((size_t)P * 25 + (size_t)2 * kRChunk * 64);
+  return 8 * ((size_t)P * 25 + (size_t)2 * rchunk(P) * 64);
 }
 
 // P <= kRSmall: the nodal values and, after them, the corner contributions of

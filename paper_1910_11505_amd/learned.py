@@ -45,8 +45,9 @@ class PairStore:
 
 def generate_pairs(net: "sg.CNN", problems, store: PairStore, cycle: int = 5,
                    ref_tol: float = 1e-10, stop_tol: float = 1e-8, grouping: str = "klvar",
-                   pc: str = "fs", max_per_problem: int = 1000):
-    """Fills `store` from field-split GMRES(cycle) runs; returns generation stats."""
+                   pc: str = "fs", max_per_problem: int = 1000, log=None):
+    """Fills `store` from field-split GMRES(cycle) runs; returns generation stats.
+    `log` (optional) is called with a progress message every 100 problems."""
     import torch
     t0 = time.perf_counter()
     used = 0
@@ -73,6 +74,8 @@ def generate_pairs(net: "sg.CNN", problems, store: PairStore, cycle: int = 5,
         torch.cuda.synchronize()
         inst.close()
         used += 1
+        if log is not None and used % 100 == 0:
+            log(f"{store.count} pairs from {used} problems, {time.perf_counter() - t0:.0f} s")
     return {"pairs": store.count, "problems": used, "seconds": time.perf_counter() - t0}
 
 

@@ -129,8 +129,6 @@ def test_autotuner_picks_a_candidate_and_batch_uses_it(tmp_path, monkeypatch):
                                                  p.corr_len, p.a_min))
     forms = {1} | {100 + qb for qb in (8, 16, 32, 64)} | {200 + kc for kc in (16, 32, 48, 64)}
     assert code in forms and ms > 0
-    # q = 2p here, and the register kernel is the fastest form by far
-    assert code == 1
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         B, fs = _make(stream, autotune=True)
