@@ -91,6 +91,10 @@ def _args():
     ap.add_argument("--profile-apply", action="store_true",
                     help="counter-collection mode: only the 256x256 P=84 apply loop and a plain "
                          "256 MiB device copy (the scale reference for FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--paper-tables", metavar="MD",
+                    help="run the paper's mesh, sigma, p, q and N studies in their own setting "
+                         "(Q1 grids with the paper's unknown counts), print one JSON line and "
+                         "write the tables as markdown to MD")
     ap.add_argument("--profile-step", action="store_true",
                     help="kernel-trace mode: set-up, warm-up and timed steps only")
     return ap.parse_args()
@@ -378,6 +382,93 @@ def learned_comparison(npairs, steps, draws, stream, gen_problems=400):
             "problems": rows, "cnn": rates, "total_s": time.perf_counter() - t0}
 
 
+# The paper's studies (Sec. 4: Tabs. mesh_variation, sigma_variation, p_var_*,
+# q_var_*, N_var_*) in their setting: L1-exponential covariance, L_c = 0.1,
+# mu = 0, a_min = 0.01, f = 1.  Its level-L Q2 mesh has (2^(L+1) - 1)^2
+# interior nodes, the unknowns per mode of a Q1 grid of 2^(L+1) elements.
+PAPER_PCS = (  # (column, preconditioner, grouping)
+    ("mean-based", "mean", "klvar"),
+    ("G-F-I (K_ii blocks)", "fs_kii", "permode"),
+    ("G-M-I (all modes)", "mg", "all"),
+    ("G-M-F-I", "mg", "permode"),
+    ("G-M-Fg-I", "mg", "fg"),
+)
+PAPER_SIGMAS3 = (0.08, 0.8, 1.4)
+
+
+def paper_studies():
+    """(table, row label, n, M, p, q, sigma) of every solve set."""
+    rows = []
+    for L in (3, 4, 5, 6):
+        rows.append(("mesh_variation", f"L={L}", 2 ** (L + 1), 2, 4, 5, 0.08))
+    for sg_ in (0.08, 0.1, 0.2, 0.4, 0.8, 1.0, 1.4, 1.6):
+        rows.append(("sigma_variation", f"sigma={sg_}", 64, 2, 5, 5, sg_))
+    for sg_ in PAPER_SIGMAS3:
+        for p in (4, 5, 6, 7):
+            rows.append((f"p_var sigma={sg_}", f"p={p}", 64, 2, p, 5, sg_))
+        for q in (4, 5, 6, 7):
+            rows.append((f"q_var sigma={sg_}", f"q={q}", 64, 2, 5, q, sg_))
+        for N in (2, 3, 4):
+            rows.append((f"N_var sigma={sg_}", f"N={N}", 64, N, 3, 3, sg_))
+    return rows
+
+
+def paper_tables(stream, md_path):
+    """Every solve of the paper's studies with the five preconditioners: GMRES(50)
+    to the true relative residual 1e-8; per solve the iterations and the time of
+    a second, timed solve (HIP events).  Writes the tables as markdown."""
+    import torch
+    import paper_1910_11505_amd as sg
+    out = []
+    t_all = time.perf_counter()
+    for table, label, n, M, p, q, sigma in paper_studies():
+        inst = sg.SGInstance(n, M, p, q, "exp_l1", 0.0, sigma, 0.1, 0.01)
+        F = inst.rhs()
+        u = inst.vec()
+        row = {"table": table, "row": label, "n": n, "M": M, "p": p, "q": q, "sigma": sigma,
+               "P": inst.P, "unknowns": inst.P * inst.Nh, "solves": {}}
+        for col, pc, grouping in PAPER_PCS:
+            if pc == "mg":
+                inst.bind_mg(grouping)
+            inst.solve(F, pc=pc, grouping=grouping, restart=50, tol=1e-8, u=u, max_it=2000)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            _, info, _ = inst.solve(F, pc=pc, grouping=grouping, restart=50, tol=1e-8, u=u,
+                                    max_it=2000)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            row["solves"][col] = {"iterations": info.iterations, "ms": e0.elapsed_time(e1),
+                                  "relres": info.relres, "status": info.status}
+        inst.close()
+        out.append(row)
+        _log(f"{table} {label}: " + ", ".join(
+            f"{c} {v['iterations']} it {v['ms']:.1f} ms" for c, v in row["solves"].items()))
+    total_s = time.perf_counter() - t_all
+    if md_path:
+        cols = [c for c, _, _ in PAPER_PCS]
+        lines = []
+        for table in dict.fromkeys(r["table"] for r in out):
+            rs = [r for r in out if r["table"] == table]
+            r0 = rs[0]
+            lines.append(f"### {table}\n")
+            lines.append("| row | grid | P | unknowns | " + " | ".join(cols) + " |")
+            lines.append("|---|---|---|---|" + "---|" * len(cols))
+            for r in rs:
+                cells = []
+                for c in cols:
+                    v = r["solves"][c]
+                    mark = "" if v["status"] == 0 else " (not converged)"
+                    cells.append(f"{v['ms']:.2f} ms ({v['iterations']}){mark}")
+                lines.append(f"| {r['row']} | {r['n']}x{r['n']} | {r['P']} | {r['unknowns']} | "
+                             + " | ".join(cells) + " |")
+            lines.append("")
+        with open(md_path, "w") as f:
+            f.write("\n".join(lines))
+    return {"studies": out, "wall_s": total_s}
+
+
 def profile_apply(stream):
     import torch
     p, inst = make_c2(1.0)
@@ -407,6 +498,10 @@ def main():
     stream = torch.cuda.current_stream()
     if args.profile_apply:
         profile_apply(stream)
+        return
+    if args.paper_tables:
+        res = paper_tables(stream, args.paper_tables)
+        print(json.dumps({"paper_tables": res}), flush=True)
         return
     if args.learned_full:
         res = learned_comparison(20000, 3750, 32, stream, gen_problems=2000)

@@ -87,8 +87,21 @@ enum { SG_PC_INNER_SHIFT = 16 };
  *  KLVAR_MEANSEP KLVAR with the mean mode as its own first split
  *  PERMODE       one split per mode (the paper's G-M-F-I splitting)
  *  FG            the paper's leading-digit grouping (Sec. 3, worked example
- *                N=2, p=4 -> splits of 5, 4, 6 modes)                        */
-enum { SG_GROUP_KLVAR = 0, SG_GROUP_KLVAR_MEANSEP = 1, SG_GROUP_PERMODE = 2, SG_GROUP_FG = 3 };
+ *                N=2, p=4 -> splits of 5, 4, 6 modes)
+ *  ALL           one split of all modes: with SG_PC_FS the block-diagonal
+ *                (mean-based, or K_ii with SG_PC_DIAG_KII) preconditioner;
+ *                with SG_PC_MG a smoother that couples every mode at a node,
+ *                the counterpart of the paper's G-M-I (Sec. 3, a level
+ *                smoother preconditioned by an incomplete factorisation of
+ *                the whole K)                                                */
+enum {
+  SG_GROUP_KLVAR = 0,
+  SG_GROUP_KLVAR_MEANSEP = 1,
+  SG_GROUP_PERMODE = 2,
+  SG_GROUP_FG = 3,
+  SG_GROUP_ALL = 4,
+  SG_GROUP_COUNT = 5
+};
 
 /* form of the operator apply (sg_set_apply):
  *  TRIPLE    sum over the n_a coefficient modes a_k(x_q) with the triple
@@ -222,14 +235,16 @@ int sg_precond_apply(sg_handle* h, int pc, int grouping, const double* r, double
  * of the smoother; SG_GROUP_FG is the paper's G-M-Fg-I, SG_GROUP_PERMODE its
  * G-M-F-I), 0 for a bad argument.  sg_mg_bind builds the hierarchy in a
  * caller-owned, 256-byte aligned workspace on a bound handle: the KL values
- * of every coarser level, the nodal blocks of every split on every level but
+ * and coefficient modes a_k (eq. dataProjection) at the Gauss points of every
+ * coarser level, so that every level is applied in the handle's current apply
+ * form (factored or triple-product), the nodal blocks of every split on every level but
  * the coarsest (K applied to probe vectors, one mode and one of four node
  * colours at a time, then inverted in place), and the coarsest level's K
  * (column by column) inverted on the host.  Synchronises `stream`.  The
  * workspace must outlive the multigrid's use; binding again replaces the
  * hierarchy.  SG_PC_MG calls must pass the bound grouping.  Errors:
- * INVALID_ARG, NOT_BOUND (handle), UNSUPPORTED (the triple-product apply
- * form, i.e. q < 2p, or a split of more than 128 modes), WORKSPACE, HIP.  */
+ * INVALID_ARG, NOT_BOUND (handle), UNSUPPORTED (a split of more than 128
+ * modes), WORKSPACE, HIP.  */
 size_t sg_mg_workspace_bytes(const sg_handle* h, int grouping);
 int sg_mg_bind(sg_handle* h, int grouping, void* ws, size_t bytes, void* stream);
 

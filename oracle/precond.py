@@ -17,7 +17,8 @@ Split choices (grouping):
   fg             the paper's leading-digit grouping (Sec. 3, the worked
                  example for N=2, p=4): groups by first index value g = 0..p;
                  a group opens a new split iff (g, ..., g) is in J(p),
-                 otherwise it joins the preceding split.
+                 otherwise it joins the preceding split;
+  mean / all     one split of every mode.
 
 Inner iterations (the paper's G-F-I, eq. level_solver applied to each
 diagonal block with i_max > 1): richardson_block_solve gives the block solve
@@ -34,12 +35,12 @@ from __future__ import annotations
 
 import numpy as np
 
-GROUPINGS = ("klvar", "klvar_meansep", "permode", "fg", "mean")
+GROUPINGS = ("klvar", "klvar_meansep", "permode", "fg", "mean", "all")
 
 
 def make_groups(J: np.ndarray, grouping: str):
     P, M = J.shape
-    if grouping == "mean":
+    if grouping in ("mean", "all"):
         return [list(range(P))]
     if grouping == "permode":
         return [[i] for i in range(P)]

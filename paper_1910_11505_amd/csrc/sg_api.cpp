@@ -69,7 +69,7 @@ struct DevPtrs {
   std::vector<Level> L;
   RowSetDev full{};
   FRowSetDev ffull{};
-  FSDev fs[4];
+  FSDev fs[SG_GROUP_COUNT];
   double* edge = nullptr;
   std::vector<double*> mg_b, mg_x, mg_xa, mg_r;
   double *fsT = nullptr, *fsX = nullptr;
@@ -97,13 +97,14 @@ struct Carver {
 }  // namespace
 
 // Multigrid on the full SG system (sg_mg_bind): per level its grid, KL values
-// at its Gauss points and edge buffer (level 0: the handle's own), right-hand
-// side and correction (level 0: the caller's), work vectors, and the inverted
-// nodal blocks of every split; the coarsest level's dense inverse.
+// and coefficient modes at its Gauss points and edge buffer (level 0: the
+// handle's own), right-hand side and correction (level 0: the caller's), work
+// vectors, and the inverted nodal blocks of every split; the coarsest level's
+// dense inverse.
 struct MGLevel {
   int n = 0;
   int64_t N = 0;
-  double *g = nullptr, *edge = nullptr, *b = nullptr, *z = nullptr;
+  double *g = nullptr, *a = nullptr, *edge = nullptr, *b = nullptr, *z = nullptr;
   double *res = nullptr, *dz = nullptr, *t = nullptr;
   std::vector<double*> Dinv;
 };
@@ -134,9 +135,9 @@ struct sg_handle {
   bool rapply_ok = false;             // register form compiled for (M, p) and P <= 64
   int fqb = 0;                        // forced sub-batch size (0: planner's choice)
   RApplyRows rfull{};                 // register-form rows: whole operator
-  std::vector<RApplyRows> rpart[4];   // and the field-split blocks (index 0 unused)
-  std::vector<int> rkv[4];            // block index of the first-variable split, else 0
-  FSHost fs[4];
+  std::vector<RApplyRows> rpart[SG_GROUP_COUNT];  // and the field-split blocks (index 0 unused)
+  std::vector<int> rkv[SG_GROUP_COUNT];         // block index of the first-variable split, else 0
+  FSHost fs[SG_GROUP_COUNT];
   std::vector<int> level_n;
   std::vector<int> diag_ptr, diag_k, diag_sid;  // per mode i: [G_k]_{ii} != 0 entries
   std::vector<double> diag_v;
@@ -559,7 +560,7 @@ void carve(const sg_handle& H, DevPtrs& D, Carver& c) {
     d.blob = c.take<int>(f.blob.size());
   };
   if (H.factored_ok) put_frowset(H.ffull, D.ffull);
-  for (int g = 0; g < 4; ++g) {
+  for (int g = 0; g < SG_GROUP_COUNT; ++g) {
     const FSHost& fh = H.fs[g];
     FSDev& fd = D.fs[g];
     fd.split_idx.assign(fh.splits.size(), nullptr);
@@ -832,6 +833,8 @@ size_t mg_layout(const sg_handle& H, int grouping, MGState& st, char* base) {
     const bool last = nl <= kMGCoarseN;
     if (nl != H.n) {
       L.g = c.take<double>((size_t)H.M * 4 * nl * nl);
+      // the triple-product form's coefficient modes (either form may be selected later)
+      L.a = c.take<double>((size_t)H.na * 4 * nl * nl);
       L.edge = c.take<double>((size_t)H.P * (nl / kTileE) * (nl / kTileE) * kEdgeVals);
       L.b = c.take<double>(PN);
       L.z = c.take<double>(PN);
@@ -855,13 +858,14 @@ void mg_apply(sg_handle& H, hipStream_t s, int l, const double* U, const double*
   const MGLevel& L = H.mg.L[l];
   const double* g = l ? L.g : H.d.g;
   double* edge = l ? L.edge : H.d.edge;
-  if (!H.use_factored) throw Error(SG_ERR_UNSUPPORTED, "full-system multigrid needs the factored apply");
-  if (H.use_rapply)
+  if (H.use_factored && H.use_rapply)
     launch_rapply(s, H.M, H.prob.p, L.n, H.prob.mu, H.prob.a_min, g, H.rfull, U, L.N, rin, beta,
                   sgn, out, edge, true);
-  else
+  else if (H.use_factored)
     launch_fapply(s, L.n, H.prob.mu, H.prob.a_min, g, H.d.ffull, U, L.N, rin, beta, sgn, out, edge,
                   true);
+  else
+    launch_apply(s, L.n, H.na, l ? L.a : H.d.a, H.d.full, U, L.N, rin, beta, sgn, out, edge, true);
 }
 
 // out (the split's rows, compact) = rin_{g_sp} - K_{g_sp, g_<sp} U on level l
@@ -871,12 +875,15 @@ void mg_partial(sg_handle& H, hipStream_t s, int l, int sp, const double* U, con
   const int gr = H.mg.grouping;
   const double* g = l ? L.g : H.d.g;
   double* edge = l ? L.edge : H.d.edge;
-  if (H.use_rapply)
+  if (H.use_factored && H.use_rapply)
     launch_rapply(s, H.M, H.prob.p, L.n, H.prob.mu, H.prob.a_min, g, H.rpart[gr][sp], U, L.N, rin,
                   1.0, -1.0, out, edge, true, H.rkv[gr][sp]);
-  else
+  else if (H.use_factored)
     launch_fapply(s, L.n, H.prob.mu, H.prob.a_min, g, H.d.fs[gr].fpartial[sp], U, L.N, rin, 1.0,
                   -1.0, out, edge, true);
+  else
+    launch_apply(s, L.n, H.na, l ? L.a : H.d.a, H.d.fs[gr].partial[sp], U, L.N, rin, 1.0, -1.0,
+                 out, edge, true);
 }
 
 // One level iteration z <- z + P_FS^{-1}(b - K z) (eq. level_solver); with
@@ -976,7 +983,7 @@ void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double*
   if (inner > 1 && (kind == SG_PC_MEAN || kind == SG_PC_FS)) {
     // the blocks' inner iterations run on compact copies of each split
     const int g = kind == SG_PC_MEAN ? -1 : grouping;
-    if (g > 3) throw Error(SG_ERR_INVALID_ARG, "unknown grouping");
+    if (g >= SG_GROUP_COUNT) throw Error(SG_ERR_INVALID_ARG, "unknown grouping");
     if (g < 0) {
       block_solve(H, s, H.P, kii ? H.d.all_sid : nullptr, inner, r, z);
       return;
@@ -1017,7 +1024,7 @@ void do_precond(sg_handle& H, hipStream_t s, int pc, int grouping, const double*
     return;
   }
   if (kind != SG_PC_FS) throw Error(SG_ERR_INVALID_ARG, "unknown preconditioner");
-  if (grouping < 0 || grouping > 3) throw Error(SG_ERR_INVALID_ARG, "unknown grouping");
+  if (grouping < 0 || grouping >= SG_GROUP_COUNT) throw Error(SG_ERR_INVALID_ARG, "unknown grouping");
   const FSHost& fh = H.fs[grouping];
   const FSDev& fd = H.d.fs[grouping];
   for (size_t sp = 0; sp < fh.splits.size(); ++sp) {
@@ -1165,7 +1172,7 @@ int setup_impl(const sg_problem* prob, const double* f_nodal, int force_kc, sg_h
     H->full = build_rowset(*H, all, all, force_kc);
     H->factored_ok = prob->q >= 2 * prob->p;
     H->use_factored = H->factored_ok;
-    for (int g = 0; g < 4; ++g) {
+    for (int g = 0; g < SG_GROUP_COUNT; ++g) {
       FSHost& fh = H->fs[g];
       fh.splits = make_splits(H->Jp, g);
       fh.partial.assign(fh.splits.size(), RowSetHost{});
@@ -1185,7 +1192,7 @@ int setup_impl(const sg_problem* prob, const double* f_nodal, int force_kc, sg_h
         std::vector<TPair> T = t_pairs(*H);
         monomial_tables(*H);
         H->ffull = build_frowset(*H, T, all, all, 0);
-        for (int g = 0; g < 4; ++g) {
+        for (int g = 0; g < SG_GROUP_COUNT; ++g) {
           FSHost& fh = H->fs[g];
           std::vector<int> prev = fh.splits[0];
           for (size_t s = 1; s < fh.splits.size(); ++s) {
@@ -1228,7 +1235,7 @@ int setup_impl(const sg_problem* prob, const double* f_nodal, int force_kc, sg_h
         return r;
       };
       H->rfull = rows(all, all);
-      for (int g = 0; g < 4; ++g) {
+      for (int g = 0; g < SG_GROUP_COUNT; ++g) {
         FSHost& fh = H->fs[g];
         H->rpart[g].assign(fh.splits.size(), RApplyRows{});
         H->rkv[g].assign(fh.splits.size(), 0);
@@ -1317,7 +1324,7 @@ int sg_bind(sg_handle* h, void* dev_workspace, size_t bytes, void* stream) {
     upload(s, D.f, H.f_nodal);
     upload_rowset(s, H.full, D.full);
     if (H.factored_ok) upload_frowset(s, H.ffull, D.ffull);
-    for (int g = 0; g < 4; ++g)
+    for (int g = 0; g < SG_GROUP_COUNT; ++g)
       for (size_t sp = 0; sp < H.fs[g].splits.size(); ++sp) {
         upload(s, D.fs[g].split_idx[sp], H.fs[g].splits[sp]);
         upload(s, D.fs[g].split_sid[sp], H.fs[g].sid[sp]);
@@ -1405,18 +1412,18 @@ int sg_set_apply(sg_handle* h, int kind, int points_per_batch, void* stream) {
       // plan on copies first: a size that does not fit leaves the old plan in place
       FRowSetHost full = H.ffull;
       plan_frowset(H, full, qb);
-      std::vector<std::vector<FRowSetHost>> parts(4);
-      for (int g = 0; g < 4; ++g) {
+      std::vector<std::vector<FRowSetHost>> parts(SG_GROUP_COUNT);
+      for (int g = 0; g < SG_GROUP_COUNT; ++g) {
         parts[g] = H.fs[g].fpartial;
         for (size_t sp = 1; sp < parts[g].size(); ++sp) plan_frowset(H, parts[g][sp], qb);
       }
       H.ffull = std::move(full);
-      for (int g = 0; g < 4; ++g) H.fs[g].fpartial = std::move(parts[g]);
+      for (int g = 0; g < SG_GROUP_COUNT; ++g) H.fs[g].fpartial = std::move(parts[g]);
       H.fqb = qb;
       if (H.bound) {
         hipStream_t s = reinterpret_cast<hipStream_t>(stream);
         upload_frowset(s, H.ffull, H.d.ffull);
-        for (int g = 0; g < 4; ++g)
+        for (int g = 0; g < SG_GROUP_COUNT; ++g)
           for (size_t sp = 1; sp < H.fs[g].fpartial.size(); ++sp)
             upload_frowset(s, H.fs[g].fpartial[sp], H.d.fs[g].fpartial[sp]);
         SG_HIP(hipStreamSynchronize(s));
@@ -1486,7 +1493,7 @@ int sg_precond_apply(sg_handle* h, int pc, int grouping, const double* r, double
   if (r == z) return fail(SG_ERR_INVALID_ARG, "r and z must not alias");
   if (!h->bound) return fail(SG_ERR_NOT_BOUND, "handle not bound");
   if (!valid_pc(pc, true)) return fail(SG_ERR_INVALID_ARG, "unknown preconditioner");
-  if (grouping < 0 || grouping > 3) return fail(SG_ERR_INVALID_ARG, "unknown grouping");
+  if (grouping < 0 || grouping >= SG_GROUP_COUNT) return fail(SG_ERR_INVALID_ARG, "unknown grouping");
   const bool learned = (pc & 0xff) == SG_PC_LEARNED;
   if (learned && !h->cnn) return fail(SG_ERR_INVALID_ARG, "learned stage needs an attached network");
   try {
@@ -1510,7 +1517,7 @@ int sg_precond_apply(sg_handle* h, int pc, int grouping, const double* r, double
 }
 
 size_t sg_mg_workspace_bytes(const sg_handle* h, int grouping) {
-  if (!h || grouping < 0 || grouping > 3) return 0;
+  if (!h || grouping < 0 || grouping >= SG_GROUP_COUNT) return 0;
   MGState st;
   return mg_layout(*h, grouping, st, nullptr);
 }
@@ -1518,9 +1525,7 @@ size_t sg_mg_workspace_bytes(const sg_handle* h, int grouping) {
 int sg_mg_bind(sg_handle* h, int grouping, void* ws, size_t bytes, void* stream) {
   if (!h || !ws) return fail(SG_ERR_INVALID_ARG, "null argument");
   if (!h->bound) return fail(SG_ERR_NOT_BOUND, "handle not bound");
-  if (grouping < 0 || grouping > 3) return fail(SG_ERR_INVALID_ARG, "unknown grouping");
-  if (!h->use_factored)
-    return fail(SG_ERR_UNSUPPORTED, "full-system multigrid needs the factored apply (q >= 2p)");
+  if (grouping < 0 || grouping >= SG_GROUP_COUNT) return fail(SG_ERR_INVALID_ARG, "unknown grouping");
   for (const auto& g : h->fs[grouping].splits)
     if (mg_block_pad((int)g.size()) == 0)
       return fail(SG_ERR_UNSUPPORTED, "full-system multigrid: a split of more than 128 modes");
@@ -1540,7 +1545,11 @@ int sg_mg_bind(sg_handle* h, int grouping, void* ws, size_t bytes, void* stream)
         split_of[splits[sp][a]] = (int)sp;
         pos_of[splits[sp][a]] = (int)a;
       }
-    for (size_t l = 1; l < H.mg.L.size(); ++l) upload(s, H.mg.L[l].g, mg_level_g(H, H.mg.L[l].n));
+    for (size_t l = 1; l < H.mg.L.size(); ++l) {
+      MGLevel& L = H.mg.L[l];
+      upload(s, L.g, mg_level_g(H, L.n));
+      launch_coeff(s, L.n, H.M, H.na, L.g, H.d.Jq, H.d.isf, H.prob.mu, H.prob.a_min, L.a);
+    }
     const int last = (int)H.mg.L.size() - 1;
     // nodal blocks: apply K to one mode on one node colour at a time
     for (int l = 0; l < last; ++l) {
@@ -1639,7 +1648,7 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
   if (!(o->tol > 0.0)) return fail(SG_ERR_INVALID_ARG, "tol must be positive");
   if (!valid_pc(o->pc, true, true)) return fail(SG_ERR_INVALID_ARG, "unknown preconditioner");
   if (is_learned(o) && !h->cnn) return fail(SG_ERR_INVALID_ARG, "learned stage needs an attached network");
-  if (o->grouping < 0 || o->grouping > 3) return fail(SG_ERR_INVALID_ARG, "unknown grouping");
+  if (o->grouping < 0 || o->grouping >= SG_GROUP_COUNT) return fail(SG_ERR_INVALID_ARG, "unknown grouping");
   if (ws_bytes < sg_gmres_workspace_bytes(h, o)) return fail(SG_ERR_WORKSPACE, "Krylov workspace too small");
   if (reinterpret_cast<uintptr_t>(krylov_ws) % 256) return fail(SG_ERR_WORKSPACE, "Krylov workspace must be 256-byte aligned");
   try {
@@ -1848,7 +1857,7 @@ int sg_export(sg_handle* h, int what, int level, double* out, size_t count) {
         std::copy(H.kl.gq.begin(), H.kl.gq.end(), out);
         return SG_OK;
       case SG_EXPORT_GROUPS: {
-        if (level < 0 || level > 3) throw Error(SG_ERR_INVALID_ARG, "grouping out of range");
+        if (level < 0 || level >= SG_GROUP_COUNT) throw Error(SG_ERR_INVALID_ARG, "grouping out of range");
         std::vector<double> v;
         v.push_back((double)H.fs[level].splits.size());
         for (auto& sp : H.fs[level].splits) {
@@ -2610,7 +2619,7 @@ int sg_batch_solve(sg_batch* b, const sg_solve_opts* o, const double* F, double*
   const int kind = o->pc & 0xff;
   if ((kind != SG_PC_MEAN && kind != SG_PC_FS) || (o->pc & ~(0xff | SG_PC_SWITCH_KII)))
     return fail(SG_ERR_UNSUPPORTED, "batched solves take the mean-based or field-split preconditioner");
-  if (o->grouping < 0 || o->grouping > 3) return fail(SG_ERR_INVALID_ARG, "unknown grouping");
+  if (o->grouping < 0 || o->grouping >= SG_GROUP_COUNT) return fail(SG_ERR_INVALID_ARG, "unknown grouping");
   if (o->use_x0) return fail(SG_ERR_UNSUPPORTED, "batched solves start from zero");
   if (!(o->tol > 0.0) || o->max_it < 1) return fail(SG_ERR_INVALID_ARG, "need tol > 0 and max_it >= 1");
   try {

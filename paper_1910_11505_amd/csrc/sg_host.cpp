@@ -271,6 +271,11 @@ std::vector<std::vector<int>> make_splits(const std::vector<std::vector<int>>& J
     for (int i = 0; i < P; ++i) out.push_back({i});
     return out;
   }
+  if (grouping == SG_GROUP_ALL) {
+    out.emplace_back(P);
+    for (int i = 0; i < P; ++i) out[0][i] = i;
+    return out;
+  }
   if (grouping == SG_GROUP_KLVAR || grouping == SG_GROUP_KLVAR_MEANSEP) {
     std::vector<std::vector<int>> byvar(M);
     std::vector<int> mean;

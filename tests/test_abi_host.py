@@ -97,7 +97,8 @@ def test_kl_tables_match_oracle(name):
 
 
 @pytest.mark.parametrize("M,p", [(2, 4), (4, 3), (6, 3), (3, 3)])
-@pytest.mark.parametrize("gname,gid", [("klvar", 0), ("klvar_meansep", 1), ("permode", 2), ("fg", 3)])
+@pytest.mark.parametrize("gname,gid", [("klvar", 0), ("klvar_meansep", 1), ("permode", 2), ("fg", 3),
+                                         ("all", 4)])
 def test_groupings_match_oracle(M, p, gname, gid):
     h = _setup(M=M, p=p, q=2 * p)
     out = np.zeros(2000)

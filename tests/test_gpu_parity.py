@@ -102,7 +102,8 @@ def kii_solver(name):
 @pytest.mark.parametrize("name", SMALL_P)
 @pytest.mark.parametrize("pc,grouping", [("mean", "klvar"), ("fs", "klvar"), ("fs", "klvar_meansep"),
                                          ("fs", "permode"), ("fs", "fg"), ("mean_kii", "klvar"),
-                                         ("fs_kii", "klvar"), ("fs_kii", "permode")])
+                                         ("fs_kii", "klvar"), ("fs_kii", "permode"), ("fs", "all"),
+                                         ("fs_kii", "all")])
 def test_precond(name, pc, grouping):
     from oracle.precond import FieldSplit, make_groups
     S, H, G = pair(name)

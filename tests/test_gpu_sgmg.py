@@ -2,7 +2,8 @@
 family of Sec. 3) through the C ABI against the oracle (oracle/sgmg.py):
 one V-cycle application at 1e-12 relative (max-norm) for several groupings,
 grids and chaos sizes, including a one-level hierarchy, the compiled
-first-variable split blocks and the streamed register apply; GMRES with the
+first-variable split blocks, the streamed register apply, the triple-product
+form (q < 2p) and one split of all modes; GMRES with the
 V-cycle against the oracle's GMRES with the oracle's V-cycle (iterations
 +-1, solution 1e-10, true residual from the oracle)."""
 import numpy as np
@@ -29,6 +30,14 @@ CASES = {
     "n8_m6p3_klvar": (Problem(n=8, M=6, p=3, q=6, cov="exp_l1", sigma=1.5, corr_len=0.25), "klvar"),
     # a single level: the V-cycle is the coarsest level's direct solve
     "n4_m3p3_fg": (Problem(n=4, M=3, p=3, q=6, cov="exp_l1", sigma=1.1, corr_len=0.6), "fg"),
+    # q < 2p: every level in the triple-product form with its own coefficient
+    # modes (the paper's p- and q-variation settings, N = 2, q = 5)
+    "n16_m2p4_q5_fg": (Problem(n=16, M=2, p=4, q=5, cov="exp_l1", sigma=1.4, corr_len=0.3), "fg"),
+    "n16_m2p5_q4_permode": (Problem(n=16, M=2, p=5, q=4, cov="exp_l1", sigma=0.8, corr_len=0.3), "permode"),
+    # the N-variation setting p = q = 3, and one split of all modes (nodal
+    # blocks of the whole K, the counterpart of the paper's G-M-I)
+    "n16_m3p3_q3_all": (Problem(n=16, M=3, p=3, q=3, cov="exp_l1", sigma=1.4, corr_len=0.3), "all"),
+    "n16_m3p2_all": (Problem(n=16, M=3, p=2, q=4, cov="exp_l1", sigma=1.0, corr_len=0.3), "all"),
 }
 
 _cache = {}
@@ -61,7 +70,8 @@ def test_vcycle_matches_oracle(name):
     assert np.array_equal(z, z2)
 
 
-@pytest.mark.parametrize("name", ["n32_m3p2_klvar", "n32_m4p3_fg", "n8_m6p3_klvar"])
+@pytest.mark.parametrize("name", ["n32_m3p2_klvar", "n32_m4p3_fg", "n8_m6p3_klvar", "n16_m2p4_q5_fg",
+                                  "n16_m3p3_q3_all"])
 def test_gmres_with_vcycle_matches_oracle(name):
     from oracle.gmres import gmres
     S, mg, G, grouping = case(name)

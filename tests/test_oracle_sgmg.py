@@ -1,6 +1,6 @@
 """Pins for oracle.sgmg: multigrid on the full SG system with the field-split
 smoother (paper Sec. 3, eqs. level_solver and P_group; trends of Tabs.
-sigma_variation and mesh_variation)."""
+sigma_variation, mesh_variation, p_var_*, q_var_* and N_var_*)."""
 import numpy as np
 import pytest
 
@@ -120,3 +120,51 @@ def test_paper_trend_in_the_mesh():
     # Tab. mesh_variation: multigrid iteration counts do not grow with the mesh
     its = [_iters(n, 0.8, "fg", M=2, p=3) for n in (8, 16, 32)]
     assert max(its) - min(its) <= 1, its
+
+
+# The paper's p-, q- and N-variation studies (Tabs. p_var_*, q_var_*, N_var_*)
+# in their own setting: L1-exponential covariance with L_c = 0.1, mu = 0,
+# a_min = 0.01, f = 1, here on a 16 x 16 grid.  Iteration counts of GMRES
+# with one V-cycle per step, for one split per mode (G-M-F-I), the
+# leading-digit grouping (G-M-Fg-I) and one split of all modes (the
+# counterpart of G-M-I).  Measured: p = 3..6 (q = 5, sigma = 1.4)
+# permode 12/15/17/20, fg 9/10/10/12, all 7/7/7/7; q = 4..7 (p = 4) all
+# three flat; N = 2..4 (p = q = 3, sigma = 1.4) permode 13/14/16, fg 9/9/7,
+# all 7/7/7.
+
+def _paper_iters(M, p, q, sigma, grouping, n=16):
+    S = SGSystem(Problem(n=n, M=M, p=p, q=q, cov="exp_l1", sigma=sigma, corr_len=0.1))
+    mg = FullSGMultigrid(S, grouping=grouping)
+    K = mg.K[0]
+    _, info = gmres(lambda v: K @ v, mg.vcycle, S.rhs(), tol=1e-8, restart=50, max_it=200)
+    assert info["converged"]
+    return info["iterations"]
+
+
+def test_paper_trend_in_p():
+    # Tab. p_var_high: G-M-F-I grows with p, G-M-Fg-I and G-M-I stay flat
+    ps = (3, 4, 6)
+    pm = [_paper_iters(2, p, 5, 1.4, "permode") for p in ps]
+    fg = [_paper_iters(2, p, 5, 1.4, "fg") for p in ps]
+    al = [_paper_iters(2, p, 5, 1.4, "all") for p in ps]
+    assert pm[-1] >= pm[0] + 5 and all(a < b for a, b in zip(pm, pm[1:])), pm
+    assert max(fg) - min(fg) <= 3 and all(f < m for f, m in zip(fg, pm)), (fg, pm)
+    assert max(al) - min(al) <= 1, al
+
+
+def test_paper_trend_in_q():
+    # Tabs. q_var_*: the iteration count does not depend on q
+    for grouping in ("permode", "fg", "all"):
+        its = [_paper_iters(2, 4, q, 1.4, grouping) for q in (4, 5, 7)]
+        assert max(its) - min(its) <= 1, (grouping, its)
+
+
+def test_paper_trend_in_the_stochastic_dimension():
+    # Tab. N_var_high: G-M-F-I grows with N, G-M-Fg-I and G-M-I do not
+    Ns = (2, 3, 4)
+    pm = [_paper_iters(M, 3, 3, 1.4, "permode") for M in Ns]
+    fg = [_paper_iters(M, 3, 3, 1.4, "fg") for M in Ns]
+    al = [_paper_iters(M, 3, 3, 1.4, "all") for M in Ns]
+    assert pm[-1] >= pm[0] + 2, pm
+    assert max(fg) <= pm[0] and fg[-1] <= fg[0], (fg, pm)
+    assert max(al) - min(al) <= 1, al
