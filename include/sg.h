@@ -381,7 +381,9 @@ int    sg_batch_solve(sg_batch* b, const sg_solve_opts* opts, const double* F, d
                       sg_solve_info* infos, void* stream);
 void   sg_batch_destroy(sg_batch* b);
 /* the autotuner on its own: the code of the fastest apply form for the
- * problem's class and its time per apply (ms) on the tuning grid           */
+ * problem's class and its time per apply (ms) on the tuning grid; the code
+ * is recorded in the tuning cache that sg_batch_create reads, replacing any
+ * earlier entry for the class                                              */
 int    sg_autotune_apply(const sg_problem* prob, int32_t* best_form, float* best_ms);
 
 #ifdef __cplusplus

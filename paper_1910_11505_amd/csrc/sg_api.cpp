@@ -1611,8 +1611,9 @@ size_t krylov_layout(const sg_handle* h, int restart, bool flexible, KrylovWS* k
   K.z = c.take<double>(Nv);
   K.t = c.take<double>(Nv);
   K.x2 = c.take<double>(Nv);
-  K.partial = c.take<double>((size_t)std::max(K.nblk, gs_blocks(Nv)) * (restart + 1));
-  K.hdev = c.take<double>(2 * (size_t)(restart + 1) + 4);
+  K.partial = c.take<double>(std::max((size_t)std::max(K.nblk, gs_blocks(Nv)) * (restart + 1),
+                                       gs2_partial_doubles(restart)));
+  K.hdev = c.take<double>(3 * (size_t)(restart + 1) + 16);
   K.ydev = c.take<double>(restart + 1);
   return c.off;
 }
@@ -1707,93 +1708,209 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
     int it = 0, restarts = 0;
     bool broke = false;
     double est = beta;
+    // Rotates column j of Hat by the rotations 0..j-1, forms rotation j and
+    // applies it to g.
+    auto rotate_column = [&](int j) {
+      for (int i = 0; i < j; ++i) {
+        double tmp = cs[i] * Hat(i, j) + sn[i] * Hat(i + 1, j);
+        Hat(i + 1, j) = -sn[i] * Hat(i, j) + cs[i] * Hat(i + 1, j);
+        Hat(i, j) = tmp;
+      }
+      double a = Hat(j, j), b = Hat(j + 1, j);
+      if (b == 0.0) {
+        cs[j] = 1.0;
+        sn[j] = 0.0;
+      } else {
+        double r = std::hypot(a, b);
+        cs[j] = a / r;
+        sn[j] = b / r;
+      }
+      Hat(j, j) = cs[j] * a + sn[j] * b;
+      Hat(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+    };
+    // Linear preconditioners: Gram-Schmidt with the second projection delayed
+    // by one step (launch_gs2_*, two passes over the basis per step).  Step j
+    // applies the operator B = K M^{-1} to u_j, the previous step's vector after
+    // one projection, u_j = nu_j q_j + Q s_j.  Pass A/B give
+    //   B u_j = Q_{0..j} c_j + a_j u_{j+1},  a_j = nu_j rho_j,
+    // so in the vectors the operator was applied to, B U = Q H~ with column j
+    // of H~ equal to (c_j + a_j s_{j+1}, a_j nu_{j+1}): complete one step later,
+    // once s_{j+1} and nu_{j+1} are known.  GMRES minimises |beta nu_0 e_1 -
+    // H~ y| and corrects x by M^{-1} U y = M^{-1} Q (S y), S the upper
+    // triangle with columns (s_j, nu_j).  The residual estimate of step j
+    // takes column j with s_{j+1} = 0, nu_{j+1} = 1; when it meets the
+    // tolerance, and at the end of a cycle, one more dot pass completes it.
+    std::vector<double> Ht(learned ? 0 : (size_t)(m + 1) * m), Sm(learned ? 0 : (size_t)m * m),
+        av(m), col(m + 1);
+    auto Htt = [&](int i, int j) -> double& { return Ht[(size_t)i * m + j]; };
+    auto Smm = [&](int i, int j) -> double& { return Sm[(size_t)i * m + j]; };
+    const int kCoef = 2 * (m + 1) + 2;  // offsets into hdev and hp
+    const int kFin = kCoef + 4;
+    int nfinal = 0;
+    // completes column j from s_{j+1} (j + 1 values) and nu_{j+1}
+    auto finish_column = [&](int j, const double* s1, double nu1) {
+      for (int i = 0; i <= j; ++i) Htt(i, j) += av[j] * s1[i];
+      Htt(j + 1, j) = av[j] * nu1;
+      for (int i = 0; i <= j + 1; ++i) Hat(i, j) = Htt(i, j);
+      rotate_column(j);
+      nfinal = j + 1;
+    };
+    // |g_{j+1}| with column j completed by s_{j+1} = 0, nu_{j+1} = 1
+    auto provisional = [&](int j) {
+      for (int i = 0; i <= j; ++i) col[i] = Htt(i, j);
+      double b = av[j];
+      for (int i = 0; i < j; ++i) {
+        double tmp = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = tmp;
+      }
+      const double r = std::hypot(col[j], b);
+      return r > 0.0 ? std::fabs(g[j]) * std::fabs(b) / r : std::fabs(g[j]);
+    };
+    auto linear_cycle = [&]() -> int {
+      nfinal = 0;
+      std::fill(Ht.begin(), Ht.end(), 0.0);
+      std::fill(Sm.begin(), Sm.end(), 0.0);
+      // the next step's preconditioner and operator apply (which need only
+      // u_{j+1}, already on the device) are queued before the host waits for
+      // step j's scalars; wasted once, when step j ends the solve
+      bool queued = false;
+      for (int j = 0; j < m; ++j) {
+        double* uj = K.V + (int64_t)j * Nv;
+        double* un = K.V + (int64_t)(j + 1) * Nv;
+        if (!queued) {
+          do_precond(H, s, pc, o->grouping, uj, K.z);
+          do_apply(H, s, K.z, K.w, false);
+        }
+        queued = false;
+        // the apply's edge sums are added by both passes as they read w
+        const EdgeFix ef = pending_edges(H, 1.0);
+        launch_gs2_dot(s, K.V, Nv, j, uj, K.w, Nv, K.partial, K.hdev, ef);
+        launch_gs2_coef(s, j, K.hdev, K.hdev + kCoef);
+        launch_gs2_update(s, K.V, Nv, j, K.hdev, K.hdev + j, K.hdev + kCoef, uj, K.w, un, Nv, ef);
+        check_launch();
+        SG_HIP(hipMemcpyAsync(hp, K.hdev, (kCoef + 4) * sizeof(double), hipMemcpyDeviceToHost, s));
+        SG_HIP(hipEventRecord(H.fetched, s));
+        if (j + 1 < m && it + 1 < o->max_it) {
+          do_precond(H, s, pc, o->grouping, un, K.z);
+          do_apply(H, s, K.z, K.w, false);
+          queued = true;
+        }
+        SG_HIP(hipEventSynchronize(H.fetched));
+        const double nu = hp[kCoef], cj = hp[kCoef + 1], rho = hp[kCoef + 2];
+        if (!std::isfinite(nu)) {
+          broke = true;
+          return nfinal;
+        }
+        // u_j = nu_j q_j + Q s_j completes column j - 1 (r = beta u_0 = beta nu_0 q_0)
+        if (j == 0)
+          g[0] = beta * nu;
+        else if (nfinal == j - 1)
+          finish_column(j - 1, hp, nu);
+        if (j > 0) {
+          est = std::fabs(g[j]);
+          if (Hat(j - 1, j - 1) == 0.0) {
+            broke = true;
+            return nfinal;
+          }
+        }
+        // nu_j = 0: u_j lies in the span of the basis, the space is exhausted
+        if (nu == 0.0) {
+          if (j == 0) broke = true;
+          return nfinal;
+        }
+        if (!std::isfinite(cj) || !std::isfinite(rho)) {
+          broke = true;
+          return nfinal;
+        }
+        for (int i = 0; i < j; ++i) Smm(i, j) = hp[i];
+        Smm(j, j) = nu;
+        for (int i = 0; i < j; ++i) Htt(i, j) = hp[j + i];
+        Htt(j, j) = cj;
+        av[j] = nu * rho;
+        ++it;
+        est = provisional(j);
+        push_hist(est / nF);
+        if (est <= target || j + 1 == m || it >= o->max_it) {
+          // complete column j: s_{j+1} = Q_{0..j}^T u_{j+1} and |u_{j+1}|^2
+          launch_gs2_dot(s, K.V, Nv, j + 1, un, nullptr, Nv, K.partial, K.hdev + kFin);
+          check_launch();
+          SG_HIP(hipMemcpyAsync(hp + kFin, K.hdev + kFin, (j + 2) * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+          SG_HIP(hipStreamSynchronize(s));
+          double ss = 0.0;
+          for (int i = 0; i <= j; ++i) ss = std::fma(hp[kFin + i], hp[kFin + i], ss);
+          const double nu1 = std::sqrt(hp[kFin + j + 1] - ss);
+          if (!std::isfinite(nu1)) {
+            broke = true;
+            return nfinal;
+          }
+          finish_column(j, hp + kFin, nu1);
+          est = std::fabs(g[j + 1]);
+          if (resid_hist && hist_n - 1 < hist_len) resid_hist[hist_n - 1] = est / nF;
+          if (Hat(j, j) == 0.0) broke = true;
+          if (broke || est <= target || j + 1 == m || it >= o->max_it) return nfinal;
+          // not met after all: go on (the next step's pass A recomputes
+          // s_{j+1}, and column j is not completed twice)
+        }
+      }
+      return nfinal;
+    };
     while (beta > target && it < o->max_it && !broke) {
       std::fill(Hm.begin(), Hm.end(), 0.0);
       std::fill(g.begin(), g.end(), 0.0);
       g[0] = beta;
       launch_axpby(s, 1.0 / beta, K.t, 0.0, K.V, Nv);
       int kdone = 0;
-      // the next step's preconditioner and operator apply (which need only
-      // v_{j+1}, already on the device) are queued before the host waits for
-      // step j's Hessenberg column, so the device keeps working while the host
-      // updates the rotations; wasted once, when step j ends the solve
-      bool queued = false;
-      for (int j = 0; j < m; ++j) {
-        double* vj = K.V + (int64_t)j * Nv;
-        double* zj = K.z;
-        // the main apply's edge sums are added by the first two Gram-Schmidt
-        // passes while they read w (they hold the basis in registers up to 64
-        // vectors)
-        const bool defer = !learned && j + 1 <= 64;
-        if (queued) {
-          queued = false;
-        } else if (learned) {
+      if (!learned) {
+        kdone = linear_cycle();
+      } else {
+        // flexible GMRES (the learned stage is nonlinear): classical
+        // Gram-Schmidt with both projections in the same step
+        for (int j = 0; j < m; ++j) {
+          double* vj = K.V + (int64_t)j * Nv;
           // field split first, then the network's prediction c of the error
           // left in the field-split residual r = v - K P_FS^{-1} v, weighted by
           // alpha = <r, K c> / ||K c||^2 (the residual-minimising step), so the
           // stage's residual never exceeds the field split's; alpha = 0 (plain
           // field split) when the prediction is not finite
-          zj = K.Z + (int64_t)j * Nv;
+          double* zj = K.Z + (int64_t)j * Nv;
           learned_stage(H, s, fs_pc, o->grouping, vj, zj, K.w, K.x2, K.z, K.t, K.partial, K.nblk,
                         K.hdev + 2 * (m + 1) + 1);
-        } else {
-          do_precond(H, s, pc, o->grouping, vj, K.z);
-          do_apply(H, s, zj, K.w, !defer);
-        }
-        const EdgeFix ef = defer ? pending_edges(H, 1.0) : EdgeFix{};
-        double* h1 = K.hdev;
-        double* h2 = K.hdev + (m + 1);
-        double* nrm = K.hdev + 2 * (m + 1);
-        // CGS2: h1 = V^T w, w -= V h1, h2 = V^T w (fused with that update),
-        // w -= V h2 and |w|^2 (fused with the second update), v_{j+1} = w / |w|
-        launch_gs_dot(s, K.V, Nv, j + 1, K.w, Nv, K.partial, h1, ef);
-        launch_gs_update_dot(s, K.V, Nv, j + 1, h1, K.w, Nv, -1.0, K.partial, h2, ef);
-        launch_gs_update_norm_scale(s, K.V, Nv, j + 1, h2, K.w, Nv, -1.0, K.partial, nrm,
-                                    K.V + (int64_t)(j + 1) * Nv);
-        check_launch();
-        // the Hessenberg column and the norm; for the learned stage also its alpha
-        SG_HIP(hipMemcpyAsync(hp, K.hdev, (2 * (m + 1) + (learned ? 4 : 1)) * sizeof(double),
-                              hipMemcpyDeviceToHost, s));
-        SG_HIP(hipEventRecord(H.fetched, s));
-        if (!learned && j + 1 < m && it + 1 < o->max_it) {
-          do_precond(H, s, pc, o->grouping, K.V + (int64_t)(j + 1) * Nv, K.z);
-          do_apply(H, s, K.z, K.w, !(j + 2 <= 64));
-          queued = true;
-        }
-        SG_HIP(hipEventSynchronize(H.fetched));
-        if (learned && hp[2 * (m + 1) + 3] == 0.0) ++fallbacks;
-        for (int i = 0; i <= j; ++i) Hat(i, j) = hp[i] + hp[m + 1 + i];
-        Hat(j + 1, j) = std::sqrt(hp[2 * (m + 1)]);
-        if (!std::isfinite(Hat(j + 1, j))) {
-          broke = true;
-          break;
-        }
-        for (int i = 0; i < j; ++i) {
-          double tmp = cs[i] * Hat(i, j) + sn[i] * Hat(i + 1, j);
-          Hat(i + 1, j) = -sn[i] * Hat(i, j) + cs[i] * Hat(i + 1, j);
-          Hat(i, j) = tmp;
-        }
-        double a = Hat(j, j), b = Hat(j + 1, j);
-        if (b == 0.0) {
-          cs[j] = 1.0;
-          sn[j] = 0.0;
-        } else {
-          double r = std::hypot(a, b);
-          cs[j] = a / r;
-          sn[j] = b / r;
-        }
-        Hat(j, j) = cs[j] * a + sn[j] * b;
-        Hat(j + 1, j) = 0.0;
-        g[j + 1] = -sn[j] * g[j];
-        g[j] = cs[j] * g[j];
-        ++it;
-        kdone = j + 1;
-        est = std::fabs(g[j + 1]);
-        push_hist(est / nF);
-        if (est <= target || it >= o->max_it) break;
-        if (Hat(j, j) == 0.0) {
-          broke = true;
-          break;
+          double* h1 = K.hdev;
+          double* h2 = K.hdev + (m + 1);
+          double* nrm = K.hdev + 2 * (m + 1);
+          // CGS2: h1 = V^T w, w -= V h1, h2 = V^T w (fused with that update),
+          // w -= V h2 and |w|^2 (fused with the second update), v_{j+1} = w / |w|
+          launch_gs_dot(s, K.V, Nv, j + 1, K.w, Nv, K.partial, h1);
+          launch_gs_update_dot(s, K.V, Nv, j + 1, h1, K.w, Nv, -1.0, K.partial, h2);
+          launch_gs_update_norm_scale(s, K.V, Nv, j + 1, h2, K.w, Nv, -1.0, K.partial, nrm,
+                                      K.V + (int64_t)(j + 1) * Nv);
+          check_launch();
+          // the Hessenberg column and the norm; for the learned stage also its alpha
+          SG_HIP(hipMemcpyAsync(hp, K.hdev, (2 * (m + 1) + 4) * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+          SG_HIP(hipEventRecord(H.fetched, s));
+          SG_HIP(hipEventSynchronize(H.fetched));
+          if (hp[2 * (m + 1) + 3] == 0.0) ++fallbacks;
+          for (int i = 0; i <= j; ++i) Hat(i, j) = hp[i] + hp[m + 1 + i];
+          Hat(j + 1, j) = std::sqrt(hp[2 * (m + 1)]);
+          if (!std::isfinite(Hat(j + 1, j))) {
+            broke = true;
+            break;
+          }
+          rotate_column(j);
+          ++it;
+          kdone = j + 1;
+          est = std::fabs(g[j + 1]);
+          push_hist(est / nF);
+          if (est <= target || it >= o->max_it) break;
+          if (Hat(j, j) == 0.0) {
+            broke = true;
+            break;
+          }
         }
       }
       if (kdone == 0) break;
@@ -1802,7 +1919,16 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
         for (int l = i + 1; l < kdone; ++l) acc -= Hat(i, l) * y[l];
         y[i] = acc / Hat(i, i);
       }
-      for (int i = 0; i < kdone; ++i) hp[i] = y[i];
+      if (learned) {
+        for (int i = 0; i < kdone; ++i) hp[i] = y[i];
+      } else {
+        // the correction in the vectors the operator was applied to: U y = Q (S y)
+        for (int i = 0; i < kdone; ++i) {
+          double acc = 0.0;
+          for (int l = i; l < kdone; ++l) acc += Smm(i, l) * y[l];
+          hp[i] = acc;
+        }
+      }
       SG_HIP(hipMemcpyAsync(K.ydev, hp, kdone * sizeof(double), hipMemcpyHostToDevice, s));
       if (learned) {
         launch_combine(s, K.Z, Nv, kdone, K.ydev, K.t, Nv);
@@ -2491,7 +2617,11 @@ int sg_autotune_apply(const sg_problem* prob, int32_t* best_form, float* best_ms
   try {
     validate(*prob);
     *best_form = tune_apply(*prob, best_ms);
-    return *best_form > 0 ? SG_OK : fail(SG_ERR_HIP, "no candidate could be timed");
+    if (*best_form <= 0) return fail(SG_ERR_HIP, "no candidate could be timed");
+    std::map<std::string, int> cache = tune_load();
+    cache[tune_key(*prob)] = *best_form;
+    tune_store(cache);
+    return SG_OK;
   } catch (const Error& e) {
     return fail(e.code, e.what());
   }

@@ -284,6 +284,19 @@ void launch_gs_update_dot(hipStream_t s, const double* V, int64_t ldv, int nv, c
 void launch_gs_update_norm_scale(hipStream_t s, const double* V, int64_t ldv, int nv,
                                  const double* h, double* w, int64_t N, double sign,
                                  double* partial, double* nrm2, double* vnext);
+// Gram-Schmidt with the second projection delayed by one step: pass A
+// (out = Q^T u, Q^T w, u.u, u.w, w.w over nv basis vectors; without w:
+// Q^T u, u.u), its coefficients (nu, c_j, rho, raw |w - Q c|^2), pass B
+// (q_j in place of u_j, u_{j+1}); partial sized gs2_partial_doubles(nv)
+int gs2_dot_slots(int nv, bool with_w);
+size_t gs2_partial_doubles(int max_nv);
+void launch_gs2_dot(hipStream_t s, const double* Q, int64_t ldq, int nv, const double* u,
+                    const double* w, int64_t N, double* partial, double* out,
+                    const EdgeFix& ef = EdgeFix{});
+void launch_gs2_coef(hipStream_t s, int nv, const double* dots, double* coef);
+void launch_gs2_update(hipStream_t s, const double* Q, int64_t ldq, int nv, const double* sv,
+                       const double* tv, const double* coef, double* uq, const double* w,
+                       double* unext, int64_t N, const EdgeFix& ef = EdgeFix{});
 void launch_combine(hipStream_t s, const double* V, int64_t ldv, int nv, const double* y,
                     double* out, int64_t N);
 void launch_scale_by_inv_norm(hipStream_t s, const double* w, const double* nrm2, double* v,

@@ -1323,6 +1323,153 @@ void launch_gs_update_norm_scale(hipStream_t s, const double* V, int64_t ldv, in
                      nrm2, vnext, N);
 }
 
+// ---------------------------------------------------------------------------
+// Gram-Schmidt with the second projection delayed by one step (two passes over
+// the basis per Arnoldi step instead of three).  At step j the basis holds
+// orthonormal q_0..q_{j-1} and, in slot j, u_j: the previous step's vector
+// after one projection.  With w the operator applied to u_j:
+//   pass A   s = Q^T u_j, t = Q^T w, u_j.u_j, u_j.w, w.w      (one read of Q)
+//   coefs    nu = |u_j - Q s|, c_j = q_j . w, rho = |w - Q_{0..j} c| / nu
+//            (by Pythagoras, with c = (t, c_j))
+//   pass B   q_j = (u_j - Q s) / nu            (slot j, in place)
+//            u_{j+1} = (w - Q t - c_j q_j) / (nu rho)       (slot j + 1)
+// so q_j receives its second projection one step late, and u_{j+1} its first.
+// The host keeps the Arnoldi relation exact by expressing each step in the
+// vectors it actually applied the operator to (u_j = nu_j q_j + Q s_j).
+// ---------------------------------------------------------------------------
+constexpr int kPassVecs = 16;
+
+int gs2_dot_slots(int nv, bool with_w) { return with_w ? 2 * nv + 3 : nv + 1; }
+size_t gs2_partial_doubles(int max_nv) {
+  return (size_t)gs2_dot_slots(max_nv, true) * kStreamBlocks;
+}
+
+// Block partials of Q_l . u (slot l < nv), Q_l . w (slot nv + l) and, from the
+// first row of blocks, u.u, u.w, w.w (slots 2 nv .. 2 nv + 2; without w only
+// Q_l . u and u.u at slot nv).  Grid-stride over elements, kPassVecs basis
+// vectors per block row.
+__global__ __launch_bounds__(kDotThreads) void gs2_dot_kernel(
+    const double* __restrict__ Q, int64_t ldq, int nv, const double* __restrict__ u,
+    const double* __restrict__ w, int64_t N, double* __restrict__ partial, EdgeFix ef) {
+  __shared__ double red[4 * 64];
+  const int l0 = kPassVecs * blockIdx.y;
+  const int cnt = max(0, min(nv - l0, kPassVecs));
+  const bool extras = blockIdx.y == 0;
+  const bool hasw = w != nullptr;
+  const double* Qb = Q + (int64_t)l0 * ldq;
+  double acc[64];
+#pragma unroll
+  for (int k = 0; k < 64; ++k) acc[k] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kDotThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kDotThreads) {
+    const double ui = u[i];
+    const double wi = hasw ? w_fixed(w, i, ef) : 0.0;
+    double a[kPassVecs];
+#pragma unroll
+    for (int l = 0; l < kPassVecs; ++l) a[l] = l < cnt ? Qb[(int64_t)l * ldq + i] : 0.0;
+#pragma unroll
+    for (int l = 0; l < kPassVecs; ++l) {
+      acc[l] = fma(a[l], ui, acc[l]);
+      acc[kPassVecs + l] = fma(a[l], wi, acc[kPassVecs + l]);
+    }
+    if (extras) {
+      acc[2 * kPassVecs] = fma(ui, ui, acc[2 * kPassVecs]);
+      acc[2 * kPassVecs + 1] = fma(ui, wi, acc[2 * kPassVecs + 1]);
+      acc[2 * kPassVecs + 2] = fma(wi, wi, acc[2 * kPassVecs + 2]);
+    }
+  }
+  wave_sums<64>(acc, red + 64 * (threadIdx.x >> 6));
+  __syncthreads();
+  const int k = threadIdx.x;
+  if (k >= 64) return;
+  int slot = -1;
+  if (k < kPassVecs) {
+    if (k < cnt) slot = l0 + k;
+  } else if (k < 2 * kPassVecs) {
+    if (hasw && k - kPassVecs < cnt) slot = nv + l0 + (k - kPassVecs);
+  } else if (extras && k < 2 * kPassVecs + 3) {
+    const int e = k - 2 * kPassVecs;
+    if (e == 0 || hasw) slot = (hasw ? 2 * nv : nv) + e;
+  }
+  if (slot >= 0)
+    partial[(int64_t)slot * gridDim.x + blockIdx.x] = (red[k] + red[64 + k]) + (red[128 + k] + red[192 + k]);
+}
+
+void launch_gs2_dot(hipStream_t s, const double* Q, int64_t ldq, int nv, const double* u,
+                    const double* w, int64_t N, double* partial, double* out, const EdgeFix& ef) {
+  const int nb = std::min(gs_blocks(N), kStreamBlocks);
+  const int ny = std::max(1, cdiv(nv, kPassVecs));
+  hipLaunchKernelGGL(gs2_dot_kernel, dim3(nb, ny), dim3(kDotThreads), 0, s, Q, ldq, nv, u, w, N,
+                     partial, ef);
+  hipLaunchKernelGGL(reduce_wide_kernel, dim3(gs2_dot_slots(nv, w != nullptr)), dim3(kDotThreads),
+                     0, s, partial, nb, out);
+}
+
+// coef[0] = nu, coef[1] = c_j, coef[2] = rho, coef[3] = |w - Q c|^2 before the
+// floor, from dots = (s, t, u.u, u.w, w.w) of pass A; the sums run in index
+// order.  rho^2 is floored at 1e-28 w.w / nu^2 so that a cancelled Pythagorean
+// difference only mis-scales u_{j+1} (the next step measures its norm).
+__global__ void gs2_coef_kernel(int nv, const double* __restrict__ dots, double* __restrict__ coef) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double* sv = dots;
+  const double* tv = dots + nv;
+  double ss = 0.0, st = 0.0, tt = 0.0;
+  for (int l = 0; l < nv; ++l) {
+    ss = fma(sv[l], sv[l], ss);
+    st = fma(sv[l], tv[l], st);
+    tt = fma(tv[l], tv[l], tt);
+  }
+  const double uu = dots[2 * nv], uw = dots[2 * nv + 1], ww = dots[2 * nv + 2];
+  const double nu = sqrt(uu - ss);
+  const double cj = (uw - st) / nu;
+  const double r2 = ww - tt - cj * cj;
+  const double rho = sqrt(fmax(r2, 1e-28 * ww)) / nu;
+  coef[0] = nu;
+  coef[1] = cj;
+  coef[2] = rho;
+  coef[3] = r2;
+}
+
+void launch_gs2_coef(hipStream_t s, int nv, const double* dots, double* coef) {
+  hipLaunchKernelGGL(gs2_coef_kernel, dim3(1), dim3(64), 0, s, nv, dots, coef);
+}
+
+// pass B, one element per thread: q_j = (u_j - Q s) / nu in place of u_j, then
+// u_{j+1} = (w - Q t - c_j q_j) / (nu rho); the basis values of a chunk of
+// kPassVecs vectors are loaded together and serve both sums
+__global__ __launch_bounds__(kDotThreads) void gs2_update_kernel(
+    const double* __restrict__ Q, int64_t ldq, int nv, const double* __restrict__ sv,
+    const double* __restrict__ tv, const double* __restrict__ coef, double* __restrict__ uq,
+    const double* __restrict__ w, double* __restrict__ unext, int64_t N, EdgeFix ef) {
+  const int64_t i = (int64_t)blockIdx.x * kDotThreads + threadIdx.x;
+  if (i >= N) return;
+  double as = 0.0, at = 0.0;
+  for (int l0 = 0; l0 < nv; l0 += kPassVecs) {
+    const int cnt = min(nv - l0, kPassVecs);
+    double a[kPassVecs];
+#pragma unroll
+    for (int l = 0; l < kPassVecs; ++l) a[l] = l < cnt ? Q[(int64_t)(l0 + l) * ldq + i] : 0.0;
+#pragma unroll
+    for (int l = 0; l < kPassVecs; ++l) {
+      if (l < cnt) {
+        as = fma(sv[l0 + l], a[l], as);
+        at = fma(tv[l0 + l], a[l], at);
+      }
+    }
+  }
+  const double nu = coef[0], cj = coef[1], rho = coef[2];
+  const double q = (uq[i] - as) / nu;
+  uq[i] = q;
+  unext[i] = (w_fixed(w, i, ef) - at - cj * q) / (nu * rho);
+}
+
+void launch_gs2_update(hipStream_t s, const double* Q, int64_t ldq, int nv, const double* sv,
+                       const double* tv, const double* coef, double* uq, const double* w,
+                       double* unext, int64_t N, const EdgeFix& ef) {
+  hipLaunchKernelGGL(gs2_update_kernel, dim3(gs_blocks(N)), dim3(kDotThreads), 0, s, Q, ldq, nv,
+                     sv, tv, coef, uq, w, unext, N, ef);
+}
+
 // out = sum_l y[l] V_l
 __global__ void combine_kernel(const double* __restrict__ V, int64_t ldv, int nv,
                                const double* __restrict__ y, double* __restrict__ out, int64_t N) {
