@@ -731,6 +731,8 @@ EdgeFix pending_edges(const sg_handle& H, double sgn) {
   f.sgn = sgn;
   f.Nh = H.Nh;
   f.m = H.n - 1;
+  f.rNh = recip64((uint64_t)f.Nh);
+  f.rm = recip64((uint64_t)f.m);
   return f;
 }
 

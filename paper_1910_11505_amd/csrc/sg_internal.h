@@ -174,7 +174,15 @@ struct EdgeFix {
   double sgn = 1.0;   // sign the sums enter the output with
   int64_t Nh = 0;     // vector length (node count) of one output vector
   int m = 0;          // interior nodes per side
+  uint64_t rNh = 0;   // recip64(Nh) and recip64(m), for w_fixed's divisions
+  uint64_t rm = 0;
 };
+
+// ceil(2^64 / d) for 2 <= d < 2^32 (2^(64 - t) when d = 2^t): with it the high
+// 64 bits of x * recip64(d) equal x / d for every x < 2^32 (with
+// recip64(d) d = 2^64 + e, 0 <= e < d, the product overshoots x / d by
+// x e / (d 2^64) < 1 / d, too little to reach the next integer)
+inline uint64_t recip64(uint64_t d) { return ~uint64_t(0) / d + 1; }
 
 __device__ __forceinline__ double edge_fixed(double v, const EdgeFix& f, int slot, int gx, int gy) {
   const int nx = gx & 3, ny = gy & 3;
@@ -188,13 +196,13 @@ __device__ __forceinline__ double edge_fixed(double v, const EdgeFix& f, int slo
 }
 
 // element i of a vector of output vectors (vector i / Nh, node i % Nh) with
-// its pending edge sums added
+// its pending edge sums added; i < P N_h < 2^32 (P <= 256, N_h < 4096^2)
 __device__ __forceinline__ double w_fixed(const double* __restrict__ w, int64_t i, const EdgeFix& f) {
   double v = w[i];
   if (f.edge) {
-    const unsigned ii = (unsigned)i, nh = (unsigned)f.Nh, mm = (unsigned)f.m;
-    const unsigned slot = ii / nh, node = ii - slot * nh;
-    const unsigned gy = node / mm, gx = node - gy * mm;
+    const uint64_t ii = (uint64_t)i;
+    const uint64_t slot = __umul64hi(ii, f.rNh), node = ii - slot * (uint64_t)f.Nh;
+    const uint64_t gy = __umul64hi(node, f.rm), gx = node - gy * (uint64_t)f.m;
     v = edge_fixed(v, f, (int)slot, (int)gx + 1, (int)gy + 1);
   }
   return v;

@@ -1339,56 +1339,83 @@ void launch_gs_update_norm_scale(hipStream_t s, const double* V, int64_t ldv, in
 // ---------------------------------------------------------------------------
 constexpr int kPassVecs = 16;
 
+// Shape of pass A for nv basis vectors: VB vectors per block row, U elements
+// per thread and loop iteration, at most `blocks` blocks per row.  Few basis
+// vectors leave a thread few loads per iteration, so those shapes take more
+// elements per iteration and more blocks.
+struct Gs2Shape {
+  int vb, u, blocks;
+};
+Gs2Shape gs2_shape(int nv) {
+  if (nv <= 4) return {4, 4, 2048};
+  if (nv <= 8) return {8, 2, 1024};
+  if (nv <= 16) return {16, 1, 1024};
+  return {16, 1, kStreamBlocks};
+}
+
 int gs2_dot_slots(int nv, bool with_w) { return with_w ? 2 * nv + 3 : nv + 1; }
 size_t gs2_partial_doubles(int max_nv) {
-  return (size_t)gs2_dot_slots(max_nv, true) * kStreamBlocks;
+  size_t most = 0;
+  for (int nv = 0; nv <= max_nv; ++nv)
+    most = std::max(most, (size_t)gs2_dot_slots(nv, true) * gs2_shape(nv).blocks);
+  return most;
 }
 
 // Block partials of Q_l . u (slot l < nv), Q_l . w (slot nv + l) and, from the
 // first row of blocks, u.u, u.w, w.w (slots 2 nv .. 2 nv + 2; without w only
-// Q_l . u and u.u at slot nv).  Grid-stride over elements, kPassVecs basis
-// vectors per block row.
+// Q_l . u and u.u at slot nv).  Grid-stride over elements, VB basis vectors
+// per block row, U elements per iteration.
+template <int VB, int U>
 __global__ __launch_bounds__(kDotThreads) void gs2_dot_kernel(
     const double* __restrict__ Q, int64_t ldq, int nv, const double* __restrict__ u,
     const double* __restrict__ w, int64_t N, double* __restrict__ partial, EdgeFix ef) {
+  constexpr int NA = 2 * VB + 3 <= 16 ? 16 : 2 * VB + 3 <= 32 ? 32 : 64;
   __shared__ double red[4 * 64];
-  const int l0 = kPassVecs * blockIdx.y;
-  const int cnt = max(0, min(nv - l0, kPassVecs));
+  const int l0 = VB * blockIdx.y;
+  const int cnt = max(0, min(nv - l0, VB));
   const bool extras = blockIdx.y == 0;
   const bool hasw = w != nullptr;
   const double* Qb = Q + (int64_t)l0 * ldq;
-  double acc[64];
+  double acc[NA];
 #pragma unroll
-  for (int k = 0; k < 64; ++k) acc[k] = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kDotThreads + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * kDotThreads) {
-    const double ui = u[i];
-    const double wi = hasw ? w_fixed(w, i, ef) : 0.0;
-    double a[kPassVecs];
+  for (int k = 0; k < NA; ++k) acc[k] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kDotThreads;
+  for (int64_t i0 = (int64_t)blockIdx.x * kDotThreads + threadIdx.x; i0 < N; i0 += U * stride) {
+    double ui[U], wi[U], a[U][VB];
 #pragma unroll
-    for (int l = 0; l < kPassVecs; ++l) a[l] = l < cnt ? Qb[(int64_t)l * ldq + i] : 0.0;
+    for (int e = 0; e < U; ++e) {
+      const int64_t i = i0 + e * stride;
+      const bool in = i < N;
+      ui[e] = in ? u[i] : 0.0;
+      wi[e] = in && hasw ? w_fixed(w, i, ef) : 0.0;
 #pragma unroll
-    for (int l = 0; l < kPassVecs; ++l) {
-      acc[l] = fma(a[l], ui, acc[l]);
-      acc[kPassVecs + l] = fma(a[l], wi, acc[kPassVecs + l]);
+      for (int l = 0; l < VB; ++l) a[e][l] = in && l < cnt ? Qb[(int64_t)l * ldq + i] : 0.0;
     }
-    if (extras) {
-      acc[2 * kPassVecs] = fma(ui, ui, acc[2 * kPassVecs]);
-      acc[2 * kPassVecs + 1] = fma(ui, wi, acc[2 * kPassVecs + 1]);
-      acc[2 * kPassVecs + 2] = fma(wi, wi, acc[2 * kPassVecs + 2]);
+#pragma unroll
+    for (int e = 0; e < U; ++e) {
+#pragma unroll
+      for (int l = 0; l < VB; ++l) {
+        acc[l] = fma(a[e][l], ui[e], acc[l]);
+        acc[VB + l] = fma(a[e][l], wi[e], acc[VB + l]);
+      }
+      if (extras) {
+        acc[2 * VB] = fma(ui[e], ui[e], acc[2 * VB]);
+        acc[2 * VB + 1] = fma(ui[e], wi[e], acc[2 * VB + 1]);
+        acc[2 * VB + 2] = fma(wi[e], wi[e], acc[2 * VB + 2]);
+      }
     }
   }
-  wave_sums<64>(acc, red + 64 * (threadIdx.x >> 6));
+  wave_sums<NA>(acc, red + 64 * (threadIdx.x >> 6));
   __syncthreads();
   const int k = threadIdx.x;
-  if (k >= 64) return;
+  if (k >= NA) return;
   int slot = -1;
-  if (k < kPassVecs) {
+  if (k < VB) {
     if (k < cnt) slot = l0 + k;
-  } else if (k < 2 * kPassVecs) {
-    if (hasw && k - kPassVecs < cnt) slot = nv + l0 + (k - kPassVecs);
-  } else if (extras && k < 2 * kPassVecs + 3) {
-    const int e = k - 2 * kPassVecs;
+  } else if (k < 2 * VB) {
+    if (hasw && k - VB < cnt) slot = nv + l0 + (k - VB);
+  } else if (extras && k < 2 * VB + 3) {
+    const int e = k - 2 * VB;
     if (e == 0 || hasw) slot = (hasw ? 2 * nv : nv) + e;
   }
   if (slot >= 0)
@@ -1397,12 +1424,18 @@ __global__ __launch_bounds__(kDotThreads) void gs2_dot_kernel(
 
 void launch_gs2_dot(hipStream_t s, const double* Q, int64_t ldq, int nv, const double* u,
                     const double* w, int64_t N, double* partial, double* out, const EdgeFix& ef) {
-  const int nb = std::min(gs_blocks(N), kStreamBlocks);
-  const int ny = std::max(1, cdiv(nv, kPassVecs));
-  hipLaunchKernelGGL(gs2_dot_kernel, dim3(nb, ny), dim3(kDotThreads), 0, s, Q, ldq, nv, u, w, N,
-                     partial, ef);
-  hipLaunchKernelGGL(reduce_wide_kernel, dim3(gs2_dot_slots(nv, w != nullptr)), dim3(kDotThreads),
-                     0, s, partial, nb, out);
+  const Gs2Shape sh = gs2_shape(nv);
+  const int nb = std::min(gs_blocks(N), sh.blocks);
+  const int ny = std::max(1, cdiv(nv, sh.vb));
+  const dim3 grid(nb, ny), block(kDotThreads);
+  if (sh.vb == 4)
+    hipLaunchKernelGGL((gs2_dot_kernel<4, 4>), grid, block, 0, s, Q, ldq, nv, u, w, N, partial, ef);
+  else if (sh.vb == 8)
+    hipLaunchKernelGGL((gs2_dot_kernel<8, 2>), grid, block, 0, s, Q, ldq, nv, u, w, N, partial, ef);
+  else
+    hipLaunchKernelGGL((gs2_dot_kernel<16, 1>), grid, block, 0, s, Q, ldq, nv, u, w, N, partial, ef);
+  hipLaunchKernelGGL(reduce_wide_kernel, dim3(gs2_dot_slots(nv, w != nullptr)), block, 0, s,
+                     partial, nb, out);
 }
 
 // coef[0] = nu, coef[1] = c_j, coef[2] = rho, coef[3] = |w - Q c|^2 before the
