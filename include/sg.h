@@ -371,9 +371,9 @@ int    sg_batch_handle(sg_batch* b, int32_t i, sg_handle** h);
  * the one-at-a-time solves below, the lockstep part keeps the A_0 cycles); F, u packed device vectors;
  * infos: count entries.  Graph capture needs a non-null stream (the null
  * stream runs the same launch sequences eagerly).  On a non-null stream,
- * instances of at least 2^20 unknowns (P*N_h) are solved one at a time by
- * sg_gmres_solve on a second stream, from a host thread, beside the lockstep
- * batch of the others.  At a restart that leaves at most four lockstep
+ * instances of at least 2^20 unknowns (P*N_h) are solved by sg_gmres_solve,
+ * up to three at a time (largest first, each from a host thread on a stream
+ * of its own), beside the lockstep batch of the others.  At a restart that leaves at most four lockstep
  * instances running, those continue one at a time through sg_gmres_solve
  * from their current iterate; their infos add both parts.  The batch
  * workspace reserves the Krylov areas of both.  Synchronous.               */

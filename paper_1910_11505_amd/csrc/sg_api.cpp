@@ -1,6 +1,7 @@
 // C ABI of the SG solver: handle life cycle, workspace layout, operator and
 // preconditioner applies, and the restarted GMRES driver.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -2084,7 +2085,8 @@ struct sg_batch {
   BItem* dItems = nullptr;
   size_t item_cap = 0;
   BState* hS = nullptr;  // pinned
-  char* solo_ws = nullptr;  // Krylov workspace of the instances solved one at a time
+  char* solo_ws = nullptr;  // Krylov workspaces (kSoloStreams of solo_bytes) of the
+                            // instances solved one at a time
   size_t solo_bytes = 0;
   char* tail_ws = nullptr;  // ... of the lockstep instances that finish one at a time
   size_t tail_bytes = 0;
@@ -2104,9 +2106,12 @@ namespace {
 constexpr size_t kBatchItemCap = 1 << 24;  // work items of all tables of one plan
 constexpr int kBatchTail = 4;  // instances left when a solve continues them one at a time
 // instances with at least this many unknowns fill the chip with their own
-// kernels: a batched solve on a stream runs them one at a time beside the
-// lockstep batch of the others
+// kernels: a batched solve on a stream runs them through the single-instance
+// solver beside the lockstep batch of the others, kSoloStreams at a time
+// (their kernels are short enough that one instance alone leaves the chip
+// idle between launches)
 constexpr int64_t kBatchSoloUnknowns = int64_t(1) << 20;
+constexpr int kSoloStreams = 3;
 
 int cdivi(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
@@ -2154,7 +2159,8 @@ size_t batch_layout(sg_batch& B, char* base) {
     solo = std::max(solo, kb);
     if ((int64_t)B.h[i]->P * B.h[i]->Nh < kBatchSoloUnknowns) tail = std::max(tail, kb);
   }
-  char* sw = c.take<char>(solo);
+  solo = (solo + 255) & ~size_t(255);  // each of the kSoloStreams areas 256-byte aligned
+  char* sw = c.take<char>(solo * kSoloStreams);
   char* tw = c.take<char>(tail);
   if (base) {
     B.solo_ws = sw;
@@ -2805,31 +2811,61 @@ int sg_batch_solve(sg_batch* b, const sg_solve_opts* o, const double* F, double*
     }
     SG_HIP(hipMemcpyAsync(B.dS, B.hS, sizeof(BState) * B.count, hipMemcpyHostToDevice, s));
     SG_HIP(hipStreamSynchronize(s));
-    // the solo instances' solves, on a thread of their own (joined on every
-    // way out of this call)
+    // the solo instances' solves: up to kSoloStreams host threads, each with
+    // a stream (default priority) and a Krylov area of its own, take the
+    // instances largest first from a shared counter (joined on every way out
+    // of this call)
     std::vector<sg_solve_info> solo_info(B.count);
-    int solo_rc = SG_OK;
+    std::atomic<int> solo_rc{SG_OK};
+    std::atomic<int> solo_next{0};
+    std::mutex solo_mu;
     std::string solo_err;
-    hipStream_t s2 = nullptr;
-    std::thread solo_thread;
+    std::vector<int> solo_order;
+    for (int i = 0; i < B.count; ++i)
+      if (solo[i]) solo_order.push_back(i);
+    std::stable_sort(solo_order.begin(), solo_order.end(), [&](int a, int b) {
+      return (int64_t)B.h[a]->P * B.h[a]->Nh > (int64_t)B.h[b]->P * B.h[b]->Nh;
+    });
+    std::vector<hipStream_t> s2;
+    std::vector<std::thread> solo_threads;
     struct Joiner {
-      std::thread& t;
-      hipStream_t& st;
+      std::vector<std::thread>& t;
+      std::vector<hipStream_t>& st;
       ~Joiner() {
-        if (t.joinable()) t.join();
-        if (st) (void)hipStreamDestroy(st);
+        for (auto& th : t)
+          if (th.joinable()) th.join();
+        for (hipStream_t x : st) (void)hipStreamDestroy(x);
       }
-    } joiner{solo_thread, s2};
-    if (nsolo > 0) {
-      SG_HIP(hipStreamCreate(&s2));
-      solo_thread = std::thread([&]() {
-        for (int i = 0; i < B.count && solo_rc == SG_OK; ++i) {
-          if (!solo[i]) continue;
+    } joiner{solo_threads, s2};
+    const int nthreads = std::min(nsolo, kSoloStreams);
+    for (int k = 0; k < nthreads; ++k) {
+      hipStream_t x = nullptr;
+      SG_HIP(hipStreamCreate(&x));
+      s2.push_back(x);
+    }
+    int dev = 0;
+    SG_HIP(hipGetDevice(&dev));
+    for (int k = 0; k < nthreads; ++k) {
+      solo_threads.emplace_back([&, k]() {
+        if (hipSetDevice(dev) != hipSuccess) {
+          solo_rc = SG_ERR_HIP;
+          return;
+        }
+        char* ws = B.solo_ws + (size_t)k * B.solo_bytes;
+        for (;;) {
+          const int t = solo_next.fetch_add(1);
+          if (t >= nsolo || solo_rc.load() != SG_OK) return;
+          const int i = solo_order[t];
           sg_solve_opts oi = *o;
           oi.use_x0 = 0;
-          solo_rc = sg_gmres_solve(B.h[i], &oi, F + B.voff[i], u + B.voff[i], B.solo_ws,
-                                   B.solo_bytes, nullptr, 0, &solo_info[i], s2);
-          if (solo_rc != SG_OK) solo_err = sg_last_error();
+          const int rc = sg_gmres_solve(B.h[i], &oi, F + B.voff[i], u + B.voff[i], ws,
+                                        B.solo_bytes, nullptr, 0, &solo_info[i], s2[k]);
+          if (rc != SG_OK) {
+            std::lock_guard<std::mutex> lk(solo_mu);
+            if (solo_rc.load() == SG_OK) solo_err = sg_last_error();
+            solo_rc = rc;
+            return;
+          }
         }
       });
     }
@@ -2926,8 +2962,9 @@ int sg_batch_solve(sg_batch* b, const sg_solve_opts* o, const double* F, double*
         live_at_build = nlive;
       }
     }
-    if (solo_thread.joinable()) solo_thread.join();
-    if (solo_rc != SG_OK) return fail(solo_rc, "solo instance: " + solo_err);
+    for (auto& th : solo_threads)
+      if (th.joinable()) th.join();
+    if (solo_rc.load() != SG_OK) return fail(solo_rc.load(), "solo instance: " + solo_err);
     for (int i = 0; i < B.count; ++i) {
       const BState& st = B.hS[i];
       sg_solve_info& inf = infos[i];

@@ -3,7 +3,8 @@ SG_PC_LEARNED) against the oracle's composition z = P_FS^{-1} v + alpha c
 (oracle.learned.stage), with the field split (A_0 or K_ii blocks) from the
 oracle, alpha from the oracle, and the network's prediction c taken from the
 GPU: the same kernels the stage runs (field split, residual, network in SG
-units), called one by one through the C ABI.  Bar: 1e-12 relative (max-norm)."""
+units), called one by one through the C ABI.  Bar: 1e-12 relative (max-norm);
+and the stage's one-step residual |v - K z| is at most the field split's."""
 import numpy as np
 import pytest
 
@@ -69,6 +70,12 @@ def test_learned_stage_matches_oracle(name, kii, c0):
     print(f"[learned stage {name}] alpha {alpha:.3e}", flush=True)
     assert alpha != 0.0
     assert relmax(z, zo) < 1e-12
+    # the stage never leaves a larger one-step residual than the field split
+    # alone (alpha minimises |v - K(z0 + alpha c)|), by the oracle's operator
+    r_fs = np.linalg.norm(v - S.apply(to_host(z0)))
+    r_st = np.linalg.norm(v - S.apply(z))
+    print(f"[learned stage {name}] one-step residual FS {r_fs:.6e}, stage {r_st:.6e}", flush=True)
+    assert r_st <= r_fs * (1 + 1e-12)
     G.attach(None, 0.0)
     net.close()
     G.close()
