@@ -48,9 +48,9 @@ MG_GROUPING = "fg"
 # scaled by the same counter read on a plain 256 MiB device copy.  Valid only
 # for the kernel source the counters were taken on: the sha256 of
 # sg_rapply.hip + sg_kernels.hip + sg_internal.h is compared at run time.
-APPLY_TRAFFIC = {"src_sha256": "56493c8c7829fd4c3f50e8c931388c840e620ac4e4793fd1170a0c97855173a5",
-                 "fetch_bytes": (29125.52 + 48457.77) * 1024 * 2.0,
-                 "write_bytes": (68782.88 + 42606.44) * 1024 * 1.0}
+APPLY_TRAFFIC = {"src_sha256": "82d1dc78a8508d7fe5c3dac17fe5e3b9062c3308e2476a4b6323496080c5270d",
+                 "fetch_bytes": (29035.91 + 48457.77) * 1024 * 2.0,
+                 "write_bytes": (68837.72 + 42606.46) * 1024 * 1.0}
 
 
 def _src_hash():
