@@ -349,14 +349,19 @@ def cnn_rates(net, store, batch, stream):
     return out
 
 
-def learned_comparison(npairs, steps, draws, stream, gen_problems=400):
+def learned_comparison(npairs, steps, draws, stream, gen_problems=400, objectives=("error",)):
     """The learned workload (Q1 128x128, M=4, p=3, squared-exponential L_c=0.5,
-    sigma ~ U[0.3, 1.5], nodal-noise forcing) with a reduced training budget:
-    pairs from field-split GMRES(5) cycles (K_ii blocks), Adam training on the
-    GPU, then flexible GMRES(30) with the learned stage (K_ii field split
-    inside) against field-split GMRES(50) with K_ii blocks on held-out draws,
-    both to the FP64 true relative residual 1e-8; the learned stage also in
-    flexible GMRES(50), for a comparison at equal restart lengths."""
+    sigma ~ U[0.3, 1.5], nodal-noise forcing): pairs from field-split GMRES(5)
+    cycles (K_ii blocks), Adam training on the GPU, then flexible GMRES(30)
+    with the learned stage (K_ii field split inside) against field-split
+    GMRES(50) with K_ii blocks on held-out draws, both to the FP64 true
+    relative residual 1e-8; the learned stage also in flexible GMRES(50), for
+    a comparison at equal restart lengths.  Each objective trains its own
+    network from the same initial weights on the same pairs: "error" (the
+    relative squared error against the stored errors) or "stage" (the share of
+    the residual the stage's step leaves, which needs each pair's operator:
+    the training problems' sigma is taken on a grid of 16 values, one bound
+    operator per value; the held-out draws keep continuous sigma)."""
     import numpy as np
     import paper_1910_11505_amd as sg
     from paper_1910_11505_amd import learned as L
@@ -365,41 +370,59 @@ def learned_comparison(npairs, steps, draws, stream, gen_problems=400):
     probe = L.make_instance(base)
     P, Nh = probe.P, probe.Nh
     probe.close()
-    net = sg.CNN(P, base.n, max_batch=16, c0=64, c1=64)
+    grid = np.linspace(0.3, 1.5, 16)
+    problems = [(p.with_(sigma=float(grid[np.abs(grid - p.sigma).argmin()])), f)
+                for p, f in learned_problems(base, gen_problems, 11505 + 4000)]
     Ws, bs = cnn_init(P, 1, c0=64, c1=64)
+    net = sg.CNN(P, base.n, max_batch=16, c0=64, c1=64)
     net.set_params(Ws, bs)
     store = L.PairStore(npairs, P, Nh)
     t0 = time.perf_counter()
-    gen = L.generate_pairs(net, learned_problems(base, gen_problems, 11505 + 4000), store, cycle=5,
-                           max_per_problem=16, pc="fs_kii", log=lambda m: _log(f"learned: {m}"))
+    gen = L.generate_pairs(net, problems, store, cycle=5, max_per_problem=16, pc="fs_kii",
+                           log=lambda m: _log(f"learned: {m}"))
     _log(f"learned: {gen['pairs']} pairs from {gen['problems']} problems in {gen['seconds']:.1f} s")
-    losses, train_s = L.train(net, store, steps, 16, 1e-3, lr_final=1e-4)
-    _log(f"learned: {steps} Adam steps in {train_s:.1f} s, loss {losses[-1][1]:.3g}")
-    rates = cnn_rates(net, store, 16, stream)
-    _log(f"cnn: forward {rates['forward']['tflops']:.1f} TFLOP/s, "
-         f"forward+backward {rates['forward_backward']['tflops']:.1f} TFLOP/s")
-    eval_loss = L.eval_loss(net, store, 16) if npairs <= 2000 else None
-    rows = []
-    for prob, f in learned_problems(base, draws, 11505 + 4999):
-        c = L.compare(net, prob, f, max_it=3000, fs_pc="fs_kii", learned_pc="learned_kii")
-        # and at equal restart lengths, so that the stage is not charged for
-        # the flexible solve's shorter restart
-        c50 = L.compare(net, prob, f, max_it=3000, fs_pc="fs_kii", learned_pc="learned_kii",
-                        learned_restart=50)
-        rows.append({"sigma": c.sigma, "fs_iterations": c.fs_iterations, "fs_s": c.fs_seconds,
-                     "learned_iterations": c.learned_iterations, "learned_s": c.learned_seconds,
-                     "fallbacks": c.fallbacks, "fs_relres": c.fs_relres,
-                     "learned_relres": c.learned_relres,
-                     "learned50_iterations": c50.learned_iterations,
-                     "learned50_s": c50.learned_seconds, "learned50_relres": c50.learned_relres,
-                     "learned50_fallbacks": c50.fallbacks})
-        _log(f"learned: sigma {c.sigma:.2f} FS-GMRES(50) {c.fs_iterations} it {c.fs_seconds * 1e3:.1f} ms, "
-             f"learned FGMRES(30) {c.learned_iterations} it {c.learned_seconds * 1e3:.1f} ms, "
-             f"learned FGMRES(50) {c50.learned_iterations} it {c50.learned_seconds * 1e3:.1f} ms")
-    net.close()
-    return {"pairs": gen["pairs"], "training_problems": gen["problems"], "train_steps": steps,
-            "train_s": train_s, "final_loss": losses[-1][1], "train_set_loss": eval_loss,
-            "pair_generation_s": gen["seconds"],
+    draws_list = learned_problems(base, draws, 11505 + 4999)
+    out = {"pairs": gen["pairs"], "training_problems": gen["problems"], "train_steps": steps,
+           "pair_generation_s": gen["seconds"], "training_sigma_grid": grid.tolist(),
+           "field_split": "K_ii blocks (SG_PC_DIAG_KII) in both solvers"}
+    for k, objective in enumerate(objectives):
+        if k:
+            net.set_params(Ws, bs)
+        if objective == "error":
+            losses, train_s = L.train(net, store, steps, 16, 1e-3, lr_final=1e-4)
+        else:
+            sig_host = store.sig[:store.count].cpu().numpy()
+            pair_op = np.abs(sig_host[:, None] - grid[None, :].astype(np.float32)).argmin(axis=1)
+            ops = [L.make_instance(base.with_(sigma=float(g))) for g in grid]
+            losses, train_s = L.train_stage_objective(net, store, ops, pair_op, steps, 16, 1e-3,
+                                                      lr_final=1e-4)
+            for op in ops:
+                op.close()
+        _log(f"learned ({objective} objective): {steps} Adam steps in {train_s:.1f} s, "
+             f"final {losses[-1][1]:.3g}")
+        if "cnn" not in out:
+            out["cnn"] = cnn_rates(net, store, 16, stream)
+            _log(f"cnn: forward {out['cnn']['forward']['tflops']:.1f} TFLOP/s, "
+                 f"forward+backward {out['cnn']['forward_backward']['tflops']:.1f} TFLOP/s")
+        rows = []
+        for prob, f in draws_list:
+            c = L.compare(net, prob, f, max_it=3000, fs_pc="fs_kii", learned_pc="learned_kii")
+            c50 = L.compare(net, prob, f, max_it=3000, fs_pc="fs_kii", learned_pc="learned_kii",
+                            learned_restart=50)
+            rows.append({"sigma": c.sigma, "fs_iterations": c.fs_iterations, "fs_s": c.fs_seconds,
+                         "learned_iterations": c.learned_iterations,
+                         "learned_s": c.learned_seconds, "fallbacks": c.fallbacks,
+                         "fs_relres": c.fs_relres, "learned_relres": c.learned_relres,
+                         "learned50_iterations": c50.learned_iterations,
+                         "learned50_s": c50.learned_seconds,
+                         "learned50_relres": c50.learned_relres,
+                         "learned50_fallbacks": c50.fallbacks})
+            _log(f"learned ({objective}): sigma {c.sigma:.2f} FS-GMRES(50) {c.fs_iterations} it "
+                 f"{c.fs_seconds * 1e3:.1f} ms, learned FGMRES(30) {c.learned_iterations} it "
+                 f"{c.learned_seconds * 1e3:.1f} ms, learned FGMRES(50) {c50.learned_iterations} it "
+                 f"{c50.learned_seconds * 1e3:.1f} ms")
+        out[f"{objective}_objective"] = {
+            "train_s": train_s, "final_loss": losses[-1][1],
             "fs_iterations_median": float(np.median([r["fs_iterations"] for r in rows])),
             "learned_iterations_median": float(np.median([r["learned_iterations"] for r in rows])),
             "learned50_iterations_median": float(np.median([r["learned50_iterations"] for r in rows])),
@@ -407,11 +430,15 @@ def learned_comparison(npairs, steps, draws, stream, gen_problems=400):
                                                    for r in rows),
             "all_reach_tolerance": all(r["fs_relres"] <= 1e-8 and r["learned_relres"] <= 1e-8
                                        and r["learned50_relres"] <= 1e-8 for r in rows),
-            "field_split": "K_ii blocks (SG_PC_DIAG_KII) in both solvers",
             "time_ratio_fs_over_learned": float(np.median([r["fs_s"] / r["learned_s"] for r in rows])),
-            "iteration_ratio_fs_over_learned": float(np.median(
-                [r["fs_iterations"] / max(r["learned_iterations"], 1) for r in rows])),
-            "problems": rows, "cnn": rates, "total_s": time.perf_counter() - t0}
+            "time_ratio_fs_over_learned50": float(np.median([r["fs_s"] / r["learned50_s"]
+                                                             for r in rows])),
+            "iteration_ratio_fs_over_learned50": float(np.median(
+                [r["fs_iterations"] / max(r["learned50_iterations"], 1) for r in rows])),
+            "problems": rows}
+    net.close()
+    out["total_s"] = time.perf_counter() - t0
+    return out
 
 
 # The paper's studies (Sec. 4: Tabs. mesh_variation, sigma_variation, p_var_*,
@@ -535,7 +562,8 @@ def main():
         print(json.dumps({"paper_tables": res}), flush=True)
         return
     if args.learned_full:
-        res = learned_comparison(20000, 3750, 32, stream, gen_problems=2000)
+        res = learned_comparison(20000, 3750, 32, stream, gen_problems=2000,
+                                 objectives=("error", "stage"))
         print(json.dumps({"learned_protocol": res}), flush=True)
         return
 

@@ -326,8 +326,27 @@ int    sg_cnn_make_pair(sg_cnn* c, const double* r, const double* ustar, const d
 int    sg_cnn_run(sg_cnn* c, const uint16_t* R, const uint16_t* T, const float* sigma,
                   const int32_t* idx, int32_t batch, int32_t mode, float lr, int32_t step,
                   float* Y_out, double* loss, void* stream);
-/* weight and bias gradients of the last sg_cnn_run with mode >= 1 (host)    */
+/* weight and bias gradients of the last sg_cnn_run with mode >= 1, or of the
+ * last sg_cnn_backward (host)                                               */
 int    sg_cnn_get_grads(sg_cnn* c, float* dw_host, float* db_host);
+/* Training on the learned stage's own objective (the stage is z = z0 + alpha
+ * c with alpha minimising |r - alpha K c|, so it removes the share
+ * (r.Kc)^2 / (|r|^2 |Kc|^2) of the residual's square).  After a forward
+ * (sg_cnn_run, mode 0) on pairs idx[0..batch), for each slot: with r the
+ * stored residual R[pair] (bf16 npairs x P x N_h device array, the layout of
+ * sg_cnn_make_pair) and c the network's output for that slot, writes the
+ * output gradient of L = 1 - (r.Kc)^2 / (|r|^2 |Kc|^2), divided by batch, into
+ * the network; K is h's operator (the pair's problem; P and n must match the
+ * network).  work: device, sg_cnn_stage_work_doubles(h) doubles; loss
+ * (host, nullable): L, synchronous when given.  Then sg_cnn_backward takes
+ * the gradients of the summed objective and, with adam != 0, one Adam step
+ * (learning rate lr, step number >= 1).  Errors: INVALID_ARG, NOT_BOUND.
+ * Not part of the paper.                                                    */
+size_t sg_cnn_stage_work_doubles(const sg_handle* h);
+int    sg_cnn_stage_grad(sg_handle* h, sg_cnn* c, const uint16_t* R, int64_t pair, int32_t slot,
+                         int32_t batch, double* work, double* loss, void* stream);
+int    sg_cnn_backward(sg_cnn* c, int32_t batch, int32_t adam, float lr, int32_t step,
+                       void* stream);
 /* c = prediction for the FP64 SG vector v (device, P*N_h), SG units          */
 int    sg_cnn_apply(sg_cnn* c, const double* v, double sigma, double* out, void* stream);
 void   sg_cnn_destroy(sg_cnn* c);

@@ -15,6 +15,7 @@ from .binding import (  # noqa: F401
     sg_mg_workspace_bytes, sg_mg_bind,
     sg_cnn_create, sg_cnn_param_counts, sg_cnn_workspace_bytes, sg_cnn_bind, sg_cnn_set_params,
     sg_cnn_get_params, sg_cnn_make_pair, sg_cnn_run, sg_cnn_get_grads, sg_cnn_apply,
-    sg_cnn_destroy, sg_cnn_last_error, sg_attach_cnn,
+    sg_cnn_destroy, sg_cnn_last_error, sg_attach_cnn, sg_cnn_stage_work_doubles,
+    sg_cnn_stage_grad, sg_cnn_backward,
     COV, PC, GROUPING, EXPORT,
 )

@@ -104,6 +104,11 @@ def load_library():
         "sg_cnn_run": (I32, [HP, VP, VP, VP, VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
                              ctypes.c_int32, VP, ctypes.POINTER(ctypes.c_double), VP]),
         "sg_cnn_get_grads": (I32, [HP, VP, VP]),
+        "sg_cnn_stage_work_doubles": (SZ, [HP]),
+        "sg_cnn_stage_grad": (I32, [HP, HP, VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, VP,
+                                    ctypes.POINTER(ctypes.c_double), VP]),
+        "sg_cnn_backward": (I32, [HP, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_int32,
+                                  VP]),
         "sg_cnn_apply": (I32, [HP, VP, ctypes.c_double, VP, VP]),
         "sg_cnn_destroy": (None, [HP]),
         "sg_cnn_last_error": (ctypes.c_char_p, []),
@@ -310,6 +315,25 @@ def sg_cnn_run(c, R, T, sigma, idx, mode, lr=0.0, step=1, Y_out=None, want_loss=
 
 def sg_cnn_get_grads(c, dw, db):
     _ccheck(load_library().sg_cnn_get_grads(c, dw.ctypes.data, db.ctypes.data))
+
+
+def sg_cnn_stage_work_doubles(h) -> int:
+    return int(load_library().sg_cnn_stage_work_doubles(h))
+
+
+def sg_cnn_stage_grad(h, c, R, pair, slot, batch, work, want_loss=False, stream=None):
+    """The learned stage's objective for stored pair `pair` (batch slot `slot`
+    of the last forward) with h's operator; returns it when want_loss."""
+    loss = ctypes.c_double(0.0)
+    _check(load_library().sg_cnn_stage_grad(h, c, _ptr(R), int(pair), int(slot), int(batch),
+                                            _ptr(work), ctypes.byref(loss) if want_loss else None,
+                                            _stream(stream)))
+    return loss.value if want_loss else None
+
+
+def sg_cnn_backward(c, batch, adam, lr=0.0, step=1, stream=None):
+    _ccheck(load_library().sg_cnn_backward(c, int(batch), 1 if adam else 0, lr, int(step),
+                                           _stream(stream)))
 
 
 def sg_cnn_apply(c, v, sigma, out, stream=None):

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "sg_internal.h"
+#include "sg_learned.h"
 
 using namespace sg;
 
@@ -1627,6 +1628,58 @@ bool is_learned(const sg_solve_opts* o) { return (o->pc & 0xff) == SG_PC_LEARNED
 size_t sg_gmres_workspace_bytes(const sg_handle* h, const sg_solve_opts* o) {
   if (!h || !o || o->restart < 1 || o->restart > kMaxRestart) return 0;
   return krylov_layout(h, o->restart, is_learned(o), nullptr, nullptr);
+}
+
+size_t sg_cnn_stage_work_doubles(const sg_handle* h) {
+  if (!h) return 0;
+  const int64_t Nv = (int64_t)h->P * h->Nh;
+  return (size_t)(5 * Nv + 16 + gs_blocks(Nv));
+}
+
+// The learned stage's own objective for one stored pair: with c the network's
+// output for the pair (batch slot `slot` of the last forward) and r its
+// residual, the stage's step z0 + alpha c leaves the fraction
+// L = 1 - (r.Kc)^2 / (|r|^2 |Kc|^2) of the residual (squared); this writes
+// dL/dc / batch = 2a / (rho b batch) K((a/b) Kc - r), a = r.Kc, b = |Kc|^2,
+// rho = |r|^2 (K symmetric), into the network's output gradient of that slot.
+int sg_cnn_stage_grad(sg_handle* h, sg_cnn* c, const uint16_t* R, int64_t pair, int32_t slot,
+                      int32_t batch, double* work, double* loss, void* stream) {
+  if (!h || !c || !R || !work) return fail(SG_ERR_INVALID_ARG, "null argument");
+  if (!h->bound) return fail(SG_ERR_NOT_BOUND, "handle not bound");
+  if (!cnn_bound(c)) return fail(SG_ERR_NOT_BOUND, "network not bound");
+  if (cnn_modes(c) != h->P || cnn_grid(c) != h->n)
+    return fail(SG_ERR_INVALID_ARG, "network P / n do not match the problem");
+  if (batch < 1 || batch > cnn_max_batch(c) || slot < 0 || slot >= batch || pair < 0)
+    return fail(SG_ERR_INVALID_ARG, "slot, batch or pair out of range");
+  try {
+    sg_handle& H = *h;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int64_t Nv = (int64_t)H.P * H.Nh;
+    double* cv = work;
+    double* r = work + Nv;
+    double* Kc = work + 2 * Nv;
+    double* v = work + 3 * Nv;
+    double* Kv = work + 4 * Nv;
+    double* d = work + 5 * Nv;
+    double* partial = d + 16;
+    cnn_slot_to_sg(c, s, slot, cv);
+    cnn_pair_to_sg(c, s, R, pair, r);
+    do_apply(H, s, cv, Kc);
+    launch_gs_dot(s, r, Nv, 1, Kc, Nv, partial, d);
+    launch_gs_dot(s, Kc, Nv, 1, Kc, Nv, partial, d + 1);
+    launch_gs_dot(s, r, Nv, 1, r, Nv, partial, d + 2);
+    launch_stage_objective(s, d, batch, Kc, r, v, Nv);
+    do_apply(H, s, v, Kv);
+    cnn_slot_grad_from_sg(c, s, slot, Kv, d + 4);
+    check_launch();
+    if (loss) {
+      SG_HIP(hipMemcpyAsync(loss, d + 5, sizeof(double), hipMemcpyDeviceToHost, s));
+      SG_HIP(hipStreamSynchronize(s));
+    }
+    return SG_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  }
 }
 
 int sg_attach_cnn(sg_handle* h, sg_cnn* c, double sigma) {

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "sg_internal.h"
+#include "sg_learned.h"
 
 namespace sg {
 
@@ -436,6 +437,42 @@ __global__ void image_to_sg_kernel(const float* __restrict__ Y, const double* __
   c[i] = (double)Y[((int64_t)y * n + x) * CO + mode] * s;
 }
 
+// batch slot of the network output -> SG vector (no scaling; the stage
+// objective is scale-free): c[mode * N_h + node] = Y[slot][y][x][mode]
+__global__ void slot_to_sg_kernel(const float* __restrict__ Y, int slot, int P, int n, int CO,
+                                  double* __restrict__ c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = n - 1;
+  const int64_t Nh = (int64_t)m * m;
+  if (i >= (int64_t)P * Nh) return;
+  const int mode = (int)(i / Nh);
+  const int64_t node = i - (int64_t)mode * Nh;
+  const int x = (int)(node % m), y = (int)(node / m);
+  c[i] = (double)Y[(((int64_t)slot * n + y) * n + x) * CO + mode];
+}
+
+// stored bf16 pair residual -> FP64 SG vector
+__global__ void pair_to_sg_kernel(const bf16_t* __restrict__ R, int64_t len, double* __restrict__ r) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) r[i] = (double)bf2f(R[i]);
+}
+
+// output gradient of one batch slot from an SG vector: dY[slot][y][x][c] =
+// scale[0] g[c * N_h + node] on interior pixels and the first P channels,
+// zero elsewhere in the slot
+__global__ void sg_to_slot_grad_kernel(const double* __restrict__ g, const double* __restrict__ scale,
+                                       int slot, int P, int n, int CO, float* __restrict__ dY) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * n * CO) return;
+  const int c = (int)(i % CO);
+  const int64_t px = i / CO;
+  const int x = (int)(px % n), y = (int)(px / n);
+  const int m = n - 1;
+  float v = 0.f;
+  if (c < P && x < m && y < m) v = (float)(scale[0] * g[(int64_t)c * m * m + (int64_t)y * m + x]);
+  dY[(int64_t)slot * n * n * CO + i] = v;
+}
+
 // one training pair from FP64 SG vectors: residual r and error e = ustar - u;
 // R = bf16(r s), T = bf16(e s kappa / n^2), s = sqrt(P N_h) / ||r||
 __global__ void make_pair_kernel(const double* __restrict__ r, const double* __restrict__ ustar,
@@ -717,6 +754,50 @@ void cnn_apply_sg(sg_cnn* C, hipStream_t s, const double* v, double sigma, doubl
                      C->n, C->CO, c);
 }
 
+void cnn_slot_to_sg(sg_cnn* C, hipStream_t s, int slot, double* c) {
+  const int64_t Nv = (int64_t)C->P * (C->n - 1) * (C->n - 1);
+  hipLaunchKernelGGL(slot_to_sg_kernel, dim3(cdivl(Nv, 256)), dim3(256), 0, s, C->Y, slot, C->P,
+                     C->n, C->CO, c);
+}
+
+void cnn_pair_to_sg(sg_cnn* C, hipStream_t s, const uint16_t* R, int64_t pair, double* r) {
+  const int64_t Nv = (int64_t)C->P * (C->n - 1) * (C->n - 1);
+  hipLaunchKernelGGL(pair_to_sg_kernel, dim3(cdivl(Nv, 256)), dim3(256), 0, s,
+                     reinterpret_cast<const bf16_t*>(R) + pair * Nv, Nv, r);
+}
+
+void cnn_slot_grad_from_sg(sg_cnn* C, hipStream_t s, int slot, const double* g,
+                           const double* scale) {
+  const int64_t tot = (int64_t)C->n * C->n * C->CO;
+  hipLaunchKernelGGL(sg_to_slot_grad_kernel, dim3(cdivl(tot, 256)), dim3(256), 0, s, g, scale,
+                     slot, C->P, C->n, C->CO, C->g0);
+}
+
+int cnn_max_batch(const sg_cnn* C) { return C->maxB; }
+
+__global__ void stage_objective_coef_kernel(double* __restrict__ d, int batch) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double a = d[0], b = d[1], rho = d[2];
+  const bool ok = b > 0.0 && rho > 0.0;
+  d[3] = ok ? a / b : 0.0;
+  d[4] = ok ? 2.0 * a / (rho * b * batch) : 0.0;
+  d[5] = ok ? 1.0 - a * a / (rho * b) : 0.0;
+}
+
+__global__ void stage_objective_vec_kernel(const double* __restrict__ d, const double* __restrict__ Kc,
+                                           const double* __restrict__ r, double* __restrict__ v,
+                                           int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) v[i] = d[3] * Kc[i] - r[i];
+}
+
+void launch_stage_objective(hipStream_t s, double* dots, int batch, const double* Kc,
+                            const double* r, double* v, int64_t N) {
+  hipLaunchKernelGGL(stage_objective_coef_kernel, dim3(1), dim3(64), 0, s, dots, batch);
+  hipLaunchKernelGGL(stage_objective_vec_kernel, dim3(cdivl(N, 256)), dim3(256), 0, s, dots, Kc, r,
+                     v, N);
+}
+
 int cnn_modes(const sg_cnn* C) { return C->P; }
 int cnn_grid(const sg_cnn* C) { return C->n; }
 bool cnn_bound(const sg_cnn* C) { return C && C->bound; }
@@ -899,6 +980,33 @@ int sg_cnn_get_grads(sg_cnn* C, float* dW, float* dB) {
       hipMemcpy(dB, C->dB, C->nb * 4, hipMemcpyDeviceToHost) != hipSuccess)
     return cfail(SG_ERR_HIP, "copy failed");
   return SG_OK;
+}
+
+// Gradients (and, with adam != 0, one Adam step) from the output gradient the
+// caller's sg_cnn_stage_grad calls left in the network for the batch of the
+// last forward (sg_cnn_run)
+int sg_cnn_backward(sg_cnn* C, int32_t batch, int32_t adam, float lr, int32_t step, void* stream) {
+  if (!C) return cfail(SG_ERR_INVALID_ARG, "null argument");
+  if (!C->bound) return cfail(SG_ERR_NOT_BOUND, "CNN not bound");
+  if (batch < 1 || batch > C->maxB) return cfail(SG_ERR_INVALID_ARG, "batch out of range");
+  if (adam && step < 1) return cfail(SG_ERR_INVALID_ARG, "Adam step numbers start at 1");
+  try {
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    backward(s, *C, batch);
+    if (adam) {
+      const float b1 = 0.9f, b2 = 0.999f;
+      const float c1 = 1.f - std::pow(b1, (float)step), c2 = 1.f - std::pow(b2, (float)step);
+      hipLaunchKernelGGL(adam_kernel, dim3(cdivl(C->nw, 256)), dim3(256), 0, s, C->W, C->Wm, C->Wv,
+                         C->dW, (int64_t)C->nw, lr, b1, b2, 1e-8f, c1, c2);
+      hipLaunchKernelGGL(adam_kernel, dim3(cdivl(C->nb, 256)), dim3(256), 0, s, C->Bs, C->Bm, C->Bv,
+                         C->dB, (int64_t)C->nb, lr, b1, b2, 1e-8f, c1, c2);
+      cast_all(s, *C);
+    }
+    check_last();
+    return SG_OK;
+  } catch (const Error& e) {
+    return cfail(e.code, e.what());
+  }
 }
 
 // Inference in SG units: c = ||v|| n^2 / sqrt(P N_h) * N(v sqrt(P N_h) / ||v||, sigma)

@@ -101,6 +101,41 @@ def train(net: "sg.CNN", store: PairStore, steps: int, batch: int, lr: float, se
     return losses, time.perf_counter() - t0
 
 
+def train_stage_objective(net: "sg.CNN", store: PairStore, operators, pair_operator, steps: int,
+                          batch: int, lr: float, seed: int = 0, log_every: int = 0,
+                          lr_final: float | None = None):
+    """Adam on the learned stage's own objective instead of the error: for a
+    stored pair (r, e) and the network's output c = N(r), the stage
+    z0 + alpha c leaves the share 1 - (r.Kc)^2 / (|r|^2 |Kc|^2) of the
+    residual's square, K the operator of the pair's problem.  operators:
+    bound instances, one per distinct operator of the training problems;
+    pair_operator[i]: the index of pair i's operator.  Returns the mean
+    objective (every log_every steps, else the last step's) and the wall time."""
+    import torch
+    rng = np.random.default_rng(seed)
+    work = torch.empty(sg.sg_cnn_stage_work_doubles(operators[0].h), dtype=torch.float64,
+                       device=store.R.device)
+    losses = []
+    t0 = time.perf_counter()
+    for step in range(1, steps + 1):
+        idx = rng.choice(store.count, size=min(batch, store.count), replace=False).astype(np.int32)
+        lr_t = lr
+        if lr_final is not None:
+            lr_t = lr * (lr_final / lr) ** ((step - 1) / max(steps - 1, 1))
+        want = bool((log_every and step % log_every == 0) or step == steps)
+        sg.sg_cnn_run(net.c, store.R, None, store.sig, idx, 0)
+        tot = 0.0
+        for slot, pr in enumerate(idx):
+            L = sg.sg_cnn_stage_grad(operators[pair_operator[pr]].h, net.c, store.R, int(pr), slot,
+                                     len(idx), work, want_loss=want)
+            tot += L if want else 0.0
+        sg.sg_cnn_backward(net.c, len(idx), True, lr_t, step)
+        if want:
+            losses.append((step, tot / len(idx)))
+    torch.cuda.synchronize()
+    return losses, time.perf_counter() - t0
+
+
 def eval_loss(net: "sg.CNN", store: PairStore, batch: int):
     """Mean loss over the stored pairs (forward only)."""
     tot, cnt = 0.0, 0
