@@ -1825,6 +1825,11 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
       const double r = std::hypot(col[j], b);
       return r > 0.0 ? std::fabs(g[j]) * std::fabs(b) / r : std::fabs(g[j]);
     };
+    // Up to this Krylov size both passes add the apply's pending edge sums as
+    // they read w; from it on the apply adds them itself (apply_fixup_kernel):
+    // pass A re-reads w once per row of its grid, and with two or more rows
+    // the repeated scattered edge reads cost more than the fixup.
+    constexpr int kFixupFromJ = 24;
     auto linear_cycle = [&]() -> int {
       nfinal = 0;
       std::fill(Ht.begin(), Ht.end(), 0.0);
@@ -1838,11 +1843,10 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
         double* un = K.V + (int64_t)(j + 1) * Nv;
         if (!queued) {
           do_precond(H, s, pc, o->grouping, uj, K.z);
-          do_apply(H, s, K.z, K.w, false);
+          do_apply(H, s, K.z, K.w, j >= kFixupFromJ);
         }
         queued = false;
-        // the apply's edge sums are added by both passes as they read w
-        const EdgeFix ef = pending_edges(H, 1.0);
+        const EdgeFix ef = j >= kFixupFromJ ? EdgeFix{} : pending_edges(H, 1.0);
         launch_gs2_dot(s, K.V, Nv, j, uj, K.w, Nv, K.partial, K.hdev, ef);
         launch_gs2_coef(s, j, K.hdev, K.hdev + kCoef);
         launch_gs2_update(s, K.V, Nv, j, K.hdev, K.hdev + j, K.hdev + kCoef, uj, K.w, un, Nv, ef);
@@ -1851,7 +1855,7 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
         SG_HIP(hipEventRecord(H.fetched, s));
         if (j + 1 < m && it + 1 < o->max_it) {
           do_precond(H, s, pc, o->grouping, un, K.z);
-          do_apply(H, s, K.z, K.w, false);
+          do_apply(H, s, K.z, K.w, j + 1 >= kFixupFromJ);
           queued = true;
         }
         SG_HIP(hipEventSynchronize(H.fetched));
