@@ -279,9 +279,15 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* opts, const double* F, dou
  *                   (0 = finest), 9 x (n_l - 1)^2 values, entry s*N_l + node,
  *                   s = 3(dy+1) + (dx+1) (synchronous)
  *  SG_EXPORT_GROUPS for grouping `level`: the number of splits, then for
- *                   each split its size followed by its mode indices      */
+ *                   each split its size followed by its mode indices
+ *  SG_EXPORT_BLOCKS for grouping `level` (an inspection for tests): the
+ *                   number of splits, then per split the compiled block
+ *                   kernel its off-diagonal apply runs in the register form
+ *                   (its first KL variable), 0 where the run-time-mask
+ *                   kernel runs it, for split 0 and when the register form
+ *                   is not in use                                            */
 enum { SG_EXPORT_COEFF = 0, SG_EXPORT_KL = 1, SG_EXPORT_GQ = 2, SG_EXPORT_STENCIL = 3,
-       SG_EXPORT_GROUPS = 4 };
+       SG_EXPORT_GROUPS = 4, SG_EXPORT_BLOCKS = 5 };
 int sg_export(sg_handle* h, int what, int level, double* host_out, size_t count);
 
 void sg_destroy(sg_handle* h);

@@ -16,7 +16,7 @@ COV = {"exp_l1": 0, "sqexp": 1}
 PC = {"none": 0, "mean": 1, "fs": 2, "learned": 3, "mg": 4, "mean_kii": 0x101, "fs_kii": 0x102,
       "learned_kii": 0x103, "mean_switch": 0x201, "fs_switch": 0x202}
 GROUPING = {"klvar": 0, "klvar_meansep": 1, "permode": 2, "fg": 3, "all": 4}
-EXPORT = {"coeff": 0, "kl": 1, "gq": 2, "stencil": 3, "groups": 4}
+EXPORT = {"coeff": 0, "kl": 1, "gq": 2, "stencil": 3, "groups": 4, "blocks": 5}
 STATUS = {0: "converged", 1: "not_converged", 2: "breakdown"}
 PC_INNER_SHIFT = 16
 

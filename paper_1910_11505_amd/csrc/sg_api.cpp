@@ -2054,6 +2054,17 @@ int sg_export(sg_handle* h, int what, int level, double* out, size_t count) {
         std::copy(v.begin(), v.end(), out);
         return SG_OK;
       }
+      case SG_EXPORT_BLOCKS: {
+        if (level < 0 || level >= SG_GROUP_COUNT) throw Error(SG_ERR_INVALID_ARG, "grouping out of range");
+        const size_t S = H.fs[level].splits.size();
+        need(1 + S);
+        out[0] = (double)S;
+        for (size_t sp = 0; sp < S; ++sp)
+          out[1 + sp] = (H.use_factored && H.use_rapply && sp < H.rkv[level].size())
+                            ? (double)H.rkv[level][sp]
+                            : 0.0;
+        return SG_OK;
+      }
       case SG_EXPORT_COEFF: {
         if (!H.bound) return fail(SG_ERR_NOT_BOUND, "handle not bound");
         need((size_t)H.na * H.Nq);

@@ -87,6 +87,40 @@ def test_field_split_through_both_forms(name, grouping):
         assert relmax(z, ref) < 1e-12, form
 
 
+# every (M, p) class the register form is compiled for, with M >= 2 (the
+# first-variable split has off-diagonal blocks), on an 8 x 8 grid
+COMPILED = [(M, p) for M in range(2, 7) for p in range(1, 5)
+            if (M, p) not in ((4, 4), (5, 3), (5, 4), (6, 3), (6, 4))] + \
+           [(4, 4), (5, 3), (6, 3), (5, 4), (6, 4)]
+
+
+@pytest.mark.parametrize("M,p", COMPILED)
+def test_field_split_every_compiled_class(M, p):
+    """The first-variable field split through the register form against the
+    oracle, and every split after the first runs the compiled block kernel of
+    its KL variable (no fall-back to the run-time-mask kernel)."""
+    from oracle.gmg import GMGHierarchy
+    from oracle.precond import FieldSplit, make_groups
+    from oracle.system import SGSystem
+    need_gpu()
+    prob = Problem(n=8, M=M, p=p, q=2 * p, cov="exp_l1", sigma=0.9, corr_len=0.5)
+    S = SGSystem(prob)
+    G = instance(prob)
+    print(f"[fs compiled class M={M} p={p}] P={S.P}", flush=True)
+    form, _ = sg.sg_apply_form(G.h)
+    assert form == 2                                  # the register-resident kernel
+    groups = make_groups(S.Jp, "klvar")
+    blocks = G.export("blocks", sg.GROUPING["klvar"], count=1 + len(groups))
+    assert int(blocks[0]) == len(groups)
+    # split sp > 0 holds the modes whose first nonzero index is sp
+    assert [int(b) for b in blocks[1:]] == list(range(len(groups))), blocks
+    r = random_vector(S.P * S.Nh, 303)
+    ref = FieldSplit(S, GMGHierarchy(S.A[0], S.n), groups).apply(r)
+    z = to_host(G.precond(to_dev(r), "fs", "klvar"))
+    assert relmax(z, ref) < 1e-12
+    G.close()
+
+
 @pytest.mark.parametrize("form,qb", [("triple", 0), ("factored", 8), ("factored", 32),
                                      ("factored", 0)])
 def test_deferred_edge_sums_every_form(form, qb):
