@@ -318,6 +318,14 @@ int    sg_cnn_bind(sg_cnn* c, void* dev_workspace, size_t bytes, void* stream);
 /* host FP32 weights/biases in, Adam moments reset (synchronous)               */
 int    sg_cnn_set_params(sg_cnn* c, const float* w_host, const float* b_host, void* stream);
 int    sg_cnn_get_params(sg_cnn* c, float* w_host, float* b_host);
+/* Adam's first and second moments of the weights (n_weights floats each) and
+ * biases (n_bias each), host arrays: with the parameters and the step number
+ * the caller passes to training calls, the whole optimiser state, so that
+ * training can be stopped and resumed.  set: after sg_cnn_set_params (which
+ * resets them); synchronous.                                                 */
+int    sg_cnn_get_adam(sg_cnn* c, float* wm_host, float* wv_host, float* bm_host, float* bv_host);
+int    sg_cnn_set_adam(sg_cnn* c, const float* wm_host, const float* wv_host,
+                       const float* bm_host, const float* bv_host, void* stream);
 /* one training pair from device FP64 SG vectors: residual r = F - K u of an
  * iterate u and the reference solution ustar (error e = ustar - u):
  * R_out = bf16(r s), T_out = bf16(e s kappa / n^2), s = sqrt(P N_h)/||r||, both

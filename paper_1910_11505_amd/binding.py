@@ -97,6 +97,8 @@ def load_library():
         "sg_cnn_bind": (I32, [HP, VP, SZ, VP]),
         "sg_cnn_set_params": (I32, [HP, VP, VP, VP]),
         "sg_cnn_get_params": (I32, [HP, VP, VP]),
+        "sg_cnn_get_adam": (I32, [HP, VP, VP, VP, VP]),
+        "sg_cnn_set_adam": (I32, [HP, VP, VP, VP, VP, VP]),
         "sg_cnn_make_pair": (I32, [HP, VP, VP, VP, VP, VP, VP]),
         "sg_residual": (I32, [HP, VP, VP, VP, VP]),
         "sg_mg_workspace_bytes": (SZ, [HP, I32]),
@@ -485,6 +487,25 @@ class CNN:
         b = np.zeros(self.nb, dtype=np.float32)
         sg_cnn_get_params(self.c, w, b)
         return w, b
+
+    def get_state(self):
+        """Parameters and Adam moments (host copies): (w, b, wm, wv, bm, bv)."""
+        import numpy as np
+        w, b = self.get_params()
+        wm, wv = np.zeros(self.nw, np.float32), np.zeros(self.nw, np.float32)
+        bm, bv = np.zeros(self.nb, np.float32), np.zeros(self.nb, np.float32)
+        _ccheck(load_library().sg_cnn_get_adam(self.c, wm.ctypes.data, wv.ctypes.data,
+                                               bm.ctypes.data, bv.ctypes.data))
+        return w, b, wm, wv, bm, bv
+
+    def set_state(self, state):
+        """Restores get_state()'s parameters and Adam moments."""
+        import numpy as np
+        w, b, wm, wv, bm, bv = (np.ascontiguousarray(x, dtype=np.float32) for x in state)
+        sg_cnn_set_params(self.c, w, b, self.stream)
+        _ccheck(load_library().sg_cnn_set_adam(self.c, wm.ctypes.data, wv.ctypes.data,
+                                               bm.ctypes.data, bv.ctypes.data,
+                                               _stream(self.stream)))
 
     def get_grads(self):
         import numpy as np

@@ -895,6 +895,35 @@ int sg_cnn_get_params(sg_cnn* C, float* W, float* b) {
   return SG_OK;
 }
 
+// Adam moments (first and second, weights then biases) out and in, so that a
+// training run can be stopped and resumed: together with the parameters and
+// the step number the caller passes, they are the whole optimiser state
+int sg_cnn_get_adam(sg_cnn* C, float* wm, float* wv, float* bm, float* bv) {
+  if (!C || !wm || !wv || !bm || !bv) return cfail(SG_ERR_INVALID_ARG, "null argument");
+  if (!C->bound) return cfail(SG_ERR_NOT_BOUND, "CNN not bound");
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(wm, C->Wm, C->nw * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(wv, C->Wv, C->nw * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(bm, C->Bm, C->nb * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(bv, C->Bv, C->nb * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return cfail(SG_ERR_HIP, "copy failed");
+  return SG_OK;
+}
+
+int sg_cnn_set_adam(sg_cnn* C, const float* wm, const float* wv, const float* bm, const float* bv,
+                    void* stream) {
+  if (!C || !wm || !wv || !bm || !bv) return cfail(SG_ERR_INVALID_ARG, "null argument");
+  if (!C->bound) return cfail(SG_ERR_NOT_BOUND, "CNN not bound");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (hipMemcpyAsync(C->Wm, wm, C->nw * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(C->Wv, wv, C->nw * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(C->Bm, bm, C->nb * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(C->Bv, bv, C->nb * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return cfail(SG_ERR_HIP, "copy failed");
+  return SG_OK;
+}
+
 // One training pair from device FP64 SG vectors: residual r, reference solution
 // ustar and iterate u (error ustar - u); R_out, T_out are P*N_h bf16
 int sg_cnn_make_pair(sg_cnn* C, const double* r, const double* ustar, const double* u,

@@ -146,3 +146,36 @@ def test_apply_in_sg_units_matches_oracle():
     cg = c.cpu().numpy()
     assert np.linalg.norm(cg - ref) <= 1e-2 * np.linalg.norm(ref)
     net.close()
+
+
+def test_training_resumes_from_saved_state():
+    """Stopping after some Adam steps, restoring parameters and Adam moments
+    into a fresh network and continuing gives the same bits as training
+    without the stop."""
+    need_gpu()
+    P, n, B = 3, 16, 4
+    R, T, sig, Ws, bs, X0, Tt = _case(P, n, B, 23)
+    Rd = torch.from_numpy(_bf16_bits(R).view(np.int16)).cuda()
+    Td = torch.from_numpy(_bf16_bits(T).view(np.int16)).cuda()
+    sd = _dev(sig, torch.float32)
+    idx = np.arange(B)
+
+    def steps(net, first, last):
+        for step in range(first, last + 1):
+            sg.sg_cnn_run(net.c, Rd, Td, sd, idx, 2, lr=2e-3, step=step, want_loss=False)
+        torch.cuda.synchronize()
+
+    a = _net(P, n, B, Ws, bs)
+    steps(a, 1, 6)
+    w_ref, b_ref = a.get_params()
+    b = _net(P, n, B, Ws, bs)
+    steps(b, 1, 3)
+    state = b.get_state()
+    b.close()
+    c = _net(P, n, B, Ws, bs)
+    c.set_state(state)
+    steps(c, 4, 6)
+    w, bb = c.get_params()
+    assert np.any(state[2] != 0) and np.array_equal(w, w_ref) and np.array_equal(bb, b_ref)
+    a.close()
+    c.close()
