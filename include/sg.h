@@ -399,17 +399,19 @@ int    sg_batch_bind(sg_batch* b, int32_t restart, void* ws, size_t bytes, void*
 int    sg_batch_rhs(sg_batch* b, double* F, void* stream);
 /* the bound handle of instance i (for single-instance calls; owned by b)   */
 int    sg_batch_handle(sg_batch* b, int32_t i, sg_handle** h);
-/* solves every instance from zero with opts (pc SG_PC_MEAN or SG_PC_FS, any
- * grouping, restart equal to the bound value; SG_PC_SWITCH_KII applies to
- * the one-at-a-time solves below, the lockstep part keeps the A_0 cycles); F, u packed device vectors;
- * infos: count entries.  Graph capture needs a non-null stream (the null
- * stream runs the same launch sequences eagerly).  On a non-null stream,
- * instances of at least 2^20 unknowns (P*N_h) are solved by sg_gmres_solve,
- * up to three at a time (largest first, each from a host thread on a stream
- * of its own), beside the lockstep batch of the others.  At a restart that leaves at most four lockstep
- * instances running, those continue one at a time through sg_gmres_solve
- * from their current iterate; their infos add both parts.  The batch
- * workspace reserves the Krylov areas of both.  Synchronous.               */
+/* solves every instance from zero with opts (pc SG_PC_MEAN or SG_PC_FS,
+ * restart equal to the bound value; SG_PC_SWITCH_KII applies to the
+ * one-at-a-time solves below, the lockstep part keeps the A_0 cycles; any
+ * grouping whose splits number at most 12 for every lockstep instance, else
+ * UNSUPPORTED); F, u packed device vectors; infos: count entries.  Graph
+ * capture needs a non-null stream (the null stream runs the same launch
+ * sequences eagerly).  On a non-null stream, instances of at least 2^20
+ * unknowns (P*N_h) are solved by sg_gmres_solve, up to three at a time
+ * (largest first, each from a host thread on a stream of its own), beside
+ * the lockstep batch of the others.  At a restart that leaves at most four
+ * lockstep instances running, those continue one at a time through
+ * sg_gmres_solve from their current iterate; their infos add both parts.
+ * The batch workspace reserves the Krylov areas of both.  Synchronous.     */
 int    sg_batch_solve(sg_batch* b, const sg_solve_opts* opts, const double* F, double* u,
                       sg_solve_info* infos, void* stream);
 void   sg_batch_destroy(sg_batch* b);

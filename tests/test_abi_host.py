@@ -63,6 +63,28 @@ def test_device_calls_need_binding():
     sg.sg_destroy(h)
 
 
+def test_new_entry_points_validate_before_any_device_call():
+    """The full-system multigrid, the stage objective, the network's backward
+    pass and its Adam state check their arguments (and the handle's binding)
+    before touching the device."""
+    lib = sg.load_library()
+    h = _setup()
+    assert sg.sg_mg_workspace_bytes(h, 7) == 0                   # unknown grouping
+    assert sg.sg_mg_workspace_bytes(h, "all") > 0
+    with pytest.raises(sg.SGError) as e:
+        sg.sg_mg_bind(h, "fg", 256, 1 << 20, 0)                # handle not bound
+    assert e.value.code == -4
+    assert lib.sg_cnn_stage_work_doubles(None) == 0
+    assert sg.sg_cnn_stage_work_doubles(h) > 5 * 6 * 15 * 15
+    # null network / workspace, then an unbound handle
+    assert lib.sg_cnn_stage_grad(h, None, 256, 0, 0, 1, 256, None, None) == -1
+    assert lib.sg_cnn_stage_grad(h, 512, 256, 0, 0, 1, None, None, None) == -1
+    assert lib.sg_cnn_backward(None, 1, 0, ctypes.c_float(0.0), 1, None) == -1
+    assert lib.sg_cnn_get_adam(None, None, None, None, None) == -1
+    assert lib.sg_cnn_set_adam(None, None, None, None, None, None) == -1
+    sg.sg_destroy(h)
+
+
 def test_nonfinite_forcing_rejected():
     f = np.ones(17 * 17)
     f[5] = np.inf

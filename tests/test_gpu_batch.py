@@ -65,6 +65,59 @@ def test_batch_matches_single_instance_solves(pc, form, qb):
         B.close()
 
 
+@pytest.mark.parametrize("grouping", ["all", "fg"])
+def test_batch_groupings_match_single_instance_solves(grouping):
+    """The field split over the other groupings (one split of all modes, the
+    leading-digit rule) batched as the single-instance solver runs it: the same
+    outcome per instance (for M = 1 the leading-digit rule is one split per
+    mode, whose A_0 blocks stall at sigma = 1.3 in both solvers), and for the
+    converged ones equal iteration counts and solutions to 1e-12."""
+    need_gpu()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        B, fs = _make(stream)
+        F = B.rhs()
+        u, infos = B.solve(F, pc="fs", grouping=grouping, tol=1e-8, max_it=400)
+        torch.cuda.synchronize()
+        ub = u.cpu().numpy()
+        converged = 0
+        for i, p in enumerate(PROBS):
+            inst = sg.SGInstance(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma, p.corr_len, p.a_min,
+                                 f_nodal=fs[i], stream=stream)
+            ui, info, _ = inst.solve(inst.rhs(), pc="fs", grouping=grouping, restart=20, tol=1e-8,
+                                     max_it=400)
+            torch.cuda.synchronize()
+            o0, o1 = B.offsets[i], B.offsets[i + 1]
+            assert infos[i].status == info.status, (grouping, i, infos[i].status, info.status)
+            if info.status == 0:
+                converged += 1
+                assert infos[i].iterations == info.iterations, (grouping, i, infos[i].iterations,
+                                                                info.iterations)
+                uref = ui.cpu().numpy()
+                assert np.linalg.norm(ub[o0:o1] - uref) <= 1e-12 * np.linalg.norm(uref)
+            inst.close()
+        assert converged >= len(PROBS) - 1, converged
+        B.close()
+
+
+def test_batch_rejects_more_splits_than_its_tables_hold():
+    """One split per mode gives the P = 56 instance 56 splits, more than a
+    lockstep instance's 12: a clean UNSUPPORTED, and the batch still solves
+    with another grouping afterwards."""
+    need_gpu()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        B, fs = _make(stream)
+        F = B.rhs()
+        with pytest.raises(sg.SGError) as e:
+            B.solve(F, pc="fs", grouping="permode", tol=1e-8)
+        assert e.value.code == -2
+        u, infos = B.solve(F, pc="fs", grouping="klvar", tol=1e-8)
+        torch.cuda.synchronize()
+        assert all(i.status == 0 for i in infos)
+        B.close()
+
+
 def test_batch_large_instance_beside_the_lockstep():
     """An instance of at least 2^20 unknowns (128x128, P = 70) is solved by the
     single-instance solver on a stream of its own while the others advance in
