@@ -159,6 +159,27 @@ def test_gmres_restart_and_max_it():
     assert info.iterations == 0 and info.status == 0
 
 
+@pytest.mark.parametrize("restart", [1, 2, 7])
+def test_gmres_short_restarts_match_oracle(restart):
+    """Cycles of one, two and seven steps: the delayed second projection's
+    column completed by the end-of-cycle pass at every restart."""
+    from oracle.gmres import gmres
+    from oracle.precond import FieldSplit, make_groups
+    S, H, G = pair("n16_m2p2")
+    K = S.assemble()
+    F = S.rhs()
+    fs = FieldSplit(S, H, make_groups(S.Jp, "mean"))
+    xo, io = gmres(lambda v: K @ v, fs.apply, F, tol=1e-8, restart=restart, max_it=2000)
+    u, info, _ = G.solve(pc="mean", tol=1e-8, restart=restart, max_it=2000)
+    ug = to_host(u)
+    print(f"[gmres restart {restart}] GPU {info.iterations} it, oracle {io['iterations']} it",
+          flush=True)
+    assert info.status == 0 and io["converged"]
+    assert abs(info.iterations - io["iterations"]) <= 1
+    relres = np.linalg.norm(F - K @ ug) / np.linalg.norm(F)
+    assert relres <= 1e-8 * (1 + 1e-6) and abs(relres - info.relres) <= 1e-12
+
+
 def test_gmres_long_cycle_matches_oracle():
     """One unpreconditioned GMRES cycle of 96 steps (restart 120): the Krylov
     basis passes 64 vectors, so the Gram-Schmidt passes run both with the basis
