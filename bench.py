@@ -48,9 +48,9 @@ MG_GROUPING = "fg"
 # scaled by the same counter read on a plain 256 MiB device copy.  Valid only
 # for the kernel source the counters were taken on: the sha256 of
 # sg_rapply.hip + sg_kernels.hip + sg_internal.h is compared at run time.
-APPLY_TRAFFIC = {"src_sha256": "82d1dc78a8508d7fe5c3dac17fe5e3b9062c3308e2476a4b6323496080c5270d",
-                 "fetch_bytes": (29035.91 + 48457.77) * 1024 * 2.0,
-                 "write_bytes": (68837.72 + 42606.46) * 1024 * 1.0}
+APPLY_TRAFFIC = {"src_sha256": "26eab8d619d152e3ff26126a1c9957ea111de36ade606d792628761cda9be163",
+                 "fetch_bytes": (29236.10 + 48464.79) * 1024 * 2.0,
+                 "write_bytes": (68935.41 + 42606.27) * 1024 * 1.0}
 
 
 def _src_hash():

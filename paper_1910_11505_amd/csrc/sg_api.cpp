@@ -1616,7 +1616,7 @@ size_t krylov_layout(const sg_handle* h, int restart, bool flexible, KrylovWS* k
   K.t = c.take<double>(Nv);
   K.x2 = c.take<double>(Nv);
   K.partial = c.take<double>(std::max((size_t)std::max(K.nblk, gs_blocks(Nv)) * (restart + 1),
-                                       gs2_partial_doubles(restart)));
+                                       gs2_partial_doubles(restart, Nv)));
   K.hdev = c.take<double>(3 * (size_t)(restart + 1) + 16);
   K.ydev = c.take<double>(restart + 1);
   return c.off;
@@ -1825,11 +1825,8 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
       const double r = std::hypot(col[j], b);
       return r > 0.0 ? std::fabs(g[j]) * std::fabs(b) / r : std::fabs(g[j]);
     };
-    // Up to this Krylov size both passes add the apply's pending edge sums as
-    // they read w; from it on the apply adds them itself (apply_fixup_kernel):
-    // pass A re-reads w once per row of its grid, and with two or more rows
-    // the repeated scattered edge reads cost more than the fixup.
-    constexpr int kFixupFromJ = 24;
+    // The operator apply leaves its edge sums pending (no apply_fixup_kernel):
+    // both passes add them as they read w, each once per element.
     auto linear_cycle = [&]() -> int {
       nfinal = 0;
       std::fill(Ht.begin(), Ht.end(), 0.0);
@@ -1843,10 +1840,10 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
         double* un = K.V + (int64_t)(j + 1) * Nv;
         if (!queued) {
           do_precond(H, s, pc, o->grouping, uj, K.z);
-          do_apply(H, s, K.z, K.w, j >= kFixupFromJ);
+          do_apply(H, s, K.z, K.w, false);
         }
         queued = false;
-        const EdgeFix ef = j >= kFixupFromJ ? EdgeFix{} : pending_edges(H, 1.0);
+        const EdgeFix ef = pending_edges(H, 1.0);
         launch_gs2_dot(s, K.V, Nv, j, uj, K.w, Nv, K.partial, K.hdev, ef);
         launch_gs2_coef(s, j, K.hdev, K.hdev + kCoef);
         launch_gs2_update(s, K.V, Nv, j, K.hdev, K.hdev + j, K.hdev + kCoef, uj, K.w, un, Nv, ef);
@@ -1855,7 +1852,7 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
         SG_HIP(hipEventRecord(H.fetched, s));
         if (j + 1 < m && it + 1 < o->max_it) {
           do_precond(H, s, pc, o->grouping, un, K.z);
-          do_apply(H, s, K.z, K.w, j + 1 >= kFixupFromJ);
+          do_apply(H, s, K.z, K.w, false);
           queued = true;
         }
         SG_HIP(hipEventSynchronize(H.fetched));

@@ -295,9 +295,9 @@ void launch_gs_update_norm_scale(hipStream_t s, const double* V, int64_t ldv, in
 // Gram-Schmidt with the second projection delayed by one step: pass A
 // (out = Q^T u, Q^T w, u.u, u.w, w.w over nv basis vectors; without w:
 // Q^T u, u.u), its coefficients (nu, c_j, rho, raw |w - Q c|^2), pass B
-// (q_j in place of u_j, u_{j+1}); partial sized gs2_partial_doubles(nv)
+// (q_j in place of u_j, u_{j+1}); partial sized gs2_partial_doubles(nv, N)
 int gs2_dot_slots(int nv, bool with_w);
-size_t gs2_partial_doubles(int max_nv);
+size_t gs2_partial_doubles(int max_nv, int64_t N);
 void launch_gs2_dot(hipStream_t s, const double* Q, int64_t ldq, int nv, const double* u,
                     const double* w, int64_t N, double* partial, double* out,
                     const EdgeFix& ef = EdgeFix{});

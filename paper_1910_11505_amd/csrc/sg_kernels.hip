@@ -1353,11 +1353,25 @@ Gs2Shape gs2_shape(int nv) {
   return {16, 1, kStreamBlocks};
 }
 
+// Above kPassVecs basis vectors pass A runs gs2_dotc_kernel: each block owns
+// E kDotThreads consecutive elements, E <= 4 chosen so that a vector fills at
+// least about 2048 blocks.
+constexpr int kChunkMinBlocks = 2048;
+int gs2_chunk(int64_t N) {
+  int e = 4;
+  while (e > 1 && N < (int64_t)e * kDotThreads * kChunkMinBlocks) e >>= 1;
+  return e;
+}
+int gs2_dot_blocks(int nv, int64_t N) {
+  if (nv > kPassVecs) return (int)std::max<int64_t>(1, cdiv(N, (int64_t)gs2_chunk(N) * kDotThreads));
+  return std::min(gs_blocks(N), gs2_shape(nv).blocks);
+}
+
 int gs2_dot_slots(int nv, bool with_w) { return with_w ? 2 * nv + 3 : nv + 1; }
-size_t gs2_partial_doubles(int max_nv) {
+size_t gs2_partial_doubles(int max_nv, int64_t N) {
   size_t most = 0;
   for (int nv = 0; nv <= max_nv; ++nv)
-    most = std::max(most, (size_t)gs2_dot_slots(nv, true) * gs2_shape(nv).blocks);
+    most = std::max(most, (size_t)gs2_dot_slots(nv, true) * gs2_dot_blocks(nv, N));
   return most;
 }
 
@@ -1422,10 +1436,94 @@ __global__ __launch_bounds__(kDotThreads) void gs2_dot_kernel(
     partial[(int64_t)slot * gridDim.x + blockIdx.x] = (red[k] + red[64 + k]) + (red[128 + k] + red[192 + k]);
 }
 
+// Pass A for more than kPassVecs basis vectors, with the slots of
+// gs2_dot_kernel.  A block owns elements [b E T, (b + 1) E T) (T =
+// kDotThreads), keeps their u and w (pending edge sums added once) in
+// registers and runs over the basis in groups of eight vectors, writing each
+// group's block partials before the next: u and w are read once whatever nv
+// is, and the basis once.  (Groups of 16, eight elements per thread, or
+// per-wavefront partials without the barriers measured 2-5% slower.)
+template <int E>
+__global__ __launch_bounds__(kDotThreads) void gs2_dotc_kernel(
+    const double* __restrict__ Q, int64_t ldq, int nv, const double* __restrict__ u,
+    const double* __restrict__ w, int64_t N, double* __restrict__ partial, EdgeFix ef) {
+  constexpr int VB = 8;
+  __shared__ double red[4 * 64];
+  const bool hasw = w != nullptr;
+  const int64_t i0 = (int64_t)blockIdx.x * (E * kDotThreads) + threadIdx.x;
+  double ui[E], wi[E];
+  double ex[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int64_t i = i0 + (int64_t)e * kDotThreads;
+    const bool in = i < N;
+    ui[e] = in ? u[i] : 0.0;
+    wi[e] = in && hasw ? w_fixed(w, i, ef) : 0.0;
+    ex[0] = fma(ui[e], ui[e], ex[0]);
+    ex[1] = fma(ui[e], wi[e], ex[1]);
+    ex[2] = fma(wi[e], wi[e], ex[2]);
+  }
+  double* redw = red + 64 * (threadIdx.x >> 6);
+  const int k = threadIdx.x;
+  for (int l0 = 0; l0 < nv; l0 += VB) {
+    const int cnt = min(nv - l0, VB);
+    const double* Qb = Q + (int64_t)l0 * ldq;
+    double acc[2 * VB];
+#pragma unroll
+    for (int l = 0; l < 2 * VB; ++l) acc[l] = 0.0;
+#pragma unroll 1
+    for (int e = 0; e < E; ++e) {
+      const int64_t i = i0 + (int64_t)e * kDotThreads;
+      const bool in = i < N;
+      double a[VB];
+#pragma unroll
+      for (int l = 0; l < VB; ++l) a[l] = in && l < cnt ? Qb[(int64_t)l * ldq + i] : 0.0;
+#pragma unroll
+      for (int l = 0; l < VB; ++l) {
+        acc[l] = fma(a[l], ui[e], acc[l]);
+        acc[VB + l] = fma(a[l], wi[e], acc[VB + l]);
+      }
+    }
+    wave_sums<2 * VB>(acc, redw);
+    __syncthreads();
+    int slot = -1;
+    if (k < VB) {
+      if (k < cnt) slot = l0 + k;
+    } else if (k < 2 * VB) {
+      if (hasw && k - VB < cnt) slot = nv + l0 + (k - VB);
+    }
+    if (slot >= 0)
+      partial[(int64_t)slot * gridDim.x + blockIdx.x] = (red[k] + red[64 + k]) + (red[128 + k] + red[192 + k]);
+    __syncthreads();  // red is rewritten by the next group
+  }
+  wave_sums<4>(ex, redw);
+  __syncthreads();
+  if (k < 3 && (k == 0 || hasw))
+    partial[(int64_t)((hasw ? 2 * nv : nv) + k) * gridDim.x + blockIdx.x] =
+        (red[k] + red[64 + k]) + (red[128 + k] + red[192 + k]);
+}
+
 void launch_gs2_dot(hipStream_t s, const double* Q, int64_t ldq, int nv, const double* u,
                     const double* w, int64_t N, double* partial, double* out, const EdgeFix& ef) {
+  if (nv > kPassVecs) {
+    const int nb = gs2_dot_blocks(nv, N);
+    const dim3 grid(nb), block(kDotThreads);
+    switch (gs2_chunk(N)) {
+      case 4:
+        hipLaunchKernelGGL(gs2_dotc_kernel<4>, grid, block, 0, s, Q, ldq, nv, u, w, N, partial, ef);
+        break;
+      case 2:
+        hipLaunchKernelGGL(gs2_dotc_kernel<2>, grid, block, 0, s, Q, ldq, nv, u, w, N, partial, ef);
+        break;
+      default:
+        hipLaunchKernelGGL(gs2_dotc_kernel<1>, grid, block, 0, s, Q, ldq, nv, u, w, N, partial, ef);
+    }
+    hipLaunchKernelGGL(reduce_wide_kernel, dim3(gs2_dot_slots(nv, w != nullptr)), block, 0, s,
+                       partial, nb, out);
+    return;
+  }
   const Gs2Shape sh = gs2_shape(nv);
-  const int nb = std::min(gs_blocks(N), sh.blocks);
+  const int nb = gs2_dot_blocks(nv, N);
   const int ny = std::max(1, cdiv(nv, sh.vb));
   const dim3 grid(nb, ny), block(kDotThreads);
   if (sh.vb == 4)

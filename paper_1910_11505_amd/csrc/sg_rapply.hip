@@ -284,6 +284,13 @@ __device__ __forceinline__ double r_grad(const RGrad& r, const double* u) {
   return r.ga * d + r.gb * quad_xor<2>(d);
 }
 
+// Corner buffers: one row of 64 corner slots per output row, rows kCS apart
+// and slot s at cpos(s), so that the node sums' reads (the same corner of
+// elements four apart, the same slot of neighbouring rows) fall in different
+// LDS banks.  cpos keeps the four slots of an element adjacent.
+constexpr int kCS = 66;
+__device__ __forceinline__ int cpos(int s) { return s + (s >> 5); }
+
 // One of a tile's 25 nodes in the node sums: the lanes of the corner slots it
 // adds (corner 3 of element (x-1, y-1), 2 of (x, y-1), 1 of (x-1, y), 0 of
 // (x, y); -1 where the element lies outside the tile; the y part holds corners
@@ -298,10 +305,10 @@ struct RNode {
 __device__ __forceinline__ RNode r_node(int nd, int x0, int y0, int m) {
   const int nx = nd % 5, ny = nd / 5;
   RNode q;
-  q.i3 = nx >= 1 && ny >= 1 ? ((ny - 1) * 4 + nx - 1) * 4 + 3 : -1;
-  q.i2 = nx <= 3 && ny >= 1 ? ((ny - 1) * 4 + nx) * 4 + 2 : -1;
-  q.i1 = nx >= 1 && ny <= 3 ? (ny * 4 + nx - 1) * 4 + 1 : -1;
-  q.i0 = nx <= 3 && ny <= 3 ? (ny * 4 + nx) * 4 : -1;
+  q.i3 = nx >= 1 && ny >= 1 ? cpos(((ny - 1) * 4 + nx - 1) * 4 + 3) : -1;
+  q.i2 = nx <= 3 && ny >= 1 ? cpos(((ny - 1) * 4 + nx) * 4 + 2) : -1;
+  q.i1 = nx >= 1 && ny <= 3 ? cpos((ny * 4 + nx - 1) * 4 + 1) : -1;
+  q.i0 = nx <= 3 && ny <= 3 ? cpos((ny * 4 + nx) * 4) : -1;
   q.owned = nx <= 3 && ny <= 3;
   const int gx = x0 + nx, gy = y0 + ny;
   q.write = q.owned && gx >= 1 && gy >= 1;
@@ -452,7 +459,7 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
   constexpr uint64_t kAll = P >= 64 ? ~0ull : ((1ull << P) - 1);
   const int nrows = FULL ? P : rr.nrows;
   double* sN = smem;  // [P][25] nodal values (steps 1-2)
-  double* sC = smem;  // [2][nrows][64] corner contributions (steps 4-5)
+  double* sC = smem;  // [2][nrows][kCS] corner contributions (steps 4-5)
   const int nt = n / kTileE, ntiles = nt * nt;
   const int tx = tile % nt, ty = tile / nt;
   const int x0 = tx * kTileE, y0 = ty * kTileE;
@@ -542,7 +549,8 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
   // (see r_lane_qp); lane j of an element ends with its corner r_lane_qp(j, c)
   double wc, wo;
   r_corner_weights(comp, ql, xi, eta, wc, wo);
-  double* sCc = sC + comp * nrows * 64;
+  double* sCc = sC + comp * nrows * kCS;
+  const int lpos = cpos(lane);
 #pragma unroll
   for (int b = 0; b < P; ++b) {
     if (SEL ? !S.row[b] : !((rowmask >> b) & 1)) continue;
@@ -554,7 +562,7 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
     double f = sr * sx;
     if (FULL || (!SEL && ((colmask >> b) & 1))) f = fma(a_min, Gc[b], f);
     const double t = wc * f + quad_xor<2>(wo * f);
-    sCc[slot_of(b) * 64 + lane] = t - quad_xor<1>(t);
+    sCc[slot_of(b) * kCS + lpos] = t - quad_xor<1>(t);
     __builtin_amdgcn_sched_barrier(0);
   }
   __syncthreads();
@@ -567,8 +575,8 @@ __device__ __forceinline__ void rapply_tile(double* smem, int tile, int n, doubl
     for (int k = 0; k < (P + 4) / 5; ++k) {
       const int slot = tid / 25 + 5 * k;
       if (slot >= nrows) break;
-      const double* c = sC + slot * 64;
-      const double sum = r_node_sum(q, c, c + nrows * 64);
+      const double* c = sC + slot * kCS;
+      const double sum = r_node_sum(q, c, c + nrows * kCS);
       if (q.owned) {
         if (q.write) {
           double base = 0.0;
@@ -668,7 +676,7 @@ __device__ __forceinline__ void rapply_stream_tile(double* smem, int tile, int n
   constexpr int SN1 = S.n1, SNQ = S.nq;
   double* sN = smem;            // [P][25] nodal values
   constexpr int kRChunk = rchunk(P);
-  double* sC = sN + P * 25;     // [2][kRChunk][64] corner contributions of a row chunk
+  double* sC = sN + P * 25;     // [2][kRChunk][kCS] corner contributions of a row chunk
   const int nt = n / kTileE, ntiles = nt * nt;
   const int tx = tile % nt, ty = tile / nt;
   const int x0 = tx * kTileE, y0 = ty * kTileE;
@@ -807,8 +815,9 @@ __device__ __forceinline__ void rapply_stream_tile(double* smem, int tile, int n
     gv2[nn] = gv[nn];
     asm volatile("" : "+v"(gv2[nn]));
   }
-  double* sCc = sC + comp * kRChunk * 64;
-  const double* sCy = sC + kRChunk * 64;
+  double* sCc = sC + comp * kRChunk * kCS;
+  const double* sCy = sC + kRChunk * kCS;
+  const int lpos = cpos(lane);
   const RNode nq = r_node(tid % 25, x0, y0, m);
 #pragma unroll
   for (int b0 = 0; b0 < P; b0 += kRChunk) {
@@ -839,7 +848,7 @@ __device__ __forceinline__ void rapply_stream_tile(double* smem, int tile, int n
         if (FULL || col(b)) f = fma(a_min, db, f);
       }
       const double t = wc * f + quad_xor<2>(wo * f);
-      sCc[(b - b0) * 64 + lane] = t - quad_xor<1>(t);
+      sCc[(b - b0) * kCS + lpos] = t - quad_xor<1>(t);
       if ((!FULL && !SEL) || b % kRFence == kRFence - 1) __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
@@ -850,7 +859,7 @@ __device__ __forceinline__ void rapply_stream_tile(double* smem, int tile, int n
         if (bl >= kRChunk || b >= P) break;
         if (!row(b)) continue;
         const int slot = FULL ? b : rr.slot[b];
-        const double sum = r_node_sum(nq, sC + bl * 64, sCy + bl * 64);
+        const double sum = r_node_sum(nq, sC + bl * kCS, sCy + bl * kCS);
         if (nq.owned) {
           if (nq.write) {
             double base = 0.0;
@@ -908,7 +917,7 @@ void launch_rblock(hipStream_t s, int kv, int n, double mu, double a_min, const 
     const int nt = n / kTileE;
     constexpr int P = RTab<M, p>::P;
     if constexpr (P > kRSmall) {
-      const size_t lds = 8 * ((size_t)25 * P + 2 * rchunk(P) * 64);
+      const size_t lds = 8 * ((size_t)25 * P + 2 * rchunk(P) * kCS);
       static const bool attr_ok =
           hipFuncSetAttribute((const void*)rapply_stream_kernel<M, p, false, V>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
@@ -916,7 +925,7 @@ void launch_rblock(hipStream_t s, int kv, int n, double mu, double a_min, const 
       hipLaunchKernelGGL((rapply_stream_kernel<M, p, false, V>), dim3(nt * nt), dim3(kRThreads),
                          lds, s, n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);
     } else {
-      const size_t lds = 8 * (size_t)std::max(25 * P, 2 * rr.nrows * 64);
+      const size_t lds = 8 * (size_t)std::max(25 * P, 2 * rr.nrows * kCS);
       hipLaunchKernelGGL((rapply_kernel<M, p, false, V>), dim3(nt * nt), dim3(kRThreads), lds, s,
                          n, mu, a_min, g, rr, U, Nh, rin, beta, sgn, out, edge);
     }
@@ -942,14 +951,14 @@ SG_RAPPLY_LIST(SG_RBLOCK_EXTERN)
 #undef SG_RBLOCK_EXTERN
 
 size_t rapply_stream_lds_bytes(int P) {
-  return 8 * ((size_t)P * 25 + (size_t)2 * rchunk(P) * 64);
+  return 8 * ((size_t)P * 25 + (size_t)2 * rchunk(P) * kCS);
 }
 
 // P <= kRSmall: the nodal values and, after them, the corner contributions of
 // both components; above, the layout of rapply_stream_tile
 size_t rapply_lds_bytes(int P, int nrows) {
   if (P > kRSmall) return rapply_stream_lds_bytes(P);
-  return 8 * std::max((size_t)P * 25, (size_t)2 * nrows * 64);
+  return 8 * std::max((size_t)P * 25, (size_t)2 * nrows * kCS);
 }
 
 
