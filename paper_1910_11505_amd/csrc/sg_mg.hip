@@ -26,6 +26,9 @@ namespace sg {
 namespace {
 
 inline int mg_cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+// the most modes one split's nodal blocks may hold (the largest inversion
+// kernel below)
+constexpr int kMgMaxSplit = 128;
 
 // colour of an interior node: (ix mod 2) + 2 (iy mod 2); two nodes of one
 // colour are at least two grid steps apart in x or in y, so the 9-point
@@ -110,31 +113,59 @@ __global__ __launch_bounds__(MP < 64 ? 64 : MP) __attribute__((amdgpu_waves_per_
 // dz[modes[a]*N + node] = omega * sum_b Dinv_ab(node) t_b(node), Dinv the
 // symmetric inverse, its upper triangle packed over the padded size mp
 // (pair-major); t_b = t[(tmap ? tmap[b] : b)*N + node].  One thread per (node,
-// output row); the row index varies fastest over the grid, so the rows of one
-// range of nodes run back to back and the second read of every pair (once
-// for row a, once for row b) is served by the caches.
+// output row a), 256 nodes per workgroup.  Every pair is read by two rows (a
+// and b); so that the second read comes from L2, not memory:
+//  - row a takes its pairs in the order b = (s - a) mod mm, s = 0, 1, ...,
+//    so rows a and b read pair {a, b} at the same step s;
+//  - the rows of one node block run on one XCD, back to back: workgroups go
+//    to the XCDs in turn (id mod 8), and the r-th workgroup of XCD x takes
+//    node block 8 (r / mm) + x, row r mod mm (the node blocks padded to a
+//    multiple of 8; the padding's workgroups have no nodes).
 __global__ __launch_bounds__(256) void mg_block_kernel(const double* __restrict__ Dinv, int mm, int mp,
                                                        const double* __restrict__ t,
                                                        const int* __restrict__ tmap,
                                                        const int* __restrict__ modes, double omega,
                                                        double* __restrict__ dz, int64_t N) {
-  const int a = blockIdx.x;
-  const int64_t node = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+  const int x = blockIdx.x & 7, r = blockIdx.x >> 3;
+  const int a = r % mm, nb = 8 * (r / mm) + x;
+  const int64_t node = (int64_t)nb * 256 + threadIdx.x;
+  // the input map in LDS (splits hold at most kMgMaxSplit modes), so that a
+  // group's input rows are known without a wait per step
+  __shared__ int smap[kMgMaxSplit];
+  for (int i = threadIdx.x; i < mm; i += blockDim.x) smap[i] = tmap ? tmap[i] : i;
+  __syncthreads();
   if (node >= N) return;
+  auto pair = [&](int bb) {
+    const int lo = min(a, bb), hi = max(a, bb);
+    return (int64_t)lo * mp - (int64_t)lo * (lo - 1) / 2 + (hi - lo);
+  };
+  // steps in groups of kU: the group's map entries, pairs and inputs are all
+  // requested before the first product, so a wavefront waits once per group
+  // (even steps add into acc0, odd ones into acc1, as one step at a time)
+  constexpr int kU = 8;
   double acc0 = 0.0, acc1 = 0.0;
-  // b < a: pair (b, a) in row b's segment; b >= a: row a's own segment
-  int64_t pr = a;  // packed index of pair (0, a)
-  int b = 0;
-  for (; b < a; ++b) {
-    const double tb = t[(int64_t)(tmap ? tmap[b] : b) * N + node];
-    if (b & 1) acc1 = fma(Dinv[pr * N + node], tb, acc1);
-    else acc0 = fma(Dinv[pr * N + node], tb, acc0);
-    pr += mp - b - 1;  // from (b, a) to (b + 1, a)
+  int b = a == 0 ? 0 : mm - a;  // (0 - a) mod mm
+  int st = 0;
+  for (; st + kU <= mm; st += kU) {
+    double dv[kU], tv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int bb = b + u < mm ? b + u : b + u - mm;
+      tv[u] = t[(int64_t)smap[bb] * N + node];
+      dv[u] = Dinv[pair(bb) * N + node];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; u += 2) {
+      acc0 = fma(dv[u], tv[u], acc0);
+      acc1 = fma(dv[u + 1], tv[u + 1], acc1);
+    }
+    b = b + kU < mm ? b + kU : b + kU - mm;
   }
-  for (; b < mm; ++b, ++pr) {
-    const double tb = t[(int64_t)(tmap ? tmap[b] : b) * N + node];
-    if (b & 1) acc1 = fma(Dinv[pr * N + node], tb, acc1);
-    else acc0 = fma(Dinv[pr * N + node], tb, acc0);
+  for (; st < mm; ++st) {
+    const double tb = t[(int64_t)smap[b] * N + node];
+    if (st & 1) acc1 = fma(Dinv[pair(b) * N + node], tb, acc1);
+    else acc0 = fma(Dinv[pair(b) * N + node], tb, acc0);
+    if (++b == mm) b = 0;
   }
   dz[(int64_t)modes[a] * N + node] = omega * (acc0 + acc1);
 }
@@ -278,7 +309,10 @@ void launch_mg_invert(hipStream_t s, double* D, int mm, int64_t N) {
 
 void launch_mg_block(hipStream_t s, const double* Dinv, int mm, int64_t N, const double* t,
                      const int* tmap, const int* modes, double omega, double* dz) {
-  hipLaunchKernelGGL(mg_block_kernel, dim3(mm, mg_cdiv(N, 256)), dim3(256), 0, s, Dinv, mm,
+  if (mm < 1 || mm > kMgMaxSplit)
+    throw Error(SG_ERR_UNSUPPORTED, "full-system multigrid: a split of more than 128 modes");
+  const int64_t nblk8 = (mg_cdiv(N, 256) + 7) / 8 * 8;
+  hipLaunchKernelGGL(mg_block_kernel, dim3((unsigned)(mm * nblk8)), dim3(256), 0, s, Dinv, mm,
                      mg_block_pad(mm), t, tmap, modes, omega, dz, N);
 }
 
