@@ -95,6 +95,10 @@ def _args():
                     help="run the paper's mesh, sigma, p, q and N studies in their own setting "
                          "(Q1 grids with the paper's unknown counts), print one JSON line and "
                          "write the tables as markdown to MD")
+    ap.add_argument("--profile-vcycle", action="store_true",
+                    help="counter-collection mode: only the mean-based preconditioner (one V(2,2) "
+                         "cycle on A_0 over all 84 modes) on the 256x256 P=84 workload, and the "
+                         "plain 256 MiB device copy")
     ap.add_argument("--profile-step", action="store_true",
                     help="kernel-trace mode: set-up, warm-up and timed steps only")
     return ap.parse_args()
@@ -542,6 +546,35 @@ def profile_apply(stream):
                       "src_sha256": _src_hash()}), flush=True)
 
 
+def profile_vcycle(stream, reps=30):
+    """Average time (ms) of one mean-based preconditioner application on the
+    256x256 P=84 workload (HIP events on the stream it runs on), with the
+    copy of profile_apply as the counter scale reference."""
+    import torch
+    from synth import random_vector
+    p, inst = make_c2(1.0)
+    R = torch.from_numpy(random_vector(inst.nvec, 7)).to(inst.device)
+    Z = inst.vec()
+    for _ in range(3):
+        inst.precond(R, "mean", "klvar", z=Z)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        inst.precond(R, "mean", "klvar", z=Z)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    src = torch.ones(32 << 20, dtype=torch.float64, device=inst.device)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile": "vcycle", "precond_ms": e0.elapsed_time(e1) / reps,
+                      "modes": inst.P, "nodes": inst.Nh, "copy_bytes_each_way": src.numel() * 8,
+                      "copies": 5}), flush=True)
+
+
 def main():
     args = _args()
     if args.gpus != 1:
@@ -556,6 +589,9 @@ def main():
     stream = torch.cuda.current_stream()
     if args.profile_apply:
         profile_apply(stream)
+        return
+    if args.profile_vcycle:
+        profile_vcycle(stream)
         return
     if args.paper_tables:
         res = paper_tables(stream, args.paper_tables)
