@@ -332,12 +332,16 @@ __device__ __forceinline__ double r_node_sum(const RNode& q, const double* c, co
   return sum;
 }
 
-// output rows per corner-sum chunk of the streamed tile: 8 up to P = 84 (the
-// smaller corner buffer lets three tiles' wavefronts share a SIMD instead of
-// two; 256x256 applies: P = 84 0.140 -> 0.122 ms, P = 56 0.099 -> 0.085 ms,
-// P = 70 0.130 -> 0.120 ms), 16 above (at P = 210 registers allow one
-// wavefront per SIMD anyway, and twice the chunks cost 0.43 -> 0.51 ms)
-constexpr int rchunk(int P) { return P <= 84 ? 8 : 16; }
+// output rows per corner-sum chunk of the streamed tile: the most that keep
+// the tiles per CU the registers allow.  P = 56 and 84 fit six tiles (three
+// wavefronts per SIMD) with 14 and 9 rows (26 KB of LDS each; 16 rows at
+// P = 84 left two wavefronts per SIMD: 0.140 against 0.122 ms per 256x256
+// apply); P = 70 is held to two wavefronts per SIMD by its registers and
+// takes 16 rows, the larger spaces (one wavefront per SIMD) 24.  Fewer chunks
+// mean fewer barriers and fuller node-sum passes (125 threads, five rows
+// each): against 8 rows (16 above P = 84), 2% at P = 56, 1% at P = 70, 3.6%
+// at P = 210 on 128x128, the same at P = 84.
+constexpr int rchunk(int P) { return P == 84 ? 9 : P == 56 ? 14 : P == 70 ? 16 : P > 84 ? 24 : 8; }
 constexpr int kRFence = 4;   // rows between its scheduling fences
 
 // Field-split blocks known at compile time.  With the splits taken by the
