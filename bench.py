@@ -48,9 +48,9 @@ MG_GROUPING = "fg"
 # scaled by the same counter read on a plain 256 MiB device copy.  Valid only
 # for the kernel source the counters were taken on: the sha256 of
 # sg_rapply.hip + sg_kernels.hip + sg_internal.h is compared at run time.
-APPLY_TRAFFIC = {"src_sha256": "a2abbb02b3c47a9ea41c1afaa3da9d3d7e8a3bf4947bcaaed30b9d4ae0b07845",
-                 "fetch_bytes": (29215.18 + 48464.79) * 1024 * 2.0,
-                 "write_bytes": (69002.36 + 42606.41) * 1024 * 1.0}
+APPLY_TRAFFIC = {"src_sha256": "4a369a467965818e33e4b9149cc00b6b1880869f29bd3eb513c8b056a016c474",
+                 "fetch_bytes": (29079.74 + 48464.78) * 1024 * 2.0,
+                 "write_bytes": (68986.36 + 42606.31) * 1024 * 1.0}
 
 
 def _src_hash():

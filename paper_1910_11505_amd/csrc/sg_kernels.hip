@@ -1339,18 +1339,17 @@ void launch_gs_update_norm_scale(hipStream_t s, const double* V, int64_t ldv, in
 // ---------------------------------------------------------------------------
 constexpr int kPassVecs = 16;
 
-// Shape of pass A for nv basis vectors: VB vectors per block row, U elements
-// per thread and loop iteration, at most `blocks` blocks per row.  Few basis
-// vectors leave a thread few loads per iteration, so those shapes take more
-// elements per iteration and more blocks.
+// Shape of pass A for nv <= kPassVecs basis vectors (one block row): VB
+// vectors per block, U elements per thread and loop iteration, at most
+// `blocks` blocks.  Few basis vectors leave a thread few loads per iteration,
+// so those shapes take more elements per iteration and more blocks.
 struct Gs2Shape {
   int vb, u, blocks;
 };
 Gs2Shape gs2_shape(int nv) {
   if (nv <= 4) return {4, 4, 2048};
   if (nv <= 8) return {8, 2, 1024};
-  if (nv <= 16) return {16, 1, 1024};
-  return {16, 1, kStreamBlocks};
+  return {16, 1, 1024};
 }
 
 // Above kPassVecs basis vectors pass A runs gs2_dotc_kernel: each block owns
