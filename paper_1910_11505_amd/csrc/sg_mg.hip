@@ -114,7 +114,8 @@ __global__ __launch_bounds__(MP < 64 ? 64 : MP) __attribute__((amdgpu_waves_per_
 // symmetric inverse, its upper triangle packed over the padded size mp
 // (pair-major); t_b = t[(tmap ? tmap[b] : b)*N + node].  One thread per (node,
 // output row a), 256 nodes per workgroup.  Every pair is read by two rows (a
-// and b); so that the second read comes from L2, not memory:
+// and b); to give the second read a chance in L2 (measured on 256x256 with
+// one split of 84 modes: about a quarter of them avoid memory):
 //  - row a takes its pairs in the order b = (s - a) mod mm, s = 0, 1, ...,
 //    so rows a and b read pair {a, b} at the same step s;
 //  - the rows of one node block run on one XCD, back to back: workgroups go
