@@ -99,6 +99,9 @@ def _args():
                     help="counter-collection mode: only the mean-based preconditioner (one V(2,2) "
                          "cycle on A_0 over all 84 modes) on the 256x256 P=84 workload, and the "
                          "plain 256 MiB device copy")
+    ap.add_argument("--profile-batched", action="store_true",
+                    help="kernel-trace mode: only the 64-instance batched workload (batch and "
+                         "one-at-a-time solves)")
     ap.add_argument("--profile-step", action="store_true",
                     help="kernel-trace mode: set-up, warm-up and timed steps only")
     return ap.parse_args()
@@ -592,6 +595,9 @@ def main():
         return
     if args.profile_vcycle:
         profile_vcycle(stream)
+        return
+    if args.profile_batched:
+        print(json.dumps({"profile": "batched", "batched_64": batched_workload()}), flush=True)
         return
     if args.paper_tables:
         res = paper_tables(stream, args.paper_tables)
