@@ -329,7 +329,7 @@ def cnn_rates(net, store, batch, stream):
     import torch
     import paper_1910_11505_amd as sg
     from synth import cnn_layers
-    layers = cnn_layers(net.P, 64, 64)
+    layers = cnn_layers(net.P, net.c0, net.c1)
     fl = 0.0
     for ci, co, _, lvl in layers:
         S = net.n >> lvl

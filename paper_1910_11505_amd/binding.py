@@ -466,7 +466,7 @@ class CNN:
 
     def __init__(self, P, n, max_batch=16, device="cuda:0", stream=None, c0=32, c1=64):
         import torch
-        self.P, self.n = P, n
+        self.P, self.n, self.c0, self.c1 = P, n, c0, c1
         self.c = sg_cnn_create(P, n, c0, c1, max_batch)
         self.nw, self.nb = sg_cnn_param_counts(self.c)
         self.device = torch.device(device)

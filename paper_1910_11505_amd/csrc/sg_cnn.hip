@@ -53,13 +53,16 @@ __device__ __forceinline__ f32x4 mfma32(short8 a, short8 b, f32x4 c) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// 3x3 convolution, implicit GEMM.  One workgroup = 64 consecutive pixels of
-// one image (four wavefronts of 16), all output channels.  Per tap and 32
-// input channels: A = 16 pixels x 32 channels (one 16-byte load per lane),
-// B = 32 channels x 16 output channels.  Zero padding at the image border.
+// 3x3 convolution, implicit GEMM.  One workgroup = 64 PT consecutive pixels of
+// the batch (four wavefronts of PT tiles of 16), all output channels.  Per tap
+// and 32 input channels: B = 32 channels x 16 output channels (one 16-byte
+// weight load per lane and output block, shared by the wavefront's PT tiles),
+// A = 16 pixels x 32 channels per tile (one 16-byte load per lane).  Zero
+// padding at the image border.  Every tile's accumulators see the same
+// products in the same order for any PT.
 //   MODE 0: + bias, ReLU, bf16 out;  1: + bias, fp32 out;  2: fp32 out.
 // ---------------------------------------------------------------------------
-template <int CIN, int COUT, int MODE>
+template <int CIN, int COUT, int MODE, int PT>
 __global__ __launch_bounds__(256) void conv_fwd_kernel(const bf16_t* __restrict__ X,
                                                        const bf16_t* __restrict__ W,
                                                        const float* __restrict__ bias,
@@ -69,46 +72,59 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const bf16_t* __restrict_
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int SS = S * S;
   const int row = lane & 15, kg = lane >> 4;
-  const int pbase = blockIdx.x * 64 + wave * 16;
-  const int gp = pbase + row;
-  const bool valid = gp < npix;
-  const int b = valid ? gp / SS : 0;
-  const int p = gp - b * SS;
-  const int py = p / S, px = p - py * S;
+  const int wbase = blockIdx.x * (64 * PT) + wave * (16 * PT);
   constexpr int NB = COUT / 16;
-  f32x4 acc[NB];
+  f32x4 acc[PT][NB];
+  const bf16_t* Xb[PT];
+  int py[PT], px[PT];
+  bool valid[PT];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const bf16_t* Xb = X + (size_t)b * SS * CIN;
+  for (int t = 0; t < PT; ++t) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[t][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int gp = wbase + 16 * t + row;
+    valid[t] = gp < npix;
+    const int b = valid[t] ? gp / SS : 0;
+    const int p = gp - b * SS;
+    py[t] = p / S;
+    px[t] = p - py[t] * S;
+    Xb[t] = X + (size_t)b * SS * CIN;
+  }
 #pragma unroll
   for (int tap = 0; tap < 9; ++tap) {
-    const int qx = px + tap % 3 - 1, qy = py + tap / 3 - 1;
-    const bool in = valid && (unsigned)qx < (unsigned)S && (unsigned)qy < (unsigned)S;
-    const bf16_t* xp = Xb + (size_t)(in ? (qy * S + qx) : 0) * CIN + kg * 8;
 #pragma unroll
     for (int cb = 0; cb < CIN / 32; ++cb) {
-      short8 a = short8{0, 0, 0, 0, 0, 0, 0, 0};
-      if (in) a = *reinterpret_cast<const short8*>(xp + cb * 32);
+      short8 w[NB];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const short8 w = *reinterpret_cast<const short8*>(
+      for (int nb = 0; nb < NB; ++nb)
+        w[nb] = *reinterpret_cast<const short8*>(
             W + (size_t)(tap * COUT + nb * 16 + row) * CIN + cb * 32 + kg * 8);
-        acc[nb] = mfma32(a, w, acc[nb]);
+#pragma unroll
+      for (int t = 0; t < PT; ++t) {
+        const int qx = px[t] + tap % 3 - 1, qy = py[t] + tap / 3 - 1;
+        const bool in = valid[t] && (unsigned)qx < (unsigned)S && (unsigned)qy < (unsigned)S;
+        short8 a = short8{0, 0, 0, 0, 0, 0, 0, 0};
+        if (in) a = *reinterpret_cast<const short8*>(Xb[t] + (size_t)(qy * S + qx) * CIN + kg * 8 + cb * 32);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[t][nb] = mfma32(a, w[nb], acc[t][nb]);
       }
     }
   }
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
+  for (int t = 0; t < PT; ++t) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int pix = pbase + kg * 4 + i;
-      if (pix >= npix) continue;
-      const int co = nb * 16 + row;
-      float v = acc[nb][i];
-      if (MODE < 2) v += bias[co];
-      const size_t o = (size_t)pix * COUT + co;
-      if (MODE == 0) reinterpret_cast<bf16_t*>(Yv)[o] = f2bf(fmaxf(v, 0.f));
-      else reinterpret_cast<float*>(Yv)[o] = v;
+    for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pix = wbase + 16 * t + kg * 4 + i;
+        if (pix >= npix) continue;
+        const int co = nb * 16 + row;
+        float v = acc[t][nb][i];
+        if (MODE < 2) v += bias[co];
+        const size_t o = (size_t)pix * COUT + co;
+        if (MODE == 0) reinterpret_cast<bf16_t*>(Yv)[o] = f2bf(fmaxf(v, 0.f));
+        else reinterpret_cast<float*>(Yv)[o] = v;
+      }
     }
   }
 }
@@ -524,6 +540,11 @@ namespace {
 using namespace sg;
 
 constexpr int kChunk = 2048;   // pixels per weight-gradient workgroup
+// convolutions over at least kConvWidePix pixels (the finest levels at full
+// batch) take kConvTiles 16-pixel tiles per wavefront, so that each weight
+// fragment a wavefront loads serves that many tiles
+constexpr int kConvTiles = 4;
+constexpr int kConvWidePix = 64 * kConvTiles * 512;
 constexpr int kLossBlk = 16;
 
 template <class T>
@@ -592,14 +613,19 @@ void conv_forward(hipStream_t s, const sg_cnn_impl& C, int l, const bf16_t* X, v
   const CnnLayer& ly = C.L[l];
   const int S = level_size(C, ly.level);
   const int npix = B * S * S;
-  dim3 grid(cdivl(npix, 64));
+  const bool wide = npix >= kConvWidePix;
+  dim3 grid(cdivl(npix, wide ? 64 * kConvTiles : 64));
   const bf16_t* W = C.Wq + ly.woff;
   const float* bias = C.Bs + ly.boff;
-#define SG_CONV(CI, CO_, M)                                                                  \
-  if (ly.ci == CI && ly.co == CO_ && mode == M) {                                            \
-    hipLaunchKernelGGL((conv_fwd_kernel<CI, CO_, M>), grid, dim3(256), 0, s, X, W, bias, Y, S, \
-                       npix);                                                                \
-    return;                                                                                  \
+#define SG_CONV(CI, CO_, M)                                                                   \
+  if (ly.ci == CI && ly.co == CO_ && mode == M) {                                             \
+    if (wide)                                                                                 \
+      hipLaunchKernelGGL((conv_fwd_kernel<CI, CO_, M, kConvTiles>), grid, dim3(256), 0, s, X, W, \
+                         bias, Y, S, npix);                                                   \
+    else                                                                                      \
+      hipLaunchKernelGGL((conv_fwd_kernel<CI, CO_, M, 1>), grid, dim3(256), 0, s, X, W, bias, Y, \
+                         S, npix);                                                            \
+    return;                                                                                   \
   }
   SG_CONV(32, 32, 0) SG_CONV(64, 32, 0) SG_CONV(32, 64, 0) SG_CONV(64, 64, 0)
   SG_CONV(32, 32, 1) SG_CONV(32, 64, 1) SG_CONV(64, 32, 1) SG_CONV(64, 64, 1)
@@ -613,13 +639,18 @@ void conv_backward_data(hipStream_t s, const sg_cnn_impl& C, int l, const bf16_t
   const CnnLayer& ly = C.L[l];
   const int S = level_size(C, ly.level);
   const int npix = B * S * S;
-  dim3 grid(cdivl(npix, 64));
+  const bool wide = npix >= kConvWidePix;
+  dim3 grid(cdivl(npix, wide ? 64 * kConvTiles : 64));
   const bf16_t* Wf = C.Wf + ly.woff;
-#define SG_CONVT(CO_, CI)                                                                        \
-  if (ly.co == CO_ && ly.ci == CI) {                                                             \
-    hipLaunchKernelGGL((conv_fwd_kernel<CO_, CI, 2>), grid, dim3(256), 0, s, G, Wf, nullptr, dX, S, \
-                       npix);                                                                    \
-    return;                                                                                      \
+#define SG_CONVT(CO_, CI)                                                                       \
+  if (ly.co == CO_ && ly.ci == CI) {                                                            \
+    if (wide)                                                                                   \
+      hipLaunchKernelGGL((conv_fwd_kernel<CO_, CI, 2, kConvTiles>), grid, dim3(256), 0, s, G, Wf, \
+                         nullptr, dX, S, npix);                                                 \
+    else                                                                                        \
+      hipLaunchKernelGGL((conv_fwd_kernel<CO_, CI, 2, 1>), grid, dim3(256), 0, s, G, Wf, nullptr, \
+                         dX, S, npix);                                                          \
+    return;                                                                                     \
   }
   SG_CONVT(32, 32) SG_CONVT(32, 64) SG_CONVT(64, 32) SG_CONVT(64, 64)
 #undef SG_CONVT

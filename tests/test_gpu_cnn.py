@@ -52,10 +52,13 @@ def _dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dtype).cuda()
 
 
-@pytest.mark.parametrize("P,n,B,c0", [(3, 16, 2, 32), (35, 32, 2, 32), (35, 128, 2, 64)])
+@pytest.mark.parametrize("P,n,B,c0", [(3, 16, 2, 32), (35, 32, 2, 32), (35, 128, 2, 64),
+                                      (35, 128, 8, 64)])
 def test_forward_loss_and_gradients(P, n, B, c0):
-    """(35, 128, 2, 64) is the network of the learned workload (128 x 128 grid,
-    35 modes, 64-wide finest level)."""
+    """(35, 128, B, 64) is the network of the learned workload (128 x 128 grid,
+    35 modes, 64-wide finest level).  At B = 8 the finest level's convolutions
+    cover 131072 pixels, where the forward and data-gradient convolutions take
+    four 16-pixel tiles per wavefront (the smaller cases take one)."""
     need_gpu()
     print(f"[cnn parity P={P} n={n} B={B} c0={c0}]", flush=True)
     R, T, sig, Ws, bs, X0, Tt = _case(P, n, B, 7, c0)
