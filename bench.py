@@ -102,6 +102,11 @@ def _args():
     ap.add_argument("--profile-batched", action="store_true",
                     help="kernel-trace mode: only the 64-instance batched workload (batch and "
                          "one-at-a-time solves)")
+    ap.add_argument("--q2", action="store_true",
+                    help="biquadratic-element mode: the Q2 apply and GMRES solves on the meshes "
+                         "with the 128x128 and 256x256 workloads' unknowns (64x64 and 128x128 Q2 "
+                         "elements), the Q1 solves of the same unknowns beside them, and the "
+                         "mean-based iteration counts from 8x8 to 256x256 Q2 elements")
     ap.add_argument("--profile-step", action="store_true",
                     help="kernel-trace mode: set-up, warm-up and timed steps only")
     return ap.parse_args()
@@ -578,6 +583,82 @@ def profile_vcycle(stream, reps=30):
                       "copies": 5}), flush=True)
 
 
+def q2_workloads(stream, reps=30):
+    """Q2 (sg_setup_q2) against Q1 on the same unknowns: the apply (HIP events
+    on `stream`, average of `reps`), its algorithmic bytes 8 (M N_q + 2 P N_h)
+    and flops (8 nnz(T) + 76 P per Gauss point: gradients and node sums over 9
+    nodes, the a_min term, and the two products with T), and GMRES(50) to the
+    true relative residual 1e-8 with the refined-grid preconditioners."""
+    import math
+    import torch
+    import paper_1910_11505_amd as sg
+    from synth import CONFIGS, random_vector, rhs_noisy
+    out = {"apply": [], "solves": [], "mesh": []}
+    for name, n2 in (("c1", 64), ("c2", 128)):
+        base = CONFIGS[name]
+        f = rhs_noisy(2 * n2, 11505 + 4000)
+        for q2 in (True, False):
+            p = base.with_(n=n2 if q2 else 2 * n2)
+            inst = sg.SGInstance(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma, p.corr_len, p.a_min,
+                                 f_nodal=f, q2=q2)
+            U = torch.from_numpy(random_vector(inst.nvec, 7)).to(inst.device)
+            W = inst.vec()
+            for _ in range(3):
+                inst.apply(U, W)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                inst.apply(U, W)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            Nq = 9 * n2 * n2 if q2 else 4 * p.n * p.n
+            nnzT = sum(math.prod(a + 1 for a in al) for al in _multi_indices(p.M, p.p))
+            per_pt = 8 * nnzT + (76 if q2 else 36) * inst.P
+            byts = 8 * (p.M * Nq + 2 * inst.P * inst.Nh)
+            out["apply"].append({"workload": name, "elements": "Q2" if q2 else "Q1", "n": p.n,
+                                 "P": inst.P, "N_h": inst.Nh, "ms": ms, "bytes": byts,
+                                 "flops": Nq * per_pt, "GB_s": byts / ms / 1e6,
+                                 "TFLOP_s": Nq * per_pt / ms / 1e9})
+            _log(f"q2 mode: {name} {'Q2' if q2 else 'Q1'} n={p.n} apply {ms * 1e3:.1f} us")
+            F = inst.rhs()
+            pcs = (("mean", "klvar"), ("fs", "klvar"), ("mg", "fg"))
+            inst.bind_mg("fg")
+            for pc, gr in pcs:
+                u, info, _ = inst.solve(F, pc=pc, grouping=gr, restart=50, tol=1e-8, max_it=3000)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                u, info, _ = inst.solve(F, pc=pc, grouping=gr, restart=50, tol=1e-8, max_it=3000)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                out["solves"].append({"workload": name, "elements": "Q2" if q2 else "Q1",
+                                      "pc": pc, "iterations": info.iterations,
+                                      "relres": info.relres, "converged": info.status == 0,
+                                      "ms": dt * 1e3})
+                _log(f"q2 mode: {name} {'Q2' if q2 else 'Q1'} {pc}: {info.iterations} it "
+                     f"{dt * 1e3:.1f} ms relres {info.relres:.2e}")
+            inst.close()
+            del U, W, F
+            torch.cuda.empty_cache()
+    for n2 in (8, 16, 32, 64, 128, 256):
+        p = CONFIGS["c0"].with_(n=n2)
+        inst = sg.SGInstance(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma, p.corr_len, p.a_min, q2=True)
+        u, info, _ = inst.solve(inst.rhs(), pc="mean", restart=50, tol=1e-8, max_it=1000)
+        out["mesh"].append({"n": n2, "P": inst.P, "mean_iterations": info.iterations,
+                            "converged": info.status == 0})
+        inst.close()
+    _log(f"q2 mode: mean-based iterations by mesh {[m['mean_iterations'] for m in out['mesh']]}")
+    return out
+
+
+def _multi_indices(M, p):
+    """Total-degree multi-indices of M variables up to degree p."""
+    if M == 0:
+        return [()]
+    return [(a,) + r for a in range(p + 1) for r in _multi_indices(M - 1, p - a)]
+
+
 def main():
     args = _args()
     if args.gpus != 1:
@@ -598,6 +679,9 @@ def main():
         return
     if args.profile_batched:
         print(json.dumps({"profile": "batched", "batched_64": batched_workload()}), flush=True)
+        return
+    if args.q2:
+        print(json.dumps({"q2": q2_workloads(stream)}), flush=True)
         return
     if args.paper_tables:
         res = paper_tables(stream, args.paper_tables)

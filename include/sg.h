@@ -162,6 +162,26 @@ typedef struct sg_handle sg_handle;
  * *out receives a new handle (free with sg_destroy).  No device work.      */
 int sg_setup(const sg_problem* prob, const double* f_nodal, sg_handle** out);
 
+/* The same instance on continuous biquadratic (Q2) elements, the paper's
+ * spatial space (Sec. 2.2): prob->n (a power of two in [4, 2048]) elements
+ * per side, 3 x 3 Gauss points per element (eq. A_q), K = sum_k G_k (x) A_k
+ * with A_k the Q2 stiffness of a_k, F = e_0 (x) M f with the consistent Q2
+ * mass matrix.  The unknowns of a mode are the (2n-1)^2 interior Q2 nodes,
+ * which are the interior vertices of the twice-refined grid, numbered as for
+ * Q1 on 2n elements; f_nodal holds (2n+1)^2 values at those vertices (NULL
+ * for f = 1).  The KL eigenpairs come from the 1D Galerkin procedure on the
+ * refined grid, and g at a Gauss point is their bilinear interpolant.
+ * sg_apply, sg_residual, sg_rhs and sg_gmres_solve use the Q2 operator; the
+ * preconditioners (SG_PC_MEAN, SG_PC_FS with any grouping and flag,
+ * SG_PC_MG) are those of the Q1 operator on the refined grid, which is
+ * spectrally equivalent to the Q2 one with constants independent of n.  The
+ * apply is the factored form only.  Errors: INVALID_ARG (as sg_setup, or n
+ * out of range), UNSUPPORTED (q < 2p, or p > 15).  A Q2 handle rejects
+ * sg_set_apply, sg_apply_noalloc and sg_attach_cnn with UNSUPPORTED;
+ * sg_apply_form reports form 3; sg_sizes reports the Q1 refined grid's n_a
+ * and nnz_G; sg_export describes the refined grid's Q1 data.               */
+int sg_setup_q2(const sg_problem* prob, const double* f_nodal, sg_handle** out);
+
 /* Sizes of the discrete system (Sec. 2.2): P = |J(p)| = (M+p)!/(M!p!) chaos
  * modes of u, N_h = (n-1)^2 unknowns per mode (Q1, Dirichlet nodes
  * eliminated), n_a = |J(q)| coefficient modes of eq. dataProjection, nnz_G
@@ -216,7 +236,7 @@ int sg_set_apply(sg_handle* h, int kind, int points_per_batch, void* stream);
 /* The apply form in use (an inspection call for tests and tools): *form = 2
  * for the register-resident factored kernel, 1 for the factored LDS tile
  * kernel (*points_per_batch: its Gauss points per sub-batch), 0 for the
- * triple-product form.  Host only.  Errors: INVALID_ARG (null argument).    */
+ * triple-product form, 3 for the biquadratic apply of a sg_setup_q2 handle.  Host only.  Errors: INVALID_ARG (null argument).    */
 int sg_apply_form(const sg_handle* h, int* form, int* points_per_batch);
 
 /* z = P^{-1} r for pc in {SG_PC_NONE, SG_PC_MEAN, SG_PC_FS} and a grouping

@@ -8,7 +8,7 @@ the library has not been built.
 """
 from .binding import (  # noqa: F401
     SGError, Problem, SolveOpts, SolveInfo, load_library, library_path,
-    sg_setup, sg_sizes, sg_workspace_bytes, sg_bind, sg_rhs, sg_apply, sg_apply_noalloc,
+    sg_setup, sg_setup_q2, sg_sizes, sg_workspace_bytes, sg_bind, sg_rhs, sg_apply, sg_apply_noalloc,
     sg_set_apply, sg_apply_form,
     sg_precond_apply, sg_gmres_workspace_bytes, sg_gmres_solve, sg_export,
     sg_destroy, sg_last_error, SGInstance, CNN, sg_residual, Batch, sg_autotune_apply,

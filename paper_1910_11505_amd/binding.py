@@ -75,6 +75,7 @@ def load_library():
     HP = ctypes.c_void_p
     sig = {
         "sg_setup": (I32, [P(Problem), VP, P(HP)]),
+        "sg_setup_q2": (I32, [P(Problem), VP, P(HP)]),
         "sg_sizes": (I32, [HP, I64P, I64P, I64P, I64P]),
         "sg_workspace_bytes": (SZ, [HP]),
         "sg_bind": (I32, [HP, VP, SZ, VP]),
@@ -174,6 +175,18 @@ def sg_setup(prob: Problem, f_nodal=None):
     return h
 
 
+def sg_setup_q2(prob: Problem, f_nodal=None):
+    import numpy as np
+    lib = load_library()
+    h = ctypes.c_void_p()
+    fp = None
+    if f_nodal is not None:
+        f_nodal = np.ascontiguousarray(f_nodal, dtype=np.float64)
+        fp = f_nodal.ctypes.data
+    _check(lib.sg_setup_q2(ctypes.byref(prob), fp, ctypes.byref(h)))
+    return h
+
+
 def sg_sizes(h):
     vals = [ctypes.c_int64() for _ in range(4)]
     _check(load_library().sg_sizes(h, *[ctypes.byref(v) for v in vals]))
@@ -201,7 +214,7 @@ APPLY = {"auto": 0, "triple": 1, "factored": 2}
 
 def sg_apply_form(h):
     """(form, points per sub-batch): form 2 register-resident, 1 factored LDS
-    tiles, 0 triple products."""
+    tiles, 0 triple products, 3 the biquadratic apply of a Q2 handle."""
     f, q = ctypes.c_int32(), ctypes.c_int32()
     _check(load_library().sg_apply_form(h, ctypes.byref(f), ctypes.byref(q)))
     return f.value, q.value
@@ -359,10 +372,12 @@ class SGInstance:
     """One problem bound to a device workspace owned by a torch uint8 tensor."""
 
     def __init__(self, n, M, p, q, cov="exp_l1", mu=0.0, sigma=0.5, corr_len=0.5, a_min=0.01,
-                 f_nodal=None, device="cuda:0", stream=None):
+                 f_nodal=None, device="cuda:0", stream=None, q2=False):
+        """q2: biquadratic elements (sg_setup_q2), n elements per side."""
         import torch
         self.prob = make_problem(n, M, p, q, cov, mu, sigma, corr_len, a_min)
-        self.h = sg_setup(self.prob, f_nodal)
+        self.q2 = q2
+        self.h = (sg_setup_q2 if q2 else sg_setup)(self.prob, f_nodal)
         self.P, self.Nh, self.na, self.nnz = sg_sizes(self.h)
         self.device = torch.device(device)
         self.stream = stream

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsgfs.so")
 SOURCES = ["sg_host.cpp", "sg_api.cpp", "sg_kernels.hip", "sg_rapply.hip", "sg_rapply_blocks_64.hip",
            "sg_rapply_blocks_54.hip", "sg_rapply_blocks_63.hip", "sg_rapply_blocks_small.hip",
-           "sg_cnn.hip", "sg_mg.hip"]
+           "sg_cnn.hip", "sg_mg.hip", "sg_q2.hip"]
 ARCH = os.environ.get("SG_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -15,6 +15,7 @@
 
 #include "sg_internal.h"
 #include "sg_learned.h"
+#include "sg_q2.h"
 
 using namespace sg;
 
@@ -82,6 +83,10 @@ struct DevPtrs {
   double* cdiag = nullptr;       // one coefficient field (set-up scratch)
   double* Cd = nullptr;          // dense coarse V-cycle operator, N x N column-major
   double* stage = nullptr;       // learned stage of sg_precond_apply: dot partials, 4 scalars
+  // biquadratic handles: KL values at the Q2 Gauss points, the apply's two
+  // per-point buffers, and the translation-matrix lists
+  double *q2g = nullptr, *q2grad = nullptr, *q2y = nullptr;
+  Q2TDev q2t{};
 };
 
 // bump allocator over the caller's workspace (or a dry run to size it)
@@ -157,6 +162,16 @@ struct sg_handle {
   sg_cnn* cnn = nullptr;          // attached learned stage (not owned)
   double cnn_sigma = 0.0;
   MGState mg;                     // full-system multigrid (sg_mg_bind)
+  // biquadratic elements (sg_setup_q2): n2 elements per side; everything above
+  // describes the Q1 operator of the refined grid (2 n2 elements per side,
+  // the same nodes), which the preconditioners use
+  bool q2 = false;
+  int n2 = 0;
+  int64_t Nq2 = 0;
+  std::vector<double> q2g;                      // M x 9 n2^2 KL values
+  std::vector<int> q2p1, q2i1, q2p2, q2i2;      // T by column, by row
+  std::vector<double> q2c1, q2c2;
+  std::vector<uint64_t> q2e1, q2e2;
 
   ~sg_handle() {
     if (host_pinned) (void)hipHostFree(host_pinned);
@@ -608,6 +623,19 @@ void carve(const sg_handle& H, DevPtrs& D, Carver& c) {
     const size_t Nd = (size_t)(H.level_n[H.ldense] - 1) * (H.level_n[H.ldense] - 1);
     D.Cd = c.take<double>(Nd * Nd);
   }
+  if (H.q2) {
+    D.q2g = c.take<double>((size_t)H.M * H.Nq2);
+    D.q2grad = c.take<double>((size_t)2 * H.P * H.Nq2);
+    D.q2y = c.take<double>((size_t)2 * H.P * H.Nq2);
+    D.q2t.ptr1 = c.take<int>(H.q2p1.size());
+    D.q2t.idx1 = c.take<int>(H.q2i1.size());
+    D.q2t.c1 = c.take<double>(H.q2c1.size());
+    D.q2t.e1 = c.take<uint64_t>(H.q2e1.size());
+    D.q2t.ptr2 = c.take<int>(H.q2p2.size());
+    D.q2t.idx2 = c.take<int>(H.q2i2.size());
+    D.q2t.c2 = c.take<double>(H.q2c2.size());
+    D.q2t.e2 = c.take<uint64_t>(H.q2e2.size());
+  }
 }
 
 template <class T>
@@ -743,6 +771,12 @@ EdgeFix pending_edges(const sg_handle& H, double sgn) {
 // * kEdgeVals values, every one written by the apply before the fixup reads it.
 void do_apply(sg_handle& H, hipStream_t s, const double* U, double* W, bool fixup = true,
               double* edge = nullptr) {
+  if (H.q2) {
+    // complete on return: no edge sums are left pending
+    launch_q2_apply(s, H.n2, H.M, H.P, H.prob.mu, H.prob.a_min, H.d.q2g, H.d.q2t, U, W,
+                    H.d.q2grad, H.d.q2y);
+    return;
+  }
   if (!edge) edge = H.d.edge;
   if (H.use_factored && H.use_rapply)
     launch_rapply(s, H.M, H.prob.p, H.n, H.prob.mu, H.prob.a_min, H.d.g, H.rfull, U, H.Nh,
@@ -1123,6 +1157,91 @@ int sg_setup(const sg_problem* prob, const double* f_nodal, sg_handle** out) {
   return setup_impl(prob, f_nodal, 0, out);
 }
 
+int sg_setup_q2(const sg_problem* prob, const double* f_nodal, sg_handle** out) {
+  if (!prob || !out) return fail(SG_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (prob->n < 4 || prob->n > 2048 || (prob->n & (prob->n - 1)))
+    return fail(SG_ERR_INVALID_ARG, "n must be a power of two in [4, 2048] for Q2 elements");
+  if (prob->p < 0 || prob->q < 2 * prob->p)
+    return fail(SG_ERR_UNSUPPORTED, "the Q2 apply is the factored form: q >= 2p required");
+  if (prob->p > 15) return fail(SG_ERR_UNSUPPORTED, "the Q2 apply packs exponents below 16: p <= 15");
+  sg_problem r = *prob;
+  r.n = 2 * prob->n;
+  sg_handle* raw = nullptr;
+  const int rc = setup_impl(&r, f_nodal, 0, &raw);
+  if (rc != SG_OK) return rc;
+  std::unique_ptr<sg_handle> H(raw);
+  try {
+    H->q2 = true;
+    H->n2 = prob->n;
+    const int n2 = H->n2, nr = H->n, M = H->M, P = H->P;
+    H->Nq2 = (int64_t)9 * n2 * n2;
+    // KL values at the 3 x 3 Gauss points: the refined grid's 1D eigenvectors,
+    // linear in each coordinate within a refined cell
+    const double gp[3] = {0.5 - 0.5 * std::sqrt(0.6), 0.5, 0.5 + 0.5 * std::sqrt(0.6)};
+    H->q2g.assign((size_t)M * H->Nq2, 0.0);
+    auto lin = [&](const std::vector<double>& e, int el, int qi) {
+      const double X = 2.0 * (el + gp[qi]);
+      const int c = std::min((int)std::floor(X), nr - 1);
+      const double t = X - c;
+      return (1.0 - t) * e[c] + t * e[c + 1];
+    };
+    for (int m = 0; m < M; ++m) {
+      const auto& er = H->kl.e1[H->kl.pairs[m].first];
+      const auto& es = H->kl.e1[H->kl.pairs[m].second];
+      const double sq = std::sqrt(H->kl.lam[m]);
+      for (int ey = 0; ey < n2; ++ey)
+        for (int ex = 0; ex < n2; ++ex)
+          for (int qy = 0; qy < 3; ++qy)
+            for (int qx = 0; qx < 3; ++qx)
+              H->q2g[(size_t)m * H->Nq2 + (size_t)(3 * qy + qx) * n2 * n2 + (size_t)ey * n2 + ex] =
+                  sq * lin(er, ex, qx) * lin(es, ey, qy);
+    }
+    // T_{alpha beta} = prod_m sqrt(alpha_m! / beta_m!) g_m^(alpha_m - beta_m) / (alpha_m - beta_m)!
+    // for beta <= alpha, listed by column and by row
+    auto fact = [](int k) { double f = 1.0; for (int i = 2; i <= k; ++i) f *= i; return f; };
+    struct Ent { int a, b; double c; uint64_t e; };
+    std::vector<Ent> ent;
+    for (int a = 0; a < P; ++a)
+      for (int b = 0; b < P; ++b) {
+        bool le = true;
+        for (int m = 0; m < M; ++m) le = le && H->Jp[b][m] <= H->Jp[a][m];
+        if (!le) continue;
+        double c = 1.0;
+        uint64_t code = 0;
+        for (int m = 0; m < M; ++m) {
+          const int am = H->Jp[a][m], bm = H->Jp[b][m];
+          c *= std::sqrt(fact(am) / fact(bm)) / fact(am - bm);
+          code |= (uint64_t)(am - bm) << (4 * m);
+        }
+        ent.push_back({a, b, c, code});
+      }
+    auto lists = [&](bool by_col, std::vector<int>& ptr, std::vector<int>& idx,
+                     std::vector<double>& cv, std::vector<uint64_t>& ev) {
+      std::vector<Ent> v = ent;
+      std::stable_sort(v.begin(), v.end(), [&](const Ent& x, const Ent& y) {
+        return by_col ? (x.b != y.b ? x.b < y.b : x.a < y.a) : (x.a != y.a ? x.a < y.a : x.b < y.b);
+      });
+      ptr.assign(P + 1, 0);
+      for (const Ent& x : v) {
+        ptr[(by_col ? x.b : x.a) + 1]++;
+        idx.push_back(by_col ? x.a : x.b);
+        cv.push_back(x.c);
+        ev.push_back(x.e);
+      }
+      for (int i = 0; i < P; ++i) ptr[i + 1] += ptr[i];
+    };
+    lists(true, H->q2p1, H->q2i1, H->q2c1, H->q2e1);
+    lists(false, H->q2p2, H->q2i2, H->q2c2, H->q2e2);
+    *out = H.release();
+    return SG_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return fail(SG_ERR_INTERNAL, e.what());
+  }
+}
+
 namespace {
 int setup_impl(const sg_problem* prob, const double* f_nodal, int force_kc, sg_handle** out) {
   if (!prob || !out) return fail(SG_ERR_INVALID_ARG, "null argument");
@@ -1339,6 +1458,17 @@ int sg_bind(sg_handle* h, void* dev_workspace, size_t bytes, void* stream) {
     upload(s, D.all_sid, H.diag_sid);
     upload(s, D.diag_k, H.diag_k);
     upload(s, D.diag_v, H.diag_v);
+    if (H.q2) {
+      upload(s, D.q2g, H.q2g);
+      upload(s, D.q2t.ptr1, H.q2p1);
+      upload(s, D.q2t.idx1, H.q2i1);
+      upload(s, D.q2t.c1, H.q2c1);
+      upload(s, D.q2t.e1, H.q2e1);
+      upload(s, D.q2t.ptr2, H.q2p2);
+      upload(s, D.q2t.idx2, H.q2i2);
+      upload(s, D.q2t.c2, H.q2c2);
+      upload(s, D.q2t.e2, H.q2e2);
+    }
     launch_coeff(s, H.n, H.M, H.na, D.g, D.Jq, D.isf, H.prob.mu, H.prob.a_min, D.a);
     // stencil 0: mean stiffness A_0; stencil i+1: diagonal block K_ii
     for (int id = 0; id <= H.P; ++id) {
@@ -1386,7 +1516,10 @@ int sg_rhs(sg_handle* h, double* F, void* stream) {
   if (!h || !F) return fail(SG_ERR_INVALID_ARG, "null argument");
   if (!h->bound) return fail(SG_ERR_NOT_BOUND, "handle not bound");
   try {
-    launch_rhs(reinterpret_cast<hipStream_t>(stream), h->n, h->d.f, F, (int64_t)h->P * h->Nh);
+    if (h->q2)
+      launch_q2_rhs(reinterpret_cast<hipStream_t>(stream), h->n2, h->P, h->d.f, F);
+    else
+      launch_rhs(reinterpret_cast<hipStream_t>(stream), h->n, h->d.f, F, (int64_t)h->P * h->Nh);
     check_launch();
     return SG_OK;
   } catch (const Error& e) {
@@ -1396,13 +1529,14 @@ int sg_rhs(sg_handle* h, double* F, void* stream) {
 
 int sg_apply_form(const sg_handle* h, int* form, int* points_per_batch) {
   if (!h || !form || !points_per_batch) return fail(SG_ERR_INVALID_ARG, "null argument");
-  *form = !h->use_factored ? 0 : h->use_rapply ? 2 : 1;
+  *form = h->q2 ? 3 : !h->use_factored ? 0 : h->use_rapply ? 2 : 1;
   *points_per_batch = *form == 1 ? h->ffull.qb : 0;
   return SG_OK;
 }
 
 int sg_set_apply(sg_handle* h, int kind, int points_per_batch, void* stream) {
   if (!h) return fail(SG_ERR_INVALID_ARG, "null argument");
+  if (h->q2) return fail(SG_ERR_UNSUPPORTED, "a Q2 handle has one apply form");
   if (kind < SG_APPLY_AUTO || kind > SG_APPLY_FACTORED)
     return fail(SG_ERR_INVALID_ARG, "unknown apply form");
   const int qb = points_per_batch;
@@ -1460,6 +1594,7 @@ int sg_apply(sg_handle* h, const double* U, double* W, void* stream) {
 int sg_apply_noalloc(sg_handle* h, const double* U, double* W, void* stream) {
   if (!h || !U || !W) return fail(SG_ERR_INVALID_ARG, "null argument");
   if (U == W) return fail(SG_ERR_INVALID_ARG, "U and W must not alias");
+  if (h->q2) return fail(SG_ERR_UNSUPPORTED, "sg_apply_noalloc: Q1 handles only");
   const size_t need = (size_t)h->P * h->ntiles * kEdgeVals * sizeof(double);
   if (need > kNoAllocScratchBytes)
     return fail(SG_ERR_UNSUPPORTED, "sg_apply_noalloc: the edge sums need " + std::to_string(need) +
@@ -1685,6 +1820,7 @@ int sg_cnn_stage_grad(sg_handle* h, sg_cnn* c, const uint16_t* R, int64_t pair, 
 int sg_attach_cnn(sg_handle* h, sg_cnn* c, double sigma) {
   if (!h) return fail(SG_ERR_INVALID_ARG, "null handle");
   if (c) {
+    if (h->q2) return fail(SG_ERR_UNSUPPORTED, "the learned stage serves Q1 handles only");
     if (!cnn_bound(c)) return fail(SG_ERR_NOT_BOUND, "network not bound");
     if (cnn_modes(c) != h->P || cnn_grid(c) != h->n)
       return fail(SG_ERR_INVALID_ARG, "network P / n do not match the problem");
@@ -1843,7 +1979,7 @@ int sg_gmres_solve(sg_handle* h, const sg_solve_opts* o, const double* F, double
           do_apply(H, s, K.z, K.w, false);
         }
         queued = false;
-        const EdgeFix ef = pending_edges(H, 1.0);
+        const EdgeFix ef = H.q2 ? EdgeFix{} : pending_edges(H, 1.0);
         launch_gs2_dot(s, K.V, Nv, j, uj, K.w, Nv, K.partial, K.hdev, ef);
         launch_gs2_coef(s, j, K.hdev, K.hdev + kCoef);
         launch_gs2_update(s, K.V, Nv, j, K.hdev, K.hdev + j, K.hdev + kCoef, uj, K.w, un, Nv, ef);

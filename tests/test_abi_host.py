@@ -160,3 +160,22 @@ def test_set_apply_oversized_batch_keeps_plan():
     assert e.value.code == -2
     sg.sg_set_apply(h, "factored", 8, stream=0)
     sg.sg_destroy(h)
+
+
+def test_q2_setup_validates_and_reports_refined_sizes():
+    """sg_setup_q2: n2 elements per side give (2 n2 - 1)^2 unknowns per mode;
+    the factored-only apply rejects q < 2p; the form query reports 3 and the
+    form setter refuses (no device call is made)."""
+    base = dict(n=8, M=2, p=2, q=4, cov="exp_l1", mu=0.0, sigma=0.5, corr_len=0.5, a_min=0.01)
+    h = sg.sg_setup_q2(make_problem(**base))
+    P, Nh, _, _ = sg.sg_sizes(h)
+    assert (P, Nh) == (6, 15 * 15)
+    assert sg.sg_apply_form(h)[0] == 3
+    with pytest.raises(sg.SGError) as e:
+        sg.sg_set_apply(h, 2, 0, 0)
+    assert e.value.code == -2
+    sg.sg_destroy(h)
+    for kw, code in ((dict(q=3), -2), (dict(n=6), -1), (dict(n=4096), -1)):
+        with pytest.raises(sg.SGError) as e:
+            sg.sg_setup_q2(make_problem(**{**base, **kw}))
+        assert e.value.code == code
