@@ -15,6 +15,7 @@ Modules
   pc       index sets J(p) and Hermite triple products          (Sec. 2.2)
   kl       Karhunen-Loeve expansion by a Galerkin procedure      (Sec. 2.1)
   fem      Q1 finite elements, quadrature, stiffness and mass    (Sec. 2.2)
+  q2       biquadratic elements: stiffness, mass, the SG system (Sec. 2.2)
   system   coefficient chaos modes, A_k, K = sum G_k (x) A_k, F (Sec. 2.2)
   gmg      geometric multigrid V-cycle on the mean stiffness     (Sec. 3)
   precond  mean-based and field-split block Gauss-Seidel         (Sec. 3)
