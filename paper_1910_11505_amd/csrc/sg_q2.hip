@@ -90,16 +90,11 @@ __device__ __forceinline__ double q2_mono(const double (&g)[kQ2MaxM], uint64_t c
   return v;
 }
 
-// the KL values of Gauss point q and exp(mu + |g|^2 / 2)
-__device__ __forceinline__ double q2_point(const double* __restrict__ g, int64_t Nq, int M,
-                                           int64_t q, double mu, double (&gv)[kQ2MaxM]) {
-  double g2 = 0.0;
+// the KL values of Gauss point q (zero past M)
+__device__ __forceinline__ void q2_point(const double* __restrict__ g, int64_t Nq, int M,
+                                         int64_t q, double (&gv)[kQ2MaxM]) {
 #pragma unroll
-  for (int k = 0; k < kQ2MaxM; ++k) {
-    gv[k] = k < M ? g[(int64_t)k * Nq + q] : 0.0;
-    g2 += gv[k] * gv[k];
-  }
-  return exp(mu + 0.5 * g2);
+  for (int k = 0; k < kQ2MaxM; ++k) gv[k] = k < M ? g[(int64_t)k * Nq + q] : 0.0;
 }
 
 // pass 2: thread (mode beta, Gauss point q), y_beta = sum_alpha T_{alpha beta} grad_alpha
@@ -115,7 +110,7 @@ __global__ __launch_bounds__(kQ2Threads) void q2_ty_kernel(int64_t Nq, int M, in
   const int b = (int)(gid / Nq);
   const int64_t q = gid - (int64_t)b * Nq;
   double gv[kQ2MaxM];
-  (void)q2_point(g, Nq, M, q, 0.0, gv);
+  q2_point(g, Nq, M, q, gv);
   double yx = 0.0, yy = 0.0;
   for (int t = T.ptr1[b]; t < T.ptr1[b + 1]; ++t) {
     const int a = T.idx1[t];
@@ -140,7 +135,11 @@ __global__ __launch_bounds__(kQ2Threads) void q2_tflux_kernel(int64_t Nq, int M,
   const int a = (int)(gid / Nq);
   const int64_t q = gid - (int64_t)a * Nq;
   double gv[kQ2MaxM];
-  const double sc = q2_point(g, Nq, M, q, mu, gv);
+  q2_point(g, Nq, M, q, gv);
+  double g2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < kQ2MaxM; ++k) g2 += gv[k] * gv[k];
+  const double sc = exp(mu + 0.5 * g2);
   double fx = 0.0, fy = 0.0;
   for (int t = T.ptr2[a]; t < T.ptr2[a + 1]; ++t) {
     const int b = T.idx2[t];
