@@ -31,8 +31,9 @@ Pins (tests/test_oracle_q2.py): the 1D element matrices against their closed
 forms, exact reproduction of a biquadratic solution of the Poisson problem,
 the energy u^T A v for a bilinear coefficient against an independent 5x5
 Gauss quadrature of the interpolants, the mass matrix against the integral
-of 1 and of x^2 y^2, and the SG operator at P = 1 and sigma = 0 reducing to
-the deterministic stiffness.
+of 1 and of x^2 y^2, and the SG operator at sigma = 0 reducing to the
+deterministic stiffness; the pointwise and sampled applies are pinned against
+the Kronecker-sum apply.
 """
 from __future__ import annotations
 
@@ -226,3 +227,37 @@ class SGSystemQ2:
             for a in range(9):
                 np.add.at(W, nd[:, a], contrib[:, a, :])
         return W[inner][np.argsort(g2i[inner])].T.reshape(-1)
+
+    def apply_at(self, U: np.ndarray, modes, nodes) -> np.ndarray:
+        """(K U) at selected (mode, interior node) pairs straight from the
+        definition: the sum over the node's 1, 2 or 4 elements and their Gauss
+        points of w_q grad phi_node . sum_k a_k sum_j [G_k]_ij grad U_j, for
+        grids where even the pointwise apply is slow.  Returns an array
+        (len(modes), len(nodes))."""
+        n, P = self.n, self.P
+        m = 2 * n - 1
+        Um = np.asarray(U).reshape(P, self.Nh)
+        _, Gref, wq = ref_tables()
+        out = np.zeros((len(modes), len(nodes)))
+        for t, node in enumerate(nodes):
+            X, Y = node % m + 1, node // m + 1
+            exs = [X // 2 - 1, X // 2] if X % 2 == 0 else [(X - 1) // 2]
+            eys = [Y // 2 - 1, Y // 2] if Y % 2 == 0 else [(Y - 1) // 2]
+            for ey in eys:
+                for ex in exs:
+                    e = ey * n + ex
+                    la = 3 * (Y - 2 * ey) + (X - 2 * ex)
+                    uc = np.zeros((P, 9))
+                    for by in range(3):
+                        for bx in range(3):
+                            cx, cy = 2 * ex + bx, 2 * ey + by
+                            if 1 <= cx <= m and 1 <= cy <= m:
+                                uc[:, 3 * by + bx] = Um[:, (cy - 1) * m + (cx - 1)]
+                    aq = coeff_modes(self.g[:, 9 * e:9 * e + 9], self.Jq, self.prob.mu,
+                                     self.prob.a_min)
+                    for q in range(9):
+                        C = np.zeros((P, P))
+                        np.add.at(C, (self.Gi, self.Gj), aq[self.Gk, q] * self.Gv)
+                        flux = C @ (uc @ Gref[q])
+                        out[:, t] += wq[q] * flux[list(modes)] @ Gref[q, la]
+        return out

@@ -88,3 +88,30 @@ def test_q2_mean_based_iterations_do_not_grow_with_the_mesh():
         G.close()
     print(f"[q2 mesh] mean-based iterations n=8..128: {its}", flush=True)
     assert max(its) <= min(its) + 3
+
+
+def test_q2_apply_sampled_at_the_measured_size():
+    """The Q2 size bench.py --q2 times, 128 x 128 elements with the 256 x 256
+    workload's chaos space (M = 6, p = 3, P = 84, q = 6, L1-exponential
+    L_c = 0.25, sigma = 1): 60 (mode, node) outputs of the GPU apply, at
+    vertex, edge-midpoint and element-centre nodes next to the boundary and
+    inside, against the oracle's sampled apply from the definition (bar 1e-12
+    relative to the largest sampled value)."""
+    need_gpu()
+    prob = CONFIGS["c2"].with_(n=128)
+    print("[q2 sampled parity 128x128 P=84]", flush=True)
+    S = SGSystemQ2(prob)
+    G = _inst(prob)
+    U = np.random.default_rng(84).standard_normal(S.P * S.Nh)
+    Ud, W = to_dev(U), G.vec()
+    sg.sg_apply(G.h, Ud.data_ptr(), W.data_ptr(), None)
+    Wg = to_host(W).reshape(S.P, S.Nh)
+    G.close()
+    m = 2 * prob.n - 1
+    rng = np.random.default_rng(85)
+    nodes = [0, 1, m, m + 1, S.Nh - 1, (m // 2) * m + m // 2] + list(rng.integers(0, S.Nh, 4))
+    modes = [0, 1, 7, 27, 55, 83]
+    Wo = S.apply_at(U, modes, nodes)
+    err = np.max(np.abs(Wg[np.ix_(modes, nodes)] - Wo)) / np.max(np.abs(Wo))
+    print(f"[q2 sampled parity] {len(modes) * len(nodes)} outputs, rel err {err:.2e}", flush=True)
+    assert err <= 1e-12

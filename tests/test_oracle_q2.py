@@ -142,3 +142,19 @@ def test_pointwise_apply_matches_kronecker_apply_and_is_symmetric():
     KU = S.apply(U)
     assert np.max(np.abs(S.apply_pointwise(U, chunk=5) - KU)) <= 1e-13 * np.max(np.abs(KU))
     assert abs(V @ KU - U @ S.apply(V)) <= 1e-12 * abs(V @ KU)
+
+
+def test_apply_at_matches_kronecker_apply_on_every_node_kind():
+    """Sampled outputs (vertex, edge-midpoint and element-centre nodes, next to
+    the boundary and inside) against the full apply."""
+    prob = CONFIGS["c0"].with_(n=4, M=2, p=2, q=4, sigma=0.7)
+    S = q2.SGSystemQ2(prob)
+    rng = np.random.default_rng(3)
+    U = rng.standard_normal(S.P * S.Nh)
+    KU = S.apply(U).reshape(S.P, S.Nh)
+    m = 2 * prob.n - 1
+    nodes = [0, 1, m + 1, 2 * m + 3, 3 * m + 3, S.Nh - 1, (m // 2) * m + m // 2]
+    modes = [0, 2, S.P - 1]
+    got = S.apply_at(U, modes, nodes)
+    ref = KU[np.ix_(modes, nodes)]
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(KU))
