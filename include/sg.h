@@ -176,7 +176,7 @@ int sg_setup(const sg_problem* prob, const double* f_nodal, sg_handle** out);
  * SG_PC_MG) are those of the Q1 operator on the refined grid, which is
  * spectrally equivalent to the Q2 one with constants independent of n.  The
  * apply is the factored form only.  Errors: INVALID_ARG (as sg_setup, or n
- * out of range), UNSUPPORTED (q < 2p, or p > 15).  A Q2 handle rejects
+ * out of range), UNSUPPORTED (q < 2p, p > 15, or P * 9 n^2 >= 2^31).  A Q2 handle rejects
  * sg_set_apply, sg_apply_noalloc and sg_attach_cnn with UNSUPPORTED;
  * sg_apply_form reports form 3; sg_sizes reports the Q1 refined grid's n_a
  * and nnz_G; sg_export describes the refined grid's Q1 data.               */

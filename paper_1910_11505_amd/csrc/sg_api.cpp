@@ -1176,6 +1176,9 @@ int sg_setup_q2(const sg_problem* prob, const double* f_nodal, sg_handle** out) 
     H->n2 = prob->n;
     const int n2 = H->n2, nr = H->n, M = H->M, P = H->P;
     H->Nq2 = (int64_t)9 * n2 * n2;
+    // the apply's launches take one work-item per (mode, Gauss point)
+    if ((int64_t)P * H->Nq2 >= (int64_t(1) << 31))
+      return fail(SG_ERR_UNSUPPORTED, "Q2: P * 9 n^2 must stay below 2^31");
     // KL values at the 3 x 3 Gauss points: the refined grid's 1D eigenvectors,
     // linear in each coordinate within a refined cell
     const double gp[3] = {0.5 - 0.5 * std::sqrt(0.6), 0.5, 0.5 + 0.5 * std::sqrt(0.6)};
