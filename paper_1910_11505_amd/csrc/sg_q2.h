@@ -13,15 +13,15 @@
 
 namespace sg {
 
+// KL variables a Gauss point carries at most (the problem limit on M)
+constexpr int kQ2MaxM = 12;
+
 // the Hermite translation matrix T(g) of the factored apply
 // (sum_k a_k G_k = a_min I + exp(mu + |g|^2/2) T T^T) as two CSR lists of its
 // nonzeros T_{alpha beta} = c * g^(alpha - beta), beta <= alpha:
 //  by column beta: ptr1 (P+1), row index alpha, c, packed exponents;
 //  by row alpha:   ptr2 (P+1), column index beta, c, packed exponents.
 // Exponents are packed 4 bits per KL variable (variable m at bits 4m..4m+3).
-// KL variables a Gauss point carries at most (the problem limit on M)
-constexpr int kQ2MaxM = 12;
-
 struct Q2TDev {
   const int *ptr1 = nullptr, *idx1 = nullptr, *ptr2 = nullptr, *idx2 = nullptr;
   const double *c1 = nullptr, *c2 = nullptr;
