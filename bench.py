@@ -80,6 +80,8 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c1", action="store_true", help="skip the 128x128 context solves")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batched workload")
+    ap.add_argument("--no-q2", action="store_true",
+                    help="skip the biquadratic-element apply and solves (the q2 key)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-stage comparison (learned workload, reduced training)")
     ap.add_argument("--learned-pairs", type=int, default=640)
@@ -583,12 +585,14 @@ def profile_vcycle(stream, reps=30):
                       "copies": 5}), flush=True)
 
 
-def q2_workloads(stream, reps=30):
+def q2_workloads(stream, reps=30, light=False):
     """Q2 (sg_setup_q2) against Q1 on the same unknowns: the apply (HIP events
     on `stream`, average of `reps`), its algorithmic bytes 8 (M N_q + 2 P N_h)
     and flops (8 nnz(T) + 76 P per Gauss point: gradients and node sums over 9
     nodes, the a_min term, and the two products with T), and GMRES(50) to the
-    true relative residual 1e-8 with the refined-grid preconditioners."""
+    true relative residual 1e-8 with the refined-grid preconditioners.  light:
+    the Q2 side only, the mean-based and multigrid solves, no mesh sweep (the
+    default run's `q2` key)."""
     import math
     import torch
     import paper_1910_11505_amd as sg
@@ -597,7 +601,7 @@ def q2_workloads(stream, reps=30):
     for name, n2 in (("c1", 64), ("c2", 128)):
         base = CONFIGS[name]
         f = rhs_noisy(2 * n2, 11505 + 4000)
-        for q2 in (True, False):
+        for q2 in ((True,) if light else (True, False)):
             p = base.with_(n=n2 if q2 else 2 * n2)
             inst = sg.SGInstance(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma, p.corr_len, p.a_min,
                                  f_nodal=f, q2=q2)
@@ -623,7 +627,8 @@ def q2_workloads(stream, reps=30):
                                  "TFLOP_s": Nq * per_pt / ms / 1e9})
             _log(f"q2 mode: {name} {'Q2' if q2 else 'Q1'} n={p.n} apply {ms * 1e3:.1f} us")
             F = inst.rhs()
-            pcs = (("mean", "klvar"), ("fs", "klvar"), ("mg", "fg"))
+            pcs = ((("mean", "klvar"), ("mg", "fg")) if light else
+                   (("mean", "klvar"), ("fs", "klvar"), ("mg", "fg")))
             inst.bind_mg("fg")
             for pc, gr in pcs:
                 u, info, _ = inst.solve(F, pc=pc, grouping=gr, restart=50, tol=1e-8, max_it=3000)
@@ -641,14 +646,15 @@ def q2_workloads(stream, reps=30):
             inst.close()
             del U, W, F
             torch.cuda.empty_cache()
-    for n2 in (8, 16, 32, 64, 128, 256):
+    for n2 in (() if light else (8, 16, 32, 64, 128, 256)):
         p = CONFIGS["c0"].with_(n=n2)
         inst = sg.SGInstance(p.n, p.M, p.p, p.q, p.cov, p.mu, p.sigma, p.corr_len, p.a_min, q2=True)
         u, info, _ = inst.solve(inst.rhs(), pc="mean", restart=50, tol=1e-8, max_it=1000)
         out["mesh"].append({"n": n2, "P": inst.P, "mean_iterations": info.iterations,
                             "converged": info.status == 0})
         inst.close()
-    _log(f"q2 mode: mean-based iterations by mesh {[m['mean_iterations'] for m in out['mesh']]}")
+    if not light:
+        _log(f"q2 mode: mean-based iterations by mesh {[m['mean_iterations'] for m in out['mesh']]}")
     return out
 
 
@@ -761,6 +767,8 @@ def main():
     c1 = None if args.no_c1 else c1_context(stream)
     torch.cuda.empty_cache()
     batched = None if args.no_batched else batched_workload()
+    torch.cuda.empty_cache()
+    q2 = None if args.no_q2 else q2_workloads(stream, light=True)
     learned = None
     if not args.no_learned:
         torch.cuda.empty_cache()
@@ -797,6 +805,7 @@ def main():
         "apply_256x256_p84": {"per_sigma": applies, "algorithmic_bytes": nb, "fp64_flops": fl},
         "solves_128x128_p35": c1,
         "batched_64": batched,
+        "q2": q2,
         "learned_vs_field_split": learned,
         # The factored apply does 2 nnz(T) multiply-adds per Gauss point and
         # gradient component in each contraction step on 8 (M + 2P N_h/N_q)
