@@ -9,8 +9,9 @@
 //  3. per mode and Gauss point, flux_alpha = a_min grad_alpha
 //       + exp(mu + |g|^2/2) sum_beta T_{alpha beta} y_beta, written over the
 //     gradients;
-//  4. per node and mode, the weighted sum of grad phi_node . flux over the
-//     Gauss points of the node's 1, 2 or 4 elements.
+//  4. per element and mode, in four colours of elements that share no node,
+//     the weighted sums of grad phi_node . flux over the element's Gauss
+//     points, added to the output (zeroed first).
 // Index layout is described in sg_q2.h.
 #include <hip/hip_runtime.h>
 
@@ -153,44 +154,57 @@ __global__ __launch_bounds__(kQ2Threads) void q2_tflux_kernel(int64_t Nq, int M,
   *py = a_min * *py + sc * fy;
 }
 
-// pass 4: thread (mode i, interior node); elements in the order (ey, ex)
-// ascending, points q ascending
-__global__ __launch_bounds__(kQ2Threads) void q2_scatter_kernel(int n2, int P,
+// pass 4, in four colours: thread (mode i, element of colour (ex & 1) + 2 (ey & 1));
+// the element's 9 node sums from its 9 Gauss points are added to W (zeroed
+// first).  Two elements of one colour are two element rows or columns apart
+// and share no node, so a colour's threads never touch the same entry; each
+// entry receives its elements' sums in colour order.  Each flux value is
+// read once.
+__global__ __launch_bounds__(kQ2Threads) void q2_scatter_kernel(int n2, int P, int colour,
                                                                 const double* __restrict__ flux,
                                                                 double* __restrict__ W) {
   const int m = 2 * n2 - 1;
-  const int64_t Nh = (int64_t)m * m, Nq = 9 * (int64_t)n2 * n2;
+  const int h2 = n2 / 2;  // elements of one colour per row (n2 is even)
+  const int64_t Ec = (int64_t)h2 * h2, E = (int64_t)n2 * n2, Nq = 9 * E;
+  const int64_t Nh = (int64_t)m * m;
   const int64_t gid = (int64_t)blockIdx.x * kQ2Threads + threadIdx.x;
-  if (gid >= (int64_t)P * Nh) return;
-  const int i = (int)(gid / Nh);
-  const int64_t node = gid - (int64_t)i * Nh;
-  const int Y = (int)(node / m) + 1, X = (int)(node - (int64_t)(Y - 1) * m) + 1;
-  // the (element, local index) pairs of X along one axis: an even coordinate
-  // is a vertex of two elements, an odd one the midpoint of one
-  const int nx = (X & 1) ? 1 : 2, ny = (Y & 1) ? 1 : 2;
-  const int ex0 = (X & 1) ? (X - 1) / 2 : X / 2 - 1, ax0 = (X & 1) ? 1 : 2;
-  const int ey0 = (Y & 1) ? (Y - 1) / 2 : Y / 2 - 1, ay0 = (Y & 1) ? 1 : 2;
-  const double* fx = flux + (int64_t)(2 * i) * Nq;
-  const double* fy = flux + (int64_t)(2 * i + 1) * Nq;
-  double acc = 0.0;
-  for (int jy = 0; jy < ny; ++jy) {
-    const int ey = ey0 + jy, ay = jy ? 0 : ay0;
-    for (int jx = 0; jx < nx; ++jx) {
-      const int ex = ex0 + jx, ax = jx ? 0 : ax0;
-      const int64_t el = (int64_t)ey * n2 + ex, E = (int64_t)n2 * n2;
+  if (gid >= (int64_t)P * Ec) return;
+  const int i = (int)(gid / Ec);
+  const int64_t k = gid - (int64_t)i * Ec;
+  const int ey = 2 * (int)(k / h2) + (colour >> 1), ex = 2 * (int)(k % h2) + (colour & 1);
+  const int64_t el = (int64_t)ey * n2 + ex;
+  const double* fx = flux + (int64_t)(2 * i) * Nq + el;
+  const double* fy = flux + (int64_t)(2 * i + 1) * Nq + el;
+  double fxq[9], fyq[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    fxq[q] = fx[q * E];
+    fyq[q] = fy[q * E];
+  }
+  double* Wi = W + (int64_t)i * Nh;
+#pragma unroll
+  for (int ay = 0; ay < 3; ++ay)
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const int X = 2 * ex + ax, Y = 2 * ey + ay;
+      if (X < 1 || X > m || Y < 1 || Y > m) continue;
+      double acc = 0.0;
 #pragma unroll
       for (int qy = 0; qy < 3; ++qy)
 #pragma unroll
         for (int qx = 0; qx < 3; ++qx) {
           const double sx = q2_pt(qx), sy = q2_pt(qy);
           const double w = q2_wt(qx) * q2_wt(qy);
-          const double dx = dlag(ax, sx) * lag(ay, sy), dy = lag(ax, sx) * dlag(ay, sy);
-          const int64_t qi = (3 * qy + qx) * E + el;
-          acc += w * (dx * fx[qi] + dy * fy[qi]);
+          acc += w * (dlag(ax, sx) * lag(ay, sy) * fxq[3 * qy + qx] +
+                      lag(ax, sx) * dlag(ay, sy) * fyq[3 * qy + qx]);
         }
+      Wi[(int64_t)(Y - 1) * m + (X - 1)] += acc;
     }
-  }
-  W[gid] = acc;
+}
+
+__global__ __launch_bounds__(kQ2Threads) void q2_zero_kernel(double* __restrict__ W, int64_t n) {
+  const int64_t gid = (int64_t)blockIdx.x * kQ2Threads + threadIdx.x;
+  if (gid < n) W[gid] = 0.0;
 }
 
 // F(node) for mode 0: sum over the node's elements of h^2 (M1 (x) M1)_{a b} f_b,
@@ -248,8 +262,11 @@ void launch_q2_apply(hipStream_t s, int n2, int M, int P, double mu, double a_mi
                      T, grad, y);
   hipLaunchKernelGGL(q2_tflux_kernel, dim3(q2_blocks(P * Nq)), dim3(kQ2Threads), 0, s, Nq, M, P,
                      mu, a_min, g, T, grad, y);
-  hipLaunchKernelGGL(q2_scatter_kernel, dim3(q2_blocks(P * Nh)), dim3(kQ2Threads), 0, s, n2, P,
-                     grad, W);
+  hipLaunchKernelGGL(q2_zero_kernel, dim3(q2_blocks(P * Nh)), dim3(kQ2Threads), 0, s, W, P * Nh);
+  const int64_t Ec = (int64_t)(n2 / 2) * (n2 / 2);
+  for (int colour = 0; colour < 4; ++colour)
+    hipLaunchKernelGGL(q2_scatter_kernel, dim3(q2_blocks(P * Ec)), dim3(kQ2Threads), 0, s, n2, P,
+                       colour, grad, W);
 }
 
 void launch_q2_rhs(hipStream_t s, int n2, int P, const double* f, double* F) {
