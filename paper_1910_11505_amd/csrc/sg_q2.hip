@@ -80,12 +80,15 @@ __global__ __launch_bounds__(kQ2Threads) void q2_grad_kernel(int n2, int P,
     }
 }
 
-// g^(packed exponents), 4 bits per KL variable
+// g^(packed exponents), 4 bits per KL variable; variables past the highest
+// nonzero exponent are skipped (code runs out)
 __device__ __forceinline__ double q2_mono(const double (&g)[kQ2MaxM], uint64_t code) {
   double v = 1.0;
 #pragma unroll
   for (int k = 0; k < kQ2MaxM; ++k) {
-    const int ek = (int)((code >> (4 * k)) & 15u);
+    if (code == 0) break;
+    const int ek = (int)(code & 15u);
+    code >>= 4;
     for (int t = 0; t < ek; ++t) v *= g[k];
   }
   return v;
